@@ -1,0 +1,201 @@
+/*
+ * tw.h — C ABI of the MI355X streaming temporal random-walk library.
+ *
+ * The library keeps a sliding window of timestamped directed edges (u, v, t)
+ * resident in HBM under the dual index of Tempest (arxiv 2605.16182,
+ * Sec. "Dual-Index Organization"), rebuilds it on every ingested batch
+ * (Sec. "Streaming Ingestion and Window Management"), and samples
+ * causality-preserving temporal random walks from it with the closed-form
+ * pickers of Eqs. (1)-(3) and temporal node2vec (Sec. "Temporal Bias
+ * Sampling").
+ *
+ * Conventions shared by every call:
+ *  - Every pointer named d_* is a device pointer on the graph's device.
+ *    The library never frees caller memory. Input arrays are only read, and
+ *    only until the call's work on the graph's stream has finished.
+ *  - Work is enqueued on the graph's HIP stream (tw_config.hip_stream, or
+ *    tw_set_stream). Calls that must read a count back synchronise that
+ *    stream; this is stated per call.
+ *  - No C++ exception crosses this boundary. A failing call returns a
+ *    non-zero tw_status and tw_last_error() describes it (thread-local).
+ *  - One graph handle must not be used from two host threads at once.
+ *  - Timestamps are int64. Node ids are int32 in [0, num_nodes).
+ *  - The active window holds at most 2^32 - 2 edges.
+ */
+#ifndef TW_H
+#define TW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tw_graph tw_graph;
+
+typedef enum {
+    TW_OK = 0,
+    TW_EINVAL = 1,  /* bad argument; nothing was changed or enqueued */
+    TW_ENOMEM = 2,  /* device allocation failed; graph left unchanged */
+    TW_EDEVICE = 3, /* a HIP runtime call failed */
+    TW_ERANGE = 4   /* a node id outside [0, num_nodes) */
+} tw_status;
+
+/* Pickers, Sec. "Temporal Bias Sampling".
+ *  TW_UNIFORM:     Eq. (1) over the candidate edges.
+ *  TW_LINEAR:      Eq. (2) over the candidate distinct-timestamp groups
+ *                  (P(i) proportional to i+1, later groups heavier), then a
+ *                  uniform edge inside the group (ties broken uniformly,
+ *                  Sec. "Design Constraints").
+ *  TW_EXPONENTIAL: Eq. (3) read as the exact inverse CDF of
+ *                  P(i) ~ exp(lambda i) over the n candidate groups, with
+ *                  lambda = (t_last - t_first) / ((n - 1) tau) when tau > 0
+ *                  and lambda = 1 when tau <= 0; then a uniform edge in the
+ *                  group.
+ *  TW_NODE2VEC:    rejection on the TW_EXPONENTIAL proposal: a candidate w
+ *                  is accepted when U * max(1/p, 1, 1/q) < beta, beta = 1/p
+ *                  if w is the previous node, 1 if the window holds an edge
+ *                  previous -> w, else 1/q. At most 4096 trials per hop; a
+ *                  walk that exhausts them ends there. Hop bias only. */
+typedef enum { TW_UNIFORM = 0, TW_LINEAR = 1, TW_EXPONENTIAL = 2, TW_NODE2VEC = 3 } tw_bias_kind;
+
+/* TW_START_EDGE: the first edge is drawn from the whole window (timestamp
+ * view) under start_bias. TW_START_NODE: walk i starts at d_start_nodes[i]
+ * and its first edge is drawn from that node's whole run under start_bias. */
+typedef enum { TW_START_EDGE = 0, TW_START_NODE = 1 } tw_start_mode;
+
+/* Where each hop runs (Sec. "Hierarchical Cooperative Scheduling"). The
+ * result never depends on it: the RNG is keyed by (seed, walk, hop, trial).
+ *  TW_DISPATCH_FULL_WALK: one thread carries a walk through all its hops.
+ *  TW_DISPATCH_COOP: per-step regrouping of live walks by current node and
+ *    dispatch to a thread, a wavefront or a workgroup per node.
+ *  TW_DISPATCH_AUTO: the library's choice. */
+typedef enum {
+    TW_DISPATCH_AUTO = 0,
+    TW_DISPATCH_FULL_WALK = 1,
+    TW_DISPATCH_COOP = 2
+} tw_dispatch;
+
+typedef struct {
+    int32_t kind; /* tw_bias_kind */
+    double tau;   /* exponential decay scale in timestamp units */
+    double p, q;  /* node2vec return / in-out parameters, > 0 */
+} tw_bias;
+
+typedef struct {
+    int32_t num_nodes; /* node ids are in [0, num_nodes), num_nodes >= 1 */
+    int32_t directed;  /* 0: every edge (u,v,t) is stored as (u,v,t), (v,u,t) */
+    int64_t window;    /* Delta > 0: keep t_now - Delta <= t_e; <= 0: no window */
+    void* hip_stream;  /* hipStream_t; NULL is the default stream */
+} tw_config;
+
+typedef struct {
+    int64_t num_walks;           /* >= 0 */
+    int32_t max_len;             /* nodes per walk, >= 1 */
+    tw_bias hop_bias;            /* any tw_bias_kind */
+    tw_bias start_bias;          /* TW_UNIFORM, TW_LINEAR or TW_EXPONENTIAL */
+    int32_t start_mode;          /* tw_start_mode */
+    const int32_t* d_start_nodes;/* TW_START_NODE: num_walks ids; else ignored */
+    uint64_t seed;               /* RNG key */
+    uint64_t walk_id_base;       /* walk i uses RNG id walk_id_base + i */
+    int32_t dispatch;            /* tw_dispatch */
+} tw_walk_params;
+
+typedef struct {
+    int64_t accepted;     /* records merged by the last ingest (after mirroring) */
+    int64_t dropped_late; /* records of the last ingest older than t_now - Delta */
+    int64_t evicted;      /* records evicted by the last ingest / evict call */
+    int64_t active_edges; /* records in the window now */
+    int64_t t_min, t_max; /* timestamp range of the window (0, 0 when empty) */
+} tw_ingest_info;
+
+/* Create an empty graph. Allocates nothing on the device until the first
+ * ingest. Returns TW_EINVAL for num_nodes < 1 or a null out. */
+tw_status tw_create(const tw_config* cfg, tw_graph** out);
+
+/* Synchronise the graph's stream and free everything the graph owns. */
+tw_status tw_destroy(tw_graph* g);
+
+/* Use another stream for all later calls. */
+tw_status tw_set_stream(tw_graph* g, void* hip_stream);
+
+/*
+ * Ingest one batch of n edges (Sec. "Streaming Ingestion and Window
+ * Management"): mirror (undirected graphs), advance t_now to the largest
+ * timestamp seen, drop batch records older than t_now - Delta, evict window
+ * records older than t_now - Delta, sort the batch by timestamp (stable) and
+ * merge it after the window's records of equal timestamp, then rebuild both
+ * views of the dual index (Sec. "Dual-Index Organization").
+ * d_src, d_dst: int32[n]; d_ts: int64[n]; device memory, any alignment.
+ * info (nullable) receives the counts. The call synchronises the stream.
+ * Returns TW_ERANGE, with the graph unchanged, if any id is outside
+ * [0, num_nodes); TW_ENOMEM, graph unchanged, if the device is full.
+ */
+tw_status tw_ingest_batch(tw_graph* g, const int32_t* d_src, const int32_t* d_dst,
+                          const int64_t* d_ts, int64_t n, tw_ingest_info* info);
+
+/*
+ * Remove every window record with timestamp < t_cutoff from both views and
+ * rebuild the offsets (Sec. "Dual-Index Organization": eviction is a prefix
+ * of the timestamp view). Idempotent. Does not move t_now.
+ * n_evicted (nullable) receives the count. Synchronises the stream.
+ */
+tw_status tw_evict_before(tw_graph* g, int64_t t_cutoff, int64_t* n_evicted);
+
+/*
+ * Sample params->num_walks walks (Sec. "Temporal Bias Sampling", "Hierarchical
+ * Cooperative Scheduling"). Outputs are walk-major, caller-owned device
+ * arrays:
+ *   d_nodes: int32[num_walks * max_len], row i = walk i's nodes, padded -1;
+ *   d_ts:    int64[num_walks * max_len], d_ts[i*max_len + j] = timestamp of
+ *            the edge into node j; position 0 and padding hold INT64_MIN;
+ *   d_len:   int32[num_walks], nodes in walk i (0 only for an empty window in
+ *            TW_START_EDGE mode or a start node out of range).
+ * Each hop keeps the timestamp strictly increasing (Gamma_t(v) holds edges
+ * with t' > t). Asynchronous: returns after enqueue. A start node outside
+ * [0, num_nodes) gives that walk length 0 and makes the next synchronising
+ * call (tw_stats, tw_ingest_batch, tw_evict_before, tw_sync) return
+ * TW_ERANGE. Returns TW_EINVAL for bad parameters (nothing enqueued).
+ */
+tw_status tw_sample_walks(tw_graph* g, const tw_walk_params* params, int32_t* d_nodes,
+                          int64_t* d_ts, int32_t* d_len);
+
+/* Synchronise the stream and report a pending device-side range error. */
+tw_status tw_sync(tw_graph* g);
+
+/* Window counts and timestamp range (active_edges, t_min, t_max; the
+ * per-call fields repeat the last ingest / evict). Synchronises. */
+tw_status tw_stats(tw_graph* g, tw_ingest_info* info);
+
+/*
+ * Sizes of the index: out[0] active edges m, out[1] distinct timestamps Gg,
+ * out[2] distinct (node, timestamp) pairs Gn, out[3] num_nodes. Synchronises.
+ */
+tw_status tw_view_sizes(tw_graph* g, int64_t out[4]);
+
+/*
+ * Copy the index into caller device buffers (any pointer may be null), for
+ * inspection and tests. Sizes as returned by tw_view_sizes:
+ *   src, dst: int32[m], ts: int64[m]          timestamp view (the edge store)
+ *   g_ts: int64[Gg], g_off: int64[Gg+1]       its timestamp-group offsets
+ *   n_dst: int32[m], n_ts: int64[m]           node-and-timestamp view
+ *   n_gts: int64[Gn], n_goff: int64[Gn+1]     its (node, timestamp) groups
+ *   n_ebeg, n_gbeg: int64[V+1]                first edge / group of node v
+ * Synchronises.
+ */
+tw_status tw_export_views(tw_graph* g, int32_t* src, int32_t* dst, int64_t* ts, int64_t* g_ts,
+                          int64_t* g_off, int32_t* n_dst, int64_t* n_ts, int64_t* n_gts,
+                          int64_t* n_goff, int64_t* n_ebeg, int64_t* n_gbeg);
+
+/* Device bytes the graph holds now. */
+int64_t tw_device_bytes(const tw_graph* g);
+
+/* Message for the last non-OK status returned on this host thread. */
+const char* tw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TW_H */

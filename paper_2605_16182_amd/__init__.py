@@ -1,0 +1,215 @@
+"""Python binding of the MI355X streaming temporal random-walk library.
+
+Argument marshalling only: every step of ingest, eviction and walk sampling
+runs in the HIP kernels of ``libtw.so`` (C ABI in ``include/tw.h``). PyTorch
+supplies device memory (tensors) and the HIP stream. The library must be
+built (``__graft_entry__.build()``); importing works without it, but every
+call raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtw.so")
+
+UNIFORM, LINEAR, EXPONENTIAL, NODE2VEC = 0, 1, 2, 3
+KINDS = {"uniform": UNIFORM, "linear": LINEAR, "exponential": EXPONENTIAL, "node2vec": NODE2VEC}
+START_EDGE, START_NODE = 0, 1
+START_MODES = {"edge": START_EDGE, "node": START_NODE}
+DISPATCH = {"auto": 0, "full_walk": 1, "coop": 2}
+TW_OK, TW_EINVAL, TW_ENOMEM, TW_EDEVICE, TW_ERANGE = 0, 1, 2, 3, 4
+TS_NONE = -(1 << 63)
+
+_c = ctypes
+
+
+class _Bias(_c.Structure):
+    _fields_ = [("kind", _c.c_int32), ("tau", _c.c_double), ("p", _c.c_double),
+                ("q", _c.c_double)]
+
+
+class _Config(_c.Structure):
+    _fields_ = [("num_nodes", _c.c_int32), ("directed", _c.c_int32), ("window", _c.c_int64),
+                ("hip_stream", _c.c_void_p)]
+
+
+class _WalkParams(_c.Structure):
+    _fields_ = [("num_walks", _c.c_int64), ("max_len", _c.c_int32), ("hop_bias", _Bias),
+                ("start_bias", _Bias), ("start_mode", _c.c_int32),
+                ("d_start_nodes", _c.c_void_p), ("seed", _c.c_uint64),
+                ("walk_id_base", _c.c_uint64), ("dispatch", _c.c_int32)]
+
+
+class _Info(_c.Structure):
+    _fields_ = [(k, _c.c_int64) for k in ("accepted", "dropped_late", "evicted",
+                                          "active_edges", "t_min", "t_max")]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libtw.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = _c.CDLL(LIB_PATH)
+    P, I64 = _c.c_void_p, _c.c_int64
+    sig = {
+        "tw_create": ([_c.POINTER(_Config), _c.POINTER(P)], _c.c_int),
+        "tw_destroy": ([P], _c.c_int),
+        "tw_set_stream": ([P, P], _c.c_int),
+        "tw_ingest_batch": ([P, P, P, P, I64, _c.POINTER(_Info)], _c.c_int),
+        "tw_evict_before": ([P, I64, _c.POINTER(I64)], _c.c_int),
+        "tw_sample_walks": ([P, _c.POINTER(_WalkParams), P, P, P], _c.c_int),
+        "tw_sync": ([P], _c.c_int),
+        "tw_stats": ([P, _c.POINTER(_Info)], _c.c_int),
+        "tw_view_sizes": ([P, _c.POINTER(I64)], _c.c_int),
+        "tw_export_views": ([P] * 12, _c.c_int),
+        "tw_device_bytes": ([P], I64),
+        "tw_last_error": ([], _c.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+class TwError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[tw status {code}] {msg}")
+        self.code = code
+
+
+def _check(rc: int):
+    if rc != TW_OK:
+        raise TwError(rc, lib().tw_last_error().decode(errors="replace"))
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tw arrays must be device tensors")
+    if not t.is_contiguous():
+        raise ValueError("tw arrays must be contiguous")
+    return _c.c_void_p(t.data_ptr())
+
+
+def _info(i: _Info) -> dict:
+    return {k: int(getattr(i, k)) for k, _ in _Info._fields_}
+
+
+class Graph:
+    """A sliding-window temporal graph resident on one GPU."""
+
+    def __init__(self, num_nodes: int, directed: bool = True, window: int = 0,
+                 stream: Optional[torch.cuda.Stream] = None, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        self.num_nodes = int(num_nodes)
+        self._lib = lib()
+        with torch.cuda.device(self.device):
+            s = stream if stream is not None else torch.cuda.current_stream()
+            self.stream = s
+            cfg = _Config(self.num_nodes, 1 if directed else 0, int(window),
+                          _c.c_void_p(s.cuda_stream))
+            h = _c.c_void_p()
+            _check(self._lib.tw_create(_c.byref(cfg), _c.byref(h)))
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.tw_destroy(h)
+            self._h = None
+
+    __del__ = close
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        _check(self._lib.tw_set_stream(self._h, _c.c_void_p(stream.cuda_stream)))
+        self.stream = stream
+
+    def ingest_batch(self, src: torch.Tensor, dst: torch.Tensor, ts: torch.Tensor) -> dict:
+        assert src.dtype == torch.int32 and dst.dtype == torch.int32 and ts.dtype == torch.int64
+        n = src.numel()
+        assert dst.numel() == n and ts.numel() == n
+        info = _Info()
+        _check(self._lib.tw_ingest_batch(self._h, _ptr(src), _ptr(dst), _ptr(ts), n,
+                                         _c.byref(info)))
+        return _info(info)
+
+    def evict_before(self, cutoff: int) -> int:
+        n = _c.c_int64(0)
+        _check(self._lib.tw_evict_before(self._h, int(cutoff), _c.byref(n)))
+        return int(n.value)
+
+    def sample_walks(self, num_walks: int, max_len: int, hop_bias: str = "uniform",
+                     hop_tau: float = 0.0, p: float = 1.0, q: float = 1.0,
+                     start_bias: str = "uniform", start_tau: float = 0.0,
+                     start_mode: str = "edge", start_nodes: Optional[torch.Tensor] = None,
+                     seed: int = 42, walk_id_base: int = 0, dispatch: str = "auto",
+                     out=None):
+        """Returns (nodes int32[W, L], ts int64[W, L], len int32[W]) on the device."""
+        W, L = int(num_walks), int(max_len)
+        if out is None:
+            nodes = torch.empty((W, max(L, 1)), dtype=torch.int32, device=self.device)
+            ts = torch.empty((W, max(L, 1)), dtype=torch.int64, device=self.device)
+            lens = torch.empty(W, dtype=torch.int32, device=self.device)
+        else:
+            nodes, ts, lens = out
+        if start_nodes is not None:
+            assert start_nodes.dtype == torch.int32 and start_nodes.numel() >= W
+        prm = _WalkParams(W, L, _Bias(KINDS[hop_bias], float(hop_tau), float(p), float(q)),
+                          _Bias(KINDS[start_bias], float(start_tau), 1.0, 1.0),
+                          START_MODES[start_mode], _ptr(start_nodes), int(seed),
+                          int(walk_id_base), DISPATCH[dispatch])
+        _check(self._lib.tw_sample_walks(self._h, _c.byref(prm), _ptr(nodes), _ptr(ts),
+                                         _ptr(lens)))
+        return nodes, ts, lens
+
+    def sync(self):
+        _check(self._lib.tw_sync(self._h))
+
+    def stats(self) -> dict:
+        info = _Info()
+        _check(self._lib.tw_stats(self._h, _c.byref(info)))
+        return _info(info)
+
+    def view_sizes(self) -> dict:
+        out = (_c.c_int64 * 4)()
+        _check(self._lib.tw_view_sizes(self._h, out))
+        return dict(m=out[0], gg=out[1], gn=out[2], V=out[3])
+
+    def export_views(self) -> dict:
+        s = self.view_sizes()
+        m, gg, gn, V = s["m"], s["gg"], s["gn"], s["V"]
+        d = self.device
+        t = dict(src=torch.empty(m, dtype=torch.int32, device=d),
+                 dst=torch.empty(m, dtype=torch.int32, device=d),
+                 ts=torch.empty(m, dtype=torch.int64, device=d),
+                 g_ts=torch.empty(gg, dtype=torch.int64, device=d),
+                 g_off=torch.empty(gg + 1, dtype=torch.int64, device=d),
+                 n_dst=torch.empty(m, dtype=torch.int32, device=d),
+                 n_ts=torch.empty(m, dtype=torch.int64, device=d),
+                 n_gts=torch.empty(gn, dtype=torch.int64, device=d),
+                 n_goff=torch.empty(gn + 1, dtype=torch.int64, device=d),
+                 n_ebeg=torch.empty(V + 1, dtype=torch.int64, device=d),
+                 n_gbeg=torch.empty(V + 1, dtype=torch.int64, device=d))
+        order = ("src", "dst", "ts", "g_ts", "g_off", "n_dst", "n_ts", "n_gts", "n_goff",
+                 "n_ebeg", "n_gbeg")
+        _check(self._lib.tw_export_views(self._h, *(_ptr(t[k]) if t[k].numel() else None
+                                                    for k in order)))
+        return t
+
+    def device_bytes(self) -> int:
+        return int(self._lib.tw_device_bytes(self._h))

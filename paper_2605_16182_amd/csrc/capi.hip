@@ -1,0 +1,182 @@
+// The C ABI declared in include/tw.h: argument checks, error reporting and
+// dispatch to the ingest and walk code. No exception crosses this layer.
+#include <new>
+#include <string>
+
+#include "tw_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+tw_status fail(tw_status code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+tw_status report(tw_status code, const tw::Error& e) {
+    if (code != TW_OK) g_last_error = e.msg;
+    return code;
+}
+
+template <typename F>
+tw_status guarded(const char* what, F&& f) {
+    try {
+        return f();
+    } catch (const std::bad_alloc&) {
+        return fail(TW_ENOMEM, std::string(what) + ": host allocation failed");
+    } catch (...) {
+        return fail(TW_EDEVICE, std::string(what) + ": unexpected exception");
+    }
+}
+
+// pending device-side range error from walks (start node out of range)
+tw_status check_device_flags(tw_graph* g) {
+    if (!g->err.p) return TW_OK;
+    uint32_t f = 0;
+    if (hipMemcpyAsync(&f, g->err.p, sizeof(f), hipMemcpyDeviceToHost, g->stream) != hipSuccess ||
+        hipStreamSynchronize(g->stream) != hipSuccess)
+        return fail(TW_EDEVICE, "reading device error flags failed");
+    if (f) {
+        hipMemsetAsync(g->err.p, 0, sizeof(uint32_t), g->stream);
+        hipStreamSynchronize(g->stream);
+        return fail(TW_ERANGE, "a walk start node was outside [0, num_nodes)");
+    }
+    return TW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tw_status tw_create(const tw_config* cfg, tw_graph** out) {
+    return guarded("tw_create", [&]() -> tw_status {
+        if (!cfg || !out) return fail(TW_EINVAL, "tw_create: null argument");
+        if (cfg->num_nodes < 1) return fail(TW_EINVAL, "tw_create: num_nodes must be >= 1");
+        tw_graph* g = new tw_graph();
+        g->V = cfg->num_nodes;
+        g->directed = cfg->directed != 0;
+        g->window = cfg->window;
+        g->stream = static_cast<hipStream_t>(cfg->hip_stream);
+        if (hipGetDevice(&g->device) != hipSuccess) {
+            delete g;
+            return fail(TW_EDEVICE, "tw_create: no HIP device");
+        }
+        *out = g;
+        return TW_OK;
+    });
+}
+
+tw_status tw_destroy(tw_graph* g) {
+    if (!g) return TW_OK;
+    return guarded("tw_destroy", [&]() -> tw_status {
+        hipStreamSynchronize(g->stream);
+        tw::DevBuf* bufs[] = {&g->e_src, &g->e_dst, &g->e_ts, &g->a_src, &g->a_dst, &g->a_ts,
+                              &g->gg_ts, &g->gg_off, &g->n_dst, &g->n_ts, &g->ng_ts, &g->ng_off,
+                              &g->n_src, &g->rec, &g->adj, &g->b_src, &g->b_dst, &g->b_ts,
+                              &g->b_keys, &g->b_vals, &g->b_flags, &g->flags, &g->idx, &g->err,
+                              &g->scal, &g->ws.scan_part, &g->ws.hist, &g->ws.keys_alt,
+                              &g->ws.vals_alt, &g->ws.misc};
+        for (tw::DevBuf* b : bufs) tw::release(*b);
+        delete g;
+        return TW_OK;
+    });
+}
+
+tw_status tw_set_stream(tw_graph* g, void* hip_stream) {
+    if (!g) return fail(TW_EINVAL, "tw_set_stream: null graph");
+    if (hipStreamSynchronize(g->stream) != hipSuccess)
+        return fail(TW_EDEVICE, "tw_set_stream: synchronising the old stream failed");
+    g->stream = static_cast<hipStream_t>(hip_stream);
+    return TW_OK;
+}
+
+tw_status tw_ingest_batch(tw_graph* g, const int32_t* d_src, const int32_t* d_dst,
+                          const int64_t* d_ts, int64_t n, tw_ingest_info* info) {
+    if (!g) return fail(TW_EINVAL, "tw_ingest_batch: null graph");
+    if (n < 0 || (n > 0 && (!d_src || !d_dst || !d_ts)))
+        return fail(TW_EINVAL, "tw_ingest_batch: need n >= 0 and non-null arrays");
+    return guarded("tw_ingest_batch", [&]() -> tw_status {
+        tw_status st = check_device_flags(g);
+        if (st != TW_OK) return st;
+        tw::Error e{TW_OK, ""};
+        return report(tw::ingest(g, d_src, d_dst, d_ts, n, info, e), e);
+    });
+}
+
+tw_status tw_evict_before(tw_graph* g, int64_t t_cutoff, int64_t* n_evicted) {
+    if (!g) return fail(TW_EINVAL, "tw_evict_before: null graph");
+    return guarded("tw_evict_before", [&]() -> tw_status {
+        tw_status st = check_device_flags(g);
+        if (st != TW_OK) return st;
+        tw::Error e{TW_OK, ""};
+        return report(tw::evict_before(g, t_cutoff, n_evicted, e), e);
+    });
+}
+
+tw_status tw_sample_walks(tw_graph* g, const tw_walk_params* params, int32_t* d_nodes,
+                          int64_t* d_ts, int32_t* d_len) {
+    if (!g) return fail(TW_EINVAL, "tw_sample_walks: null graph");
+    return guarded("tw_sample_walks", [&]() -> tw_status {
+        tw::Error e{TW_OK, ""};
+        return report(tw::sample_walks(g, params, d_nodes, d_ts, d_len, e), e);
+    });
+}
+
+tw_status tw_sync(tw_graph* g) {
+    if (!g) return fail(TW_EINVAL, "tw_sync: null graph");
+    if (hipStreamSynchronize(g->stream) != hipSuccess)
+        return fail(TW_EDEVICE, "tw_sync: stream synchronisation failed");
+    return check_device_flags(g);
+}
+
+tw_status tw_stats(tw_graph* g, tw_ingest_info* info) {
+    if (!g || !info) return fail(TW_EINVAL, "tw_stats: null argument");
+    tw_status st = tw_sync(g);
+    *info = g->last;
+    info->active_edges = g->m;
+    info->t_min = g->t_min;
+    info->t_max = g->t_max;
+    return st;
+}
+
+tw_status tw_view_sizes(tw_graph* g, int64_t out[4]) {
+    if (!g || !out) return fail(TW_EINVAL, "tw_view_sizes: null argument");
+    if (hipStreamSynchronize(g->stream) != hipSuccess)
+        return fail(TW_EDEVICE, "tw_view_sizes: stream synchronisation failed");
+    out[0] = g->m;
+    out[1] = g->Gg;
+    out[2] = g->Gn;
+    out[3] = g->V;
+    return TW_OK;
+}
+
+tw_status tw_export_views(tw_graph* g, int32_t* src, int32_t* dst, int64_t* ts, int64_t* g_ts,
+                          int64_t* g_off, int32_t* n_dst, int64_t* n_ts, int64_t* n_gts,
+                          int64_t* n_goff, int64_t* n_ebeg, int64_t* n_gbeg) {
+    if (!g) return fail(TW_EINVAL, "tw_export_views: null graph");
+    return guarded("tw_export_views", [&]() -> tw_status {
+        tw::Error e{TW_OK, ""};
+        if (!g->rec.p && tw::init_empty(g, e) != TW_OK) return report(e.code, e);
+        return report(tw::export_views(g, src, dst, ts, g_ts, g_off, n_dst, n_ts, n_gts, n_goff,
+                                       n_ebeg, n_gbeg, e),
+                      e);
+    });
+}
+
+int64_t tw_device_bytes(const tw_graph* g) {
+    if (!g) return 0;
+    const tw::DevBuf* bufs[] = {&g->e_src, &g->e_dst, &g->e_ts, &g->a_src, &g->a_dst, &g->a_ts,
+                                &g->gg_ts, &g->gg_off, &g->n_dst, &g->n_ts, &g->ng_ts, &g->ng_off,
+                                &g->n_src, &g->rec, &g->adj, &g->b_src, &g->b_dst, &g->b_ts,
+                                &g->b_keys, &g->b_vals, &g->b_flags, &g->flags, &g->idx, &g->err,
+                                &g->scal, &g->ws.scan_part, &g->ws.hist, &g->ws.keys_alt,
+                                &g->ws.vals_alt, &g->ws.misc};
+    int64_t total = 0;
+    for (const tw::DevBuf* b : bufs) total += (int64_t)b->bytes;
+    return total;
+}
+
+const char* tw_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,270 @@
+// Data-parallel primitives for the index rebuild, written for wave64 CDNA:
+// an exclusive scan and a stable LSD radix sort whose per-tile ranks come
+// from wave ballots (each lane learns which lanes of its wavefront share its
+// digit from one ballot per digit bit, then counts the lower ones).
+#include "tw_internal.h"
+
+namespace tw {
+
+namespace {
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_WAVES = RS_THREADS / 64;
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+// exclusive scan of one value per thread over a 256-thread block; returns
+// this thread's exclusive prefix and writes the block total to *total
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
+    __shared__ uint32_t wsum[SCAN_THREADS / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < SCAN_THREADS / 64; ++w) {
+        uint32_t s = wsum[w];
+        before += (w < wave) ? s : 0;
+        all += s;
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+__global__ void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                              uint32_t* __restrict__ part) {
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    uint32_t s = 0;
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + (int64_t)j * SCAN_THREADS + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    uint32_t total;
+    block_excl_scan(s, &total);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+// one block: exclusive scan of the partials in place, total to *total
+__global__ void k_scan_partials(uint32_t* part, int64_t nb, uint32_t* total) {
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nb; base += SCAN_THREADS) {
+        int64_t i = base + threadIdx.x;
+        uint32_t v = i < nb ? part[i] : 0;
+        uint32_t tot;
+        uint32_t ex = block_excl_scan(v, &tot);
+        uint32_t c = carry;
+        if (i < nb) part[i] = c + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ void k_scan_down(const uint32_t* in, uint32_t* out, int64_t n,
+                            const uint32_t* __restrict__ part) {
+    __shared__ uint32_t tile[SCAN_TILE];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int k = j * SCAN_THREADS + threadIdx.x;
+        int64_t i = base + k;
+        tile[k] = i < n ? in[i] : 0;
+    }
+    __syncthreads();
+    uint32_t loc[SCAN_ITEMS];
+    uint32_t s = 0;
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        loc[j] = s;
+        s += tile[threadIdx.x * SCAN_ITEMS + j];
+    }
+    uint32_t tot;
+    uint32_t pre = block_excl_scan(s, &tot) + part[blockIdx.x];
+    for (int j = 0; j < SCAN_ITEMS; ++j) tile[threadIdx.x * SCAN_ITEMS + j] = pre + loc[j];
+    __syncthreads();
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int k = j * SCAN_THREADS + threadIdx.x;
+        int64_t i = base + k;
+        if (i < n) out[i] = tile[k];
+    }
+}
+
+__global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+
+// ------------------------------------------------------------ radix sort
+
+template <typename K>
+__global__ void k_rs_hist(const K* __restrict__ keys, int64_t n, int shift, int nbits,
+                          uint32_t* __restrict__ hist, int64_t nblocks) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t mask = (1u << nbits) - 1u;
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        int64_t i = base + (int64_t)j * RS_THREADS + threadIdx.x;
+        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & mask], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Scatter one tile to its stable positions. offs[d * nblocks + b] is the
+// first output slot of digit d for tile b (exclusive scan of the histogram).
+template <typename K>
+__global__ void __launch_bounds__(RS_THREADS)
+k_rs_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n, int shift,
+             int nbits, const uint32_t* __restrict__ offs, int64_t nblocks,
+             K* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+    __shared__ uint32_t running[256];
+    __shared__ uint32_t wcnt[RS_WAVES][256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t mask = (1u << nbits) - 1u;
+    running[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < RS_WAVES; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const uint64_t lower = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        int64_t i = base + (int64_t)r * RS_THREADS + tid;
+        bool valid = i < n;
+        K k = valid ? keys[i] : K(0);
+        uint32_t v = (valid && vals) ? vals[i] : 0u;
+        uint32_t d = (uint32_t)(k >> shift) & mask;
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < nbits; ++b) {
+            bool bit = (d >> b) & 1u;
+            uint64_t bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        uint32_t rank = (uint32_t)__popcll(peers & lower);
+        if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = running[d] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+            keys_out[pos] = k;
+            if (vals_out) vals_out[pos] = v;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < RS_WAVES; ++w) {
+            add += wcnt[w][tid];
+            wcnt[w][tid] = 0;
+        }
+        running[tid] += add;
+        __syncthreads();
+    }
+}
+
+template <typename K>
+hipError_t radix_sort_impl(K* keys, uint32_t* vals, int64_t n, int bit_lo, int bit_hi,
+                           Workspace& ws, hipStream_t s) {
+    if (n <= 1 || bit_hi <= bit_lo) return hipSuccess;
+    int64_t nblocks = ceil_div(n, RS_TILE);
+    hipError_t e;
+    if ((e = ensure(ws.hist, sizeof(uint32_t) * 256 * nblocks)) != hipSuccess) return e;
+    if ((e = ensure(ws.keys_alt, sizeof(K) * n)) != hipSuccess) return e;
+    if (vals && (e = ensure(ws.vals_alt, sizeof(uint32_t) * n)) != hipSuccess) return e;
+    K* kin = keys;
+    uint32_t* vin = vals;
+    K* kout = ws.keys_alt.as<K>();
+    uint32_t* vout = vals ? ws.vals_alt.as<uint32_t>() : nullptr;
+    uint32_t* hist = ws.hist.as<uint32_t>();
+    for (int sh = bit_lo; sh < bit_hi; sh += 8) {
+        int nb = bit_hi - sh < 8 ? bit_hi - sh : 8;
+        hipLaunchKernelGGL(k_rs_hist<K>, dim3(nblocks), dim3(RS_THREADS), 0, s, kin, n, sh, nb,
+                           hist, nblocks);
+        if ((e = scan_exclusive_u32(hist, hist, 256 * nblocks, nullptr, ws, s)) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_rs_scatter<K>, dim3(nblocks), dim3(RS_THREADS), 0, s, kin, vin, n, sh,
+                           nb, hist, nblocks, kout, vout);
+        K* tk = kin; kin = kout; kout = tk;
+        uint32_t* tv = vin; vin = vout; vout = tv;
+    }
+    if (kin != keys) {
+        if ((e = hipMemcpyAsync(keys, kin, sizeof(K) * n, hipMemcpyDeviceToDevice, s)) !=
+            hipSuccess)
+            return e;
+        if (vals && (e = hipMemcpyAsync(vals, vin, sizeof(uint32_t) * n,
+                                        hipMemcpyDeviceToDevice, s)) != hipSuccess)
+            return e;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t ensure(DevBuf& b, size_t bytes) {
+    if (bytes <= b.bytes) return hipSuccess;
+    size_t want = bytes + bytes / 4 + 256;
+    if (b.p) {
+        // the old block may still be read by enqueued kernels
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return e;
+        e = hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return e;
+    }
+    b.bytes = want;
+    return hipSuccess;
+}
+
+void release(DevBuf& b) {
+    if (b.p) hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
+                              Workspace& ws, hipStream_t s) {
+    if (n <= 0) {
+        if (total) hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, total, 0u);
+        return hipGetLastError();
+    }
+    int64_t nb = ceil_div(n, SCAN_TILE);
+    hipError_t e = ensure(ws.scan_part, sizeof(uint32_t) * (nb + 1));
+    if (e != hipSuccess) return e;
+    uint32_t* part = ws.scan_part.as<uint32_t>();
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, part);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, part, nb, total);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(SCAN_THREADS), 0, s, in, out, n, part);
+    return hipGetLastError();
+}
+
+hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bit_lo, int bit_hi,
+                          Workspace& ws, hipStream_t s) {
+    return radix_sort_impl<uint64_t>(keys, vals, n, bit_lo, bit_hi, ws, s);
+}
+
+hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bit_lo, int bit_hi,
+                          Workspace& ws, hipStream_t s) {
+    return radix_sort_impl<uint32_t>(keys, vals, n, bit_lo, bit_hi, ws, s);
+}
+
+}  // namespace tw

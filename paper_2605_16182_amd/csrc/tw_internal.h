@@ -1,0 +1,138 @@
+// Internal declarations of the MI355X temporal-walk library: graph state,
+// device buffers and the primitives shared between the ingest and walk
+// translation units. Not part of the public ABI (include/tw.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "tw.h"
+
+namespace tw {
+
+constexpr int64_t TS_NONE = INT64_MIN;
+
+// One record per node, 32 bytes so a hop reads all of it with one
+// contiguous load: the node's range of (node, timestamp) groups [gb, ge),
+// its edge range [eb, ee) in the node view, and the first / last group
+// timestamps (t_last lets a hop that cannot continue stop without searching).
+struct alignas(32) NodeRec {
+    uint32_t gb, ge, eb, ee;
+    int64_t t_first, t_last;
+};
+
+// A grow-only device allocation.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+// Error carried up to the C ABI.
+struct Error {
+    tw_status code;
+    std::string msg;
+};
+
+hipError_t ensure(DevBuf& b, size_t bytes);  // keeps contents only if no growth
+void release(DevBuf& b);
+
+// Scratch space reused by the primitives.
+struct Workspace {
+    DevBuf scan_part;   // scan partial sums
+    DevBuf hist;        // radix histograms
+    DevBuf keys_alt, vals_alt;
+    DevBuf misc;        // small scalars
+};
+
+// -------------------------------------------------------------- primitives
+
+// out[i] = sum_{j<i} in[i]; total (device scalar, nullable) = sum of all.
+// n may be 0. in and out may alias.
+hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
+                              Workspace& ws, hipStream_t s);
+
+// Stable LSD radix sort of (keys, vals) by bits [bit_lo, bit_hi) of the key.
+// vals may be null. Result ends in keys / vals. The alternate buffers come
+// from the workspace.
+hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bit_lo, int bit_hi,
+                          Workspace& ws, hipStream_t s);
+hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bit_lo, int bit_hi,
+                          Workspace& ws, hipStream_t s);
+
+// Bits needed to represent values in [0, x].
+inline int bits_for(uint64_t x) {
+    int b = 0;
+    while (b < 64 && (x >> b) != 0) ++b;
+    return b;
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace tw
+
+// --------------------------------------------------------------- graph
+
+struct tw_graph {
+    int32_t V = 0;
+    bool directed = true;
+    int64_t window = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    bool has_time = false;
+    int64_t t_now = 0;
+
+    // host mirrors of the index sizes
+    int64_t m = 0, Gg = 0, Gn = 0;
+    int64_t t_min = 0, t_max = 0;
+    tw_ingest_info last{};
+
+    // timestamp view (the edge store) and its alternate for merges
+    tw::DevBuf e_src, e_dst, e_ts, a_src, a_dst, a_ts;
+    tw::DevBuf gg_ts, gg_off;          // global timestamp groups
+    tw::DevBuf n_dst, n_ts;            // node-and-timestamp view
+    tw::DevBuf ng_ts, ng_off;          // its (node, timestamp) groups
+    tw::DevBuf n_src;                  // source of each node-view edge (build temp)
+    tw::DevBuf rec;                    // NodeRec[V]
+    tw::DevBuf adj;                    // per-node dst sorted ascending (node2vec)
+    bool adj_ready = false;
+
+    // batch staging
+    tw::DevBuf b_src, b_dst, b_ts, b_keys, b_vals, b_flags;
+    tw::DevBuf flags, idx;             // per-edge temporaries
+    tw::DevBuf err;                    // device error flags (uint32)
+    tw::DevBuf scal;                   // device scalars
+    tw::Workspace ws;
+};
+
+namespace tw {
+
+// index.hip
+tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int64_t* ts,
+                 int64_t n, tw_ingest_info* info, Error& err);
+tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& err);
+tw_status build_adjacency(tw_graph* g, Error& err);
+tw_status init_empty(tw_graph* g, Error& err);  // empty index for a graph never ingested
+tw_status export_views(tw_graph* g, int32_t* src, int32_t* dst, int64_t* ts, int64_t* g_ts,
+                       int64_t* g_off, int32_t* n_dst, int64_t* n_ts, int64_t* n_gts,
+                       int64_t* n_goff, int64_t* n_ebeg, int64_t* n_gbeg, Error& err);
+
+// walk.hip
+tw_status sample_walks(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int64_t* ts,
+                       int32_t* len, Error& err);
+
+}  // namespace tw
+
+#define TW_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            err = tw::Error{e_ == hipErrorOutOfMemory ? TW_ENOMEM : TW_EDEVICE,       \
+                            std::string(#call) + ": " + hipGetErrorString(e_)};       \
+            return err.code;                                                          \
+        }                                                                             \
+    } while (0)

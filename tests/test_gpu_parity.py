@@ -1,0 +1,195 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Indices, eviction, uniform and linear walks must be bit-exact. Exponential
+and node2vec walks must be identical except where a pick's draw lies within
+1e-6 of a CDF boundary of the exact law; the rate is reported.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import compare_walks, gpu_or_skip, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _views_equal(g, og):
+    v = {k: t.cpu().numpy() for k, t in g.export_views().items()}
+    o = og.views()
+    for k in o:
+        assert np.array_equal(v[k], o[k]), f"view {k} differs"
+
+
+def _stream_batches(rng, V, nb, n_lo, n_hi, step, spread):
+    t_base = 0
+    for _ in range(nb):
+        n = int(rng.integers(n_lo, n_hi))
+        src = rng.integers(0, V, n).astype(np.int32)
+        dst = rng.integers(0, V, n).astype(np.int32)
+        ts = (t_base + rng.integers(-spread, spread, n)).astype(np.int64)
+        t_base += step
+        yield src, dst, ts
+
+
+@pytest.mark.parametrize("directed", [True, False])
+@pytest.mark.parametrize("window", [0, 700])
+def test_stream_index_parity_small(directed, window):
+    torch, tw = gpu_or_skip()
+    rng = np.random.default_rng(7 + window + directed)
+    V = 53
+    g = tw.Graph(V, directed=directed, window=window)
+    og = oracle.OracleGraph(V, directed=directed, window=window)
+    for b, (s, d, t) in enumerate(_stream_batches(rng, V, 10, 0, 300, 150, 400)):
+        s_, d_, t_ = to_dev(torch, s, d, t)
+        info = g.ingest_batch(s_, d_, t_)
+        oinfo = og.ingest_batch(s, d, t)
+        assert info == oinfo, (b, info, oinfo)
+        _views_equal(g, og)
+        if b == 5:
+            cut = 600
+            assert g.evict_before(cut) == og.evict_before(cut)
+            assert g.evict_before(cut) == 0
+            _views_equal(g, og)
+    g.close()
+
+
+def test_index_parity_multi_tile_ragged():
+    # several radix / scan tiles (4096) with a ragged tail, duplicate timestamps
+    torch, tw = gpu_or_skip()
+    rng = np.random.default_rng(11)
+    V = 5003
+    g = tw.Graph(V, window=3_000)
+    og = oracle.OracleGraph(V, window=3_000)
+    for s, d, t in _stream_batches(rng, V, 6, 40_000, 90_001, 1000, 2500):
+        s_, d_, t_ = to_dev(torch, s, d, t)
+        assert g.ingest_batch(s_, d_, t_) == og.ingest_batch(s, d, t)
+    _views_equal(g, og)
+    g.close()
+
+
+def test_ingest_rejects_out_of_range_ids():
+    torch, tw = gpu_or_skip()
+    g = tw.Graph(10)
+    s, d, t = to_dev(torch, np.array([1, 2], np.int32), np.array([3, 4], np.int32),
+                     np.array([5, 6], np.int64))
+    g.ingest_batch(s, d, t)
+    bad = to_dev(torch, np.array([1, 10], np.int32), np.array([3, 4], np.int32),
+                 np.array([7, 8], np.int64))
+    with pytest.raises(tw.TwError) as ei:
+        g.ingest_batch(*bad)
+    assert ei.value.code == tw.TW_ERANGE
+    assert g.view_sizes()["m"] == 2
+    g.close()
+
+
+def _tiny_workload(V=4000, m=60000, **over):
+    w = synth.scaled("tiny", V, m, **over)
+    return w, w["stream"].all()
+
+
+WALK_CASES = [
+    # hop, hop tau, p, q, start, start tau, mode
+    ("uniform", 0.0, 1, 1, "uniform", 0.0, "edge"),
+    ("linear", 0.0, 1, 1, "linear", 0.0, "edge"),
+    ("linear", 0.0, 1, 1, "uniform", 0.0, "node"),
+    ("exponential", 0.0, 1, 1, "exponential", 0.0, "edge"),
+    ("exponential", 5e4, 1, 1, "exponential", 1e5, "edge"),
+    ("exponential", 2e4, 1, 1, "linear", 0.0, "node"),
+    ("node2vec", 5e4, 0.5, 2.0, "uniform", 0.0, "edge"),
+    ("node2vec", 5e4, 2.0, 0.5, "exponential", 5e4, "node"),
+    ("node2vec", 5e4, 1.0, 1.0, "uniform", 0.0, "edge"),
+]
+
+
+@pytest.mark.parametrize("ci", range(len(WALK_CASES)),
+                         ids=["-".join(map(str, c[:1] + c[4:])) for c in WALK_CASES])
+@pytest.mark.parametrize("directed", [True, False])
+def test_walk_parity(ci, directed):
+    torch, tw = gpu_or_skip()
+    hk, ht, p, q, sk, st, mode = WALK_CASES[ci]
+    V, m = 4000, 60000
+    w = synth.scaled("tiny", V, m)
+    w["stream"].directed = directed
+    src, dst, ts = w["stream"].all()
+    g = tw.Graph(V, directed=directed)
+    og = oracle.OracleGraph(V, directed=directed)
+    g.ingest_batch(*to_dev(torch, src, dst, ts))
+    og.ingest_batch(src, dst, ts)
+    W, L, seed, base = 20000, 16, 42, 777
+    starts = synth.start_nodes(9, W, V)
+    st_dev = to_dev(torch, starts)[0]
+    nodes, tts, lens = g.sample_walks(W, L, hop_bias=hk, hop_tau=ht, p=p, q=q, start_bias=sk,
+                                      start_tau=st, start_mode=mode, start_nodes=st_dev,
+                                      seed=seed, walk_id_base=base)
+    g.sync()
+    r = og.sample_walks(W, L, hop_bias=hk, hop_tau=ht, p=p, q=q, start_bias=sk, start_tau=st,
+                        start_mode=mode, start_nodes=starts, seed=seed, walk_id_base=base,
+                        with_margin=True)
+    exact = hk in ("uniform", "linear") and sk in ("uniform", "linear")
+    same, boundary = compare_walks((nodes.cpu().numpy(), tts.cpu().numpy(), lens.cpu().numpy()),
+                                   r, exact)
+    hops = int(np.maximum(r["len"] - 1, 0).sum())
+    print(f"{hk}/{sk}/{mode}: {same}/{W} identical, boundary mismatches {boundary} "
+          f"({boundary / max(hops, 1):.2e} per hop)")
+    assert boundary <= max(2, W // 2000)
+    g.close()
+
+
+def test_empty_graph_and_degenerate_walks():
+    torch, tw = gpu_or_skip()
+    g = tw.Graph(6)
+    nodes, ts, lens = g.sample_walks(4, 5)
+    g.sync()
+    assert (lens.cpu().numpy() == 0).all() and (nodes.cpu().numpy() == -1).all()
+    st = to_dev(torch, np.array([0, 5, 3, 1], np.int32))[0]
+    nodes, ts, lens = g.sample_walks(4, 5, start_mode="node", start_nodes=st)
+    g.sync()
+    assert (lens.cpu().numpy() == 1).all()
+    s, d, t = (np.array([0, 1, 2, 0], np.int32), np.array([1, 2, 0, 2], np.int32),
+               np.array([1, 2, 3, 1], np.int64))
+    g.ingest_batch(*to_dev(torch, s, d, t))
+    og = oracle.OracleGraph(6)
+    og.ingest_batch(s, d, t)
+    for L in (1, 2, 7):
+        for mode in ("edge", "node"):
+            stn = np.array([0, 1, 4, 2, 5], np.int32)
+            nodes, ts, lens = g.sample_walks(5, L, start_mode=mode, start_nodes=to_dev(torch, stn)[0],
+                                             seed=3)
+            g.sync()
+            r = og.sample_walks(5, L, start_mode=mode, start_nodes=stn, seed=3)
+            assert np.array_equal(nodes.cpu().numpy(), r["nodes"])
+            assert np.array_equal(ts.cpu().numpy(), r["ts"])
+            assert np.array_equal(lens.cpu().numpy(), r["len"])
+    bad = to_dev(torch, np.array([0, 6], np.int32))[0]
+    g.sample_walks(2, 4, start_mode="node", start_nodes=bad)
+    with pytest.raises(tw.TwError) as ei:
+        g.sync()
+    assert ei.value.code == tw.TW_ERANGE
+    g.sync()  # the flag is cleared once reported
+    for kw in (dict(max_len=0), dict(hop_bias="node2vec", p=0.0), dict(start_mode="node")):
+        args = dict(num_walks=2, max_len=4)
+        args.update(kw)
+        with pytest.raises(tw.TwError) as ei:
+            g.sample_walks(**args)
+        assert ei.value.code == tw.TW_EINVAL
+    g.close()
+
+
+def test_windowed_stream_walks_parity():
+    # streaming window: walks after every batch, linear hops, uniform start
+    torch, tw = gpu_or_skip()
+    w = synth.scaled("stream", 20000, 400_000)
+    spec = w["stream"]
+    window = 150_000 * 10
+    g = tw.Graph(spec.num_nodes, window=window)
+    og = oracle.OracleGraph(spec.num_nodes, window=window)
+    for b, (s, d, t) in enumerate(spec.batches(50_000)):
+        assert g.ingest_batch(*to_dev(torch, s, d, t)) == og.ingest_batch(s, d, t)
+        nodes, ts, lens = g.sample_walks(4000, 40, hop_bias="linear", seed=b)
+        g.sync()
+        r = og.sample_walks(4000, 40, hop_bias="linear", seed=b)
+        assert np.array_equal(nodes.cpu().numpy(), r["nodes"])
+        assert np.array_equal(ts.cpu().numpy(), r["ts"])
+        assert np.array_equal(lens.cpu().numpy(), r["len"])
+    g.close()
