@@ -1,0 +1,267 @@
+#!/usr/bin/env python3
+"""Benchmark of the streaming temporal-walk hot path on one MI355X.
+
+One step = one pass of the whole path over one batch of synthetic input that
+is already resident in HBM: empty the window, ingest the batch (validate,
+sort, merge, rebuild both views of the dual index), then sample the walks.
+
+Default workload ("single"): directed graph, 2M nodes, 100M edges, source and
+destination Zipf(1.2), sorted Poisson arrivals (mean gap 10); 4M walks of at
+most 80 nodes, exponential start and hop bias with tau = 0.1 x time span.
+
+Prints one JSON line (see the design doc for every field).
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "temporal-walk hops/sec + ingest edges/sec, batched/served vs plain, 1 MI355X"
+HBM_PEAK_GBS = 8000.0
+SECTOR = 64
+INT64_MAX = (1 << 63) - 1
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="single", choices=["single", "tiny"])
+    ap.add_argument("--dispatch", default="auto", choices=["auto", "full_walk", "coop"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probe", action="store_true")
+    return ap.parse_args()
+
+
+def describe(name, w, tau):
+    s = w["stream"]
+    return {
+        "workload": name,
+        "directed": s.directed,
+        "nodes": s.num_nodes,
+        "edges": s.num_edges,
+        "src_zipf": s.src_s, "dst_zipf": s.dst_s,
+        "timestamps": s.ts_kind,
+        "walks": w["walks"], "max_len": w["max_len"],
+        "start_bias": w["start_bias"], "hop_bias": w["hop_bias"],
+        "tau": tau, "window": w["window"],
+    }
+
+
+def probe_rates(torch, dev):
+    """Random 64 B-sector read rate over 8 GiB and streaming copy bandwidth."""
+    import paper_2605_16182_amd as tw
+    lib = ctypes.CDLL(os.path.join(os.path.dirname(tw.__file__), "libtw_probe.so"))
+    lib.probe_gather.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                                 ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
+    lib.probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                               ctypes.c_void_p]
+    stream = torch.cuda.current_stream()
+    nbytes = 8 << 30
+    buf = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    buf.random_(0, 255)
+    sink = torch.zeros(4, dtype=torch.int32, device=dev)
+    threads, iters = 256 * 2048 * 4, 64
+    best = 0.0
+    for rep in range(4):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        assert lib.probe_gather(buf.data_ptr(), nbytes, threads, iters, rep + 1, sink.data_ptr(),
+                                stream.cuda_stream) == 0
+        e1.record()
+        torch.cuda.synchronize()
+        if rep:
+            best = max(best, threads * iters / (e0.elapsed_time(e1) * 1e-3))
+    cb = 2 << 30
+    a = buf[:cb]
+    b = buf[cb:2 * cb]
+    copy_best = 0.0
+    for rep in range(4):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        assert lib.probe_copy(a.data_ptr(), b.data_ptr(), cb, stream.cuda_stream) == 0
+        e1.record()
+        torch.cuda.synchronize()
+        if rep:
+            copy_best = max(copy_best, 2 * cb / (e0.elapsed_time(e1) * 1e-3))
+    del buf
+    torch.cuda.empty_cache()
+    return best, copy_best
+
+
+def walk_bytes(walks, hops, max_len, start_bias, hop_bias):
+    """Algorithmic bytes of one walk launch: random 64 B sectors per start and
+    per hop (node record, search leaf, group bounds, chosen edge; uniform
+    picks need no group bounds) plus the walk-major output rows."""
+    start = 3 if start_bias == "uniform" else 4
+    per_hop = 3 if hop_bias == "uniform" else 4
+    return walks * start * SECTOR + hops * per_hop * SECTOR + walks * (12 * max_len + 4)
+
+
+def ingest_bytes(b, m_old, m_new, V):
+    """Algorithmic bytes of one ingest: read the batch (16 B/edge), one
+    read+write sort pass (32 B/edge), read the old and write the new window in
+    both views (28 B/edge), and the node table (4 B/node)."""
+    return 16 * b + 32 * b + 28 * (m_old + m_new) + 4 * V
+
+
+def cpu_baseline(w, tau, gpu_hops_per_step):
+    """The oracle on a bounded sample: ingest of the stream's first 20% of
+    edges (scaled linearly to the full batch) and 1% of the walk ids on that
+    graph (hop rate applied to the GPU step's hop count)."""
+    import oracle
+    spec = w["stream"]
+    frac = 0.2 if spec.num_edges >= 10_000_000 else 1.0
+    n = int(spec.num_edges * frac)
+    src, dst, ts = next(spec.batches(n))
+    og = oracle.OracleGraph(spec.num_nodes, directed=spec.directed, window=w["window"])
+    t0 = time.perf_counter()
+    og.ingest_batch(src, dst, ts)
+    og.sizes()  # builds the views
+    t_ing = (time.perf_counter() - t0) / frac
+    nw = max(1000, w["walks"] // 100)
+    idx = np.arange(0, w["walks"], max(1, w["walks"] // nw))[:nw]
+    threads = oracle.threads()
+    t0 = time.perf_counter()
+    r = og.sample_walks(w["walks"], w["max_len"], hop_bias=w["hop_bias"], hop_tau=tau,
+                        start_bias=w["start_bias"], start_tau=tau, seed=42, walk_idx=idx,
+                        threads=threads)
+    t_walk = time.perf_counter() - t0
+    hops = int(np.maximum(r["len"] - 1, 0).sum())
+    hop_rate = hops / t_walk
+    t_step = t_ing + gpu_hops_per_step / hop_rate
+    return {
+        "value": gpu_hops_per_step / t_step, "unit": "hops/s", "cores": threads,
+        "kind": "oracle",
+        "ingest_edges_per_s": spec.num_edges / t_ing, "walk_hops_per_s": hop_rate,
+        "sample": (f"oracle ingest of the first {n} edges ({frac:.0%}, single-threaded), "
+                   f"scaled linearly to {spec.num_edges}; {len(idx)} walk ids (1%) on that "
+                   f"graph with {threads} OpenMP threads, hop rate applied to the GPU step's "
+                   f"hop count"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import synth
+    import paper_2605_16182_amd as tw
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    w = synth.workload(args.workload)
+    spec = w["stream"]
+    t0 = time.perf_counter()
+    src, dst, ts = spec.all()
+    gen_s = time.perf_counter() - t0
+    span = int(ts.max() - ts.min())
+    tau = float(w.get("tau_frac", 0.0) * span)
+    d_src = torch.from_numpy(src).to(dev)
+    d_dst = torch.from_numpy(dst).to(dev)
+    d_ts = torch.from_numpy(ts).to(dev)
+    W, L = w["walks"], w["max_len"]
+    out = (torch.empty((W, L), dtype=torch.int32, device=dev),
+           torch.empty((W, L), dtype=torch.int64, device=dev),
+           torch.empty(W, dtype=torch.int32, device=dev))
+    print(f"# inputs generated in {gen_s:.1f}s; span {span}; tau {tau}", file=sys.stderr, flush=True)
+
+    gather_rate, copy_bw = (0.0, 0.0) if args.no_probe else probe_rates(torch, dev)
+    print(f"# probe: {gather_rate / 1e9:.2f} G random sectors/s, copy {copy_bw / 1e9:.0f} GB/s",
+          file=sys.stderr, flush=True)
+
+    g = tw.Graph(spec.num_nodes, directed=spec.directed, window=w["window"])
+    walk_kw = dict(hop_bias=w["hop_bias"], hop_tau=tau, start_bias=w["start_bias"],
+                   start_tau=tau, seed=42, dispatch=args.dispatch, out=out)
+
+    def step(events=None):
+        g.evict_before(INT64_MAX)
+        if events:
+            events[0].record()
+        g.ingest_batch(d_src, d_dst, d_ts)
+        if events:
+            events[1].record()
+        g.sample_walks(W, L, **walk_kw)
+        if events:
+            events[2].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    hops = int((out[2].to(torch.int64) - 1).clamp_min(0).sum().item())
+    m_active = g.view_sizes()["m"]
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ingest_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    walk_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    ms_per_step = wall * 1e3 / args.steps
+    hops_check = int((out[2].to(torch.int64) - 1).clamp_min(0).sum().item())
+    assert hops_check == hops, "walks changed between steps"
+
+    wb = walk_bytes(W, hops, L, w["start_bias"], w["hop_bias"])
+    ib = ingest_bytes(spec.num_edges, 0, m_active, spec.num_nodes)
+    walk_gbs = wb / (walk_ms * 1e-3) / 1e9
+    ingest_gbs = ib / (ingest_ms * 1e-3) / 1e9
+    per_hop_sectors = 3 if w["hop_bias"] == "uniform" else 4
+    gather_roof_hops = gather_rate / per_hop_sectors if gather_rate else None
+    walk_hops_s = hops / (walk_ms * 1e-3)
+    res = {
+        "metric": METRIC,
+        "value": hops / (ms_per_step * 1e-3),
+        "unit": "hops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64+f64",
+        "data": "synthetic",
+        "config": describe(args.workload, w, tau),
+        "dispatch": args.dispatch,
+        "hops_per_step": hops,
+        "walk_ms": walk_ms,
+        "ingest_ms": ingest_ms,
+        "walk_hops_per_s": walk_hops_s,
+        "ingest_edges_per_s": spec.num_edges / (ingest_ms * 1e-3),
+        "roofline": {"bound": "hbm", "kernel": "k_walk_full", "achieved": walk_gbs,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": walk_gbs / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes": wb},
+        "roofline_ingest": {"bound": "hbm", "achieved": ingest_gbs, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": ingest_gbs / HBM_PEAK_GBS,
+                            "algorithmic_bytes": ib,
+                            "copy_GBps_measured": copy_bw / 1e9},
+        "gather_roofline": {"random_sectors_per_s": gather_rate,
+                            "sectors_per_hop": per_hop_sectors,
+                            "hops_per_s_roof": gather_roof_hops,
+                            "frac": (walk_hops_s / gather_roof_hops) if gather_roof_hops else None},
+    }
+    g.close()
+    if not args.no_cpu_baseline:
+        print("# oracle baseline ...", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(w, tau, hops)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -32,20 +32,24 @@ inline dim3 grid_for(int64_t n, int per_thread = 1) {
 __device__ __host__ inline uint64_t ord(int64_t x) { return (uint64_t)x ^ 0x8000000000000000ull; }
 __device__ __host__ inline int64_t unord(uint64_t x) { return (int64_t)(x ^ 0x8000000000000000ull); }
 
-// scalars[0] = min ts (ordered), scalars[1] = max ts (ordered)
+// scalars[0] = min ts (ordered), scalars[1] = max ts (ordered). Grid-stride
+// over the batch so that only one pair of atomics per block reaches memory.
 __global__ void k_stage(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
                         const int64_t* __restrict__ ts, int64_t n, int32_t V, int directed,
                         int32_t* __restrict__ b_src, int32_t* __restrict__ b_dst,
                         int64_t* __restrict__ b_ts, uint32_t* err,
                         unsigned long long* scalars) {
     __shared__ unsigned long long smin[T], smax[T];
-    int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
     unsigned long long lo = ~0ull, hi = 0ull;
-    if (i < n) {
+    bool bad = false;
+    const int64_t stride = (int64_t)gridDim.x * T;
+    for (int64_t i = (int64_t)blockIdx.x * T + threadIdx.x; i < n; i += stride) {
         int32_t u = src[i], v = dst[i];
         int64_t t = ts[i];
-        if (u < 0 || u >= V || v < 0 || v >= V) atomicOr(err, 1u);
-        lo = hi = ord(t);
+        bad |= (u < 0 || u >= V || v < 0 || v >= V);
+        unsigned long long o = ord(t);
+        lo = o < lo ? o : lo;
+        hi = o > hi ? o : hi;
         if (directed) {
             b_src[i] = u; b_dst[i] = v; b_ts[i] = t;
         } else {
@@ -53,6 +57,7 @@ __global__ void k_stage(const int32_t* __restrict__ src, const int32_t* __restri
             b_src[2 * i + 1] = v; b_dst[2 * i + 1] = u; b_ts[2 * i + 1] = t;
         }
     }
+    if (bad) atomicOr(err, 1u);
     smin[threadIdx.x] = lo;
     smax[threadIdx.x] = hi;
     __syncthreads();
@@ -194,22 +199,40 @@ __global__ void k_node_group_flags(const uint32_t* __restrict__ n_src,
         flags[i] = (i == 0 || n_src[i] != n_src[i - 1] || n_ts[i] != n_ts[i - 1]) ? 1u : 0u;
 }
 
-// For each node-run boundary i in [0, m], nodes (prev src, this src] start at
-// edge i and at group gidx[i] (Gn at i == m).
-__global__ void k_node_starts(const uint32_t* __restrict__ n_src, int64_t m, int32_t V,
-                              const uint32_t* __restrict__ gidx, const uint32_t* Gn,
-                              uint32_t* __restrict__ node_e, uint32_t* __restrict__ node_g) {
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
     int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
-    if (i > m) return;
-    bool boundary = (i == 0) || (i == m) || (n_src[i] != n_src[i - 1]);
-    if (!boundary) return;
-    int64_t lo = (i == 0) ? 0 : (int64_t)n_src[i - 1] + 1;
-    int64_t hi = (i == m) ? (int64_t)V : (int64_t)n_src[i];
-    uint32_t gs = (i == m) ? *Gn : gidx[i];
-    for (int64_t v = lo; v <= hi; ++v) {
-        node_e[v] = (uint32_t)i;
-        node_g[v] = gs;
+    if (i < n) p[i] = v;
+}
+
+// Per node present in the node view: first edge and one past its last edge.
+__global__ void k_run_bounds(const uint32_t* __restrict__ n_src, int64_t m,
+                             uint32_t* __restrict__ first, uint32_t* __restrict__ end) {
+    int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (i >= m) return;
+    uint32_t u = n_src[i];
+    if (i == 0 || n_src[i - 1] != u) first[u] = (uint32_t)i;
+    if (i == m - 1 || n_src[i + 1] != u) end[u] = (uint32_t)(i + 1);
+}
+
+// Edge and group counts per node (in place over first / end); the exclusive
+// scans of these counts are the node offsets. gidx is the exclusive scan of
+// the (node, timestamp) group flags, so gidx[j] counts groups starting before
+// edge j, and Gn stands for gidx[m].
+__global__ void k_node_counts(uint32_t* __restrict__ first_to_ecnt,
+                              uint32_t* __restrict__ end_to_gcnt, int32_t V, int64_t m,
+                              const uint32_t* __restrict__ gidx, const uint32_t* Gn) {
+    int64_t v = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (v > V) return;
+    if (v == V) {
+        first_to_ecnt[v] = 0;
+        end_to_gcnt[v] = 0;
+        return;
     }
+    uint32_t f = first_to_ecnt[v], e = end_to_gcnt[v];
+    uint32_t ge = (int64_t)e >= m ? *Gn : gidx[e];
+    uint32_t gc = e > f ? ge - gidx[f] : 0;
+    first_to_ecnt[v] = e - f;
+    end_to_gcnt[v] = gc;
 }
 
 __global__ void k_node_records(const uint32_t* __restrict__ node_e,
@@ -302,11 +325,15 @@ tw_status rebuild_views(tw_graph* g, Error& err) {
     hipLaunchKernelGGL(k_ts_group_scatter, grid_for(m), dim3(T), 0, s, g->n_ts.as<int64_t>(), m,
                        flags, gidx, g->ng_ts.as<int64_t>(), g->ng_off.as<uint32_t>(), sc + 3);
 
-    // node table
+    // node table: per-node edge / group counts, then their exclusive scans
     uint32_t* node_e = perm;               // reuse: V+1 entries each
     uint32_t* node_g = perm + (V + 1);
-    hipLaunchKernelGGL(k_node_starts, grid_for(m + 1), dim3(T), 0, s, keys, m, (int32_t)V, gidx,
-                       sc + 3, node_e, node_g);
+    hipLaunchKernelGGL(k_fill_u32, grid_for(2 * (V + 1)), dim3(T), 0, s, perm, 2 * (V + 1), 0u);
+    hipLaunchKernelGGL(k_run_bounds, grid_for(m), dim3(T), 0, s, keys, m, node_e, node_g);
+    hipLaunchKernelGGL(k_node_counts, grid_for(V + 1), dim3(T), 0, s, node_e, node_g,
+                       (int32_t)V, m, gidx, sc + 3);
+    TW_HIP(scan_exclusive_u32(node_e, node_e, V + 1, nullptr, g->ws, s));
+    TW_HIP(scan_exclusive_u32(node_g, node_g, V + 1, nullptr, g->ws, s));
     hipLaunchKernelGGL(k_node_records, grid_for(V), dim3(T), 0, s, node_e, node_g, (int32_t)V,
                        g->ng_ts.as<int64_t>(), g->rec.as<NodeRec>());
     TW_HIP(hipGetLastError());
@@ -363,7 +390,8 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
     int32_t* s_dst = g->b_dst.as<int32_t>();
     int64_t* s_ts = g->b_ts.as<int64_t>();
     if (n > 0)
-        hipLaunchKernelGGL(k_stage, grid_for(n), dim3(T), 0, s, src, dst, ts, n, g->V,
+        hipLaunchKernelGGL(k_stage, dim3((unsigned)std::min<int64_t>(ceil_div(n, T), 2048)),
+                           dim3(T), 0, s, src, dst, ts, n, g->V,
                            g->directed ? 1 : 0, s_src, s_dst, s_ts, errf + 1, mm);
     TW_HIP(hipGetLastError());
     unsigned long long hmm[2];
