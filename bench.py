@@ -198,11 +198,15 @@ def main():
         if events:
             events[2].record()
 
+    def count_hops():
+        return int((out[2].to(torch.int64) - 1).clamp_min(0).sum().item())
+
+    hops = None
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    hops = int((out[2].to(torch.int64) - 1).clamp_min(0).sum().item())
-    m_active = g.view_sizes()["m"]
+    if args.warmup:
+        hops = count_hops()
 
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -214,8 +218,10 @@ def main():
     ingest_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     walk_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     ms_per_step = wall * 1e3 / args.steps
-    hops_check = int((out[2].to(torch.int64) - 1).clamp_min(0).sum().item())
-    assert hops_check == hops, "walks changed between steps"
+    hops_check = count_hops()
+    assert hops is None or hops_check == hops, "walks changed between steps"
+    hops = hops_check
+    m_active = g.view_sizes()["m"]
 
     wb = walk_bytes(W, hops, L, w["start_bias"], w["hop_bias"])
     ib = ingest_bytes(spec.num_edges, 0, m_active, spec.num_nodes)

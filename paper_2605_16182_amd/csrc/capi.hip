@@ -73,10 +73,10 @@ tw_status tw_destroy(tw_graph* g) {
         hipStreamSynchronize(g->stream);
         tw::DevBuf* bufs[] = {&g->e_src, &g->e_dst, &g->e_ts, &g->a_src, &g->a_dst, &g->a_ts,
                               &g->gg_ts, &g->gg_off, &g->n_dst, &g->n_ts, &g->ng_ts, &g->ng_off,
-                              &g->n_src, &g->rec, &g->adj, &g->b_src, &g->b_dst, &g->b_ts,
+                              &g->n_src, &g->ng_node, &g->fence, &g->rec, &g->adj, &g->b_src, &g->b_dst, &g->b_ts,
                               &g->b_keys, &g->b_vals, &g->b_flags, &g->flags, &g->idx, &g->err,
                               &g->scal, &g->ws.scan_part, &g->ws.hist, &g->ws.keys_alt,
-                              &g->ws.vals_alt, &g->ws.misc};
+                              &g->ws.vals_alt, &g->ws.v64_alt, &g->ws.misc};
         for (tw::DevBuf* b : bufs) tw::release(*b);
         delete g;
         return TW_OK;
@@ -168,10 +168,10 @@ int64_t tw_device_bytes(const tw_graph* g) {
     if (!g) return 0;
     const tw::DevBuf* bufs[] = {&g->e_src, &g->e_dst, &g->e_ts, &g->a_src, &g->a_dst, &g->a_ts,
                                 &g->gg_ts, &g->gg_off, &g->n_dst, &g->n_ts, &g->ng_ts, &g->ng_off,
-                                &g->n_src, &g->rec, &g->adj, &g->b_src, &g->b_dst, &g->b_ts,
+                                &g->n_src, &g->ng_node, &g->fence, &g->rec, &g->adj, &g->b_src, &g->b_dst, &g->b_ts,
                                 &g->b_keys, &g->b_vals, &g->b_flags, &g->flags, &g->idx, &g->err,
                                 &g->scal, &g->ws.scan_part, &g->ws.hist, &g->ws.keys_alt,
-                                &g->ws.vals_alt, &g->ws.misc};
+                                &g->ws.vals_alt, &g->ws.v64_alt, &g->ws.misc};
     int64_t total = 0;
     for (const tw::DevBuf* b : bufs) total += (int64_t)b->bytes;
     return total;

@@ -38,15 +38,16 @@ __global__ void k_stage(const int32_t* __restrict__ src, const int32_t* __restri
                         const int64_t* __restrict__ ts, int64_t n, int32_t V, int directed,
                         int32_t* __restrict__ b_src, int32_t* __restrict__ b_dst,
                         int64_t* __restrict__ b_ts, uint32_t* err,
-                        unsigned long long* scalars) {
+                        unsigned long long* scalars, uint32_t* unsorted) {
     __shared__ unsigned long long smin[T], smax[T];
     unsigned long long lo = ~0ull, hi = 0ull;
-    bool bad = false;
+    bool bad = false, down = false;
     const int64_t stride = (int64_t)gridDim.x * T;
     for (int64_t i = (int64_t)blockIdx.x * T + threadIdx.x; i < n; i += stride) {
         int32_t u = src[i], v = dst[i];
         int64_t t = ts[i];
         bad |= (u < 0 || u >= V || v < 0 || v >= V);
+        down |= (i > 0 && ts[i - 1] > t);
         unsigned long long o = ord(t);
         lo = o < lo ? o : lo;
         hi = o > hi ? o : hi;
@@ -58,6 +59,7 @@ __global__ void k_stage(const int32_t* __restrict__ src, const int32_t* __restri
         }
     }
     if (bad) atomicOr(err, 1u);
+    if (down) atomicOr(unsorted, 1u);
     smin[threadIdx.x] = lo;
     smax[threadIdx.x] = hi;
     __syncthreads();
@@ -74,10 +76,23 @@ __global__ void k_stage(const int32_t* __restrict__ src, const int32_t* __restri
     }
 }
 
-__global__ void k_init_minmax(unsigned long long* scalars, uint32_t* err) {
+__global__ void k_init_minmax(unsigned long long* scalars, uint32_t* err, uint32_t* unsorted) {
     scalars[0] = ~0ull;
     scalars[1] = 0ull;
     *err = 0u;
+    *unsorted = 0u;
+}
+
+// first index of the sorted ts[0..n) with ts >= cut, and ts at that index
+__global__ void k_sorted_cut(const int64_t* __restrict__ ts, int64_t n, int64_t cut,
+                             uint32_t* pos, int64_t* first_ts) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (ts[mid] < cut) lo = mid + 1; else hi = mid;
+    }
+    *pos = (uint32_t)lo;
+    *first_ts = lo < n ? ts[lo] : INT64_MAX;
 }
 
 // keep flag of staged records for the late-edge drop
@@ -171,24 +186,36 @@ __global__ void k_ts_group_scatter(const int64_t* __restrict__ ts, int64_t m,
     if (i == 0) g_off[*G] = (uint32_t)m;
 }
 
-__global__ void k_src_keys(const int32_t* __restrict__ src, int64_t m, uint32_t* __restrict__ keys,
-                           uint32_t* __restrict__ vals) {
+// (node, timestamp) groups of the node view, with the node of each group
+__global__ void k_node_group_scatter(const int64_t* __restrict__ ts,
+                                     const uint32_t* __restrict__ n_src, int64_t m,
+                                     const uint32_t* __restrict__ flags,
+                                     const uint32_t* __restrict__ gidx, int64_t* __restrict__ g_ts,
+                                     uint32_t* __restrict__ g_off, uint32_t* __restrict__ g_node,
+                                     const uint32_t* G) {
     int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
-    if (i < m) {
-        keys[i] = (uint32_t)src[i];
-        vals[i] = (uint32_t)i;
+    if (i < m && flags[i]) {
+        uint32_t k = gidx[i];
+        g_ts[k] = ts[i];
+        g_off[k] = (uint32_t)i;
+        g_node[k] = n_src[i];
     }
+    if (i == 0) g_off[*G] = (uint32_t)m;
 }
 
-__global__ void k_node_gather(const uint32_t* __restrict__ perm, int64_t m,
-                              const int32_t* __restrict__ e_dst, const int64_t* __restrict__ e_ts,
-                              int32_t* __restrict__ n_dst, int64_t* __restrict__ n_ts) {
-    int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
-    if (i < m) {
-        uint32_t j = perm[i];
-        n_dst[i] = e_dst[j];
-        n_ts[i] = e_ts[j];
+// levels K and total entries of the fence of a node with G groups
+__device__ __forceinline__ void fence_shape(uint32_t G, uint32_t* levels, uint32_t* size) {
+    uint32_t K = 0, total = 0;
+    if (G > (uint32_t)FENCE_FAN) {
+        uint64_t n = G;
+        do {
+            n = (n + FENCE_FAN - 1) / FENCE_FAN;
+            ++K;
+            total += (uint32_t)((n + FENCE_FAN - 1) / FENCE_FAN * FENCE_FAN);
+        } while (n > (uint64_t)FENCE_FAN);
     }
+    *levels = K;
+    *size = total;
 }
 
 __global__ void k_node_group_flags(const uint32_t* __restrict__ n_src,
@@ -235,19 +262,66 @@ __global__ void k_node_counts(uint32_t* __restrict__ first_to_ecnt,
     end_to_gcnt[v] = gc;
 }
 
+// node records; fence sizes of every node into fsize[v] (fsize[V] = 0)
 __global__ void k_node_records(const uint32_t* __restrict__ node_e,
                                const uint32_t* __restrict__ node_g, int32_t V,
-                               const int64_t* __restrict__ ng_ts, NodeRec* __restrict__ rec) {
+                               const int64_t* __restrict__ ng_ts, NodeRec* __restrict__ rec,
+                               uint32_t* __restrict__ fsize) {
     int64_t v = (int64_t)blockIdx.x * T + threadIdx.x;
-    if (v >= V) return;
+    if (v > V) return;
+    if (v == V) {
+        fsize[v] = 0;
+        return;
+    }
     NodeRec r;
     r.gb = node_g[v];
     r.ge = node_g[v + 1];
     r.eb = node_e[v];
     r.ee = node_e[v + 1];
-    r.t_first = r.gb < r.ge ? ng_ts[r.gb] : INT64_MAX;
+    uint32_t size;
+    fence_shape(r.ge - r.gb, &r.levels, &size);
+    r.fence_off = 0;
     r.t_last = r.gb < r.ge ? ng_ts[r.ge - 1] : INT64_MIN;
     rec[v] = r;
+    fsize[v] = size;
+}
+
+__global__ void k_fence_offsets(const uint32_t* __restrict__ foff, int32_t V,
+                                NodeRec* __restrict__ rec) {
+    int64_t v = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (v < V) rec[v].fence_off = foff[v];
+}
+
+__global__ void k_fill_i64(int64_t* __restrict__ p, int64_t n, int64_t v) {
+    int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Each group p whose position inside its node is a multiple of FENCE_FAN^k
+// writes its timestamp into level k of the node's fence.
+__global__ void k_fence_fill(const int64_t* __restrict__ ng_ts, const uint32_t* __restrict__ ng_node,
+                             int64_t Gn, const NodeRec* __restrict__ rec,
+                             int64_t* __restrict__ fence) {
+    int64_t p = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (p >= Gn) return;
+    const NodeRec r = rec[ng_node[p]];
+    if (r.levels == 0) return;
+    const uint64_t rel = (uint64_t)((uint32_t)p - r.gb);
+    if (rel & (FENCE_FAN - 1)) return;
+    const uint32_t G = r.ge - r.gb;
+    uint64_t nk[9];
+    uint64_t n = G;
+    for (uint32_t k = 1; k <= r.levels; ++k) {
+        n = (n + FENCE_FAN - 1) / FENCE_FAN;
+        nk[k] = n;
+    }
+    uint64_t off = r.fence_off;  // level K first
+    const int64_t t = ng_ts[p];
+    for (uint32_t k = r.levels; k >= 1; --k) {
+        const uint32_t sh = FENCE_LOG * k;
+        if ((rel & ((1ull << sh) - 1)) == 0) fence[off + (rel >> sh)] = t;
+        off += (nk[k] + FENCE_FAN - 1) / FENCE_FAN * FENCE_FAN;
+    }
 }
 
 __global__ void k_adj_keys(const uint32_t* __restrict__ n_src, const int32_t* __restrict__ n_dst,
@@ -288,8 +362,10 @@ __global__ void k_summary(const int64_t* __restrict__ ts, int64_t m, const uint3
 tw_status rebuild_views(tw_graph* g, Error& err) {
     hipStream_t s = g->stream;
     const int64_t m = g->m, V = g->V;
-    // device scalars: bytes 16..23 hold Gg, Gn; bytes 32..63 the summary
+    // device scalars: bytes 16..23 hold Gg, Gn, bytes 24..31 the fence length;
+    // bytes 32..63 the summary
     uint32_t* sc = g->scal.as<uint32_t>() + 2;  // sc[2] = Gg, sc[3] = Gn
+    uint32_t* fence_total = g->scal.as<uint32_t>() + 7;
     TW_HIP(ensure(g->flags, sizeof(uint32_t) * (m + 1)));
     TW_HIP(ensure(g->idx, sizeof(uint32_t) * (m + 1)));
     TW_HIP(ensure(g->gg_ts, sizeof(int64_t) * (m + 1)));
@@ -299,8 +375,9 @@ tw_status rebuild_views(tw_graph* g, Error& err) {
     TW_HIP(ensure(g->n_src, sizeof(uint32_t) * (m + 1)));
     TW_HIP(ensure(g->ng_ts, sizeof(int64_t) * (m + 1)));
     TW_HIP(ensure(g->ng_off, sizeof(uint32_t) * (m + 2)));
+    TW_HIP(ensure(g->ng_node, sizeof(uint32_t) * (m + 1)));
     TW_HIP(ensure(g->rec, sizeof(NodeRec) * V));
-    TW_HIP(ensure(g->b_vals, sizeof(uint32_t) * (std::max<int64_t>(m, 2 * (V + 1)) + 1)));
+    TW_HIP(ensure(g->b_vals, sizeof(uint32_t) * (3 * (V + 1) + 1)));
     uint32_t* flags = g->flags.as<uint32_t>();
     uint32_t* gidx = g->idx.as<uint32_t>();
 
@@ -310,32 +387,39 @@ tw_status rebuild_views(tw_graph* g, Error& err) {
     hipLaunchKernelGGL(k_ts_group_scatter, grid_for(m), dim3(T), 0, s, g->e_ts.as<int64_t>(), m,
                        flags, gidx, g->gg_ts.as<int64_t>(), g->gg_off.as<uint32_t>(), sc + 2);
 
-    // node view: stable sort of the timestamp view by source
+    // node view: stable sort of the timestamp view by source, carrying the
+    // destination and timestamp as payload
     uint32_t* keys = g->n_src.as<uint32_t>();
-    uint32_t* perm = g->b_vals.as<uint32_t>();
-    hipLaunchKernelGGL(k_src_keys, grid_for(m), dim3(T), 0, s, g->e_src.as<int32_t>(), m, keys, perm);
-    TW_HIP(radix_sort_u32(keys, perm, m, 0, bits_for((uint64_t)(V - 1)), g->ws, s));
-    hipLaunchKernelGGL(k_node_gather, grid_for(m), dim3(T), 0, s, perm, m, g->e_dst.as<int32_t>(),
-                       g->e_ts.as<int64_t>(), g->n_dst.as<int32_t>(), g->n_ts.as<int64_t>());
+    TW_HIP(radix_sort_u32_kv(reinterpret_cast<const uint32_t*>(g->e_src.p),
+                             reinterpret_cast<const uint32_t*>(g->e_dst.p),
+                             reinterpret_cast<const uint64_t*>(g->e_ts.p), keys,
+                             reinterpret_cast<uint32_t*>(g->n_dst.p),
+                             reinterpret_cast<uint64_t*>(g->n_ts.p), m, 0,
+                             bits_for((uint64_t)(V - 1)), g->ws, s));
 
     // (node, timestamp) groups
     hipLaunchKernelGGL(k_node_group_flags, grid_for(m), dim3(T), 0, s, keys, g->n_ts.as<int64_t>(),
                        m, flags);
     TW_HIP(scan_exclusive_u32(flags, gidx, m, sc + 3, g->ws, s));
-    hipLaunchKernelGGL(k_ts_group_scatter, grid_for(m), dim3(T), 0, s, g->n_ts.as<int64_t>(), m,
-                       flags, gidx, g->ng_ts.as<int64_t>(), g->ng_off.as<uint32_t>(), sc + 3);
+    hipLaunchKernelGGL(k_node_group_scatter, grid_for(m), dim3(T), 0, s, g->n_ts.as<int64_t>(),
+                       keys, m, flags, gidx, g->ng_ts.as<int64_t>(), g->ng_off.as<uint32_t>(),
+                       g->ng_node.as<uint32_t>(), sc + 3);
 
     // node table: per-node edge / group counts, then their exclusive scans
-    uint32_t* node_e = perm;               // reuse: V+1 entries each
-    uint32_t* node_g = perm + (V + 1);
-    hipLaunchKernelGGL(k_fill_u32, grid_for(2 * (V + 1)), dim3(T), 0, s, perm, 2 * (V + 1), 0u);
+    uint32_t* node_e = g->b_vals.as<uint32_t>();  // V+1 entries each
+    uint32_t* node_g = node_e + (V + 1);
+    uint32_t* fsize = node_g + (V + 1);
+    hipLaunchKernelGGL(k_fill_u32, grid_for(2 * (V + 1)), dim3(T), 0, s, node_e, 2 * (V + 1), 0u);
     hipLaunchKernelGGL(k_run_bounds, grid_for(m), dim3(T), 0, s, keys, m, node_e, node_g);
     hipLaunchKernelGGL(k_node_counts, grid_for(V + 1), dim3(T), 0, s, node_e, node_g,
                        (int32_t)V, m, gidx, sc + 3);
     TW_HIP(scan_exclusive_u32(node_e, node_e, V + 1, nullptr, g->ws, s));
     TW_HIP(scan_exclusive_u32(node_g, node_g, V + 1, nullptr, g->ws, s));
-    hipLaunchKernelGGL(k_node_records, grid_for(V), dim3(T), 0, s, node_e, node_g, (int32_t)V,
-                       g->ng_ts.as<int64_t>(), g->rec.as<NodeRec>());
+    hipLaunchKernelGGL(k_node_records, grid_for(V + 1), dim3(T), 0, s, node_e, node_g, (int32_t)V,
+                       g->ng_ts.as<int64_t>(), g->rec.as<NodeRec>(), fsize);
+    TW_HIP(scan_exclusive_u32(fsize, fsize, V + 1, fence_total, g->ws, s));
+    hipLaunchKernelGGL(k_fence_offsets, grid_for(V), dim3(T), 0, s, fsize, (int32_t)V,
+                       g->rec.as<NodeRec>());
     TW_HIP(hipGetLastError());
 
     int64_t* summary = g->scal.as<int64_t>() + 4;  // bytes 32..63
@@ -343,12 +427,26 @@ tw_status rebuild_views(tw_graph* g, Error& err) {
                        summary);
     TW_HIP(hipGetLastError());
     int64_t host_sum[4];
+    uint32_t host_fence = 0;
     TW_HIP(hipMemcpyAsync(host_sum, summary, sizeof(host_sum), hipMemcpyDeviceToHost, s));
+    TW_HIP(hipMemcpyAsync(&host_fence, fence_total, sizeof(host_fence), hipMemcpyDeviceToHost, s));
     TW_HIP(hipStreamSynchronize(s));
     g->Gg = host_sum[0];
     g->Gn = host_sum[1];
     g->t_min = host_sum[2];
     g->t_max = host_sum[3];
+
+    // fence levels of nodes with many groups
+    g->fence_len = host_fence;
+    TW_HIP(ensure(g->fence, sizeof(int64_t) * (host_fence + FENCE_FAN)));
+    if (host_fence > 0) {
+        hipLaunchKernelGGL(k_fill_i64, grid_for(host_fence), dim3(T), 0, s, g->fence.as<int64_t>(),
+                           (int64_t)host_fence, INT64_MAX);
+        hipLaunchKernelGGL(k_fence_fill, grid_for(g->Gn), dim3(T), 0, s, g->ng_ts.as<int64_t>(),
+                           g->ng_node.as<uint32_t>(), g->Gn, g->rec.as<NodeRec>(),
+                           g->fence.as<int64_t>());
+        TW_HIP(hipGetLastError());
+    }
     g->adj_ready = false;
     return TW_OK;
 }
@@ -374,10 +472,6 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
     TW_HIP(ensure(g->b_src, sizeof(int32_t) * (B + 1)));
     TW_HIP(ensure(g->b_dst, sizeof(int32_t) * (B + 1)));
     TW_HIP(ensure(g->b_ts, sizeof(int64_t) * (B + 1)));
-    TW_HIP(ensure(g->b_keys, sizeof(uint64_t) * (B + 1)));
-    TW_HIP(ensure(g->b_flags, sizeof(uint32_t) * (B + 1)));
-    TW_HIP(ensure(g->b_vals, sizeof(uint32_t) * (B + 1)));
-    TW_HIP(ensure(g->idx, sizeof(uint32_t) * (B + 1)));
     const int64_t m_max = g->m + B;
     TW_HIP(ensure(g->a_src, sizeof(int32_t) * (m_max + 1)));
     TW_HIP(ensure(g->a_dst, sizeof(int32_t) * (m_max + 1)));
@@ -385,19 +479,21 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
 
     unsigned long long* mm = g->scal.as<unsigned long long>();  // [0] min, [1] max
     uint32_t* errf = g->err.as<uint32_t>();
-    hipLaunchKernelGGL(k_init_minmax, dim3(1), dim3(1), 0, s, mm, errf + 1);
+    uint32_t* unsorted = g->scal.as<uint32_t>() + 6;
+    hipLaunchKernelGGL(k_init_minmax, dim3(1), dim3(1), 0, s, mm, errf + 1, unsorted);
     int32_t* s_src = g->b_src.as<int32_t>();
     int32_t* s_dst = g->b_dst.as<int32_t>();
     int64_t* s_ts = g->b_ts.as<int64_t>();
     if (n > 0)
         hipLaunchKernelGGL(k_stage, dim3((unsigned)std::min<int64_t>(ceil_div(n, T), 2048)),
-                           dim3(T), 0, s, src, dst, ts, n, g->V,
-                           g->directed ? 1 : 0, s_src, s_dst, s_ts, errf + 1, mm);
+                           dim3(T), 0, s, src, dst, ts, n, g->V, g->directed ? 1 : 0, s_src, s_dst,
+                           s_ts, errf + 1, mm, unsorted);
     TW_HIP(hipGetLastError());
     unsigned long long hmm[2];
-    uint32_t herr = 0;
+    uint32_t herr = 0, hunsorted = 0;
     TW_HIP(hipMemcpyAsync(hmm, mm, sizeof(hmm), hipMemcpyDeviceToHost, s));
     TW_HIP(hipMemcpyAsync(&herr, errf + 1, sizeof(herr), hipMemcpyDeviceToHost, s));
+    TW_HIP(hipMemcpyAsync(&hunsorted, unsorted, sizeof(hunsorted), hipMemcpyDeviceToHost, s));
     TW_HIP(hipStreamSynchronize(s));
     if (herr) {
         err = Error{TW_ERANGE, "ingest_batch: node id outside [0, num_nodes)"};
@@ -410,71 +506,106 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
         g->t_now = g->has_time ? std::max(g->t_now, bmax) : bmax;
         g->has_time = true;
     }
+    const bool sorted = hunsorted == 0;
 
-    // window cut and late drop
-    bool windowed = g->window > 0 && g->has_time;
+    // window cut, late drop and eviction counts
+    const bool windowed = g->window > 0 && g->has_time;
     int64_t cut = INT64_MIN;
-    if (windowed) {
-        // t_now - window, saturating
-        cut = (g->t_now < INT64_MIN + g->window) ? INT64_MIN : g->t_now - g->window;
-    }
-    uint32_t* sc = g->scal.as<uint32_t>() + 24;  // [0] kept, [1] evicted (bytes 96..103)
-    int64_t kept = B;
-    uint64_t* keys = g->b_keys.as<uint64_t>();
-    uint32_t* vals = g->b_vals.as<uint32_t>();
-    bool drop = windowed && B > 0 && bmin < cut;
+    if (windowed) cut = (g->t_now < INT64_MIN + g->window) ? INT64_MIN : g->t_now - g->window;
+    uint32_t* sc = g->scal.as<uint32_t>() + 24;          // [0] kept / cut position, [1] evicted
+    int64_t* first_kept = g->scal.as<int64_t>() + 13;    // bytes 104..111
+    const bool drop = windowed && B > 0 && bmin < cut;
+    const bool evicting = windowed && g->m > 0 && g->t_min < cut;
+    int64_t kept = B, evicted = 0, batch_first = bmin, drop_lo = 0;
     int64_t key_base = drop ? cut : bmin;
-    if (drop) {
-        uint32_t* fl = g->b_flags.as<uint32_t>();
-        uint32_t* pos = g->idx.as<uint32_t>();
-        hipLaunchKernelGGL(k_keep_flags, grid_for(B), dim3(T), 0, s, s_ts, B, cut, fl);
-        TW_HIP(scan_exclusive_u32(fl, pos, B, sc, g->ws, s));
-        hipLaunchKernelGGL(k_make_keys, grid_for(B), dim3(T), 0, s, s_ts, B, key_base, fl, pos,
-                           keys, vals);
-    } else if (B > 0) {
-        hipLaunchKernelGGL(k_make_keys, grid_for(B), dim3(T), 0, s, s_ts, B, key_base, nullptr,
-                           nullptr, keys, vals);
+    uint64_t* keys = nullptr;
+    uint32_t* vals = nullptr;
+    if (drop && sorted) {
+        // late records of a sorted batch are a prefix
+        hipLaunchKernelGGL(k_sorted_cut, dim3(1), dim3(1), 0, s, s_ts, B, cut, sc, first_kept);
+    } else if (!sorted && B > 0) {
+        TW_HIP(ensure(g->b_keys, sizeof(uint64_t) * (B + 1)));
+        TW_HIP(ensure(g->b_vals, sizeof(uint32_t) * (B + 1)));
+        keys = g->b_keys.as<uint64_t>();
+        vals = g->b_vals.as<uint32_t>();
+        if (drop) {
+            TW_HIP(ensure(g->b_flags, sizeof(uint32_t) * (B + 1)));
+            TW_HIP(ensure(g->idx, sizeof(uint32_t) * (B + 1)));
+            uint32_t* fl = g->b_flags.as<uint32_t>();
+            uint32_t* pos = g->idx.as<uint32_t>();
+            hipLaunchKernelGGL(k_keep_flags, grid_for(B), dim3(T), 0, s, s_ts, B, cut, fl);
+            TW_HIP(scan_exclusive_u32(fl, pos, B, sc, g->ws, s));
+            hipLaunchKernelGGL(k_make_keys, grid_for(B), dim3(T), 0, s, s_ts, B, key_base, fl,
+                               pos, keys, vals);
+        } else {
+            hipLaunchKernelGGL(k_make_keys, grid_for(B), dim3(T), 0, s, s_ts, B, key_base, nullptr,
+                               nullptr, keys, vals);
+        }
     }
-    int64_t evicted = 0;
-    if (windowed && g->m > 0 && g->t_min < cut)
+    if (evicting)
         hipLaunchKernelGGL(k_lower_bound, dim3(1), dim3(1), 0, s, g->e_ts.as<int64_t>(), g->m, cut,
                            sc + 1);
     TW_HIP(hipGetLastError());
-    if (drop || (windowed && g->m > 0 && g->t_min < cut)) {
-        uint32_t h2[2] = {(uint32_t)B, 0};
+    if (drop || evicting) {
+        uint32_t h2[2] = {0, 0};
+        int64_t hf = INT64_MAX;
         TW_HIP(hipMemcpyAsync(h2, sc, sizeof(h2), hipMemcpyDeviceToHost, s));
+        TW_HIP(hipMemcpyAsync(&hf, first_kept, sizeof(hf), hipMemcpyDeviceToHost, s));
         TW_HIP(hipStreamSynchronize(s));
-        if (drop) kept = h2[0];
-        if (windowed && g->m > 0 && g->t_min < cut) evicted = h2[1];
+        if (drop && sorted) {
+            drop_lo = h2[0];
+            kept = B - drop_lo;
+            batch_first = hf;
+        } else if (drop) {
+            kept = h2[0];
+            batch_first = cut;  // a lower bound of the kept records
+        }
+        if (evicting) evicted = h2[1];
     }
 
-    // sort the kept batch records by timestamp (stable) and gather them
-    int32_t* o_src = g->b_src.as<int32_t>();
-    if (kept > 0) {
+    // the kept batch records in timestamp order (stable)
+    const int32_t* q_src = s_src + drop_lo;
+    const int32_t* q_dst = s_dst + drop_lo;
+    const int64_t* q_ts = s_ts + drop_lo;
+    if (!sorted && kept > 0) {
         int kb = bits_for((uint64_t)(bmax - key_base));
         TW_HIP(radix_sort_u64(keys, vals, kept, 0, kb, g->ws, s));
-    }
-    // gather into the alternate window buffers' tail region is not possible
-    // (merge reads both), so gather into a scratch SoA: keys buffer reused for ts
-    TW_HIP(ensure(g->n_src, sizeof(uint32_t) * (kept + 1)));
-    TW_HIP(ensure(g->flags, sizeof(uint32_t) * (kept + 1)));
-    int32_t* q_src = reinterpret_cast<int32_t*>(g->n_src.as<uint32_t>());
-    int32_t* q_dst = reinterpret_cast<int32_t*>(g->flags.as<uint32_t>());
-    int64_t* q_ts = reinterpret_cast<int64_t*>(keys);  // overwritten in place below
-    // keys are no longer needed once vals holds the permutation; gathering ts
-    // into the same array would race, so gather ts into b_flags first
-    if (kept > 0) {
+        TW_HIP(ensure(g->n_src, sizeof(uint32_t) * (kept + 1)));
+        TW_HIP(ensure(g->flags, sizeof(uint32_t) * (kept + 1)));
         TW_HIP(ensure(g->b_flags, sizeof(int64_t) * (kept + 1)));
-        int64_t* t_tmp = reinterpret_cast<int64_t*>(g->b_flags.as<uint32_t>());
-        hipLaunchKernelGGL(k_gather_batch, grid_for(kept), dim3(T), 0, s, vals, kept, o_src, s_dst,
-                           s_ts, q_src, q_dst, t_tmp);
-        TW_HIP(hipMemcpyAsync(q_ts, t_tmp, sizeof(int64_t) * kept, hipMemcpyDeviceToDevice, s));
+        int32_t* o_src = reinterpret_cast<int32_t*>(g->n_src.as<uint32_t>());
+        int32_t* o_dst = reinterpret_cast<int32_t*>(g->flags.as<uint32_t>());
+        int64_t* o_ts = reinterpret_cast<int64_t*>(g->b_flags.as<uint32_t>());
+        hipLaunchKernelGGL(k_gather_batch, grid_for(kept), dim3(T), 0, s, vals, kept, s_src, s_dst,
+                           s_ts, o_src, o_dst, o_ts);
+        q_src = o_src;
+        q_dst = o_dst;
+        q_ts = o_ts;
     }
 
-    // merge the surviving window with the sorted batch into the alternate buffers
+    // merge the surviving window with the batch into the alternate buffers;
+    // a batch that starts at or after the window's last timestamp is appended
     const int64_t na = g->m - evicted;
     const int64_t m_new = na + kept;
-    if (m_new > 0) {
+    const bool append = na == 0 || kept == 0 || batch_first >= g->t_max;
+    if (append) {
+        if (na > 0) {
+            TW_HIP(hipMemcpyAsync(g->a_src.p, g->e_src.as<int32_t>() + evicted, 4 * na,
+                                  hipMemcpyDeviceToDevice, s));
+            TW_HIP(hipMemcpyAsync(g->a_dst.p, g->e_dst.as<int32_t>() + evicted, 4 * na,
+                                  hipMemcpyDeviceToDevice, s));
+            TW_HIP(hipMemcpyAsync(g->a_ts.p, g->e_ts.as<int64_t>() + evicted, 8 * na,
+                                  hipMemcpyDeviceToDevice, s));
+        }
+        if (kept > 0) {
+            TW_HIP(hipMemcpyAsync(g->a_src.as<int32_t>() + na, q_src, 4 * kept,
+                                  hipMemcpyDeviceToDevice, s));
+            TW_HIP(hipMemcpyAsync(g->a_dst.as<int32_t>() + na, q_dst, 4 * kept,
+                                  hipMemcpyDeviceToDevice, s));
+            TW_HIP(hipMemcpyAsync(g->a_ts.as<int64_t>() + na, q_ts, 8 * kept,
+                                  hipMemcpyDeviceToDevice, s));
+        }
+    } else {
         hipLaunchKernelGGL(k_merge, grid_for(m_new, MP_ITEMS), dim3(T), 0, s,
                            g->e_src.as<int32_t>() + evicted, g->e_dst.as<int32_t>() + evicted,
                            g->e_ts.as<int64_t>() + evicted, na, q_src, q_dst, q_ts, kept,

@@ -130,9 +130,10 @@ __global__ void k_rs_hist(const K* __restrict__ keys, int64_t n, int shift, int 
 // first output slot of digit d for tile b (exclusive scan of the histogram).
 template <typename K>
 __global__ void __launch_bounds__(RS_THREADS)
-k_rs_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n, int shift,
-             int nbits, const uint32_t* __restrict__ offs, int64_t nblocks,
-             K* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+k_rs_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
+             const uint64_t* __restrict__ v64, int64_t n, int shift, int nbits,
+             const uint32_t* __restrict__ offs, int64_t nblocks, K* __restrict__ keys_out,
+             uint32_t* __restrict__ vals_out, uint64_t* __restrict__ v64_out) {
     __shared__ uint32_t running[256];
     __shared__ uint32_t wcnt[RS_WAVES][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -148,6 +149,7 @@ k_rs_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals, int6
         bool valid = i < n;
         K k = valid ? keys[i] : K(0);
         uint32_t v = (valid && vals) ? vals[i] : 0u;
+        uint64_t v2 = (valid && v64) ? v64[i] : 0ull;
         uint32_t d = (uint32_t)(k >> shift) & mask;
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < nbits; ++b) {
@@ -163,6 +165,7 @@ k_rs_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals, int6
             for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
             keys_out[pos] = k;
             if (vals_out) vals_out[pos] = v;
+            if (v64_out) v64_out[pos] = v2;
         }
         __syncthreads();
         uint32_t add = 0;
@@ -176,38 +179,67 @@ k_rs_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals, int6
     }
 }
 
+// Sort (kin, vin, win) into (kout, vout, wout). Inputs are only read; when
+// they alias the outputs the sort works in place. Passes alternate between
+// the outputs and the workspace buffers, arranged so that the last pass
+// lands in the outputs (a final copy happens only for an in-place sort with
+// an odd number of passes).
 template <typename K>
-hipError_t radix_sort_impl(K* keys, uint32_t* vals, int64_t n, int bit_lo, int bit_hi,
+hipError_t radix_sort_impl(const K* kin0, const uint32_t* vin0, const uint64_t* win0, K* kout,
+                           uint32_t* vout, uint64_t* wout, int64_t n, int bit_lo, int bit_hi,
                            Workspace& ws, hipStream_t s) {
-    if (n <= 1 || bit_hi <= bit_lo) return hipSuccess;
-    int64_t nblocks = ceil_div(n, RS_TILE);
     hipError_t e;
+    const bool has_v = vout != nullptr, has_w = wout != nullptr;
+    if (bit_hi <= bit_lo || n <= 1) {
+        if (n > 0 && kin0 != kout) {
+            if ((e = hipMemcpyAsync(kout, kin0, sizeof(K) * n, hipMemcpyDeviceToDevice, s)))
+                return e;
+            if (has_v && (e = hipMemcpyAsync(vout, vin0, 4 * n, hipMemcpyDeviceToDevice, s)))
+                return e;
+            if (has_w && (e = hipMemcpyAsync(wout, win0, 8 * n, hipMemcpyDeviceToDevice, s)))
+                return e;
+        }
+        return hipSuccess;
+    }
+    int64_t nblocks = ceil_div(n, RS_TILE);
     if ((e = ensure(ws.hist, sizeof(uint32_t) * 256 * nblocks)) != hipSuccess) return e;
     if ((e = ensure(ws.keys_alt, sizeof(K) * n)) != hipSuccess) return e;
-    if (vals && (e = ensure(ws.vals_alt, sizeof(uint32_t) * n)) != hipSuccess) return e;
-    K* kin = keys;
-    uint32_t* vin = vals;
-    K* kout = ws.keys_alt.as<K>();
-    uint32_t* vout = vals ? ws.vals_alt.as<uint32_t>() : nullptr;
+    if (has_v && (e = ensure(ws.vals_alt, sizeof(uint32_t) * n)) != hipSuccess) return e;
+    if (has_w && (e = ensure(ws.v64_alt, sizeof(uint64_t) * n)) != hipSuccess) return e;
+    const int passes = (int)ceil_div(bit_hi - bit_lo, 8);
+    const bool in_place = (const void*)kin0 == (const void*)kout;
+    K* ka = ws.keys_alt.as<K>();
+    uint32_t* va = has_v ? ws.vals_alt.as<uint32_t>() : nullptr;
+    uint64_t* wa = has_w ? ws.v64_alt.as<uint64_t>() : nullptr;
+    // destination of pass p (0-based): the outputs when (passes - 1 - p) is
+    // even, else the alternates; an in-place sort must start in the alternates
+    bool copy_back = in_place && (passes % 2 == 1);
     uint32_t* hist = ws.hist.as<uint32_t>();
-    for (int sh = bit_lo; sh < bit_hi; sh += 8) {
+    const K* ki = kin0;
+    const uint32_t* vi = vin0;
+    const uint64_t* wi = win0;
+    for (int p = 0; p < passes; ++p) {
+        int sh = bit_lo + 8 * p;
         int nb = bit_hi - sh < 8 ? bit_hi - sh : 8;
-        hipLaunchKernelGGL(k_rs_hist<K>, dim3(nblocks), dim3(RS_THREADS), 0, s, kin, n, sh, nb,
+        bool to_out = copy_back ? (p % 2 == 1) : ((passes - 1 - p) % 2 == 0);
+        K* ko = to_out ? kout : ka;
+        uint32_t* vo = to_out ? vout : va;
+        uint64_t* wo = to_out ? wout : wa;
+        hipLaunchKernelGGL(k_rs_hist<K>, dim3(nblocks), dim3(RS_THREADS), 0, s, ki, n, sh, nb,
                            hist, nblocks);
         if ((e = scan_exclusive_u32(hist, hist, 256 * nblocks, nullptr, ws, s)) != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_rs_scatter<K>, dim3(nblocks), dim3(RS_THREADS), 0, s, kin, vin, n, sh,
-                           nb, hist, nblocks, kout, vout);
-        K* tk = kin; kin = kout; kout = tk;
-        uint32_t* tv = vin; vin = vout; vout = tv;
+        hipLaunchKernelGGL(k_rs_scatter<K>, dim3(nblocks), dim3(RS_THREADS), 0, s, ki,
+                           has_v ? vi : nullptr, has_w ? wi : nullptr, n, sh, nb, hist, nblocks,
+                           ko, vo, wo);
+        ki = ko;
+        vi = vo;
+        wi = wo;
     }
-    if (kin != keys) {
-        if ((e = hipMemcpyAsync(keys, kin, sizeof(K) * n, hipMemcpyDeviceToDevice, s)) !=
-            hipSuccess)
-            return e;
-        if (vals && (e = hipMemcpyAsync(vals, vin, sizeof(uint32_t) * n,
-                                        hipMemcpyDeviceToDevice, s)) != hipSuccess)
-            return e;
+    if (copy_back) {
+        if ((e = hipMemcpyAsync(kout, ka, sizeof(K) * n, hipMemcpyDeviceToDevice, s))) return e;
+        if (has_v && (e = hipMemcpyAsync(vout, va, 4 * n, hipMemcpyDeviceToDevice, s))) return e;
+        if (has_w && (e = hipMemcpyAsync(wout, wa, 8 * n, hipMemcpyDeviceToDevice, s))) return e;
     }
     return hipGetLastError();
 }
@@ -259,12 +291,20 @@ hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint
 
 hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bit_lo, int bit_hi,
                           Workspace& ws, hipStream_t s) {
-    return radix_sort_impl<uint64_t>(keys, vals, n, bit_lo, bit_hi, ws, s);
+    return radix_sort_impl<uint64_t>(keys, vals, nullptr, keys, vals, nullptr, n, bit_lo, bit_hi,
+                                     ws, s);
 }
 
 hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bit_lo, int bit_hi,
                           Workspace& ws, hipStream_t s) {
-    return radix_sort_impl<uint32_t>(keys, vals, n, bit_lo, bit_hi, ws, s);
+    return radix_sort_impl<uint32_t>(keys, vals, nullptr, keys, vals, nullptr, n, bit_lo, bit_hi,
+                                     ws, s);
+}
+
+hipError_t radix_sort_u32_kv(const uint32_t* kin, const uint32_t* vin, const uint64_t* win,
+                             uint32_t* kout, uint32_t* vout, uint64_t* wout, int64_t n, int bit_lo,
+                             int bit_hi, Workspace& ws, hipStream_t s) {
+    return radix_sort_impl<uint32_t>(kin, vin, win, kout, vout, wout, n, bit_lo, bit_hi, ws, s);
 }
 
 }  // namespace tw

@@ -16,12 +16,22 @@ constexpr int64_t TS_NONE = INT64_MIN;
 
 // One record per node, 32 bytes so a hop reads all of it with one
 // contiguous load: the node's range of (node, timestamp) groups [gb, ge),
-// its edge range [eb, ee) in the node view, and the first / last group
-// timestamps (t_last lets a hop that cannot continue stop without searching).
+// its edge range [eb, ee) in the node view, where its fence levels start in
+// the fence array and how many there are, and the last group timestamp
+// (t_last lets a hop that cannot continue stop without searching).
 struct alignas(32) NodeRec {
     uint32_t gb, ge, eb, ee;
-    int64_t t_first, t_last;
+    uint32_t fence_off, levels;
+    int64_t t_last;
 };
+
+// Fence index: for a node with G > FENCE_FAN groups, level k (k = 1..K)
+// holds every FENCE_FAN^k-th group timestamp of the node, padded to a
+// multiple of FENCE_FAN entries with INT64_MAX; levels are stored top (K)
+// first. K is the smallest level with at most FENCE_FAN entries. A search
+// reads one FENCE_FAN-entry window (one 128-byte line) per level.
+constexpr int FENCE_FAN = 16;
+constexpr int FENCE_LOG = 4;
 
 // A grow-only device allocation.
 struct DevBuf {
@@ -44,7 +54,7 @@ void release(DevBuf& b);
 struct Workspace {
     DevBuf scan_part;   // scan partial sums
     DevBuf hist;        // radix histograms
-    DevBuf keys_alt, vals_alt;
+    DevBuf keys_alt, vals_alt, v64_alt;
     DevBuf misc;        // small scalars
 };
 
@@ -62,6 +72,13 @@ hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bit_lo,
                           Workspace& ws, hipStream_t s);
 hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bit_lo, int bit_hi,
                           Workspace& ws, hipStream_t s);
+// Stable sort of (kin, vin, win) by bits [bit_lo, bit_hi) of kin into
+// (kout, vout, wout), carrying a 32-bit and a 64-bit payload (either may be
+// null). The inputs are only read; no pass writes into them unless they are
+// the outputs.
+hipError_t radix_sort_u32_kv(const uint32_t* kin, const uint32_t* vin, const uint64_t* win,
+                             uint32_t* kout, uint32_t* vout, uint64_t* wout, int64_t n, int bit_lo,
+                             int bit_hi, Workspace& ws, hipStream_t s);
 
 // Bits needed to represent values in [0, x].
 inline int bits_for(uint64_t x) {
@@ -97,6 +114,9 @@ struct tw_graph {
     tw::DevBuf n_dst, n_ts;            // node-and-timestamp view
     tw::DevBuf ng_ts, ng_off;          // its (node, timestamp) groups
     tw::DevBuf n_src;                  // source of each node-view edge (build temp)
+    tw::DevBuf ng_node;                // node of each (node, timestamp) group
+    tw::DevBuf fence;                  // fence levels of nodes with many groups
+    int64_t fence_len = 0;
     tw::DevBuf rec;                    // NodeRec[V]
     tw::DevBuf adj;                    // per-node dst sorted ascending (node2vec)
     bool adj_ready = false;

@@ -24,6 +24,7 @@ struct WalkArgs {
     const int64_t* ng_ts;
     const uint32_t* ng_off;
     const NodeRec* rec;
+    const int64_t* fence;
     const int32_t* adj;
     int32_t V;
     // parameters
@@ -103,7 +104,7 @@ __global__ void __launch_bounds__(WALK_THREADS) k_walk_full(const WalkArgs a) {
     for (uint64_t hop = 1; len < L; ++hop) {
         const NodeRec r = a.rec[cur];
         if (tcur >= r.t_last) break;  // Gamma_t(cur) is empty
-        const uint32_t gc = tcur < r.t_first ? r.gb : upper_bound_ts(a.ng_ts, r.gb, r.ge, tcur);
+        const uint32_t gc = fence_search(a.ng_ts, a.fence, r, tcur);
         Pick p;
         if (a.hop_kind == TW_NODE2VEC) {
             const NodeRec rp = a.rec[prev];
@@ -204,6 +205,7 @@ tw_status sample_walks(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int
     a.ng_ts = g->ng_ts.as<int64_t>();
     a.ng_off = g->ng_off.as<uint32_t>();
     a.rec = g->rec.as<NodeRec>();
+    a.fence = g->fence.as<int64_t>();
     a.adj = g->adj.as<int32_t>();
     a.V = g->V;
     a.num_walks = p->num_walks;

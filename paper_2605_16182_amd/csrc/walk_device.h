@@ -100,6 +100,45 @@ __device__ __forceinline__ uint32_t upper_bound_ts(const int64_t* __restrict__ t
     return lo;
 }
 
+// Gamma lookup (Sec. "Dual-Index Organization": the first timestamp group of
+// the node strictly after t) through the node's fence: one FENCE_FAN-entry
+// window per level, each a single 128-byte line, then one window of the
+// node's own group timestamps. Requires t < r.t_last, so the result is
+// below r.ge. Returns the absolute group index.
+__device__ __forceinline__ uint32_t fence_search(const int64_t* __restrict__ gts,
+                                                 const int64_t* __restrict__ fence,
+                                                 const NodeRec& r, int64_t t) {
+    const uint32_t G = r.ge - r.gb;
+    uint64_t lo = 0;
+    if (r.levels > 0) {
+        uint64_t off = r.fence_off;
+        for (int k = (int)r.levels; k >= 1; --k) {
+            const longlong2* win = reinterpret_cast<const longlong2*>(fence + off + lo);
+            uint32_t c = 0;
+#pragma unroll
+            for (int j = 0; j < FENCE_FAN / 2; ++j) {
+                const longlong2 v = win[j];
+                c += (v.x <= t) + (v.y <= t);
+            }
+            if (c == 0) return r.gb;  // only possible at the top level: t precedes the node
+            lo = (lo + c - 1) * FENCE_FAN;
+            const uint32_t sh = FENCE_LOG * (uint32_t)k;
+            const uint64_t nk = ((uint64_t)G + (1ull << sh) - 1) >> sh;
+            off += (nk + FENCE_FAN - 1) / FENCE_FAN * FENCE_FAN;
+        }
+    }
+    const int64_t* base = gts + r.gb + lo;
+    uint32_t c = 0;
+    if (lo + FENCE_FAN <= G) {
+#pragma unroll
+        for (int j = 0; j < FENCE_FAN; ++j) c += (base[j] <= t);
+    } else {
+        const uint32_t rem = (uint32_t)(G - lo);
+        for (uint32_t j = 0; j < rem; ++j) c += (base[j] <= t);
+    }
+    return r.gb + (uint32_t)lo + c;
+}
+
 // is w among the sorted values adj[lo, hi)?
 __device__ __forceinline__ bool sorted_contains(const int32_t* __restrict__ adj, uint32_t lo,
                                                 uint32_t hi, int32_t w) {

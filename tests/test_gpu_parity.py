@@ -193,3 +193,38 @@ def test_windowed_stream_walks_parity():
         assert np.array_equal(ts.cpu().numpy(), r["ts"])
         assert np.array_equal(lens.cpu().numpy(), r["len"])
     g.close()
+
+
+@pytest.mark.parametrize("groups", [1, 15, 16, 17, 255, 256, 257, 4097, 70_001])
+def test_fence_search_depths(groups):
+    # one hub whose out-edges all loop back to itself, so every hop searches
+    # the hub's groups again with a later time; two edges share each
+    # timestamp, and a second node keeps the hub off position 0 of the view
+    torch, tw = gpu_or_skip()
+    rng = np.random.default_rng(groups)
+    V = 3
+    ts_groups = np.sort(rng.choice(np.arange(10 * groups + 10), groups, replace=False))
+    t = np.repeat(ts_groups, 2).astype(np.int64)
+    src = np.full(len(t), 1, np.int32)
+    dst = np.where(np.arange(len(t)) % 2 == 0, 1, 2).astype(np.int32)
+    src = np.concatenate([src, np.array([0, 2], np.int32)])
+    dst = np.concatenate([dst, np.array([1, 1], np.int32)])
+    t = np.concatenate([t, np.array([0, 5], np.int64)])
+    g = tw.Graph(V)
+    og = oracle.OracleGraph(V)
+    g.ingest_batch(*to_dev(torch, src, dst, t))
+    og.ingest_batch(src, dst, t)
+    _views_equal(g, og)
+    W, L = 3000, 24
+    starts = np.full(W, 1, np.int32)
+    for kind in ("uniform", "linear"):
+        nodes, tts, lens = g.sample_walks(W, L, hop_bias=kind, start_bias=kind,
+                                          start_mode="node",
+                                          start_nodes=to_dev(torch, starts)[0], seed=5)
+        g.sync()
+        r = og.sample_walks(W, L, hop_bias=kind, start_bias=kind, start_mode="node",
+                            start_nodes=starts, seed=5)
+        assert np.array_equal(nodes.cpu().numpy(), r["nodes"])
+        assert np.array_equal(tts.cpu().numpy(), r["ts"])
+        assert np.array_equal(lens.cpu().numpy(), r["len"])
+    g.close()
