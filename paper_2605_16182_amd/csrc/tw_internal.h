@@ -121,6 +121,10 @@ struct tw_graph {
     tw::DevBuf adj;                    // per-node dst sorted ascending (node2vec)
     bool adj_ready = false;
 
+    // cooperative dispatch: per-walk state, live list, sort buffers
+    tw::DevBuf c_cur, c_prev, c_t, c_list, c_keys, c_skeys, c_swalks, c_flags, c_pos;
+    uint32_t coop_panel = 4096;        // LDS panel entries per workgroup
+
     // batch staging
     tw::DevBuf b_src, b_dst, b_ts, b_keys, b_vals, b_flags;
     tw::DevBuf flags, idx;             // per-edge temporaries

@@ -44,20 +44,21 @@ struct WalkArgs {
 constexpr int WALK_THREADS = 256;
 constexpr uint32_t N2V_MAX_TRIALS = 4096;
 
-// One full walk per thread: the full-walk baseline.
-__global__ void __launch_bounds__(WALK_THREADS) k_walk_full(const WalkArgs a) {
-    const int64_t w = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
-    if (w >= a.num_walks) return;
-    const uint64_t id = a.base + (uint64_t)w;
-    const int32_t L = a.L;
-    int32_t* out_n = a.nodes + w * L;
-    int64_t* out_t = a.ts + w * L;
-    int32_t len = 0, cur = 0, prev = 0;
-    int64_t tcur = 0;
+// Walk state after the first pick (RNG hop 0).
+struct StartState {
+    int32_t len;   // nodes written so far
+    int32_t cur, prev;
+    int64_t t;
+};
 
+// First pick of walk w: EDGE mode draws from the whole window, NODE mode from
+// the start node's run; writes output positions 0 and 1.
+__device__ __forceinline__ StartState walk_start(const WalkArgs& a, int64_t w, uint64_t id,
+                                                 int32_t* out_n, int64_t* out_t) {
+    StartState st{0, 0, 0, 0};
     const Draw d0 = philox(id, 0, 0, a.seed);
     if (a.start_mode == TW_START_EDGE) {
-        if (a.m == 0) goto done;
+        if (a.m == 0) return st;
         uint32_t e;
         if (a.start_kind == TW_UNIFORM) {
             e = (uint32_t)scale_u64(d0.x0, a.m);
@@ -70,85 +71,277 @@ __global__ void __launch_bounds__(WALK_THREADS) k_walk_full(const WalkArgs a) {
         const int64_t t = a.e_ts[e];
         out_n[0] = s;
         out_t[0] = TS_NONE;
-        len = 1;
-        if (L == 1) goto done;
+        st.len = 1;
+        if (a.L == 1) return st;
         out_n[1] = t_dst;
         out_t[1] = t;
-        len = 2;
-        prev = s;
-        cur = t_dst;
-        tcur = t;
-    } else {
-        const int32_t v0 = a.start_nodes[w];
-        if (v0 < 0 || v0 >= a.V) {
-            atomicOr(&a.err[0], 1u);
-            goto done;
-        }
-        out_n[0] = v0;
-        out_t[0] = TS_NONE;
-        len = 1;
-        if (L == 1) goto done;
-        const NodeRec r = a.rec[v0];
-        if (r.gb == r.ge) goto done;
-        Pick p = pick_in_groups(a.ng_ts, a.ng_off, a.n_ts, r.gb, r.ge, r.ee, a.start_kind,
-                                a.start_tau, r.t_last, d0);
-        const int32_t nx = a.n_dst[p.e];
-        out_n[1] = nx;
-        out_t[1] = p.t;
-        len = 2;
-        prev = v0;
-        cur = nx;
-        tcur = p.t;
+        st.len = 2;
+        st.prev = s;
+        st.cur = t_dst;
+        st.t = t;
+        return st;
     }
+    const int32_t v0 = a.start_nodes[w];
+    if (v0 < 0 || v0 >= a.V) {
+        atomicOr(&a.err[0], 1u);
+        return st;
+    }
+    out_n[0] = v0;
+    out_t[0] = TS_NONE;
+    st.len = 1;
+    if (a.L == 1) return st;
+    const NodeRec r = a.rec[v0];
+    if (r.gb == r.ge) return st;
+    Pick p = pick_in_groups(a.ng_ts, a.ng_off, a.n_ts, r.gb, r.ge, r.ee, a.start_kind, a.start_tau,
+                            r.t_last, d0);
+    const int32_t nx = a.n_dst[p.e];
+    out_n[1] = nx;
+    out_t[1] = p.t;
+    st.len = 2;
+    st.prev = v0;
+    st.cur = nx;
+    st.t = p.t;
+    return st;
+}
 
-    for (uint64_t hop = 1; len < L; ++hop) {
-        const NodeRec r = a.rec[cur];
-        if (tcur >= r.t_last) break;  // Gamma_t(cur) is empty
-        const uint32_t gc = fence_search(a.ng_ts, a.fence, r, tcur);
-        Pick p;
-        if (a.hop_kind == TW_NODE2VEC) {
-            const NodeRec rp = a.rec[prev];
-            bool accepted = false;
-            for (uint32_t trial = 0; trial < N2V_MAX_TRIALS; ++trial) {
-                const Draw d = philox(id, hop, trial, a.seed);
-                p = pick_in_groups(a.ng_ts, a.ng_off, a.n_ts, gc, r.ge, r.ee, TW_EXPONENTIAL,
-                                   a.hop_tau, r.t_last, d);
-                const int32_t wnode = a.n_dst[p.e];
-                double beta;
-                if (wnode == prev) beta = a.inv_p;
-                else if (sorted_contains(a.adj, rp.eb, rp.ee, wnode)) beta = 1.0;
-                else beta = a.inv_q;
-                if (unit_closed_open(d.x2) * a.beta_max < beta) {
-                    accepted = true;
-                    break;
-                }
-            }
-            if (!accepted) {
-                atomicAdd(&a.err[2], 1u);
-                break;
-            }
-        } else {
-            const Draw d = philox(id, hop, 0, a.seed);
-            p = pick_in_groups(a.ng_ts, a.ng_off, a.n_ts, gc, r.ge, r.ee, a.hop_kind, a.hop_tau,
-                               r.t_last, d);
-        }
-        const int32_t nx = a.n_dst[p.e];
-        out_n[len] = nx;
-        out_t[len] = p.t;
-        ++len;
-        prev = cur;
-        cur = nx;
-        tcur = p.t;
+// The pick of hop `hop` among groups [gc, r.ge) of node cur (previous node
+// prev): the hop bias, or node2vec's rejection loop. Returns false when
+// node2vec exhausts its trials (the walk ends).
+__device__ __forceinline__ bool hop_pick(const WalkArgs& a, const NodeRec& r, uint32_t gc,
+                                         uint64_t id, uint64_t hop, int32_t prev, Pick& p,
+                                         int32_t& nx) {
+    if (a.hop_kind != TW_NODE2VEC) {
+        const Draw d = philox(id, hop, 0, a.seed);
+        p = pick_in_groups(a.ng_ts, a.ng_off, a.n_ts, gc, r.ge, r.ee, a.hop_kind, a.hop_tau,
+                           r.t_last, d);
+        nx = a.n_dst[p.e];
+        return true;
     }
-done:
-    for (int32_t j = len; j < L; ++j) {
+    const NodeRec rp = a.rec[prev];
+    for (uint32_t trial = 0; trial < N2V_MAX_TRIALS; ++trial) {
+        const Draw d = philox(id, hop, trial, a.seed);
+        p = pick_in_groups(a.ng_ts, a.ng_off, a.n_ts, gc, r.ge, r.ee, TW_EXPONENTIAL, a.hop_tau,
+                           r.t_last, d);
+        nx = a.n_dst[p.e];
+        double beta;
+        if (nx == prev) beta = a.inv_p;
+        else if (sorted_contains(a.adj, rp.eb, rp.ee, nx)) beta = 1.0;
+        else beta = a.inv_q;
+        if (unit_closed_open(d.x2) * a.beta_max < beta) return true;
+    }
+    atomicAdd(&a.err[2], 1u);
+    return false;
+}
+
+__device__ __forceinline__ void finish_walk(const WalkArgs& a, int64_t w, int32_t len) {
+    int32_t* out_n = a.nodes + w * a.L;
+    int64_t* out_t = a.ts + w * a.L;
+    for (int32_t j = len; j < a.L; ++j) {
         out_n[j] = -1;
         out_t[j] = TS_NONE;
     }
     a.len[w] = len;
 }
 
+// One full walk per thread: the full-walk baseline (Sec. "The Full-Walk
+// Baseline").
+__global__ void __launch_bounds__(WALK_THREADS) k_walk_full(const WalkArgs a) {
+    const int64_t w = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
+    if (w >= a.num_walks) return;
+    const uint64_t id = a.base + (uint64_t)w;
+    int32_t* out_n = a.nodes + w * a.L;
+    int64_t* out_t = a.ts + w * a.L;
+    StartState st = walk_start(a, w, id, out_n, out_t);
+    int32_t len = st.len, cur = st.cur, prev = st.prev;
+    int64_t tcur = st.t;
+    if (len >= 2) {
+        for (uint64_t hop = 1; len < a.L; ++hop) {
+            const NodeRec r = a.rec[cur];
+            if (tcur >= r.t_last) break;  // Gamma_t(cur) is empty
+            const uint32_t gc = fence_search(a.ng_ts, a.fence, r, tcur, nullptr, 0);
+            Pick p;
+            int32_t nx;
+            if (!hop_pick(a, r, gc, id, hop, prev, p, nx)) break;
+            out_n[len] = nx;
+            out_t[len] = p.t;
+            ++len;
+            prev = cur;
+            cur = nx;
+            tcur = p.t;
+        }
+    }
+    finish_walk(a, w, len);
+}
+
+// ------------------------------------------------------------------ coop
+//
+// Cooperative dispatch (Sec. "Hierarchical Cooperative Scheduling"): each
+// step sorts the live walks by current node, and k_hop_coop advances them
+// in that order. A wavefront whose 64 walks share one node, or a workgroup
+// whose 256 walks do, reads the node record once and stages the top levels
+// of the node's fence in LDS (the panel); mixed chunks run one walk per
+// thread. Walks at a node with W walks thus get the workgroup tier for each
+// full 256-walk chunk, the wavefront tier for each remaining full 64-walk
+// chunk, and the thread tier otherwise; a node's walks beyond one
+// workgroup are split over several workgroups.
+
+struct CoopState {
+    int32_t* cur;
+    int32_t* prev;
+    int64_t* t;
+};
+
+__global__ void __launch_bounds__(WALK_THREADS) k_coop_start(const WalkArgs a, CoopState cs,
+                                                              uint32_t* __restrict__ alive) {
+    const int64_t w = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
+    if (w >= a.num_walks) return;
+    const uint64_t id = a.base + (uint64_t)w;
+    StartState st = walk_start(a, w, id, a.nodes + w * a.L, a.ts + w * a.L);
+    bool live = st.len >= 2 && st.len < a.L;
+    if (live) {
+        cs.cur[w] = st.cur;
+        cs.prev[w] = st.prev;
+        cs.t[w] = st.t;
+    } else {
+        finish_walk(a, w, st.len);
+    }
+    alive[w] = live ? 1u : 0u;
+}
+
+__global__ void k_compact_ids(const uint32_t* __restrict__ flags, const uint32_t* __restrict__ pos,
+                              int64_t n, const uint32_t* __restrict__ ids,
+                              uint32_t* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
+    if (i < n && flags[i]) out[pos[i]] = ids ? ids[i] : (uint32_t)i;
+}
+
+__global__ void k_coop_keys(const uint32_t* __restrict__ list, const uint32_t* n_live,
+                            const int32_t* __restrict__ cur, uint32_t* __restrict__ keys) {
+    int64_t i = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
+    if (i < *n_live) keys[i] = (uint32_t)cur[list[i]];
+}
+
+__global__ void __launch_bounds__(WALK_THREADS)
+k_hop_coop(const WalkArgs a, CoopState cs, const uint32_t* __restrict__ keys,
+           const uint32_t* __restrict__ walks, int64_t n, uint64_t hop, uint32_t panel_cap,
+           uint32_t* __restrict__ alive) {
+    extern __shared__ __align__(16) int64_t panel[];
+    __shared__ int32_t wave_node[WALK_THREADS / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
+    const bool valid = i < n;
+    const int32_t v = valid ? (int32_t)keys[i] : -1;
+    const int32_t v0 = __shfl(v, 0, 64);
+    const bool wave_uniform = __ballot(valid && v == v0) == ~0ull;
+    if (lane == 0) wave_node[wave] = wave_uniform ? v0 : -1;
+    __syncthreads();
+    bool wg_uniform = wave_node[0] >= 0;
+#pragma unroll
+    for (int k = 1; k < WALK_THREADS / 64; ++k) wg_uniform &= wave_node[k] == wave_node[0];
+
+    // stage the top of the node's fence: the whole panel for a uniform
+    // workgroup, a quarter of it per uniform wavefront otherwise
+    const int64_t* my_panel = nullptr;
+    uint32_t my_cap = 0;
+    if (wg_uniform || wave_uniform) {
+        const int32_t node = wg_uniform ? wave_node[0] : v0;
+        const NodeRec r = a.rec[node];
+        const uint32_t slice = wg_uniform ? panel_cap : panel_cap / (WALK_THREADS / 64);
+        int64_t* dst = wg_uniform ? panel : panel + wave * slice;
+        uint32_t lv, size;
+        fence_shape_dev(r.ge - r.gb, &lv, &size);
+        my_cap = size < slice ? size : slice;
+        const int first = wg_uniform ? threadIdx.x : lane;
+        const int stride = wg_uniform ? WALK_THREADS : 64;
+        for (uint32_t j = first; j < my_cap; j += stride) dst[j] = a.fence[r.fence_off + j];
+        my_panel = dst;
+    }
+    __syncthreads();
+    if (!valid) return;
+
+    const int64_t w = walks[i];
+    const uint64_t id = a.base + (uint64_t)w;
+    const NodeRec r = a.rec[v];
+    const int64_t tcur = cs.t[w];
+    const int32_t len = (int32_t)hop + 1;  // nodes written before this hop
+    bool live = false;
+    if (tcur < r.t_last) {
+        const uint32_t gc = fence_search(a.ng_ts, a.fence, r, tcur, my_panel, my_cap);
+        Pick p;
+        int32_t nx;
+        const int32_t prev = a.hop_kind == TW_NODE2VEC ? cs.prev[w] : 0;
+        if (hop_pick(a, r, gc, id, hop, prev, p, nx)) {
+            a.nodes[w * a.L + len] = nx;
+            a.ts[w * a.L + len] = p.t;
+            if (len + 1 < a.L) {
+                cs.cur[w] = nx;
+                cs.prev[w] = v;
+                cs.t[w] = p.t;
+                live = true;
+            } else {
+                a.len[w] = len + 1;
+            }
+        } else {
+            finish_walk(a, w, len);
+        }
+    } else {
+        finish_walk(a, w, len);
+    }
+    alive[i] = live ? 1u : 0u;
+}
+
 bool valid_tau(double t) { return std::isfinite(t); }
+
+// Host loop of the cooperative dispatch: one synchronisation per step (the
+// live count), then keys -> sort by node -> hop -> compaction.
+tw_status coop_walks(tw_graph* g, const WalkArgs& a, Error& err) {
+    hipStream_t s = g->stream;
+    const int64_t W = a.num_walks;
+    TW_HIP(ensure(g->c_cur, sizeof(int32_t) * W));
+    TW_HIP(ensure(g->c_prev, sizeof(int32_t) * W));
+    TW_HIP(ensure(g->c_t, sizeof(int64_t) * W));
+    TW_HIP(ensure(g->c_list, sizeof(uint32_t) * W));
+    TW_HIP(ensure(g->c_keys, sizeof(uint32_t) * W));
+    TW_HIP(ensure(g->c_skeys, sizeof(uint32_t) * W));
+    TW_HIP(ensure(g->c_swalks, sizeof(uint32_t) * W));
+    TW_HIP(ensure(g->c_flags, sizeof(uint32_t) * W));
+    TW_HIP(ensure(g->c_pos, sizeof(uint32_t) * W));
+    CoopState cs{g->c_cur.as<int32_t>(), g->c_prev.as<int32_t>(), g->c_t.as<int64_t>()};
+    uint32_t* list = g->c_list.as<uint32_t>();
+    uint32_t* keys = g->c_keys.as<uint32_t>();
+    uint32_t* skeys = g->c_skeys.as<uint32_t>();
+    uint32_t* swalks = g->c_swalks.as<uint32_t>();
+    uint32_t* flags = g->c_flags.as<uint32_t>();
+    uint32_t* pos = g->c_pos.as<uint32_t>();
+    uint32_t* n_live_d = g->scal.as<uint32_t>() + 28;  // bytes 112..115
+    const int vbits = bits_for((uint64_t)(g->V - 1));
+    const uint32_t panel_cap = g->coop_panel;
+
+    hipLaunchKernelGGL(k_coop_start, dim3((unsigned)ceil_div(W, WALK_THREADS)), dim3(WALK_THREADS),
+                       0, s, a, cs, flags);
+    TW_HIP(scan_exclusive_u32(flags, pos, W, n_live_d, g->ws, s));
+    hipLaunchKernelGGL(k_compact_ids, dim3((unsigned)ceil_div(W, WALK_THREADS)),
+                       dim3(WALK_THREADS), 0, s, flags, pos, W, nullptr, list);
+    TW_HIP(hipGetLastError());
+    for (uint64_t hop = 1; hop + 1 < (uint64_t)a.L; ++hop) {
+        uint32_t n_live = 0;
+        TW_HIP(hipMemcpyAsync(&n_live, n_live_d, sizeof(n_live), hipMemcpyDeviceToHost, s));
+        TW_HIP(hipStreamSynchronize(s));
+        if (n_live == 0) break;
+        const dim3 grid((unsigned)ceil_div(n_live, WALK_THREADS));
+        hipLaunchKernelGGL(k_coop_keys, grid, dim3(WALK_THREADS), 0, s, list, n_live_d, cs.cur,
+                           keys);
+        TW_HIP(radix_sort_u32_kv(keys, list, nullptr, skeys, swalks, nullptr, n_live, 0, vbits,
+                                 g->ws, s));
+        hipLaunchKernelGGL(k_hop_coop, grid, dim3(WALK_THREADS), sizeof(int64_t) * panel_cap, s, a,
+                           cs, skeys, swalks, (int64_t)n_live, hop, panel_cap, flags);
+        TW_HIP(scan_exclusive_u32(flags, pos, n_live, n_live_d, g->ws, s));
+        hipLaunchKernelGGL(k_compact_ids, grid, dim3(WALK_THREADS), 0, s, flags, pos,
+                           (int64_t)n_live, swalks, list);
+        TW_HIP(hipGetLastError());
+    }
+    return TW_OK;
+}
 
 }  // namespace
 
@@ -225,10 +418,15 @@ tw_status sample_walks(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int
     a.ts = ts;
     a.len = len;
     a.err = g->err.as<uint32_t>();
-    int64_t blocks = ceil_div(p->num_walks, WALK_THREADS);
-    hipLaunchKernelGGL(k_walk_full, dim3((unsigned)blocks), dim3(WALK_THREADS), 0, g->stream, a);
-    TW_HIP(hipGetLastError());
-    return TW_OK;
+    const bool coop = p->dispatch == TW_DISPATCH_COOP;
+    if (!coop) {
+        int64_t blocks = ceil_div(p->num_walks, WALK_THREADS);
+        hipLaunchKernelGGL(k_walk_full, dim3((unsigned)blocks), dim3(WALK_THREADS), 0, g->stream,
+                           a);
+        TW_HIP(hipGetLastError());
+        return TW_OK;
+    }
+    return coop_walks(g, a, err);
 }
 
 }  // namespace tw

@@ -105,15 +105,20 @@ __device__ __forceinline__ uint32_t upper_bound_ts(const int64_t* __restrict__ t
 // window per level, each a single 128-byte line, then one window of the
 // node's own group timestamps. Requires t < r.t_last, so the result is
 // below r.ge. Returns the absolute group index.
+// panel (nullable) holds the first panel_len entries of the node's fence
+// (its top levels) in LDS; windows inside it are read from there.
 __device__ __forceinline__ uint32_t fence_search(const int64_t* __restrict__ gts,
                                                  const int64_t* __restrict__ fence,
-                                                 const NodeRec& r, int64_t t) {
+                                                 const NodeRec& r, int64_t t,
+                                                 const int64_t* panel, uint32_t panel_len) {
     const uint32_t G = r.ge - r.gb;
     uint64_t lo = 0;
     if (r.levels > 0) {
         uint64_t off = r.fence_off;
         for (int k = (int)r.levels; k >= 1; --k) {
-            const longlong2* win = reinterpret_cast<const longlong2*>(fence + off + lo);
+            const uint64_t rel = off - r.fence_off + lo;
+            const longlong2* win = reinterpret_cast<const longlong2*>(
+                rel + FENCE_FAN <= panel_len ? panel + rel : fence + off + lo);
             uint32_t c = 0;
 #pragma unroll
             for (int j = 0; j < FENCE_FAN / 2; ++j) {
@@ -137,6 +142,21 @@ __device__ __forceinline__ uint32_t fence_search(const int64_t* __restrict__ gts
         for (uint32_t j = 0; j < rem; ++j) c += (base[j] <= t);
     }
     return r.gb + (uint32_t)lo + c;
+}
+
+// levels K and total entries of the fence of a node with G groups
+__device__ __forceinline__ void fence_shape_dev(uint32_t G, uint32_t* levels, uint32_t* size) {
+    uint32_t K = 0, total = 0;
+    if (G > (uint32_t)FENCE_FAN) {
+        uint64_t n = G;
+        do {
+            n = (n + FENCE_FAN - 1) / FENCE_FAN;
+            ++K;
+            total += (uint32_t)((n + FENCE_FAN - 1) / FENCE_FAN * FENCE_FAN);
+        } while (n > (uint64_t)FENCE_FAN);
+    }
+    *levels = K;
+    *size = total;
 }
 
 // is w among the sorted values adj[lo, hi)?

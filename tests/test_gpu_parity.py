@@ -102,10 +102,11 @@ WALK_CASES = [
 ]
 
 
+@pytest.mark.parametrize("dispatch", ["full_walk", "coop"])
 @pytest.mark.parametrize("ci", range(len(WALK_CASES)),
                          ids=["-".join(map(str, c[:1] + c[4:])) for c in WALK_CASES])
 @pytest.mark.parametrize("directed", [True, False])
-def test_walk_parity(ci, directed):
+def test_walk_parity(ci, directed, dispatch):
     torch, tw = gpu_or_skip()
     hk, ht, p, q, sk, st, mode = WALK_CASES[ci]
     V, m = 4000, 60000
@@ -121,7 +122,7 @@ def test_walk_parity(ci, directed):
     st_dev = to_dev(torch, starts)[0]
     nodes, tts, lens = g.sample_walks(W, L, hop_bias=hk, hop_tau=ht, p=p, q=q, start_bias=sk,
                                       start_tau=st, start_mode=mode, start_nodes=st_dev,
-                                      seed=seed, walk_id_base=base)
+                                      seed=seed, walk_id_base=base, dispatch=dispatch)
     g.sync()
     r = og.sample_walks(W, L, hop_bias=hk, hop_tau=ht, p=p, q=q, start_bias=sk, start_tau=st,
                         start_mode=mode, start_nodes=starts, seed=seed, walk_id_base=base,
@@ -130,7 +131,7 @@ def test_walk_parity(ci, directed):
     same, boundary = compare_walks((nodes.cpu().numpy(), tts.cpu().numpy(), lens.cpu().numpy()),
                                    r, exact)
     hops = int(np.maximum(r["len"] - 1, 0).sum())
-    print(f"{hk}/{sk}/{mode}: {same}/{W} identical, boundary mismatches {boundary} "
+    print(f"{dispatch} {hk}/{sk}/{mode}: {same}/{W} identical, boundary mismatches {boundary} "
           f"({boundary / max(hops, 1):.2e} per hop)")
     assert boundary <= max(2, W // 2000)
     g.close()
@@ -217,14 +218,38 @@ def test_fence_search_depths(groups):
     _views_equal(g, og)
     W, L = 3000, 24
     starts = np.full(W, 1, np.int32)
-    for kind in ("uniform", "linear"):
+    for kind, dispatch in (("uniform", "full_walk"), ("linear", "full_walk"),
+                           ("uniform", "coop"), ("linear", "coop")):
         nodes, tts, lens = g.sample_walks(W, L, hop_bias=kind, start_bias=kind,
                                           start_mode="node",
-                                          start_nodes=to_dev(torch, starts)[0], seed=5)
+                                          start_nodes=to_dev(torch, starts)[0], seed=5,
+                                          dispatch=dispatch)
         g.sync()
         r = og.sample_walks(W, L, hop_bias=kind, start_bias=kind, start_mode="node",
                             start_nodes=starts, seed=5)
         assert np.array_equal(nodes.cpu().numpy(), r["nodes"])
         assert np.array_equal(tts.cpu().numpy(), r["ts"])
         assert np.array_equal(lens.cpu().numpy(), r["len"])
+    g.close()
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 40])
+def test_dispatches_agree_on_lengths_and_edge_cases(L):
+    # the cooperative path against the full-walk path on a hub-heavy graph:
+    # identical bytes for every walk, including walks that end at the start
+    torch, tw = gpu_or_skip()
+    w = synth.scaled("single", 5000, 300_000)
+    s, d, t = w["stream"].all()
+    g = tw.Graph(5000)
+    g.ingest_batch(*to_dev(torch, s, d, t))
+    span = float(t.max() - t.min())
+    outs = []
+    for dispatch in ("full_walk", "coop"):
+        r = g.sample_walks(30_000, L, hop_bias="exponential", hop_tau=0.1 * span,
+                           start_bias="exponential", start_tau=0.1 * span, seed=9,
+                           dispatch=dispatch)
+        g.sync()
+        outs.append([x.cpu().numpy() for x in r])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
     g.close()
