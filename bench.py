@@ -223,6 +223,24 @@ def main():
     hops = hops_check
     m_active = g.view_sizes()["m"]
 
+    # walk phase alone under each dispatch (index built once): plain full-walk
+    # against the cooperative per-step regrouping
+    compare = {}
+    for disp in ("full_walk", "coop"):
+        kw = dict(walk_kw, dispatch=disp)
+        times = []
+        for rep in range(4):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            g.sample_walks(W, L, **kw)
+            e1.record()
+            torch.cuda.synchronize()
+            if rep:
+                times.append(e0.elapsed_time(e1))
+        assert count_hops() == hops, f"{disp} walks differ in length"
+        ms = float(np.median(times))
+        compare[disp] = {"walk_ms": ms, "walk_hops_per_s": hops / (ms * 1e-3)}
+
     wb = walk_bytes(W, hops, L, w["start_bias"], w["hop_bias"])
     ib = ingest_bytes(spec.num_edges, 0, m_active, spec.num_nodes)
     walk_gbs = wb / (walk_ms * 1e-3) / 1e9
@@ -246,6 +264,7 @@ def main():
         "config": describe(args.workload, w, tau),
         "dispatch": args.dispatch,
         "hops_per_step": hops,
+        "plain_vs_tuned": compare,
         "walk_ms": walk_ms,
         "ingest_ms": ingest_ms,
         "walk_hops_per_s": walk_hops_s,

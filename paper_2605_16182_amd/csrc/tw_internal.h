@@ -122,7 +122,8 @@ struct tw_graph {
     bool adj_ready = false;
 
     // cooperative dispatch: per-walk state, live list, sort buffers
-    tw::DevBuf c_cur, c_prev, c_t, c_list, c_keys, c_skeys, c_swalks, c_flags, c_pos;
+    tw::DevBuf c_node0, c_walk0, c_t0, c_node1, c_walk1, c_t1, c_node2, c_walk2, c_t2;
+    tw::DevBuf c_prev, c_flags, c_pos;
     uint32_t coop_panel = 4096;        // LDS panel entries per workgroup
 
     // batch staging

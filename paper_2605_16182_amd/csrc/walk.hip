@@ -185,13 +185,16 @@ __global__ void __launch_bounds__(WALK_THREADS) k_walk_full(const WalkArgs a) {
 // chunk, and the thread tier otherwise; a node's walks beyond one
 // workgroup are split over several workgroups.
 
-struct CoopState {
-    int32_t* cur;
-    int32_t* prev;
-    int64_t* t;
+// Live walks of one step, structure of arrays in one order: current node,
+// walk index, time of arrival.
+struct Live {
+    uint32_t* node;
+    uint32_t* walk;
+    uint64_t* t;
 };
 
-__global__ void __launch_bounds__(WALK_THREADS) k_coop_start(const WalkArgs a, CoopState cs,
+__global__ void __launch_bounds__(WALK_THREADS) k_coop_start(const WalkArgs a, Live nx,
+                                                              int32_t* __restrict__ prev,
                                                               uint32_t* __restrict__ alive) {
     const int64_t w = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
     if (w >= a.num_walks) return;
@@ -199,38 +202,39 @@ __global__ void __launch_bounds__(WALK_THREADS) k_coop_start(const WalkArgs a, C
     StartState st = walk_start(a, w, id, a.nodes + w * a.L, a.ts + w * a.L);
     bool live = st.len >= 2 && st.len < a.L;
     if (live) {
-        cs.cur[w] = st.cur;
-        cs.prev[w] = st.prev;
-        cs.t[w] = st.t;
+        nx.node[w] = (uint32_t)st.cur;
+        nx.walk[w] = (uint32_t)w;
+        nx.t[w] = (uint64_t)st.t;
+        prev[w] = st.prev;
     } else {
         finish_walk(a, w, st.len);
     }
     alive[w] = live ? 1u : 0u;
 }
 
-__global__ void k_compact_ids(const uint32_t* __restrict__ flags, const uint32_t* __restrict__ pos,
-                              int64_t n, const uint32_t* __restrict__ ids,
-                              uint32_t* __restrict__ out) {
+// in-order compaction of the walks flagged alive
+__global__ void k_compact_live(const uint32_t* __restrict__ flags, const uint32_t* __restrict__ pos,
+                               int64_t n, Live in, Live out) {
     int64_t i = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
-    if (i < n && flags[i]) out[pos[i]] = ids ? ids[i] : (uint32_t)i;
+    if (i < n && flags[i]) {
+        uint32_t o = pos[i];
+        out.node[o] = in.node[i];
+        out.walk[o] = in.walk[i];
+        out.t[o] = in.t[i];
+    }
 }
 
-__global__ void k_coop_keys(const uint32_t* __restrict__ list, const uint32_t* n_live,
-                            const int32_t* __restrict__ cur, uint32_t* __restrict__ keys) {
-    int64_t i = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
-    if (i < *n_live) keys[i] = (uint32_t)cur[list[i]];
-}
-
+// One hop for the n live walks of `cur`, sorted by node. Results go to `nx`
+// at the same positions, with alive[i] set for walks that continue.
 __global__ void __launch_bounds__(WALK_THREADS)
-k_hop_coop(const WalkArgs a, CoopState cs, const uint32_t* __restrict__ keys,
-           const uint32_t* __restrict__ walks, int64_t n, uint64_t hop, uint32_t panel_cap,
-           uint32_t* __restrict__ alive) {
+k_hop_coop(const WalkArgs a, Live cur, Live nxt, int32_t* __restrict__ prev_of, int64_t n,
+           uint64_t hop, uint32_t panel_cap, uint32_t* __restrict__ alive) {
     extern __shared__ __align__(16) int64_t panel[];
     __shared__ int32_t wave_node[WALK_THREADS / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
     const bool valid = i < n;
-    const int32_t v = valid ? (int32_t)keys[i] : -1;
+    const int32_t v = valid ? (int32_t)cur.node[i] : -1;
     const int32_t v0 = __shfl(v, 0, 64);
     const bool wave_uniform = __ballot(valid && v == v0) == ~0ull;
     if (lane == 0) wave_node[wave] = wave_uniform ? v0 : -1;
@@ -259,24 +263,25 @@ k_hop_coop(const WalkArgs a, CoopState cs, const uint32_t* __restrict__ keys,
     __syncthreads();
     if (!valid) return;
 
-    const int64_t w = walks[i];
+    const uint32_t w = cur.walk[i];
     const uint64_t id = a.base + (uint64_t)w;
     const NodeRec r = a.rec[v];
-    const int64_t tcur = cs.t[w];
+    const int64_t tcur = (int64_t)cur.t[i];
     const int32_t len = (int32_t)hop + 1;  // nodes written before this hop
     bool live = false;
     if (tcur < r.t_last) {
         const uint32_t gc = fence_search(a.ng_ts, a.fence, r, tcur, my_panel, my_cap);
         Pick p;
         int32_t nx;
-        const int32_t prev = a.hop_kind == TW_NODE2VEC ? cs.prev[w] : 0;
+        const int32_t prev = a.hop_kind == TW_NODE2VEC ? prev_of[w] : 0;
         if (hop_pick(a, r, gc, id, hop, prev, p, nx)) {
-            a.nodes[w * a.L + len] = nx;
-            a.ts[w * a.L + len] = p.t;
+            a.nodes[(int64_t)w * a.L + len] = nx;
+            a.ts[(int64_t)w * a.L + len] = p.t;
             if (len + 1 < a.L) {
-                cs.cur[w] = nx;
-                cs.prev[w] = v;
-                cs.t[w] = p.t;
+                nxt.node[i] = (uint32_t)nx;
+                nxt.walk[i] = w;
+                nxt.t[i] = (uint64_t)p.t;
+                if (a.hop_kind == TW_NODE2VEC) prev_of[w] = v;
                 live = true;
             } else {
                 a.len[w] = len + 1;
@@ -293,35 +298,31 @@ k_hop_coop(const WalkArgs a, CoopState cs, const uint32_t* __restrict__ keys,
 bool valid_tau(double t) { return std::isfinite(t); }
 
 // Host loop of the cooperative dispatch: one synchronisation per step (the
-// live count), then keys -> sort by node -> hop -> compaction.
+// live count), then sort by node -> hop -> in-order compaction.
 tw_status coop_walks(tw_graph* g, const WalkArgs& a, Error& err) {
     hipStream_t s = g->stream;
     const int64_t W = a.num_walks;
-    TW_HIP(ensure(g->c_cur, sizeof(int32_t) * W));
-    TW_HIP(ensure(g->c_prev, sizeof(int32_t) * W));
-    TW_HIP(ensure(g->c_t, sizeof(int64_t) * W));
-    TW_HIP(ensure(g->c_list, sizeof(uint32_t) * W));
-    TW_HIP(ensure(g->c_keys, sizeof(uint32_t) * W));
-    TW_HIP(ensure(g->c_skeys, sizeof(uint32_t) * W));
-    TW_HIP(ensure(g->c_swalks, sizeof(uint32_t) * W));
-    TW_HIP(ensure(g->c_flags, sizeof(uint32_t) * W));
-    TW_HIP(ensure(g->c_pos, sizeof(uint32_t) * W));
-    CoopState cs{g->c_cur.as<int32_t>(), g->c_prev.as<int32_t>(), g->c_t.as<int64_t>()};
-    uint32_t* list = g->c_list.as<uint32_t>();
-    uint32_t* keys = g->c_keys.as<uint32_t>();
-    uint32_t* skeys = g->c_skeys.as<uint32_t>();
-    uint32_t* swalks = g->c_swalks.as<uint32_t>();
+    DevBuf* bufs32[] = {&g->c_node0, &g->c_walk0, &g->c_node1, &g->c_walk1, &g->c_node2,
+                        &g->c_walk2, &g->c_flags, &g->c_pos, &g->c_prev};
+    for (DevBuf* b : bufs32) TW_HIP(ensure(*b, sizeof(uint32_t) * W));
+    TW_HIP(ensure(g->c_t0, sizeof(uint64_t) * W));
+    TW_HIP(ensure(g->c_t1, sizeof(uint64_t) * W));
+    TW_HIP(ensure(g->c_t2, sizeof(uint64_t) * W));
+    // live (compacted) -> sorted (by node) -> next (after the hop) -> live
+    Live live{g->c_node0.as<uint32_t>(), g->c_walk0.as<uint32_t>(), g->c_t0.as<uint64_t>()};
+    Live sorted{g->c_node1.as<uint32_t>(), g->c_walk1.as<uint32_t>(), g->c_t1.as<uint64_t>()};
+    Live next{g->c_node2.as<uint32_t>(), g->c_walk2.as<uint32_t>(), g->c_t2.as<uint64_t>()};
+    int32_t* prev = g->c_prev.as<int32_t>();
     uint32_t* flags = g->c_flags.as<uint32_t>();
     uint32_t* pos = g->c_pos.as<uint32_t>();
     uint32_t* n_live_d = g->scal.as<uint32_t>() + 28;  // bytes 112..115
     const int vbits = bits_for((uint64_t)(g->V - 1));
     const uint32_t panel_cap = g->coop_panel;
+    const dim3 wgrid((unsigned)ceil_div(W, WALK_THREADS));
 
-    hipLaunchKernelGGL(k_coop_start, dim3((unsigned)ceil_div(W, WALK_THREADS)), dim3(WALK_THREADS),
-                       0, s, a, cs, flags);
+    hipLaunchKernelGGL(k_coop_start, wgrid, dim3(WALK_THREADS), 0, s, a, next, prev, flags);
     TW_HIP(scan_exclusive_u32(flags, pos, W, n_live_d, g->ws, s));
-    hipLaunchKernelGGL(k_compact_ids, dim3((unsigned)ceil_div(W, WALK_THREADS)),
-                       dim3(WALK_THREADS), 0, s, flags, pos, W, nullptr, list);
+    hipLaunchKernelGGL(k_compact_live, wgrid, dim3(WALK_THREADS), 0, s, flags, pos, W, next, live);
     TW_HIP(hipGetLastError());
     for (uint64_t hop = 1; hop + 1 < (uint64_t)a.L; ++hop) {
         uint32_t n_live = 0;
@@ -329,15 +330,13 @@ tw_status coop_walks(tw_graph* g, const WalkArgs& a, Error& err) {
         TW_HIP(hipStreamSynchronize(s));
         if (n_live == 0) break;
         const dim3 grid((unsigned)ceil_div(n_live, WALK_THREADS));
-        hipLaunchKernelGGL(k_coop_keys, grid, dim3(WALK_THREADS), 0, s, list, n_live_d, cs.cur,
-                           keys);
-        TW_HIP(radix_sort_u32_kv(keys, list, nullptr, skeys, swalks, nullptr, n_live, 0, vbits,
-                                 g->ws, s));
+        TW_HIP(radix_sort_u32_kv(live.node, live.walk, live.t, sorted.node, sorted.walk, sorted.t,
+                                 n_live, 0, vbits, g->ws, s));
         hipLaunchKernelGGL(k_hop_coop, grid, dim3(WALK_THREADS), sizeof(int64_t) * panel_cap, s, a,
-                           cs, skeys, swalks, (int64_t)n_live, hop, panel_cap, flags);
+                           sorted, next, prev, (int64_t)n_live, hop, panel_cap, flags);
         TW_HIP(scan_exclusive_u32(flags, pos, n_live, n_live_d, g->ws, s));
-        hipLaunchKernelGGL(k_compact_ids, grid, dim3(WALK_THREADS), 0, s, flags, pos,
-                           (int64_t)n_live, swalks, list);
+        hipLaunchKernelGGL(k_compact_live, grid, dim3(WALK_THREADS), 0, s, flags, pos,
+                           (int64_t)n_live, next, live);
         TW_HIP(hipGetLastError());
     }
     return TW_OK;
@@ -418,6 +417,9 @@ tw_status sample_walks(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int
     a.ts = ts;
     a.len = len;
     a.err = g->err.as<uint32_t>();
+    // AUTO runs the full-walk kernel: on MI355X the per-step regrouping costs
+    // more (sorting, step tails, partial-line output writes) than it saves,
+    // since L2 and the MALL already hold the hot node metadata.
     const bool coop = p->dispatch == TW_DISPATCH_COOP;
     if (!coop) {
         int64_t blocks = ceil_div(p->num_walks, WALK_THREADS);
