@@ -36,7 +36,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="single", choices=["single", "tiny"])
+    ap.add_argument("--workload", default="single", choices=["single", "tiny", "stream"])
+    ap.add_argument("--batches", type=int, default=0,
+                    help="stream workload: number of 10M-edge batches (0 = the whole stream)")
     ap.add_argument("--dispatch", default="auto", choices=["auto", "full_walk", "coop"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
@@ -151,6 +153,125 @@ def cpu_baseline(w, tau, gpu_hops_per_step):
     }
 
 
+def stream_cpu_baseline(w, n_batches, hops_per_batch):
+    """The oracle on the stream's first batches: ingest (single-threaded) and
+    1% of each batch's walk ids (OpenMP), scaled to the GPU's hop count."""
+    import oracle
+    spec = w["stream"]
+    og = oracle.OracleGraph(spec.num_nodes, directed=spec.directed, window=w["window"])
+    t_ing = t_walk = 0.0
+    hops = 0
+    nw = max(1000, w["walks"] // 100)
+    idx = np.arange(0, w["walks"], w["walks"] // nw)[:nw]
+    threads = oracle.threads()
+    for b, (s, d, t) in enumerate(spec.batches(w["batch_edges"])):
+        if b >= n_batches:
+            break
+        t0 = time.perf_counter()
+        og.ingest_batch(s, d, t)
+        og.evict_before(-(1 << 63))
+        og.sizes()
+        t_ing += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        r = og.sample_walks(w["walks"], w["max_len"], hop_bias=w["hop_bias"],
+                            start_bias=w["start_bias"], seed=b, walk_idx=idx, threads=threads)
+        t_walk += time.perf_counter() - t0
+        hops += int(np.maximum(r["len"] - 1, 0).sum())
+    hop_rate = hops / t_walk
+    per_batch = t_ing / n_batches + hops_per_batch / hop_rate
+    return {"value": hops_per_batch / per_batch, "unit": "hops/s", "cores": threads,
+            "kind": "oracle", "ingest_edges_per_s": n_batches * w["batch_edges"] / t_ing,
+            "walk_hops_per_s": hop_rate,
+            "sample": (f"oracle on the first {n_batches} batches of the stream (ingest "
+                       f"single-threaded, window still filling) and {len(idx)} walk ids (1%) per "
+                       f"batch with {threads} OpenMP threads; hop rate applied to the GPU's mean "
+                       f"hops per steady-state batch")}
+
+
+def run_stream(args, torch, tw, w, dev, gather_rate, copy_bw):
+    """Streaming window: ingest 10M-edge batches under the sliding window,
+    evict, then sample the batch's walks; every batch is timed."""
+    spec = w["stream"]
+    B = w["batch_edges"]
+    nb = spec.num_edges // B if args.batches <= 0 else args.batches
+    t0 = time.perf_counter()
+    batches = []
+    for b, (s, d, t) in enumerate(spec.batches(B)):
+        if b >= nb:
+            break
+        batches.append((torch.from_numpy(s).to(dev), torch.from_numpy(d).to(dev),
+                        torch.from_numpy(t).to(dev)))
+        if b % 10 == 0:
+            print(f"# generated batch {b}", file=sys.stderr, flush=True)
+    print(f"# {nb} batches resident in HBM ({time.perf_counter() - t0:.1f}s)", file=sys.stderr,
+          flush=True)
+    W, L = w["walks"], w["max_len"]
+    out = (torch.empty((W, L), dtype=torch.int32, device=dev),
+           torch.empty((W, L), dtype=torch.int64, device=dev),
+           torch.empty(W, dtype=torch.int32, device=dev))
+    g = tw.Graph(spec.num_nodes, directed=spec.directed, window=w["window"])
+    hops_dev = torch.zeros(nb, dtype=torch.int64, device=dev)
+    m_dev = []
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(nb)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b, (s, d, t) in enumerate(batches):
+        e = evs[b]
+        e[0].record()
+        info = g.ingest_batch(s, d, t)
+        e[1].record()
+        g.evict_before(info["t_max"] - w["window"])
+        e[2].record()
+        g.sample_walks(W, L, hop_bias=w["hop_bias"], start_bias=w["start_bias"], seed=b,
+                       dispatch=args.dispatch, out=out)
+        e[3].record()
+        hops_dev[b] = (out[2].to(torch.int64) - 1).clamp_min(0).sum()
+        m_dev.append(info["active_edges"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    hops = hops_dev.cpu().numpy()
+    ing = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    ev = np.array([e[1].elapsed_time(e[2]) for e in evs])
+    wk = np.array([e[2].elapsed_time(e[3]) for e in evs])
+    # steady state: the window has filled (the last 80% of the batches)
+    ss = slice(nb // 5, nb) if nb >= 5 else slice(0, nb)
+    per_hop = 3 if w["hop_bias"] == "uniform" else 4
+    m_ss = float(np.mean(m_dev[ss]))
+    ib = ingest_bytes(B, m_ss, m_ss, spec.num_nodes)
+    roof_ing = ib / copy_bw * 1e3 if copy_bw else None
+    roof_walk = float(np.mean(hops[ss])) / (gather_rate / per_hop) * 1e3 if gather_rate else None
+    meas = float(np.mean(ing[ss] + ev[ss] + wk[ss]))
+    res = {
+        "metric": METRIC,
+        "value": float(hops.sum()) / wall,
+        "unit": "hops/s",
+        "n_gpus": 1, "steps": nb, "warmup": 0,
+        "ms_per_step": wall * 1e3 / nb,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64+f64", "data": "synthetic",
+        "config": describe("stream", w, 0.0) | {"batches": nb, "batch_edges": B},
+        "dispatch": args.dispatch,
+        "steady_state": {
+            "batches": f"{ss.start}..{nb - 1}",
+            "active_edges": m_ss,
+            "ingest_ms": float(np.mean(ing[ss])), "evict_ms": float(np.mean(ev[ss])),
+            "walk_ms": float(np.mean(wk[ss])), "hops_per_batch": float(np.mean(hops[ss])),
+            "ingest_edges_per_s": B / (float(np.mean(ing[ss])) * 1e-3),
+            "walk_hops_per_s": float(np.mean(hops[ss])) / (float(np.mean(wk[ss])) * 1e-3),
+        },
+        "roofline": {"bound": "hbm", "ingest_roof_ms": roof_ing, "walk_roof_ms": roof_walk,
+                     "measured_ms": meas,
+                     "frac": ((roof_ing + roof_walk) / meas) if roof_ing and roof_walk else None,
+                     "ingest_algorithmic_bytes": ib, "copy_GBps_measured": copy_bw / 1e9,
+                     "random_sectors_per_s": gather_rate},
+    }
+    g.close()
+    if not args.no_cpu_baseline:
+        print("# oracle baseline ...", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = stream_cpu_baseline(w, 3, float(np.mean(hops[ss])))
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -164,6 +285,9 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     w = synth.workload(args.workload)
+    if args.workload == "stream":
+        gather_rate, copy_bw = (0.0, 0.0) if args.no_probe else probe_rates(torch, dev)
+        return run_stream(args, torch, tw, w, dev, gather_rate, copy_bw)
     spec = w["stream"]
     t0 = time.perf_counter()
     src, dst, ts = spec.all()

@@ -2,18 +2,25 @@
 // (Tempest, Sec. "Dual-Index Organization" and "Streaming Ingestion and
 // Window Management").
 //
-// Layout in HBM (structure of arrays, all indices uint32):
-//   timestamp view (the edge store):   e_src[m] e_dst[m] e_ts[m]
-//   its timestamp groups:              gg_ts[Gg] gg_off[Gg+1]
-//   node-and-timestamp view:           n_dst[m] n_ts[m]  (sorted by src, ts,
-//                                      timestamp-view position)
-//   its (node, timestamp) groups:      ng_ts[Gn] ng_off[Gn+1]
-//   node table:                        rec[V] (32-byte NodeRec)
+// Layout in HBM (structure of arrays, all positions uint32):
+//   timestamp view (the edge store):   e_src e_dst e_ts, the window at
+//                                      [e_base, e_base + m) of buffers with
+//                                      room to append
+//   its timestamp groups:              gg_ts gg_off at [gg_base, gg_base + Gg],
+//                                      offsets are edge-store positions
+//   node-and-timestamp view:           n_src n_dst n_ts [m] (sorted by source,
+//                                      timestamp, arrival)
+//   its (node, timestamp) groups:      ng_ts ng_off ng_node [Gn]
+//   node table:                        rec[V] (32-byte NodeRec), fence levels
 //
-// One ingest: stage (validate, mirror, min/max) -> late drop -> stable radix
-// sort of the batch by timestamp -> merge-path merge after the surviving
-// window (old records first on equal timestamps) -> rebuild of the groups,
-// the node view (stable radix sort by source) and the node table.
+// One ingest: stage (validate, mirror, min/max, sortedness) -> late drop ->
+// (unsorted batch only) stable radix sort by timestamp -> timestamp view:
+// evicting moves e_base, a batch that starts at or after the window's last
+// timestamp is appended in place and its groups appended, any other batch is
+// merged (merge path, older records first on equal timestamps) and the groups
+// rebuilt -> node view: the batch is sorted by source and every node's
+// surviving run is merged with its batch run -> (node, timestamp) groups,
+// node table and fence from the node view.
 #include <algorithm>
 
 #include "tw_internal.h"
@@ -174,16 +181,117 @@ __global__ void k_ts_group_flags(const int64_t* __restrict__ ts, int64_t m,
     if (i < m) flags[i] = (i == 0 || ts[i] != ts[i - 1]) ? 1u : 0u;
 }
 
+// groups of the timestamp view; offsets are positions in the edge-store
+// buffer (pos_base is the buffer position of ts[0])
 __global__ void k_ts_group_scatter(const int64_t* __restrict__ ts, int64_t m,
                                    const uint32_t* __restrict__ flags,
                                    const uint32_t* __restrict__ gidx, int64_t* __restrict__ g_ts,
-                                   uint32_t* __restrict__ g_off, const uint32_t* G) {
+                                   uint32_t* __restrict__ g_off, const uint32_t* G,
+                                   uint32_t pos_base) {
     int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
     if (i < m && flags[i]) {
         g_ts[gidx[i]] = ts[i];
-        g_off[gidx[i]] = (uint32_t)i;
+        g_off[gidx[i]] = pos_base + (uint32_t)i;
     }
-    if (i == 0) g_off[*G] = (uint32_t)m;
+    if (i == 0) g_off[*G] = pos_base + (uint32_t)m;
+}
+
+// group-start flags of a batch appended after a window whose last timestamp
+// is last_ts (has_last = 0: empty window)
+__global__ void k_append_group_flags(const int64_t* __restrict__ ts, int64_t n, int64_t last_ts,
+                                     int has_last, uint32_t* __restrict__ flags) {
+    int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (i >= n) return;
+    flags[i] = (i == 0) ? (!has_last || ts[0] != last_ts) : (ts[i] != ts[i - 1]);
+}
+
+// Per-node plan of the node-view merge: first surviving old edge ob (the
+// node's edges before `cut` are evicted), old end oe, and the node's run
+// [bf, be) in the batch sorted by source; cnt[v] = merged size of the node.
+__global__ void k_merge_plan(const NodeRec* __restrict__ rec, const int64_t* __restrict__ n_ts,
+                             int32_t V, int64_t cut, int evicting,
+                             const uint32_t* __restrict__ b_first,
+                             const uint32_t* __restrict__ b_end, uint4* __restrict__ plan,
+                             uint32_t* __restrict__ cnt) {
+    int64_t v = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (v > V) return;
+    if (v == V) {
+        cnt[v] = 0;
+        return;
+    }
+    const NodeRec r = rec[v];
+    uint32_t ob = r.eb;
+    if (evicting && r.eb < r.ee && n_ts[r.eb] < cut) {
+        uint32_t lo = r.eb, hi = r.ee;
+        while (lo < hi) {
+            uint32_t mid = lo + ((hi - lo) >> 1);
+            if (n_ts[mid] < cut) lo = mid + 1; else hi = mid;
+        }
+        ob = lo;
+    }
+    const uint32_t bf = b_first[v], be = b_end[v];
+    plan[v] = make_uint4(ob, r.ee, bf, be);
+    cnt[v] = (r.ee - ob) + (be - bf);
+}
+
+// Surviving old edges to their merged positions: before them within the node
+// go the batch edges with a strictly smaller timestamp (older edges first on
+// equal timestamps).
+__global__ void k_merge_old(const uint32_t* __restrict__ n_src, const int32_t* __restrict__ n_dst,
+                            const int64_t* __restrict__ n_ts, int64_t m_old,
+                            const uint4* __restrict__ plan, const uint32_t* __restrict__ neb,
+                            const int64_t* __restrict__ bs_ts, uint32_t* __restrict__ o_src,
+                            int32_t* __restrict__ o_dst, int64_t* __restrict__ o_ts) {
+    int64_t j = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (j >= m_old) return;
+    const uint32_t v = n_src[j];
+    const uint4 p = plan[v];
+    if ((uint32_t)j < p.x) return;  // evicted
+    const int64_t t = n_ts[j];
+    uint32_t c = 0;
+    if (p.z < p.w && bs_ts[p.z] < t) {
+        uint32_t lo = p.z, hi = p.w;
+        while (lo < hi) {
+            uint32_t mid = lo + ((hi - lo) >> 1);
+            if (bs_ts[mid] < t) lo = mid + 1; else hi = mid;
+        }
+        c = lo - p.z;
+    }
+    const uint32_t d = neb[v] + ((uint32_t)j - p.x) + c;
+    o_src[d] = v;
+    o_dst[d] = n_dst[j];
+    o_ts[d] = t;
+}
+
+// Batch edges (sorted by source, stable) to their merged positions: before
+// them go the surviving old edges of the node with a timestamp <= theirs.
+__global__ void k_merge_new(const uint32_t* __restrict__ bs_src, const int32_t* __restrict__ bs_dst,
+                            const int64_t* __restrict__ bs_ts, int64_t nb,
+                            const uint4* __restrict__ plan, const uint32_t* __restrict__ neb,
+                            const int64_t* __restrict__ n_ts, uint32_t* __restrict__ o_src,
+                            int32_t* __restrict__ o_dst, int64_t* __restrict__ o_ts) {
+    int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (i >= nb) return;
+    const uint32_t v = bs_src[i];
+    const uint4 p = plan[v];
+    const int64_t y = bs_ts[i];
+    uint32_t c = 0;
+    if (p.x < p.y) {
+        if (n_ts[p.y - 1] <= y) {
+            c = p.y - p.x;
+        } else {
+            uint32_t lo = p.x, hi = p.y;
+            while (lo < hi) {
+                uint32_t mid = lo + ((hi - lo) >> 1);
+                if (n_ts[mid] <= y) lo = mid + 1; else hi = mid;
+            }
+            c = lo - p.x;
+        }
+    }
+    const uint32_t d = neb[v] + ((uint32_t)i - p.z) + c;
+    o_src[d] = v;
+    o_dst[d] = bs_dst[i];
+    o_ts[d] = y;
 }
 
 // (node, timestamp) groups of the node view, with the node of each group
@@ -336,9 +444,10 @@ __global__ void k_adj_extract(const uint64_t* __restrict__ keys, int64_t m,
     if (i < m) adj[i] = (int32_t)(uint32_t)keys[i];
 }
 
-__global__ void k_widen(const uint32_t* __restrict__ in, int64_t n, int64_t* __restrict__ out) {
+__global__ void k_widen(const uint32_t* __restrict__ in, int64_t n, int64_t* __restrict__ out,
+                        int64_t minus) {
     int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
-    if (i < n) out[i] = (int64_t)in[i];
+    if (i < n) out[i] = (int64_t)in[i] - minus;
 }
 
 __global__ void k_export_nodes(const NodeRec* __restrict__ rec, int32_t V, int64_t m, int64_t Gn,
@@ -349,30 +458,129 @@ __global__ void k_export_nodes(const NodeRec* __restrict__ rec, int32_t V, int64
     if (gbeg) gbeg[v] = v < V ? (int64_t)rec[v].gb : Gn;
 }
 
-// sizes and timestamp range after a rebuild: out = {Gg, Gn, t_min, t_max}
-__global__ void k_summary(const int64_t* __restrict__ ts, int64_t m, const uint32_t* G,
-                          int64_t* out) {
-    out[0] = G[0];
-    out[1] = G[1];
-    out[2] = m > 0 ? ts[0] : 0;
-    out[3] = m > 0 ? ts[m - 1] : 0;
+__global__ void k_window_summary(const int64_t* __restrict__ ts, int64_t m, int64_t* out) {
+    out[0] = m > 0 ? ts[0] : 0;
+    out[1] = m > 0 ? ts[m - 1] : 0;
 }
 
-// Rebuild everything derived from the timestamp view e_* (m records).
-tw_status rebuild_views(tw_graph* g, Error& err) {
+uint32_t* u32_slot(tw_graph* g, int k) { return g->scal.as<uint32_t>() + k; }
+int64_t* i64_slot(tw_graph* g, int k) { return g->scal.as<int64_t>() + k; }
+
+tw_status ensure_common(tw_graph* g, Error& err) {
+    TW_HIP(ensure(g->err, sizeof(uint32_t) * 4));
+    TW_HIP(ensure(g->scal, SCALAR_BYTES));
+    return TW_OK;
+}
+
+// Capacity of the edge-store buffers for a window of `need` records; growing
+// copies the window to the front of the new buffers (e_base = 0).
+tw_status reserve_window(tw_graph* g, int64_t need, Error& err) {
+    if (need <= g->e_cap) return TW_OK;
+    int64_t cap = std::max<int64_t>(need, 2 * g->e_cap);
+    cap = std::max<int64_t>(cap, need + need / 2 + 1024);
+    cap = std::min<int64_t>(cap, (int64_t)UINT32_MAX - 1);
+    TW_HIP(ensure(g->a_src, sizeof(int32_t) * cap));
+    TW_HIP(ensure(g->a_dst, sizeof(int32_t) * cap));
+    TW_HIP(ensure(g->a_ts, sizeof(int64_t) * cap));
     hipStream_t s = g->stream;
-    const int64_t m = g->m, V = g->V;
-    // device scalars: bytes 16..23 hold Gg, Gn, bytes 24..31 the fence length;
-    // bytes 32..63 the summary
-    uint32_t* sc = g->scal.as<uint32_t>() + 2;  // sc[2] = Gg, sc[3] = Gn
-    uint32_t* fence_total = g->scal.as<uint32_t>() + 7;
+    if (g->m > 0) {
+        TW_HIP(hipMemcpyAsync(g->a_src.p, g->e_src.as<int32_t>() + g->e_base, 4 * g->m,
+                              hipMemcpyDeviceToDevice, s));
+        TW_HIP(hipMemcpyAsync(g->a_dst.p, g->e_dst.as<int32_t>() + g->e_base, 4 * g->m,
+                              hipMemcpyDeviceToDevice, s));
+        TW_HIP(hipMemcpyAsync(g->a_ts.p, g->e_ts.as<int64_t>() + g->e_base, 8 * g->m,
+                              hipMemcpyDeviceToDevice, s));
+    }
+    std::swap(g->e_src, g->a_src);
+    std::swap(g->e_dst, g->a_dst);
+    std::swap(g->e_ts, g->a_ts);
+    TW_HIP(ensure(g->a_src, sizeof(int32_t) * cap));
+    TW_HIP(ensure(g->a_dst, sizeof(int32_t) * cap));
+    TW_HIP(ensure(g->a_ts, sizeof(int64_t) * cap));
+    TW_HIP(ensure(g->gg_ts, sizeof(int64_t) * (cap + 2)));
+    TW_HIP(ensure(g->gg_off, sizeof(uint32_t) * (cap + 2)));
+    g->e_base = 0;
+    g->e_cap = cap;
+    return TW_OK;
+}
+
+// Global timestamp groups of the whole window, from scratch (gg_base = 0).
+// The count lands in the GROUPS slot.
+tw_status build_ts_groups(tw_graph* g, Error& err) {
+    hipStream_t s = g->stream;
+    const int64_t m = g->m;
     TW_HIP(ensure(g->flags, sizeof(uint32_t) * (m + 1)));
     TW_HIP(ensure(g->idx, sizeof(uint32_t) * (m + 1)));
-    TW_HIP(ensure(g->gg_ts, sizeof(int64_t) * (m + 1)));
-    TW_HIP(ensure(g->gg_off, sizeof(uint32_t) * (m + 2)));
-    TW_HIP(ensure(g->n_dst, sizeof(int32_t) * (m + 1)));
-    TW_HIP(ensure(g->n_ts, sizeof(int64_t) * (m + 1)));
-    TW_HIP(ensure(g->n_src, sizeof(uint32_t) * (m + 1)));
+    uint32_t* flags = g->flags.as<uint32_t>();
+    uint32_t* gidx = g->idx.as<uint32_t>();
+    const int64_t* ts = g->e_ts.as<int64_t>() + g->e_base;
+    uint32_t* G = u32_slot(g, SLOT_U32_GROUPS);
+    hipLaunchKernelGGL(k_ts_group_flags, grid_for(m), dim3(T), 0, s, ts, m, flags);
+    TW_HIP(scan_exclusive_u32(flags, gidx, m, G, g->ws, s));
+    hipLaunchKernelGGL(k_ts_group_scatter, grid_for(m), dim3(T), 0, s, ts, m, flags, gidx,
+                       g->gg_ts.as<int64_t>(), g->gg_off.as<uint32_t>(), G, (uint32_t)g->e_base);
+    g->gg_base = 0;
+    return TW_OK;
+}
+
+// Merge the node view with `kept` batch records (timestamp order) after
+// removing every node's edges older than `cut` (when evicting): the batch is
+// sorted by source (stable), each node's surviving run and batch run are
+// merged by timestamp (old first on ties) into the alternate arrays.
+tw_status merge_node_view(tw_graph* g, const int32_t* q_src, const int32_t* q_dst,
+                          const int64_t* q_ts, int64_t kept, int64_t m_old, int64_t m_new,
+                          bool evicting, int64_t cut, Error& err) {
+    hipStream_t s = g->stream;
+    const int64_t V = g->V;
+    TW_HIP(ensure(g->bs_src, sizeof(uint32_t) * (kept + 1)));
+    TW_HIP(ensure(g->bs_dst, sizeof(int32_t) * (kept + 1)));
+    TW_HIP(ensure(g->bs_ts, sizeof(int64_t) * (kept + 1)));
+    TW_HIP(ensure(g->an_src, sizeof(uint32_t) * (m_new + 1)));
+    TW_HIP(ensure(g->an_dst, sizeof(int32_t) * (m_new + 1)));
+    TW_HIP(ensure(g->an_ts, sizeof(int64_t) * (m_new + 1)));
+    TW_HIP(ensure(g->plan, sizeof(uint4) * (V + 1)));
+    TW_HIP(ensure(g->node_tmp, sizeof(uint32_t) * 3 * (V + 1)));
+    uint32_t* bsrc = g->bs_src.as<uint32_t>();
+    int32_t* bdst = g->bs_dst.as<int32_t>();
+    int64_t* bts = g->bs_ts.as<int64_t>();
+    TW_HIP(radix_sort_u32_kv(reinterpret_cast<const uint32_t*>(q_src),
+                             reinterpret_cast<const uint32_t*>(q_dst),
+                             reinterpret_cast<const uint64_t*>(q_ts), bsrc,
+                             reinterpret_cast<uint32_t*>(bdst), reinterpret_cast<uint64_t*>(bts),
+                             kept, 0, bits_for((uint64_t)(V - 1)), g->ws, s));
+    uint32_t* b_first = g->node_tmp.as<uint32_t>();
+    uint32_t* b_end = b_first + (V + 1);
+    uint32_t* neb = b_end + (V + 1);
+    hipLaunchKernelGGL(k_fill_u32, grid_for(2 * (V + 1)), dim3(T), 0, s, b_first, 2 * (V + 1), 0u);
+    hipLaunchKernelGGL(k_run_bounds, grid_for(kept), dim3(T), 0, s, bsrc, kept, b_first, b_end);
+    hipLaunchKernelGGL(k_merge_plan, grid_for(V + 1), dim3(T), 0, s, g->rec.as<NodeRec>(),
+                       g->n_ts.as<int64_t>(), (int32_t)V, cut, evicting ? 1 : 0, b_first, b_end,
+                       g->plan.as<uint4>(), neb);
+    TW_HIP(scan_exclusive_u32(neb, neb, V + 1, nullptr, g->ws, s));
+    hipLaunchKernelGGL(k_merge_old, grid_for(m_old), dim3(T), 0, s, g->n_src.as<uint32_t>(),
+                       g->n_dst.as<int32_t>(), g->n_ts.as<int64_t>(), m_old, g->plan.as<uint4>(),
+                       neb, bts, g->an_src.as<uint32_t>(), g->an_dst.as<int32_t>(),
+                       g->an_ts.as<int64_t>());
+    hipLaunchKernelGGL(k_merge_new, grid_for(kept), dim3(T), 0, s, bsrc, bdst, bts, kept,
+                       g->plan.as<uint4>(), neb, g->n_ts.as<int64_t>(), g->an_src.as<uint32_t>(),
+                       g->an_dst.as<int32_t>(), g->an_ts.as<int64_t>());
+    TW_HIP(hipGetLastError());
+    std::swap(g->n_src, g->an_src);
+    std::swap(g->n_dst, g->an_dst);
+    std::swap(g->n_ts, g->an_ts);
+    (void)m_new;
+    return TW_OK;
+}
+
+// Groups, node table and fence from the node view; then one synchronisation
+// reads the counts. Gg is taken from the GROUPS slot when gg_full, else it
+// is gg_old - gg_evicted + GROUPS (appended groups).
+tw_status finish_index(tw_graph* g, bool gg_full, int64_t gg_old, int64_t gg_evicted,
+                       Error& err) {
+    hipStream_t s = g->stream;
+    const int64_t m = g->m, V = g->V;
+    TW_HIP(ensure(g->flags, sizeof(uint32_t) * (m + 1)));
+    TW_HIP(ensure(g->idx, sizeof(uint32_t) * (m + 1)));
     TW_HIP(ensure(g->ng_ts, sizeof(int64_t) * (m + 1)));
     TW_HIP(ensure(g->ng_off, sizeof(uint32_t) * (m + 2)));
     TW_HIP(ensure(g->ng_node, sizeof(uint32_t) * (m + 1)));
@@ -380,30 +588,17 @@ tw_status rebuild_views(tw_graph* g, Error& err) {
     TW_HIP(ensure(g->b_vals, sizeof(uint32_t) * (3 * (V + 1) + 1)));
     uint32_t* flags = g->flags.as<uint32_t>();
     uint32_t* gidx = g->idx.as<uint32_t>();
-
-    // global timestamp groups
-    hipLaunchKernelGGL(k_ts_group_flags, grid_for(m), dim3(T), 0, s, g->e_ts.as<int64_t>(), m, flags);
-    TW_HIP(scan_exclusive_u32(flags, gidx, m, sc + 2, g->ws, s));
-    hipLaunchKernelGGL(k_ts_group_scatter, grid_for(m), dim3(T), 0, s, g->e_ts.as<int64_t>(), m,
-                       flags, gidx, g->gg_ts.as<int64_t>(), g->gg_off.as<uint32_t>(), sc + 2);
-
-    // node view: stable sort of the timestamp view by source, carrying the
-    // destination and timestamp as payload
-    uint32_t* keys = g->n_src.as<uint32_t>();
-    TW_HIP(radix_sort_u32_kv(reinterpret_cast<const uint32_t*>(g->e_src.p),
-                             reinterpret_cast<const uint32_t*>(g->e_dst.p),
-                             reinterpret_cast<const uint64_t*>(g->e_ts.p), keys,
-                             reinterpret_cast<uint32_t*>(g->n_dst.p),
-                             reinterpret_cast<uint64_t*>(g->n_ts.p), m, 0,
-                             bits_for((uint64_t)(V - 1)), g->ws, s));
+    uint32_t* Gn = u32_slot(g, SLOT_U32_GN);
+    uint32_t* fence_total = u32_slot(g, SLOT_U32_FENCE);
+    const uint32_t* keys = g->n_src.as<uint32_t>();
 
     // (node, timestamp) groups
     hipLaunchKernelGGL(k_node_group_flags, grid_for(m), dim3(T), 0, s, keys, g->n_ts.as<int64_t>(),
                        m, flags);
-    TW_HIP(scan_exclusive_u32(flags, gidx, m, sc + 3, g->ws, s));
+    TW_HIP(scan_exclusive_u32(flags, gidx, m, Gn, g->ws, s));
     hipLaunchKernelGGL(k_node_group_scatter, grid_for(m), dim3(T), 0, s, g->n_ts.as<int64_t>(),
                        keys, m, flags, gidx, g->ng_ts.as<int64_t>(), g->ng_off.as<uint32_t>(),
-                       g->ng_node.as<uint32_t>(), sc + 3);
+                       g->ng_node.as<uint32_t>(), Gn);
 
     // node table: per-node edge / group counts, then their exclusive scans
     uint32_t* node_e = g->b_vals.as<uint32_t>();  // V+1 entries each
@@ -412,7 +607,7 @@ tw_status rebuild_views(tw_graph* g, Error& err) {
     hipLaunchKernelGGL(k_fill_u32, grid_for(2 * (V + 1)), dim3(T), 0, s, node_e, 2 * (V + 1), 0u);
     hipLaunchKernelGGL(k_run_bounds, grid_for(m), dim3(T), 0, s, keys, m, node_e, node_g);
     hipLaunchKernelGGL(k_node_counts, grid_for(V + 1), dim3(T), 0, s, node_e, node_g,
-                       (int32_t)V, m, gidx, sc + 3);
+                       (int32_t)V, m, gidx, Gn);
     TW_HIP(scan_exclusive_u32(node_e, node_e, V + 1, nullptr, g->ws, s));
     TW_HIP(scan_exclusive_u32(node_g, node_g, V + 1, nullptr, g->ws, s));
     hipLaunchKernelGGL(k_node_records, grid_for(V + 1), dim3(T), 0, s, node_e, node_g, (int32_t)V,
@@ -420,21 +615,22 @@ tw_status rebuild_views(tw_graph* g, Error& err) {
     TW_HIP(scan_exclusive_u32(fsize, fsize, V + 1, fence_total, g->ws, s));
     hipLaunchKernelGGL(k_fence_offsets, grid_for(V), dim3(T), 0, s, fsize, (int32_t)V,
                        g->rec.as<NodeRec>());
+    int64_t* summary = i64_slot(g, SLOT_I64_SUMMARY);
+    hipLaunchKernelGGL(k_window_summary, dim3(1), dim3(1), 0, s, g->e_ts.as<int64_t>() + g->e_base,
+                       m, summary);
     TW_HIP(hipGetLastError());
 
-    int64_t* summary = g->scal.as<int64_t>() + 4;  // bytes 32..63
-    hipLaunchKernelGGL(k_summary, dim3(1), dim3(1), 0, s, g->e_ts.as<int64_t>(), m, sc + 2,
-                       summary);
-    TW_HIP(hipGetLastError());
-    int64_t host_sum[4];
-    uint32_t host_fence = 0;
+    uint32_t host_u32[4];  // GROUPS, GN, UNSORTED, FENCE
+    int64_t host_sum[2];
+    TW_HIP(hipMemcpyAsync(host_u32, u32_slot(g, SLOT_U32_GROUPS), sizeof(host_u32),
+                          hipMemcpyDeviceToHost, s));
     TW_HIP(hipMemcpyAsync(host_sum, summary, sizeof(host_sum), hipMemcpyDeviceToHost, s));
-    TW_HIP(hipMemcpyAsync(&host_fence, fence_total, sizeof(host_fence), hipMemcpyDeviceToHost, s));
     TW_HIP(hipStreamSynchronize(s));
-    g->Gg = host_sum[0];
-    g->Gn = host_sum[1];
-    g->t_min = host_sum[2];
-    g->t_max = host_sum[3];
+    g->Gg = gg_full ? (int64_t)host_u32[0] : gg_old - gg_evicted + (int64_t)host_u32[0];
+    g->Gn = host_u32[1];
+    g->t_min = host_sum[0];
+    g->t_max = host_sum[1];
+    const uint32_t host_fence = host_u32[3];
 
     // fence levels of nodes with many groups
     g->fence_len = host_fence;
@@ -451,35 +647,25 @@ tw_status rebuild_views(tw_graph* g, Error& err) {
     return TW_OK;
 }
 
-tw_status ensure_common(tw_graph* g, Error& err) {
-    TW_HIP(ensure(g->err, sizeof(uint32_t) * 4));
-    TW_HIP(ensure(g->scal, sizeof(uint64_t) * 16));
-    return TW_OK;
-}
-
 }  // namespace
 
 tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int64_t* ts,
                  int64_t n, tw_ingest_info* info, Error& err) {
     hipStream_t s = g->stream;
     if (ensure_common(g, err) != TW_OK) return err.code;
+    if (!g->rec.p && init_empty(g, err) != TW_OK) return err.code;
     const int64_t B = g->directed ? n : 2 * n;  // staged records
     if (g->m + B > (int64_t)UINT32_MAX - 2) {
         err = Error{TW_EINVAL, "window would exceed 2^32 - 2 records"};
         return err.code;
     }
-    // reserve everything this ingest may need before touching the window
     TW_HIP(ensure(g->b_src, sizeof(int32_t) * (B + 1)));
     TW_HIP(ensure(g->b_dst, sizeof(int32_t) * (B + 1)));
     TW_HIP(ensure(g->b_ts, sizeof(int64_t) * (B + 1)));
-    const int64_t m_max = g->m + B;
-    TW_HIP(ensure(g->a_src, sizeof(int32_t) * (m_max + 1)));
-    TW_HIP(ensure(g->a_dst, sizeof(int32_t) * (m_max + 1)));
-    TW_HIP(ensure(g->a_ts, sizeof(int64_t) * (m_max + 1)));
 
-    unsigned long long* mm = g->scal.as<unsigned long long>();  // [0] min, [1] max
+    unsigned long long* mm = reinterpret_cast<unsigned long long*>(i64_slot(g, SLOT_I64_MINMAX));
     uint32_t* errf = g->err.as<uint32_t>();
-    uint32_t* unsorted = g->scal.as<uint32_t>() + 6;
+    uint32_t* unsorted = u32_slot(g, SLOT_U32_UNSORTED);
     hipLaunchKernelGGL(k_init_minmax, dim3(1), dim3(1), 0, s, mm, errf + 1, unsorted);
     int32_t* s_src = g->b_src.as<int32_t>();
     int32_t* s_dst = g->b_dst.as<int32_t>();
@@ -512,17 +698,20 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
     const bool windowed = g->window > 0 && g->has_time;
     int64_t cut = INT64_MIN;
     if (windowed) cut = (g->t_now < INT64_MIN + g->window) ? INT64_MIN : g->t_now - g->window;
-    uint32_t* sc = g->scal.as<uint32_t>() + 24;          // [0] kept / cut position, [1] evicted
-    int64_t* first_kept = g->scal.as<int64_t>() + 13;    // bytes 104..111
+    uint32_t* sc_kept = u32_slot(g, SLOT_U32_KEPT);
+    uint32_t* sc_ev = u32_slot(g, SLOT_U32_EVICTED);
+    uint32_t* sc_gev = u32_slot(g, SLOT_U32_GG_EVICTED);
+    int64_t* first_kept = i64_slot(g, SLOT_I64_FIRST_KEPT);
     const bool drop = windowed && B > 0 && bmin < cut;
     const bool evicting = windowed && g->m > 0 && g->t_min < cut;
-    int64_t kept = B, evicted = 0, batch_first = bmin, drop_lo = 0;
-    int64_t key_base = drop ? cut : bmin;
+    int64_t kept = B, evicted = 0, gg_evicted = 0, batch_first = bmin, drop_lo = 0;
+    const int64_t key_base = drop ? cut : bmin;
     uint64_t* keys = nullptr;
     uint32_t* vals = nullptr;
     if (drop && sorted) {
         // late records of a sorted batch are a prefix
-        hipLaunchKernelGGL(k_sorted_cut, dim3(1), dim3(1), 0, s, s_ts, B, cut, sc, first_kept);
+        hipLaunchKernelGGL(k_sorted_cut, dim3(1), dim3(1), 0, s, s_ts, B, cut, sc_kept,
+                           first_kept);
     } else if (!sorted && B > 0) {
         TW_HIP(ensure(g->b_keys, sizeof(uint64_t) * (B + 1)));
         TW_HIP(ensure(g->b_vals, sizeof(uint32_t) * (B + 1)));
@@ -534,7 +723,7 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
             uint32_t* fl = g->b_flags.as<uint32_t>();
             uint32_t* pos = g->idx.as<uint32_t>();
             hipLaunchKernelGGL(k_keep_flags, grid_for(B), dim3(T), 0, s, s_ts, B, cut, fl);
-            TW_HIP(scan_exclusive_u32(fl, pos, B, sc, g->ws, s));
+            TW_HIP(scan_exclusive_u32(fl, pos, B, sc_kept, g->ws, s));
             hipLaunchKernelGGL(k_make_keys, grid_for(B), dim3(T), 0, s, s_ts, B, key_base, fl,
                                pos, keys, vals);
         } else {
@@ -542,14 +731,18 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
                                nullptr, keys, vals);
         }
     }
-    if (evicting)
-        hipLaunchKernelGGL(k_lower_bound, dim3(1), dim3(1), 0, s, g->e_ts.as<int64_t>(), g->m, cut,
-                           sc + 1);
+    if (evicting) {
+        hipLaunchKernelGGL(k_lower_bound, dim3(1), dim3(1), 0, s, g->e_ts.as<int64_t>() + g->e_base,
+                           g->m, cut, sc_ev);
+        hipLaunchKernelGGL(k_lower_bound, dim3(1), dim3(1), 0, s,
+                           g->gg_ts.as<int64_t>() + g->gg_base, g->Gg, cut, sc_gev);
+    }
     TW_HIP(hipGetLastError());
     if (drop || evicting) {
-        uint32_t h2[2] = {0, 0};
+        uint32_t h2[2] = {0, 0}, hg = 0;
         int64_t hf = INT64_MAX;
-        TW_HIP(hipMemcpyAsync(h2, sc, sizeof(h2), hipMemcpyDeviceToHost, s));
+        TW_HIP(hipMemcpyAsync(h2, sc_kept, sizeof(h2), hipMemcpyDeviceToHost, s));
+        TW_HIP(hipMemcpyAsync(&hg, sc_gev, sizeof(hg), hipMemcpyDeviceToHost, s));
         TW_HIP(hipMemcpyAsync(&hf, first_kept, sizeof(hf), hipMemcpyDeviceToHost, s));
         TW_HIP(hipStreamSynchronize(s));
         if (drop && sorted) {
@@ -560,7 +753,10 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
             kept = h2[0];
             batch_first = cut;  // a lower bound of the kept records
         }
-        if (evicting) evicted = h2[1];
+        if (evicting) {
+            evicted = h2[1];
+            gg_evicted = hg;
+        }
     }
 
     // the kept batch records in timestamp order (stable)
@@ -570,53 +766,105 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
     if (!sorted && kept > 0) {
         int kb = bits_for((uint64_t)(bmax - key_base));
         TW_HIP(radix_sort_u64(keys, vals, kept, 0, kb, g->ws, s));
-        TW_HIP(ensure(g->n_src, sizeof(uint32_t) * (kept + 1)));
-        TW_HIP(ensure(g->flags, sizeof(uint32_t) * (kept + 1)));
-        TW_HIP(ensure(g->b_flags, sizeof(int64_t) * (kept + 1)));
-        int32_t* o_src = reinterpret_cast<int32_t*>(g->n_src.as<uint32_t>());
-        int32_t* o_dst = reinterpret_cast<int32_t*>(g->flags.as<uint32_t>());
-        int64_t* o_ts = reinterpret_cast<int64_t*>(g->b_flags.as<uint32_t>());
+        TW_HIP(ensure(g->q_src, sizeof(int32_t) * (kept + 1)));
+        TW_HIP(ensure(g->q_dst, sizeof(int32_t) * (kept + 1)));
+        TW_HIP(ensure(g->q_ts, sizeof(int64_t) * (kept + 1)));
         hipLaunchKernelGGL(k_gather_batch, grid_for(kept), dim3(T), 0, s, vals, kept, s_src, s_dst,
-                           s_ts, o_src, o_dst, o_ts);
-        q_src = o_src;
-        q_dst = o_dst;
-        q_ts = o_ts;
+                           s_ts, g->q_src.as<int32_t>(), g->q_dst.as<int32_t>(),
+                           g->q_ts.as<int64_t>());
+        q_src = g->q_src.as<int32_t>();
+        q_dst = g->q_dst.as<int32_t>();
+        q_ts = g->q_ts.as<int64_t>();
     }
 
-    // merge the surviving window with the batch into the alternate buffers;
-    // a batch that starts at or after the window's last timestamp is appended
-    const int64_t na = g->m - evicted;
+    // timestamp view: a batch that starts at or after the window's last
+    // timestamp is appended in place (eviction only moves e_base); any other
+    // batch is merged (merge path, older records first on equal timestamps)
+    const int64_t m_old = g->m;
+    const int64_t na = m_old - evicted;
     const int64_t m_new = na + kept;
     const bool append = na == 0 || kept == 0 || batch_first >= g->t_max;
+    const int64_t last_ts = g->t_max;
+    const int64_t gg_old = g->Gg;
+    bool gg_full = false;
     if (append) {
-        if (na > 0) {
-            TW_HIP(hipMemcpyAsync(g->a_src.p, g->e_src.as<int32_t>() + evicted, 4 * na,
-                                  hipMemcpyDeviceToDevice, s));
-            TW_HIP(hipMemcpyAsync(g->a_dst.p, g->e_dst.as<int32_t>() + evicted, 4 * na,
-                                  hipMemcpyDeviceToDevice, s));
-            TW_HIP(hipMemcpyAsync(g->a_ts.p, g->e_ts.as<int64_t>() + evicted, 8 * na,
-                                  hipMemcpyDeviceToDevice, s));
+        g->e_base += evicted;
+        g->gg_base += gg_evicted;
+        if (na == 0) {
+            g->e_base = 0;
+            g->gg_base = 0;
+        }
+        g->m = na;
+        if (g->e_base + m_new > g->e_cap) {
+            if (m_new <= g->e_cap && g->m > 0) {
+                // compact to the front of the alternate buffers
+                TW_HIP(hipMemcpyAsync(g->a_src.p, g->e_src.as<int32_t>() + g->e_base, 4 * na,
+                                      hipMemcpyDeviceToDevice, s));
+                TW_HIP(hipMemcpyAsync(g->a_dst.p, g->e_dst.as<int32_t>() + g->e_base, 4 * na,
+                                      hipMemcpyDeviceToDevice, s));
+                TW_HIP(hipMemcpyAsync(g->a_ts.p, g->e_ts.as<int64_t>() + g->e_base, 8 * na,
+                                      hipMemcpyDeviceToDevice, s));
+                std::swap(g->e_src, g->a_src);
+                std::swap(g->e_dst, g->a_dst);
+                std::swap(g->e_ts, g->a_ts);
+                g->e_base = 0;
+            } else if (reserve_window(g, m_new, err) != TW_OK) {
+                return err.code;
+            }
+            gg_full = true;
         }
         if (kept > 0) {
-            TW_HIP(hipMemcpyAsync(g->a_src.as<int32_t>() + na, q_src, 4 * kept,
+            const int64_t at = g->e_base + na;
+            TW_HIP(hipMemcpyAsync(g->e_src.as<int32_t>() + at, q_src, 4 * kept,
                                   hipMemcpyDeviceToDevice, s));
-            TW_HIP(hipMemcpyAsync(g->a_dst.as<int32_t>() + na, q_dst, 4 * kept,
+            TW_HIP(hipMemcpyAsync(g->e_dst.as<int32_t>() + at, q_dst, 4 * kept,
                                   hipMemcpyDeviceToDevice, s));
-            TW_HIP(hipMemcpyAsync(g->a_ts.as<int64_t>() + na, q_ts, 8 * kept,
+            TW_HIP(hipMemcpyAsync(g->e_ts.as<int64_t>() + at, q_ts, 8 * kept,
                                   hipMemcpyDeviceToDevice, s));
         }
+        g->m = m_new;
+        if (gg_full || na == 0) {
+            gg_full = true;
+            if (build_ts_groups(g, err) != TW_OK) return err.code;
+        } else if (kept > 0) {
+            TW_HIP(ensure(g->flags, sizeof(uint32_t) * (kept + 1)));
+            TW_HIP(ensure(g->idx, sizeof(uint32_t) * (kept + 1)));
+            uint32_t* fl = g->flags.as<uint32_t>();
+            uint32_t* gi = g->idx.as<uint32_t>();
+            uint32_t* G = u32_slot(g, SLOT_U32_GROUPS);
+            const int64_t gpos = g->gg_base + (gg_old - gg_evicted);
+            hipLaunchKernelGGL(k_append_group_flags, grid_for(kept), dim3(T), 0, s, q_ts, kept,
+                               last_ts, 1, fl);
+            TW_HIP(scan_exclusive_u32(fl, gi, kept, G, g->ws, s));
+            hipLaunchKernelGGL(k_ts_group_scatter, grid_for(kept), dim3(T), 0, s, q_ts, kept, fl,
+                               gi, g->gg_ts.as<int64_t>() + gpos, g->gg_off.as<uint32_t>() + gpos,
+                               G, (uint32_t)(g->e_base + na));
+        } else {
+            // eviction only: the groups keep their offsets
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(T), 0, s, u32_slot(g, SLOT_U32_GROUPS), 1,
+                               0u);
+        }
     } else {
+        if (reserve_window(g, m_new, err) != TW_OK) return err.code;
+        const int64_t from = g->e_base + evicted;
         hipLaunchKernelGGL(k_merge, grid_for(m_new, MP_ITEMS), dim3(T), 0, s,
-                           g->e_src.as<int32_t>() + evicted, g->e_dst.as<int32_t>() + evicted,
-                           g->e_ts.as<int64_t>() + evicted, na, q_src, q_dst, q_ts, kept,
+                           g->e_src.as<int32_t>() + from, g->e_dst.as<int32_t>() + from,
+                           g->e_ts.as<int64_t>() + from, na, q_src, q_dst, q_ts, kept,
                            g->a_src.as<int32_t>(), g->a_dst.as<int32_t>(), g->a_ts.as<int64_t>());
+        TW_HIP(hipGetLastError());
+        std::swap(g->e_src, g->a_src);
+        std::swap(g->e_dst, g->a_dst);
+        std::swap(g->e_ts, g->a_ts);
+        g->e_base = 0;
+        g->m = m_new;
+        gg_full = true;
+        if (build_ts_groups(g, err) != TW_OK) return err.code;
     }
-    TW_HIP(hipGetLastError());
-    std::swap(g->e_src, g->a_src);
-    std::swap(g->e_dst, g->a_dst);
-    std::swap(g->e_ts, g->a_ts);
-    g->m = m_new;
-    if (rebuild_views(g, err) != TW_OK) return err.code;
+
+    // node view: per-node merge of the surviving runs with the batch
+    if (merge_node_view(g, q_src, q_dst, q_ts, kept, m_old, m_new, evicting, cut, err) != TW_OK)
+        return err.code;
+    if (finish_index(g, gg_full, gg_old, gg_evicted, err) != TW_OK) return err.code;
 
     g->last.accepted = kept;
     g->last.dropped_late = B - kept;
@@ -631,32 +879,40 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
 tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& err) {
     hipStream_t s = g->stream;
     if (ensure_common(g, err) != TW_OK) return err.code;
-    int64_t ev = 0;
+    if (!g->rec.p && init_empty(g, err) != TW_OK) return err.code;
+    int64_t ev = 0, gev = 0;
     if (g->m > 0 && g->t_min < cutoff) {
-        uint32_t* sc = g->scal.as<uint32_t>() + 24;
-        hipLaunchKernelGGL(k_lower_bound, dim3(1), dim3(1), 0, s, g->e_ts.as<int64_t>(), g->m,
-                           cutoff, sc + 1);
-        uint32_t h = 0;
-        TW_HIP(hipMemcpyAsync(&h, sc + 1, sizeof(h), hipMemcpyDeviceToHost, s));
+        uint32_t* sc_ev = u32_slot(g, SLOT_U32_EVICTED);
+        uint32_t* sc_gev = u32_slot(g, SLOT_U32_GG_EVICTED);
+        hipLaunchKernelGGL(k_lower_bound, dim3(1), dim3(1), 0, s, g->e_ts.as<int64_t>() + g->e_base,
+                           g->m, cutoff, sc_ev);
+        hipLaunchKernelGGL(k_lower_bound, dim3(1), dim3(1), 0, s,
+                           g->gg_ts.as<int64_t>() + g->gg_base, g->Gg, cutoff, sc_gev);
+        uint32_t h[2] = {0, 0};
+        TW_HIP(hipMemcpyAsync(&h[0], sc_ev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        TW_HIP(hipMemcpyAsync(&h[1], sc_gev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         TW_HIP(hipStreamSynchronize(s));
-        ev = h;
+        ev = h[0];
+        gev = h[1];
     }
     if (ev > 0) {
-        int64_t keep = g->m - ev;
-        TW_HIP(ensure(g->a_src, sizeof(int32_t) * (keep + 1)));
-        TW_HIP(ensure(g->a_dst, sizeof(int32_t) * (keep + 1)));
-        TW_HIP(ensure(g->a_ts, sizeof(int64_t) * (keep + 1)));
-        TW_HIP(hipMemcpyAsync(g->a_src.p, g->e_src.as<int32_t>() + ev, sizeof(int32_t) * keep,
-                              hipMemcpyDeviceToDevice, s));
-        TW_HIP(hipMemcpyAsync(g->a_dst.p, g->e_dst.as<int32_t>() + ev, sizeof(int32_t) * keep,
-                              hipMemcpyDeviceToDevice, s));
-        TW_HIP(hipMemcpyAsync(g->a_ts.p, g->e_ts.as<int64_t>() + ev, sizeof(int64_t) * keep,
-                              hipMemcpyDeviceToDevice, s));
-        std::swap(g->e_src, g->a_src);
-        std::swap(g->e_dst, g->a_dst);
-        std::swap(g->e_ts, g->a_ts);
-        g->m = keep;
-        if (rebuild_views(g, err) != TW_OK) return err.code;
+        const int64_t m_old = g->m, gg_old = g->Gg;
+        g->e_base += ev;
+        g->gg_base += gev;
+        g->m = m_old - ev;
+        bool gg_full = false;
+        if (g->m == 0) {
+            g->e_base = 0;
+            gg_full = true;
+            if (build_ts_groups(g, err) != TW_OK) return err.code;
+        } else {
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(T), 0, s, u32_slot(g, SLOT_U32_GROUPS), 1,
+                               0u);
+        }
+        if (merge_node_view(g, nullptr, nullptr, nullptr, 0, m_old, g->m, true, cutoff, err) !=
+            TW_OK)
+            return err.code;
+        if (finish_index(g, gg_full, gg_old, gev, err) != TW_OK) return err.code;
     }
     g->last.accepted = 0;
     g->last.dropped_late = 0;
@@ -670,7 +926,13 @@ tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& e
 
 tw_status init_empty(tw_graph* g, Error& err) {
     if (ensure_common(g, err) != TW_OK) return err.code;
-    return rebuild_views(g, err);
+    if (reserve_window(g, 1024, err) != TW_OK) return err.code;
+    TW_HIP(ensure(g->n_src, sizeof(uint32_t) * 2));
+    TW_HIP(ensure(g->n_dst, sizeof(int32_t) * 2));
+    TW_HIP(ensure(g->n_ts, sizeof(int64_t) * 2));
+    g->m = 0;
+    if (build_ts_groups(g, err) != TW_OK) return err.code;
+    return finish_index(g, true, 0, 0, err);
 }
 
 tw_status build_adjacency(tw_graph* g, Error& err) {
@@ -700,30 +962,22 @@ tw_status export_views(tw_graph* g, int32_t* src, int32_t* dst, int64_t* ts, int
         if (!d || bytes == 0) return hipSuccess;
         return hipMemcpyAsync(d, sp, bytes, hipMemcpyDeviceToDevice, s);
     };
-    TW_HIP(cp(src, g->e_src.p, sizeof(int32_t) * m));
-    TW_HIP(cp(dst, g->e_dst.p, sizeof(int32_t) * m));
-    TW_HIP(cp(ts, g->e_ts.p, sizeof(int64_t) * m));
-    TW_HIP(cp(g_ts, g->gg_ts.p, sizeof(int64_t) * g->Gg));
+    TW_HIP(cp(src, g->e_src.as<int32_t>() + g->e_base, sizeof(int32_t) * m));
+    TW_HIP(cp(dst, g->e_dst.as<int32_t>() + g->e_base, sizeof(int32_t) * m));
+    TW_HIP(cp(ts, g->e_ts.as<int64_t>() + g->e_base, sizeof(int64_t) * m));
+    TW_HIP(cp(g_ts, g->gg_ts.as<int64_t>() + g->gg_base, sizeof(int64_t) * g->Gg));
     TW_HIP(cp(n_dst, g->n_dst.p, sizeof(int32_t) * m));
     TW_HIP(cp(n_ts, g->n_ts.p, sizeof(int64_t) * m));
     TW_HIP(cp(n_gts, g->ng_ts.p, sizeof(int64_t) * g->Gn));
-    if (g_off && g->gg_off.p)
-        hipLaunchKernelGGL(k_widen, grid_for(g->Gg + 1), dim3(T), 0, s, g->gg_off.as<uint32_t>(),
-                           g->Gg + 1, g_off);
-    else if (g_off)
-        TW_HIP(hipMemsetAsync(g_off, 0, sizeof(int64_t), s));
-    if (n_goff && g->ng_off.p)
+    if (g_off)
+        hipLaunchKernelGGL(k_widen, grid_for(g->Gg + 1), dim3(T), 0, s,
+                           g->gg_off.as<uint32_t>() + g->gg_base, g->Gg + 1, g_off, g->e_base);
+    if (n_goff)
         hipLaunchKernelGGL(k_widen, grid_for(g->Gn + 1), dim3(T), 0, s, g->ng_off.as<uint32_t>(),
-                           g->Gn + 1, n_goff);
-    else if (n_goff)
-        TW_HIP(hipMemsetAsync(n_goff, 0, sizeof(int64_t), s));
-    if ((n_ebeg || n_gbeg) && g->rec.p)
+                           g->Gn + 1, n_goff, (int64_t)0);
+    if (n_ebeg || n_gbeg)
         hipLaunchKernelGGL(k_export_nodes, grid_for(g->V + 1), dim3(T), 0, s,
                            g->rec.as<NodeRec>(), g->V, m, g->Gn, n_ebeg, n_gbeg);
-    else {
-        if (n_ebeg) TW_HIP(hipMemsetAsync(n_ebeg, 0, sizeof(int64_t) * (g->V + 1), s));
-        if (n_gbeg) TW_HIP(hipMemsetAsync(n_gbeg, 0, sizeof(int64_t) * (g->V + 1), s));
-    }
     TW_HIP(hipGetLastError());
     TW_HIP(hipStreamSynchronize(s));
     return TW_OK;

@@ -33,6 +33,21 @@ struct alignas(32) NodeRec {
 constexpr int FENCE_FAN = 16;
 constexpr int FENCE_LOG = 4;
 
+// Slots of the graph's device scalar buffer (256 bytes): u32 indices
+// (SLOT_U32_*) and int64 indices (SLOT_I64_*).
+constexpr int SLOT_I64_MINMAX = 0;     // batch min / max timestamp (ordered u64) in [0], [1]
+constexpr int SLOT_U32_GROUPS = 4;     // groups counted by the last timestamp-group scan
+constexpr int SLOT_U32_GN = 5;         // node-timestamp groups
+constexpr int SLOT_U32_UNSORTED = 6;   // batch not in timestamp order
+constexpr int SLOT_U32_FENCE = 7;      // fence entries
+constexpr int SLOT_I64_SUMMARY = 4;    // [4] t_min, [5] t_max of the window
+constexpr int SLOT_U32_KEPT = 24;      // kept batch records / late-prefix length
+constexpr int SLOT_U32_EVICTED = 25;   // evicted window records
+constexpr int SLOT_I64_FIRST_KEPT = 13;
+constexpr int SLOT_U32_N_LIVE = 28;    // live walks (cooperative dispatch)
+constexpr int SLOT_U32_GG_EVICTED = 29;
+constexpr int SCALAR_BYTES = 256;
+
 // A grow-only device allocation.
 struct DevBuf {
     void* p = nullptr;
@@ -103,8 +118,12 @@ struct tw_graph {
     bool has_time = false;
     int64_t t_now = 0;
 
-    // host mirrors of the index sizes
+    // host mirrors of the index sizes. The window occupies positions
+    // [e_base, e_base + m) of the edge-store buffers (capacity e_cap); its
+    // timestamp groups occupy [gg_base, gg_base + Gg) of gg_ts / gg_off, whose
+    // offsets are edge-store buffer positions.
     int64_t m = 0, Gg = 0, Gn = 0;
+    int64_t e_base = 0, e_cap = 0, gg_base = 0;
     int64_t t_min = 0, t_max = 0;
     tw_ingest_info last{};
 
@@ -112,6 +131,10 @@ struct tw_graph {
     tw::DevBuf e_src, e_dst, e_ts, a_src, a_dst, a_ts;
     tw::DevBuf gg_ts, gg_off;          // global timestamp groups
     tw::DevBuf n_dst, n_ts;            // node-and-timestamp view
+    tw::DevBuf an_src, an_dst, an_ts;  // its alternate for the merge
+    tw::DevBuf bs_src, bs_dst, bs_ts;  // batch sorted by source
+    tw::DevBuf q_src, q_dst, q_ts;     // batch sorted by timestamp (unsorted input)
+    tw::DevBuf plan, node_tmp;         // per-node merge plan, per-node counts
     tw::DevBuf ng_ts, ng_off;          // its (node, timestamp) groups
     tw::DevBuf n_src;                  // source of each node-view edge (build temp)
     tw::DevBuf ng_node;                // node of each (node, timestamp) group

@@ -17,7 +17,7 @@ struct WalkArgs {
     const int64_t* e_ts;
     const int64_t* gg_ts;
     const uint32_t* gg_off;
-    uint32_t m, Gg;
+    uint32_t m, Gg, e_base;  // the window is e_*[e_base, e_base + m)
     // node view
     const int32_t* n_dst;
     const int64_t* n_ts;
@@ -61,7 +61,7 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, int64_t w, u
         if (a.m == 0) return st;
         uint32_t e;
         if (a.start_kind == TW_UNIFORM) {
-            e = (uint32_t)scale_u64(d0.x0, a.m);
+            e = a.e_base + (uint32_t)scale_u64(d0.x0, a.m);
         } else {
             Pick p = pick_in_groups(a.gg_ts, a.gg_off, a.e_ts, 0, a.Gg, a.m, a.start_kind,
                                     a.start_tau, a.gg_ts[a.Gg - 1], d0);
@@ -315,7 +315,7 @@ tw_status coop_walks(tw_graph* g, const WalkArgs& a, Error& err) {
     int32_t* prev = g->c_prev.as<int32_t>();
     uint32_t* flags = g->c_flags.as<uint32_t>();
     uint32_t* pos = g->c_pos.as<uint32_t>();
-    uint32_t* n_live_d = g->scal.as<uint32_t>() + 28;  // bytes 112..115
+    uint32_t* n_live_d = g->scal.as<uint32_t>() + SLOT_U32_N_LIVE;
     const int vbits = bits_for((uint64_t)(g->V - 1));
     const uint32_t panel_cap = g->coop_panel;
     const dim3 wgrid((unsigned)ceil_div(W, WALK_THREADS));
@@ -388,8 +388,9 @@ tw_status sample_walks(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int
     a.e_src = g->e_src.as<int32_t>();
     a.e_dst = g->e_dst.as<int32_t>();
     a.e_ts = g->e_ts.as<int64_t>();
-    a.gg_ts = g->gg_ts.as<int64_t>();
-    a.gg_off = g->gg_off.as<uint32_t>();
+    a.gg_ts = g->gg_ts.as<int64_t>() + g->gg_base;
+    a.gg_off = g->gg_off.as<uint32_t>() + g->gg_base;
+    a.e_base = (uint32_t)g->e_base;
     a.m = (uint32_t)g->m;
     a.Gg = (uint32_t)g->Gg;
     a.n_dst = g->n_dst.as<int32_t>();

@@ -253,3 +253,38 @@ def test_dispatches_agree_on_lengths_and_edge_cases(L):
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
     g.close()
+
+
+@pytest.mark.parametrize("sorted_arrivals", [True, False])
+def test_long_stream_compactions(sorted_arrivals):
+    # many batches under a short window: the window's start moves through
+    # the edge-store buffers and forces repeated compaction / regrowth;
+    # explicit evictions in between
+    torch, tw = gpu_or_skip()
+    rng = np.random.default_rng(21 + sorted_arrivals)
+    V, window = 997, 4_000
+    g = tw.Graph(V, window=window)
+    og = oracle.OracleGraph(V, window=window)
+    t0 = 0
+    for b in range(60):
+        n = int(rng.integers(500, 3000))
+        s = rng.integers(0, V, n).astype(np.int32)
+        d = rng.integers(0, V, n).astype(np.int32)
+        if sorted_arrivals:
+            t = (t0 + np.sort(rng.integers(0, 1000, n))).astype(np.int64)
+        else:
+            t = (t0 + rng.integers(-1500, 1000, n)).astype(np.int64)
+        t0 += 1000
+        assert g.ingest_batch(*to_dev(torch, s, d, t)) == og.ingest_batch(s, d, t), b
+        if b % 7 == 3:
+            cut = t0 - 2500
+            assert g.evict_before(cut) == og.evict_before(cut)
+        if b % 10 == 9:
+            _views_equal(g, og)
+            nodes, ts, lens = g.sample_walks(500, 12, hop_bias="linear",
+                                             start_bias="exponential", start_tau=300.0, seed=b)
+            g.sync()
+            r = og.sample_walks(500, 12, hop_bias="linear", start_bias="exponential",
+                                start_tau=300.0, seed=b, with_margin=True)
+            compare_walks((nodes.cpu().numpy(), ts.cpu().numpy(), lens.cpu().numpy()), r, False)
+    g.close()
