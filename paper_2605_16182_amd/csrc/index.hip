@@ -10,7 +10,7 @@
 //                                      offsets are edge-store positions
 //   node-and-timestamp view:           n_src n_dst n_ts [m] (sorted by source,
 //                                      timestamp, arrival)
-//   its (node, timestamp) groups:      ng_ts ng_off ng_node [Gn]
+//   its (node, timestamp) groups:      ng_ts ng_off [Gn]
 //   node table:                        rec[V] (32-byte NodeRec), fence levels
 //
 // One ingest: stage (validate, mirror, min/max, sortedness) -> late drop ->
@@ -205,35 +205,6 @@ __global__ void k_append_group_flags(const int64_t* __restrict__ ts, int64_t n, 
     flags[i] = (i == 0) ? (!has_last || ts[0] != last_ts) : (ts[i] != ts[i - 1]);
 }
 
-// Per-node plan of the node-view merge: first surviving old edge ob (the
-// node's edges before `cut` are evicted), old end oe, and the node's run
-// [bf, be) in the batch sorted by source; cnt[v] = merged size of the node.
-__global__ void k_merge_plan(const NodeRec* __restrict__ rec, const int64_t* __restrict__ n_ts,
-                             int32_t V, int64_t cut, int evicting,
-                             const uint32_t* __restrict__ b_first,
-                             const uint32_t* __restrict__ b_end, uint4* __restrict__ plan,
-                             uint32_t* __restrict__ cnt) {
-    int64_t v = (int64_t)blockIdx.x * T + threadIdx.x;
-    if (v > V) return;
-    if (v == V) {
-        cnt[v] = 0;
-        return;
-    }
-    const NodeRec r = rec[v];
-    uint32_t ob = r.eb;
-    if (evicting && r.eb < r.ee && n_ts[r.eb] < cut) {
-        uint32_t lo = r.eb, hi = r.ee;
-        while (lo < hi) {
-            uint32_t mid = lo + ((hi - lo) >> 1);
-            if (n_ts[mid] < cut) lo = mid + 1; else hi = mid;
-        }
-        ob = lo;
-    }
-    const uint32_t bf = b_first[v], be = b_end[v];
-    plan[v] = make_uint4(ob, r.ee, bf, be);
-    cnt[v] = (r.ee - ob) + (be - bf);
-}
-
 // Surviving old edges to their merged positions: before them within the node
 // go the batch edges with a strictly smaller timestamp (older edges first on
 // equal timestamps).
@@ -241,7 +212,8 @@ __global__ void k_merge_old(const uint32_t* __restrict__ n_src, const int32_t* _
                             const int64_t* __restrict__ n_ts, int64_t m_old,
                             const uint4* __restrict__ plan, const uint32_t* __restrict__ neb,
                             const int64_t* __restrict__ bs_ts, uint32_t* __restrict__ o_src,
-                            int32_t* __restrict__ o_dst, int64_t* __restrict__ o_ts) {
+                            int32_t* __restrict__ o_dst, int64_t* __restrict__ o_ts,
+                            uint32_t* __restrict__ o_flag) {
     int64_t j = (int64_t)blockIdx.x * T + threadIdx.x;
     if (j >= m_old) return;
     const uint32_t v = n_src[j];
@@ -261,6 +233,10 @@ __global__ void k_merge_old(const uint32_t* __restrict__ n_src, const int32_t* _
     o_src[d] = v;
     o_dst[d] = n_dst[j];
     o_ts[d] = t;
+    // a surviving old edge starts a (node, timestamp) group unless the old
+    // edge before it has the same timestamp (no batch edge can sit between
+    // equal old timestamps, since older edges go first on ties)
+    o_flag[d] = ((uint32_t)j == p.x || n_ts[j - 1] != t) ? 1u : 0u;
 }
 
 // Batch edges (sorted by source, stable) to their merged positions: before
@@ -269,7 +245,8 @@ __global__ void k_merge_new(const uint32_t* __restrict__ bs_src, const int32_t* 
                             const int64_t* __restrict__ bs_ts, int64_t nb,
                             const uint4* __restrict__ plan, const uint32_t* __restrict__ neb,
                             const int64_t* __restrict__ n_ts, uint32_t* __restrict__ o_src,
-                            int32_t* __restrict__ o_dst, int64_t* __restrict__ o_ts) {
+                            int32_t* __restrict__ o_dst, int64_t* __restrict__ o_ts,
+                            uint32_t* __restrict__ o_flag) {
     int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
     if (i >= nb) return;
     const uint32_t v = bs_src[i];
@@ -292,24 +269,21 @@ __global__ void k_merge_new(const uint32_t* __restrict__ bs_src, const int32_t* 
     o_src[d] = v;
     o_dst[d] = bs_dst[i];
     o_ts[d] = y;
+    // the merged predecessor: the last surviving old edge with timestamp <= y
+    // when it comes after the previous batch edge of the node (old edges
+    // with a timestamp equal to that batch edge's come before it), else the
+    // previous batch edge; none for the node's first edge
+    uint32_t flag = 1;
+    const bool has_prev_b = (uint32_t)i > p.z;
+    if (c > 0 && (!has_prev_b || n_ts[p.x + c - 1] > bs_ts[i - 1]))
+        flag = n_ts[p.x + c - 1] != y;
+    else if (has_prev_b)
+        flag = bs_ts[i - 1] != y;
+    o_flag[d] = flag;
 }
 
 // (node, timestamp) groups of the node view, with the node of each group
-__global__ void k_node_group_scatter(const int64_t* __restrict__ ts,
-                                     const uint32_t* __restrict__ n_src, int64_t m,
-                                     const uint32_t* __restrict__ flags,
-                                     const uint32_t* __restrict__ gidx, int64_t* __restrict__ g_ts,
-                                     uint32_t* __restrict__ g_off, uint32_t* __restrict__ g_node,
-                                     const uint32_t* G) {
-    int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
-    if (i < m && flags[i]) {
-        uint32_t k = gidx[i];
-        g_ts[k] = ts[i];
-        g_off[k] = (uint32_t)i;
-        g_node[k] = n_src[i];
-    }
-    if (i == 0) g_off[*G] = (uint32_t)m;
-}
+
 
 // levels K and total entries of the fence of a node with G groups
 __device__ __forceinline__ void fence_shape(uint32_t G, uint32_t* levels, uint32_t* size) {
@@ -349,87 +323,9 @@ __global__ void k_run_bounds(const uint32_t* __restrict__ n_src, int64_t m,
     if (i == m - 1 || n_src[i + 1] != u) end[u] = (uint32_t)(i + 1);
 }
 
-// Edge and group counts per node (in place over first / end); the exclusive
-// scans of these counts are the node offsets. gidx is the exclusive scan of
-// the (node, timestamp) group flags, so gidx[j] counts groups starting before
-// edge j, and Gn stands for gidx[m].
-__global__ void k_node_counts(uint32_t* __restrict__ first_to_ecnt,
-                              uint32_t* __restrict__ end_to_gcnt, int32_t V, int64_t m,
-                              const uint32_t* __restrict__ gidx, const uint32_t* Gn) {
-    int64_t v = (int64_t)blockIdx.x * T + threadIdx.x;
-    if (v > V) return;
-    if (v == V) {
-        first_to_ecnt[v] = 0;
-        end_to_gcnt[v] = 0;
-        return;
-    }
-    uint32_t f = first_to_ecnt[v], e = end_to_gcnt[v];
-    uint32_t ge = (int64_t)e >= m ? *Gn : gidx[e];
-    uint32_t gc = e > f ? ge - gidx[f] : 0;
-    first_to_ecnt[v] = e - f;
-    end_to_gcnt[v] = gc;
-}
-
-// node records; fence sizes of every node into fsize[v] (fsize[V] = 0)
-__global__ void k_node_records(const uint32_t* __restrict__ node_e,
-                               const uint32_t* __restrict__ node_g, int32_t V,
-                               const int64_t* __restrict__ ng_ts, NodeRec* __restrict__ rec,
-                               uint32_t* __restrict__ fsize) {
-    int64_t v = (int64_t)blockIdx.x * T + threadIdx.x;
-    if (v > V) return;
-    if (v == V) {
-        fsize[v] = 0;
-        return;
-    }
-    NodeRec r;
-    r.gb = node_g[v];
-    r.ge = node_g[v + 1];
-    r.eb = node_e[v];
-    r.ee = node_e[v + 1];
-    uint32_t size;
-    fence_shape(r.ge - r.gb, &r.levels, &size);
-    r.fence_off = 0;
-    r.t_last = r.gb < r.ge ? ng_ts[r.ge - 1] : INT64_MIN;
-    rec[v] = r;
-    fsize[v] = size;
-}
-
-__global__ void k_fence_offsets(const uint32_t* __restrict__ foff, int32_t V,
-                                NodeRec* __restrict__ rec) {
-    int64_t v = (int64_t)blockIdx.x * T + threadIdx.x;
-    if (v < V) rec[v].fence_off = foff[v];
-}
-
 __global__ void k_fill_i64(int64_t* __restrict__ p, int64_t n, int64_t v) {
     int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
     if (i < n) p[i] = v;
-}
-
-// Each group p whose position inside its node is a multiple of FENCE_FAN^k
-// writes its timestamp into level k of the node's fence.
-__global__ void k_fence_fill(const int64_t* __restrict__ ng_ts, const uint32_t* __restrict__ ng_node,
-                             int64_t Gn, const NodeRec* __restrict__ rec,
-                             int64_t* __restrict__ fence) {
-    int64_t p = (int64_t)blockIdx.x * T + threadIdx.x;
-    if (p >= Gn) return;
-    const NodeRec r = rec[ng_node[p]];
-    if (r.levels == 0) return;
-    const uint64_t rel = (uint64_t)((uint32_t)p - r.gb);
-    if (rel & (FENCE_FAN - 1)) return;
-    const uint32_t G = r.ge - r.gb;
-    uint64_t nk[9];
-    uint64_t n = G;
-    for (uint32_t k = 1; k <= r.levels; ++k) {
-        n = (n + FENCE_FAN - 1) / FENCE_FAN;
-        nk[k] = n;
-    }
-    uint64_t off = r.fence_off;  // level K first
-    const int64_t t = ng_ts[p];
-    for (uint32_t k = r.levels; k >= 1; --k) {
-        const uint32_t sh = FENCE_LOG * k;
-        if ((rel & ((1ull << sh) - 1)) == 0) fence[off + (rel >> sh)] = t;
-        off += (nk[k] + FENCE_FAN - 1) / FENCE_FAN * FENCE_FAN;
-    }
 }
 
 __global__ void k_adj_keys(const uint32_t* __restrict__ n_src, const int32_t* __restrict__ n_dst,
@@ -450,12 +346,243 @@ __global__ void k_widen(const uint32_t* __restrict__ in, int64_t n, int64_t* __r
     if (i < n) out[i] = (int64_t)in[i] - minus;
 }
 
-__global__ void k_export_nodes(const NodeRec* __restrict__ rec, int32_t V, int64_t m, int64_t Gn,
+// ---------------------------------------------------------- active nodes
+//
+// The node table is maintained over the nodes that have edges (the active
+// nodes, kept as a sorted list); every other node holds the empty record.
+// Each ingest forms the union of the active list with the batch's source
+// runs, merges per union node, and writes records only for union nodes.
+
+__device__ __forceinline__ NodeRec empty_rec() {
+    NodeRec r;
+    r.gb = r.ge = r.eb = r.ee = 0;
+    r.fence_off = r.levels = 0;
+    r.t_last = INT64_MIN;
+    return r;
+}
+
+__global__ void k_fill_empty_rec(NodeRec* __restrict__ rec, int64_t V) {
+    int64_t v = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (v < V) rec[v] = empty_rec();
+}
+
+// flags[i] = 1 where a new source starts in the source-sorted src[0..n)
+__global__ void k_run_start_flags(const uint32_t* __restrict__ src, int64_t n,
+                                  uint32_t* __restrict__ flags) {
+    int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (i < n) flags[i] = (i == 0 || src[i] != src[i - 1]) ? 1u : 0u;
+}
+
+// Union items: the old active nodes (payload ~0) after the batch's source
+// runs (payload bf << 32 | be), so that a stable sort keeps a node's old
+// item first. rpos = exclusive scan of the run-start flags.
+__global__ void k_items_old(const uint32_t* __restrict__ act, int64_t A, int64_t at,
+                            uint32_t* __restrict__ keys, uint64_t* __restrict__ pay) {
+    int64_t k = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (k < A) {
+        keys[at + k] = act[k];
+        pay[at + k] = ~0ull;
+    }
+}
+
+__global__ void k_items_batch(const uint32_t* __restrict__ bsrc, int64_t n,
+                              const uint32_t* __restrict__ flags, const uint32_t* __restrict__ rpos,
+                              uint32_t* __restrict__ keys, uint64_t* __restrict__ pay) {
+    int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t v = bsrc[i];
+    uint32_t* halves = reinterpret_cast<uint32_t*>(pay);  // [2r] = be, [2r+1] = bf
+    if (flags[i]) {
+        const uint32_t r = rpos[i];
+        keys[r] = v;
+        halves[2 * r + 1] = (uint32_t)i;
+    }
+    if (i == n - 1 || bsrc[i + 1] != v) halves[2 * (rpos[i] + flags[i] - 1)] = (uint32_t)(i + 1);
+}
+
+// Per union node (first item of each key): the merge plan {ob, oe, bf, be}
+// (surviving old run [ob, oe) after evicting edges older than cut, batch run
+// [bf, be)) and its merged size.
+__global__ void k_union_plan(const uint32_t* __restrict__ keys, const uint64_t* __restrict__ pay,
+                             int64_t n, const uint32_t* __restrict__ uflags,
+                             const uint32_t* __restrict__ upos, const NodeRec* __restrict__ rec,
+                             const int64_t* __restrict__ n_ts, int evicting, int64_t cut,
+                             uint4* __restrict__ plan, uint32_t* __restrict__ u_node,
+                             uint32_t* __restrict__ u_cnt) {
+    int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (i >= n || !uflags[i]) return;
+    const uint32_t v = keys[i];
+    bool has_old = false;
+    uint32_t bf = 0, be = 0;
+    for (int64_t j = i; j < n && j < i + 2 && keys[j] == v; ++j) {
+        const uint64_t p = pay[j];
+        if (p == ~0ull) {
+            has_old = true;
+        } else {
+            bf = (uint32_t)(p >> 32);
+            be = (uint32_t)p;
+        }
+    }
+    uint32_t ob = 0, oe = 0;
+    if (has_old) {
+        const NodeRec r = rec[v];
+        ob = r.eb;
+        oe = r.ee;
+        if (evicting && ob < oe && n_ts[ob] < cut) {
+            uint32_t lo = ob, hi = oe;
+            while (lo < hi) {
+                uint32_t mid = lo + ((hi - lo) >> 1);
+                if (n_ts[mid] < cut) lo = mid + 1; else hi = mid;
+            }
+            ob = lo;
+        }
+    }
+    plan[v] = make_uint4(ob, oe, bf, be);
+    const uint32_t u = upos[i];
+    u_node[u] = v;
+    u_cnt[u] = (oe - ob) + (be - bf);
+}
+
+__global__ void k_union_offsets(const uint32_t* __restrict__ u_node,
+                                const uint32_t* __restrict__ u_neb, int64_t U,
+                                uint32_t* __restrict__ neb_v) {
+    int64_t u = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (u < U) neb_v[u_node[u]] = u_neb[u];
+}
+
+// union nodes left without edges get the empty record; flags the others
+__global__ void k_union_active(const uint32_t* __restrict__ u_node,
+                               const uint32_t* __restrict__ u_cnt, int64_t U,
+                               NodeRec* __restrict__ rec, uint32_t* __restrict__ aflags) {
+    int64_t u = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (u >= U) return;
+    const bool a = u_cnt[u] > 0;
+    if (!a) rec[u_node[u]] = empty_rec();
+    aflags[u] = a ? 1u : 0u;
+}
+
+// the new active list with each node's first edge and edge count
+__global__ void k_active_compact(const uint32_t* __restrict__ aflags,
+                                 const uint32_t* __restrict__ apos, int64_t U,
+                                 const uint32_t* __restrict__ u_node,
+                                 const uint32_t* __restrict__ u_neb,
+                                 const uint32_t* __restrict__ u_cnt, uint32_t* __restrict__ act,
+                                 uint32_t* __restrict__ a_eb, uint32_t* __restrict__ a_cnt) {
+    int64_t u = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (u < U && aflags[u]) {
+        const uint32_t k = apos[u];
+        act[k] = u_node[u];
+        a_eb[k] = u_neb[u];
+        a_cnt[k] = u_cnt[u];
+    }
+}
+
+// group range and fence size of every active node
+__global__ void k_active_groups(const uint32_t* __restrict__ a_eb,
+                                const uint32_t* __restrict__ a_cnt, int64_t A, int64_t m,
+                                const uint32_t* __restrict__ gidx, const uint32_t* Gn,
+                                uint32_t* __restrict__ a_gb, uint32_t* __restrict__ fsize) {
+    int64_t k = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (k >= A) return;
+    const uint32_t eb = a_eb[k], ee = eb + a_cnt[k];
+    const uint32_t gb = gidx[eb];
+    const uint32_t ge = (int64_t)ee >= m ? *Gn : gidx[ee];
+    uint32_t lv, size;
+    fence_shape(ge - gb, &lv, &size);
+    a_gb[k] = gb;
+    fsize[k] = size;
+}
+
+// Fence entries [j0, j1) (stride) of a node with G groups from gb.
+__device__ __forceinline__ void fence_entries(const int64_t* __restrict__ ng_ts, uint32_t gb,
+                                              uint32_t G, uint32_t levels, uint32_t j0,
+                                              uint32_t j1, uint32_t stride,
+                                              int64_t* __restrict__ out) {
+    // level k (stored from K down to 1) holds ng_ts[gb + i * FAN^k], i < n_k,
+    // padded with INT64_MAX to a multiple of FENCE_FAN
+    uint64_t nk[9];
+    uint64_t n = G;
+    for (uint32_t k = 1; k <= levels; ++k) {
+        n = (n + FENCE_FAN - 1) / FENCE_FAN;
+        nk[k] = n;
+    }
+    for (uint32_t j = j0; j < j1; j += stride) {
+        uint64_t off = 0;
+        int k = (int)levels;
+        for (; k >= 1; --k) {
+            const uint64_t len = (nk[k] + FENCE_FAN - 1) / FENCE_FAN * FENCE_FAN;
+            if (j < off + len) break;
+            off += len;
+        }
+        const uint64_t i = j - off;
+        out[j] = i < nk[k] ? ng_ts[gb + (i << (FENCE_LOG * k))] : INT64_MAX;
+    }
+}
+
+__global__ void k_active_records(const uint32_t* __restrict__ act,
+                                 const uint32_t* __restrict__ a_eb,
+                                 const uint32_t* __restrict__ a_cnt,
+                                 const uint32_t* __restrict__ a_gb,
+                                 const uint32_t* __restrict__ foff, int64_t A, int64_t m,
+                                 const uint32_t* __restrict__ gidx, const uint32_t* Gn,
+                                 const int64_t* __restrict__ ng_ts, NodeRec* __restrict__ rec) {
+    int64_t k = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (k >= A) return;
+    NodeRec r;
+    r.eb = a_eb[k];
+    r.ee = r.eb + a_cnt[k];
+    r.gb = a_gb[k];
+    r.ge = (int64_t)r.ee >= m ? *Gn : gidx[r.ee];
+    uint32_t size;
+    fence_shape(r.ge - r.gb, &r.levels, &size);
+    r.fence_off = foff[k];
+    r.t_last = ng_ts[r.ge - 1];
+    (void)size;
+    rec[act[k]] = r;
+}
+
+// Fence entry j of the concatenated fences of the active nodes: its node is
+// the last active node whose fence starts at or before j.
+__global__ void k_fence_fill(const uint32_t* __restrict__ foff, int64_t A, int64_t total,
+                             const uint32_t* __restrict__ act, const NodeRec* __restrict__ rec,
+                             const int64_t* __restrict__ ng_ts, int64_t* __restrict__ fence) {
+    int64_t j = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (j >= total) return;
+    int64_t lo = 0, hi = A;  // first node whose fence starts after j
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)foff[mid] <= j) lo = mid + 1; else hi = mid;
+    }
+    const uint32_t k = (uint32_t)(lo - 1);
+    const NodeRec r = rec[act[k]];
+    const uint32_t rel = (uint32_t)(j - foff[k]);
+    fence_entries(ng_ts, r.gb, r.ge - r.gb, r.levels, rel, rel + 1, 1, fence + foff[k]);
+}
+
+// CSR-style export of the node table: an empty node starts where the next
+// active node starts (or at the end)
+__global__ void k_export_nodes(const NodeRec* __restrict__ rec, const uint32_t* __restrict__ act,
+                               int64_t A, int32_t V, int64_t m, int64_t Gn,
                                int64_t* __restrict__ ebeg, int64_t* __restrict__ gbeg) {
     int64_t v = (int64_t)blockIdx.x * T + threadIdx.x;
     if (v > V) return;
-    if (ebeg) ebeg[v] = v < V ? (int64_t)rec[v].eb : m;
-    if (gbeg) gbeg[v] = v < V ? (int64_t)rec[v].gb : Gn;
+    int64_t e = m, gg = Gn;
+    if (v < V && rec[v].ee > rec[v].eb) {
+        e = rec[v].eb;
+        gg = rec[v].gb;
+    } else if (v < V) {
+        int64_t lo = 0, hi = A;  // first active node > v
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)act[mid] <= v) lo = mid + 1; else hi = mid;
+        }
+        if (lo < A) {
+            e = rec[act[lo]].eb;
+            gg = rec[act[lo]].gb;
+        }
+    }
+    if (ebeg) ebeg[v] = e;
+    if (gbeg) gbeg[v] = gg;
 }
 
 __global__ void k_window_summary(const int64_t* __restrict__ ts, int64_t m, int64_t* out) {
@@ -524,14 +651,17 @@ tw_status build_ts_groups(tw_graph* g, Error& err) {
 }
 
 // Merge the node view with `kept` batch records (timestamp order) after
-// removing every node's edges older than `cut` (when evicting): the batch is
-// sorted by source (stable), each node's surviving run and batch run are
-// merged by timestamp (old first on ties) into the alternate arrays.
+// removing every node's edges older than `cut` (when evicting). The batch is
+// sorted by source (stable); the union of the active nodes and the batch's
+// sources gets per-node plans and offsets (a scan over the union only); each
+// node's surviving run and batch run are merged by timestamp, older first on
+// ties, into the alternate arrays. Leaves the new active list in act0 with
+// each node's first edge and edge count.
 tw_status merge_node_view(tw_graph* g, const int32_t* q_src, const int32_t* q_dst,
                           const int64_t* q_ts, int64_t kept, int64_t m_old, int64_t m_new,
                           bool evicting, int64_t cut, Error& err) {
     hipStream_t s = g->stream;
-    const int64_t V = g->V;
+    const int64_t V = g->V, A_old = g->A;
     TW_HIP(ensure(g->bs_src, sizeof(uint32_t) * (kept + 1)));
     TW_HIP(ensure(g->bs_dst, sizeof(int32_t) * (kept + 1)));
     TW_HIP(ensure(g->bs_ts, sizeof(int64_t) * (kept + 1)));
@@ -539,7 +669,9 @@ tw_status merge_node_view(tw_graph* g, const int32_t* q_src, const int32_t* q_ds
     TW_HIP(ensure(g->an_dst, sizeof(int32_t) * (m_new + 1)));
     TW_HIP(ensure(g->an_ts, sizeof(int64_t) * (m_new + 1)));
     TW_HIP(ensure(g->plan, sizeof(uint4) * (V + 1)));
-    TW_HIP(ensure(g->node_tmp, sizeof(uint32_t) * 3 * (V + 1)));
+    TW_HIP(ensure(g->neb_v, sizeof(uint32_t) * (V + 1)));
+    TW_HIP(ensure(g->flags, sizeof(uint32_t) * (kept + 1)));
+    TW_HIP(ensure(g->idx, sizeof(uint32_t) * (kept + 1)));
     uint32_t* bsrc = g->bs_src.as<uint32_t>();
     int32_t* bdst = g->bs_dst.as<int32_t>();
     int64_t* bts = g->bs_ts.as<int64_t>();
@@ -548,73 +680,121 @@ tw_status merge_node_view(tw_graph* g, const int32_t* q_src, const int32_t* q_ds
                              reinterpret_cast<const uint64_t*>(q_ts), bsrc,
                              reinterpret_cast<uint32_t*>(bdst), reinterpret_cast<uint64_t*>(bts),
                              kept, 0, bits_for((uint64_t)(V - 1)), g->ws, s));
-    uint32_t* b_first = g->node_tmp.as<uint32_t>();
-    uint32_t* b_end = b_first + (V + 1);
-    uint32_t* neb = b_end + (V + 1);
-    hipLaunchKernelGGL(k_fill_u32, grid_for(2 * (V + 1)), dim3(T), 0, s, b_first, 2 * (V + 1), 0u);
-    hipLaunchKernelGGL(k_run_bounds, grid_for(kept), dim3(T), 0, s, bsrc, kept, b_first, b_end);
-    hipLaunchKernelGGL(k_merge_plan, grid_for(V + 1), dim3(T), 0, s, g->rec.as<NodeRec>(),
-                       g->n_ts.as<int64_t>(), (int32_t)V, cut, evicting ? 1 : 0, b_first, b_end,
-                       g->plan.as<uint4>(), neb);
-    TW_HIP(scan_exclusive_u32(neb, neb, V + 1, nullptr, g->ws, s));
+
+    // the batch's source runs
+    uint32_t* rflags = g->flags.as<uint32_t>();
+    uint32_t* rpos = g->idx.as<uint32_t>();
+    uint32_t* sc_runs = u32_slot(g, SLOT_U32_RUNS);
+    hipLaunchKernelGGL(k_run_start_flags, grid_for(kept), dim3(T), 0, s, bsrc, kept, rflags);
+    TW_HIP(scan_exclusive_u32(rflags, rpos, kept, sc_runs, g->ws, s));
+    uint32_t R = 0;
+    TW_HIP(hipMemcpyAsync(&R, sc_runs, sizeof(R), hipMemcpyDeviceToHost, s));
+    TW_HIP(hipStreamSynchronize(s));
+
+    // union items: batch runs, then the old active nodes; sort by node (stable)
+    const int64_t n_items = (int64_t)R + A_old;
+    TW_HIP(ensure(g->it_keys, sizeof(uint32_t) * (n_items + 1)));
+    TW_HIP(ensure(g->it_pay, sizeof(uint64_t) * (n_items + 1)));
+    TW_HIP(ensure(g->it_skeys, sizeof(uint32_t) * (n_items + 1)));
+    TW_HIP(ensure(g->it_spay, sizeof(uint64_t) * (n_items + 1)));
+    hipLaunchKernelGGL(k_items_batch, grid_for(kept), dim3(T), 0, s, bsrc, kept, rflags, rpos,
+                       g->it_keys.as<uint32_t>(), g->it_pay.as<uint64_t>());
+    hipLaunchKernelGGL(k_items_old, grid_for(A_old), dim3(T), 0, s, g->act0.as<uint32_t>(), A_old,
+                       (int64_t)R, g->it_keys.as<uint32_t>(), g->it_pay.as<uint64_t>());
+    TW_HIP(radix_sort_u32_kv(g->it_keys.as<uint32_t>(), nullptr, g->it_pay.as<uint64_t>(),
+                             g->it_skeys.as<uint32_t>(), nullptr, g->it_spay.as<uint64_t>(),
+                             n_items, 0, bits_for((uint64_t)(V - 1)), g->ws, s));
+
+    // union nodes: plans, merged sizes, offsets
+    TW_HIP(ensure(g->u_flags, sizeof(uint32_t) * (n_items + 1)));
+    TW_HIP(ensure(g->u_pos, sizeof(uint32_t) * (n_items + 1)));
+    TW_HIP(ensure(g->u_node, sizeof(uint32_t) * (n_items + 1)));
+    TW_HIP(ensure(g->u_cnt, sizeof(uint32_t) * (n_items + 1)));
+    TW_HIP(ensure(g->u_neb, sizeof(uint32_t) * (n_items + 1)));
+    uint32_t* uflags = g->u_flags.as<uint32_t>();
+    uint32_t* upos = g->u_pos.as<uint32_t>();
+    uint32_t* sc_u = u32_slot(g, SLOT_U32_UNION);
+    hipLaunchKernelGGL(k_run_start_flags, grid_for(n_items), dim3(T), 0, s,
+                       g->it_skeys.as<uint32_t>(), n_items, uflags);
+    TW_HIP(scan_exclusive_u32(uflags, upos, n_items, sc_u, g->ws, s));
+    hipLaunchKernelGGL(k_union_plan, grid_for(n_items), dim3(T), 0, s, g->it_skeys.as<uint32_t>(),
+                       g->it_spay.as<uint64_t>(), n_items, uflags, upos, g->rec.as<NodeRec>(),
+                       g->n_ts.as<int64_t>(), evicting ? 1 : 0, cut, g->plan.as<uint4>(),
+                       g->u_node.as<uint32_t>(), g->u_cnt.as<uint32_t>());
+    uint32_t U = 0;
+    TW_HIP(hipMemcpyAsync(&U, sc_u, sizeof(U), hipMemcpyDeviceToHost, s));
+    TW_HIP(hipStreamSynchronize(s));
+    TW_HIP(scan_exclusive_u32(g->u_cnt.as<uint32_t>(), g->u_neb.as<uint32_t>(), U, nullptr, g->ws,
+                              s));
+    hipLaunchKernelGGL(k_union_offsets, grid_for(U), dim3(T), 0, s, g->u_node.as<uint32_t>(),
+                       g->u_neb.as<uint32_t>(), (int64_t)U, g->neb_v.as<uint32_t>());
+
+    // merge
+    TW_HIP(ensure(g->gflags, sizeof(uint32_t) * (m_new + 1)));
     hipLaunchKernelGGL(k_merge_old, grid_for(m_old), dim3(T), 0, s, g->n_src.as<uint32_t>(),
                        g->n_dst.as<int32_t>(), g->n_ts.as<int64_t>(), m_old, g->plan.as<uint4>(),
-                       neb, bts, g->an_src.as<uint32_t>(), g->an_dst.as<int32_t>(),
-                       g->an_ts.as<int64_t>());
+                       g->neb_v.as<uint32_t>(), bts, g->an_src.as<uint32_t>(),
+                       g->an_dst.as<int32_t>(), g->an_ts.as<int64_t>(), g->gflags.as<uint32_t>());
     hipLaunchKernelGGL(k_merge_new, grid_for(kept), dim3(T), 0, s, bsrc, bdst, bts, kept,
-                       g->plan.as<uint4>(), neb, g->n_ts.as<int64_t>(), g->an_src.as<uint32_t>(),
-                       g->an_dst.as<int32_t>(), g->an_ts.as<int64_t>());
+                       g->plan.as<uint4>(), g->neb_v.as<uint32_t>(), g->n_ts.as<int64_t>(),
+                       g->an_src.as<uint32_t>(), g->an_dst.as<int32_t>(), g->an_ts.as<int64_t>(),
+                       g->gflags.as<uint32_t>());
     TW_HIP(hipGetLastError());
     std::swap(g->n_src, g->an_src);
     std::swap(g->n_dst, g->an_dst);
     std::swap(g->n_ts, g->an_ts);
+
+    // the new active list; nodes left without edges get the empty record
+    TW_HIP(ensure(g->act1, sizeof(uint32_t) * (U + 1)));
+    TW_HIP(ensure(g->a_eb, sizeof(uint32_t) * (U + 1)));
+    TW_HIP(ensure(g->a_cnt, sizeof(uint32_t) * (U + 1)));
+    uint32_t* sc_a = u32_slot(g, SLOT_U32_ACTIVE);
+    hipLaunchKernelGGL(k_union_active, grid_for(U), dim3(T), 0, s, g->u_node.as<uint32_t>(),
+                       g->u_cnt.as<uint32_t>(), (int64_t)U, g->rec.as<NodeRec>(), uflags);
+    TW_HIP(scan_exclusive_u32(uflags, upos, U, sc_a, g->ws, s));
+    hipLaunchKernelGGL(k_active_compact, grid_for(U), dim3(T), 0, s, uflags, upos, (int64_t)U,
+                       g->u_node.as<uint32_t>(), g->u_neb.as<uint32_t>(), g->u_cnt.as<uint32_t>(),
+                       g->act1.as<uint32_t>(), g->a_eb.as<uint32_t>(), g->a_cnt.as<uint32_t>());
+    TW_HIP(hipGetLastError());
+    std::swap(g->act0, g->act1);
+    uint32_t A = 0;
+    TW_HIP(hipMemcpyAsync(&A, sc_a, sizeof(A), hipMemcpyDeviceToHost, s));
+    TW_HIP(hipStreamSynchronize(s));
+    g->A = A;
     (void)m_new;
     return TW_OK;
 }
 
-// Groups, node table and fence from the node view; then one synchronisation
-// reads the counts. Gg is taken from the GROUPS slot when gg_full, else it
-// is gg_old - gg_evicted + GROUPS (appended groups).
+// Groups, node records and fences of the active nodes; then one
+// synchronisation reads the counts. Gg is taken from the GROUPS slot when
+// gg_full, else it is gg_old - gg_evicted + GROUPS (appended groups).
 tw_status finish_index(tw_graph* g, bool gg_full, int64_t gg_old, int64_t gg_evicted,
                        Error& err) {
     hipStream_t s = g->stream;
-    const int64_t m = g->m, V = g->V;
+    const int64_t m = g->m, A = g->A;
     TW_HIP(ensure(g->flags, sizeof(uint32_t) * (m + 1)));
     TW_HIP(ensure(g->idx, sizeof(uint32_t) * (m + 1)));
     TW_HIP(ensure(g->ng_ts, sizeof(int64_t) * (m + 1)));
     TW_HIP(ensure(g->ng_off, sizeof(uint32_t) * (m + 2)));
-    TW_HIP(ensure(g->ng_node, sizeof(uint32_t) * (m + 1)));
-    TW_HIP(ensure(g->rec, sizeof(NodeRec) * V));
-    TW_HIP(ensure(g->b_vals, sizeof(uint32_t) * (3 * (V + 1) + 1)));
-    uint32_t* flags = g->flags.as<uint32_t>();
+    TW_HIP(ensure(g->a_gb, sizeof(uint32_t) * (A + 1)));
+    TW_HIP(ensure(g->a_foff, sizeof(uint32_t) * (A + 1)));
+    TW_HIP(ensure(g->gflags, sizeof(uint32_t) * (m + 1)));
+    uint32_t* flags = g->gflags.as<uint32_t>();  // group starts, written by the merge
     uint32_t* gidx = g->idx.as<uint32_t>();
     uint32_t* Gn = u32_slot(g, SLOT_U32_GN);
     uint32_t* fence_total = u32_slot(g, SLOT_U32_FENCE);
-    const uint32_t* keys = g->n_src.as<uint32_t>();
 
     // (node, timestamp) groups
-    hipLaunchKernelGGL(k_node_group_flags, grid_for(m), dim3(T), 0, s, keys, g->n_ts.as<int64_t>(),
-                       m, flags);
     TW_HIP(scan_exclusive_u32(flags, gidx, m, Gn, g->ws, s));
-    hipLaunchKernelGGL(k_node_group_scatter, grid_for(m), dim3(T), 0, s, g->n_ts.as<int64_t>(),
-                       keys, m, flags, gidx, g->ng_ts.as<int64_t>(), g->ng_off.as<uint32_t>(),
-                       g->ng_node.as<uint32_t>(), Gn);
+    hipLaunchKernelGGL(k_ts_group_scatter, grid_for(m), dim3(T), 0, s, g->n_ts.as<int64_t>(), m,
+                       flags, gidx, g->ng_ts.as<int64_t>(), g->ng_off.as<uint32_t>(), Gn, 0u);
 
-    // node table: per-node edge / group counts, then their exclusive scans
-    uint32_t* node_e = g->b_vals.as<uint32_t>();  // V+1 entries each
-    uint32_t* node_g = node_e + (V + 1);
-    uint32_t* fsize = node_g + (V + 1);
-    hipLaunchKernelGGL(k_fill_u32, grid_for(2 * (V + 1)), dim3(T), 0, s, node_e, 2 * (V + 1), 0u);
-    hipLaunchKernelGGL(k_run_bounds, grid_for(m), dim3(T), 0, s, keys, m, node_e, node_g);
-    hipLaunchKernelGGL(k_node_counts, grid_for(V + 1), dim3(T), 0, s, node_e, node_g,
-                       (int32_t)V, m, gidx, Gn);
-    TW_HIP(scan_exclusive_u32(node_e, node_e, V + 1, nullptr, g->ws, s));
-    TW_HIP(scan_exclusive_u32(node_g, node_g, V + 1, nullptr, g->ws, s));
-    hipLaunchKernelGGL(k_node_records, grid_for(V + 1), dim3(T), 0, s, node_e, node_g, (int32_t)V,
-                       g->ng_ts.as<int64_t>(), g->rec.as<NodeRec>(), fsize);
-    TW_HIP(scan_exclusive_u32(fsize, fsize, V + 1, fence_total, g->ws, s));
-    hipLaunchKernelGGL(k_fence_offsets, grid_for(V), dim3(T), 0, s, fsize, (int32_t)V,
-                       g->rec.as<NodeRec>());
+    // fence sizes and offsets of the active nodes
+    hipLaunchKernelGGL(k_active_groups, grid_for(A), dim3(T), 0, s, g->a_eb.as<uint32_t>(),
+                       g->a_cnt.as<uint32_t>(), A, m, gidx, Gn, g->a_gb.as<uint32_t>(),
+                       g->a_foff.as<uint32_t>());
+    TW_HIP(scan_exclusive_u32(g->a_foff.as<uint32_t>(), g->a_foff.as<uint32_t>(), A, fence_total,
+                              g->ws, s));
     int64_t* summary = i64_slot(g, SLOT_I64_SUMMARY);
     hipLaunchKernelGGL(k_window_summary, dim3(1), dim3(1), 0, s, g->e_ts.as<int64_t>() + g->e_base,
                        m, summary);
@@ -630,19 +810,19 @@ tw_status finish_index(tw_graph* g, bool gg_full, int64_t gg_old, int64_t gg_evi
     g->Gn = host_u32[1];
     g->t_min = host_sum[0];
     g->t_max = host_sum[1];
-    const uint32_t host_fence = host_u32[3];
+    g->fence_len = host_u32[3];
+    TW_HIP(ensure(g->fence, sizeof(int64_t) * (g->fence_len + FENCE_FAN)));
 
-    // fence levels of nodes with many groups
-    g->fence_len = host_fence;
-    TW_HIP(ensure(g->fence, sizeof(int64_t) * (host_fence + FENCE_FAN)));
-    if (host_fence > 0) {
-        hipLaunchKernelGGL(k_fill_i64, grid_for(host_fence), dim3(T), 0, s, g->fence.as<int64_t>(),
-                           (int64_t)host_fence, INT64_MAX);
-        hipLaunchKernelGGL(k_fence_fill, grid_for(g->Gn), dim3(T), 0, s, g->ng_ts.as<int64_t>(),
-                           g->ng_node.as<uint32_t>(), g->Gn, g->rec.as<NodeRec>(),
-                           g->fence.as<int64_t>());
-        TW_HIP(hipGetLastError());
-    }
+    // records, then the fences
+    hipLaunchKernelGGL(k_active_records, grid_for(A), dim3(T), 0, s, g->act0.as<uint32_t>(),
+                       g->a_eb.as<uint32_t>(), g->a_cnt.as<uint32_t>(), g->a_gb.as<uint32_t>(),
+                       g->a_foff.as<uint32_t>(), A, m, gidx, Gn, g->ng_ts.as<int64_t>(),
+                       g->rec.as<NodeRec>());
+    if (g->fence_len > 0)
+        hipLaunchKernelGGL(k_fence_fill, grid_for(g->fence_len), dim3(T), 0, s,
+                           g->a_foff.as<uint32_t>(), A, g->fence_len, g->act0.as<uint32_t>(),
+                           g->rec.as<NodeRec>(), g->ng_ts.as<int64_t>(), g->fence.as<int64_t>());
+    TW_HIP(hipGetLastError());
     g->adj_ready = false;
     return TW_OK;
 }
@@ -931,6 +1111,11 @@ tw_status init_empty(tw_graph* g, Error& err) {
     TW_HIP(ensure(g->n_dst, sizeof(int32_t) * 2));
     TW_HIP(ensure(g->n_ts, sizeof(int64_t) * 2));
     g->m = 0;
+    g->A = 0;
+    TW_HIP(ensure(g->rec, sizeof(NodeRec) * g->V));
+    TW_HIP(ensure(g->act0, sizeof(uint32_t) * 2));
+    hipLaunchKernelGGL(k_fill_empty_rec, grid_for(g->V), dim3(T), 0, g->stream,
+                       g->rec.as<NodeRec>(), (int64_t)g->V);
     if (build_ts_groups(g, err) != TW_OK) return err.code;
     return finish_index(g, true, 0, 0, err);
 }
@@ -977,7 +1162,8 @@ tw_status export_views(tw_graph* g, int32_t* src, int32_t* dst, int64_t* ts, int
                            g->Gn + 1, n_goff, (int64_t)0);
     if (n_ebeg || n_gbeg)
         hipLaunchKernelGGL(k_export_nodes, grid_for(g->V + 1), dim3(T), 0, s,
-                           g->rec.as<NodeRec>(), g->V, m, g->Gn, n_ebeg, n_gbeg);
+                           g->rec.as<NodeRec>(), g->act0.as<uint32_t>(), g->A, g->V, m, g->Gn,
+                           n_ebeg, n_gbeg);
     TW_HIP(hipGetLastError());
     TW_HIP(hipStreamSynchronize(s));
     return TW_OK;

@@ -46,6 +46,10 @@ constexpr int SLOT_U32_EVICTED = 25;   // evicted window records
 constexpr int SLOT_I64_FIRST_KEPT = 13;
 constexpr int SLOT_U32_N_LIVE = 28;    // live walks (cooperative dispatch)
 constexpr int SLOT_U32_GG_EVICTED = 29;
+constexpr int SLOT_U32_RUNS = 30;      // source runs of the batch
+constexpr int SLOT_U32_UNION = 31;     // union of active nodes and batch sources
+constexpr int SLOT_U32_ACTIVE = 32;    // active nodes
+constexpr int SLOT_U32_BIG = 33;       // queued large fences
 constexpr int SCALAR_BYTES = 256;
 
 // A grow-only device allocation.
@@ -134,10 +138,15 @@ struct tw_graph {
     tw::DevBuf an_src, an_dst, an_ts;  // its alternate for the merge
     tw::DevBuf bs_src, bs_dst, bs_ts;  // batch sorted by source
     tw::DevBuf q_src, q_dst, q_ts;     // batch sorted by timestamp (unsorted input)
-    tw::DevBuf plan, node_tmp;         // per-node merge plan, per-node counts
+    tw::DevBuf plan, neb_v;            // per-node merge plan / merged offset (union nodes)
+    tw::DevBuf act0, act1;             // sorted active nodes (current, scratch)
+    int64_t A = 0;                     // active nodes
+    tw::DevBuf a_eb, a_cnt, a_gb, a_foff;   // per active node
+    tw::DevBuf gflags;                 // (node, timestamp) group starts of the node view
+    tw::DevBuf it_keys, it_pay, it_skeys, it_spay;  // union items
+    tw::DevBuf u_flags, u_pos, u_node, u_cnt, u_neb;  // union nodes
     tw::DevBuf ng_ts, ng_off;          // its (node, timestamp) groups
     tw::DevBuf n_src;                  // source of each node-view edge (build temp)
-    tw::DevBuf ng_node;                // node of each (node, timestamp) group
     tw::DevBuf fence;                  // fence levels of nodes with many groups
     int64_t fence_len = 0;
     tw::DevBuf rec;                    // NodeRec[V]
