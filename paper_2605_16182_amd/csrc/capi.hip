@@ -76,7 +76,7 @@ tw_status tw_destroy(tw_graph* g) {
                               &g->n_src, &g->fence, &g->rec, &g->adj, &g->b_src, &g->b_dst, &g->b_ts,
                               &g->b_keys, &g->b_vals, &g->b_flags, &g->flags, &g->idx, &g->err,
                               &g->scal, &g->ws.scan_part, &g->ws.hist, &g->ws.keys_alt,
-                              &g->ws.vals_alt, &g->ws.v64_alt, &g->ws.misc, &g->c_node0, &g->c_walk0, &g->c_t0, &g->c_node1, &g->c_walk1, &g->c_t1, &g->c_node2, &g->c_walk2, &g->c_t2, &g->c_prev, &g->c_flags, &g->c_pos, &g->an_src, &g->an_dst, &g->an_ts, &g->bs_src, &g->bs_dst, &g->bs_ts, &g->q_src, &g->q_dst, &g->q_ts, &g->plan, &g->neb_v, &g->act0, &g->act1, &g->a_eb, &g->a_cnt, &g->a_gb, &g->a_foff, &g->gflags, &g->it_keys, &g->it_pay, &g->it_skeys, &g->it_spay, &g->u_flags, &g->u_pos, &g->u_node, &g->u_cnt, &g->u_neb};
+                              &g->ws.vals_alt, &g->ws.v64_alt, &g->ws.misc, &g->c_node0, &g->c_walk0, &g->c_t0, &g->c_node1, &g->c_walk1, &g->c_t1, &g->c_node2, &g->c_walk2, &g->c_t2, &g->c_prev, &g->c_flags, &g->c_pos, &g->an_src, &g->an_dst, &g->an_ts, &g->bs_src, &g->bs_dst, &g->bs_ts, &g->q_src, &g->q_dst, &g->q_ts, &g->plan, &g->neb_v, &g->act0, &g->act1, &g->a_eb, &g->a_cnt, &g->a_gb, &g->a_ge, &g->a_foff, &g->gflags, &g->it_keys, &g->it_pay, &g->it_skeys, &g->it_spay, &g->u_flags, &g->u_pos, &g->u_node, &g->u_cnt, &g->u_neb};
         for (tw::DevBuf* b : bufs) tw::release(*b);
         delete g;
         return TW_OK;
@@ -171,7 +171,7 @@ int64_t tw_device_bytes(const tw_graph* g) {
                                 &g->n_src, &g->fence, &g->rec, &g->adj, &g->b_src, &g->b_dst, &g->b_ts,
                                 &g->b_keys, &g->b_vals, &g->b_flags, &g->flags, &g->idx, &g->err,
                                 &g->scal, &g->ws.scan_part, &g->ws.hist, &g->ws.keys_alt,
-                                &g->ws.vals_alt, &g->ws.v64_alt, &g->ws.misc, &g->c_node0, &g->c_walk0, &g->c_t0, &g->c_node1, &g->c_walk1, &g->c_t1, &g->c_node2, &g->c_walk2, &g->c_t2, &g->c_prev, &g->c_flags, &g->c_pos, &g->an_src, &g->an_dst, &g->an_ts, &g->bs_src, &g->bs_dst, &g->bs_ts, &g->q_src, &g->q_dst, &g->q_ts, &g->plan, &g->neb_v, &g->act0, &g->act1, &g->a_eb, &g->a_cnt, &g->a_gb, &g->a_foff, &g->gflags, &g->it_keys, &g->it_pay, &g->it_skeys, &g->it_spay, &g->u_flags, &g->u_pos, &g->u_node, &g->u_cnt, &g->u_neb};
+                                &g->ws.vals_alt, &g->ws.v64_alt, &g->ws.misc, &g->c_node0, &g->c_walk0, &g->c_t0, &g->c_node1, &g->c_walk1, &g->c_t1, &g->c_node2, &g->c_walk2, &g->c_t2, &g->c_prev, &g->c_flags, &g->c_pos, &g->an_src, &g->an_dst, &g->an_ts, &g->bs_src, &g->bs_dst, &g->bs_ts, &g->q_src, &g->q_dst, &g->q_ts, &g->plan, &g->neb_v, &g->act0, &g->act1, &g->a_eb, &g->a_cnt, &g->a_gb, &g->a_ge, &g->a_foff, &g->gflags, &g->it_keys, &g->it_pay, &g->it_skeys, &g->it_spay, &g->u_flags, &g->u_pos, &g->u_node, &g->u_cnt, &g->u_neb};
     int64_t total = 0;
     for (const tw::DevBuf* b : bufs) total += (int64_t)b->bytes;
     return total;

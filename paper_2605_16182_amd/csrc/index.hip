@@ -477,19 +477,33 @@ __global__ void k_active_compact(const uint32_t* __restrict__ aflags,
     }
 }
 
-// group range and fence size of every active node
+// group range and fence size of every active node: its first edge and its
+// end are group starts, found by binary search in the group offsets
+__device__ __forceinline__ uint32_t find_group(const uint32_t* __restrict__ g_off, uint32_t n,
+                                               uint32_t e) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint32_t mid = lo + ((hi - lo) >> 1);
+        if (g_off[mid] < e) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
 __global__ void k_active_groups(const uint32_t* __restrict__ a_eb,
                                 const uint32_t* __restrict__ a_cnt, int64_t A, int64_t m,
-                                const uint32_t* __restrict__ gidx, const uint32_t* Gn,
-                                uint32_t* __restrict__ a_gb, uint32_t* __restrict__ fsize) {
+                                const uint32_t* __restrict__ g_off, const uint32_t* Gn,
+                                uint32_t* __restrict__ a_gb, uint32_t* __restrict__ a_ge,
+                                uint32_t* __restrict__ fsize) {
     int64_t k = (int64_t)blockIdx.x * T + threadIdx.x;
     if (k >= A) return;
+    const uint32_t G = *Gn;
     const uint32_t eb = a_eb[k], ee = eb + a_cnt[k];
-    const uint32_t gb = gidx[eb];
-    const uint32_t ge = (int64_t)ee >= m ? *Gn : gidx[ee];
+    const uint32_t gb = find_group(g_off, G, eb);
+    const uint32_t ge = (int64_t)ee >= m ? G : find_group(g_off, G, ee);
     uint32_t lv, size;
     fence_shape(ge - gb, &lv, &size);
     a_gb[k] = gb;
+    a_ge[k] = ge;
     fsize[k] = size;
 }
 
@@ -523,8 +537,8 @@ __global__ void k_active_records(const uint32_t* __restrict__ act,
                                  const uint32_t* __restrict__ a_eb,
                                  const uint32_t* __restrict__ a_cnt,
                                  const uint32_t* __restrict__ a_gb,
-                                 const uint32_t* __restrict__ foff, int64_t A, int64_t m,
-                                 const uint32_t* __restrict__ gidx, const uint32_t* Gn,
+                                 const uint32_t* __restrict__ a_ge,
+                                 const uint32_t* __restrict__ foff, int64_t A,
                                  const int64_t* __restrict__ ng_ts, NodeRec* __restrict__ rec) {
     int64_t k = (int64_t)blockIdx.x * T + threadIdx.x;
     if (k >= A) return;
@@ -532,7 +546,7 @@ __global__ void k_active_records(const uint32_t* __restrict__ act,
     r.eb = a_eb[k];
     r.ee = r.eb + a_cnt[k];
     r.gb = a_gb[k];
-    r.ge = (int64_t)r.ee >= m ? *Gn : gidx[r.ee];
+    r.ge = a_ge[k];
     uint32_t size;
     fence_shape(r.ge - r.gb, &r.levels, &size);
     r.fence_off = foff[k];
@@ -636,16 +650,10 @@ tw_status reserve_window(tw_graph* g, int64_t need, Error& err) {
 tw_status build_ts_groups(tw_graph* g, Error& err) {
     hipStream_t s = g->stream;
     const int64_t m = g->m;
-    TW_HIP(ensure(g->flags, sizeof(uint32_t) * (m + 1)));
-    TW_HIP(ensure(g->idx, sizeof(uint32_t) * (m + 1)));
-    uint32_t* flags = g->flags.as<uint32_t>();
-    uint32_t* gidx = g->idx.as<uint32_t>();
     const int64_t* ts = g->e_ts.as<int64_t>() + g->e_base;
     uint32_t* G = u32_slot(g, SLOT_U32_GROUPS);
-    hipLaunchKernelGGL(k_ts_group_flags, grid_for(m), dim3(T), 0, s, ts, m, flags);
-    TW_HIP(scan_exclusive_u32(flags, gidx, m, G, g->ws, s));
-    hipLaunchKernelGGL(k_ts_group_scatter, grid_for(m), dim3(T), 0, s, ts, m, flags, gidx,
-                       g->gg_ts.as<int64_t>(), g->gg_off.as<uint32_t>(), G, (uint32_t)g->e_base);
+    TW_HIP(group_starts(nullptr, ts, m, (uint32_t)g->e_base, g->gg_ts.as<int64_t>(),
+                        g->gg_off.as<uint32_t>(), G, g->ws, s));
     g->gg_base = 0;
     return TW_OK;
 }
@@ -780,19 +788,18 @@ tw_status finish_index(tw_graph* g, bool gg_full, int64_t gg_old, int64_t gg_evi
     TW_HIP(ensure(g->a_foff, sizeof(uint32_t) * (A + 1)));
     TW_HIP(ensure(g->gflags, sizeof(uint32_t) * (m + 1)));
     uint32_t* flags = g->gflags.as<uint32_t>();  // group starts, written by the merge
-    uint32_t* gidx = g->idx.as<uint32_t>();
     uint32_t* Gn = u32_slot(g, SLOT_U32_GN);
     uint32_t* fence_total = u32_slot(g, SLOT_U32_FENCE);
+    TW_HIP(ensure(g->a_ge, sizeof(uint32_t) * (A + 1)));
 
     // (node, timestamp) groups
-    TW_HIP(scan_exclusive_u32(flags, gidx, m, Gn, g->ws, s));
-    hipLaunchKernelGGL(k_ts_group_scatter, grid_for(m), dim3(T), 0, s, g->n_ts.as<int64_t>(), m,
-                       flags, gidx, g->ng_ts.as<int64_t>(), g->ng_off.as<uint32_t>(), Gn, 0u);
+    TW_HIP(group_starts(flags, g->n_ts.as<int64_t>(), m, 0u, g->ng_ts.as<int64_t>(),
+                        g->ng_off.as<uint32_t>(), Gn, g->ws, s));
 
-    // fence sizes and offsets of the active nodes
+    // group ranges, fence sizes and offsets of the active nodes
     hipLaunchKernelGGL(k_active_groups, grid_for(A), dim3(T), 0, s, g->a_eb.as<uint32_t>(),
-                       g->a_cnt.as<uint32_t>(), A, m, gidx, Gn, g->a_gb.as<uint32_t>(),
-                       g->a_foff.as<uint32_t>());
+                       g->a_cnt.as<uint32_t>(), A, m, g->ng_off.as<uint32_t>(), Gn,
+                       g->a_gb.as<uint32_t>(), g->a_ge.as<uint32_t>(), g->a_foff.as<uint32_t>());
     TW_HIP(scan_exclusive_u32(g->a_foff.as<uint32_t>(), g->a_foff.as<uint32_t>(), A, fence_total,
                               g->ws, s));
     int64_t* summary = i64_slot(g, SLOT_I64_SUMMARY);
@@ -816,8 +823,8 @@ tw_status finish_index(tw_graph* g, bool gg_full, int64_t gg_old, int64_t gg_evi
     // records, then the fences
     hipLaunchKernelGGL(k_active_records, grid_for(A), dim3(T), 0, s, g->act0.as<uint32_t>(),
                        g->a_eb.as<uint32_t>(), g->a_cnt.as<uint32_t>(), g->a_gb.as<uint32_t>(),
-                       g->a_foff.as<uint32_t>(), A, m, gidx, Gn, g->ng_ts.as<int64_t>(),
-                       g->rec.as<NodeRec>());
+                       g->a_ge.as<uint32_t>(), g->a_foff.as<uint32_t>(), A,
+                       g->ng_ts.as<int64_t>(), g->rec.as<NodeRec>());
     if (g->fence_len > 0)
         hipLaunchKernelGGL(k_fence_fill, grid_for(g->fence_len), dim3(T), 0, s,
                            g->a_foff.as<uint32_t>(), A, g->fence_len, g->act0.as<uint32_t>(),
@@ -1008,17 +1015,14 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
             if (build_ts_groups(g, err) != TW_OK) return err.code;
         } else if (kept > 0) {
             TW_HIP(ensure(g->flags, sizeof(uint32_t) * (kept + 1)));
-            TW_HIP(ensure(g->idx, sizeof(uint32_t) * (kept + 1)));
             uint32_t* fl = g->flags.as<uint32_t>();
-            uint32_t* gi = g->idx.as<uint32_t>();
             uint32_t* G = u32_slot(g, SLOT_U32_GROUPS);
             const int64_t gpos = g->gg_base + (gg_old - gg_evicted);
             hipLaunchKernelGGL(k_append_group_flags, grid_for(kept), dim3(T), 0, s, q_ts, kept,
                                last_ts, 1, fl);
-            TW_HIP(scan_exclusive_u32(fl, gi, kept, G, g->ws, s));
-            hipLaunchKernelGGL(k_ts_group_scatter, grid_for(kept), dim3(T), 0, s, q_ts, kept, fl,
-                               gi, g->gg_ts.as<int64_t>() + gpos, g->gg_off.as<uint32_t>() + gpos,
-                               G, (uint32_t)(g->e_base + na));
+            TW_HIP(group_starts(fl, q_ts, kept, (uint32_t)(g->e_base + na),
+                                g->gg_ts.as<int64_t>() + gpos, g->gg_off.as<uint32_t>() + gpos, G,
+                                g->ws, s));
         } else {
             // eviction only: the groups keep their offsets
             hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(T), 0, s, u32_slot(g, SLOT_U32_GROUPS), 1,

@@ -2,6 +2,8 @@
 // an exclusive scan and a stable LSD radix sort whose per-tile ranks come
 // from wave ballots (each lane learns which lanes of its wavefront share its
 // digit from one ballot per digit bit, then counts the lower ones).
+#include <algorithm>
+
 #include "tw_internal.h"
 
 namespace tw {
@@ -107,6 +109,67 @@ __global__ void k_scan_down(const uint32_t* in, uint32_t* out, int64_t n,
 }
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+
+// group-start flag of position i: flags[i], or a timestamp change when flags
+// is null
+__device__ __forceinline__ uint32_t start_flag(const uint32_t* __restrict__ flags,
+                                               const int64_t* __restrict__ ts, int64_t i) {
+    if (flags) return flags[i];
+    return (i == 0 || ts[i] != ts[i - 1]) ? 1u : 0u;
+}
+
+__global__ void k_flag_reduce(const uint32_t* __restrict__ flags, const int64_t* __restrict__ ts,
+                              int64_t n, uint32_t* __restrict__ part) {
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    uint32_t s = 0;
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + (int64_t)j * SCAN_THREADS + threadIdx.x;
+        if (i < n) s += start_flag(flags, ts, i);
+    }
+    uint32_t total;
+    block_excl_scan(s, &total);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+// down-sweep that scatters each group start: g_ts[k] = ts[i],
+// g_off[k] = pos_base + i for the k-th flagged position i; g_off[total] =
+// pos_base + n
+__global__ void k_flag_scatter(const uint32_t* __restrict__ flags, const int64_t* __restrict__ ts,
+                               int64_t n, const uint32_t* __restrict__ part, uint32_t pos_base,
+                               int64_t* __restrict__ g_ts, uint32_t* __restrict__ g_off,
+                               const uint32_t* total) {
+    __shared__ uint32_t tile[SCAN_TILE];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int k = j * SCAN_THREADS + threadIdx.x;
+        int64_t i = base + k;
+        tile[k] = i < n ? start_flag(flags, ts, i) : 0;
+    }
+    __syncthreads();
+    uint32_t loc[SCAN_ITEMS];
+    uint32_t s = 0;
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        loc[j] = s;
+        s += tile[threadIdx.x * SCAN_ITEMS + j];
+    }
+    uint32_t tot;
+    uint32_t pre = block_excl_scan(s, &tot) + part[blockIdx.x];
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const uint32_t f = tile[threadIdx.x * SCAN_ITEMS + j];
+        tile[threadIdx.x * SCAN_ITEMS + j] = f ? pre + loc[j] : UINT32_MAX;
+    }
+    __syncthreads();
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int k = j * SCAN_THREADS + threadIdx.x;
+        int64_t i = base + k;
+        const uint32_t gk = tile[k];
+        if (i < n && gk != UINT32_MAX) {
+            g_ts[gk] = ts[i];
+            g_off[gk] = pos_base + (uint32_t)i;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) g_off[*total] = pos_base + (uint32_t)n;
+}
 
 // ------------------------------------------------------------ radix sort
 
@@ -286,6 +349,20 @@ hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, part);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, part, nb, total);
     hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(SCAN_THREADS), 0, s, in, out, n, part);
+    return hipGetLastError();
+}
+
+hipError_t group_starts(const uint32_t* flags, const int64_t* ts, int64_t n, uint32_t pos_base,
+                        int64_t* g_ts, uint32_t* g_off, uint32_t* total, Workspace& ws,
+                        hipStream_t s) {
+    const int64_t nb = std::max<int64_t>(ceil_div(n, SCAN_TILE), 1);
+    hipError_t e = ensure(ws.scan_part, sizeof(uint32_t) * (nb + 1));
+    if (e != hipSuccess) return e;
+    uint32_t* part = ws.scan_part.as<uint32_t>();
+    hipLaunchKernelGGL(k_flag_reduce, dim3(nb), dim3(SCAN_THREADS), 0, s, flags, ts, n, part);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, part, nb, total);
+    hipLaunchKernelGGL(k_flag_scatter, dim3(nb), dim3(SCAN_THREADS), 0, s, flags, ts, n, part,
+                       pos_base, g_ts, g_off, total);
     return hipGetLastError();
 }
 

@@ -84,6 +84,14 @@ struct Workspace {
 hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
                               Workspace& ws, hipStream_t s);
 
+// Groups of a sequence: the k-th position i that starts a group (flags[i]
+// != 0, or with flags null, ts[i] != ts[i-1]) gives g_ts[k] = ts[i] and
+// g_off[k] = pos_base + i; g_off[total] = pos_base + n; total (device) = the
+// number of groups. n may be 0.
+hipError_t group_starts(const uint32_t* flags, const int64_t* ts, int64_t n, uint32_t pos_base,
+                        int64_t* g_ts, uint32_t* g_off, uint32_t* total, Workspace& ws,
+                        hipStream_t s);
+
 // Stable LSD radix sort of (keys, vals) by bits [bit_lo, bit_hi) of the key.
 // vals may be null. Result ends in keys / vals. The alternate buffers come
 // from the workspace.
@@ -141,7 +149,7 @@ struct tw_graph {
     tw::DevBuf plan, neb_v;            // per-node merge plan / merged offset (union nodes)
     tw::DevBuf act0, act1;             // sorted active nodes (current, scratch)
     int64_t A = 0;                     // active nodes
-    tw::DevBuf a_eb, a_cnt, a_gb, a_foff;   // per active node
+    tw::DevBuf a_eb, a_cnt, a_gb, a_ge, a_foff;   // per active node
     tw::DevBuf gflags;                 // (node, timestamp) group starts of the node view
     tw::DevBuf it_keys, it_pay, it_skeys, it_spay;  // union items
     tw::DevBuf u_flags, u_pos, u_node, u_cnt, u_neb;  // union nodes
