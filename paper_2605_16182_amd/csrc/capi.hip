@@ -72,7 +72,7 @@ tw_status tw_destroy(tw_graph* g) {
     return guarded("tw_destroy", [&]() -> tw_status {
         hipStreamSynchronize(g->stream);
         tw::DevBuf* bufs[] = {&g->e_src, &g->e_dst, &g->e_ts, &g->a_src, &g->a_dst, &g->a_ts,
-                              &g->gg_ts, &g->gg_off, &g->n_dst, &g->n_ts, &g->ng_ts, &g->ng_off,
+                              &g->gg_ts, &g->gg_off, &g->n_dst, &g->n_ts, &g->ng_ts, &g->ngo,
                               &g->n_src, &g->fence, &g->rec, &g->adj, &g->b_src, &g->b_dst, &g->b_ts,
                               &g->b_keys, &g->b_vals, &g->b_flags, &g->flags, &g->idx, &g->err,
                               &g->scal, &g->ws.scan_part, &g->ws.hist, &g->ws.keys_alt,
@@ -167,7 +167,7 @@ tw_status tw_export_views(tw_graph* g, int32_t* src, int32_t* dst, int64_t* ts, 
 int64_t tw_device_bytes(const tw_graph* g) {
     if (!g) return 0;
     const tw::DevBuf* bufs[] = {&g->e_src, &g->e_dst, &g->e_ts, &g->a_src, &g->a_dst, &g->a_ts,
-                                &g->gg_ts, &g->gg_off, &g->n_dst, &g->n_ts, &g->ng_ts, &g->ng_off,
+                                &g->gg_ts, &g->gg_off, &g->n_dst, &g->n_ts, &g->ng_ts, &g->ngo,
                                 &g->n_src, &g->fence, &g->rec, &g->adj, &g->b_src, &g->b_dst, &g->b_ts,
                                 &g->b_keys, &g->b_vals, &g->b_flags, &g->flags, &g->idx, &g->err,
                                 &g->scal, &g->ws.scan_part, &g->ws.hist, &g->ws.keys_alt,

@@ -285,21 +285,6 @@ __global__ void k_merge_new(const uint32_t* __restrict__ bs_src, const int32_t* 
 // (node, timestamp) groups of the node view, with the node of each group
 
 
-// levels K and total entries of the fence of a node with G groups
-__device__ __forceinline__ void fence_shape(uint32_t G, uint32_t* levels, uint32_t* size) {
-    uint32_t K = 0, total = 0;
-    if (G > (uint32_t)FENCE_FAN) {
-        uint64_t n = G;
-        do {
-            n = (n + FENCE_FAN - 1) / FENCE_FAN;
-            ++K;
-            total += (uint32_t)((n + FENCE_FAN - 1) / FENCE_FAN * FENCE_FAN);
-        } while (n > (uint64_t)FENCE_FAN);
-    }
-    *levels = K;
-    *size = total;
-}
-
 __global__ void k_node_group_flags(const uint32_t* __restrict__ n_src,
                                    const int64_t* __restrict__ n_ts, int64_t m,
                                    uint32_t* __restrict__ flags) {
@@ -338,6 +323,11 @@ __global__ void k_adj_extract(const uint64_t* __restrict__ keys, int64_t m,
                               int32_t* __restrict__ adj) {
     int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
     if (i < m) adj[i] = (int32_t)(uint32_t)keys[i];
+}
+
+__global__ void k_widen2(const uint2* __restrict__ in, int64_t n, int64_t* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (i < n) out[i] = (int64_t)in[i].x;
 }
 
 __global__ void k_widen(const uint32_t* __restrict__ in, int64_t n, int64_t* __restrict__ out,
@@ -479,19 +469,19 @@ __global__ void k_active_compact(const uint32_t* __restrict__ aflags,
 
 // group range and fence size of every active node: its first edge and its
 // end are group starts, found by binary search in the group offsets
-__device__ __forceinline__ uint32_t find_group(const uint32_t* __restrict__ g_off, uint32_t n,
+__device__ __forceinline__ uint32_t find_group(const uint2* __restrict__ g_od, uint32_t n,
                                                uint32_t e) {
     uint32_t lo = 0, hi = n;
     while (lo < hi) {
         uint32_t mid = lo + ((hi - lo) >> 1);
-        if (g_off[mid] < e) lo = mid + 1; else hi = mid;
+        if (g_od[mid].x < e) lo = mid + 1; else hi = mid;
     }
     return lo;
 }
 
 __global__ void k_active_groups(const uint32_t* __restrict__ a_eb,
                                 const uint32_t* __restrict__ a_cnt, int64_t A, int64_t m,
-                                const uint32_t* __restrict__ g_off, const uint32_t* Gn,
+                                const uint2* __restrict__ g_off, const uint32_t* Gn,
                                 uint32_t* __restrict__ a_gb, uint32_t* __restrict__ a_ge,
                                 uint32_t* __restrict__ fsize) {
     int64_t k = (int64_t)blockIdx.x * T + threadIdx.x;
@@ -500,22 +490,21 @@ __global__ void k_active_groups(const uint32_t* __restrict__ a_eb,
     const uint32_t eb = a_eb[k], ee = eb + a_cnt[k];
     const uint32_t gb = find_group(g_off, G, eb);
     const uint32_t ge = (int64_t)ee >= m ? G : find_group(g_off, G, ee);
-    uint32_t lv, size;
-    fence_shape(ge - gb, &lv, &size);
     a_gb[k] = gb;
     a_ge[k] = ge;
-    fsize[k] = size;
+    fsize[k] = fence_geometry(gb, ge).size;
 }
 
-// Fence entries [j0, j1) (stride) of a node with G groups from gb.
-__device__ __forceinline__ void fence_entries(const int64_t* __restrict__ ng_ts, uint32_t gb,
-                                              uint32_t G, uint32_t levels, uint32_t j0,
+// Fence entries [j0, j1) (stride) of a node whose fence body starts at
+// group a0 and has `body` groups.
+__device__ __forceinline__ void fence_entries(const int64_t* __restrict__ ng_ts, uint32_t a0,
+                                              uint32_t body, uint32_t levels, uint32_t j0,
                                               uint32_t j1, uint32_t stride,
                                               int64_t* __restrict__ out) {
-    // level k (stored from K down to 1) holds ng_ts[gb + i * FAN^k], i < n_k,
+    // level k (stored from K down to 1) holds ng_ts[a0 + i * FAN^k], i < n_k,
     // padded with INT64_MAX to a multiple of FENCE_FAN
     uint64_t nk[9];
-    uint64_t n = G;
+    uint64_t n = body;
     for (uint32_t k = 1; k <= levels; ++k) {
         n = (n + FENCE_FAN - 1) / FENCE_FAN;
         nk[k] = n;
@@ -529,7 +518,7 @@ __device__ __forceinline__ void fence_entries(const int64_t* __restrict__ ng_ts,
             off += len;
         }
         const uint64_t i = j - off;
-        out[j] = i < nk[k] ? ng_ts[gb + (i << (FENCE_LOG * k))] : INT64_MAX;
+        out[j] = i < nk[k] ? ng_ts[a0 + (i << (FENCE_LOG * k))] : INT64_MAX;
     }
 }
 
@@ -547,11 +536,9 @@ __global__ void k_active_records(const uint32_t* __restrict__ act,
     r.ee = r.eb + a_cnt[k];
     r.gb = a_gb[k];
     r.ge = a_ge[k];
-    uint32_t size;
-    fence_shape(r.ge - r.gb, &r.levels, &size);
+    r.levels = fence_geometry(r.gb, r.ge).levels;
     r.fence_off = foff[k];
     r.t_last = ng_ts[r.ge - 1];
-    (void)size;
     rec[act[k]] = r;
 }
 
@@ -569,8 +556,9 @@ __global__ void k_fence_fill(const uint32_t* __restrict__ foff, int64_t A, int64
     }
     const uint32_t k = (uint32_t)(lo - 1);
     const NodeRec r = rec[act[k]];
+    const FenceGeom f = fence_geometry(r.gb, r.ge);
     const uint32_t rel = (uint32_t)(j - foff[k]);
-    fence_entries(ng_ts, r.gb, r.ge - r.gb, r.levels, rel, rel + 1, 1, fence + foff[k]);
+    fence_entries(ng_ts, f.a0, r.ge - f.a0, f.levels, rel, rel + 1, 1, fence + foff[k]);
 }
 
 // CSR-style export of the node table: an empty node starts where the next
@@ -653,7 +641,7 @@ tw_status build_ts_groups(tw_graph* g, Error& err) {
     const int64_t* ts = g->e_ts.as<int64_t>() + g->e_base;
     uint32_t* G = u32_slot(g, SLOT_U32_GROUPS);
     TW_HIP(group_starts(nullptr, ts, m, (uint32_t)g->e_base, g->gg_ts.as<int64_t>(),
-                        g->gg_off.as<uint32_t>(), G, g->ws, s));
+                        g->gg_off.as<uint32_t>(), nullptr, nullptr, G, g->ws, s));
     g->gg_base = 0;
     return TW_OK;
 }
@@ -783,7 +771,7 @@ tw_status finish_index(tw_graph* g, bool gg_full, int64_t gg_old, int64_t gg_evi
     TW_HIP(ensure(g->flags, sizeof(uint32_t) * (m + 1)));
     TW_HIP(ensure(g->idx, sizeof(uint32_t) * (m + 1)));
     TW_HIP(ensure(g->ng_ts, sizeof(int64_t) * (m + 1)));
-    TW_HIP(ensure(g->ng_off, sizeof(uint32_t) * (m + 2)));
+    TW_HIP(ensure(g->ngo, sizeof(uint2) * (m + 2)));
     TW_HIP(ensure(g->a_gb, sizeof(uint32_t) * (A + 1)));
     TW_HIP(ensure(g->a_foff, sizeof(uint32_t) * (A + 1)));
     TW_HIP(ensure(g->gflags, sizeof(uint32_t) * (m + 1)));
@@ -793,12 +781,12 @@ tw_status finish_index(tw_graph* g, bool gg_full, int64_t gg_old, int64_t gg_evi
     TW_HIP(ensure(g->a_ge, sizeof(uint32_t) * (A + 1)));
 
     // (node, timestamp) groups
-    TW_HIP(group_starts(flags, g->n_ts.as<int64_t>(), m, 0u, g->ng_ts.as<int64_t>(),
-                        g->ng_off.as<uint32_t>(), Gn, g->ws, s));
+    TW_HIP(group_starts(flags, g->n_ts.as<int64_t>(), m, 0u, g->ng_ts.as<int64_t>(), nullptr,
+                        g->ngo.as<uint2>(), g->n_dst.as<int32_t>(), Gn, g->ws, s));
 
     // group ranges, fence sizes and offsets of the active nodes
     hipLaunchKernelGGL(k_active_groups, grid_for(A), dim3(T), 0, s, g->a_eb.as<uint32_t>(),
-                       g->a_cnt.as<uint32_t>(), A, m, g->ng_off.as<uint32_t>(), Gn,
+                       g->a_cnt.as<uint32_t>(), A, m, g->ngo.as<uint2>(), Gn,
                        g->a_gb.as<uint32_t>(), g->a_ge.as<uint32_t>(), g->a_foff.as<uint32_t>());
     TW_HIP(scan_exclusive_u32(g->a_foff.as<uint32_t>(), g->a_foff.as<uint32_t>(), A, fence_total,
                               g->ws, s));
@@ -1021,8 +1009,8 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
             hipLaunchKernelGGL(k_append_group_flags, grid_for(kept), dim3(T), 0, s, q_ts, kept,
                                last_ts, 1, fl);
             TW_HIP(group_starts(fl, q_ts, kept, (uint32_t)(g->e_base + na),
-                                g->gg_ts.as<int64_t>() + gpos, g->gg_off.as<uint32_t>() + gpos, G,
-                                g->ws, s));
+                                g->gg_ts.as<int64_t>() + gpos, g->gg_off.as<uint32_t>() + gpos,
+                                nullptr, nullptr, G, g->ws, s));
         } else {
             // eviction only: the groups keep their offsets
             hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(T), 0, s, u32_slot(g, SLOT_U32_GROUPS), 1,
@@ -1162,8 +1150,8 @@ tw_status export_views(tw_graph* g, int32_t* src, int32_t* dst, int64_t* ts, int
         hipLaunchKernelGGL(k_widen, grid_for(g->Gg + 1), dim3(T), 0, s,
                            g->gg_off.as<uint32_t>() + g->gg_base, g->Gg + 1, g_off, g->e_base);
     if (n_goff)
-        hipLaunchKernelGGL(k_widen, grid_for(g->Gn + 1), dim3(T), 0, s, g->ng_off.as<uint32_t>(),
-                           g->Gn + 1, n_goff, (int64_t)0);
+        hipLaunchKernelGGL(k_widen2, grid_for(g->Gn + 1), dim3(T), 0, s, g->ngo.as<uint2>(),
+                           g->Gn + 1, n_goff);
     if (n_ebeg || n_gbeg)
         hipLaunchKernelGGL(k_export_nodes, grid_for(g->V + 1), dim3(T), 0, s,
                            g->rec.as<NodeRec>(), g->act0.as<uint32_t>(), g->A, g->V, m, g->Gn,

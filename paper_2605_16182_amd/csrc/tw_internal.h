@@ -25,13 +25,39 @@ struct alignas(32) NodeRec {
     int64_t t_last;
 };
 
-// Fence index: for a node with G > FENCE_FAN groups, level k (k = 1..K)
-// holds every FENCE_FAN^k-th group timestamp of the node, padded to a
-// multiple of FENCE_FAN entries with INT64_MAX; levels are stored top (K)
-// first. K is the smallest level with at most FENCE_FAN entries. A search
-// reads one FENCE_FAN-entry window (one 128-byte line) per level.
+// Fence index. A node's groups [gb, ge) split into a head [gb, a0), where
+// a0 is the first group index that is a multiple of FENCE_FAN, and a body
+// [a0, ge). When the body has more than FENCE_FAN groups, fence level k
+// (k = 1..K) holds the timestamps of groups a0 + i FENCE_FAN^k, padded to a
+// multiple of FENCE_FAN entries with INT64_MAX, stored top level (K) first;
+// K is the smallest level with at most FENCE_FAN entries. A search reads one
+// FENCE_FAN-entry window (one aligned 128-byte line) per level and one
+// aligned window of the group timestamps.
 constexpr int FENCE_FAN = 16;
 constexpr int FENCE_LOG = 4;
+
+struct FenceGeom {
+    uint32_t a0;      // first aligned group of the body
+    uint32_t levels;  // K (0: no fence, the node is scanned directly)
+    uint32_t size;    // fence entries
+};
+
+__host__ __device__ inline FenceGeom fence_geometry(uint32_t gb, uint32_t ge) {
+    FenceGeom f;
+    f.a0 = (gb + FENCE_FAN - 1) & ~(uint32_t)(FENCE_FAN - 1);
+    f.levels = 0;
+    f.size = 0;
+    const uint64_t body = ge > f.a0 ? (uint64_t)(ge - f.a0) : 0;
+    if (body > (uint64_t)FENCE_FAN) {
+        uint64_t n = body;
+        do {
+            n = (n + FENCE_FAN - 1) / FENCE_FAN;
+            ++f.levels;
+            f.size += (uint32_t)((n + FENCE_FAN - 1) / FENCE_FAN * FENCE_FAN);
+        } while (n > (uint64_t)FENCE_FAN);
+    }
+    return f;
+}
 
 // Slots of the graph's device scalar buffer (256 bytes): u32 indices
 // (SLOT_U32_*) and int64 indices (SLOT_I64_*).
@@ -88,9 +114,10 @@ hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint
 // != 0, or with flags null, ts[i] != ts[i-1]) gives g_ts[k] = ts[i] and
 // g_off[k] = pos_base + i; g_off[total] = pos_base + n; total (device) = the
 // number of groups. n may be 0.
+// With g_od non-null, g_od[k] = {pos_base + i, dst[i]} replaces g_off.
 hipError_t group_starts(const uint32_t* flags, const int64_t* ts, int64_t n, uint32_t pos_base,
-                        int64_t* g_ts, uint32_t* g_off, uint32_t* total, Workspace& ws,
-                        hipStream_t s);
+                        int64_t* g_ts, uint32_t* g_off, uint2* g_od, const int32_t* dst,
+                        uint32_t* total, Workspace& ws, hipStream_t s);
 
 // Stable LSD radix sort of (keys, vals) by bits [bit_lo, bit_hi) of the key.
 // vals may be null. Result ends in keys / vals. The alternate buffers come
@@ -153,7 +180,8 @@ struct tw_graph {
     tw::DevBuf gflags;                 // (node, timestamp) group starts of the node view
     tw::DevBuf it_keys, it_pay, it_skeys, it_spay;  // union items
     tw::DevBuf u_flags, u_pos, u_node, u_cnt, u_neb;  // union nodes
-    tw::DevBuf ng_ts, ng_off;          // its (node, timestamp) groups
+    tw::DevBuf ng_ts, ngo;             // its (node, timestamp) groups: timestamps,
+                                       // {first edge, destination of the first edge}
     tw::DevBuf n_src;                  // source of each node-view edge (build temp)
     tw::DevBuf fence;                  // fence levels of nodes with many groups
     int64_t fence_len = 0;

@@ -22,7 +22,7 @@ struct WalkArgs {
     const int32_t* n_dst;
     const int64_t* n_ts;
     const int64_t* ng_ts;
-    const uint32_t* ng_off;
+    const uint2* ngo;
     const NodeRec* rec;
     const int64_t* fence;
     const int32_t* adj;
@@ -63,14 +63,11 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, int64_t w, u
         if (a.start_kind == TW_UNIFORM) {
             e = a.e_base + (uint32_t)scale_u64(d0.x0, a.m);
         } else {
-            Pick p = pick_in_groups(a.gg_ts, a.gg_off, a.e_ts, 0, a.Gg, a.m, a.start_kind,
-                                    a.start_tau, a.gg_ts[a.Gg - 1], d0);
-            e = p.e;
+            e = pick_global(a.gg_ts, a.gg_off, a.Gg, a.start_kind, a.start_tau, d0);
         }
         const int32_t s = a.e_src[e], t_dst = a.e_dst[e];
         const int64_t t = a.e_ts[e];
         out_n[0] = s;
-        out_t[0] = TS_NONE;
         st.len = 1;
         if (a.L == 1) return st;
         out_n[1] = t_dst;
@@ -87,14 +84,13 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, int64_t w, u
         return st;
     }
     out_n[0] = v0;
-    out_t[0] = TS_NONE;
     st.len = 1;
     if (a.L == 1) return st;
     const NodeRec r = a.rec[v0];
     if (r.gb == r.ge) return st;
-    Pick p = pick_in_groups(a.ng_ts, a.ng_off, a.n_ts, r.gb, r.ge, r.ee, a.start_kind, a.start_tau,
-                            r.t_last, d0);
-    const int32_t nx = a.n_dst[p.e];
+    Pick p = pick_node(a.ng_ts, a.ngo, a.n_dst, a.n_ts, r.gb, r.ge, r.ee, a.start_kind,
+                       a.start_tau, r.t_last, d0);
+    const int32_t nx = p.dst;
     out_n[1] = nx;
     out_t[1] = p.t;
     st.len = 2;
@@ -112,17 +108,17 @@ __device__ __forceinline__ bool hop_pick(const WalkArgs& a, const NodeRec& r, ui
                                          int32_t& nx) {
     if (a.hop_kind != TW_NODE2VEC) {
         const Draw d = philox(id, hop, 0, a.seed);
-        p = pick_in_groups(a.ng_ts, a.ng_off, a.n_ts, gc, r.ge, r.ee, a.hop_kind, a.hop_tau,
-                           r.t_last, d);
-        nx = a.n_dst[p.e];
+        p = pick_node(a.ng_ts, a.ngo, a.n_dst, a.n_ts, gc, r.ge, r.ee, a.hop_kind, a.hop_tau,
+                      r.t_last, d);
+        nx = p.dst;
         return true;
     }
     const NodeRec rp = a.rec[prev];
     for (uint32_t trial = 0; trial < N2V_MAX_TRIALS; ++trial) {
         const Draw d = philox(id, hop, trial, a.seed);
-        p = pick_in_groups(a.ng_ts, a.ng_off, a.n_ts, gc, r.ge, r.ee, TW_EXPONENTIAL, a.hop_tau,
-                           r.t_last, d);
-        nx = a.n_dst[p.e];
+        p = pick_node(a.ng_ts, a.ngo, a.n_dst, a.n_ts, gc, r.ge, r.ee, TW_EXPONENTIAL, a.hop_tau,
+                      r.t_last, d);
+        nx = p.dst;
         double beta;
         if (nx == prev) beta = a.inv_p;
         else if (sorted_contains(a.adj, rp.eb, rp.ee, nx)) beta = 1.0;
@@ -133,14 +129,32 @@ __device__ __forceinline__ bool hop_pick(const WalkArgs& a, const NodeRec& r, ui
     return false;
 }
 
+// the output rows were pre-filled with -1 / INT64_MIN, so ending a walk
+// only records its length
 __device__ __forceinline__ void finish_walk(const WalkArgs& a, int64_t w, int32_t len) {
-    int32_t* out_n = a.nodes + w * a.L;
-    int64_t* out_t = a.ts + w * a.L;
-    for (int32_t j = len; j < a.L; ++j) {
-        out_n[j] = -1;
-        out_t[j] = TS_NONE;
-    }
     a.len[w] = len;
+}
+
+// Fill every output slot with the padding values (-1 nodes, INT64_MIN
+// timestamps) with wide, fully coalesced stores; the walk kernels then write
+// only the slots their walks reach.
+__global__ void k_fill_outputs(int32_t* __restrict__ nodes, int64_t* __restrict__ ts,
+                               int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // nodes: 16-byte stores where the array is 16-byte aligned
+    const int64_t head_n = ((16 - ((uintptr_t)nodes & 15)) & 15) / 4;
+    for (int64_t i = tid; i < head_n && i < n; i += stride) nodes[i] = -1;
+    const int64_t nv = (n - head_n) / 4;
+    int4* nv4 = reinterpret_cast<int4*>(nodes + head_n);
+    for (int64_t i = tid; i < nv; i += stride) nv4[i] = make_int4(-1, -1, -1, -1);
+    for (int64_t i = head_n + 4 * nv + tid; i < n; i += stride) nodes[i] = -1;
+    const int64_t head_t = ((16 - ((uintptr_t)ts & 15)) & 15) / 8;
+    for (int64_t i = tid; i < head_t && i < n; i += stride) ts[i] = TS_NONE;
+    const int64_t tv = (n - head_t) / 2;
+    longlong2* tv2 = reinterpret_cast<longlong2*>(ts + head_t);
+    for (int64_t i = tid; i < tv; i += stride) tv2[i] = make_longlong2(TS_NONE, TS_NONE);
+    for (int64_t i = head_t + 2 * tv + tid; i < n; i += stride) ts[i] = TS_NONE;
 }
 
 // One full walk per thread: the full-walk baseline (Sec. "The Full-Walk
@@ -252,8 +266,7 @@ k_hop_coop(const WalkArgs a, Live cur, Live nxt, int32_t* __restrict__ prev_of, 
         const NodeRec r = a.rec[node];
         const uint32_t slice = wg_uniform ? panel_cap : panel_cap / (WALK_THREADS / 64);
         int64_t* dst = wg_uniform ? panel : panel + wave * slice;
-        uint32_t lv, size;
-        fence_shape_dev(r.ge - r.gb, &lv, &size);
+        const uint32_t size = fence_geometry(r.gb, r.ge).size;
         my_cap = size < slice ? size : slice;
         const int first = wg_uniform ? threadIdx.x : lane;
         const int stride = wg_uniform ? WALK_THREADS : 64;
@@ -396,7 +409,7 @@ tw_status sample_walks(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int
     a.n_dst = g->n_dst.as<int32_t>();
     a.n_ts = g->n_ts.as<int64_t>();
     a.ng_ts = g->ng_ts.as<int64_t>();
-    a.ng_off = g->ng_off.as<uint32_t>();
+    a.ngo = g->ngo.as<uint2>();
     a.rec = g->rec.as<NodeRec>();
     a.fence = g->fence.as<int64_t>();
     a.adj = g->adj.as<int32_t>();
@@ -422,6 +435,10 @@ tw_status sample_walks(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int
     // more (sorting, step tails, partial-line output writes) than it saves,
     // since L2 and the MALL already hold the hot node metadata.
     const bool coop = p->dispatch == TW_DISPATCH_COOP;
+    const int64_t slots = p->num_walks * (int64_t)p->max_len;
+    hipLaunchKernelGGL(k_fill_outputs,
+                       dim3((unsigned)std::min<int64_t>(ceil_div(slots, 4 * WALK_THREADS), 8192)),
+                       dim3(WALK_THREADS), 0, g->stream, nodes, ts, slots);
     if (!coop) {
         int64_t blocks = ceil_div(p->num_walks, WALK_THREADS);
         hipLaunchKernelGGL(k_walk_full, dim3((unsigned)blocks), dim3(WALK_THREADS), 0, g->stream,

@@ -100,63 +100,67 @@ __device__ __forceinline__ uint32_t upper_bound_ts(const int64_t* __restrict__ t
     return lo;
 }
 
+// count of ts[lo, hi) that are <= t (ts ascending): a few entries are
+// counted directly, longer ranges by binary search
+__device__ __forceinline__ uint32_t count_le(const int64_t* __restrict__ ts, uint32_t lo,
+                                             uint32_t hi, int64_t t) {
+    if (hi - lo <= 4) {
+        uint32_t c = 0;
+        for (uint32_t j = lo; j < hi; ++j) c += (ts[j] <= t);
+        return c;
+    }
+    uint32_t a = lo, b = hi;
+    while (a < b) {
+        const uint32_t mid = a + ((b - a) >> 1);
+        if (ts[mid] <= t) a = mid + 1; else b = mid;
+    }
+    return a - lo;
+}
+
 // Gamma lookup (Sec. "Dual-Index Organization": the first timestamp group of
-// the node strictly after t) through the node's fence: one FENCE_FAN-entry
-// window per level, each a single 128-byte line, then one window of the
-// node's own group timestamps. Requires t < r.t_last, so the result is
-// below r.ge. Returns the absolute group index.
-// panel (nullable) holds the first panel_len entries of the node's fence
-// (its top levels) in LDS; windows inside it are read from there.
+// the node strictly after t) through the node's fence: one aligned
+// FENCE_FAN-entry window per level, each a single 128-byte line, then one
+// aligned window of the node's group timestamps. Requires t < r.t_last, so
+// the result is below r.ge. Returns the absolute group index. panel
+// (nullable) holds the first panel_len entries of the node's fence (its top
+// levels) in LDS; windows inside it are read from there.
 __device__ __forceinline__ uint32_t fence_search(const int64_t* __restrict__ gts,
                                                  const int64_t* __restrict__ fence,
                                                  const NodeRec& r, int64_t t,
                                                  const int64_t* panel, uint32_t panel_len) {
-    const uint32_t G = r.ge - r.gb;
-    uint64_t lo = 0;
-    if (r.levels > 0) {
-        uint64_t off = r.fence_off;
-        for (int k = (int)r.levels; k >= 1; --k) {
-            const uint64_t rel = off - r.fence_off + lo;
-            const longlong2* win = reinterpret_cast<const longlong2*>(
-                rel + FENCE_FAN <= panel_len ? panel + rel : fence + off + lo);
-            uint32_t c = 0;
+    if (r.levels == 0) return r.gb + count_le(gts, r.gb, r.ge, t);
+    const uint32_t a0 = (r.gb + FENCE_FAN - 1) & ~(uint32_t)(FENCE_FAN - 1);
+    const uint32_t body = r.ge - a0;
+    uint64_t lo = 0, off = r.fence_off;
+    for (int k = (int)r.levels; k >= 1; --k) {
+        const uint64_t rel = off - r.fence_off + lo;
+        const longlong2* win = reinterpret_cast<const longlong2*>(
+            rel + FENCE_FAN <= panel_len ? panel + rel : fence + off + lo);
+        uint32_t c = 0;
 #pragma unroll
-            for (int j = 0; j < FENCE_FAN / 2; ++j) {
-                const longlong2 v = win[j];
-                c += (v.x <= t) + (v.y <= t);
-            }
-            if (c == 0) return r.gb;  // only possible at the top level: t precedes the node
-            lo = (lo + c - 1) * FENCE_FAN;
-            const uint32_t sh = FENCE_LOG * (uint32_t)k;
-            const uint64_t nk = ((uint64_t)G + (1ull << sh) - 1) >> sh;
-            off += (nk + FENCE_FAN - 1) / FENCE_FAN * FENCE_FAN;
+        for (int j = 0; j < FENCE_FAN / 2; ++j) {
+            const longlong2 v = win[j];
+            c += (v.x <= t) + (v.y <= t);
         }
+        // only possible at the top level: t precedes the body
+        if (c == 0) return r.gb + count_le(gts, r.gb, a0, t);
+        lo = (lo + c - 1) * FENCE_FAN;
+        const uint32_t sh = FENCE_LOG * (uint32_t)k;
+        const uint64_t nk = ((uint64_t)body + (1ull << sh) - 1) >> sh;
+        off += (nk + FENCE_FAN - 1) / FENCE_FAN * FENCE_FAN;
     }
-    const int64_t* base = gts + r.gb + lo;
     uint32_t c = 0;
-    if (lo + FENCE_FAN <= G) {
+    if (lo + FENCE_FAN <= body) {
+        const longlong2* win = reinterpret_cast<const longlong2*>(gts + a0 + lo);
 #pragma unroll
-        for (int j = 0; j < FENCE_FAN; ++j) c += (base[j] <= t);
+        for (int j = 0; j < FENCE_FAN / 2; ++j) {
+            const longlong2 v = win[j];
+            c += (v.x <= t) + (v.y <= t);
+        }
     } else {
-        const uint32_t rem = (uint32_t)(G - lo);
-        for (uint32_t j = 0; j < rem; ++j) c += (base[j] <= t);
+        c = count_le(gts, a0 + (uint32_t)lo, r.ge, t);
     }
-    return r.gb + (uint32_t)lo + c;
-}
-
-// levels K and total entries of the fence of a node with G groups
-__device__ __forceinline__ void fence_shape_dev(uint32_t G, uint32_t* levels, uint32_t* size) {
-    uint32_t K = 0, total = 0;
-    if (G > (uint32_t)FENCE_FAN) {
-        uint64_t n = G;
-        do {
-            n = (n + FENCE_FAN - 1) / FENCE_FAN;
-            ++K;
-            total += (uint32_t)((n + FENCE_FAN - 1) / FENCE_FAN * FENCE_FAN);
-        } while (n > (uint64_t)FENCE_FAN);
-    }
-    *levels = K;
-    *size = total;
+    return a0 + (uint32_t)lo + c;
 }
 
 // is w among the sorted values adj[lo, hi)?
@@ -171,33 +175,49 @@ __device__ __forceinline__ bool sorted_contains(const int32_t* __restrict__ adj,
     return false;
 }
 
-// One biased or uniform pick among groups [gc, ge) of (gts, goff), where
-// goff[ge] == end. Returns the edge index and its timestamp.
+// The group index picked among n groups by a linear or exponential bias.
+__device__ __forceinline__ uint32_t pick_group(uint32_t n, int kind, double tau, int64_t t_first,
+                                               int64_t t_last, uint64_t x) {
+    if (kind == TW_LINEAR) return pick_linear(n, x);
+    return pick_exponential(n, exp_lambda(t_first, t_last, n, tau), x);
+}
+
+// A pick in the node view among the groups [gc, ge) of a node whose edges
+// end at `end`: uniform over the edges, or biased over the groups and then
+// uniform inside the group. The destination of a group's first edge is
+// stored with the group, so a one-edge group needs no edge load.
 struct Pick {
-    uint32_t e;
+    int32_t dst;
     int64_t t;
 };
 
-__device__ __forceinline__ Pick pick_in_groups(const int64_t* __restrict__ gts,
-                                               const uint32_t* __restrict__ goff,
-                                               const int64_t* __restrict__ ets, uint32_t gc,
-                                               uint32_t ge, uint32_t end, int kind, double tau,
-                                               int64_t t_last, const Draw& d) {
+__device__ __forceinline__ Pick pick_node(const int64_t* __restrict__ gts,
+                                          const uint2* __restrict__ ngo,
+                                          const int32_t* __restrict__ n_dst,
+                                          const int64_t* __restrict__ n_ts, uint32_t gc,
+                                          uint32_t ge, uint32_t end, int kind, double tau,
+                                          int64_t t_last, const Draw& d) {
     if (kind == TW_UNIFORM) {
-        uint32_t c = goff[gc];
-        uint32_t e = c + (uint32_t)scale_u64(d.x0, end - c);
-        return Pick{e, ets[e]};
+        const uint32_t c = ngo[gc].x;
+        const uint32_t e = c + (uint32_t)scale_u64(d.x0, end - c);
+        return Pick{n_dst[e], n_ts[e]};
     }
-    uint32_t n = ge - gc, i;
-    if (kind == TW_LINEAR) {
-        i = pick_linear(n, d.x0);
-    } else {
-        double lam = exp_lambda(n > 1 ? gts[gc] : 0, t_last, n, tau);
-        i = pick_exponential(n, lam, d.x0);
-    }
-    uint32_t k = gc + i;
-    uint32_t b0 = goff[k], b1 = goff[k + 1];
-    return Pick{b0 + (uint32_t)scale_u64(d.x1, b1 - b0), gts[k]};
+    const uint32_t n = ge - gc;
+    const uint32_t k = gc + pick_group(n, kind, tau, n > 1 ? gts[gc] : 0, t_last, d.x0);
+    const uint2 a = ngo[k];
+    const uint32_t size = ngo[k + 1].x - a.x;
+    const int32_t dst =
+        size == 1 ? (int32_t)a.y : n_dst[a.x + (uint32_t)scale_u64(d.x1, size)];
+    return Pick{dst, gts[k]};
+}
+
+// The edge-store position picked among the window's Gg timestamp groups.
+__device__ __forceinline__ uint32_t pick_global(const int64_t* __restrict__ gg_ts,
+                                                const uint32_t* __restrict__ gg_off, uint32_t Gg,
+                                                int kind, double tau, const Draw& d) {
+    const uint32_t k = pick_group(Gg, kind, tau, Gg > 1 ? gg_ts[0] : 0, gg_ts[Gg - 1], d.x0);
+    const uint32_t b0 = gg_off[k], b1 = gg_off[k + 1];
+    return b0 + (uint32_t)scale_u64(d.x1, b1 - b0);
 }
 
 }  // namespace tw
