@@ -503,8 +503,9 @@ __device__ __forceinline__ void fence_entries(const int64_t* __restrict__ ng_ts,
                                               int64_t* __restrict__ out) {
     // level k (stored from K down to 1) holds ng_ts[a0 + i * FAN^k], i < n_k,
     // padded with INT64_MAX to a multiple of FENCE_FAN
-    uint64_t nk[9];
+    uint64_t nk[FENCE_MAX_LEVELS + 1];
     uint64_t n = body;
+    if (levels > (uint32_t)FENCE_MAX_LEVELS) return;  // cannot happen for 32-bit groups
     for (uint32_t k = 1; k <= levels; ++k) {
         n = (n + FENCE_FAN - 1) / FENCE_FAN;
         nk[k] = n;
@@ -596,7 +597,11 @@ uint32_t* u32_slot(tw_graph* g, int k) { return g->scal.as<uint32_t>() + k; }
 int64_t* i64_slot(tw_graph* g, int k) { return g->scal.as<int64_t>() + k; }
 
 tw_status ensure_common(tw_graph* g, Error& err) {
-    TW_HIP(ensure(g->err, sizeof(uint32_t) * 4));
+    if (!g->err.p) {
+        // device error flags start cleared
+        TW_HIP(ensure(g->err, sizeof(uint32_t) * 4));
+        TW_HIP(hipMemsetAsync(g->err.p, 0, sizeof(uint32_t) * 4, g->stream));
+    }
     TW_HIP(ensure(g->scal, SCALAR_BYTES));
     return TW_OK;
 }

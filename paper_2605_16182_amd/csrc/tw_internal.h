@@ -33,8 +33,12 @@ struct alignas(32) NodeRec {
 // K is the smallest level with at most FENCE_FAN entries. A search reads one
 // FENCE_FAN-entry window (one aligned 128-byte line) per level and one
 // aligned window of the group timestamps.
-constexpr int FENCE_FAN = 16;
-constexpr int FENCE_LOG = 4;
+constexpr int FENCE_FAN = 8;
+constexpr int FENCE_LOG = 3;
+
+// most levels a fence can have: group indices are 32-bit
+constexpr int FENCE_MAX_LEVELS = (32 + FENCE_LOG - 1) / FENCE_LOG + 1;
+static_assert((1 << FENCE_LOG) == FENCE_FAN, "FENCE_FAN must be 2^FENCE_LOG");
 
 struct FenceGeom {
     uint32_t a0;      // first aligned group of the body

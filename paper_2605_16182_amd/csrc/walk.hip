@@ -392,7 +392,6 @@ tw_status sample_walks(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int
         err = Error{TW_EINVAL, "sample_walks: null output"};
         return err.code;
     }
-    TW_HIP(ensure(g->err, sizeof(uint32_t) * 4));
     if (!g->rec.p && init_empty(g, err) != TW_OK) return err.code;
     if (hb.kind == TW_NODE2VEC && g->m > 0) {
         if (build_adjacency(g, err) != TW_OK) return err.code;

@@ -119,7 +119,7 @@ __device__ __forceinline__ uint32_t count_le(const int64_t* __restrict__ ts, uin
 
 // Gamma lookup (Sec. "Dual-Index Organization": the first timestamp group of
 // the node strictly after t) through the node's fence: one aligned
-// FENCE_FAN-entry window per level, each a single 128-byte line, then one
+// FENCE_FAN-entry window per level, each one aligned 64-byte sector, then one
 // aligned window of the node's group timestamps. Requires t < r.t_last, so
 // the result is below r.ge. Returns the absolute group index. panel
 // (nullable) holds the first panel_len entries of the node's fence (its top

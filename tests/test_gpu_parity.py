@@ -288,3 +288,44 @@ def test_long_stream_compactions(sorted_arrivals):
                                 start_tau=300.0, seed=b, with_margin=True)
             compare_walks((nodes.cpu().numpy(), ts.cpu().numpy(), lens.cpu().numpy()), r, False)
     g.close()
+
+
+def test_fresh_graph_reports_no_error():
+    # device error flags start cleared: a fresh graph's first synchronising
+    # calls succeed, before and after edge-start walks
+    torch, tw = gpu_or_skip()
+    for _ in range(3):
+        g = tw.Graph(50)
+        g.sync()
+        s, d, t = to_dev(torch, np.arange(10, dtype=np.int32), np.arange(10, dtype=np.int32)[::-1].copy(),
+                         np.arange(10, dtype=np.int64))
+        g.ingest_batch(s, d, t)
+        g.sample_walks(100, 5)
+        g.sync()
+        g.ingest_batch(s, d, t + 100)
+        g.close()
+
+
+def test_deep_fence_hub():
+    # a hub with millions of timestamp groups: many fence levels for any fan
+    torch, tw = gpu_or_skip()
+    rng = np.random.default_rng(77)
+    G = 3_000_000
+    t = np.sort(rng.choice(np.arange(4 * G), G, replace=False)).astype(np.int64)
+    src = np.zeros(G, np.int32)
+    dst = np.where(rng.random(G) < 0.9, 0, 1).astype(np.int32)
+    src = np.concatenate([src, np.array([1], np.int32)])
+    dst = np.concatenate([dst, np.array([0], np.int32)])
+    t = np.concatenate([t, np.array([1], np.int64)])
+    g = tw.Graph(2)
+    og = oracle.OracleGraph(2)
+    g.ingest_batch(*to_dev(torch, src, dst, t))
+    og.ingest_batch(src, dst, t)
+    W, L = 20_000, 30
+    for kind in ("uniform", "linear"):
+        nodes, tts, lens = g.sample_walks(W, L, hop_bias=kind, start_bias=kind, seed=13)
+        g.sync()
+        r = og.sample_walks(W, L, hop_bias=kind, start_bias=kind, seed=13)
+        assert np.array_equal(nodes.cpu().numpy(), r["nodes"])
+        assert np.array_equal(tts.cpu().numpy(), r["ts"])
+    g.close()
