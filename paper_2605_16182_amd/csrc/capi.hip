@@ -71,13 +71,7 @@ tw_status tw_destroy(tw_graph* g) {
     if (!g) return TW_OK;
     return guarded("tw_destroy", [&]() -> tw_status {
         hipStreamSynchronize(g->stream);
-        tw::DevBuf* bufs[] = {&g->e_src, &g->e_dst, &g->e_ts, &g->a_src, &g->a_dst, &g->a_ts,
-                              &g->gg_ts, &g->gg_off, &g->n_dst, &g->n_ts, &g->ng_ts, &g->ngo,
-                              &g->n_src, &g->fence, &g->rec, &g->adj, &g->b_src, &g->b_dst, &g->b_ts,
-                              &g->b_keys, &g->b_vals, &g->b_flags, &g->flags, &g->idx, &g->err,
-                              &g->scal, &g->ws.scan_part, &g->ws.hist, &g->ws.keys_alt,
-                              &g->ws.vals_alt, &g->ws.v64_alt, &g->ws.misc, &g->c_node0, &g->c_walk0, &g->c_t0, &g->c_node1, &g->c_walk1, &g->c_t1, &g->c_node2, &g->c_walk2, &g->c_t2, &g->c_prev, &g->c_flags, &g->c_pos, &g->an_src, &g->an_dst, &g->an_ts, &g->bs_src, &g->bs_dst, &g->bs_ts, &g->q_src, &g->q_dst, &g->q_ts, &g->plan, &g->neb_v, &g->act0, &g->act1, &g->a_eb, &g->a_cnt, &g->a_gb, &g->a_ge, &g->a_foff, &g->gflags, &g->it_keys, &g->it_pay, &g->it_skeys, &g->it_spay, &g->u_flags, &g->u_pos, &g->u_node, &g->u_cnt, &g->u_neb};
-        for (tw::DevBuf* b : bufs) tw::release(*b);
+        for (tw::DevBuf* b : g->buffers()) tw::release(*b);
         delete g;
         return TW_OK;
     });
@@ -144,11 +138,17 @@ tw_status tw_view_sizes(tw_graph* g, int64_t out[4]) {
     if (!g || !out) return fail(TW_EINVAL, "tw_view_sizes: null argument");
     if (hipStreamSynchronize(g->stream) != hipSuccess)
         return fail(TW_EDEVICE, "tw_view_sizes: stream synchronisation failed");
-    out[0] = g->m;
-    out[1] = g->Gg;
-    out[2] = g->Gn;
-    out[3] = g->V;
-    return TW_OK;
+    return guarded("tw_view_sizes", [&]() -> tw_status {
+        tw::Error e{TW_OK, ""};
+        if (!g->rec.p && tw::init_empty(g, e) != TW_OK) return report(e.code, e);
+        int64_t gn = 0;
+        if (tw::nv_group_count(g, &gn, e) != TW_OK) return report(e.code, e);
+        out[0] = g->m;
+        out[1] = g->Gg;
+        out[2] = gn;
+        out[3] = g->V;
+        return TW_OK;
+    });
 }
 
 tw_status tw_export_views(tw_graph* g, int32_t* src, int32_t* dst, int64_t* ts, int64_t* g_ts,
@@ -166,14 +166,9 @@ tw_status tw_export_views(tw_graph* g, int32_t* src, int32_t* dst, int64_t* ts, 
 
 int64_t tw_device_bytes(const tw_graph* g) {
     if (!g) return 0;
-    const tw::DevBuf* bufs[] = {&g->e_src, &g->e_dst, &g->e_ts, &g->a_src, &g->a_dst, &g->a_ts,
-                                &g->gg_ts, &g->gg_off, &g->n_dst, &g->n_ts, &g->ng_ts, &g->ngo,
-                                &g->n_src, &g->fence, &g->rec, &g->adj, &g->b_src, &g->b_dst, &g->b_ts,
-                                &g->b_keys, &g->b_vals, &g->b_flags, &g->flags, &g->idx, &g->err,
-                                &g->scal, &g->ws.scan_part, &g->ws.hist, &g->ws.keys_alt,
-                                &g->ws.vals_alt, &g->ws.v64_alt, &g->ws.misc, &g->c_node0, &g->c_walk0, &g->c_t0, &g->c_node1, &g->c_walk1, &g->c_t1, &g->c_node2, &g->c_walk2, &g->c_t2, &g->c_prev, &g->c_flags, &g->c_pos, &g->an_src, &g->an_dst, &g->an_ts, &g->bs_src, &g->bs_dst, &g->bs_ts, &g->q_src, &g->q_dst, &g->q_ts, &g->plan, &g->neb_v, &g->act0, &g->act1, &g->a_eb, &g->a_cnt, &g->a_gb, &g->a_ge, &g->a_foff, &g->gflags, &g->it_keys, &g->it_pay, &g->it_skeys, &g->it_spay, &g->u_flags, &g->u_pos, &g->u_node, &g->u_cnt, &g->u_neb};
+
     int64_t total = 0;
-    for (const tw::DevBuf* b : bufs) total += (int64_t)b->bytes;
+    for (const tw::DevBuf* b : const_cast<tw_graph*>(g)->buffers()) total += (int64_t)b->bytes;
     return total;
 }
 

@@ -1,0 +1,799 @@
+// Incremental node-and-timestamp view (Tempest, Sec. "Dual-Index
+// Organization"; maintained under the window of Sec. "Streaming Ingestion
+// and Window Management").
+//
+// Every node's edges (sorted by timestamp, then arrival), its (node,
+// timestamp) groups and its fence live in one segment of the edge, group and
+// fence pools. An ingest touches only the nodes that receive batch edges or
+// lose edges to eviction; each such node is a job:
+//   * evict: the node's first live group moves past the evicted groups;
+//   * append: the batch run starts at or after the node's last timestamp and
+//     fits the segment's free tail, so it is written in place, extending the
+//     last group when it shares its timestamp;
+//   * rewrite: the surviving run merged with the batch run (older first on
+//     equal timestamps) goes to a new segment with slack.
+// Only new groups add fence entries. When a pool has no room for the new
+// segments, every active node is rewritten into fresh pools.
+#include <algorithm>
+
+#include "tw_internal.h"
+
+namespace tw {
+namespace {
+
+constexpr int T = 256;
+constexpr int NV_ITEMS = 4;       // written edges per thread
+constexpr int FENCE_GRID = 2048;  // grid-stride launch for the fence entries
+
+inline dim3 grid_for(int64_t n, int items = 1) {
+    return dim3((unsigned)std::max<int64_t>(ceil_div(std::max<int64_t>(n, 1), (int64_t)T * items), 1));
+}
+
+// A node's allocation, used by ingest only. gen tags the pool generation the
+// segment belongs to; segments of older generations are void.
+struct alignas(32) SegRec {
+    uint32_t e0, ecap, g0, gcode;
+    uint32_t f0, gen, pad0, pad1;
+};
+
+enum : uint32_t { JOB_EVICT = 0, JOB_APPEND = 1, JOB_REWRITE = 2 };
+
+struct Job {
+    uint32_t v, kind, merge, fresh;  // node; kind; runs interleave; needs a new segment
+    uint32_t ob, oe, ogb, oge;       // surviving old edges / groups
+    uint32_t bf, be;                 // batch run in the source-sorted batch
+    uint32_t e0, ecap, g0, gcode, f0;  // the segment after the job
+    uint32_t e_at, g_at;             // first written edge / first new group
+    int64_t t_last;                  // last surviving old timestamp (INT64_MIN: none)
+};
+
+__device__ __forceinline__ NodeRec empty_rec() {
+    NodeRec r;
+    r.gb = r.ge = r.g0 = r.ee = 0;
+    r.fence_off = r.lv = 0;
+    r.t_last = INT64_MIN;
+    return r;
+}
+
+// edge slots for a segment holding n edges: half again, at least 4 spare
+__device__ __forceinline__ uint32_t edge_cap(uint32_t n) {
+    const uint64_t c = (uint64_t)n + std::max<uint64_t>(n >> 1, 4);
+    return (uint32_t)std::min<uint64_t>(c, UINT32_MAX - 1);
+}
+
+// capacity code of a group segment for n groups: FENCE_FAN << code >= 1.5 n
+__device__ __forceinline__ uint32_t group_code(uint64_t n) {
+    const uint64_t want = n + (n >> 1);
+    uint32_t c = 0;
+    while (seg_groups(c) < want) ++c;
+    return c;
+}
+
+// first group in [lo, hi) with timestamp >= t
+__device__ __forceinline__ uint32_t lower_bound_groups(const GroupRec* __restrict__ ng,
+                                                       uint32_t lo, uint32_t hi, int64_t t) {
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (ng[mid].ts < t) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// last index j in [0, n) with off[j] <= t (off ascending, off[0] <= t)
+__device__ __forceinline__ uint32_t job_of(const uint32_t* __restrict__ off, uint32_t n,
+                                           uint64_t t) {
+    uint32_t lo = 0, hi = n;  // first index with off > t
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if ((uint64_t)off[mid] <= t) lo = mid + 1; else hi = mid;
+    }
+    return lo - 1;
+}
+
+__global__ void k_empty_rec(NodeRec* __restrict__ rec, int64_t V) {
+    const int64_t v = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (v < V) rec[v] = empty_rec();
+}
+
+__global__ void k_zero_u32(uint32_t* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// ----------------------------------------------------------- job lists
+
+__global__ void k_run_flags(const uint32_t* __restrict__ src, int64_t n,
+                            uint32_t* __restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (i < n) flags[i] = (i == 0 || src[i] != src[i - 1]) ? 1u : 0u;
+}
+
+// one job per source run of the batch; marks the node touched
+__global__ void k_batch_jobs(const uint32_t* __restrict__ bsrc, int64_t n,
+                             const uint32_t* __restrict__ flags, const uint32_t* __restrict__ rpos,
+                             uint32_t epoch, uint32_t* __restrict__ touched,
+                             uint32_t* __restrict__ c_node, uint32_t* __restrict__ c_bf,
+                             uint32_t* __restrict__ c_be) {
+    const int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t v = bsrc[i];
+    if (flags[i]) {
+        const uint32_t r = rpos[i];
+        c_node[r] = v;
+        c_bf[r] = (uint32_t)i;
+        touched[v] = epoch;
+    }
+    if (i == n - 1 || bsrc[i + 1] != v) c_be[rpos[i] + flags[i] - 1] = (uint32_t)(i + 1);
+}
+
+// flags[i] = 1 for exactly one evicted position of every source node that is
+// not a batch node yet (the first to claim the node's mark)
+__global__ void k_evict_marks(const int32_t* __restrict__ e_src, int64_t n, uint32_t epoch,
+                              uint32_t* __restrict__ touched, uint32_t* __restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t v = (uint32_t)e_src[i];
+    uint32_t f = 0;
+    if (touched[v] != epoch && atomicExch(&touched[v], epoch) != epoch) f = 1;
+    flags[i] = f;
+}
+
+// jobs at base0 + base1 + pos[i] for flagged positions, node = nodes[i]
+// (identity when nodes is null), no batch run
+__global__ void k_flag_jobs(const uint32_t* __restrict__ flags, const uint32_t* __restrict__ pos,
+                            int64_t n, const int32_t* __restrict__ nodes,
+                            const uint32_t* __restrict__ base0, const uint32_t* __restrict__ base1,
+                            uint32_t* __restrict__ c_node, uint32_t* __restrict__ c_bf,
+                            uint32_t* __restrict__ c_be) {
+    const int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (i >= n || !flags[i]) return;
+    const uint32_t j = *base0 + (base1 ? *base1 : 0u) + pos[i];
+    c_node[j] = nodes ? (uint32_t)nodes[i] : (uint32_t)i;
+    c_bf[j] = 0;
+    c_be[j] = 0;
+}
+
+// nodes with live edges that no job covers yet
+__global__ void k_active_flags(const NodeRec* __restrict__ rec, int64_t V,
+                               const uint32_t* __restrict__ touched, uint32_t epoch,
+                               uint32_t* __restrict__ flags) {
+    const int64_t v = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (v < V) {
+        const NodeRec r = rec[v];
+        flags[v] = (r.ge > r.gb && touched[v] != epoch) ? 1u : 0u;
+    }
+}
+
+// ------------------------------------------------------------- jobs
+
+// Plan of every job: eviction of the node's groups older than cut, then the
+// kind, the written edge count and the slots a new segment needs.
+__global__ void k_job_setup(const uint32_t* __restrict__ c_node, const uint32_t* __restrict__ c_bf,
+                            const uint32_t* __restrict__ c_be, int64_t nj,
+                            const NodeRec* __restrict__ rec, const SegRec* __restrict__ seg,
+                            const GroupRec* __restrict__ ng, const int64_t* __restrict__ bts,
+                            int evicting, int64_t cut, int rewrite_all, uint32_t gen,
+                            Job* __restrict__ jobs, uint32_t* __restrict__ cnt,
+                            uint32_t* __restrict__ req_e, uint32_t* __restrict__ req_g,
+                            uint32_t* __restrict__ req_f) {
+    const int64_t j = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (j >= nj) return;
+    Job J{};
+    J.v = c_node[j];
+    J.bf = c_bf[j];
+    J.be = c_be[j];
+    const NodeRec r = rec[J.v];
+    uint32_t gb = r.gb;
+    const uint32_t ge = r.ge;
+    if (evicting && gb < ge && ng[gb].ts < cut) gb = lower_bound_groups(ng, gb, ge, cut);
+    J.ogb = gb;
+    J.oge = ge;
+    J.oe = r.ee;
+    J.ob = gb < ge ? ng[gb].first : r.ee;
+    const uint32_t ne = J.oe - J.ob;
+    J.t_last = ne ? r.t_last : INT64_MIN;
+    const uint32_t k = J.be - J.bf;
+    const SegRec sg = seg[J.v];
+    const bool has_seg = sg.gen == gen && sg.ecap > 0;
+    J.kind = JOB_EVICT;
+    J.e0 = sg.e0;
+    J.ecap = sg.ecap;
+    J.g0 = sg.g0;
+    J.gcode = sg.gcode;
+    J.f0 = sg.f0;
+    uint32_t c = 0, re = 0, rg = 0, rf = 0;
+    if ((k > 0 || rewrite_all) && ne + k > 0) {
+        const bool after = ne == 0 || k == 0 || bts[J.bf] >= J.t_last;
+        if (!rewrite_all && has_seg && ne > 0 && after &&
+            (uint64_t)J.oe + k <= (uint64_t)sg.e0 + sg.ecap &&
+            (uint64_t)ge + k <= (uint64_t)sg.g0 + seg_groups(sg.gcode)) {
+            J.kind = JOB_APPEND;
+            J.e_at = J.oe;
+            J.g_at = ge;
+            c = k;
+        } else if (!rewrite_all && has_seg && ne == 0 && k <= sg.ecap &&
+                   (uint64_t)k <= seg_groups(sg.gcode)) {
+            // nothing survives: the batch run restarts the node's own segment
+            J.kind = JOB_REWRITE;
+            J.e_at = sg.e0;
+            J.g_at = sg.g0;
+            c = k;
+        } else {
+            J.kind = JOB_REWRITE;
+            J.fresh = 1;
+            J.merge = (ne > 0 && k > 0 && !after) ? 1u : 0u;
+            J.ecap = edge_cap(ne + k);
+            J.gcode = group_code((uint64_t)(ge - gb) + k);
+            re = J.ecap;
+            rg = (uint32_t)seg_groups(J.gcode);
+            rf = fence_cap(rg);
+            c = ne + k;
+        }
+    }
+    jobs[j] = J;
+    cnt[j] = c;
+    req_e[j] = re;
+    req_g[j] = rg;
+    req_f[j] = rf;
+}
+
+// new segments at the pool tops plus the scanned requests
+__global__ void k_job_place(Job* __restrict__ jobs, int64_t nj, const uint32_t* __restrict__ e_off,
+                            const uint32_t* __restrict__ g_off, const uint32_t* __restrict__ f_off,
+                            uint32_t e_top, uint32_t g_top, uint32_t f_top) {
+    const int64_t j = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (j >= nj) return;
+    Job J = jobs[j];
+    if (!J.fresh) return;
+    J.e0 = e_top + e_off[j];
+    J.g0 = g_top + g_off[j];
+    J.f0 = f_top + f_off[j];
+    J.e_at = J.e0;
+    J.g_at = J.g0;
+    jobs[j] = J;
+}
+
+struct Elem {
+    int32_t dst;
+    int64_t ts;
+};
+
+// element i of job J's written run
+__device__ __forceinline__ Elem job_elem(const Job& J, uint32_t i, const int32_t* __restrict__ odst,
+                                         const int64_t* __restrict__ ots,
+                                         const int32_t* __restrict__ bdst,
+                                         const int64_t* __restrict__ bts) {
+    if (J.kind == JOB_APPEND) return Elem{bdst[J.bf + i], bts[J.bf + i]};
+    const uint32_t na = J.oe - J.ob, nb = J.be - J.bf;
+    if (!J.merge) {
+        if (i < na) return Elem{odst[J.ob + i], ots[J.ob + i]};
+        return Elem{bdst[J.bf + i - na], bts[J.bf + i - na]};
+    }
+    // stable merge, old first on equal timestamps: a = old elements among
+    // the first i outputs
+    uint32_t lo = i > nb ? i - nb : 0, hi = i < na ? i : na;
+    while (lo < hi) {
+        const uint32_t a = lo + ((hi - lo) >> 1);
+        if (ots[J.ob + a] <= bts[J.bf + (i - a - 1)]) lo = a + 1; else hi = a;
+    }
+    const uint32_t a = lo, b = i - lo;
+    if (a < na && (b >= nb || ots[J.ob + a] <= bts[J.bf + b]))
+        return Elem{odst[J.ob + a], ots[J.ob + a]};
+    return Elem{bdst[J.bf + b], bts[J.bf + b]};
+}
+
+// Write every job's run (NV_ITEMS consecutive outputs per thread) and flag
+// the outputs that start a group.
+__global__ void k_job_edges(const Job* __restrict__ jobs, const uint32_t* __restrict__ off,
+                            int64_t nj, int64_t total, const int32_t* __restrict__ odst,
+                            const int64_t* __restrict__ ots, const int32_t* __restrict__ bdst,
+                            const int64_t* __restrict__ bts, int32_t* __restrict__ ndst,
+                            int64_t* __restrict__ nts, uint32_t* __restrict__ oflag) {
+    const int64_t t0 = ((int64_t)blockIdx.x * T + threadIdx.x) * NV_ITEMS;
+    if (t0 >= total) return;
+    uint32_t j = job_of(off, (uint32_t)nj, (uint64_t)t0);
+    Job J = jobs[j];
+    uint32_t jb = off[j], je = off[j + 1];
+    uint32_t i = (uint32_t)(t0 - jb);
+    bool has_prev;
+    int64_t prev;
+    if (i > 0) {
+        has_prev = true;
+        prev = job_elem(J, i - 1, odst, ots, bdst, bts).ts;
+    } else {
+        has_prev = J.kind == JOB_APPEND;
+        prev = J.t_last;
+    }
+    for (int u = 0; u < NV_ITEMS; ++u) {
+        const int64_t t = t0 + u;
+        if (t >= total) break;
+        if ((uint64_t)t >= je) {
+            do {
+                ++j;
+                jb = off[j];
+                je = off[j + 1];
+            } while ((uint64_t)t >= je);
+            J = jobs[j];
+            i = 0;
+            has_prev = J.kind == JOB_APPEND;
+            prev = J.t_last;
+        }
+        const Elem e = job_elem(J, i, odst, ots, bdst, bts);
+        const uint32_t pos = J.e_at + i;
+        ndst[pos] = e.dst;
+        nts[pos] = e.ts;
+        oflag[t] = (!has_prev || e.ts != prev) ? 1u : 0u;
+        has_prev = true;
+        prev = e.ts;
+        ++i;
+    }
+}
+
+// group records of the flagged outputs; rank = exclusive scan of the flags
+__global__ void k_job_groups(const Job* __restrict__ jobs, const uint32_t* __restrict__ off,
+                             int64_t nj, int64_t total, const uint32_t* __restrict__ oflag,
+                             const uint32_t* __restrict__ rank, const int32_t* __restrict__ ndst,
+                             const int64_t* __restrict__ nts, GroupRec* __restrict__ ngd) {
+    const int64_t t = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (t >= total || !oflag[t]) return;
+    const uint32_t j = job_of(off, (uint32_t)nj, (uint64_t)t);
+    const Job J = jobs[j];
+    const uint32_t i = (uint32_t)(t - off[j]);
+    const uint32_t pos = J.e_at + i;
+    GroupRec g;
+    g.ts = nts[pos];
+    g.first = pos;
+    g.dst = ndst[pos];
+    ngd[J.g_at + (rank[t] - rank[off[j]])] = g;
+}
+
+// fence entries a job writes at level k: the new groups [from, to) of a
+// segment starting at g0 that land on the level's grid
+__device__ __forceinline__ uint64_t level_span(uint32_t g0, uint32_t from, uint32_t to, int k,
+                                               uint64_t* first) {
+    const uint64_t step = 1ull << (FENCE_LOG * k);
+    const uint64_t lo = ((uint64_t)(from - g0) + step - 1) >> (FENCE_LOG * k);
+    const uint64_t hi = ((uint64_t)(to - g0) + step - 1) >> (FENCE_LOG * k);
+    *first = lo;
+    return hi - lo;
+}
+
+// New node records (and segments) of the jobs, and the fence entries each
+// job writes: all of a new or restarted segment's fence, or the entries of
+// an append's new groups.
+__global__ void k_job_finish(const Job* __restrict__ jobs, const uint32_t* __restrict__ off,
+                             int64_t nj, const uint32_t* __restrict__ rank,
+                             const GroupRec* __restrict__ ngd, NodeRec* __restrict__ rec,
+                             SegRec* __restrict__ seg, uint32_t gen, uint32_t* __restrict__ fw) {
+    const int64_t j = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (j >= nj) return;
+    const Job J = jobs[j];
+    const uint32_t newg = rank[off[j + 1]] - rank[off[j]];
+    const uint32_t written = off[j + 1] - off[j];
+    NodeRec r = rec[J.v];
+    uint32_t f = 0;
+    if (J.kind == JOB_EVICT) {
+        r.gb = J.ogb;
+        if (r.gb >= r.ge) r = empty_rec();
+    } else {
+        const uint64_t cap = seg_groups(J.gcode);
+        if (J.kind == JOB_APPEND) {
+            r.gb = J.ogb;
+            r.ge = J.oge + newg;
+            r.ee = J.oe + written;
+            const int K = fence_levels(cap);
+            for (int k = 1; k <= K; ++k) {
+                uint64_t first;
+                f += (uint32_t)level_span(J.g0, J.oge, r.ge, k, &first);
+            }
+        } else {
+            r.gb = J.g0;
+            r.ge = J.g0 + newg;
+            r.ee = J.e_at + written;
+            f = fence_cap(cap);
+            if (J.fresh) {
+                SegRec s;
+                s.e0 = J.e0;
+                s.ecap = J.ecap;
+                s.g0 = J.g0;
+                s.gcode = J.gcode;
+                s.f0 = J.f0;
+                s.gen = gen;
+                s.pad0 = s.pad1 = 0;
+                seg[J.v] = s;
+            }
+        }
+        r.g0 = J.g0;
+        r.fence_off = J.f0;
+        r.lv = (uint32_t)fence_levels(r.ge - J.g0) | (J.gcode << 8);
+        r.t_last = ngd[r.ge - 1].ts;
+    }
+    rec[J.v] = r;
+    fw[j] = f;
+}
+
+// the fence entries of the jobs (grid-stride; total = foff[nj])
+__global__ void k_job_fence(const Job* __restrict__ jobs, const uint32_t* __restrict__ foff,
+                            int64_t nj, const NodeRec* __restrict__ rec,
+                            const GroupRec* __restrict__ ngd, int64_t* __restrict__ fence) {
+    const uint64_t total = foff[nj];
+    for (uint64_t t = (uint64_t)blockIdx.x * T + threadIdx.x; t < total;
+         t += (uint64_t)gridDim.x * T) {
+        const uint32_t j = job_of(foff, (uint32_t)nj, t);
+        const Job J = jobs[j];
+        const NodeRec r = rec[J.v];
+        const uint64_t cap = seg_groups(J.gcode);
+        const int K = fence_levels(cap);
+        uint64_t u = t - foff[j];
+        uint64_t base = 0;
+        for (int k = 1; k <= K; ++k) {
+            const uint32_t len = fence_level_len(cap, k);
+            if (J.kind == JOB_REWRITE) {
+                if (u < len) {
+                    const uint64_t g = (uint64_t)J.g0 + (u << (FENCE_LOG * k));
+                    fence[J.f0 + base + u] = g < r.ge ? ngd[g].ts : INT64_MAX;
+                    break;
+                }
+                u -= len;
+            } else {
+                uint64_t first;
+                const uint64_t c = level_span(J.g0, J.oge, r.ge, k, &first);
+                if (u < c) {
+                    const uint64_t i = first + u;
+                    fence[J.f0 + base + i] = ngd[J.g0 + (i << (FENCE_LOG * k))].ts;
+                    break;
+                }
+                u -= c;
+            }
+            base += len;
+        }
+    }
+}
+
+// ------------------------------------------------------------- export
+
+__global__ void k_node_counts(const NodeRec* __restrict__ rec, const GroupRec* __restrict__ ng,
+                              int64_t V, uint32_t* __restrict__ ecnt, uint32_t* __restrict__ gcnt) {
+    const int64_t v = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (v >= V) return;
+    const NodeRec r = rec[v];
+    const bool live = r.ge > r.gb;
+    if (ecnt) ecnt[v] = live ? r.ee - ng[r.gb].first : 0u;
+    if (gcnt) gcnt[v] = live ? r.ge - r.gb : 0u;
+}
+
+__global__ void k_widen_u32(const uint32_t* __restrict__ in, int64_t n, int64_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (i < n) out[i] = in[i];
+}
+
+// output edge p of the contiguous node view
+__global__ void k_export_edges(const uint32_t* __restrict__ ebeg, int64_t V, int64_t m,
+                               const NodeRec* __restrict__ rec, const GroupRec* __restrict__ ng,
+                               const int32_t* __restrict__ pdst, const int64_t* __restrict__ pts,
+                               int32_t* __restrict__ n_dst, int64_t* __restrict__ n_ts) {
+    const int64_t p = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (p >= m) return;
+    const uint32_t v = job_of(ebeg, (uint32_t)(V + 1), (uint64_t)p);
+    const NodeRec r = rec[v];
+    const uint32_t e = ng[r.gb].first + (uint32_t)(p - ebeg[v]);
+    if (n_dst) n_dst[p] = pdst[e];
+    if (n_ts) n_ts[p] = pts[e];
+}
+
+// output group q: its timestamp and the contiguous position of its first edge
+__global__ void k_export_groups(const uint32_t* __restrict__ gbeg, const uint32_t* __restrict__ ebeg,
+                                int64_t V, int64_t G, const NodeRec* __restrict__ rec,
+                                const GroupRec* __restrict__ ng, int64_t* __restrict__ n_gts,
+                                int64_t* __restrict__ n_goff, int64_t m) {
+    const int64_t q = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (q > G) return;
+    if (q == G) {
+        if (n_goff) n_goff[G] = m;
+        return;
+    }
+    const uint32_t v = job_of(gbeg, (uint32_t)(V + 1), (uint64_t)q);
+    const NodeRec r = rec[v];
+    const GroupRec g = ng[r.gb + (uint32_t)(q - gbeg[v])];
+    if (n_gts) n_gts[q] = g.ts;
+    if (n_goff) n_goff[q] = (int64_t)ebeg[v] + (g.first - ng[r.gb].first);
+}
+
+uint32_t* slot(tw_graph* g, int k) { return g->scal.as<uint32_t>() + k; }
+
+// scan of n job values into out (n + 1 entries: out[n] = total); the total
+// also lands in *total_slot when given
+hipError_t scan_jobs(const uint32_t* in, uint32_t* out, int64_t n, Workspace& ws, hipStream_t s) {
+    return scan_exclusive_u32(in, out, n, out + n, ws, s);
+}
+
+tw_status run_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool rewrite_all,
+                   Error& err);
+
+}  // namespace
+
+tw_status nv_reset(tw_graph* g, Error& err) {
+    const int64_t V = g->V;
+    TW_HIP(ensure(g->rec, sizeof(NodeRec) * V));
+    if (!g->seg.p) {
+        // generation 0 marks every segment void (pool_gen starts above 0)
+        TW_HIP(ensure(g->seg, sizeof(SegRec) * V));
+        const int64_t words = V * (int64_t)(sizeof(SegRec) / sizeof(uint32_t));
+        hipLaunchKernelGGL(k_zero_u32, grid_for(words), dim3(T), 0, g->stream,
+                           g->seg.as<uint32_t>(), words);
+    }
+    if (!g->touched.p) {
+        TW_HIP(ensure(g->touched, sizeof(uint32_t) * V));
+        hipLaunchKernelGGL(k_zero_u32, grid_for(V), dim3(T), 0, g->stream,
+                           g->touched.as<uint32_t>(), V);
+    }
+    hipLaunchKernelGGL(k_empty_rec, grid_for(V), dim3(T), 0, g->stream, g->rec.as<NodeRec>(), V);
+    TW_HIP(hipGetLastError());
+    g->pe_top = g->pg_top = g->pf_top = 0;
+    ++g->pool_gen;  // every segment is void
+    g->T = 0;
+    g->adj_ready = false;
+    return TW_OK;
+}
+
+tw_status nv_collect(tw_graph* g, const int32_t* q_src, const int32_t* q_dst, const int64_t* q_ts,
+                     int64_t kept, int64_t ev_from, int64_t ev_n, Error& err) {
+    hipStream_t s = g->stream;
+    if (++g->epoch == 0) {  // wrapped: clear the marks
+        hipLaunchKernelGGL(k_zero_u32, grid_for(g->V), dim3(T), 0, s, g->touched.as<uint32_t>(),
+                           (int64_t)g->V);
+        g->epoch = 1;
+    }
+    // a node is one job at most, so V + 1 entries hold any job list (also
+    // the full rewrite's, which appends to this one)
+    const int64_t cand = (int64_t)g->V + 1;
+    TW_HIP(ensure(g->c_node, sizeof(uint32_t) * cand));
+    TW_HIP(ensure(g->c_bf, sizeof(uint32_t) * cand));
+    TW_HIP(ensure(g->c_be, sizeof(uint32_t) * cand));
+    const int64_t nf = std::max(kept, ev_n);
+    TW_HIP(ensure(g->flags, sizeof(uint32_t) * (nf + 1)));
+    TW_HIP(ensure(g->idx, sizeof(uint32_t) * (nf + 1)));
+    uint32_t* flags = g->flags.as<uint32_t>();
+    uint32_t* pos = g->idx.as<uint32_t>();
+    uint32_t* sl_runs = slot(g, SLOT_U32_RUNS);
+    uint32_t* sl_ev = slot(g, SLOT_U32_EV_NODES);
+    TW_HIP(ensure(g->bs_src, sizeof(uint32_t) * (kept + 1)));
+    TW_HIP(ensure(g->bs_dst, sizeof(int32_t) * (kept + 1)));
+    TW_HIP(ensure(g->bs_ts, sizeof(int64_t) * (kept + 1)));
+    if (kept > 0) {
+        uint32_t* bsrc = g->bs_src.as<uint32_t>();
+        TW_HIP(radix_sort_u32_kv(reinterpret_cast<const uint32_t*>(q_src),
+                                 reinterpret_cast<const uint32_t*>(q_dst),
+                                 reinterpret_cast<const uint64_t*>(q_ts), bsrc,
+                                 g->bs_dst.as<uint32_t>(), g->bs_ts.as<uint64_t>(), kept, 0,
+                                 bits_for((uint64_t)(g->V - 1)), g->ws, s));
+        hipLaunchKernelGGL(k_run_flags, grid_for(kept), dim3(T), 0, s, bsrc, kept, flags);
+        TW_HIP(scan_exclusive_u32(flags, pos, kept, sl_runs, g->ws, s));
+        hipLaunchKernelGGL(k_batch_jobs, grid_for(kept), dim3(T), 0, s, bsrc, kept, flags, pos,
+                           g->epoch, g->touched.as<uint32_t>(), g->c_node.as<uint32_t>(),
+                           g->c_bf.as<uint32_t>(), g->c_be.as<uint32_t>());
+    } else {
+        TW_HIP(scan_exclusive_u32(nullptr, nullptr, 0, sl_runs, g->ws, s));
+    }
+    if (ev_n > 0) {
+        const int32_t* esrc = g->e_src.as<int32_t>() + ev_from;
+        hipLaunchKernelGGL(k_evict_marks, grid_for(ev_n), dim3(T), 0, s, esrc, ev_n, g->epoch,
+                           g->touched.as<uint32_t>(), flags);
+        TW_HIP(scan_exclusive_u32(flags, pos, ev_n, sl_ev, g->ws, s));
+        hipLaunchKernelGGL(k_flag_jobs, grid_for(ev_n), dim3(T), 0, s, flags, pos, ev_n, esrc,
+                           sl_runs, nullptr, g->c_node.as<uint32_t>(), g->c_bf.as<uint32_t>(),
+                           g->c_be.as<uint32_t>());
+    } else {
+        TW_HIP(scan_exclusive_u32(nullptr, nullptr, 0, sl_ev, g->ws, s));
+    }
+    TW_HIP(hipGetLastError());
+    uint32_t h[2];
+    TW_HIP(hipMemcpyAsync(h, sl_runs, sizeof(h), hipMemcpyDeviceToHost, s));
+    TW_HIP(hipStreamSynchronize(s));
+    g->T = (int64_t)h[0] + h[1];
+    return TW_OK;
+}
+
+namespace {
+
+tw_status ensure_jobs(tw_graph* g, int64_t nj, Error& err) {
+    TW_HIP(ensure(g->jobs, sizeof(Job) * (nj + 1)));
+    DevBuf* b[] = {&g->j_cnt, &g->j_off, &g->j_re, &g->j_rg, &g->j_rf, &g->j_fw};
+    for (DevBuf* p : b) TW_HIP(ensure(*p, sizeof(uint32_t) * (nj + 2)));
+    return TW_OK;
+}
+
+// Plan nj jobs and scan their outputs and requests; returns the totals
+// {written edges, edge slots, group slots, fence entries}. Synchronises.
+tw_status plan_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool rewrite_all,
+                    uint32_t gen, uint64_t tot[4], Error& err) {
+    hipStream_t s = g->stream;
+    if (ensure_jobs(g, nj, err) != TW_OK) return err.code;
+    hipLaunchKernelGGL(k_job_setup, grid_for(nj), dim3(T), 0, s, g->c_node.as<uint32_t>(),
+                       g->c_bf.as<uint32_t>(), g->c_be.as<uint32_t>(), nj, g->rec.as<NodeRec>(),
+                       g->seg.as<SegRec>(), g->ng.as<GroupRec>(), g->bs_ts.as<int64_t>(),
+                       evicting ? 1 : 0, cut, rewrite_all ? 1 : 0, gen, g->jobs.as<Job>(),
+                       g->j_cnt.as<uint32_t>(), g->j_re.as<uint32_t>(), g->j_rg.as<uint32_t>(),
+                       g->j_rf.as<uint32_t>());
+    TW_HIP(hipGetLastError());
+    // requests are scanned in place: j_re / j_rg / j_rf become offsets
+    TW_HIP(scan_jobs(g->j_cnt.as<uint32_t>(), g->j_off.as<uint32_t>(), nj, g->ws, s));
+    uint32_t* sl = slot(g, SLOT_U32_REQ_E);
+    TW_HIP(scan_exclusive_u32(g->j_re.as<uint32_t>(), g->j_re.as<uint32_t>(), nj, sl, g->ws, s));
+    TW_HIP(scan_exclusive_u32(g->j_rg.as<uint32_t>(), g->j_rg.as<uint32_t>(), nj, sl + 1, g->ws, s));
+    TW_HIP(scan_exclusive_u32(g->j_rf.as<uint32_t>(), g->j_rf.as<uint32_t>(), nj, sl + 2, g->ws, s));
+    uint32_t h[4];
+    TW_HIP(hipMemcpyAsync(&h[0], g->j_off.as<uint32_t>() + nj, sizeof(uint32_t),
+                          hipMemcpyDeviceToHost, s));
+    TW_HIP(hipMemcpyAsync(&h[1], sl, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    TW_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < 4; ++i) tot[i] = h[i];
+    return TW_OK;
+}
+
+// Run planned jobs: reads runs from the source pools (sdst, sts, sng),
+// writes into the destination pools (the same ones unless rewriting all).
+tw_status execute_jobs(tw_graph* g, int64_t nj, uint64_t out, const int32_t* sdst,
+                       const int64_t* sts, int32_t* ddst, int64_t* dts, GroupRec* dng,
+                       int64_t* dfence, uint32_t gen, Error& err) {
+    hipStream_t s = g->stream;
+    Job* jobs = g->jobs.as<Job>();
+    const uint32_t* off = g->j_off.as<uint32_t>();
+    TW_HIP(ensure(g->o_flag, sizeof(uint32_t) * (out + 1)));
+    TW_HIP(ensure(g->o_rank, sizeof(uint32_t) * (out + 2)));
+    uint32_t* oflag = g->o_flag.as<uint32_t>();
+    uint32_t* rank = g->o_rank.as<uint32_t>();
+    if (out > 0)
+        hipLaunchKernelGGL(k_job_edges, grid_for((int64_t)out, NV_ITEMS), dim3(T), 0, s, jobs, off,
+                           nj, (int64_t)out, sdst, sts, g->bs_dst.as<int32_t>(),
+                           g->bs_ts.as<int64_t>(), ddst, dts, oflag);
+    TW_HIP(scan_exclusive_u32(oflag, rank, (int64_t)out, rank + out, g->ws, s));
+    if (out > 0)
+        hipLaunchKernelGGL(k_job_groups, grid_for((int64_t)out), dim3(T), 0, s, jobs, off, nj,
+                           (int64_t)out, oflag, rank, ddst, dts, dng);
+    hipLaunchKernelGGL(k_job_finish, grid_for(nj), dim3(T), 0, s, jobs, off, nj, rank, dng,
+                       g->rec.as<NodeRec>(), g->seg.as<SegRec>(), gen, g->j_fw.as<uint32_t>());
+    TW_HIP(scan_jobs(g->j_fw.as<uint32_t>(), g->j_fw.as<uint32_t>(), nj, g->ws, s));
+    hipLaunchKernelGGL(k_job_fence, dim3(FENCE_GRID), dim3(T), 0, s, jobs, g->j_fw.as<uint32_t>(),
+                       nj, g->rec.as<NodeRec>(), dng, dfence);
+    TW_HIP(hipGetLastError());
+    return TW_OK;
+}
+
+tw_status run_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool rewrite_all,
+                   Error& err) {
+    hipStream_t s = g->stream;
+    uint64_t tot[4];
+    const uint32_t gen = rewrite_all ? g->pool_gen + 1 : g->pool_gen;
+    if (plan_jobs(g, nj, evicting, cut, rewrite_all, gen, tot, err) != TW_OK) return err.code;
+    if (!rewrite_all) {
+        if (g->pe_top + (int64_t)tot[1] > g->pe_cap || g->pg_top + (int64_t)tot[2] > g->pg_cap ||
+            g->pf_top + (int64_t)tot[3] > g->pf_cap) {
+            // no room: list every other active node and rewrite all of them
+            const int64_t V = g->V;
+            TW_HIP(ensure(g->v_flags, sizeof(uint32_t) * (V + 1)));
+            TW_HIP(ensure(g->v_pos, sizeof(uint32_t) * (V + 1)));
+            uint32_t* sl_act = slot(g, SLOT_U32_ACTIVE);
+            hipLaunchKernelGGL(k_active_flags, grid_for(V), dim3(T), 0, s, g->rec.as<NodeRec>(), V,
+                               g->touched.as<uint32_t>(), g->epoch, g->v_flags.as<uint32_t>());
+            TW_HIP(scan_exclusive_u32(g->v_flags.as<uint32_t>(), g->v_pos.as<uint32_t>(), V,
+                                      sl_act, g->ws, s));
+            uint32_t na = 0;
+            TW_HIP(hipMemcpyAsync(&na, sl_act, sizeof(na), hipMemcpyDeviceToHost, s));
+            TW_HIP(hipStreamSynchronize(s));
+            const int64_t all = nj + na;  // <= V: the lists hold V + 1 entries
+            hipLaunchKernelGGL(k_flag_jobs, grid_for(V), dim3(T), 0, s, g->v_flags.as<uint32_t>(),
+                               g->v_pos.as<uint32_t>(), V, nullptr, slot(g, SLOT_U32_RUNS),
+                               slot(g, SLOT_U32_EV_NODES), g->c_node.as<uint32_t>(),
+                               g->c_bf.as<uint32_t>(), g->c_be.as<uint32_t>());
+            TW_HIP(hipGetLastError());
+            return run_jobs(g, all, evicting, cut, true, err);
+        }
+        hipLaunchKernelGGL(k_job_place, grid_for(nj), dim3(T), 0, s, g->jobs.as<Job>(), nj,
+                           g->j_re.as<uint32_t>(), g->j_rg.as<uint32_t>(), g->j_rf.as<uint32_t>(),
+                           (uint32_t)g->pe_top, (uint32_t)g->pg_top, (uint32_t)g->pf_top);
+        if (execute_jobs(g, nj, tot[0], g->n_dst.as<int32_t>(), g->n_ts.as<int64_t>(),
+                         g->n_dst.as<int32_t>(), g->n_ts.as<int64_t>(), g->ng.as<GroupRec>(),
+                         g->fence.as<int64_t>(), gen, err) != TW_OK)
+            return err.code;
+        g->pe_top += (int64_t)tot[1];
+        g->pg_top += (int64_t)tot[2];
+        g->pf_top += (int64_t)tot[3];
+        return TW_OK;
+    }
+    // fresh pools with room for as much again
+    const int64_t lim = (int64_t)UINT32_MAX - 1;
+    const int64_t ce = std::min<int64_t>(std::max<int64_t>(2 * (int64_t)tot[1], 1024), lim);
+    const int64_t cg = std::min<int64_t>(std::max<int64_t>(2 * (int64_t)tot[2], 1024), lim);
+    const int64_t cf = std::min<int64_t>(std::max<int64_t>(2 * (int64_t)tot[3], 1024), lim);
+    if ((int64_t)tot[1] > lim / 2 || (int64_t)tot[2] > lim / 2 || (int64_t)tot[3] > lim / 2) {
+        err = Error{TW_ENOMEM, "node view: pools would exceed 2^32 slots"};
+        return err.code;
+    }
+    TW_HIP(ensure(g->an_dst, sizeof(int32_t) * ce));
+    TW_HIP(ensure(g->an_ts, sizeof(int64_t) * ce));
+    TW_HIP(ensure(g->ang, sizeof(GroupRec) * cg));
+    TW_HIP(ensure(g->afence, sizeof(int64_t) * cf));
+    hipLaunchKernelGGL(k_job_place, grid_for(nj), dim3(T), 0, s, g->jobs.as<Job>(), nj,
+                       g->j_re.as<uint32_t>(), g->j_rg.as<uint32_t>(), g->j_rf.as<uint32_t>(), 0u,
+                       0u, 0u);
+    if (execute_jobs(g, nj, tot[0], g->n_dst.as<int32_t>(), g->n_ts.as<int64_t>(),
+                     g->an_dst.as<int32_t>(), g->an_ts.as<int64_t>(), g->ang.as<GroupRec>(),
+                     g->afence.as<int64_t>(), gen, err) != TW_OK)
+        return err.code;
+    std::swap(g->n_dst, g->an_dst);
+    std::swap(g->n_ts, g->an_ts);
+    std::swap(g->ng, g->ang);
+    std::swap(g->fence, g->afence);
+    g->pe_cap = (int64_t)(g->n_dst.bytes / sizeof(int32_t));
+    g->pe_cap = std::min<int64_t>(g->pe_cap, (int64_t)(g->n_ts.bytes / sizeof(int64_t)));
+    g->pg_cap = (int64_t)(g->ng.bytes / sizeof(GroupRec));
+    g->pf_cap = (int64_t)(g->fence.bytes / sizeof(int64_t));
+    g->pe_cap = std::min(g->pe_cap, lim);
+    g->pg_cap = std::min(g->pg_cap, lim);
+    g->pf_cap = std::min(g->pf_cap, lim);
+    g->pe_top = (int64_t)tot[1];
+    g->pg_top = (int64_t)tot[2];
+    g->pf_top = (int64_t)tot[3];
+    g->pool_gen = gen;
+    return TW_OK;
+}
+
+}  // namespace
+
+tw_status nv_apply(tw_graph* g, bool evicting, int64_t cut, Error& err) {
+    if (g->T == 0) return TW_OK;
+    if (run_jobs(g, g->T, evicting, cut, false, err) != TW_OK) return err.code;
+    g->adj_ready = false;
+    return TW_OK;
+}
+
+tw_status nv_group_count(tw_graph* g, int64_t* gn, Error& err) {
+    hipStream_t s = g->stream;
+    const int64_t V = g->V;
+    TW_HIP(ensure(g->v_flags, sizeof(uint32_t) * (V + 1)));
+    TW_HIP(ensure(g->v_pos, sizeof(uint32_t) * (V + 1)));
+    hipLaunchKernelGGL(k_node_counts, grid_for(V), dim3(T), 0, s, g->rec.as<NodeRec>(),
+                       g->ng.as<GroupRec>(), V, nullptr, g->v_flags.as<uint32_t>());
+    uint32_t* sl = slot(g, SLOT_U32_GN);
+    TW_HIP(scan_exclusive_u32(g->v_flags.as<uint32_t>(), g->v_pos.as<uint32_t>(), V, sl, g->ws, s));
+    uint32_t h = 0;
+    TW_HIP(hipMemcpyAsync(&h, sl, sizeof(h), hipMemcpyDeviceToHost, s));
+    TW_HIP(hipStreamSynchronize(s));
+    *gn = h;
+    return TW_OK;
+}
+
+tw_status nv_export(tw_graph* g, int32_t* n_dst, int64_t* n_ts, int64_t* n_gts, int64_t* n_goff,
+                    int64_t* n_ebeg, int64_t* n_gbeg, Error& err) {
+    hipStream_t s = g->stream;
+    const int64_t V = g->V, m = g->m;
+    TW_HIP(ensure(g->v_flags, sizeof(uint32_t) * (V + 1)));
+    TW_HIP(ensure(g->v_pos, sizeof(uint32_t) * (V + 1)));
+    TW_HIP(ensure(g->idx, sizeof(uint32_t) * (V + 2)));
+    TW_HIP(ensure(g->flags, sizeof(uint32_t) * (V + 2)));
+    uint32_t* ecnt = g->v_flags.as<uint32_t>();
+    uint32_t* gcnt = g->v_pos.as<uint32_t>();
+    uint32_t* ebeg = g->idx.as<uint32_t>();
+    uint32_t* gbeg = g->flags.as<uint32_t>();
+    hipLaunchKernelGGL(k_node_counts, grid_for(V), dim3(T), 0, s, g->rec.as<NodeRec>(),
+                       g->ng.as<GroupRec>(), V, ecnt, gcnt);
+    TW_HIP(scan_exclusive_u32(ecnt, ebeg, V, ebeg + V, g->ws, s));
+    TW_HIP(scan_exclusive_u32(gcnt, gbeg, V, gbeg + V, g->ws, s));
+    uint32_t G = 0;
+    TW_HIP(hipMemcpyAsync(&G, gbeg + V, sizeof(G), hipMemcpyDeviceToHost, s));
+    TW_HIP(hipStreamSynchronize(s));
+    if (n_ebeg) hipLaunchKernelGGL(k_widen_u32, grid_for(V + 1), dim3(T), 0, s, ebeg, V + 1, n_ebeg);
+    if (n_gbeg) hipLaunchKernelGGL(k_widen_u32, grid_for(V + 1), dim3(T), 0, s, gbeg, V + 1, n_gbeg);
+    if ((n_dst || n_ts) && m > 0)
+        hipLaunchKernelGGL(k_export_edges, grid_for(m), dim3(T), 0, s, ebeg, V, m,
+                           g->rec.as<NodeRec>(), g->ng.as<GroupRec>(), g->n_dst.as<int32_t>(),
+                           g->n_ts.as<int64_t>(), n_dst, n_ts);
+    if (n_gts || n_goff)
+        hipLaunchKernelGGL(k_export_groups, grid_for((int64_t)G + 1), dim3(T), 0, s, gbeg, ebeg, V,
+                           (int64_t)G, g->rec.as<NodeRec>(), g->ng.as<GroupRec>(), n_gts, n_goff, m);
+    TW_HIP(hipGetLastError());
+    return TW_OK;
+}
+
+}  // namespace tw

@@ -137,7 +137,6 @@ __global__ void k_flag_reduce(const uint32_t* __restrict__ flags, const int64_t*
 __global__ void k_flag_scatter(const uint32_t* __restrict__ flags, const int64_t* __restrict__ ts,
                                int64_t n, const uint32_t* __restrict__ part, uint32_t pos_base,
                                int64_t* __restrict__ g_ts, uint32_t* __restrict__ g_off,
-                               uint2* __restrict__ g_od, const int32_t* __restrict__ dst,
                                const uint32_t* total) {
     __shared__ uint32_t tile[SCAN_TILE];
     int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
@@ -166,14 +165,10 @@ __global__ void k_flag_scatter(const uint32_t* __restrict__ flags, const int64_t
         const uint32_t gk = tile[k];
         if (i < n && gk != UINT32_MAX) {
             g_ts[gk] = ts[i];
-            if (g_od) g_od[gk] = make_uint2(pos_base + (uint32_t)i, (uint32_t)dst[i]);
-            else g_off[gk] = pos_base + (uint32_t)i;
+            g_off[gk] = pos_base + (uint32_t)i;
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if (g_od) g_od[*total] = make_uint2(pos_base + (uint32_t)n, 0u);
-        else g_off[*total] = pos_base + (uint32_t)n;
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) g_off[*total] = pos_base + (uint32_t)n;
 }
 
 // ------------------------------------------------------------ radix sort
@@ -358,8 +353,8 @@ hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint
 }
 
 hipError_t group_starts(const uint32_t* flags, const int64_t* ts, int64_t n, uint32_t pos_base,
-                        int64_t* g_ts, uint32_t* g_off, uint2* g_od, const int32_t* dst,
-                        uint32_t* total, Workspace& ws, hipStream_t s) {
+                        int64_t* g_ts, uint32_t* g_off, uint32_t* total, Workspace& ws,
+                        hipStream_t s) {
     const int64_t nb = std::max<int64_t>(ceil_div(n, SCAN_TILE), 1);
     hipError_t e = ensure(ws.scan_part, sizeof(uint32_t) * (nb + 1));
     if (e != hipSuccess) return e;
@@ -367,7 +362,7 @@ hipError_t group_starts(const uint32_t* flags, const int64_t* ts, int64_t n, uin
     hipLaunchKernelGGL(k_flag_reduce, dim3(nb), dim3(SCAN_THREADS), 0, s, flags, ts, n, part);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, part, nb, total);
     hipLaunchKernelGGL(k_flag_scatter, dim3(nb), dim3(SCAN_THREADS), 0, s, flags, ts, n, part,
-                       pos_base, g_ts, g_off, g_od, dst, total);
+                       pos_base, g_ts, g_off, total);
     return hipGetLastError();
 }
 

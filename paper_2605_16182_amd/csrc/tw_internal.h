@@ -7,6 +7,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "tw.h"
 
@@ -14,25 +15,39 @@ namespace tw {
 
 constexpr int64_t TS_NONE = INT64_MIN;
 
-// One record per node, 32 bytes so a hop reads all of it with one
-// contiguous load: the node's range of (node, timestamp) groups [gb, ge),
-// its edge range [eb, ee) in the node view, where its fence levels start in
-// the fence array and how many there are, and the last group timestamp
-// (t_last lets a hop that cannot continue stop without searching).
+// One (node, timestamp) group of the node view, 16 bytes: the timestamp,
+// the pool position of the group's first edge and that edge's destination
+// (a one-edge group needs no edge load). Eight records fill one 128-byte
+// line, so a fence leaf window is one line.
+struct alignas(16) GroupRec {
+    int64_t ts;
+    uint32_t first;
+    int32_t dst;
+};
+
+// One record per node, 32 bytes, read with one load per hop. A node's edges
+// and groups live in a segment of the edge and group pools: the live groups
+// are [gb, ge), the live edges end at ee (they start at the first edge of
+// group gb). g0 is the segment's first group (a multiple of FENCE_FAN), the
+// origin of the node's fence; fence_off is where the fence starts in the
+// fence pool; lv = levels in use | (capacity code << 8), the segment holding
+// FENCE_FAN << code groups. t_last is the last live timestamp (INT64_MIN for
+// a node without edges), so a hop that cannot continue stops after this load.
 struct alignas(32) NodeRec {
-    uint32_t gb, ge, eb, ee;
-    uint32_t fence_off, levels;
+    uint32_t gb, ge, g0, ee;
+    uint32_t fence_off, lv;
     int64_t t_last;
 };
 
-// Fence index. A node's groups [gb, ge) split into a head [gb, a0), where
-// a0 is the first group index that is a multiple of FENCE_FAN, and a body
-// [a0, ge). When the body has more than FENCE_FAN groups, fence level k
-// (k = 1..K) holds the timestamps of groups a0 + i FENCE_FAN^k, padded to a
-// multiple of FENCE_FAN entries with INT64_MAX, stored top level (K) first;
-// K is the smallest level with at most FENCE_FAN entries. A search reads one
-// FENCE_FAN-entry window (one aligned 128-byte line) per level and one
-// aligned window of the group timestamps.
+// Fence index. The fence of a segment with capacity C groups has levels
+// k = 1..K(C); level k holds the timestamps of groups g0 + i FENCE_FAN^k, i <
+// ceil(C / FENCE_FAN^k), padded to a multiple of FENCE_FAN entries; entries
+// of groups not written yet hold INT64_MAX. Level 1 is stored first. A
+// search over the groups [g0, ge) starts at level K(ge - g0), the smallest
+// level with at most FENCE_FAN entries in use, reads one FENCE_FAN-entry
+// window (64 bytes, aligned) per level and one aligned window of group
+// records. Groups evicted from the front of the segment stay in place until
+// the segment is rewritten; their timestamps precede every live one.
 constexpr int FENCE_FAN = 8;
 constexpr int FENCE_LOG = 3;
 
@@ -40,46 +55,55 @@ constexpr int FENCE_LOG = 3;
 constexpr int FENCE_MAX_LEVELS = (32 + FENCE_LOG - 1) / FENCE_LOG + 1;
 static_assert((1 << FENCE_LOG) == FENCE_FAN, "FENCE_FAN must be 2^FENCE_LOG");
 
-struct FenceGeom {
-    uint32_t a0;      // first aligned group of the body
-    uint32_t levels;  // K (0: no fence, the node is scanned directly)
-    uint32_t size;    // fence entries
-};
-
-__host__ __device__ inline FenceGeom fence_geometry(uint32_t gb, uint32_t ge) {
-    FenceGeom f;
-    f.a0 = (gb + FENCE_FAN - 1) & ~(uint32_t)(FENCE_FAN - 1);
-    f.levels = 0;
-    f.size = 0;
-    const uint64_t body = ge > f.a0 ? (uint64_t)(ge - f.a0) : 0;
-    if (body > (uint64_t)FENCE_FAN) {
-        uint64_t n = body;
-        do {
-            n = (n + FENCE_FAN - 1) / FENCE_FAN;
-            ++f.levels;
-            f.size += (uint32_t)((n + FENCE_FAN - 1) / FENCE_FAN * FENCE_FAN);
-        } while (n > (uint64_t)FENCE_FAN);
+// levels needed for n groups: 0 when n <= FENCE_FAN
+__host__ __device__ inline int fence_levels(uint64_t n) {
+    int k = 0;
+    while (n > (uint64_t)FENCE_FAN) {
+        n = (n + FENCE_FAN - 1) >> FENCE_LOG;
+        ++k;
     }
-    return f;
+    return k;
+}
+
+// entries stored for level k (k >= 1) of a segment of cap groups
+__host__ __device__ inline uint32_t fence_level_len(uint64_t cap, int k) {
+    const uint64_t n = (cap + (1ull << (FENCE_LOG * k)) - 1) >> (FENCE_LOG * k);
+    return (uint32_t)((n + FENCE_FAN - 1) / FENCE_FAN * FENCE_FAN);
+}
+
+// total fence entries of a segment of cap groups
+__host__ __device__ inline uint32_t fence_cap(uint64_t cap) {
+    uint32_t s = 0;
+    const int K = fence_levels(cap);
+    for (int k = 1; k <= K; ++k) s += fence_level_len(cap, k);
+    return s;
+}
+
+__host__ __device__ inline uint64_t seg_groups(uint32_t code) {
+    return (uint64_t)FENCE_FAN << code;
 }
 
 // Slots of the graph's device scalar buffer (256 bytes): u32 indices
-// (SLOT_U32_*) and int64 indices (SLOT_I64_*).
+// (SLOT_U32_*) and int64 indices (SLOT_I64_*, byte offset 8 k).
 constexpr int SLOT_I64_MINMAX = 0;     // batch min / max timestamp (ordered u64) in [0], [1]
 constexpr int SLOT_U32_GROUPS = 4;     // groups counted by the last timestamp-group scan
-constexpr int SLOT_U32_GN = 5;         // node-timestamp groups
 constexpr int SLOT_U32_UNSORTED = 6;   // batch not in timestamp order
-constexpr int SLOT_U32_FENCE = 7;      // fence entries
 constexpr int SLOT_I64_SUMMARY = 4;    // [4] t_min, [5] t_max of the window
 constexpr int SLOT_U32_KEPT = 24;      // kept batch records / late-prefix length
 constexpr int SLOT_U32_EVICTED = 25;   // evicted window records
 constexpr int SLOT_I64_FIRST_KEPT = 13;
 constexpr int SLOT_U32_N_LIVE = 28;    // live walks (cooperative dispatch)
 constexpr int SLOT_U32_GG_EVICTED = 29;
-constexpr int SLOT_U32_RUNS = 30;      // source runs of the batch
-constexpr int SLOT_U32_UNION = 31;     // union of active nodes and batch sources
-constexpr int SLOT_U32_ACTIVE = 32;    // active nodes
-constexpr int SLOT_U32_BIG = 33;       // queued large fences
+constexpr int SLOT_U32_RUNS = 30;      // source runs of the batch (node-view jobs)
+constexpr int SLOT_U32_EV_NODES = 31;  // nodes touched only by eviction
+constexpr int SLOT_U32_ACTIVE = 32;    // other active nodes (full rewrite)
+constexpr int SLOT_U32_OUT = 33;       // node-view edges written by the jobs
+constexpr int SLOT_U32_REQ_E = 34;     // edge slots requested by new segments
+constexpr int SLOT_U32_REQ_G = 35;     // group slots requested
+constexpr int SLOT_U32_REQ_F = 36;     // fence entries requested
+constexpr int SLOT_U32_FENCE_W = 37;   // fence entries written by the jobs
+constexpr int SLOT_U32_GN = 38;        // node-view groups (counted on demand)
+constexpr int SLOT_U32_EXP_E = 39;     // export: edges
 constexpr int SCALAR_BYTES = 256;
 
 // A grow-only device allocation.
@@ -118,10 +142,9 @@ hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint
 // != 0, or with flags null, ts[i] != ts[i-1]) gives g_ts[k] = ts[i] and
 // g_off[k] = pos_base + i; g_off[total] = pos_base + n; total (device) = the
 // number of groups. n may be 0.
-// With g_od non-null, g_od[k] = {pos_base + i, dst[i]} replaces g_off.
 hipError_t group_starts(const uint32_t* flags, const int64_t* ts, int64_t n, uint32_t pos_base,
-                        int64_t* g_ts, uint32_t* g_off, uint2* g_od, const int32_t* dst,
-                        uint32_t* total, Workspace& ws, hipStream_t s);
+                        int64_t* g_ts, uint32_t* g_off, uint32_t* total, Workspace& ws,
+                        hipStream_t s);
 
 // Stable LSD radix sort of (keys, vals) by bits [bit_lo, bit_hi) of the key.
 // vals may be null. Result ends in keys / vals. The alternate buffers come
@@ -165,7 +188,7 @@ struct tw_graph {
     // [e_base, e_base + m) of the edge-store buffers (capacity e_cap); its
     // timestamp groups occupy [gg_base, gg_base + Gg) of gg_ts / gg_off, whose
     // offsets are edge-store buffer positions.
-    int64_t m = 0, Gg = 0, Gn = 0;
+    int64_t m = 0, Gg = 0;
     int64_t e_base = 0, e_cap = 0, gg_base = 0;
     int64_t t_min = 0, t_max = 0;
     tw_ingest_info last{};
@@ -173,24 +196,27 @@ struct tw_graph {
     // timestamp view (the edge store) and its alternate for merges
     tw::DevBuf e_src, e_dst, e_ts, a_src, a_dst, a_ts;
     tw::DevBuf gg_ts, gg_off;          // global timestamp groups
-    tw::DevBuf n_dst, n_ts;            // node-and-timestamp view
-    tw::DevBuf an_src, an_dst, an_ts;  // its alternate for the merge
+
+    // node view: per-node segments of the edge pool (n_dst, n_ts), the
+    // group pool (ng, GroupRec) and the fence pool (fence). New segments are
+    // taken from the top of each pool; when a pool is full every active node
+    // is rewritten into the alternate pools (an_*), which then swap in.
+    tw::DevBuf n_dst, n_ts, ng, fence;
+    tw::DevBuf an_dst, an_ts, ang, afence;
+    int64_t pe_top = 0, pe_cap = 0, pg_top = 0, pg_cap = 0, pf_top = 0, pf_cap = 0;
+    uint32_t pool_gen = 1;             // segments of older generations are void
+    tw::DevBuf rec;                    // NodeRec[V]
+    tw::DevBuf seg;                    // SegRec[V] (ingest only)
+    tw::DevBuf touched;                // u32[V]: epoch of the last ingest that touched v
+    uint32_t epoch = 0;
+    // node-view jobs (one per touched node) and their temporaries
     tw::DevBuf bs_src, bs_dst, bs_ts;  // batch sorted by source
     tw::DevBuf q_src, q_dst, q_ts;     // batch sorted by timestamp (unsorted input)
-    tw::DevBuf plan, neb_v;            // per-node merge plan / merged offset (union nodes)
-    tw::DevBuf act0, act1;             // sorted active nodes (current, scratch)
-    int64_t A = 0;                     // active nodes
-    tw::DevBuf a_eb, a_cnt, a_gb, a_ge, a_foff;   // per active node
-    tw::DevBuf gflags;                 // (node, timestamp) group starts of the node view
-    tw::DevBuf it_keys, it_pay, it_skeys, it_spay;  // union items
-    tw::DevBuf u_flags, u_pos, u_node, u_cnt, u_neb;  // union nodes
-    tw::DevBuf ng_ts, ngo;             // its (node, timestamp) groups: timestamps,
-                                       // {first edge, destination of the first edge}
-    tw::DevBuf n_src;                  // source of each node-view edge (build temp)
-    tw::DevBuf fence;                  // fence levels of nodes with many groups
-    int64_t fence_len = 0;
-    tw::DevBuf rec;                    // NodeRec[V]
-    tw::DevBuf adj;                    // per-node dst sorted ascending (node2vec)
+    tw::DevBuf c_node, c_bf, c_be;     // job candidates: node, batch run
+    tw::DevBuf jobs, j_cnt, j_off, j_re, j_rg, j_rf, j_fw;
+    tw::DevBuf o_flag, o_rank;         // per written edge: group start, rank
+    int64_t T = 0;                     // jobs of the last update
+    tw::DevBuf adj, adj_rng;           // node2vec: per-node sorted destinations
     bool adj_ready = false;
 
     // cooperative dispatch: per-walk state, live list, sort buffers
@@ -201,12 +227,45 @@ struct tw_graph {
     // batch staging
     tw::DevBuf b_src, b_dst, b_ts, b_keys, b_vals, b_flags;
     tw::DevBuf flags, idx;             // per-edge temporaries
+    tw::DevBuf v_flags, v_pos;         // per-node temporaries
     tw::DevBuf err;                    // device error flags (uint32)
     tw::DevBuf scal;                   // device scalars
     tw::Workspace ws;
+
+    // every device allocation of the graph
+    std::vector<tw::DevBuf*> buffers() {
+        return {&e_src, &e_dst, &e_ts, &a_src, &a_dst, &a_ts, &gg_ts, &gg_off,
+                &n_dst, &n_ts, &ng, &fence, &an_dst, &an_ts, &ang, &afence,
+                &rec, &seg, &touched, &bs_src, &bs_dst, &bs_ts, &q_src, &q_dst, &q_ts,
+                &c_node, &c_bf, &c_be, &jobs, &j_cnt, &j_off, &j_re, &j_rg, &j_rf, &j_fw,
+                &o_flag, &o_rank, &adj, &adj_rng,
+                &c_node0, &c_walk0, &c_t0, &c_node1, &c_walk1, &c_t1, &c_node2, &c_walk2,
+                &c_t2, &c_prev, &c_flags, &c_pos,
+                &b_src, &b_dst, &b_ts, &b_keys, &b_vals, &b_flags, &flags, &idx, &v_flags,
+                &v_pos, &err, &scal, &ws.scan_part, &ws.hist, &ws.keys_alt, &ws.vals_alt,
+                &ws.v64_alt, &ws.misc};
+    }
 };
 
 namespace tw {
+
+// nodeview.hip
+// Sort the kept batch (timestamp order) by source and list the node-view
+// jobs: the batch's source nodes, then the nodes that lose edges to the
+// eviction of window positions [ev_from, ev_from + ev_n) of the timestamp
+// view, which must still hold the evicted records.
+tw_status nv_collect(tw_graph* g, const int32_t* q_src, const int32_t* q_dst, const int64_t* q_ts,
+                     int64_t kept, int64_t ev_from, int64_t ev_n, Error& err);
+// Apply the collected jobs: evict edges older than cut (when evicting),
+// append or rewrite every job node's run, its groups, fence and record.
+tw_status nv_apply(tw_graph* g, bool evicting, int64_t cut, Error& err);
+// Empty node view (every record empty, pools reset).
+tw_status nv_reset(tw_graph* g, Error& err);
+// Distinct (node, timestamp) groups of the window. Synchronises.
+tw_status nv_group_count(tw_graph* g, int64_t* gn, Error& err);
+// The node view in its canonical contiguous form (any pointer may be null).
+tw_status nv_export(tw_graph* g, int32_t* n_dst, int64_t* n_ts, int64_t* n_gts, int64_t* n_goff,
+                    int64_t* n_ebeg, int64_t* n_gbeg, Error& err);
 
 // index.hip
 tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int64_t* ts,

@@ -21,11 +21,11 @@ struct WalkArgs {
     // node view
     const int32_t* n_dst;
     const int64_t* n_ts;
-    const int64_t* ng_ts;
-    const uint2* ngo;
+    const GroupRec* ng;
     const NodeRec* rec;
     const int64_t* fence;
     const int32_t* adj;
+    const uint2* adj_rng;
     int32_t V;
     // parameters
     int64_t num_walks;
@@ -88,7 +88,7 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, int64_t w, u
     if (a.L == 1) return st;
     const NodeRec r = a.rec[v0];
     if (r.gb == r.ge) return st;
-    Pick p = pick_node(a.ng_ts, a.ngo, a.n_dst, a.n_ts, r.gb, r.ge, r.ee, a.start_kind,
+    Pick p = pick_node(a.ng, a.n_dst, a.n_ts, r.gb, r.ge, r.ee, a.start_kind,
                        a.start_tau, r.t_last, d0);
     const int32_t nx = p.dst;
     out_n[1] = nx;
@@ -108,20 +108,20 @@ __device__ __forceinline__ bool hop_pick(const WalkArgs& a, const NodeRec& r, ui
                                          int32_t& nx) {
     if (a.hop_kind != TW_NODE2VEC) {
         const Draw d = philox(id, hop, 0, a.seed);
-        p = pick_node(a.ng_ts, a.ngo, a.n_dst, a.n_ts, gc, r.ge, r.ee, a.hop_kind, a.hop_tau,
+        p = pick_node(a.ng, a.n_dst, a.n_ts, gc, r.ge, r.ee, a.hop_kind, a.hop_tau,
                       r.t_last, d);
         nx = p.dst;
         return true;
     }
-    const NodeRec rp = a.rec[prev];
+    const uint2 rp = a.adj_rng[prev];  // prev has edges: prev -> cur is one
     for (uint32_t trial = 0; trial < N2V_MAX_TRIALS; ++trial) {
         const Draw d = philox(id, hop, trial, a.seed);
-        p = pick_node(a.ng_ts, a.ngo, a.n_dst, a.n_ts, gc, r.ge, r.ee, TW_EXPONENTIAL, a.hop_tau,
+        p = pick_node(a.ng, a.n_dst, a.n_ts, gc, r.ge, r.ee, TW_EXPONENTIAL, a.hop_tau,
                       r.t_last, d);
         nx = p.dst;
         double beta;
         if (nx == prev) beta = a.inv_p;
-        else if (sorted_contains(a.adj, rp.eb, rp.ee, nx)) beta = 1.0;
+        else if (sorted_contains(a.adj, rp.x, rp.y, nx)) beta = 1.0;
         else beta = a.inv_q;
         if (unit_closed_open(d.x2) * a.beta_max < beta) return true;
     }
@@ -135,26 +135,37 @@ __device__ __forceinline__ void finish_walk(const WalkArgs& a, int64_t w, int32_
     a.len[w] = len;
 }
 
-// Fill every output slot with the padding values (-1 nodes, INT64_MIN
-// timestamps) with wide, fully coalesced stores; the walk kernels then write
-// only the slots their walks reach.
+// Padding values (-1 nodes, INT64_MIN timestamps) for the output slots
+// [b, e), written by threads tid, tid + stride, ... with 16-byte stores where
+// the arrays are 16-byte aligned.
+__device__ __forceinline__ void fill_span(int32_t* __restrict__ nodes, int64_t* __restrict__ ts,
+                                          int64_t b, int64_t e, int64_t tid, int64_t stride) {
+    if (b >= e) return;
+    // nodes: scalar head up to a 16-byte boundary, int4 body, scalar tail
+    const int64_t nb = std::min<int64_t>(
+        e, b + (int64_t)(((16 - ((uintptr_t)(nodes + b) & 15)) & 15) / 4));
+    for (int64_t i = b + tid; i < nb; i += stride) nodes[i] = -1;
+    const int64_t nv = (e - nb) / 4;
+    int4* nv4 = reinterpret_cast<int4*>(nodes + nb);
+    for (int64_t i = tid; i < nv; i += stride) nv4[i] = make_int4(-1, -1, -1, -1);
+    for (int64_t i = nb + 4 * nv + tid; i < e; i += stride) nodes[i] = -1;
+    const int64_t tb = std::min<int64_t>(
+        e, b + (int64_t)(((16 - ((uintptr_t)(ts + b) & 15)) & 15) / 8));
+    for (int64_t i = b + tid; i < tb; i += stride) ts[i] = TS_NONE;
+    const int64_t tv = (e - tb) / 2;
+    longlong2* tv2 = reinterpret_cast<longlong2*>(ts + tb);
+    for (int64_t i = tid; i < tv; i += stride) tv2[i] = make_longlong2(TS_NONE, TS_NONE);
+    for (int64_t i = tb + 2 * tv + tid; i < e; i += stride) ts[i] = TS_NONE;
+}
+
+// Fill every output slot with the padding values, fully coalesced; the walk
+// kernels then write only the slots their walks reach. (Padding inside the
+// walk kernel, block by block, measured slower: the stores compete with the
+// walks' dependent gathers.)
 __global__ void k_fill_outputs(int32_t* __restrict__ nodes, int64_t* __restrict__ ts,
                                int64_t n) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    // nodes: 16-byte stores where the array is 16-byte aligned
-    const int64_t head_n = ((16 - ((uintptr_t)nodes & 15)) & 15) / 4;
-    for (int64_t i = tid; i < head_n && i < n; i += stride) nodes[i] = -1;
-    const int64_t nv = (n - head_n) / 4;
-    int4* nv4 = reinterpret_cast<int4*>(nodes + head_n);
-    for (int64_t i = tid; i < nv; i += stride) nv4[i] = make_int4(-1, -1, -1, -1);
-    for (int64_t i = head_n + 4 * nv + tid; i < n; i += stride) nodes[i] = -1;
-    const int64_t head_t = ((16 - ((uintptr_t)ts & 15)) & 15) / 8;
-    for (int64_t i = tid; i < head_t && i < n; i += stride) ts[i] = TS_NONE;
-    const int64_t tv = (n - head_t) / 2;
-    longlong2* tv2 = reinterpret_cast<longlong2*>(ts + head_t);
-    for (int64_t i = tid; i < tv; i += stride) tv2[i] = make_longlong2(TS_NONE, TS_NONE);
-    for (int64_t i = head_t + 2 * tv + tid; i < n; i += stride) ts[i] = TS_NONE;
+    fill_span(nodes, ts, 0, n, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+              (int64_t)gridDim.x * blockDim.x);
 }
 
 // One full walk per thread: the full-walk baseline (Sec. "The Full-Walk
@@ -172,7 +183,7 @@ __global__ void __launch_bounds__(WALK_THREADS) k_walk_full(const WalkArgs a) {
         for (uint64_t hop = 1; len < a.L; ++hop) {
             const NodeRec r = a.rec[cur];
             if (tcur >= r.t_last) break;  // Gamma_t(cur) is empty
-            const uint32_t gc = fence_search(a.ng_ts, a.fence, r, tcur, nullptr, 0);
+            const uint32_t gc = fence_search(a.ng, a.fence, r, tcur, nullptr, 0, 0);
             Pick p;
             int32_t nx;
             if (!hop_pick(a, r, gc, id, hop, prev, p, nx)) break;
@@ -257,20 +268,35 @@ k_hop_coop(const WalkArgs a, Live cur, Live nxt, int32_t* __restrict__ prev_of, 
 #pragma unroll
     for (int k = 1; k < WALK_THREADS / 64; ++k) wg_uniform &= wave_node[k] == wave_node[0];
 
-    // stage the top of the node's fence: the whole panel for a uniform
-    // workgroup, a quarter of it per uniform wavefront otherwise
+    // stage the top levels of the node's fence: the whole panel for a
+    // uniform workgroup, a quarter of it per uniform wavefront otherwise.
+    // Levels are stored bottom-up, so levels K down to some m are one
+    // contiguous range.
     const int64_t* my_panel = nullptr;
+    uint64_t my_base = 0;
     uint32_t my_cap = 0;
     if (wg_uniform || wave_uniform) {
         const int32_t node = wg_uniform ? wave_node[0] : v0;
         const NodeRec r = a.rec[node];
         const uint32_t slice = wg_uniform ? panel_cap : panel_cap / (WALK_THREADS / 64);
         int64_t* dst = wg_uniform ? panel : panel + wave * slice;
-        const uint32_t size = fence_geometry(r.gb, r.ge).size;
-        my_cap = size < slice ? size : slice;
+        const int K = (int)(r.lv & 0xffu);
+        if (K > 0) {
+            const uint64_t cap = seg_groups(r.lv >> 8);
+            uint64_t top = r.fence_off;  // end of level K
+            for (int k = 1; k <= K; ++k) top += fence_level_len(cap, k);
+            uint64_t from = top;
+            for (int k = K; k >= 1; --k) {
+                const uint32_t len = fence_level_len(cap, k);
+                if (top - (from - len) > slice) break;
+                from -= len;
+            }
+            my_base = from;
+            my_cap = (uint32_t)(top - from);
+        }
         const int first = wg_uniform ? threadIdx.x : lane;
         const int stride = wg_uniform ? WALK_THREADS : 64;
-        for (uint32_t j = first; j < my_cap; j += stride) dst[j] = a.fence[r.fence_off + j];
+        for (uint32_t j = first; j < my_cap; j += stride) dst[j] = a.fence[my_base + j];
         my_panel = dst;
     }
     __syncthreads();
@@ -283,7 +309,7 @@ k_hop_coop(const WalkArgs a, Live cur, Live nxt, int32_t* __restrict__ prev_of, 
     const int32_t len = (int32_t)hop + 1;  // nodes written before this hop
     bool live = false;
     if (tcur < r.t_last) {
-        const uint32_t gc = fence_search(a.ng_ts, a.fence, r, tcur, my_panel, my_cap);
+        const uint32_t gc = fence_search(a.ng, a.fence, r, tcur, my_panel, my_base, my_cap);
         Pick p;
         int32_t nx;
         const int32_t prev = a.hop_kind == TW_NODE2VEC ? prev_of[w] : 0;
@@ -407,8 +433,8 @@ tw_status sample_walks(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int
     a.Gg = (uint32_t)g->Gg;
     a.n_dst = g->n_dst.as<int32_t>();
     a.n_ts = g->n_ts.as<int64_t>();
-    a.ng_ts = g->ng_ts.as<int64_t>();
-    a.ngo = g->ngo.as<uint2>();
+    a.ng = g->ng.as<GroupRec>();
+    a.adj_rng = g->adj_rng.as<uint2>();
     a.rec = g->rec.as<NodeRec>();
     a.fence = g->fence.as<int64_t>();
     a.adj = g->adj.as<int32_t>();

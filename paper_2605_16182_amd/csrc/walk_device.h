@@ -90,77 +90,70 @@ __device__ __forceinline__ uint32_t pick_exponential(uint32_t n, double lam, uin
     return (uint32_t)f;
 }
 
-// first index in [lo, hi) with ts[index] > t (hi when none)
-__device__ __forceinline__ uint32_t upper_bound_ts(const int64_t* __restrict__ ts, uint32_t lo,
-                                                   uint32_t hi, int64_t t) {
-    while (lo < hi) {
-        uint32_t mid = lo + ((hi - lo) >> 1);
-        if (ts[mid] <= t) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
-// count of ts[lo, hi) that are <= t (ts ascending): a few entries are
-// counted directly, longer ranges by binary search
-__device__ __forceinline__ uint32_t count_le(const int64_t* __restrict__ ts, uint32_t lo,
+// count of the groups [lo, hi) (timestamps ascending) whose timestamp is
+// <= t: a few are counted directly, longer ranges by binary search
+__device__ __forceinline__ uint32_t count_le(const GroupRec* __restrict__ ng, uint32_t lo,
                                              uint32_t hi, int64_t t) {
     if (hi - lo <= 4) {
         uint32_t c = 0;
-        for (uint32_t j = lo; j < hi; ++j) c += (ts[j] <= t);
+        for (uint32_t j = lo; j < hi; ++j) c += (ng[j].ts <= t);
         return c;
     }
     uint32_t a = lo, b = hi;
     while (a < b) {
         const uint32_t mid = a + ((b - a) >> 1);
-        if (ts[mid] <= t) a = mid + 1; else b = mid;
+        if (ng[mid].ts <= t) a = mid + 1; else b = mid;
     }
     return a - lo;
 }
 
-// Gamma lookup (Sec. "Dual-Index Organization": the first timestamp group of
-// the node strictly after t) through the node's fence: one aligned
-// FENCE_FAN-entry window per level, each one aligned 64-byte sector, then one
-// aligned window of the node's group timestamps. Requires t < r.t_last, so
-// the result is below r.ge. Returns the absolute group index. panel
-// (nullable) holds the first panel_len entries of the node's fence (its top
-// levels) in LDS; windows inside it are read from there.
-__device__ __forceinline__ uint32_t fence_search(const int64_t* __restrict__ gts,
+// Gamma lookup (Sec. "Dual-Index Organization": the node's first timestamp
+// group strictly after t) through the node's fence: one aligned
+// FENCE_FAN-entry window per level from the top level in use, then one
+// aligned window of FENCE_FAN group records (one 128-byte line). Requires
+// t < r.t_last, so the result is below r.ge, and t at or after the window's
+// first timestamp, so groups evicted from the front of the segment count as
+// earlier. Returns the absolute group index. panel (nullable) holds fence
+// entries [panel_base, panel_base + panel_len) in LDS; windows inside it are
+// read from there.
+__device__ __forceinline__ uint32_t fence_search(const GroupRec* __restrict__ ng,
                                                  const int64_t* __restrict__ fence,
                                                  const NodeRec& r, int64_t t,
-                                                 const int64_t* panel, uint32_t panel_len) {
-    if (r.levels == 0) return r.gb + count_le(gts, r.gb, r.ge, t);
-    const uint32_t a0 = (r.gb + FENCE_FAN - 1) & ~(uint32_t)(FENCE_FAN - 1);
-    const uint32_t body = r.ge - a0;
-    uint64_t lo = 0, off = r.fence_off;
-    for (int k = (int)r.levels; k >= 1; --k) {
-        const uint64_t rel = off - r.fence_off + lo;
+                                                 const int64_t* panel, uint64_t panel_base,
+                                                 uint32_t panel_len) {
+    const int K = (int)(r.lv & 0xffu);
+    if (K == 0) return r.gb + count_le(ng, r.gb, r.ge, t);
+    const uint64_t cap = seg_groups(r.lv >> 8);
+    uint64_t off = r.fence_off;  // start of level K
+    for (int k = 1; k < K; ++k) off += fence_level_len(cap, k);
+    uint64_t lo = 0;
+    for (int k = K; k >= 1; --k) {
+        const uint64_t at = off + lo;
         const longlong2* win = reinterpret_cast<const longlong2*>(
-            rel + FENCE_FAN <= panel_len ? panel + rel : fence + off + lo);
+            at >= panel_base && at + FENCE_FAN <= panel_base + panel_len ? panel + (at - panel_base)
+                                                                          : fence + at);
         uint32_t c = 0;
 #pragma unroll
         for (int j = 0; j < FENCE_FAN / 2; ++j) {
             const longlong2 v = win[j];
             c += (v.x <= t) + (v.y <= t);
         }
-        // only possible at the top level: t precedes the body
-        if (c == 0) return r.gb + count_le(gts, r.gb, a0, t);
+        // only possible at the top level: t precedes the segment
+        if (c == 0) return r.gb;
         lo = (lo + c - 1) * FENCE_FAN;
-        const uint32_t sh = FENCE_LOG * (uint32_t)k;
-        const uint64_t nk = ((uint64_t)body + (1ull << sh) - 1) >> sh;
-        off += (nk + FENCE_FAN - 1) / FENCE_FAN * FENCE_FAN;
+        if (k > 1) off -= fence_level_len(cap, k - 1);
     }
+    const uint32_t body = r.ge - r.g0;
     uint32_t c = 0;
     if (lo + FENCE_FAN <= body) {
-        const longlong2* win = reinterpret_cast<const longlong2*>(gts + a0 + lo);
+        const GroupRec* w = ng + r.g0 + lo;
 #pragma unroll
-        for (int j = 0; j < FENCE_FAN / 2; ++j) {
-            const longlong2 v = win[j];
-            c += (v.x <= t) + (v.y <= t);
-        }
+        for (int j = 0; j < FENCE_FAN; ++j) c += (w[j].ts <= t);
     } else {
-        c = count_le(gts, a0 + (uint32_t)lo, r.ge, t);
+        c = count_le(ng, r.g0 + (uint32_t)lo, r.ge, t);
     }
-    return a0 + (uint32_t)lo + c;
+    const uint32_t res = r.g0 + (uint32_t)lo + c;
+    return res < r.gb ? r.gb : res;
 }
 
 // is w among the sorted values adj[lo, hi)?
@@ -184,31 +177,29 @@ __device__ __forceinline__ uint32_t pick_group(uint32_t n, int kind, double tau,
 
 // A pick in the node view among the groups [gc, ge) of a node whose edges
 // end at `end`: uniform over the edges, or biased over the groups and then
-// uniform inside the group. The destination of a group's first edge is
-// stored with the group, so a one-edge group needs no edge load.
+// uniform inside the group. A group record carries the destination of the
+// group's first edge, so a one-edge group needs no edge load.
 struct Pick {
     int32_t dst;
     int64_t t;
 };
 
-__device__ __forceinline__ Pick pick_node(const int64_t* __restrict__ gts,
-                                          const uint2* __restrict__ ngo,
+__device__ __forceinline__ Pick pick_node(const GroupRec* __restrict__ ng,
                                           const int32_t* __restrict__ n_dst,
                                           const int64_t* __restrict__ n_ts, uint32_t gc,
                                           uint32_t ge, uint32_t end, int kind, double tau,
                                           int64_t t_last, const Draw& d) {
     if (kind == TW_UNIFORM) {
-        const uint32_t c = ngo[gc].x;
+        const uint32_t c = ng[gc].first;
         const uint32_t e = c + (uint32_t)scale_u64(d.x0, end - c);
         return Pick{n_dst[e], n_ts[e]};
     }
     const uint32_t n = ge - gc;
-    const uint32_t k = gc + pick_group(n, kind, tau, n > 1 ? gts[gc] : 0, t_last, d.x0);
-    const uint2 a = ngo[k];
-    const uint32_t size = ngo[k + 1].x - a.x;
-    const int32_t dst =
-        size == 1 ? (int32_t)a.y : n_dst[a.x + (uint32_t)scale_u64(d.x1, size)];
-    return Pick{dst, gts[k]};
+    const uint32_t k = gc + pick_group(n, kind, tau, n > 1 ? ng[gc].ts : 0, t_last, d.x0);
+    const GroupRec a = ng[k];
+    const uint32_t size = (k + 1 < ge ? ng[k + 1].first : end) - a.first;
+    const int32_t dst = size == 1 ? a.dst : n_dst[a.first + (uint32_t)scale_u64(d.x1, size)];
+    return Pick{dst, a.ts};
 }
 
 // The edge-store position picked among the window's Gg timestamp groups.
