@@ -36,10 +36,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="single", choices=["single", "tiny", "stream"])
+    ap.add_argument("--workload", default="single", choices=["single", "tiny", "stream", "mixed"])
     ap.add_argument("--batches", type=int, default=0,
                     help="stream workload: number of 10M-edge batches (0 = the whole stream)")
-    ap.add_argument("--dispatch", default="auto", choices=["auto", "full_walk", "coop"])
+    ap.add_argument("--dispatch", default="auto", choices=["auto", "full_walk", "coop", "queue"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
     return ap.parse_args()
@@ -137,10 +137,20 @@ def walk_bytes(walks, hops, max_len, start_bias, hop_bias):
     return walks * start * SECTOR + hops * per_hop * SECTOR + walks * (12 * max_len + 4)
 
 
-def ingest_bytes(b, m_old, m_new, V):
-    """Algorithmic bytes of one ingest: read the batch (16 B/edge), one
-    read+write sort pass (32 B/edge), read the old and write the new window in
-    both views (28 B/edge), and the node table (4 B/node)."""
+def ingest_bytes(b_in, kept, evicted, jobs):
+    """Algorithmic bytes of one incremental ingest: read the batch (16 B per
+    input record), one read+write pass to order the kept records by source
+    (32 B), append them to the timestamp view with its group records (16 + 12
+    B) and to their nodes' runs in the node view with group records (12 + 16
+    B), read the sources of the evicted records (4 B), and read and write the
+    record of every node whose run changed (64 B)."""
+    return 16 * b_in + 88 * kept + 4 * evicted + 64 * jobs
+
+
+def rebuild_bytes(b, m_old, m_new, V):
+    """Bytes of an ingest that rebuilds both views from scratch: read the
+    batch, one sort pass, read the old and write the new window in both
+    views (28 B per edge), the node table (4 B per node)."""
     return 16 * b + 32 * b + 28 * (m_old + m_new) + 4 * V
 
 
@@ -239,6 +249,7 @@ def run_stream(args, torch, tw, w, dev, gather_rate, copy_bw):
     g = tw.Graph(spec.num_nodes, directed=spec.directed, window=w["window"])
     hops_dev = torch.zeros(nb, dtype=torch.int64, device=dev)
     m_dev = []
+    per_batch = []  # (accepted, evicted, node-view jobs, compaction) of every ingest
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(nb)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -246,6 +257,8 @@ def run_stream(args, torch, tw, w, dev, gather_rate, copy_bw):
         e = evs[b]
         e[0].record()
         info = g.ingest_batch(s, d, t)
+        st = g.index_stats()  # host counters of the ingest just done
+        per_batch.append((info["accepted"], info["evicted"], st["jobs"], st["full_rewrite"]))
         e[1].record()
         g.evict_before(info["t_max"] - w["window"])
         e[2].record()
@@ -264,7 +277,9 @@ def run_stream(args, torch, tw, w, dev, gather_rate, copy_bw):
     ss = slice(nb // 5, nb) if nb >= 5 else slice(0, nb)
     per_hop = 3 if w["hop_bias"] == "uniform" else 4
     m_ss = float(np.mean(m_dev[ss]))
-    ib = ingest_bytes(B, m_ss, m_ss, spec.num_nodes)
+    pb = np.array(per_batch, dtype=np.float64)[ss]
+    ib = ingest_bytes(B, float(pb[:, 0].mean()), float(pb[:, 1].mean()), float(pb[:, 2].mean()))
+    rb = rebuild_bytes(B, m_ss, m_ss, spec.num_nodes)
     roof_ing = ib / copy_bw * 1e3 if copy_bw else None
     roof_walk = float(np.mean(hops[ss])) / (gather_rate / per_hop) * 1e3 if gather_rate else None
     meas = float(np.mean(ing[ss] + ev[ss] + wk[ss]))
@@ -285,17 +300,95 @@ def run_stream(args, torch, tw, w, dev, gather_rate, copy_bw):
             "walk_ms": float(np.mean(wk[ss])), "hops_per_batch": float(np.mean(hops[ss])),
             "ingest_edges_per_s": B / (float(np.mean(ing[ss])) * 1e-3),
             "walk_hops_per_s": float(np.mean(hops[ss])) / (float(np.mean(wk[ss])) * 1e-3),
+            "node_view_jobs": float(pb[:, 2].mean()), "evicted": float(pb[:, 1].mean()),
+            "compactions": int(pb[:, 3].sum()),
         },
         "roofline": {"bound": "hbm", "ingest_roof_ms": roof_ing, "walk_roof_ms": roof_walk,
                      "measured_ms": meas,
                      "frac": ((roof_ing + roof_walk) / meas) if roof_ing and roof_walk else None,
                      "ingest_algorithmic_bytes": ib, "copy_GBps_measured": copy_bw / 1e9,
                      "random_sectors_per_s": gather_rate},
+        # the same measurement against an ingest that rebuilds both views
+        "roofline_rebuild_model": {
+            "ingest_roof_ms": rb / copy_bw * 1e3 if copy_bw else None,
+            "ingest_bytes": rb,
+            "frac": ((rb / copy_bw * 1e3 + roof_walk) / meas) if copy_bw and roof_walk else None},
     }
     g.close()
     if not args.no_cpu_baseline:
         print("# oracle baseline ...", file=sys.stderr, flush=True)
         res["cpu_baseline"] = stream_cpu_baseline(w, 3, float(np.mean(hops[ss])))
+    print(json.dumps(res), flush=True)
+
+
+def run_mixed(args, torch, tw, w, dev, gather_rate):
+    """Batched mixed walks: one persistent work-queue launch of walks with
+    lengths uniform in [min_len, max_len] and six hop biases (walk id mod 6)
+    on an undirected power-law graph, against the same batch with one thread
+    per walk and no queue."""
+    import synth
+    spec = w["stream"]
+    src, dst, ts = spec.all()
+    tau = float(w["tau_frac"] * int(ts.max() - ts.min()))
+    d_src, d_dst, d_ts = (torch.from_numpy(a).to(dev) for a in (src, dst, ts))
+    g = tw.Graph(spec.num_nodes, directed=spec.directed, window=w["window"])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.ingest_batch(d_src, d_dst, d_ts)
+    e1.record()
+    torch.cuda.synchronize()
+    ingest_ms = e0.elapsed_time(e1)
+    W, L = w["walks"], w["max_len"]
+    lims = torch.from_numpy(synth.walk_lengths(4, W, w["min_len"], L)).to(dev)
+    biases = synth.mixed_biases(tau)
+    rows = g.row_offsets(lims)
+    out = (torch.empty(rows[1], dtype=torch.int32, device=dev),
+           torch.empty(rows[1], dtype=torch.int64, device=dev),
+           torch.empty(W, dtype=torch.int32, device=dev))
+    kw = dict(max_lens=lims, seed=42, ragged=True, rows=rows, out=out)
+    res_d = {}
+    hops = None
+    for disp in ("full_walk", "queue"):
+        for _ in range(max(args.warmup, 1)):
+            g.sample_walks_batch(W, L, biases, dispatch=disp, **kw)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a, b in evs:
+            a.record()
+            g.sample_walks_batch(W, L, biases, dispatch=disp, **kw)
+            b.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        h = int((out[2].to(torch.int64) - 1).clamp_min(0).sum().item())
+        assert hops is None or h == hops, "dispatches gave different walks"
+        hops = h
+        ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        res_d[disp] = {"walk_ms": ms, "walk_hops_per_s": hops / (ms * 1e-3),
+                       "ms_per_step": wall * 1e3 / args.steps}
+    g.sync()
+    q = res_d["queue"]
+    roof = gather_rate / 4 if gather_rate else None
+    res = {
+        "metric": METRIC, "value": q["walk_hops_per_s"], "unit": "hops/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": q["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64+f64", "data": "synthetic",
+        "config": describe("mixed", w, tau) | {
+            "min_len": w["min_len"], "hop_biases": [b[0] if b[0] != "node2vec" else
+                                                    f"node2vec({b[2]},{b[3]})" for b in biases],
+            "layout": "ragged rows"},
+        "dispatch": "queue",
+        "hops_per_step": hops,
+        "batched_vs_plain": res_d,
+        "ingest_ms": ingest_ms,
+        "ingest_edges_per_s": spec.num_edges * (1 if spec.directed else 2) / (ingest_ms * 1e-3),
+        "gather_roofline": {"random_sectors_per_s": gather_rate, "sectors_per_hop": 4,
+                            "hops_per_s_roof": roof,
+                            "frac": q["walk_hops_per_s"] / roof if roof else None},
+    }
+    g.close()
     print(json.dumps(res), flush=True)
 
 
@@ -312,6 +405,9 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     w = synth.workload(args.workload)
+    if args.workload == "mixed":
+        gather_rate, _ = (0.0, 0.0) if args.no_probe else probe_rates(torch, dev)
+        return run_mixed(args, torch, tw, w, dev, gather_rate)
     if args.workload == "stream":
         gather_rate, copy_bw = (0.0, 0.0) if args.no_probe else probe_rates(torch, dev)
         return run_stream(args, torch, tw, w, dev, gather_rate, copy_bw)
@@ -393,7 +489,8 @@ def main():
         compare[disp] = {"walk_ms": ms, "walk_hops_per_s": hops / (ms * 1e-3)}
 
     wb = walk_bytes(W, hops, L, w["start_bias"], w["hop_bias"])
-    ib = ingest_bytes(spec.num_edges, 0, m_active, spec.num_nodes)
+    st = g.index_stats()
+    ib = ingest_bytes(spec.num_edges, m_active, 0, st["jobs"])
     walk_gbs = wb / (walk_ms * 1e-3) / 1e9
     ingest_gbs = ib / (ingest_ms * 1e-3) / 1e9
     per_hop_sectors = 3 if w["hop_bias"] == "uniform" else 4

@@ -70,12 +70,19 @@ typedef enum { TW_START_EDGE = 0, TW_START_NODE = 1 } tw_start_mode;
  *  TW_DISPATCH_FULL_WALK: one thread carries a walk through all its hops.
  *  TW_DISPATCH_COOP: per-step regrouping of live walks by current node and
  *    dispatch to a thread, a wavefront or a workgroup per node.
- *  TW_DISPATCH_AUTO: the library's choice. */
+ *  TW_DISPATCH_QUEUE: one persistent launch; each lane of a wavefront runs
+ *    one walk at a time and takes the next walk id from a device work queue
+ *    when its walk ends, so lanes stay busy when walks end at different hops.
+ *  TW_DISPATCH_AUTO: the library's choice (tw_autotune can set it). */
 typedef enum {
     TW_DISPATCH_AUTO = 0,
     TW_DISPATCH_FULL_WALK = 1,
-    TW_DISPATCH_COOP = 2
+    TW_DISPATCH_COOP = 2,
+    TW_DISPATCH_QUEUE = 3
 } tw_dispatch;
+
+/* Most hop biases one batched launch can mix. */
+#define TW_MAX_BIASES 8
 
 typedef struct {
     int32_t kind; /* tw_bias_kind */
@@ -102,6 +109,36 @@ typedef struct {
     int32_t dispatch;            /* tw_dispatch */
 } tw_walk_params;
 
+/*
+ * A batch of walks of uneven lengths and mixed hop biases, run as one
+ * persistent launch with a device work queue (TW_DISPATCH_QUEUE). Walk i has
+ * RNG id walk_id_base + i, length limit d_max_len[i] (or max_len), hop bias
+ * hop_biases[d_bias[i]] (or hop_biases[(walk_id_base + i) mod num_biases]),
+ * and writes its nodes and timestamps at d_row[i] (or i * max_len). A walk's
+ * result is the one tw_sample_walks gives it with the same seed, id, start
+ * and bias, cut to its length limit (the RNG is keyed by walk, hop and
+ * trial, so a shorter limit only truncates).
+ */
+typedef struct {
+    int64_t num_walks;           /* >= 0 */
+    int32_t max_len;             /* row width when d_row is NULL; >= every limit, >= 1 */
+    const int32_t* d_max_len;    /* num_walks limits in [1, max_len], or NULL */
+    int32_t num_biases;          /* 1..TW_MAX_BIASES */
+    tw_bias hop_biases[TW_MAX_BIASES];
+    const uint8_t* d_bias;       /* num_walks indices < num_biases, or NULL */
+    tw_bias start_bias;          /* TW_UNIFORM, TW_LINEAR or TW_EXPONENTIAL */
+    int32_t start_mode;          /* tw_start_mode */
+    const int32_t* d_start_nodes;/* TW_START_NODE: num_walks ids; else ignored */
+    uint64_t seed;
+    uint64_t walk_id_base;
+    const int64_t* d_row;        /* num_walks row starts (see tw_row_offsets), or NULL */
+    int64_t out_slots;           /* slots of d_nodes and d_ts, padded by the call;
+                                    0 with d_row NULL: num_walks * max_len */
+    int32_t dispatch;            /* TW_DISPATCH_QUEUE (AUTO means it), or
+                                    TW_DISPATCH_FULL_WALK: one thread per walk, no
+                                    queue (the plain form, for comparison) */
+} tw_batch_params;
+
 typedef struct {
     int64_t accepted;     /* records merged by the last ingest (after mirroring) */
     int64_t dropped_late; /* records of the last ingest older than t_now - Delta */
@@ -125,8 +162,10 @@ tw_status tw_set_stream(tw_graph* g, void* hip_stream);
  * Management"): mirror (undirected graphs), advance t_now to the largest
  * timestamp seen, drop batch records older than t_now - Delta, evict window
  * records older than t_now - Delta, sort the batch by timestamp (stable) and
- * merge it after the window's records of equal timestamp, then rebuild both
- * views of the dual index (Sec. "Dual-Index Organization").
+ * merge it after the window's records of equal timestamp, then update both
+ * views of the dual index (Sec. "Dual-Index Organization"): the timestamp
+ * view in place, and the node-and-timestamp view for the nodes the batch or
+ * the eviction touches.
  * d_src, d_dst: int32[n]; d_ts: int64[n]; device memory, any alignment.
  * info (nullable) receives the counts. The call synchronises the stream.
  * Returns TW_ERANGE, with the graph unchanged, if any id is outside
@@ -160,6 +199,52 @@ tw_status tw_evict_before(tw_graph* g, int64_t t_cutoff, int64_t* n_evicted);
  */
 tw_status tw_sample_walks(tw_graph* g, const tw_walk_params* params, int32_t* d_nodes,
                           int64_t* d_ts, int32_t* d_len);
+
+/*
+ * Counters of the last index update (ingest_batch or evict_before), for
+ * measurement: out[0] nodes whose run in the node-and-timestamp view changed
+ * (appended, evicted or rewritten), out[1] node-view edges written, out[2]
+ * edge slots of the node segments allocated, out[3] 1 when every active
+ * node was rewritten into fresh pools (a compaction), out[4], out[5], out[6]
+ * edge, group and fence pool slots handed out (live data, slack and the
+ * segments of moved nodes), out[7] edge pool capacity in slots. Host-side
+ * values, no synchronisation. Returns TW_EINVAL for null arguments.
+ */
+tw_status tw_index_stats(const tw_graph* g, int64_t out[8]);
+
+/*
+ * Walks of a tw_batch_params batch in one persistent launch (see there).
+ * d_nodes: int32[out_slots], d_ts: int64[out_slots]; every slot is first set
+ * to -1 / INT64_MIN, then each walk writes its nodes and timestamps from its
+ * row start (position 0 of d_ts stays INT64_MIN). Rows must not overlap and
+ * must fit in out_slots (the caller's layout; tw_row_offsets gives a packed
+ * one). d_len: int32[num_walks] lengths. Stream-ordered, no synchronisation;
+ * a limit outside [1, max_len], a bias index >= num_biases, or a row that
+ * starts below 0 or ends past out_slots gives that walk length 0 (nothing
+ * written) and makes the next synchronising call return TW_EINVAL. Returns TW_EINVAL for bad parameters (nothing enqueued).
+ */
+tw_status tw_sample_walks_batch(tw_graph* g, const tw_batch_params* params, int32_t* d_nodes,
+                                int64_t* d_ts, int32_t* d_len);
+
+/*
+ * Row starts for ragged walk output: d_row[i] = sum of d_max_len[0..i), with
+ * d_row[n] = the total, also returned in *total (host). d_row: int64[n + 1].
+ * Synchronises. Returns TW_EINVAL for null arguments or a negative n.
+ */
+tw_status tw_row_offsets(tw_graph* g, const int32_t* d_max_len, int64_t n, int64_t* d_row,
+                         int64_t* total);
+
+/*
+ * Time the dispatches of tw_sample_walks (full-walk, cooperative, queue with
+ * several launch shapes) on the current window for these parameters, with
+ * num_walks cut to at most sample_walks, and keep the fastest as the
+ * graph's TW_DISPATCH_AUTO choice. d_nodes / d_ts / d_len: scratch of the
+ * sizes tw_sample_walks needs for the timed walk count. best (nullable)
+ * receives the chosen tw_dispatch and, for the queue, its workgroups per
+ * compute unit in best[1]. Synchronises.
+ */
+tw_status tw_autotune(tw_graph* g, const tw_walk_params* params, int64_t sample_walks,
+                      int32_t* d_nodes, int64_t* d_ts, int32_t* d_len, int32_t best[2]);
 
 /* Synchronise the stream and report a pending device-side range error. */
 tw_status tw_sync(tw_graph* g);

@@ -21,7 +21,9 @@ UNIFORM, LINEAR, EXPONENTIAL, NODE2VEC = 0, 1, 2, 3
 KINDS = {"uniform": UNIFORM, "linear": LINEAR, "exponential": EXPONENTIAL, "node2vec": NODE2VEC}
 START_EDGE, START_NODE = 0, 1
 START_MODES = {"edge": START_EDGE, "node": START_NODE}
-DISPATCH = {"auto": 0, "full_walk": 1, "coop": 2}
+DISPATCH = {"auto": 0, "full_walk": 1, "coop": 2, "queue": 3}
+DISPATCH_NAMES = {v: k for k, v in DISPATCH.items()}
+MAX_BIASES = 8
 TW_OK, TW_EINVAL, TW_ENOMEM, TW_EDEVICE, TW_ERANGE = 0, 1, 2, 3, 4
 TS_NONE = -(1 << 63)
 
@@ -43,6 +45,16 @@ class _WalkParams(_c.Structure):
                 ("start_bias", _Bias), ("start_mode", _c.c_int32),
                 ("d_start_nodes", _c.c_void_p), ("seed", _c.c_uint64),
                 ("walk_id_base", _c.c_uint64), ("dispatch", _c.c_int32)]
+
+
+class _BatchParams(_c.Structure):
+    _fields_ = [("num_walks", _c.c_int64), ("max_len", _c.c_int32),
+                ("d_max_len", _c.c_void_p), ("num_biases", _c.c_int32),
+                ("hop_biases", _Bias * MAX_BIASES), ("d_bias", _c.c_void_p),
+                ("start_bias", _Bias), ("start_mode", _c.c_int32),
+                ("d_start_nodes", _c.c_void_p), ("seed", _c.c_uint64),
+                ("walk_id_base", _c.c_uint64), ("d_row", _c.c_void_p),
+                ("out_slots", _c.c_int64), ("dispatch", _c.c_int32)]
 
 
 class _Info(_c.Structure):
@@ -74,6 +86,11 @@ def lib():
         "tw_view_sizes": ([P, _c.POINTER(I64)], _c.c_int),
         "tw_export_views": ([P] * 12, _c.c_int),
         "tw_device_bytes": ([P], I64),
+        "tw_index_stats": ([P, _c.POINTER(I64)], _c.c_int),
+        "tw_sample_walks_batch": ([P, _c.POINTER(_BatchParams), P, P, P], _c.c_int),
+        "tw_row_offsets": ([P, P, I64, P, _c.POINTER(I64)], _c.c_int),
+        "tw_autotune": ([P, _c.POINTER(_WalkParams), I64, P, P, P, _c.POINTER(_c.c_int32)],
+                        _c.c_int),
         "tw_last_error": ([], _c.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -177,6 +194,86 @@ class Graph:
                                          _ptr(lens)))
         return nodes, ts, lens
 
+    def sample_walks_batch(self, num_walks: int, max_len: int, hop_biases,
+                           max_lens: Optional[torch.Tensor] = None,
+                           bias_idx: Optional[torch.Tensor] = None,
+                           start_bias: str = "uniform", start_tau: float = 0.0,
+                           start_mode: str = "edge", start_nodes: Optional[torch.Tensor] = None,
+                           seed: int = 42, walk_id_base: int = 0, ragged: bool = False,
+                           dispatch: str = "queue", rows=None, out=None):
+        """Walks of uneven lengths and mixed hop biases in one persistent
+        launch. hop_biases: list of (kind, tau, p, q); max_lens: int32[W] or
+        None; bias_idx: uint8[W] or None (walk id mod len(hop_biases)).
+        Returns (nodes, ts, len, row): rows of width max_len (row None), or,
+        with ragged=True, packed rows starting at row[i] (int64[W + 1]; pass
+        rows=(row, total) from row_offsets to skip computing them).
+        dispatch "queue" (persistent work queue) or "full_walk" (one thread
+        per walk, no queue)."""
+        W, L = int(num_walks), int(max_len)
+        nb = len(hop_biases)  # the library rejects 0 or more than MAX_BIASES
+        biases = (_Bias * MAX_BIASES)()
+        for i, (k, tau, p, q) in enumerate(hop_biases[:MAX_BIASES]):
+            biases[i] = _Bias(KINDS[k], float(tau), float(p), float(q))
+        if max_lens is not None:
+            assert max_lens.dtype == torch.int32 and max_lens.numel() >= W
+        if bias_idx is not None:
+            assert bias_idx.dtype == torch.uint8 and bias_idx.numel() >= W
+        if start_nodes is not None:
+            assert start_nodes.dtype == torch.int32 and start_nodes.numel() >= W
+        row = None
+        slots = W * L
+        if ragged:
+            assert max_lens is not None
+            row, total = rows if rows is not None else self.row_offsets(max_lens, W)
+            slots = max(int(total), 1)
+        if out is None:
+            nodes = torch.empty(max(slots, 1), dtype=torch.int32, device=self.device)
+            ts = torch.empty(max(slots, 1), dtype=torch.int64, device=self.device)
+            lens = torch.empty(max(W, 1), dtype=torch.int32, device=self.device)
+        else:
+            nodes, ts, lens = out
+            assert nodes.numel() >= slots and ts.numel() >= slots
+        prm = _BatchParams(W, L, _ptr(max_lens), nb, biases, _ptr(bias_idx),
+                           _Bias(KINDS[start_bias], float(start_tau), 1.0, 1.0),
+                           START_MODES[start_mode], _ptr(start_nodes), int(seed),
+                           int(walk_id_base), _ptr(row), slots if ragged else 0,
+                           DISPATCH[dispatch])
+        _check(self._lib.tw_sample_walks_batch(self._h, _c.byref(prm), _ptr(nodes), _ptr(ts),
+                                               _ptr(lens)))
+        if not ragged:
+            nodes, ts = nodes[:W * L].view(W, L), ts[:W * L].view(W, L)
+        return nodes, ts, lens[:W], row
+
+    def row_offsets(self, max_lens: torch.Tensor, n: Optional[int] = None):
+        """Packed row starts for per-walk limits: (row int64[n + 1], total)."""
+        n = max_lens.numel() if n is None else int(n)
+        assert max_lens.dtype == torch.int32
+        row = torch.empty(n + 1, dtype=torch.int64, device=self.device)
+        total = _c.c_int64(0)
+        _check(self._lib.tw_row_offsets(self._h, _ptr(max_lens), n, _ptr(row), _c.byref(total)))
+        return row, int(total.value)
+
+    def autotune(self, num_walks: int, max_len: int, sample: int = 1 << 20,
+                 hop_bias: str = "uniform", hop_tau: float = 0.0, p: float = 1.0,
+                 q: float = 1.0, start_bias: str = "uniform", start_tau: float = 0.0,
+                 start_mode: str = "edge", start_nodes: Optional[torch.Tensor] = None,
+                 seed: int = 42) -> dict:
+        """Time the dispatches on the current window and keep the fastest for
+        dispatch="auto"; returns {"dispatch": name, "blocks_per_cu": n}."""
+        W = min(int(num_walks), int(sample))
+        L = int(max_len)
+        nodes = torch.empty((max(W, 1), L), dtype=torch.int32, device=self.device)
+        ts = torch.empty((max(W, 1), L), dtype=torch.int64, device=self.device)
+        lens = torch.empty(max(W, 1), dtype=torch.int32, device=self.device)
+        prm = _WalkParams(int(num_walks), L, _Bias(KINDS[hop_bias], float(hop_tau), float(p),
+                                                   float(q)),
+                          _Bias(KINDS[start_bias], float(start_tau), 1.0, 1.0),
+                          START_MODES[start_mode], _ptr(start_nodes), int(seed), 0, 0)
+        best = (_c.c_int32 * 2)()
+        _check(self._lib.tw_autotune(self._h, _c.byref(prm), int(sample), _ptr(nodes), _ptr(ts),
+                                     _ptr(lens), best))
+        return {"dispatch": DISPATCH_NAMES[int(best[0])], "blocks_per_cu": int(best[1])}
+
     def sync(self):
         _check(self._lib.tw_sync(self._h))
 
@@ -210,6 +307,14 @@ class Graph:
         _check(self._lib.tw_export_views(self._h, *(_ptr(t[k]) if t[k].numel() else None
                                                     for k in order)))
         return t
+
+    def index_stats(self) -> dict:
+        """Counters of the last index update (see tw_index_stats)."""
+        out = (_c.c_int64 * 8)()
+        _check(self._lib.tw_index_stats(self._h, out))
+        keys = ("jobs", "written", "new_slots", "full_rewrite", "edge_slots", "group_slots",
+                "fence_slots", "edge_capacity")
+        return {k: int(out[i]) for i, k in enumerate(keys)}
 
     def device_bytes(self) -> int:
         return int(self._lib.tw_device_bytes(self._h))

@@ -30,17 +30,21 @@ tw_status guarded(const char* what, F&& f) {
     }
 }
 
-// pending device-side range error from walks (start node out of range)
+// pending device-side errors from walks: flag 0, a start node out of range;
+// flag 3, a batched walk with a length limit, bias index or row out of range
 tw_status check_device_flags(tw_graph* g) {
     if (!g->err.p) return TW_OK;
-    uint32_t f = 0;
-    if (hipMemcpyAsync(&f, g->err.p, sizeof(f), hipMemcpyDeviceToHost, g->stream) != hipSuccess ||
+    uint32_t f[4] = {0, 0, 0, 0};
+    if (hipMemcpyAsync(f, g->err.p, sizeof(f), hipMemcpyDeviceToHost, g->stream) != hipSuccess ||
         hipStreamSynchronize(g->stream) != hipSuccess)
         return fail(TW_EDEVICE, "reading device error flags failed");
-    if (f) {
-        hipMemsetAsync(g->err.p, 0, sizeof(uint32_t), g->stream);
+    if (f[0] || f[3]) {
+        uint32_t* d = static_cast<uint32_t*>(g->err.p);
+        hipMemsetAsync(d, 0, sizeof(uint32_t), g->stream);
+        hipMemsetAsync(d + 3, 0, sizeof(uint32_t), g->stream);
         hipStreamSynchronize(g->stream);
-        return fail(TW_ERANGE, "a walk start node was outside [0, num_nodes)");
+        if (f[0]) return fail(TW_ERANGE, "a walk start node was outside [0, num_nodes)");
+        return fail(TW_EINVAL, "a batched walk had a length limit, bias index or row out of range");
     }
     return TW_OK;
 }
@@ -117,6 +121,33 @@ tw_status tw_sample_walks(tw_graph* g, const tw_walk_params* params, int32_t* d_
     });
 }
 
+tw_status tw_sample_walks_batch(tw_graph* g, const tw_batch_params* params, int32_t* d_nodes,
+                                int64_t* d_ts, int32_t* d_len) {
+    if (!g) return fail(TW_EINVAL, "tw_sample_walks_batch: null graph");
+    return guarded("tw_sample_walks_batch", [&]() -> tw_status {
+        tw::Error e{TW_OK, ""};
+        return report(tw::sample_walks_batch(g, params, d_nodes, d_ts, d_len, e), e);
+    });
+}
+
+tw_status tw_row_offsets(tw_graph* g, const int32_t* d_max_len, int64_t n, int64_t* d_row,
+                         int64_t* total) {
+    if (!g) return fail(TW_EINVAL, "tw_row_offsets: null graph");
+    return guarded("tw_row_offsets", [&]() -> tw_status {
+        tw::Error e{TW_OK, ""};
+        return report(tw::row_offsets(g, d_max_len, n, d_row, total, e), e);
+    });
+}
+
+tw_status tw_autotune(tw_graph* g, const tw_walk_params* params, int64_t sample_walks,
+                      int32_t* d_nodes, int64_t* d_ts, int32_t* d_len, int32_t best[2]) {
+    if (!g) return fail(TW_EINVAL, "tw_autotune: null graph");
+    return guarded("tw_autotune", [&]() -> tw_status {
+        tw::Error e{TW_OK, ""};
+        return report(tw::autotune(g, params, sample_walks, d_nodes, d_ts, d_len, best, e), e);
+    });
+}
+
 tw_status tw_sync(tw_graph* g) {
     if (!g) return fail(TW_EINVAL, "tw_sync: null graph");
     if (hipStreamSynchronize(g->stream) != hipSuccess)
@@ -162,6 +193,19 @@ tw_status tw_export_views(tw_graph* g, int32_t* src, int32_t* dst, int64_t* ts, 
                                        n_ebeg, n_gbeg, e),
                       e);
     });
+}
+
+tw_status tw_index_stats(const tw_graph* g, int64_t out[8]) {
+    if (!g || !out) return fail(TW_EINVAL, "tw_index_stats: null argument");
+    out[0] = g->st_jobs;
+    out[1] = g->st_written;
+    out[2] = g->st_new_slots;
+    out[3] = g->st_full;
+    out[4] = g->pe_top;
+    out[5] = g->pg_top;
+    out[6] = g->pf_top;
+    out[7] = g->pe_cap;
+    return TW_OK;
 }
 
 int64_t tw_device_bytes(const tw_graph* g) {

@@ -22,7 +22,8 @@ namespace tw {
 namespace {
 
 constexpr int T = 256;
-constexpr int NV_ITEMS = 4;       // written edges per thread
+constexpr int NV_ITEMS = 8;       // job outputs per thread (lane-strided)
+constexpr int NV_TILE = T * NV_ITEMS;
 constexpr int FENCE_GRID = 2048;  // grid-stride launch for the fence entries
 
 inline dim3 grid_for(int64_t n, int items = 1) {
@@ -55,15 +56,19 @@ __device__ __forceinline__ NodeRec empty_rec() {
     return r;
 }
 
-// edge slots for a segment holding n edges: half again, at least 4 spare
+// Edge slots of a new segment holding n edges: twice n plus 4. A node whose
+// window slides (appends at the tail, evictions at the head) then finds,
+// when its tail is full, its live run past the first half of the segment,
+// and rewrites it to the segment's start without a new segment (the two
+// ranges are disjoint).
 __device__ __forceinline__ uint32_t edge_cap(uint32_t n) {
-    const uint64_t c = (uint64_t)n + std::max<uint64_t>(n >> 1, 4);
+    const uint64_t c = 2 * (uint64_t)n + 4;
     return (uint32_t)std::min<uint64_t>(c, UINT32_MAX - 1);
 }
 
-// capacity code of a group segment for n groups: FENCE_FAN << code >= 1.5 n
+// capacity code of a group segment for n groups: FENCE_FAN << code >= 2 n
 __device__ __forceinline__ uint32_t group_code(uint64_t n) {
-    const uint64_t want = n + (n >> 1);
+    const uint64_t want = 2 * n;
     uint32_t c = 0;
     while (seg_groups(c) < want) ++c;
     return c;
@@ -211,13 +216,18 @@ __global__ void k_job_setup(const uint32_t* __restrict__ c_node, const uint32_t*
             J.e_at = J.oe;
             J.g_at = ge;
             c = k;
-        } else if (!rewrite_all && has_seg && ne == 0 && k <= sg.ecap &&
-                   (uint64_t)k <= seg_groups(sg.gcode)) {
-            // nothing survives: the batch run restarts the node's own segment
+        } else if (!rewrite_all && has_seg &&
+                   (ne == 0 ? k <= sg.ecap && (uint64_t)k <= seg_groups(sg.gcode)
+                            : (uint64_t)sg.e0 + ne + k <= J.ob &&
+                                  (uint64_t)sg.g0 + (ge - gb) + k <= gb)) {
+            // nothing survives and the batch run fits the node's own segment,
+            // or the merged run fits before the surviving run there: rewrite
+            // it at the segment's start (source and destination are disjoint)
             J.kind = JOB_REWRITE;
+            J.merge = (ne > 0 && k > 0 && !after) ? 1u : 0u;
             J.e_at = sg.e0;
             J.g_at = sg.g0;
-            c = k;
+            c = ne + k;
         } else {
             J.kind = JOB_REWRITE;
             J.fresh = 1;
@@ -258,93 +268,137 @@ struct Elem {
     int64_t ts;
 };
 
-// element i of job J's written run
-__device__ __forceinline__ Elem job_elem(const Job& J, uint32_t i, const int32_t* __restrict__ odst,
-                                         const int64_t* __restrict__ ots,
-                                         const int32_t* __restrict__ bdst,
-                                         const int64_t* __restrict__ bts) {
-    if (J.kind == JOB_APPEND) return Elem{bdst[J.bf + i], bts[J.bf + i]};
+// Element i of a merging job's run (stable merge of the surviving old run
+// and the batch run, old first on equal timestamps): returns true when it is
+// old element *k, else batch element *k.
+__device__ __forceinline__ bool merge_pick(const Job& J, uint32_t i,
+                                           const int64_t* __restrict__ ots,
+                                           const int64_t* __restrict__ bts, uint32_t* k) {
     const uint32_t na = J.oe - J.ob, nb = J.be - J.bf;
-    if (!J.merge) {
-        if (i < na) return Elem{odst[J.ob + i], ots[J.ob + i]};
-        return Elem{bdst[J.bf + i - na], bts[J.bf + i - na]};
-    }
-    // stable merge, old first on equal timestamps: a = old elements among
-    // the first i outputs
+    // a = old elements among the first i outputs
     uint32_t lo = i > nb ? i - nb : 0, hi = i < na ? i : na;
     while (lo < hi) {
         const uint32_t a = lo + ((hi - lo) >> 1);
         if (ots[J.ob + a] <= bts[J.bf + (i - a - 1)]) lo = a + 1; else hi = a;
     }
     const uint32_t a = lo, b = i - lo;
-    if (a < na && (b >= nb || ots[J.ob + a] <= bts[J.bf + b]))
-        return Elem{odst[J.ob + a], ots[J.ob + a]};
-    return Elem{bdst[J.bf + b], bts[J.bf + b]};
+    if (a < na && (b >= nb || ots[J.ob + a] <= bts[J.bf + b])) {
+        *k = a;
+        return true;
+    }
+    *k = b;
+    return false;
 }
 
-// Write every job's run (NV_ITEMS consecutive outputs per thread) and flag
-// the outputs that start a group.
-__global__ void k_job_edges(const Job* __restrict__ jobs, const uint32_t* __restrict__ off,
-                            int64_t nj, int64_t total, const int32_t* __restrict__ odst,
-                            const int64_t* __restrict__ ots, const int32_t* __restrict__ bdst,
-                            const int64_t* __restrict__ bts, int32_t* __restrict__ ndst,
-                            int64_t* __restrict__ nts, uint32_t* __restrict__ oflag) {
-    const int64_t t0 = ((int64_t)blockIdx.x * T + threadIdx.x) * NV_ITEMS;
-    if (t0 >= total) return;
-    uint32_t j = job_of(off, (uint32_t)nj, (uint64_t)t0);
-    Job J = jobs[j];
-    uint32_t jb = off[j], je = off[j + 1];
-    uint32_t i = (uint32_t)(t0 - jb);
-    bool has_prev;
-    int64_t prev;
-    if (i > 0) {
-        has_prev = true;
-        prev = job_elem(J, i - 1, odst, ots, bdst, bts).ts;
-    } else {
-        has_prev = J.kind == JOB_APPEND;
-        prev = J.t_last;
+// element i of job J's written run
+__device__ __forceinline__ Elem job_elem(const Job& J, uint32_t i, const int32_t* __restrict__ odst,
+                                         const int64_t* __restrict__ ots,
+                                         const int32_t* __restrict__ bdst,
+                                         const int64_t* __restrict__ bts) {
+    if (J.kind == JOB_APPEND) return Elem{bdst[J.bf + i], bts[J.bf + i]};
+    const uint32_t na = J.oe - J.ob;
+    if (!J.merge) {
+        if (i < na) return Elem{odst[J.ob + i], ots[J.ob + i]};
+        return Elem{bdst[J.bf + i - na], bts[J.bf + i - na]};
     }
+    uint32_t k;
+    if (merge_pick(J, i, ots, bts, &k)) return Elem{odst[J.ob + k], ots[J.ob + k]};
+    return Elem{bdst[J.bf + k], bts[J.bf + k]};
+}
+
+// timestamp of element i of job J's written run
+__device__ __forceinline__ int64_t job_ts(const Job& J, uint32_t i, const int64_t* __restrict__ ots,
+                                          const int64_t* __restrict__ bts) {
+    if (J.kind == JOB_APPEND) return bts[J.bf + i];
+    const uint32_t na = J.oe - J.ob;
+    if (!J.merge) return i < na ? ots[J.ob + i] : bts[J.bf + i - na];
+    uint32_t k;
+    return merge_pick(J, i, ots, bts, &k) ? ots[J.ob + k] : bts[J.bf + k];
+}
+
+// last j in [lo, hi] with off[j] <= t (off[lo] <= t)
+__device__ __forceinline__ uint32_t job_in(const uint32_t* __restrict__ off, uint32_t lo,
+                                           uint32_t hi, uint64_t t) {
+    uint32_t a = lo + 1, b = hi + 1;
+    while (a < b) {
+        const uint32_t mid = a + ((b - a) >> 1);
+        if ((uint64_t)off[mid] <= t) a = mid + 1; else b = mid;
+    }
+    return a - 1;
+}
+
+// The jobs covering a tile of NV_TILE consecutive outputs (or entries),
+// found by thread 0; the tile's items go to consecutive lanes, so reads and
+// writes of the per-node runs coalesce.
+__device__ __forceinline__ void tile_jobs(const uint32_t* __restrict__ off, int64_t nj,
+                                          uint64_t base, uint64_t last, uint32_t* jr) {
+    if (threadIdx.x == 0) {
+        jr[0] = job_of(off, (uint32_t)nj, base);
+        jr[1] = job_of(off, (uint32_t)nj, last);
+    }
+    __syncthreads();
+}
+
+// group-start flag of every job output
+__global__ void __launch_bounds__(T) k_job_flags(const Job* __restrict__ jobs,
+                                                 const uint32_t* __restrict__ off, int64_t nj,
+                                                 int64_t total, const int64_t* __restrict__ ots,
+                                                 const int64_t* __restrict__ bts,
+                                                 uint32_t* __restrict__ oflag) {
+    __shared__ uint32_t jr[2];
+    const int64_t base = (int64_t)blockIdx.x * NV_TILE;
+    tile_jobs(off, nj, (uint64_t)base, (uint64_t)std::min<int64_t>(base + NV_TILE, total) - 1,
+              jr);
     for (int u = 0; u < NV_ITEMS; ++u) {
-        const int64_t t = t0 + u;
+        const int64_t t = base + (int64_t)u * T + threadIdx.x;
         if (t >= total) break;
-        if ((uint64_t)t >= je) {
-            do {
-                ++j;
-                jb = off[j];
-                je = off[j + 1];
-            } while ((uint64_t)t >= je);
-            J = jobs[j];
-            i = 0;
-            has_prev = J.kind == JOB_APPEND;
-            prev = J.t_last;
-        }
+        const uint32_t j = job_in(off, jr[0], jr[1], (uint64_t)t);
+        const Job J = jobs[j];
+        const uint32_t i = (uint32_t)(t - off[j]);
+        const int64_t x = job_ts(J, i, ots, bts);
+        bool start;
+        if (i == 0) start = J.kind != JOB_APPEND || x != J.t_last;
+        else start = x != job_ts(J, i - 1, ots, bts);
+        oflag[t] = start ? 1u : 0u;
+    }
+}
+
+// every job output's edge, and the group record of each group start (rank =
+// exclusive scan of the flags)
+__global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
+                                                 const uint32_t* __restrict__ off, int64_t nj,
+                                                 int64_t total, const int32_t* __restrict__ odst,
+                                                 const int64_t* __restrict__ ots,
+                                                 const int32_t* __restrict__ bdst,
+                                                 const int64_t* __restrict__ bts,
+                                                 const uint32_t* __restrict__ oflag,
+                                                 const uint32_t* __restrict__ rank,
+                                                 int32_t* __restrict__ ndst,
+                                                 int64_t* __restrict__ nts,
+                                                 GroupRec* __restrict__ ngd) {
+    __shared__ uint32_t jr[2];
+    const int64_t base = (int64_t)blockIdx.x * NV_TILE;
+    tile_jobs(off, nj, (uint64_t)base, (uint64_t)std::min<int64_t>(base + NV_TILE, total) - 1,
+              jr);
+    for (int u = 0; u < NV_ITEMS; ++u) {
+        const int64_t t = base + (int64_t)u * T + threadIdx.x;
+        if (t >= total) break;
+        const uint32_t j = job_in(off, jr[0], jr[1], (uint64_t)t);
+        const Job J = jobs[j];
+        const uint32_t jb = off[j];
+        const uint32_t i = (uint32_t)(t - jb);
         const Elem e = job_elem(J, i, odst, ots, bdst, bts);
         const uint32_t pos = J.e_at + i;
         ndst[pos] = e.dst;
         nts[pos] = e.ts;
-        oflag[t] = (!has_prev || e.ts != prev) ? 1u : 0u;
-        has_prev = true;
-        prev = e.ts;
-        ++i;
+        if (oflag[t]) {
+            GroupRec g;
+            g.ts = e.ts;
+            g.first = pos;
+            g.dst = e.dst;
+            ngd[J.g_at + (rank[t] - rank[jb])] = g;
+        }
     }
-}
-
-// group records of the flagged outputs; rank = exclusive scan of the flags
-__global__ void k_job_groups(const Job* __restrict__ jobs, const uint32_t* __restrict__ off,
-                             int64_t nj, int64_t total, const uint32_t* __restrict__ oflag,
-                             const uint32_t* __restrict__ rank, const int32_t* __restrict__ ndst,
-                             const int64_t* __restrict__ nts, GroupRec* __restrict__ ngd) {
-    const int64_t t = (int64_t)blockIdx.x * T + threadIdx.x;
-    if (t >= total || !oflag[t]) return;
-    const uint32_t j = job_of(off, (uint32_t)nj, (uint64_t)t);
-    const Job J = jobs[j];
-    const uint32_t i = (uint32_t)(t - off[j]);
-    const uint32_t pos = J.e_at + i;
-    GroupRec g;
-    g.ts = nts[pos];
-    g.first = pos;
-    g.dst = ndst[pos];
-    ngd[J.g_at + (rank[t] - rank[off[j]])] = g;
 }
 
 // fence entries a job writes at level k: the new groups [from, to) of a
@@ -412,40 +466,56 @@ __global__ void k_job_finish(const Job* __restrict__ jobs, const uint32_t* __res
     fw[j] = f;
 }
 
-// the fence entries of the jobs (grid-stride; total = foff[nj])
-__global__ void k_job_fence(const Job* __restrict__ jobs, const uint32_t* __restrict__ foff,
-                            int64_t nj, const NodeRec* __restrict__ rec,
-                            const GroupRec* __restrict__ ngd, int64_t* __restrict__ fence) {
-    const uint64_t total = foff[nj];
-    for (uint64_t t = (uint64_t)blockIdx.x * T + threadIdx.x; t < total;
-         t += (uint64_t)gridDim.x * T) {
-        const uint32_t j = job_of(foff, (uint32_t)nj, t);
-        const Job J = jobs[j];
-        const NodeRec r = rec[J.v];
-        const uint64_t cap = seg_groups(J.gcode);
-        const int K = fence_levels(cap);
-        uint64_t u = t - foff[j];
-        uint64_t base = 0;
-        for (int k = 1; k <= K; ++k) {
-            const uint32_t len = fence_level_len(cap, k);
-            if (J.kind == JOB_REWRITE) {
-                if (u < len) {
-                    const uint64_t g = (uint64_t)J.g0 + (u << (FENCE_LOG * k));
-                    fence[J.f0 + base + u] = g < r.ge ? ngd[g].ts : INT64_MAX;
-                    break;
-                }
-                u -= len;
-            } else {
-                uint64_t first;
-                const uint64_t c = level_span(J.g0, J.oge, r.ge, k, &first);
-                if (u < c) {
-                    const uint64_t i = first + u;
-                    fence[J.f0 + base + i] = ngd[J.g0 + (i << (FENCE_LOG * k))].ts;
-                    break;
-                }
-                u -= c;
+// value and position of fence entry u of job J (u counts the entries the
+// job writes)
+__device__ __forceinline__ void fence_entry(const Job& J, uint32_t ge,
+                                            const GroupRec* __restrict__ ngd,
+                                            int64_t* __restrict__ fence, uint64_t u) {
+    const uint64_t cap = seg_groups(J.gcode);
+    const int K = fence_levels(cap);
+    uint64_t base = 0;
+    for (int k = 1; k <= K; ++k) {
+        const uint32_t len = fence_level_len(cap, k);
+        if (J.kind == JOB_REWRITE) {
+            if (u < len) {
+                const uint64_t g = (uint64_t)J.g0 + (u << (FENCE_LOG * k));
+                fence[J.f0 + base + u] = g < ge ? ngd[g].ts : INT64_MAX;
+                return;
             }
-            base += len;
+            u -= len;
+        } else {
+            uint64_t first;
+            const uint64_t c = level_span(J.g0, J.oge, ge, k, &first);
+            if (u < c) {
+                const uint64_t i = first + u;
+                fence[J.f0 + base + i] = ngd[J.g0 + (i << (FENCE_LOG * k))].ts;
+                return;
+            }
+            u -= c;
+        }
+        base += len;
+    }
+}
+
+// the fence entries of the jobs (total = foff[nj]), tiles of NV_TILE
+// entries, grid-stride
+__global__ void __launch_bounds__(T) k_job_fence(const Job* __restrict__ jobs,
+                                                 const uint32_t* __restrict__ foff, int64_t nj,
+                                                 const NodeRec* __restrict__ rec,
+                                                 const GroupRec* __restrict__ ngd,
+                                                 int64_t* __restrict__ fence) {
+    __shared__ uint32_t jr[2];
+    const uint64_t total = foff[nj];
+    for (uint64_t base = (uint64_t)blockIdx.x * NV_TILE; base < total;
+         base += (uint64_t)gridDim.x * NV_TILE) {
+        __syncthreads();  // jr of the previous tile is no longer read
+        tile_jobs(foff, nj, base, std::min<uint64_t>(base + NV_TILE, total) - 1, jr);
+        for (int u = 0; u < NV_ITEMS; ++u) {
+            const uint64_t t = base + (uint64_t)u * T + threadIdx.x;
+            if (t >= total) break;
+            const uint32_t j = job_in(foff, jr[0], jr[1], t);
+            const Job J = jobs[j];
+            fence_entry(J, rec[J.v].ge, ngd, fence, t - foff[j]);
         }
     }
 }
@@ -530,6 +600,7 @@ tw_status nv_reset(tw_graph* g, Error& err) {
     hipLaunchKernelGGL(k_empty_rec, grid_for(V), dim3(T), 0, g->stream, g->rec.as<NodeRec>(), V);
     TW_HIP(hipGetLastError());
     g->pe_top = g->pg_top = g->pf_top = 0;
+    g->st_jobs = g->st_written = g->st_new_slots = g->st_full = 0;
     ++g->pool_gen;  // every segment is void
     g->T = 0;
     g->adj_ready = false;
@@ -644,13 +715,13 @@ tw_status execute_jobs(tw_graph* g, int64_t nj, uint64_t out, const int32_t* sds
     uint32_t* oflag = g->o_flag.as<uint32_t>();
     uint32_t* rank = g->o_rank.as<uint32_t>();
     if (out > 0)
-        hipLaunchKernelGGL(k_job_edges, grid_for((int64_t)out, NV_ITEMS), dim3(T), 0, s, jobs, off,
-                           nj, (int64_t)out, sdst, sts, g->bs_dst.as<int32_t>(),
-                           g->bs_ts.as<int64_t>(), ddst, dts, oflag);
+        hipLaunchKernelGGL(k_job_flags, dim3((unsigned)ceil_div((int64_t)out, NV_TILE)), dim3(T), 0,
+                           s, jobs, off, nj, (int64_t)out, sts, g->bs_ts.as<int64_t>(), oflag);
     TW_HIP(scan_exclusive_u32(oflag, rank, (int64_t)out, rank + out, g->ws, s));
     if (out > 0)
-        hipLaunchKernelGGL(k_job_groups, grid_for((int64_t)out), dim3(T), 0, s, jobs, off, nj,
-                           (int64_t)out, oflag, rank, ddst, dts, dng);
+        hipLaunchKernelGGL(k_job_write, dim3((unsigned)ceil_div((int64_t)out, NV_TILE)), dim3(T), 0,
+                           s, jobs, off, nj, (int64_t)out, sdst, sts, g->bs_dst.as<int32_t>(),
+                           g->bs_ts.as<int64_t>(), oflag, rank, ddst, dts, dng);
     hipLaunchKernelGGL(k_job_finish, grid_for(nj), dim3(T), 0, s, jobs, off, nj, rank, dng,
                        g->rec.as<NodeRec>(), g->seg.as<SegRec>(), gen, g->j_fw.as<uint32_t>());
     TW_HIP(scan_jobs(g->j_fw.as<uint32_t>(), g->j_fw.as<uint32_t>(), nj, g->ws, s));
@@ -666,6 +737,10 @@ tw_status run_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool rew
     uint64_t tot[4];
     const uint32_t gen = rewrite_all ? g->pool_gen + 1 : g->pool_gen;
     if (plan_jobs(g, nj, evicting, cut, rewrite_all, gen, tot, err) != TW_OK) return err.code;
+    g->st_jobs = nj;
+    g->st_written = (int64_t)tot[0];
+    g->st_new_slots = (int64_t)tot[1];
+    g->st_full = rewrite_all ? 1 : 0;
     if (!rewrite_all) {
         if (g->pe_top + (int64_t)tot[1] > g->pe_cap || g->pg_top + (int64_t)tot[2] > g->pg_cap ||
             g->pf_top + (int64_t)tot[3] > g->pf_cap) {
@@ -742,6 +817,7 @@ tw_status run_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool rew
 }  // namespace
 
 tw_status nv_apply(tw_graph* g, bool evicting, int64_t cut, Error& err) {
+    g->st_jobs = g->st_written = g->st_new_slots = g->st_full = 0;
     if (g->T == 0) return TW_OK;
     if (run_jobs(g, g->T, evicting, cut, false, err) != TW_OK) return err.code;
     g->adj_ready = false;

@@ -19,11 +19,12 @@ constexpr int RS_WAVES = RS_THREADS / 64;
 constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
 
-__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+template <typename V>
+__device__ inline V wave_incl_scan(V v) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        uint32_t o = __shfl_up(v, off, 64);
+        V o = __shfl_up(v, off, 64);
         if (lane >= off) v += o;
     }
     return v;
@@ -31,16 +32,17 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v) {
 
 // exclusive scan of one value per thread over a 256-thread block; returns
 // this thread's exclusive prefix and writes the block total to *total
-__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
-    __shared__ uint32_t wsum[SCAN_THREADS / 64];
+template <typename V>
+__device__ inline V block_excl_scan(V v, V* total) {
+    __shared__ V wsum[SCAN_THREADS / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t inc = wave_incl_scan(v);
+    V inc = wave_incl_scan(v);
     if (lane == 63) wsum[wave] = inc;
     __syncthreads();
-    uint32_t before = 0, all = 0;
+    V before = 0, all = 0;
 #pragma unroll
     for (int w = 0; w < SCAN_THREADS / 64; ++w) {
-        uint32_t s = wsum[w];
+        V s = wsum[w];
         before += (w < wave) ? s : 0;
         all += s;
     }
@@ -49,30 +51,32 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
     return before + inc - v;
 }
 
-__global__ void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
-                              uint32_t* __restrict__ part) {
+// In is the input element type, widened to V for the sums
+template <typename In, typename V>
+__global__ void k_scan_reduce(const In* __restrict__ in, int64_t n, V* __restrict__ part) {
     int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    uint32_t s = 0;
+    V s = 0;
     for (int j = 0; j < SCAN_ITEMS; ++j) {
         int64_t i = base + (int64_t)j * SCAN_THREADS + threadIdx.x;
-        if (i < n) s += in[i];
+        if (i < n) s += (V)in[i];
     }
-    uint32_t total;
+    V total;
     block_excl_scan(s, &total);
     if (threadIdx.x == 0) part[blockIdx.x] = total;
 }
 
 // one block: exclusive scan of the partials in place, total to *total
-__global__ void k_scan_partials(uint32_t* part, int64_t nb, uint32_t* total) {
-    __shared__ uint32_t carry;
+template <typename V>
+__global__ void k_scan_partials(V* part, int64_t nb, V* total) {
+    __shared__ V carry;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     for (int64_t base = 0; base < nb; base += SCAN_THREADS) {
         int64_t i = base + threadIdx.x;
-        uint32_t v = i < nb ? part[i] : 0;
-        uint32_t tot;
-        uint32_t ex = block_excl_scan(v, &tot);
-        uint32_t c = carry;
+        V v = i < nb ? part[i] : 0;
+        V tot;
+        V ex = block_excl_scan(v, &tot);
+        V c = carry;
         if (i < nb) part[i] = c + ex;
         __syncthreads();
         if (threadIdx.x == 0) carry = c + tot;
@@ -81,24 +85,24 @@ __global__ void k_scan_partials(uint32_t* part, int64_t nb, uint32_t* total) {
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
-__global__ void k_scan_down(const uint32_t* in, uint32_t* out, int64_t n,
-                            const uint32_t* __restrict__ part) {
-    __shared__ uint32_t tile[SCAN_TILE];
+template <typename In, typename V>
+__global__ void k_scan_down(const In* in, V* out, int64_t n, const V* __restrict__ part) {
+    __shared__ V tile[SCAN_TILE];
     int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
     for (int j = 0; j < SCAN_ITEMS; ++j) {
         int k = j * SCAN_THREADS + threadIdx.x;
         int64_t i = base + k;
-        tile[k] = i < n ? in[i] : 0;
+        tile[k] = i < n ? (V)in[i] : 0;
     }
     __syncthreads();
-    uint32_t loc[SCAN_ITEMS];
-    uint32_t s = 0;
+    V loc[SCAN_ITEMS];
+    V s = 0;
     for (int j = 0; j < SCAN_ITEMS; ++j) {
         loc[j] = s;
         s += tile[threadIdx.x * SCAN_ITEMS + j];
     }
-    uint32_t tot;
-    uint32_t pre = block_excl_scan(s, &tot) + part[blockIdx.x];
+    V tot;
+    V pre = block_excl_scan(s, &tot) + part[blockIdx.x];
     for (int j = 0; j < SCAN_ITEMS; ++j) tile[threadIdx.x * SCAN_ITEMS + j] = pre + loc[j];
     __syncthreads();
     for (int j = 0; j < SCAN_ITEMS; ++j) {
@@ -108,7 +112,9 @@ __global__ void k_scan_down(const uint32_t* in, uint32_t* out, int64_t n,
     }
 }
 
-__global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+template <typename V>
+__global__ void k_set(V* p, V v) { *p = v; }
+
 
 // group-start flag of position i: flags[i], or a timestamp change when flags
 // is null
@@ -336,20 +342,31 @@ void release(DevBuf& b) {
     b.bytes = 0;
 }
 
-hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
-                              Workspace& ws, hipStream_t s) {
+template <typename In, typename V>
+hipError_t scan_exclusive(const In* in, V* out, int64_t n, V* total, DevBuf& part_buf,
+                          hipStream_t s) {
     if (n <= 0) {
-        if (total) hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, total, 0u);
+        if (total) hipLaunchKernelGGL(k_set<V>, dim3(1), dim3(1), 0, s, total, (V)0);
         return hipGetLastError();
     }
     int64_t nb = ceil_div(n, SCAN_TILE);
-    hipError_t e = ensure(ws.scan_part, sizeof(uint32_t) * (nb + 1));
+    hipError_t e = ensure(part_buf, sizeof(V) * (nb + 1));
     if (e != hipSuccess) return e;
-    uint32_t* part = ws.scan_part.as<uint32_t>();
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, part);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, part, nb, total);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(SCAN_THREADS), 0, s, in, out, n, part);
+    V* part = part_buf.as<V>();
+    hipLaunchKernelGGL((k_scan_reduce<In, V>), dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, part);
+    hipLaunchKernelGGL(k_scan_partials<V>, dim3(1), dim3(SCAN_THREADS), 0, s, part, nb, total);
+    hipLaunchKernelGGL((k_scan_down<In, V>), dim3(nb), dim3(SCAN_THREADS), 0, s, in, out, n, part);
     return hipGetLastError();
+}
+
+hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
+                              Workspace& ws, hipStream_t s) {
+    return scan_exclusive<uint32_t, uint32_t>(in, out, n, total, ws.scan_part, s);
+}
+
+hipError_t scan_exclusive_i32_to_u64(const int32_t* in, uint64_t* out, int64_t n, uint64_t* total,
+                                     Workspace& ws, hipStream_t s) {
+    return scan_exclusive<int32_t, uint64_t>(in, out, n, total, ws.scan_part, s);
 }
 
 hipError_t group_starts(const uint32_t* flags, const int64_t* ts, int64_t n, uint32_t pos_base,
@@ -360,7 +377,8 @@ hipError_t group_starts(const uint32_t* flags, const int64_t* ts, int64_t n, uin
     if (e != hipSuccess) return e;
     uint32_t* part = ws.scan_part.as<uint32_t>();
     hipLaunchKernelGGL(k_flag_reduce, dim3(nb), dim3(SCAN_THREADS), 0, s, flags, ts, n, part);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, part, nb, total);
+    hipLaunchKernelGGL(k_scan_partials<uint32_t>, dim3(1), dim3(SCAN_THREADS), 0, s, part, nb,
+                       total);
     hipLaunchKernelGGL(k_flag_scatter, dim3(nb), dim3(SCAN_THREADS), 0, s, flags, ts, n, part,
                        pos_base, g_ts, g_off, total);
     return hipGetLastError();

@@ -138,6 +138,10 @@ struct Workspace {
 hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
                               Workspace& ws, hipStream_t s);
 
+// out[i] = sum_{j<i} in[j] in 64 bits (in >= 0); total (nullable) = the sum.
+hipError_t scan_exclusive_i32_to_u64(const int32_t* in, uint64_t* out, int64_t n, uint64_t* total,
+                                     Workspace& ws, hipStream_t s);
+
 // Groups of a sequence: the k-th position i that starts a group (flags[i]
 // != 0, or with flags null, ts[i] != ts[i-1]) gives g_ts[k] = ts[i] and
 // g_off[k] = pos_base + i; g_off[total] = pos_base + n; total (device) = the
@@ -215,7 +219,10 @@ struct tw_graph {
     tw::DevBuf c_node, c_bf, c_be;     // job candidates: node, batch run
     tw::DevBuf jobs, j_cnt, j_off, j_re, j_rg, j_rf, j_fw;
     tw::DevBuf o_flag, o_rank;         // per written edge: group start, rank
-    int64_t T = 0;                     // jobs of the last update
+    int64_t T = 0;                     // jobs collected for the next update
+    // counters of the last update: jobs, edges written, edge slots of new
+    // segments, whether every active node was rewritten
+    int64_t st_jobs = 0, st_written = 0, st_new_slots = 0, st_full = 0;
     tw::DevBuf adj, adj_rng;           // node2vec: per-node sorted destinations
     bool adj_ready = false;
 
@@ -223,6 +230,12 @@ struct tw_graph {
     tw::DevBuf c_node0, c_walk0, c_t0, c_node1, c_walk1, c_t1, c_node2, c_walk2, c_t2;
     tw::DevBuf c_prev, c_flags, c_pos;
     uint32_t coop_panel = 4096;        // LDS panel entries per workgroup
+    // queue dispatch: slice counters; compute units; the dispatch AUTO runs
+    // (0: full-walk until tw_autotune chooses) and the queue's workgroups per CU
+    tw::DevBuf wq;
+    int cu_count = 0, queue_bpc_max = 0;
+    int auto_dispatch = 0;
+    int auto_bpc = 0;
 
     // batch staging
     tw::DevBuf b_src, b_dst, b_ts, b_keys, b_vals, b_flags;
@@ -240,7 +253,7 @@ struct tw_graph {
                 &c_node, &c_bf, &c_be, &jobs, &j_cnt, &j_off, &j_re, &j_rg, &j_rf, &j_fw,
                 &o_flag, &o_rank, &adj, &adj_rng,
                 &c_node0, &c_walk0, &c_t0, &c_node1, &c_walk1, &c_t1, &c_node2, &c_walk2,
-                &c_t2, &c_prev, &c_flags, &c_pos,
+                &c_t2, &c_prev, &c_flags, &c_pos, &wq,
                 &b_src, &b_dst, &b_ts, &b_keys, &b_vals, &b_flags, &flags, &idx, &v_flags,
                 &v_pos, &err, &scal, &ws.scan_part, &ws.hist, &ws.keys_alt, &ws.vals_alt,
                 &ws.v64_alt, &ws.misc};
@@ -280,6 +293,12 @@ tw_status export_views(tw_graph* g, int32_t* src, int32_t* dst, int64_t* ts, int
 // walk.hip
 tw_status sample_walks(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int64_t* ts,
                        int32_t* len, Error& err);
+tw_status sample_walks_batch(tw_graph* g, const tw_batch_params* p, int32_t* nodes, int64_t* ts,
+                             int32_t* len, Error& err);
+tw_status row_offsets(tw_graph* g, const int32_t* max_len, int64_t n, int64_t* row,
+                      int64_t* total, Error& err);
+tw_status autotune(tw_graph* g, const tw_walk_params* p, int64_t sample, int32_t* nodes,
+                   int64_t* ts, int32_t* len, int32_t best[2], Error& err);
 
 }  // namespace tw
 

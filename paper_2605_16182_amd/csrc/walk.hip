@@ -4,11 +4,28 @@
 // same walks.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "walk_device.h"
 
 namespace tw {
 namespace {
+
+// A hop bias with node2vec's constants precomputed.
+struct HopBias {
+    int32_t kind;
+    double tau, inv_p, inv_q, beta_max;
+};
+
+HopBias make_hop_bias(const tw_bias& b) {
+    HopBias h;
+    h.kind = b.kind;
+    h.tau = b.tau;
+    h.inv_p = b.kind == TW_NODE2VEC ? 1.0 / b.p : 1.0;
+    h.inv_q = b.kind == TW_NODE2VEC ? 1.0 / b.q : 1.0;
+    h.beta_max = std::max(std::max(h.inv_p, 1.0), h.inv_q);
+    return h;
+}
 
 struct WalkArgs {
     // timestamp view and its groups
@@ -30,8 +47,9 @@ struct WalkArgs {
     // parameters
     int64_t num_walks;
     int32_t L;
-    int32_t hop_kind, start_kind, start_mode;
-    double hop_tau, start_tau, inv_p, inv_q, beta_max;
+    HopBias hop;
+    int32_t start_kind, start_mode;
+    double start_tau;
     const int32_t* start_nodes;
     uint64_t seed, base;
     // outputs
@@ -54,7 +72,7 @@ struct StartState {
 // First pick of walk w: EDGE mode draws from the whole window, NODE mode from
 // the start node's run; writes output positions 0 and 1.
 __device__ __forceinline__ StartState walk_start(const WalkArgs& a, int64_t w, uint64_t id,
-                                                 int32_t* out_n, int64_t* out_t) {
+                                                 int32_t L, int32_t* out_n, int64_t* out_t) {
     StartState st{0, 0, 0, 0};
     const Draw d0 = philox(id, 0, 0, a.seed);
     if (a.start_mode == TW_START_EDGE) {
@@ -69,7 +87,7 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, int64_t w, u
         const int64_t t = a.e_ts[e];
         out_n[0] = s;
         st.len = 1;
-        if (a.L == 1) return st;
+        if (L == 1) return st;
         out_n[1] = t_dst;
         out_t[1] = t;
         st.len = 2;
@@ -85,7 +103,7 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, int64_t w, u
     }
     out_n[0] = v0;
     st.len = 1;
-    if (a.L == 1) return st;
+    if (L == 1) return st;
     const NodeRec r = a.rec[v0];
     if (r.gb == r.ge) return st;
     Pick p = pick_node(a.ng, a.n_dst, a.n_ts, r.gb, r.ge, r.ee, a.start_kind,
@@ -103,27 +121,26 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, int64_t w, u
 // The pick of hop `hop` among groups [gc, r.ge) of node cur (previous node
 // prev): the hop bias, or node2vec's rejection loop. Returns false when
 // node2vec exhausts its trials (the walk ends).
-__device__ __forceinline__ bool hop_pick(const WalkArgs& a, const NodeRec& r, uint32_t gc,
-                                         uint64_t id, uint64_t hop, int32_t prev, Pick& p,
-                                         int32_t& nx) {
-    if (a.hop_kind != TW_NODE2VEC) {
+__device__ __forceinline__ bool hop_pick(const WalkArgs& a, const HopBias& hb, const NodeRec& r,
+                                         uint32_t gc, uint64_t id, uint64_t hop, int32_t prev,
+                                         Pick& p, int32_t& nx) {
+    if (hb.kind != TW_NODE2VEC) {
         const Draw d = philox(id, hop, 0, a.seed);
-        p = pick_node(a.ng, a.n_dst, a.n_ts, gc, r.ge, r.ee, a.hop_kind, a.hop_tau,
-                      r.t_last, d);
+        p = pick_node(a.ng, a.n_dst, a.n_ts, gc, r.ge, r.ee, hb.kind, hb.tau, r.t_last, d);
         nx = p.dst;
         return true;
     }
     const uint2 rp = a.adj_rng[prev];  // prev has edges: prev -> cur is one
     for (uint32_t trial = 0; trial < N2V_MAX_TRIALS; ++trial) {
         const Draw d = philox(id, hop, trial, a.seed);
-        p = pick_node(a.ng, a.n_dst, a.n_ts, gc, r.ge, r.ee, TW_EXPONENTIAL, a.hop_tau,
-                      r.t_last, d);
+        p = pick_node(a.ng, a.n_dst, a.n_ts, gc, r.ge, r.ee, TW_EXPONENTIAL, hb.tau, r.t_last,
+                      d);
         nx = p.dst;
         double beta;
-        if (nx == prev) beta = a.inv_p;
+        if (nx == prev) beta = hb.inv_p;
         else if (sorted_contains(a.adj, rp.x, rp.y, nx)) beta = 1.0;
-        else beta = a.inv_q;
-        if (unit_closed_open(d.x2) * a.beta_max < beta) return true;
+        else beta = hb.inv_q;
+        if (unit_closed_open(d.x2) * hb.beta_max < beta) return true;
     }
     atomicAdd(&a.err[2], 1u);
     return false;
@@ -176,7 +193,7 @@ __global__ void __launch_bounds__(WALK_THREADS) k_walk_full(const WalkArgs a) {
     const uint64_t id = a.base + (uint64_t)w;
     int32_t* out_n = a.nodes + w * a.L;
     int64_t* out_t = a.ts + w * a.L;
-    StartState st = walk_start(a, w, id, out_n, out_t);
+    StartState st = walk_start(a, w, id, a.L, out_n, out_t);
     int32_t len = st.len, cur = st.cur, prev = st.prev;
     int64_t tcur = st.t;
     if (len >= 2) {
@@ -186,7 +203,7 @@ __global__ void __launch_bounds__(WALK_THREADS) k_walk_full(const WalkArgs a) {
             const uint32_t gc = fence_search(a.ng, a.fence, r, tcur, nullptr, 0, 0);
             Pick p;
             int32_t nx;
-            if (!hop_pick(a, r, gc, id, hop, prev, p, nx)) break;
+            if (!hop_pick(a, a.hop, r, gc, id, hop, prev, p, nx)) break;
             out_n[len] = nx;
             out_t[len] = p.t;
             ++len;
@@ -196,6 +213,132 @@ __global__ void __launch_bounds__(WALK_THREADS) k_walk_full(const WalkArgs a) {
         }
     }
     finish_walk(a, w, len);
+}
+
+// ----------------------------------------------------------------- queue
+//
+// Persistent dispatch with a device work queue. Every lane of a wavefront
+// carries one walk at a time; when walks end, the wavefront takes as many
+// new walk ids as it has idle lanes with one atomic add on a counter. The
+// ids are split in QUEUE_SLICES contiguous slices, each with its own counter,
+// and a wavefront starts on slice blockIdx % QUEUE_SLICES (consecutive
+// workgroups go to different XCDs), moving to the next slice when one runs
+// out, so the counters see little contention. Per walk: its length limit,
+// its hop bias (one of up to TW_MAX_BIASES) and its output row.
+
+constexpr int QUEUE_SLICES = 8;
+
+struct QueueArgs {
+    unsigned long long* counters;  // QUEUE_SLICES counters, zero at launch
+    const int32_t* max_len;        // per-walk limit, or null (a.L)
+    const uint8_t* bias_idx;       // per-walk hop bias, or null (id mod n_bias)
+    const int64_t* row;            // per-walk row start, or null (w * a.L)
+    int64_t out_slots;             // slots of the outputs: a row must end inside
+    int32_t n_bias;
+    HopBias bias[TW_MAX_BIASES];
+};
+
+__global__ void k_queue_reset(unsigned long long* counters) {
+    if (threadIdx.x < QUEUE_SLICES) counters[threadIdx.x] = 0;
+}
+
+// REFILL = false is the same per-walk work without the queue: thread i runs
+// walk i only (the full-walk form of a batch).
+template <bool REFILL>
+__global__ void __launch_bounds__(WALK_THREADS) k_walk_queue(const WalkArgs a, const QueueArgs q) {
+    const int lane = threadIdx.x & 63;
+    const int64_t W = a.num_walks;
+    const int64_t slice_len = REFILL ? (W + QUEUE_SLICES - 1) / QUEUE_SLICES : W;
+    int slice = REFILL ? (int)(blockIdx.x % QUEUE_SLICES) : 0;
+    int exhausted = 0;  // slices this wavefront found empty (wave-uniform)
+    int64_t w = -1;
+    uint64_t id = 0, hop = 0;
+    int32_t len = 0, lim = 0, cur = 0, prev = 0;
+    int64_t tcur = 0;
+    int32_t* out_n = nullptr;
+    int64_t* out_t = nullptr;
+    HopBias hb{};
+    while (true) {
+        const uint64_t idle = __ballot(w < 0);
+        if (idle && exhausted < QUEUE_SLICES) {
+            const int n = __popcll(idle);
+            const int leader = __ffsll((unsigned long long)idle) - 1;
+            unsigned long long got = 0;
+            if (REFILL) {
+                if (lane == leader) got = atomicAdd(&q.counters[slice], (unsigned long long)n);
+                got = __shfl(got, leader, 64);
+            } else {
+                // each lane its own walk, once: the wave's first walk id
+                got = (unsigned long long)blockIdx.x * WALK_THREADS + (threadIdx.x & ~63);
+            }
+            const int64_t lo = (int64_t)slice * slice_len;
+            const int64_t hi = lo + slice_len < W ? lo + slice_len : W;
+            if (w < 0) {
+                const int rank = __popcll(idle & ((1ull << lane) - 1));
+                const int64_t cand = lo + (int64_t)got + rank;
+                if (cand < hi) {
+                    w = cand;
+                    id = a.base + (uint64_t)w;
+                    lim = q.max_len ? q.max_len[w] : a.L;
+                    const uint32_t b = q.bias_idx ? q.bias_idx[w] : (uint32_t)(id % (uint64_t)q.n_bias);
+                    const int64_t row = q.row ? q.row[w] : w * (int64_t)a.L;
+                    if (lim < 1 || lim > a.L || b >= (uint32_t)q.n_bias || row < 0 ||
+                        row + lim > q.out_slots) {
+                        atomicOr(&a.err[3], 1u);
+                        a.len[w] = 0;
+                        w = -1;
+                    } else {
+                        hb = q.bias[b];
+                        out_n = a.nodes + row;
+                        out_t = a.ts + row;
+                        const StartState st = walk_start(a, w, id, lim, out_n, out_t);
+                        len = st.len;
+                        cur = st.cur;
+                        prev = st.prev;
+                        tcur = st.t;
+                        hop = 1;
+                        if (len < 2 || len >= lim) {
+                            a.len[w] = len;
+                            w = -1;
+                        }
+                    }
+                }
+            }
+            if (!REFILL) {
+                exhausted = QUEUE_SLICES;  // no more walks for this wavefront
+            } else if (lo + (int64_t)got + n >= hi) {
+                slice = (slice + 1) % QUEUE_SLICES;
+                ++exhausted;
+            }
+        }
+        if (__ballot(w >= 0) == 0) {
+            if (exhausted >= QUEUE_SLICES) break;
+            continue;
+        }
+        if (w >= 0) {
+            bool done = true;
+            const NodeRec r = a.rec[cur];
+            if (tcur < r.t_last) {  // else Gamma_t(cur) is empty
+                const uint32_t gc = fence_search(a.ng, a.fence, r, tcur, nullptr, 0, 0);
+                Pick p;
+                int32_t nx;
+                if (hop_pick(a, hb, r, gc, id, hop, prev, p, nx)) {
+                    out_n[len] = nx;
+                    out_t[len] = p.t;
+                    ++len;
+                    ++hop;
+                    prev = cur;
+                    cur = nx;
+                    tcur = p.t;
+                    done = len >= lim;
+                }
+            }
+            if (done) {
+                a.len[w] = len;
+                w = -1;
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------------ coop
@@ -224,7 +367,7 @@ __global__ void __launch_bounds__(WALK_THREADS) k_coop_start(const WalkArgs a, L
     const int64_t w = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
     if (w >= a.num_walks) return;
     const uint64_t id = a.base + (uint64_t)w;
-    StartState st = walk_start(a, w, id, a.nodes + w * a.L, a.ts + w * a.L);
+    StartState st = walk_start(a, w, id, a.L, a.nodes + w * a.L, a.ts + w * a.L);
     bool live = st.len >= 2 && st.len < a.L;
     if (live) {
         nx.node[w] = (uint32_t)st.cur;
@@ -312,15 +455,15 @@ k_hop_coop(const WalkArgs a, Live cur, Live nxt, int32_t* __restrict__ prev_of, 
         const uint32_t gc = fence_search(a.ng, a.fence, r, tcur, my_panel, my_base, my_cap);
         Pick p;
         int32_t nx;
-        const int32_t prev = a.hop_kind == TW_NODE2VEC ? prev_of[w] : 0;
-        if (hop_pick(a, r, gc, id, hop, prev, p, nx)) {
+        const int32_t prev = a.hop.kind == TW_NODE2VEC ? prev_of[w] : 0;
+        if (hop_pick(a, a.hop, r, gc, id, hop, prev, p, nx)) {
             a.nodes[(int64_t)w * a.L + len] = nx;
             a.ts[(int64_t)w * a.L + len] = p.t;
             if (len + 1 < a.L) {
                 nxt.node[i] = (uint32_t)nx;
                 nxt.walk[i] = w;
                 nxt.t[i] = (uint64_t)p.t;
-                if (a.hop_kind == TW_NODE2VEC) prev_of[w] = v;
+                if (a.hop.kind == TW_NODE2VEC) prev_of[w] = v;
                 live = true;
             } else {
                 a.len[w] = len + 1;
@@ -383,46 +526,40 @@ tw_status coop_walks(tw_graph* g, const WalkArgs& a, Error& err) {
 
 }  // namespace
 
-tw_status sample_walks(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int64_t* ts,
-                       int32_t* len, Error& err) {
-    if (!p || p->num_walks < 0 || p->max_len < 1) {
-        err = Error{TW_EINVAL, "sample_walks: need num_walks >= 0 and max_len >= 1"};
-        return err.code;
-    }
-    const tw_bias& hb = p->hop_bias;
-    const tw_bias& sb = p->start_bias;
-    if (hb.kind < TW_UNIFORM || hb.kind > TW_NODE2VEC || sb.kind < TW_UNIFORM ||
-        sb.kind > TW_EXPONENTIAL || !valid_tau(hb.tau) || !valid_tau(sb.tau)) {
+namespace {
+
+tw_status check_bias(const tw_bias& b, bool hop, Error& err) {
+    if (b.kind < TW_UNIFORM || b.kind > (hop ? TW_NODE2VEC : TW_EXPONENTIAL) || !valid_tau(b.tau)) {
         err = Error{TW_EINVAL, "sample_walks: bad bias kind or tau (start bias cannot be node2vec)"};
         return err.code;
     }
-    if (hb.kind == TW_NODE2VEC && !(hb.p > 0.0 && hb.q > 0.0 && std::isfinite(hb.p) &&
-                                    std::isfinite(hb.q))) {
+    if (b.kind == TW_NODE2VEC &&
+        !(b.p > 0.0 && b.q > 0.0 && std::isfinite(b.p) && std::isfinite(b.q))) {
         err = Error{TW_EINVAL, "sample_walks: node2vec needs p > 0 and q > 0"};
         return err.code;
     }
-    if (p->start_mode != TW_START_EDGE && p->start_mode != TW_START_NODE) {
+    return TW_OK;
+}
+
+tw_status check_start(int mode, const int32_t* starts, int64_t num_walks, Error& err) {
+    if (mode != TW_START_EDGE && mode != TW_START_NODE) {
         err = Error{TW_EINVAL, "sample_walks: bad start mode"};
         return err.code;
     }
-    if (p->start_mode == TW_START_NODE && !p->d_start_nodes && p->num_walks > 0) {
+    if (mode == TW_START_NODE && !starts && num_walks > 0) {
         err = Error{TW_EINVAL, "sample_walks: start mode NODE needs d_start_nodes"};
         return err.code;
     }
-    if (p->dispatch < TW_DISPATCH_AUTO || p->dispatch > TW_DISPATCH_COOP) {
-        err = Error{TW_EINVAL, "sample_walks: bad dispatch"};
-        return err.code;
-    }
-    if (p->num_walks == 0) return TW_OK;
-    if (!nodes || !ts || !len) {
-        err = Error{TW_EINVAL, "sample_walks: null output"};
-        return err.code;
-    }
+    return TW_OK;
+}
+
+// The index part of the walk arguments and the common parameters.
+tw_status fill_args(tw_graph* g, int64_t num_walks, int32_t L, const tw_bias& sb, int start_mode,
+                    const int32_t* starts, uint64_t seed, uint64_t base, bool node2vec,
+                    int32_t* nodes, int64_t* ts, int32_t* len, WalkArgs& a, Error& err) {
     if (!g->rec.p && init_empty(g, err) != TW_OK) return err.code;
-    if (hb.kind == TW_NODE2VEC && g->m > 0) {
-        if (build_adjacency(g, err) != TW_OK) return err.code;
-    }
-    WalkArgs a{};
+    if (node2vec && g->m > 0 && build_adjacency(g, err) != TW_OK) return err.code;
+    a = WalkArgs{};
     a.e_src = g->e_src.as<int32_t>();
     a.e_dst = g->e_dst.as<int32_t>();
     a.e_ts = g->e_ts.as<int64_t>();
@@ -439,39 +576,238 @@ tw_status sample_walks(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int
     a.fence = g->fence.as<int64_t>();
     a.adj = g->adj.as<int32_t>();
     a.V = g->V;
-    a.num_walks = p->num_walks;
-    a.L = p->max_len;
-    a.hop_kind = hb.kind;
+    a.num_walks = num_walks;
+    a.L = L;
     a.start_kind = sb.kind;
-    a.start_mode = p->start_mode;
-    a.hop_tau = hb.tau;
+    a.start_mode = start_mode;
     a.start_tau = sb.tau;
-    a.inv_p = hb.kind == TW_NODE2VEC ? 1.0 / hb.p : 1.0;
-    a.inv_q = hb.kind == TW_NODE2VEC ? 1.0 / hb.q : 1.0;
-    a.beta_max = std::max(std::max(a.inv_p, 1.0), a.inv_q);
-    a.start_nodes = p->d_start_nodes;
-    a.seed = p->seed;
-    a.base = p->walk_id_base;
+    a.start_nodes = starts;
+    a.seed = seed;
+    a.base = base;
     a.nodes = nodes;
     a.ts = ts;
     a.len = len;
     a.err = g->err.as<uint32_t>();
-    // AUTO runs the full-walk kernel: on MI355X the per-step regrouping costs
-    // more (sorting, step tails, partial-line output writes) than it saves,
-    // since L2 and the MALL already hold the hot node metadata.
-    const bool coop = p->dispatch == TW_DISPATCH_COOP;
-    const int64_t slots = p->num_walks * (int64_t)p->max_len;
+    return TW_OK;
+}
+
+void launch_fill(tw_graph* g, int32_t* nodes, int64_t* ts, int64_t slots) {
     hipLaunchKernelGGL(k_fill_outputs,
-                       dim3((unsigned)std::min<int64_t>(ceil_div(slots, 4 * WALK_THREADS), 8192)),
+                       dim3((unsigned)std::max<int64_t>(
+                           std::min<int64_t>(ceil_div(slots, 4 * WALK_THREADS), 8192), 1)),
                        dim3(WALK_THREADS), 0, g->stream, nodes, ts, slots);
-    if (!coop) {
-        int64_t blocks = ceil_div(p->num_walks, WALK_THREADS);
-        hipLaunchKernelGGL(k_walk_full, dim3((unsigned)blocks), dim3(WALK_THREADS), 0, g->stream,
-                           a);
-        TW_HIP(hipGetLastError());
-        return TW_OK;
+}
+
+// compute units and the workgroups of k_walk_queue one of them holds at
+// once, queried once per graph (host-side queries only, so a walk launch can
+// be captured in a graph afterwards)
+tw_status queue_shape(tw_graph* g, Error& err) {
+    if (g->cu_count) return TW_OK;
+    int n = 0, nb = 0;
+    TW_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, g->device));
+    TW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_queue<true>, WALK_THREADS, 0));
+    g->cu_count = std::max(n, 1);
+    g->queue_bpc_max = std::max(nb, 1);
+    return TW_OK;
+}
+
+tw_status queue_walks(tw_graph* g, const WalkArgs& a, const QueueArgs& q0, int bpc, Error& err) {
+    if (queue_shape(g, err) != TW_OK) return err.code;
+    const int maxb = g->queue_bpc_max;
+    if (bpc <= 0 || bpc > maxb) bpc = maxb;
+    TW_HIP(ensure(g->wq, sizeof(unsigned long long) * QUEUE_SLICES));
+    QueueArgs q = q0;
+    q.counters = g->wq.as<unsigned long long>();
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, g->stream, q.counters);
+    const int64_t blocks =
+        std::min<int64_t>(ceil_div(a.num_walks, WALK_THREADS), (int64_t)g->cu_count * bpc);
+    hipLaunchKernelGGL(k_walk_queue<true>, dim3((unsigned)std::max<int64_t>(blocks, 1)),
+                       dim3(WALK_THREADS), 0, g->stream, a, q);
+    TW_HIP(hipGetLastError());
+    return TW_OK;
+}
+
+// the batch with one thread per walk and no queue
+tw_status batch_full_walk(tw_graph* g, const WalkArgs& a, const QueueArgs& q, Error& err) {
+    hipLaunchKernelGGL(k_walk_queue<false>, dim3((unsigned)ceil_div(a.num_walks, WALK_THREADS)),
+                       dim3(WALK_THREADS), 0, g->stream, a, q);
+    TW_HIP(hipGetLastError());
+    return TW_OK;
+}
+
+// run the walks of `a` (outputs already padded) under a dispatch
+tw_status run_dispatch(tw_graph* g, const WalkArgs& a, int dispatch, int bpc, Error& err) {
+    if (dispatch == TW_DISPATCH_COOP) return coop_walks(g, a, err);
+    if (dispatch == TW_DISPATCH_QUEUE) {
+        QueueArgs q{};
+        q.n_bias = 1;
+        q.bias[0] = a.hop;
+        q.out_slots = a.num_walks * (int64_t)a.L;
+        return queue_walks(g, a, q, bpc, err);
     }
-    return coop_walks(g, a, err);
+    hipLaunchKernelGGL(k_walk_full, dim3((unsigned)ceil_div(a.num_walks, WALK_THREADS)),
+                       dim3(WALK_THREADS), 0, g->stream, a);
+    TW_HIP(hipGetLastError());
+    return TW_OK;
+}
+
+tw_status prepare_plain(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int64_t* ts,
+                        int32_t* len, WalkArgs& a, Error& err) {
+    if (!p || p->num_walks < 0 || p->max_len < 1) {
+        err = Error{TW_EINVAL, "sample_walks: need num_walks >= 0 and max_len >= 1"};
+        return err.code;
+    }
+    if (check_bias(p->hop_bias, true, err) != TW_OK) return err.code;
+    if (check_bias(p->start_bias, false, err) != TW_OK) return err.code;
+    if (check_start(p->start_mode, p->d_start_nodes, p->num_walks, err) != TW_OK) return err.code;
+    if (p->dispatch < TW_DISPATCH_AUTO || p->dispatch > TW_DISPATCH_QUEUE) {
+        err = Error{TW_EINVAL, "sample_walks: bad dispatch"};
+        return err.code;
+    }
+    if (p->num_walks > 0 && (!nodes || !ts || !len)) {
+        err = Error{TW_EINVAL, "sample_walks: null output"};
+        return err.code;
+    }
+    if (fill_args(g, p->num_walks, p->max_len, p->start_bias, p->start_mode, p->d_start_nodes,
+                  p->seed, p->walk_id_base, p->hop_bias.kind == TW_NODE2VEC, nodes, ts, len, a,
+                  err) != TW_OK)
+        return err.code;
+    a.hop = make_hop_bias(p->hop_bias);
+    return TW_OK;
+}
+
+}  // namespace
+
+tw_status sample_walks(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int64_t* ts,
+                       int32_t* len, Error& err) {
+    WalkArgs a;
+    if (prepare_plain(g, p, nodes, ts, len, a, err) != TW_OK) return err.code;
+    if (p->num_walks == 0) return TW_OK;
+    launch_fill(g, nodes, ts, p->num_walks * (int64_t)p->max_len);
+    int dispatch = p->dispatch;
+    // AUTO: the autotuned choice, else the full-walk kernel
+    if (dispatch == TW_DISPATCH_AUTO)
+        dispatch = g->auto_dispatch ? g->auto_dispatch : TW_DISPATCH_FULL_WALK;
+    return run_dispatch(g, a, dispatch, g->auto_bpc, err);
+}
+
+tw_status sample_walks_batch(tw_graph* g, const tw_batch_params* p, int32_t* nodes, int64_t* ts,
+                             int32_t* len, Error& err) {
+    if (!p || p->num_walks < 0 || p->max_len < 1 || p->num_biases < 1 ||
+        p->num_biases > TW_MAX_BIASES) {
+        err = Error{TW_EINVAL,
+                    "sample_walks_batch: need num_walks >= 0, max_len >= 1, 1..8 hop biases"};
+        return err.code;
+    }
+    bool n2v = false;
+    for (int b = 0; b < p->num_biases; ++b) {
+        if (check_bias(p->hop_biases[b], true, err) != TW_OK) return err.code;
+        n2v |= p->hop_biases[b].kind == TW_NODE2VEC;
+    }
+    if (check_bias(p->start_bias, false, err) != TW_OK) return err.code;
+    if (check_start(p->start_mode, p->d_start_nodes, p->num_walks, err) != TW_OK) return err.code;
+    if (p->dispatch != TW_DISPATCH_AUTO && p->dispatch != TW_DISPATCH_QUEUE &&
+        p->dispatch != TW_DISPATCH_FULL_WALK) {
+        err = Error{TW_EINVAL, "sample_walks_batch: dispatch must be AUTO, QUEUE or FULL_WALK"};
+        return err.code;
+    }
+    if (p->num_walks == 0) return TW_OK;
+    if (!nodes || !ts || !len) {
+        err = Error{TW_EINVAL, "sample_walks_batch: null output"};
+        return err.code;
+    }
+    WalkArgs a;
+    if (fill_args(g, p->num_walks, p->max_len, p->start_bias, p->start_mode, p->d_start_nodes,
+                  p->seed, p->walk_id_base, n2v, nodes, ts, len, a, err) != TW_OK)
+        return err.code;
+    a.hop = make_hop_bias(p->hop_biases[0]);
+    QueueArgs q{};
+    q.max_len = p->d_max_len;
+    q.bias_idx = p->d_bias;
+    q.row = p->d_row;
+    q.n_bias = p->num_biases;
+    for (int b = 0; b < p->num_biases; ++b) q.bias[b] = make_hop_bias(p->hop_biases[b]);
+    if (p->d_row && p->out_slots < 1) {
+        err = Error{TW_EINVAL, "sample_walks_batch: ragged rows need out_slots"};
+        return err.code;
+    }
+    const int64_t slots = p->out_slots > 0 ? p->out_slots : p->num_walks * (int64_t)p->max_len;
+    q.out_slots = slots;
+    launch_fill(g, nodes, ts, slots);
+    if (p->dispatch == TW_DISPATCH_FULL_WALK) return batch_full_walk(g, a, q, err);
+    return queue_walks(g, a, q, g->auto_bpc, err);
+}
+
+tw_status row_offsets(tw_graph* g, const int32_t* max_len, int64_t n, int64_t* row,
+                      int64_t* total, Error& err) {
+    if (!row || n < 0 || (n > 0 && !max_len)) {
+        err = Error{TW_EINVAL, "row_offsets: null argument or negative count"};
+        return err.code;
+    }
+    uint64_t* out = reinterpret_cast<uint64_t*>(row);
+    TW_HIP(scan_exclusive_i32_to_u64(max_len, out, n, out + n, g->ws, g->stream));
+    int64_t t = 0;
+    TW_HIP(hipMemcpyAsync(&t, row + n, sizeof(t), hipMemcpyDeviceToHost, g->stream));
+    TW_HIP(hipStreamSynchronize(g->stream));
+    if (total) *total = t;
+    return TW_OK;
+}
+
+tw_status autotune(tw_graph* g, const tw_walk_params* p, int64_t sample, int32_t* nodes,
+                   int64_t* ts, int32_t* len, int32_t best[2], Error& err) {
+    if (!p || sample < 1) {
+        err = Error{TW_EINVAL, "autotune: need parameters and sample_walks >= 1"};
+        return err.code;
+    }
+    tw_walk_params q = *p;
+    q.num_walks = std::min<int64_t>(p->num_walks, sample);
+    WalkArgs a;
+    if (prepare_plain(g, &q, nodes, ts, len, a, err) != TW_OK) return err.code;
+    if (q.num_walks == 0) return TW_OK;
+    struct Cand {
+        int dispatch, bpc;
+    };
+    if (queue_shape(g, err) != TW_OK) return err.code;
+    const int maxb = g->queue_bpc_max;
+    std::vector<Cand> cands{{TW_DISPATCH_FULL_WALK, 0}, {TW_DISPATCH_COOP, 0}};
+    for (int b = maxb; b >= 1; b = b > 1 ? b / 2 : 0) cands.push_back({TW_DISPATCH_QUEUE, b});
+    hipEvent_t e0, e1;
+    TW_HIP(hipEventCreate(&e0));
+    TW_HIP(hipEventCreate(&e1));
+    float best_ms = 0.0f;
+    Cand pick{TW_DISPATCH_FULL_WALK, 0};
+    bool first = true;
+    for (const Cand& c : cands) {
+        float ms_min = 0.0f;
+        for (int rep = 0; rep < 3; ++rep) {  // the first run warms up
+            launch_fill(g, nodes, ts, q.num_walks * (int64_t)q.max_len);
+            hipEventRecord(e0, g->stream);
+            if (run_dispatch(g, a, c.dispatch, c.bpc, err) != TW_OK) {
+                hipEventDestroy(e0);
+                hipEventDestroy(e1);
+                return err.code;
+            }
+            hipEventRecord(e1, g->stream);
+            TW_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            TW_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (rep == 1 || (rep > 1 && ms < ms_min)) ms_min = ms;
+        }
+        if (first || ms_min < best_ms) {
+            best_ms = ms_min;
+            pick = c;
+            first = false;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    g->auto_dispatch = pick.dispatch;
+    g->auto_bpc = pick.bpc;
+    if (best) {
+        best[0] = pick.dispatch;
+        best[1] = pick.bpc;
+    }
+    return TW_OK;
 }
 
 }  // namespace tw

@@ -28,7 +28,7 @@ LIB_PATH = os.path.join(_HERE, "_build", "libsynth.so")
 _lib = None
 
 # stream ids inside one seed
-_S_SRC, _S_DST, _S_TS, _S_SEG, _S_START = 1, 2, 3, 4, 5
+_S_SRC, _S_DST, _S_TS, _S_SEG, _S_START, _S_LEN = 1, 2, 3, 4, 5, 6
 
 
 def build(verbose: bool = False) -> str:
@@ -198,6 +198,20 @@ def start_nodes(seed: int, n: int, num_nodes: int) -> np.ndarray:
     return nodes(seed, _S_START, 0, n, num_nodes, 0.0)
 
 
+def walk_lengths(seed: int, n: int, lo: int, hi: int) -> np.ndarray:
+    """Per-walk length limits, uniform in [lo, hi] (int32)."""
+    return uniform_i64(seed, _S_LEN, 0, n, lo, hi + 1).astype(np.int32)
+
+
+def mixed_biases(tau: float) -> list:
+    """The six hop biases of the batched mixed workload, walk i taking
+    entry (walk id mod 6): uniform, linear, exponential and temporal node2vec
+    with (p, q) = (0.5, 2), (1, 1), (2, 0.5); (kind, tau, p, q) tuples."""
+    return [("uniform", 0.0, 1.0, 1.0), ("linear", 0.0, 1.0, 1.0),
+            ("exponential", tau, 1.0, 1.0), ("node2vec", tau, 0.5, 2.0),
+            ("node2vec", tau, 1.0, 1.0), ("node2vec", tau, 2.0, 0.5)]
+
+
 # --------------------------------------------------------------------------
 # the five workloads
 
@@ -221,7 +235,7 @@ WORKLOADS = {
     "mixed": dict(stream=dict(num_nodes=1_000_000, num_edges=20_000_000, directed=False,
                               src_s=1.5, dst_s=1.5, zipf_k0=200.0, ts_kind="poisson",
                               mean_gap=10.0, seed=4),
-                  window=0, walks=8_000_000, max_len=120, start_bias="uniform",
+                  window=0, walks=8_000_000, max_len=120, min_len=5, start_bias="uniform",
                   hop_bias="mixed", tau_frac=0.1, batch_edges=20_000_000),
     # serving loop: ns timestamps at 5M edges/s
     "serve": dict(stream=dict(num_nodes=10_000_000, num_edges=300_000_000, src_s=1.2, dst_s=1.2,

@@ -102,7 +102,7 @@ WALK_CASES = [
 ]
 
 
-@pytest.mark.parametrize("dispatch", ["full_walk", "coop"])
+@pytest.mark.parametrize("dispatch", ["full_walk", "coop", "queue"])
 @pytest.mark.parametrize("ci", range(len(WALK_CASES)),
                          ids=["-".join(map(str, c[:1] + c[4:])) for c in WALK_CASES])
 @pytest.mark.parametrize("directed", [True, False])
@@ -235,7 +235,7 @@ def test_fence_search_depths(groups):
 
 @pytest.mark.parametrize("L", [1, 2, 3, 40])
 def test_dispatches_agree_on_lengths_and_edge_cases(L):
-    # the cooperative path against the full-walk path on a hub-heavy graph:
+    # the cooperative and queue paths against the full-walk path on a hub-heavy graph:
     # identical bytes for every walk, including walks that end at the start
     torch, tw = gpu_or_skip()
     w = synth.scaled("single", 5000, 300_000)
@@ -244,14 +244,15 @@ def test_dispatches_agree_on_lengths_and_edge_cases(L):
     g.ingest_batch(*to_dev(torch, s, d, t))
     span = float(t.max() - t.min())
     outs = []
-    for dispatch in ("full_walk", "coop"):
+    for dispatch in ("full_walk", "coop", "queue"):
         r = g.sample_walks(30_000, L, hop_bias="exponential", hop_tau=0.1 * span,
                            start_bias="exponential", start_tau=0.1 * span, seed=9,
                            dispatch=dispatch)
         g.sync()
         outs.append([x.cpu().numpy() for x in r])
-    for a, b in zip(*outs):
-        assert np.array_equal(a, b)
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert np.array_equal(a, b)
     g.close()
 
 
