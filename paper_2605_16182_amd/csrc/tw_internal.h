@@ -300,6 +300,29 @@ tw_status row_offsets(tw_graph* g, const int32_t* max_len, int64_t n, int64_t* r
 tw_status autotune(tw_graph* g, const tw_walk_params* p, int64_t sample, int32_t* nodes,
                    int64_t* ts, int32_t* len, int32_t best[2], Error& err);
 
+// One request of a serving launch: count walks of max_len nodes written to
+// rows of width max_len at nodes / ts, lengths at len (validated by the
+// caller).
+struct ServeReq {
+    int64_t count;
+    int32_t max_len;
+    tw_bias hop, start;
+    int32_t start_mode;
+    const int32_t* start_nodes;
+    uint64_t seed, base;
+    int32_t* nodes;
+    int64_t* ts;
+    int32_t* len;
+};
+// Device table bytes for n requests (d_table / h_table hold that much; the
+// host table should be pinned and must stay untouched until the launch's
+// copy has run).
+size_t serve_table_bytes(int n);
+// Enqueue the padding and the walks of n requests (1..1024) in one launch;
+// *d_hops accumulates the launch's hops.
+tw_status serve_launch(tw_graph* g, const ServeReq* reqs, int n, void* d_table, void* h_table,
+                       unsigned long long* d_hops, Error& err);
+
 }  // namespace tw
 
 #define TW_HIP(call)                                                                  \

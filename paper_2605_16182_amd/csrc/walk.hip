@@ -4,6 +4,7 @@
 // same walks.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "walk_device.h"
@@ -59,7 +60,35 @@ struct WalkArgs {
     uint32_t* err;  // [0] start node out of range, [2] node2vec trial cap hits
 };
 
+// The start of a walk: RNG seed, start bias and mode, start nodes.
+struct StartParams {
+    uint64_t seed;
+    int32_t kind, mode;
+    double tau;
+    const int32_t* nodes;
+};
+
+__device__ __forceinline__ StartParams start_of(const WalkArgs& a) {
+    return StartParams{a.seed, a.start_kind, a.start_mode, a.start_tau, a.start_nodes};
+}
+
 constexpr int WALK_THREADS = 256;
+
+// Kernels are instantiated per hop kind HK and start kind SK (-1: read at
+// run time). A fixed kind leaves only that picker's arithmetic in the
+// kernel: the full-walk kernel takes 52-56 VGPRs for uniform and linear hops
+// (8 wavefronts per SIMD) and about 100 for exponential hops, against 129
+// for the kernel that carries every picker (3 wavefronts per SIMD).
+template <int HK>
+__device__ __forceinline__ HopBias fixed_hop(HopBias h) {
+    if (HK >= 0) h.kind = HK;
+    return h;
+}
+template <int SK>
+__device__ __forceinline__ StartParams fixed_start(StartParams sp) {
+    if (SK >= 0) sp.kind = SK;
+    return sp;
+}
 constexpr uint32_t N2V_MAX_TRIALS = 4096;
 
 // Walk state after the first pick (RNG hop 0).
@@ -71,17 +100,18 @@ struct StartState {
 
 // First pick of walk w: EDGE mode draws from the whole window, NODE mode from
 // the start node's run; writes output positions 0 and 1.
-__device__ __forceinline__ StartState walk_start(const WalkArgs& a, int64_t w, uint64_t id,
-                                                 int32_t L, int32_t* out_n, int64_t* out_t) {
+__device__ __forceinline__ StartState walk_start(const WalkArgs& a, const StartParams& sp, int64_t w,
+                                                 uint64_t id, int32_t L, int32_t* out_n,
+                                                 int64_t* out_t) {
     StartState st{0, 0, 0, 0};
-    const Draw d0 = philox(id, 0, 0, a.seed);
-    if (a.start_mode == TW_START_EDGE) {
+    const Draw d0 = philox(id, 0, 0, sp.seed);
+    if (sp.mode == TW_START_EDGE) {
         if (a.m == 0) return st;
         uint32_t e;
-        if (a.start_kind == TW_UNIFORM) {
+        if (sp.kind == TW_UNIFORM) {
             e = a.e_base + (uint32_t)scale_u64(d0.x0, a.m);
         } else {
-            e = pick_global(a.gg_ts, a.gg_off, a.Gg, a.start_kind, a.start_tau, d0);
+            e = pick_global(a.gg_ts, a.gg_off, a.Gg, sp.kind, sp.tau, d0);
         }
         const int32_t s = a.e_src[e], t_dst = a.e_dst[e];
         const int64_t t = a.e_ts[e];
@@ -96,7 +126,7 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, int64_t w, u
         st.t = t;
         return st;
     }
-    const int32_t v0 = a.start_nodes[w];
+    const int32_t v0 = sp.nodes[w];
     if (v0 < 0 || v0 >= a.V) {
         atomicOr(&a.err[0], 1u);
         return st;
@@ -106,8 +136,7 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, int64_t w, u
     if (L == 1) return st;
     const NodeRec r = a.rec[v0];
     if (r.gb == r.ge) return st;
-    Pick p = pick_node(a.ng, a.n_dst, a.n_ts, r.gb, r.ge, r.ee, a.start_kind,
-                       a.start_tau, r.t_last, d0);
+    Pick p = pick_node(a.ng, a.n_dst, a.n_ts, r.gb, r.ge, r.ee, sp.kind, sp.tau, r.t_last, d0);
     const int32_t nx = p.dst;
     out_n[1] = nx;
     out_t[1] = p.t;
@@ -121,18 +150,18 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, int64_t w, u
 // The pick of hop `hop` among groups [gc, r.ge) of node cur (previous node
 // prev): the hop bias, or node2vec's rejection loop. Returns false when
 // node2vec exhausts its trials (the walk ends).
-__device__ __forceinline__ bool hop_pick(const WalkArgs& a, const HopBias& hb, const NodeRec& r,
-                                         uint32_t gc, uint64_t id, uint64_t hop, int32_t prev,
-                                         Pick& p, int32_t& nx) {
+__device__ __forceinline__ bool hop_pick(const WalkArgs& a, const HopBias& hb, uint64_t seed,
+                                         const NodeRec& r, uint32_t gc, uint64_t id, uint64_t hop,
+                                         int32_t prev, Pick& p, int32_t& nx) {
     if (hb.kind != TW_NODE2VEC) {
-        const Draw d = philox(id, hop, 0, a.seed);
+        const Draw d = philox(id, hop, 0, seed);
         p = pick_node(a.ng, a.n_dst, a.n_ts, gc, r.ge, r.ee, hb.kind, hb.tau, r.t_last, d);
         nx = p.dst;
         return true;
     }
     const uint2 rp = a.adj_rng[prev];  // prev has edges: prev -> cur is one
     for (uint32_t trial = 0; trial < N2V_MAX_TRIALS; ++trial) {
-        const Draw d = philox(id, hop, trial, a.seed);
+        const Draw d = philox(id, hop, trial, seed);
         p = pick_node(a.ng, a.n_dst, a.n_ts, gc, r.ge, r.ee, TW_EXPONENTIAL, hb.tau, r.t_last,
                       d);
         nx = p.dst;
@@ -187,13 +216,15 @@ __global__ void k_fill_outputs(int32_t* __restrict__ nodes, int64_t* __restrict_
 
 // One full walk per thread: the full-walk baseline (Sec. "The Full-Walk
 // Baseline").
+template <int HK, int SK>
 __global__ void __launch_bounds__(WALK_THREADS) k_walk_full(const WalkArgs a) {
     const int64_t w = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
     if (w >= a.num_walks) return;
     const uint64_t id = a.base + (uint64_t)w;
     int32_t* out_n = a.nodes + w * a.L;
     int64_t* out_t = a.ts + w * a.L;
-    StartState st = walk_start(a, w, id, a.L, out_n, out_t);
+    StartState st = walk_start(a, fixed_start<SK>(start_of(a)), w, id, a.L, out_n, out_t);
+    const HopBias hb = fixed_hop<HK>(a.hop);
     int32_t len = st.len, cur = st.cur, prev = st.prev;
     int64_t tcur = st.t;
     if (len >= 2) {
@@ -203,7 +234,7 @@ __global__ void __launch_bounds__(WALK_THREADS) k_walk_full(const WalkArgs a) {
             const uint32_t gc = fence_search(a.ng, a.fence, r, tcur, nullptr, 0, 0);
             Pick p;
             int32_t nx;
-            if (!hop_pick(a, a.hop, r, gc, id, hop, prev, p, nx)) break;
+            if (!hop_pick(a, hb, a.seed, r, gc, id, hop, prev, p, nx)) break;
             out_n[len] = nx;
             out_t[len] = p.t;
             ++len;
@@ -244,7 +275,7 @@ __global__ void k_queue_reset(unsigned long long* counters) {
 
 // REFILL = false is the same per-walk work without the queue: thread i runs
 // walk i only (the full-walk form of a batch).
-template <bool REFILL>
+template <bool REFILL, int HK, int SK>
 __global__ void __launch_bounds__(WALK_THREADS) k_walk_queue(const WalkArgs a, const QueueArgs q) {
     const int lane = threadIdx.x & 63;
     const int64_t W = a.num_walks;
@@ -288,10 +319,11 @@ __global__ void __launch_bounds__(WALK_THREADS) k_walk_queue(const WalkArgs a, c
                         a.len[w] = 0;
                         w = -1;
                     } else {
-                        hb = q.bias[b];
+                        hb = fixed_hop<HK>(q.bias[b]);
                         out_n = a.nodes + row;
                         out_t = a.ts + row;
-                        const StartState st = walk_start(a, w, id, lim, out_n, out_t);
+                        const StartState st =
+                            walk_start(a, fixed_start<SK>(start_of(a)), w, id, lim, out_n, out_t);
                         len = st.len;
                         cur = st.cur;
                         prev = st.prev;
@@ -322,7 +354,7 @@ __global__ void __launch_bounds__(WALK_THREADS) k_walk_queue(const WalkArgs a, c
                 const uint32_t gc = fence_search(a.ng, a.fence, r, tcur, nullptr, 0, 0);
                 Pick p;
                 int32_t nx;
-                if (hop_pick(a, hb, r, gc, id, hop, prev, p, nx)) {
+                if (hop_pick(a, hb, a.seed, r, gc, id, hop, prev, p, nx)) {
                     out_n[len] = nx;
                     out_t[len] = p.t;
                     ++len;
@@ -339,6 +371,133 @@ __global__ void __launch_bounds__(WALK_THREADS) k_walk_queue(const WalkArgs a, c
             }
         }
     }
+}
+
+// ----------------------------------------------------------------- serve
+//
+// A serving launch: the walks of several requests, each with its own seed,
+// id base, length limit, hop and start bias, start nodes and output rows,
+// through the same work queue. Walk w of the launch belongs to the request r
+// with walk0[r] <= w < walk0[r] + count[r] and is that request's walk
+// w - walk0[r], so a request's result does not depend on what else shares
+// the launch.
+
+constexpr int SERVE_MAX_REQ = 1024;
+
+struct ServeReqDev {
+    int64_t walk0, count;
+    uint64_t seed, base;
+    int32_t L, start_kind, start_mode, pad;
+    double start_tau;
+    HopBias hop;
+    const int32_t* start_nodes;
+    int32_t* nodes;
+    int64_t* ts;
+    int32_t* len;
+};
+
+__global__ void __launch_bounds__(WALK_THREADS)
+k_walk_serve(const WalkArgs a, const ServeReqDev* __restrict__ reqs, int nreq,
+             unsigned long long* counters, unsigned long long* hops_out) {
+    __shared__ int64_t w0[SERVE_MAX_REQ];
+    for (int r = threadIdx.x; r < nreq; r += WALK_THREADS) w0[r] = reqs[r].walk0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t W = a.num_walks;  // walks of the launch
+    const int64_t slice_len = (W + QUEUE_SLICES - 1) / QUEUE_SLICES;
+    int slice = (int)(blockIdx.x % QUEUE_SLICES);
+    int exhausted = 0;
+    int64_t w = -1, i = 0;
+    uint64_t id = 0, hop = 0, hops = 0;
+    int32_t len = 0, lim = 0, cur = 0, prev = 0;
+    int64_t tcur = 0;
+    int32_t* out_n = nullptr;
+    int64_t* out_t = nullptr;
+    int32_t* out_len = nullptr;
+    StartParams sp{};
+    uint64_t seed = 0;
+    HopBias hb{};
+    while (true) {
+        const uint64_t idle = __ballot(w < 0);
+        if (idle && exhausted < QUEUE_SLICES) {
+            const int n = __popcll(idle);
+            const int leader = __ffsll((unsigned long long)idle) - 1;
+            unsigned long long got = 0;
+            if (lane == leader) got = atomicAdd(&counters[slice], (unsigned long long)n);
+            got = __shfl(got, leader, 64);
+            const int64_t lo = (int64_t)slice * slice_len;
+            const int64_t hi = lo + slice_len < W ? lo + slice_len : W;
+            if (w < 0) {
+                const int rank = __popcll(idle & ((1ull << lane) - 1));
+                const int64_t cand = lo + (int64_t)got + rank;
+                if (cand < hi) {
+                    w = cand;
+                    int rl = 0, rh = nreq;  // last request with walk0 <= w
+                    while (rh - rl > 1) {
+                        const int mid = (rl + rh) >> 1;
+                        if (w0[mid] <= w) rl = mid; else rh = mid;
+                    }
+                    const ServeReqDev& R = reqs[rl];
+                    i = w - R.walk0;
+                    seed = R.seed;
+                    sp = StartParams{R.seed, R.start_kind, R.start_mode, R.start_tau,
+                                     R.start_nodes};
+                    hb = R.hop;
+                    lim = R.L;
+                    id = R.base + (uint64_t)i;
+                    out_n = R.nodes + i * (int64_t)R.L;
+                    out_t = R.ts + i * (int64_t)R.L;
+                    out_len = R.len + i;
+                    const StartState st = walk_start(a, sp, i, id, lim, out_n, out_t);
+                    len = st.len;
+                    cur = st.cur;
+                    prev = st.prev;
+                    tcur = st.t;
+                    hop = 1;
+                    if (len < 2 || len >= lim) {
+                        *out_len = len;
+                        hops += len > 1 ? (uint64_t)(len - 1) : 0;
+                        w = -1;
+                    }
+                }
+            }
+            if (lo + (int64_t)got + n >= hi) {
+                slice = (slice + 1) % QUEUE_SLICES;
+                ++exhausted;
+            }
+        }
+        if (__ballot(w >= 0) == 0) {
+            if (exhausted >= QUEUE_SLICES) break;
+            continue;
+        }
+        if (w >= 0) {
+            bool done = true;
+            const NodeRec r = a.rec[cur];
+            if (tcur < r.t_last) {
+                const uint32_t gc = fence_search(a.ng, a.fence, r, tcur, nullptr, 0, 0);
+                Pick p;
+                int32_t nx;
+                if (hop_pick(a, hb, seed, r, gc, id, hop, prev, p, nx)) {
+                    out_n[len] = nx;
+                    out_t[len] = p.t;
+                    ++len;
+                    ++hop;
+                    prev = cur;
+                    cur = nx;
+                    tcur = p.t;
+                    done = len >= lim;
+                }
+            }
+            if (done) {
+                *out_len = len;
+                hops += (uint64_t)(len - 1);
+                w = -1;
+            }
+        }
+    }
+    // hops of the launch: one atomic per wavefront
+    for (int off = 32; off > 0; off >>= 1) hops += __shfl_down(hops, off, 64);
+    if (lane == 0 && hops) atomicAdd(hops_out, (unsigned long long)hops);
 }
 
 // ------------------------------------------------------------------ coop
@@ -361,13 +520,15 @@ struct Live {
     uint64_t* t;
 };
 
+template <int SK>
 __global__ void __launch_bounds__(WALK_THREADS) k_coop_start(const WalkArgs a, Live nx,
                                                               int32_t* __restrict__ prev,
                                                               uint32_t* __restrict__ alive) {
     const int64_t w = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
     if (w >= a.num_walks) return;
     const uint64_t id = a.base + (uint64_t)w;
-    StartState st = walk_start(a, w, id, a.L, a.nodes + w * a.L, a.ts + w * a.L);
+    StartState st = walk_start(a, fixed_start<SK>(start_of(a)), w, id, a.L, a.nodes + w * a.L,
+                               a.ts + w * a.L);
     bool live = st.len >= 2 && st.len < a.L;
     if (live) {
         nx.node[w] = (uint32_t)st.cur;
@@ -394,6 +555,7 @@ __global__ void k_compact_live(const uint32_t* __restrict__ flags, const uint32_
 
 // One hop for the n live walks of `cur`, sorted by node. Results go to `nx`
 // at the same positions, with alive[i] set for walks that continue.
+template <int HK>
 __global__ void __launch_bounds__(WALK_THREADS)
 k_hop_coop(const WalkArgs a, Live cur, Live nxt, int32_t* __restrict__ prev_of, int64_t n,
            uint64_t hop, uint32_t panel_cap, uint32_t* __restrict__ alive) {
@@ -456,7 +618,7 @@ k_hop_coop(const WalkArgs a, Live cur, Live nxt, int32_t* __restrict__ prev_of, 
         Pick p;
         int32_t nx;
         const int32_t prev = a.hop.kind == TW_NODE2VEC ? prev_of[w] : 0;
-        if (hop_pick(a, a.hop, r, gc, id, hop, prev, p, nx)) {
+        if (hop_pick(a, fixed_hop<HK>(a.hop), a.seed, r, gc, id, hop, prev, p, nx)) {
             a.nodes[(int64_t)w * a.L + len] = nx;
             a.ts[(int64_t)w * a.L + len] = p.t;
             if (len + 1 < a.L) {
@@ -478,6 +640,29 @@ k_hop_coop(const WalkArgs a, Live cur, Live nxt, int32_t* __restrict__ prev_of, 
 }
 
 bool valid_tau(double t) { return std::isfinite(t); }
+
+template <int V>
+using Kind = std::integral_constant<int, V>;
+
+// f(Kind<HK>, Kind<SK>) for the run-time hop kind hk (-1: left dynamic, for
+// batches that mix hop biases) and start kind sk
+template <typename F>
+void with_kinds(int hk, int sk, F&& f) {
+    auto by_start = [&](auto h) {
+        switch (sk) {
+            case TW_LINEAR: f(h, Kind<TW_LINEAR>{}); break;
+            case TW_EXPONENTIAL: f(h, Kind<TW_EXPONENTIAL>{}); break;
+            default: f(h, Kind<TW_UNIFORM>{}); break;
+        }
+    };
+    switch (hk) {
+        case TW_UNIFORM: by_start(Kind<TW_UNIFORM>{}); break;
+        case TW_LINEAR: by_start(Kind<TW_LINEAR>{}); break;
+        case TW_EXPONENTIAL: by_start(Kind<TW_EXPONENTIAL>{}); break;
+        case TW_NODE2VEC: by_start(Kind<TW_NODE2VEC>{}); break;
+        default: by_start(Kind<-1>{}); break;
+    }
+}
 
 // Host loop of the cooperative dispatch: one synchronisation per step (the
 // live count), then sort by node -> hop -> in-order compaction.
@@ -502,7 +687,10 @@ tw_status coop_walks(tw_graph* g, const WalkArgs& a, Error& err) {
     const uint32_t panel_cap = g->coop_panel;
     const dim3 wgrid((unsigned)ceil_div(W, WALK_THREADS));
 
-    hipLaunchKernelGGL(k_coop_start, wgrid, dim3(WALK_THREADS), 0, s, a, next, prev, flags);
+    with_kinds(-1, a.start_kind, [&](auto, auto sk) {
+        hipLaunchKernelGGL((k_coop_start<decltype(sk)::value>), wgrid, dim3(WALK_THREADS), 0, s, a,
+                           next, prev, flags);
+    });
     TW_HIP(scan_exclusive_u32(flags, pos, W, n_live_d, g->ws, s));
     hipLaunchKernelGGL(k_compact_live, wgrid, dim3(WALK_THREADS), 0, s, flags, pos, W, next, live);
     TW_HIP(hipGetLastError());
@@ -514,8 +702,11 @@ tw_status coop_walks(tw_graph* g, const WalkArgs& a, Error& err) {
         const dim3 grid((unsigned)ceil_div(n_live, WALK_THREADS));
         TW_HIP(radix_sort_u32_kv(live.node, live.walk, live.t, sorted.node, sorted.walk, sorted.t,
                                  n_live, 0, vbits, g->ws, s));
-        hipLaunchKernelGGL(k_hop_coop, grid, dim3(WALK_THREADS), sizeof(int64_t) * panel_cap, s, a,
-                           sorted, next, prev, (int64_t)n_live, hop, panel_cap, flags);
+        with_kinds(a.hop.kind, TW_UNIFORM, [&](auto hk, auto) {
+            hipLaunchKernelGGL((k_hop_coop<decltype(hk)::value>), grid, dim3(WALK_THREADS),
+                               sizeof(int64_t) * panel_cap, s, a, sorted, next, prev,
+                               (int64_t)n_live, hop, panel_cap, flags);
+        });
         TW_HIP(scan_exclusive_u32(flags, pos, n_live, n_live_d, g->ws, s));
         hipLaunchKernelGGL(k_compact_live, grid, dim3(WALK_THREADS), 0, s, flags, pos,
                            (int64_t)n_live, next, live);
@@ -605,32 +796,50 @@ tw_status queue_shape(tw_graph* g, Error& err) {
     if (g->cu_count) return TW_OK;
     int n = 0, nb = 0;
     TW_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, g->device));
-    TW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_queue<true>, WALK_THREADS, 0));
+    TW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_queue<true, -1, -1>,
+                                                         WALK_THREADS, 0));
     g->cu_count = std::max(n, 1);
     g->queue_bpc_max = std::max(nb, 1);
     return TW_OK;
 }
 
+// resident workgroups per compute unit of one queue kernel instantiation
+template <typename K>
+int resident_bpc(K kernel) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, WALK_THREADS, 0) != hipSuccess)
+        nb = 1;
+    return std::max(nb, 1);
+}
+
 tw_status queue_walks(tw_graph* g, const WalkArgs& a, const QueueArgs& q0, int bpc, Error& err) {
     if (queue_shape(g, err) != TW_OK) return err.code;
-    const int maxb = g->queue_bpc_max;
-    if (bpc <= 0 || bpc > maxb) bpc = maxb;
     TW_HIP(ensure(g->wq, sizeof(unsigned long long) * QUEUE_SLICES));
     QueueArgs q = q0;
     q.counters = g->wq.as<unsigned long long>();
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, g->stream, q.counters);
-    const int64_t blocks =
-        std::min<int64_t>(ceil_div(a.num_walks, WALK_THREADS), (int64_t)g->cu_count * bpc);
-    hipLaunchKernelGGL(k_walk_queue<true>, dim3((unsigned)std::max<int64_t>(blocks, 1)),
-                       dim3(WALK_THREADS), 0, g->stream, a, q);
+    const int hk = q.n_bias == 1 ? q.bias[0].kind : -1;
+    with_kinds(hk, a.start_kind, [&](auto h, auto st) {
+        auto kernel = k_walk_queue<true, decltype(h)::value, decltype(st)::value>;
+        static const int maxb = resident_bpc(kernel);  // per instantiation
+        const int b = (bpc <= 0 || bpc > maxb) ? maxb : bpc;
+        const int64_t blocks =
+            std::min<int64_t>(ceil_div(a.num_walks, WALK_THREADS), (int64_t)g->cu_count * b);
+        hipLaunchKernelGGL(kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)),
+                           dim3(WALK_THREADS), 0, g->stream, a, q);
+    });
     TW_HIP(hipGetLastError());
     return TW_OK;
 }
 
 // the batch with one thread per walk and no queue
 tw_status batch_full_walk(tw_graph* g, const WalkArgs& a, const QueueArgs& q, Error& err) {
-    hipLaunchKernelGGL(k_walk_queue<false>, dim3((unsigned)ceil_div(a.num_walks, WALK_THREADS)),
-                       dim3(WALK_THREADS), 0, g->stream, a, q);
+    const int hk = q.n_bias == 1 ? q.bias[0].kind : -1;
+    with_kinds(hk, a.start_kind, [&](auto h, auto st) {
+        hipLaunchKernelGGL((k_walk_queue<false, decltype(h)::value, decltype(st)::value>),
+                           dim3((unsigned)ceil_div(a.num_walks, WALK_THREADS)), dim3(WALK_THREADS),
+                           0, g->stream, a, q);
+    });
     TW_HIP(hipGetLastError());
     return TW_OK;
 }
@@ -645,8 +854,11 @@ tw_status run_dispatch(tw_graph* g, const WalkArgs& a, int dispatch, int bpc, Er
         q.out_slots = a.num_walks * (int64_t)a.L;
         return queue_walks(g, a, q, bpc, err);
     }
-    hipLaunchKernelGGL(k_walk_full, dim3((unsigned)ceil_div(a.num_walks, WALK_THREADS)),
-                       dim3(WALK_THREADS), 0, g->stream, a);
+    with_kinds(a.hop.kind, a.start_kind, [&](auto h, auto st) {
+        hipLaunchKernelGGL((k_walk_full<decltype(h)::value, decltype(st)::value>),
+                           dim3((unsigned)ceil_div(a.num_walks, WALK_THREADS)), dim3(WALK_THREADS),
+                           0, g->stream, a);
+    });
     TW_HIP(hipGetLastError());
     return TW_OK;
 }
@@ -738,6 +950,62 @@ tw_status sample_walks_batch(tw_graph* g, const tw_batch_params* p, int32_t* nod
     return queue_walks(g, a, q, g->auto_bpc, err);
 }
 
+size_t serve_table_bytes(int n) { return sizeof(ServeReqDev) * (size_t)std::max(n, 1); }
+
+tw_status serve_launch(tw_graph* g, const ServeReq* reqs, int n, void* d_table, void* h_table,
+                       unsigned long long* d_hops, Error& err) {
+    if (n < 1 || n > SERVE_MAX_REQ) {
+        err = Error{TW_EINVAL, "serve: 1..1024 requests per launch"};
+        return err.code;
+    }
+    bool n2v = false;
+    int64_t total = 0;
+    ServeReqDev* tab = static_cast<ServeReqDev*>(h_table);
+    for (int r = 0; r < n; ++r) {
+        const ServeReq& q = reqs[r];
+        n2v |= q.hop.kind == TW_NODE2VEC;
+        ServeReqDev d{};
+        d.walk0 = total;
+        d.count = q.count;
+        d.seed = q.seed;
+        d.base = q.base;
+        d.L = q.max_len;
+        d.start_kind = q.start.kind;
+        d.start_mode = q.start_mode;
+        d.start_tau = q.start.tau;
+        d.hop = make_hop_bias(q.hop);
+        d.start_nodes = q.start_nodes;
+        d.nodes = q.nodes;
+        d.ts = q.ts;
+        d.len = q.len;
+        tab[r] = d;
+        total += q.count;
+    }
+    WalkArgs a;
+    tw_bias none{TW_UNIFORM, 0.0, 1.0, 1.0};
+    if (fill_args(g, total, 1, none, TW_START_EDGE, nullptr, 0, 0, n2v, nullptr, nullptr, nullptr,
+                  a, err) != TW_OK)
+        return err.code;
+    if (queue_shape(g, err) != TW_OK) return err.code;
+    TW_HIP(ensure(g->wq, sizeof(unsigned long long) * QUEUE_SLICES));
+    TW_HIP(hipMemcpyAsync(d_table, h_table, sizeof(ServeReqDev) * n, hipMemcpyHostToDevice,
+                          g->stream));
+    for (int r = 0; r < n; ++r)
+        if (reqs[r].count > 0)
+            launch_fill(g, reqs[r].nodes, reqs[r].ts, reqs[r].count * (int64_t)reqs[r].max_len);
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, g->stream,
+                       g->wq.as<unsigned long long>());
+    if (total > 0) {
+        const int64_t blocks = std::min<int64_t>(ceil_div(total, WALK_THREADS),
+                                                 (int64_t)g->cu_count * g->queue_bpc_max);
+        hipLaunchKernelGGL(k_walk_serve, dim3((unsigned)blocks), dim3(WALK_THREADS), 0, g->stream,
+                           a, static_cast<const ServeReqDev*>(d_table), n,
+                           g->wq.as<unsigned long long>(), d_hops);
+    }
+    TW_HIP(hipGetLastError());
+    return TW_OK;
+}
+
 tw_status row_offsets(tw_graph* g, const int32_t* max_len, int64_t n, int64_t* row,
                       int64_t* total, Error& err) {
     if (!row || n < 0 || (n > 0 && !max_len)) {
@@ -768,9 +1036,10 @@ tw_status autotune(tw_graph* g, const tw_walk_params* p, int64_t sample, int32_t
         int dispatch, bpc;
     };
     if (queue_shape(g, err) != TW_OK) return err.code;
-    const int maxb = g->queue_bpc_max;
-    std::vector<Cand> cands{{TW_DISPATCH_FULL_WALK, 0}, {TW_DISPATCH_COOP, 0}};
-    for (int b = maxb; b >= 1; b = b > 1 ? b / 2 : 0) cands.push_back({TW_DISPATCH_QUEUE, b});
+    // queue launch shapes: as many workgroups as fit (0), or 4 or 2 per CU
+    std::vector<Cand> cands{{TW_DISPATCH_FULL_WALK, 0}, {TW_DISPATCH_COOP, 0},
+                            {TW_DISPATCH_QUEUE, 0}, {TW_DISPATCH_QUEUE, 4},
+                            {TW_DISPATCH_QUEUE, 2}};
     hipEvent_t e0, e1;
     TW_HIP(hipEventCreate(&e0));
     TW_HIP(hipEventCreate(&e1));
