@@ -39,7 +39,8 @@ typedef enum {
     TW_EINVAL = 1,  /* bad argument; nothing was changed or enqueued */
     TW_ENOMEM = 2,  /* device allocation failed; graph left unchanged */
     TW_EDEVICE = 3, /* a HIP runtime call failed */
-    TW_ERANGE = 4   /* a node id outside [0, num_nodes) */
+    TW_ERANGE = 4,  /* a node id outside [0, num_nodes) */
+    TW_ETIMEOUT = 5 /* tw_server_wait: the request has not finished yet */
 } tw_status;
 
 /* Pickers, Sec. "Temporal Bias Sampling".
@@ -245,6 +246,83 @@ tw_status tw_row_offsets(tw_graph* g, const int32_t* d_max_len, int64_t n, int64
  */
 tw_status tw_autotune(tw_graph* g, const tw_walk_params* params, int64_t sample_walks,
                       int32_t* d_nodes, int64_t* d_ts, int32_t* d_len, int32_t best[2]);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of walk requests interleaved with ingestion.
+ *
+ * A server owns a graph (the caller must not use the graph directly while
+ * the server exists) and a worker thread. Requests (tw_walk_params, dispatch
+ * ignored) and ingest batches are queued in submission order. The worker
+ * applies ingest batches in that order, and packs consecutive requests into
+ * one work-queue launch (up to max_walks_per_launch walks, 1024 requests)
+ * as soon as their outputs fit in the output arena, without waiting for the
+ * launch before it (up to max_inflight launches enqueued). Every request
+ * sees exactly the ingest batches submitted before it (its index epoch), and
+ * its walks are the ones tw_sample_walks gives on that window with the same
+ * parameters: requests sharing a launch do not change each other's result.
+ * Functions may be called from any host thread.
+ */
+typedef struct tw_server tw_server;
+
+typedef struct {
+    int64_t arena_bytes;          /* device memory for request outputs, allocated at create */
+    int64_t max_walks_per_launch; /* walks of one launch (a larger request runs alone) */
+    int32_t max_inflight;         /* launches enqueued at once, 1..8 */
+} tw_server_config;
+
+typedef struct {
+    tw_status status;     /* of the request (or ingest batch) */
+    int32_t* d_nodes;     /* num_walks x max_len, server memory valid until release */
+    int64_t* d_ts;        /* num_walks x max_len */
+    int32_t* d_len;       /* num_walks */
+    int64_t num_walks;
+    int32_t max_len;
+    double queue_ms;      /* submission to launch */
+    double latency_ms;    /* submission to completion seen by the worker */
+    tw_ingest_info ingest;/* ingest batches: the counts of that ingest */
+} tw_request_result;
+
+typedef struct {
+    int64_t requests_done, walks_done, hops_done, launches, ingests;
+    double p50_ms, p99_ms, max_ms, mean_ms; /* request latency, submission to completion */
+    double wall_s;        /* seconds since create */
+} tw_server_counters;
+
+/* Start a server on g. Allocates the arena and the launch tables (TW_ENOMEM
+ * if that fails). Returns TW_EINVAL for bad arguments. */
+tw_status tw_server_create(tw_graph* g, const tw_server_config* cfg, tw_server** out);
+
+/* Queue a walk request; *id names it. d_start_nodes (NODE mode) must stay
+ * valid until the request finishes. Returns TW_EINVAL for bad parameters or
+ * a request whose outputs can never fit in the arena. */
+tw_status tw_server_submit(tw_server* s, const tw_walk_params* req, uint64_t* id);
+
+/* Queue an ingest batch (as tw_ingest_batch); the arrays must stay valid
+ * until it finishes. *id names it. */
+tw_status tw_server_ingest(tw_server* s, const int32_t* d_src, const int32_t* d_dst,
+                           const int64_t* d_ts, int64_t n, uint64_t* id);
+
+/* Wait up to timeout_us (< 0: no limit) for request or batch id. TW_OK with
+ * *out filled when it has finished (out->status is its own status),
+ * TW_ETIMEOUT if it has not, TW_EINVAL for an unknown or released id. */
+tw_status tw_server_wait(tw_server* s, uint64_t id, int64_t timeout_us, tw_request_result* out);
+
+/* Return a finished request's output memory to the arena; the id is then
+ * unknown. TW_EINVAL if it has not finished or is unknown. */
+tw_status tw_server_release(tw_server* s, uint64_t id);
+
+/* Copy finished request id's outputs into caller device memory: d_nodes
+ * and d_ts num_walks x max_len, d_len num_walks (any pointer may be NULL).
+ * Synchronous. TW_EINVAL if the request is unknown or has not finished. */
+tw_status tw_server_copy_out(tw_server* s, uint64_t id, int32_t* d_nodes, int64_t* d_ts,
+                             int32_t* d_len);
+
+/* Counters and request-latency percentiles since create. */
+tw_status tw_server_stats(tw_server* s, tw_server_counters* out);
+
+/* Finish the queued work, stop the worker and free the server's memory
+ * (outputs not yet released are freed too). The graph stays valid. */
+tw_status tw_server_destroy(tw_server* s);
 
 /* Synchronise the stream and report a pending device-side range error. */
 tw_status tw_sync(tw_graph* g);

@@ -24,7 +24,7 @@ START_MODES = {"edge": START_EDGE, "node": START_NODE}
 DISPATCH = {"auto": 0, "full_walk": 1, "coop": 2, "queue": 3}
 DISPATCH_NAMES = {v: k for k, v in DISPATCH.items()}
 MAX_BIASES = 8
-TW_OK, TW_EINVAL, TW_ENOMEM, TW_EDEVICE, TW_ERANGE = 0, 1, 2, 3, 4
+TW_OK, TW_EINVAL, TW_ENOMEM, TW_EDEVICE, TW_ERANGE, TW_ETIMEOUT = 0, 1, 2, 3, 4, 5
 TS_NONE = -(1 << 63)
 
 _c = ctypes
@@ -62,6 +62,23 @@ class _Info(_c.Structure):
                                           "active_edges", "t_min", "t_max")]
 
 
+class _ServerConfig(_c.Structure):
+    _fields_ = [("arena_bytes", _c.c_int64), ("max_walks_per_launch", _c.c_int64),
+                ("max_inflight", _c.c_int32)]
+
+
+class _RequestResult(_c.Structure):
+    _fields_ = [("status", _c.c_int), ("d_nodes", _c.c_void_p), ("d_ts", _c.c_void_p),
+                ("d_len", _c.c_void_p), ("num_walks", _c.c_int64), ("max_len", _c.c_int32),
+                ("queue_ms", _c.c_double), ("latency_ms", _c.c_double), ("ingest", _Info)]
+
+
+class _ServerCounters(_c.Structure):
+    _fields_ = [(k, _c.c_int64) for k in ("requests_done", "walks_done", "hops_done",
+                                          "launches", "ingests")] + \
+               [(k, _c.c_double) for k in ("p50_ms", "p99_ms", "max_ms", "mean_ms", "wall_s")]
+
+
 _lib = None
 
 
@@ -87,6 +104,14 @@ def lib():
         "tw_export_views": ([P] * 12, _c.c_int),
         "tw_device_bytes": ([P], I64),
         "tw_index_stats": ([P, _c.POINTER(I64)], _c.c_int),
+        "tw_server_create": ([P, _c.POINTER(_ServerConfig), _c.POINTER(P)], _c.c_int),
+        "tw_server_submit": ([P, _c.POINTER(_WalkParams), _c.POINTER(_c.c_uint64)], _c.c_int),
+        "tw_server_ingest": ([P, P, P, P, I64, _c.POINTER(_c.c_uint64)], _c.c_int),
+        "tw_server_wait": ([P, _c.c_uint64, I64, _c.POINTER(_RequestResult)], _c.c_int),
+        "tw_server_release": ([P, _c.c_uint64], _c.c_int),
+        "tw_server_copy_out": ([P, _c.c_uint64, P, P, P], _c.c_int),
+        "tw_server_stats": ([P, _c.POINTER(_ServerCounters)], _c.c_int),
+        "tw_server_destroy": ([P], _c.c_int),
         "tw_sample_walks_batch": ([P, _c.POINTER(_BatchParams), P, P, P], _c.c_int),
         "tw_row_offsets": ([P, P, I64, P, _c.POINTER(I64)], _c.c_int),
         "tw_autotune": ([P, _c.POINTER(_WalkParams), I64, P, P, P, _c.POINTER(_c.c_int32)],
@@ -318,3 +343,88 @@ class Graph:
 
     def device_bytes(self) -> int:
         return int(self._lib.tw_device_bytes(self._h))
+
+
+class Server:
+    """Continuous batching of walk requests over a Graph (see tw_server_* in
+    include/tw.h). The graph must not be used directly while the server
+    exists."""
+
+    def __init__(self, graph: Graph, arena_bytes: int = 1 << 30,
+                 max_walks_per_launch: int = 1 << 21, max_inflight: int = 2):
+        self._lib = lib()
+        self.graph = graph
+        self.device = graph.device
+        cfg = _ServerConfig(int(arena_bytes), int(max_walks_per_launch), int(max_inflight))
+        h = _c.c_void_p()
+        _check(self._lib.tw_server_create(graph._h, _c.byref(cfg), _c.byref(h)))
+        self._h = h
+        self._keep = {}  # input tensors of queued work, by id
+
+    def submit(self, num_walks: int, max_len: int, hop_bias: str = "uniform",
+               hop_tau: float = 0.0, p: float = 1.0, q: float = 1.0,
+               start_bias: str = "uniform", start_tau: float = 0.0, start_mode: str = "edge",
+               start_nodes: Optional[torch.Tensor] = None, seed: int = 42,
+               walk_id_base: int = 0) -> int:
+        prm = _WalkParams(int(num_walks), int(max_len),
+                          _Bias(KINDS[hop_bias], float(hop_tau), float(p), float(q)),
+                          _Bias(KINDS[start_bias], float(start_tau), 1.0, 1.0),
+                          START_MODES[start_mode], _ptr(start_nodes), int(seed),
+                          int(walk_id_base), 0)
+        rid = _c.c_uint64(0)
+        _check(self._lib.tw_server_submit(self._h, _c.byref(prm), _c.byref(rid)))
+        if start_nodes is not None:
+            self._keep[rid.value] = start_nodes
+        return int(rid.value)
+
+    def ingest(self, src: torch.Tensor, dst: torch.Tensor, ts: torch.Tensor) -> int:
+        assert src.dtype == torch.int32 and dst.dtype == torch.int32 and ts.dtype == torch.int64
+        rid = _c.c_uint64(0)
+        _check(self._lib.tw_server_ingest(self._h, _ptr(src), _ptr(dst), _ptr(ts), src.numel(),
+                                          _c.byref(rid)))
+        self._keep[rid.value] = (src, dst, ts)
+        return int(rid.value)
+
+    def wait(self, rid: int, timeout_s: Optional[float] = None) -> Optional[dict]:
+        """The finished request's result record, or None on timeout."""
+        out = _RequestResult()
+        us = -1 if timeout_s is None else int(timeout_s * 1e6)
+        rc = self._lib.tw_server_wait(self._h, _c.c_uint64(rid), us, _c.byref(out))
+        if rc == TW_ETIMEOUT:
+            return None
+        _check(rc)
+        self._keep.pop(rid, None)
+        return {"status": int(out.status), "num_walks": int(out.num_walks),
+                "max_len": int(out.max_len), "queue_ms": out.queue_ms,
+                "latency_ms": out.latency_ms, "ingest": _info(out.ingest)}
+
+    def result(self, rid: int):
+        """(nodes, ts, len) of a finished request, copied into new tensors."""
+        r = self.wait(rid)
+        W, L = r["num_walks"], r["max_len"]
+        nodes = torch.empty((max(W, 1), max(L, 1)), dtype=torch.int32, device=self.device)
+        ts = torch.empty((max(W, 1), max(L, 1)), dtype=torch.int64, device=self.device)
+        lens = torch.empty(max(W, 1), dtype=torch.int32, device=self.device)
+        _check(self._lib.tw_server_copy_out(self._h, _c.c_uint64(rid), _ptr(nodes), _ptr(ts),
+                                            _ptr(lens)))
+        return nodes[:W], ts[:W], lens[:W]
+
+    def release(self, rid: int):
+        _check(self._lib.tw_server_release(self._h, _c.c_uint64(rid)))
+
+    def stats(self) -> dict:
+        c = _ServerCounters()
+        _check(self._lib.tw_server_stats(self._h, _c.byref(c)))
+        return {k: getattr(c, k) for k, _ in _ServerCounters._fields_}
+
+    def close(self):
+        if self._h:
+            _check(self._lib.tw_server_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -148,6 +148,71 @@ tw_status tw_autotune(tw_graph* g, const tw_walk_params* params, int64_t sample_
     });
 }
 
+tw_status tw_server_create(tw_graph* g, const tw_server_config* cfg, tw_server** out) {
+    return guarded("tw_server_create", [&]() -> tw_status {
+        tw::Error e{TW_OK, ""};
+        return report(tw::server_create(g, cfg, out, e), e);
+    });
+}
+
+tw_status tw_server_submit(tw_server* s, const tw_walk_params* req, uint64_t* id) {
+    if (!s) return fail(TW_EINVAL, "tw_server_submit: null server");
+    return guarded("tw_server_submit", [&]() -> tw_status {
+        tw::Error e{TW_OK, ""};
+        return report(tw::server_submit(s, req, id, e), e);
+    });
+}
+
+tw_status tw_server_ingest(tw_server* s, const int32_t* d_src, const int32_t* d_dst,
+                           const int64_t* d_ts, int64_t n, uint64_t* id) {
+    if (!s) return fail(TW_EINVAL, "tw_server_ingest: null server");
+    return guarded("tw_server_ingest", [&]() -> tw_status {
+        tw::Error e{TW_OK, ""};
+        return report(tw::server_ingest(s, d_src, d_dst, d_ts, n, id, e), e);
+    });
+}
+
+tw_status tw_server_wait(tw_server* s, uint64_t id, int64_t timeout_us, tw_request_result* out) {
+    if (!s) return fail(TW_EINVAL, "tw_server_wait: null server");
+    return guarded("tw_server_wait", [&]() -> tw_status {
+        tw::Error e{TW_OK, ""};
+        return report(tw::server_wait(s, id, timeout_us, out, e), e);
+    });
+}
+
+tw_status tw_server_release(tw_server* s, uint64_t id) {
+    if (!s) return fail(TW_EINVAL, "tw_server_release: null server");
+    return guarded("tw_server_release", [&]() -> tw_status {
+        tw::Error e{TW_OK, ""};
+        return report(tw::server_release(s, id, e), e);
+    });
+}
+
+tw_status tw_server_copy_out(tw_server* s, uint64_t id, int32_t* d_nodes, int64_t* d_ts,
+                             int32_t* d_len) {
+    if (!s) return fail(TW_EINVAL, "tw_server_copy_out: null server");
+    return guarded("tw_server_copy_out", [&]() -> tw_status {
+        tw::Error e{TW_OK, ""};
+        return report(tw::server_copy_out(s, id, d_nodes, d_ts, d_len, e), e);
+    });
+}
+
+tw_status tw_server_stats(tw_server* s, tw_server_counters* out) {
+    if (!s) return fail(TW_EINVAL, "tw_server_stats: null server");
+    return guarded("tw_server_stats", [&]() -> tw_status {
+        tw::Error e{TW_OK, ""};
+        return report(tw::server_stats(s, out, e), e);
+    });
+}
+
+tw_status tw_server_destroy(tw_server* s) {
+    if (!s) return TW_OK;
+    return guarded("tw_server_destroy", [&]() -> tw_status {
+        tw::Error e{TW_OK, ""};
+        return report(tw::server_destroy(s, e), e);
+    });
+}
+
 tw_status tw_sync(tw_graph* g) {
     if (!g) return fail(TW_EINVAL, "tw_sync: null graph");
     if (hipStreamSynchronize(g->stream) != hipSuccess)

@@ -314,6 +314,8 @@ struct ServeReq {
     int64_t* ts;
     int32_t* len;
 };
+// Parameter checks of a walk request (as tw_sample_walks makes them).
+tw_status check_walk_params(const tw_walk_params* p, Error& err);
 // Device table bytes for n requests (d_table / h_table hold that much; the
 // host table should be pinned and must stay untouched until the launch's
 // copy has run).
@@ -322,6 +324,19 @@ size_t serve_table_bytes(int n);
 // *d_hops accumulates the launch's hops.
 tw_status serve_launch(tw_graph* g, const ServeReq* reqs, int n, void* d_table, void* h_table,
                        unsigned long long* d_hops, Error& err);
+
+// serve.hip
+tw_status server_create(tw_graph* g, const tw_server_config* cfg, tw_server** out, Error& err);
+tw_status server_submit(tw_server* s, const tw_walk_params* p, uint64_t* id, Error& err);
+tw_status server_ingest(tw_server* s, const int32_t* src, const int32_t* dst, const int64_t* ts,
+                        int64_t n, uint64_t* id, Error& err);
+tw_status server_wait(tw_server* s, uint64_t id, int64_t timeout_us, tw_request_result* out,
+                      Error& err);
+tw_status server_release(tw_server* s, uint64_t id, Error& err);
+tw_status server_copy_out(tw_server* s, uint64_t id, int32_t* nodes, int64_t* ts, int32_t* len,
+                          Error& err);
+tw_status server_stats(tw_server* s, tw_server_counters* out, Error& err);
+tw_status server_destroy(tw_server* s, Error& err);
 
 }  // namespace tw
 

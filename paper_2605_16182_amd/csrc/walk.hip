@@ -950,6 +950,16 @@ tw_status sample_walks_batch(tw_graph* g, const tw_batch_params* p, int32_t* nod
     return queue_walks(g, a, q, g->auto_bpc, err);
 }
 
+tw_status check_walk_params(const tw_walk_params* p, Error& err) {
+    if (!p || p->num_walks < 0 || p->max_len < 1) {
+        err = Error{TW_EINVAL, "walk request: need num_walks >= 0 and max_len >= 1"};
+        return err.code;
+    }
+    if (check_bias(p->hop_bias, true, err) != TW_OK) return err.code;
+    if (check_bias(p->start_bias, false, err) != TW_OK) return err.code;
+    return check_start(p->start_mode, p->d_start_nodes, p->num_walks, err);
+}
+
 size_t serve_table_bytes(int n) { return sizeof(ServeReqDev) * (size_t)std::max(n, 1); }
 
 tw_status serve_launch(tw_graph* g, const ServeReq* reqs, int n, void* d_table, void* h_table,
