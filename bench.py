@@ -36,7 +36,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="single", choices=["single", "tiny", "stream", "mixed"])
+    ap.add_argument("--workload", default="single",
+                    choices=["single", "tiny", "stream", "mixed", "serve"])
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="serve workload: seconds of real-time arrivals")
     ap.add_argument("--batches", type=int, default=0,
                     help="stream workload: number of 10M-edge batches (0 = the whole stream)")
     ap.add_argument("--dispatch", default="auto", choices=["auto", "full_walk", "coop", "queue"])
@@ -392,6 +395,157 @@ def run_mixed(args, torch, tw, w, dev, gather_rate):
     print(json.dumps(res), flush=True)
 
 
+def run_serve(args, torch, tw, w, dev, gather_rate):
+    """Serving loop in real time: the stream's first 40 s of edges are
+    ingested up front; then, for --serve-seconds of wall time, 5M edges/s
+    arrive in 100 ms batches and walk requests arrive Poisson at 2k/s (walk
+    count log-uniform in [1e2, 1e5], length 10, 40 or 80, a random hop bias),
+    all through one tw_server. Reports sustained hops/s and request latency."""
+    import threading
+    import synth
+    spec = w["stream"]
+    rate = w["edges_per_s"]
+    warm_edges = int(40 * rate)
+    live_s = args.serve_seconds
+    step = int(rate * 0.1)
+    nb = int(live_s / 0.1)
+    gen = spec.batches(step)
+    warm = [next(gen) for _ in range(warm_edges // step)]
+    s0, d0, t0_ = (np.concatenate([b[k] for b in warm]) for k in range(3))
+    del warm
+    g = tw.Graph(spec.num_nodes, directed=spec.directed, window=w["window"])
+    info = g.ingest_batch(*(torch.from_numpy(a).to(dev) for a in (s0, d0, t0_)))
+    del s0, d0, t0_
+    tau = 0.1 * float(w["window"])
+    live = [tuple(torch.from_numpy(a).to(dev) for a in next(gen)) for _ in range(nb)]
+    torch.cuda.synchronize()
+    print(f"# warm window {info['active_edges']} edges; {nb} live batches of {step}",
+          file=sys.stderr, flush=True)
+    rng = np.random.default_rng(7)
+    n_req = rng.poisson(w["requests_per_s"] * live_s)
+    arrivals = np.sort(rng.uniform(0.0, live_s, n_req))
+    counts = np.exp(rng.uniform(np.log(1e2), np.log(1e5), n_req)).astype(np.int64)
+    lens = rng.choice([10, 40, 80], n_req)
+    kinds = rng.choice(["uniform", "linear", "exponential", "node2vec"], n_req)
+    srv = tw.Server(g, arena_bytes=w["arena_bytes"], max_walks_per_launch=1 << 20,
+                    max_inflight=2)
+    done_lat = []
+    submitted = []
+    cond = threading.Condition()
+    finished = [False]
+
+    def reaper():
+        k = 0
+        while True:
+            with cond:
+                while k >= len(submitted) and not finished[0]:
+                    cond.wait()
+                if k >= len(submitted):
+                    return
+                rid, is_req = submitted[k]
+            r = srv.wait(rid)
+            if is_req:
+                done_lat.append(r["latency_ms"])
+                srv.release(rid)
+            k += 1
+
+    th = threading.Thread(target=reaper)
+    th.start()
+    events = sorted([(i * 0.1, 0, i) for i in range(len(live))] +
+                    [(float(a), 1, i) for i, a in enumerate(arrivals)])
+    offered_walks = int(counts.sum())
+    t_start = time.perf_counter()
+    for when, kind, i in events:
+        now = time.perf_counter() - t_start
+        if when > now:
+            time.sleep(when - now)
+        if kind == 0:
+            rid = srv.ingest(*live[i])
+        else:
+            rid = srv.submit(int(counts[i]), int(lens[i]), hop_bias=str(kinds[i]), hop_tau=tau,
+                             p=0.5, q=2.0, seed=int(i), walk_id_base=0)
+        with cond:
+            submitted.append((rid, kind == 1))
+            cond.notify()
+    with cond:
+        finished[0] = True
+        cond.notify()
+    th.join()
+    wall = time.perf_counter() - t_start
+    st = srv.stats()
+    srv.close()
+    lat = np.array(done_lat)
+    hops_s = st["hops_done"] / wall
+
+    # saturation: a burst of requests submitted at once through a server,
+    # against the same requests as one tw_sample_walks call each
+    nburst = 2000
+    bidx = np.arange(nburst) % max(n_req, 1)
+    burst = [dict(num_walks=int(counts[i]), max_len=int(lens[i]), hop_bias=str(kinds[i]),
+                  hop_tau=tau, p=0.5, q=2.0, seed=int(i), walk_id_base=0) for i in bidx]
+    srv = tw.Server(g, arena_bytes=w["arena_bytes"], max_walks_per_launch=1 << 20,
+                    max_inflight=2)
+    t0 = time.perf_counter()
+    ids = [srv.submit(**r) for r in burst]
+    bhops = 0
+    for rid in ids:
+        srv.wait(rid)
+        srv.release(rid)
+    t_served = time.perf_counter() - t0
+    bst = srv.stats()
+    srv.close()
+    Lmax, Wmax = 80, int(counts.max())
+    out = (torch.empty((Wmax, Lmax), dtype=torch.int32, device=dev),
+           torch.empty((Wmax, Lmax), dtype=torch.int64, device=dev),
+           torch.empty(Wmax, dtype=torch.int32, device=dev))
+    g.sample_walks(1000, 10, out=(out[0].view(-1)[:10_000].view(1000, 10),
+                                  out[1].view(-1)[:10_000].view(1000, 10), out[2][:1000]))
+    g.sync()
+    t0 = time.perf_counter()
+    phops = torch.zeros((), dtype=torch.int64, device=dev)
+    for r in burst:
+        n, L = r["num_walks"], r["max_len"]
+        o = (out[0].view(-1)[:n * L].view(n, L), out[1].view(-1)[:n * L].view(n, L), out[2][:n])
+        g.sample_walks(n, L, hop_bias=r["hop_bias"], hop_tau=tau, p=0.5, q=2.0, seed=r["seed"],
+                       out=o)
+        phops += (o[2].to(torch.int64) - 1).clamp_min(0).sum()
+    g.sync()
+    t_plain = time.perf_counter() - t0
+    plain_hops = int(phops.item())
+    g.close()
+    assert plain_hops == bst["hops_done"], "served and plain walks differ"
+    res = {
+        "metric": METRIC, "value": hops_s, "unit": "hops/s", "n_gpus": 1,
+        "steps": int(st["launches"]), "warmup": 0, "ms_per_step": wall * 1e3 / max(st["launches"], 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64+f64", "data": "synthetic",
+        "config": {"workload": "serve", "nodes": spec.num_nodes, "src_zipf": spec.src_s,
+                   "window_ns": w["window"], "edges_per_s": rate, "warm_edges": warm_edges,
+                   "requests_per_s": w["requests_per_s"], "walks_per_request": "log-uniform 1e2..1e5",
+                   "max_len": [10, 40, 80], "hop_biases": ["uniform", "linear", "exponential",
+                                                           "node2vec(0.5,2)"],
+                   "seconds": live_s},
+        "serving": {"requests": int(st["requests_done"]), "walks": int(st["walks_done"]),
+                    "offered_walks": offered_walks, "hops": int(st["hops_done"]),
+                    "launches": int(st["launches"]), "ingests": int(st["ingests"]),
+                    "ingested_edges": int(len(live) * step), "wall_s": wall,
+                    "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
+                    "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+                    "max_ms": float(lat.max()) if len(lat) else None,
+                    "server_p50_ms": st["p50_ms"], "server_p99_ms": st["p99_ms"],
+                    "active_edges_at_start": info["active_edges"]},
+        "batched_vs_plain": {
+            "requests": nburst, "walks": int(bst["walks_done"]), "hops": plain_hops,
+            "served": {"seconds": t_served, "hops_per_s": plain_hops / t_served,
+                       "launches": int(bst["launches"])},
+            "plain_per_request": {"seconds": t_plain, "hops_per_s": plain_hops / t_plain,
+                                  "launches": nburst}},
+        "gather_roofline": {"random_sectors_per_s": gather_rate, "sectors_per_hop": 4,
+                            "frac": hops_s / (gather_rate / 4) if gather_rate else None},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -405,6 +559,9 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     w = synth.workload(args.workload)
+    if args.workload == "serve":
+        gather_rate, _ = (0.0, 0.0) if args.no_probe else probe_rates(torch, dev)
+        return run_serve(args, torch, tw, w, dev, gather_rate)
     if args.workload == "mixed":
         gather_rate, _ = (0.0, 0.0) if args.no_probe else probe_rates(torch, dev)
         return run_mixed(args, torch, tw, w, dev, gather_rate)

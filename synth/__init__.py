@@ -241,7 +241,8 @@ WORKLOADS = {
     "serve": dict(stream=dict(num_nodes=10_000_000, num_edges=300_000_000, src_s=1.2, dst_s=1.2,
                               ts_kind="poisson", mean_gap=200.0, seed=5),
                   window=60_000_000_000, walks=None, max_len=80, start_bias="uniform",
-                  hop_bias="mixed", tau_frac=0.1, batch_edges=5_000_000),
+                  hop_bias="mixed", tau_frac=0.1, batch_edges=5_000_000,
+                  edges_per_s=5_000_000, requests_per_s=2000, arena_bytes=8 << 30),
 }
 
 
