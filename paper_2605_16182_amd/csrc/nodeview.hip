@@ -45,7 +45,9 @@ struct Job {
     uint32_t bf, be;                 // batch run in the source-sorted batch
     uint32_t e0, ecap, g0, gcode, f0;  // the segment after the job
     uint32_t e_at, g_at;             // first written edge / first new group
+    uint32_t kshift;                 // fence key shift of the segment after the job
     int64_t t_last;                  // last surviving old timestamp (INT64_MIN: none)
+    int64_t kbase;                   // fence key base of the segment after the job
 };
 
 __device__ __forceinline__ NodeRec empty_rec() {
@@ -176,7 +178,8 @@ __global__ void k_active_flags(const NodeRec* __restrict__ rec, int64_t V,
 __global__ void k_job_setup(const uint32_t* __restrict__ c_node, const uint32_t* __restrict__ c_bf,
                             const uint32_t* __restrict__ c_be, int64_t nj,
                             const NodeRec* __restrict__ rec, const SegRec* __restrict__ seg,
-                            const GroupRec* __restrict__ ng, const int64_t* __restrict__ bts,
+                            const GroupRec* __restrict__ ng, const uint32_t* __restrict__ fence,
+                            const int64_t* __restrict__ bts,
                             int evicting, int64_t cut, int rewrite_all, uint32_t gen,
                             Job* __restrict__ jobs, uint32_t* __restrict__ cnt,
                             uint32_t* __restrict__ req_e, uint32_t* __restrict__ req_g,
@@ -209,7 +212,17 @@ __global__ void k_job_setup(const uint32_t* __restrict__ c_node, const uint32_t*
     uint32_t c = 0, re = 0, rg = 0, rf = 0;
     if ((k > 0 || rewrite_all) && ne + k > 0) {
         const bool after = ne == 0 || k == 0 || bts[J.bf] >= J.t_last;
-        if (!rewrite_all && has_seg && ne > 0 && after &&
+        // an append keeps the segment's key base and shift: its last
+        // timestamp must still have a key below UINT32_MAX
+        bool keys_fit = true;
+        if (has_seg && ne > 0 && k > 0 && fence_cap(seg_groups(sg.gcode)) > 0) {
+            const uint32_t* h = fence + sg.f0;
+            J.kbase = (int64_t)(((uint64_t)h[1] << 32) | h[0]);
+            J.kshift = h[2];
+            keys_fit = bts[J.be - 1] >= J.kbase &&
+                       ((uint64_t)(bts[J.be - 1] - J.kbase) >> J.kshift) < 0xFFFFFFFFull;
+        }
+        if (!rewrite_all && has_seg && ne > 0 && after && keys_fit &&
             (uint64_t)J.oe + k <= (uint64_t)sg.e0 + sg.ecap &&
             (uint64_t)ge + k <= (uint64_t)sg.g0 + seg_groups(sg.gcode)) {
             J.kind = JOB_APPEND;
@@ -238,6 +251,21 @@ __global__ void k_job_setup(const uint32_t* __restrict__ c_node, const uint32_t*
             rg = (uint32_t)seg_groups(J.gcode);
             rf = fence_cap(rg);
             c = ne + k;
+        }
+        if (J.kind == JOB_REWRITE) {
+            // keys of the rewritten run: base its first timestamp, the shift
+            // for its span (both runs are sorted by timestamp)
+            int64_t lo = INT64_MAX, hi = INT64_MIN;
+            if (ne > 0) {
+                lo = ng[gb].ts;
+                hi = r.t_last;
+            }
+            if (k > 0) {
+                lo = std::min(lo, bts[J.bf]);
+                hi = std::max(hi, bts[J.be - 1]);
+            }
+            J.kbase = lo;
+            J.kshift = fence_shift((uint64_t)(hi - lo));
         }
     }
     jobs[j] = J;
@@ -363,8 +391,8 @@ __global__ void __launch_bounds__(T) k_job_flags(const Job* __restrict__ jobs,
     }
 }
 
-// every job output's edge, and the group record of each group start (rank =
-// exclusive scan of the flags)
+// every job output's edge, and the group record and level-0 fence key of
+// each group start (rank = exclusive scan of the flags)
 __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
                                                  const uint32_t* __restrict__ off, int64_t nj,
                                                  int64_t total, const int32_t* __restrict__ odst,
@@ -375,7 +403,8 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
                                                  const uint32_t* __restrict__ rank,
                                                  int32_t* __restrict__ ndst,
                                                  int64_t* __restrict__ nts,
-                                                 GroupRec* __restrict__ ngd) {
+                                                 GroupRec* __restrict__ ngd,
+                                                 uint32_t* __restrict__ fence) {
     __shared__ uint32_t jr[2];
     const int64_t base = (int64_t)blockIdx.x * NV_TILE;
     tile_jobs(off, nj, (uint64_t)base, (uint64_t)std::min<int64_t>(base + NV_TILE, total) - 1,
@@ -396,20 +425,49 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
             g.ts = e.ts;
             g.first = pos;
             g.dst = e.dst;
-            ngd[J.g_at + (rank[t] - rank[jb])] = g;
+            const uint32_t gi = J.g_at + (rank[t] - rank[jb]);
+            ngd[gi] = g;
+            // the group's level-0 fence key (segments of more than
+            // FENCE_FAN groups have a fence)
+            if (J.gcode > 0)
+                fence[(uint64_t)J.f0 + FENCE_HDR + (gi - J.g0)] =
+                    (uint32_t)((uint64_t)(e.ts - J.kbase) >> J.kshift);
         }
     }
 }
 
-// fence entries a job writes at level k: the new groups [from, to) of a
-// segment starting at g0 that land on the level's grid
-__device__ __forceinline__ uint64_t level_span(uint32_t g0, uint32_t from, uint32_t to, int k,
-                                               uint64_t* first) {
-    const uint64_t step = 1ull << (FENCE_LOG * k);
-    const uint64_t lo = ((uint64_t)(from - g0) + step - 1) >> (FENCE_LOG * k);
-    const uint64_t hi = ((uint64_t)(to - g0) + step - 1) >> (FENCE_LOG * k);
-    *first = lo;
-    return hi - lo;
+// Level k of a segment with n groups in use holds the keys of its entries
+// [0, level_count(n, k)) and UINT32_MAX up to the next multiple of FENCE_FAN
+// (every 8-entry window a search can reach); entries past that are never read.
+__device__ __forceinline__ uint64_t level_count(uint64_t n, int k) {
+    return (n + (1ull << (FENCE_LOG * k)) - 1) >> (FENCE_LOG * k);
+}
+
+__device__ __forceinline__ uint64_t pad_fan(uint64_t c) {
+    return (c + FENCE_FAN - 1) & ~(uint64_t)(FENCE_FAN - 1);
+}
+
+// Fence words a rewrite of a segment of cap groups with n in use leaves to
+// k_job_fence (k_job_write stores the level-0 keys with the group records).
+__device__ __forceinline__ uint32_t rewrite_words(uint64_t cap, uint64_t n) {
+    if (fence_cap(cap) == 0) return 0;
+    uint64_t w = FENCE_HDR + pad_fan(n) - n;  // level 0: its padding only
+    const int K = fence_levels(cap);
+    for (int k = 1; k <= K; ++k) w += pad_fan(level_count(n, k));
+    return (uint32_t)w;
+}
+
+// What an append from n0 to n1 groups in use writes at level k: keys of the
+// entries [key0, key0 + nkeys), UINT32_MAX at [pad0, pad0 + npad). The
+// level-0 keys are k_job_write's; k_job_fence writes the rest.
+struct LevelWrite {
+    uint64_t key0, nkeys, pad0, npad;
+};
+
+__device__ __forceinline__ LevelWrite append_level(uint64_t n0, uint64_t n1, int k) {
+    const uint64_t c0 = level_count(n0, k), c1 = level_count(n1, k);
+    const uint64_t p0 = c1 > pad_fan(c0) ? c1 : pad_fan(c0), p1 = pad_fan(c1);
+    return LevelWrite{c0, c1 - c0, p0, p1 > p0 ? p1 - p0 : 0};
 }
 
 // New node records (and segments) of the jobs, and the fence entries each
@@ -435,16 +493,18 @@ __global__ void k_job_finish(const Job* __restrict__ jobs, const uint32_t* __res
             r.gb = J.ogb;
             r.ge = J.oge + newg;
             r.ee = J.oe + written;
-            const int K = fence_levels(cap);
-            for (int k = 1; k <= K; ++k) {
-                uint64_t first;
-                f += (uint32_t)level_span(J.g0, J.oge, r.ge, k, &first);
+            if (fence_cap(cap) > 0) {
+                const int K = fence_levels(cap);
+                for (int k = 0; k <= K; ++k) {
+                    const LevelWrite lw = append_level(J.oge - J.g0, r.ge - J.g0, k);
+                    f += (uint32_t)((k > 0 ? lw.nkeys : 0) + lw.npad);
+                }
             }
         } else {
             r.gb = J.g0;
             r.ge = J.g0 + newg;
             r.ee = J.e_at + written;
-            f = fence_cap(cap);
+            f = rewrite_words(cap, newg);
             if (J.fresh) {
                 SegRec s;
                 s.e0 = J.e0;
@@ -466,34 +526,53 @@ __global__ void k_job_finish(const Job* __restrict__ jobs, const uint32_t* __res
     fw[j] = f;
 }
 
-// value and position of fence entry u of job J (u counts the entries the
-// job writes)
+// Fence word u of job J (u counts the words the job writes): a rewritten
+// segment writes its header (key base and shift) and, on every level, the
+// keys and the padding; an append the keys and padding its new groups add.
+// Level-0 keys are written by k_job_write, so level 0 contributes padding only.
 __device__ __forceinline__ void fence_entry(const Job& J, uint32_t ge,
                                             const GroupRec* __restrict__ ngd,
-                                            int64_t* __restrict__ fence, uint64_t u) {
+                                            uint32_t* __restrict__ fence, uint64_t u) {
     const uint64_t cap = seg_groups(J.gcode);
-    const int K = fence_levels(cap);
-    uint64_t base = 0;
-    for (int k = 1; k <= K; ++k) {
-        const uint32_t len = fence_level_len(cap, k);
-        if (J.kind == JOB_REWRITE) {
-            if (u < len) {
-                const uint64_t g = (uint64_t)J.g0 + (u << (FENCE_LOG * k));
-                fence[J.f0 + base + u] = g < ge ? ngd[g].ts : INT64_MAX;
-                return;
-            }
-            u -= len;
-        } else {
-            uint64_t first;
-            const uint64_t c = level_span(J.g0, J.oge, ge, k, &first);
-            if (u < c) {
-                const uint64_t i = first + u;
-                fence[J.f0 + base + i] = ngd[J.g0 + (i << (FENCE_LOG * k))].ts;
-                return;
-            }
-            u -= c;
+    uint32_t* f = fence + J.f0;
+    const uint64_t n = ge - J.g0;
+    if (J.kind == JOB_REWRITE) {
+        if (u < FENCE_HDR) {
+            f[u] = u == 0 ? (uint32_t)(uint64_t)J.kbase
+                          : u == 1 ? (uint32_t)((uint64_t)J.kbase >> 32) : u == 2 ? J.kshift : 0u;
+            return;
         }
-        base += len;
+        u -= FENCE_HDR;
+    }
+    const int K = fence_levels(cap);
+    uint64_t off = FENCE_HDR;
+    for (int k = 0; k <= K; ++k) {
+        uint64_t key0 = 0, nkeys, pad0, npad;
+        if (J.kind == JOB_REWRITE) {
+            nkeys = level_count(n, k);
+            pad0 = nkeys;
+            npad = pad_fan(nkeys) - nkeys;
+        } else {
+            const LevelWrite lw = append_level(J.oge - J.g0, n, k);
+            key0 = lw.key0;
+            nkeys = lw.nkeys;
+            pad0 = lw.pad0;
+            npad = lw.npad;
+        }
+        if (k == 0) nkeys = 0;
+        if (u < nkeys) {
+            const uint64_t i = key0 + u;
+            f[off + i] = (uint32_t)((uint64_t)(ngd[J.g0 + (i << (FENCE_LOG * k))].ts - J.kbase) >>
+                                    J.kshift);
+            return;
+        }
+        u -= nkeys;
+        if (u < npad) {
+            f[off + pad0 + u] = 0xFFFFFFFFu;
+            return;
+        }
+        u -= npad;
+        off += fence_level_len(cap, k);
     }
 }
 
@@ -503,7 +582,7 @@ __global__ void __launch_bounds__(T) k_job_fence(const Job* __restrict__ jobs,
                                                  const uint32_t* __restrict__ foff, int64_t nj,
                                                  const NodeRec* __restrict__ rec,
                                                  const GroupRec* __restrict__ ngd,
-                                                 int64_t* __restrict__ fence) {
+                                                 uint32_t* __restrict__ fence) {
     __shared__ uint32_t jr[2];
     const uint64_t total = foff[nj];
     for (uint64_t base = (uint64_t)blockIdx.x * NV_TILE; base < total;
@@ -682,7 +761,8 @@ tw_status plan_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool re
     if (ensure_jobs(g, nj, err) != TW_OK) return err.code;
     hipLaunchKernelGGL(k_job_setup, grid_for(nj), dim3(T), 0, s, g->c_node.as<uint32_t>(),
                        g->c_bf.as<uint32_t>(), g->c_be.as<uint32_t>(), nj, g->rec.as<NodeRec>(),
-                       g->seg.as<SegRec>(), g->ng.as<GroupRec>(), g->bs_ts.as<int64_t>(),
+                       g->seg.as<SegRec>(), g->ng.as<GroupRec>(), g->fence.as<uint32_t>(),
+                       g->bs_ts.as<int64_t>(),
                        evicting ? 1 : 0, cut, rewrite_all ? 1 : 0, gen, g->jobs.as<Job>(),
                        g->j_cnt.as<uint32_t>(), g->j_re.as<uint32_t>(), g->j_rg.as<uint32_t>(),
                        g->j_rf.as<uint32_t>());
@@ -706,7 +786,7 @@ tw_status plan_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool re
 // writes into the destination pools (the same ones unless rewriting all).
 tw_status execute_jobs(tw_graph* g, int64_t nj, uint64_t out, const int32_t* sdst,
                        const int64_t* sts, int32_t* ddst, int64_t* dts, GroupRec* dng,
-                       int64_t* dfence, uint32_t gen, Error& err) {
+                       uint32_t* dfence, uint32_t gen, Error& err) {
     hipStream_t s = g->stream;
     Job* jobs = g->jobs.as<Job>();
     const uint32_t* off = g->j_off.as<uint32_t>();
@@ -721,7 +801,7 @@ tw_status execute_jobs(tw_graph* g, int64_t nj, uint64_t out, const int32_t* sds
     if (out > 0)
         hipLaunchKernelGGL(k_job_write, dim3((unsigned)ceil_div((int64_t)out, NV_TILE)), dim3(T), 0,
                            s, jobs, off, nj, (int64_t)out, sdst, sts, g->bs_dst.as<int32_t>(),
-                           g->bs_ts.as<int64_t>(), oflag, rank, ddst, dts, dng);
+                           g->bs_ts.as<int64_t>(), oflag, rank, ddst, dts, dng, dfence);
     hipLaunchKernelGGL(k_job_finish, grid_for(nj), dim3(T), 0, s, jobs, off, nj, rank, dng,
                        g->rec.as<NodeRec>(), g->seg.as<SegRec>(), gen, g->j_fw.as<uint32_t>());
     TW_HIP(scan_jobs(g->j_fw.as<uint32_t>(), g->j_fw.as<uint32_t>(), nj, g->ws, s));
@@ -769,7 +849,7 @@ tw_status run_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool rew
                            (uint32_t)g->pe_top, (uint32_t)g->pg_top, (uint32_t)g->pf_top);
         if (execute_jobs(g, nj, tot[0], g->n_dst.as<int32_t>(), g->n_ts.as<int64_t>(),
                          g->n_dst.as<int32_t>(), g->n_ts.as<int64_t>(), g->ng.as<GroupRec>(),
-                         g->fence.as<int64_t>(), gen, err) != TW_OK)
+                         g->fence.as<uint32_t>(), gen, err) != TW_OK)
             return err.code;
         g->pe_top += (int64_t)tot[1];
         g->pg_top += (int64_t)tot[2];
@@ -788,13 +868,13 @@ tw_status run_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool rew
     TW_HIP(ensure(g->an_dst, sizeof(int32_t) * ce));
     TW_HIP(ensure(g->an_ts, sizeof(int64_t) * ce));
     TW_HIP(ensure(g->ang, sizeof(GroupRec) * cg));
-    TW_HIP(ensure(g->afence, sizeof(int64_t) * cf));
+    TW_HIP(ensure(g->afence, sizeof(uint32_t) * cf));
     hipLaunchKernelGGL(k_job_place, grid_for(nj), dim3(T), 0, s, g->jobs.as<Job>(), nj,
                        g->j_re.as<uint32_t>(), g->j_rg.as<uint32_t>(), g->j_rf.as<uint32_t>(), 0u,
                        0u, 0u);
     if (execute_jobs(g, nj, tot[0], g->n_dst.as<int32_t>(), g->n_ts.as<int64_t>(),
                      g->an_dst.as<int32_t>(), g->an_ts.as<int64_t>(), g->ang.as<GroupRec>(),
-                     g->afence.as<int64_t>(), gen, err) != TW_OK)
+                     g->afence.as<uint32_t>(), gen, err) != TW_OK)
         return err.code;
     std::swap(g->n_dst, g->an_dst);
     std::swap(g->n_ts, g->an_ts);
@@ -803,7 +883,7 @@ tw_status run_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool rew
     g->pe_cap = (int64_t)(g->n_dst.bytes / sizeof(int32_t));
     g->pe_cap = std::min<int64_t>(g->pe_cap, (int64_t)(g->n_ts.bytes / sizeof(int64_t)));
     g->pg_cap = (int64_t)(g->ng.bytes / sizeof(GroupRec));
-    g->pf_cap = (int64_t)(g->fence.bytes / sizeof(int64_t));
+    g->pf_cap = (int64_t)(g->fence.bytes / sizeof(uint32_t));
     g->pe_cap = std::min(g->pe_cap, lim);
     g->pg_cap = std::min(g->pg_cap, lim);
     g->pf_cap = std::min(g->pf_cap, lim);

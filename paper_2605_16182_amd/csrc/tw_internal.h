@@ -39,23 +39,30 @@ struct alignas(32) NodeRec {
     int64_t t_last;
 };
 
-// Fence index. The fence of a segment with capacity C groups has levels
-// k = 1..K(C); level k holds the timestamps of groups g0 + i FENCE_FAN^k, i <
-// ceil(C / FENCE_FAN^k), padded to a multiple of FENCE_FAN entries; entries
-// of groups not written yet hold INT64_MAX. Level 1 is stored first. A
-// search over the groups [g0, ge) starts at level K(ge - g0), the smallest
-// level with at most FENCE_FAN entries in use, reads one FENCE_FAN-entry
-// window (64 bytes, aligned) per level and one aligned window of group
-// records. Groups evicted from the front of the segment stay in place until
-// the segment is rewritten; their timestamps precede every live one.
+// Fence index with 32-bit keys. A segment of capacity C > FENCE_FAN groups
+// has a fence of FENCE_HDR header words (the key base, a 64-bit timestamp,
+// in words 0-1 and the key shift in word 2) and levels k = 0..K(C): level k
+// holds the keys of groups g0 + i FENCE_FAN^k, i < ceil(C / FENCE_FAN^k),
+// padded to a multiple of FENCE_FAN words; key(g) = (ts(g) - base) >> shift,
+// and unwritten entries hold UINT32_MAX. Ingest keeps every key of a segment
+// below UINT32_MAX (a batch that would not fit rewrites the segment with a
+// new base and shift). Keys are monotone in the timestamp; where a key equals
+// the query's, the group's own timestamp decides. A search over the groups
+// [g0, ge) starts at level K(ge - g0), the smallest level with at most
+// FENCE_FAN entries in use, and reads one FENCE_FAN-word window (32 bytes,
+// two 16-byte loads) per level down to level 0. Groups evicted from the
+// front of the segment stay in place until the segment is rewritten; their
+// timestamps precede every live one. Segments of at most FENCE_FAN groups
+// have no fence: their few groups are counted directly.
 constexpr int FENCE_FAN = 8;
 constexpr int FENCE_LOG = 3;
+constexpr int FENCE_HDR = 8;  // header words (32 bytes)
 
 // most levels a fence can have: group indices are 32-bit
 constexpr int FENCE_MAX_LEVELS = (32 + FENCE_LOG - 1) / FENCE_LOG + 1;
 static_assert((1 << FENCE_LOG) == FENCE_FAN, "FENCE_FAN must be 2^FENCE_LOG");
 
-// levels needed for n groups: 0 when n <= FENCE_FAN
+// levels above level 0 needed for n groups: 0 when n <= FENCE_FAN
 __host__ __device__ inline int fence_levels(uint64_t n) {
     int k = 0;
     while (n > (uint64_t)FENCE_FAN) {
@@ -65,17 +72,33 @@ __host__ __device__ inline int fence_levels(uint64_t n) {
     return k;
 }
 
-// entries stored for level k (k >= 1) of a segment of cap groups
+// words stored for level k (k >= 0) of a segment of cap groups
 __host__ __device__ inline uint32_t fence_level_len(uint64_t cap, int k) {
     const uint64_t n = (cap + (1ull << (FENCE_LOG * k)) - 1) >> (FENCE_LOG * k);
     return (uint32_t)((n + FENCE_FAN - 1) / FENCE_FAN * FENCE_FAN);
 }
 
-// total fence entries of a segment of cap groups
+// total fence words of a segment of cap groups (0: no fence)
 __host__ __device__ inline uint32_t fence_cap(uint64_t cap) {
-    uint32_t s = 0;
+    if (cap <= (uint64_t)FENCE_FAN) return 0;
+    uint32_t s = FENCE_HDR;
     const int K = fence_levels(cap);
-    for (int k = 1; k <= K; ++k) s += fence_level_len(cap, k);
+    for (int k = 0; k <= K; ++k) s += fence_level_len(cap, k);
+    return s;
+}
+
+// word offset of level k inside a segment's fence
+__host__ __device__ inline uint32_t fence_level_off(uint64_t cap, int k) {
+    uint32_t off = FENCE_HDR;
+    for (int j = 0; j < k; ++j) off += fence_level_len(cap, j);
+    return off;
+}
+
+// key shift for a segment whose keys must reach span (keep a 4x margin for
+// later appends before a rewrite)
+__host__ __device__ inline uint32_t fence_shift(uint64_t span) {
+    uint32_t s = 0;
+    while ((span >> s) >= (1ull << 30)) ++s;
     return s;
 }
 
@@ -205,7 +228,7 @@ struct tw_graph {
     // group pool (ng, GroupRec) and the fence pool (fence). New segments are
     // taken from the top of each pool; when a pool is full every active node
     // is rewritten into the alternate pools (an_*), which then swap in.
-    tw::DevBuf n_dst, n_ts, ng, fence;
+    tw::DevBuf n_dst, n_ts, ng, fence;  // fence: uint32 words
     tw::DevBuf an_dst, an_ts, ang, afence;
     int64_t pe_top = 0, pe_cap = 0, pg_top = 0, pg_cap = 0, pf_top = 0, pf_cap = 0;
     uint32_t pool_gen = 1;             // segments of older generations are void

@@ -41,7 +41,7 @@ struct WalkArgs {
     const int64_t* n_ts;
     const GroupRec* ng;
     const NodeRec* rec;
-    const int64_t* fence;
+    const uint32_t* fence;
     const int32_t* adj;
     const uint2* adj_rng;
     int32_t V;
@@ -373,6 +373,93 @@ __global__ void __launch_bounds__(WALK_THREADS) k_walk_queue(const WalkArgs a, c
     }
 }
 
+// Live walks between steps: current node, walk index, current timestamp.
+struct Live {
+    uint32_t* node;
+    uint32_t* walk;
+    uint64_t* t;
+};
+
+// Hops of the live walks after their start (k_coop_start and
+// k_compact_live leave them in `live`, n_live of them): the work queue
+// without the start pick, so a lane that takes a walk only loads its state
+// and the kernel keeps the registers of the full-walk kernel.
+template <int HK>
+__global__ void __launch_bounds__(WALK_THREADS)
+k_walk_hops(const WalkArgs a, Live live, const int32_t* __restrict__ prev_of,
+            const uint32_t* __restrict__ n_live_p, unsigned long long* counters) {
+    const int lane = threadIdx.x & 63;
+    const int64_t W = *n_live_p;
+    const int64_t slice_len = (W + QUEUE_SLICES - 1) / QUEUE_SLICES;
+    int slice = (int)(blockIdx.x % QUEUE_SLICES);
+    int exhausted = 0;
+    int64_t w = -1;
+    uint64_t id = 0, hop = 0;
+    int32_t len = 0, cur = 0, prev = 0;
+    int64_t tcur = 0;
+    int32_t* out_n = nullptr;
+    int64_t* out_t = nullptr;
+    const HopBias hb = fixed_hop<HK>(a.hop);
+    while (true) {
+        const uint64_t idle = __ballot(w < 0);
+        if (idle && exhausted < QUEUE_SLICES) {
+            const int n = __popcll(idle);
+            const int leader = __ffsll((unsigned long long)idle) - 1;
+            unsigned long long got = 0;
+            if (lane == leader) got = atomicAdd(&counters[slice], (unsigned long long)n);
+            got = __shfl(got, leader, 64);
+            const int64_t lo = (int64_t)slice * slice_len;
+            const int64_t hi = lo + slice_len < W ? lo + slice_len : W;
+            if (w < 0) {
+                const int rank = __popcll(idle & ((1ull << lane) - 1));
+                const int64_t j = lo + (int64_t)got + rank;
+                if (j < hi) {
+                    w = live.walk[j];
+                    cur = (int32_t)live.node[j];
+                    tcur = (int64_t)live.t[j];
+                    prev = prev_of[w];
+                    id = a.base + (uint64_t)w;
+                    out_n = a.nodes + w * (int64_t)a.L;
+                    out_t = a.ts + w * (int64_t)a.L;
+                    len = 2;
+                    hop = 1;
+                }
+            }
+            if (lo + (int64_t)got + n >= hi) {
+                slice = (slice + 1) % QUEUE_SLICES;
+                ++exhausted;
+            }
+        }
+        if (__ballot(w >= 0) == 0) {
+            if (exhausted >= QUEUE_SLICES) break;
+            continue;
+        }
+        if (w >= 0) {
+            bool done = true;
+            const NodeRec r = a.rec[cur];
+            if (tcur < r.t_last) {
+                const uint32_t gc = fence_search(a.ng, a.fence, r, tcur, nullptr, 0, 0);
+                Pick p;
+                int32_t nx;
+                if (hop_pick(a, hb, a.seed, r, gc, id, hop, prev, p, nx)) {
+                    out_n[len] = nx;
+                    out_t[len] = p.t;
+                    ++len;
+                    ++hop;
+                    prev = cur;
+                    cur = nx;
+                    tcur = p.t;
+                    done = len >= a.L;
+                }
+            }
+            if (done) {
+                a.len[w] = len;
+                w = -1;
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------------- serve
 //
 // A serving launch: the walks of several requests, each with its own seed,
@@ -514,12 +601,6 @@ k_walk_serve(const WalkArgs a, const ServeReqDev* __restrict__ reqs, int nreq,
 
 // Live walks of one step, structure of arrays in one order: current node,
 // walk index, time of arrival.
-struct Live {
-    uint32_t* node;
-    uint32_t* walk;
-    uint64_t* t;
-};
-
 template <int SK>
 __global__ void __launch_bounds__(WALK_THREADS) k_coop_start(const WalkArgs a, Live nx,
                                                               int32_t* __restrict__ prev,
@@ -559,7 +640,7 @@ template <int HK>
 __global__ void __launch_bounds__(WALK_THREADS)
 k_hop_coop(const WalkArgs a, Live cur, Live nxt, int32_t* __restrict__ prev_of, int64_t n,
            uint64_t hop, uint32_t panel_cap, uint32_t* __restrict__ alive) {
-    extern __shared__ __align__(16) int64_t panel[];
+    extern __shared__ __align__(16) uint32_t panel[];
     __shared__ int32_t wave_node[WALK_THREADS / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
@@ -577,21 +658,21 @@ k_hop_coop(const WalkArgs a, Live cur, Live nxt, int32_t* __restrict__ prev_of, 
     // uniform workgroup, a quarter of it per uniform wavefront otherwise.
     // Levels are stored bottom-up, so levels K down to some m are one
     // contiguous range.
-    const int64_t* my_panel = nullptr;
+    const uint32_t* my_panel = nullptr;
     uint64_t my_base = 0;
     uint32_t my_cap = 0;
     if (wg_uniform || wave_uniform) {
         const int32_t node = wg_uniform ? wave_node[0] : v0;
         const NodeRec r = a.rec[node];
         const uint32_t slice = wg_uniform ? panel_cap : panel_cap / (WALK_THREADS / 64);
-        int64_t* dst = wg_uniform ? panel : panel + wave * slice;
+        uint32_t* dst = wg_uniform ? panel : panel + wave * slice;
         const int K = (int)(r.lv & 0xffu);
         if (K > 0) {
             const uint64_t cap = seg_groups(r.lv >> 8);
-            uint64_t top = r.fence_off;  // end of level K
-            for (int k = 1; k <= K; ++k) top += fence_level_len(cap, k);
+            const uint64_t top = (uint64_t)r.fence_off + fence_level_off(cap, K) +
+                                 fence_level_len(cap, K);  // end of level K
             uint64_t from = top;
-            for (int k = K; k >= 1; --k) {
+            for (int k = K; k >= 0; --k) {
                 const uint32_t len = fence_level_len(cap, k);
                 if (top - (from - len) > slice) break;
                 from -= len;
@@ -704,7 +785,7 @@ tw_status coop_walks(tw_graph* g, const WalkArgs& a, Error& err) {
                                  n_live, 0, vbits, g->ws, s));
         with_kinds(a.hop.kind, TW_UNIFORM, [&](auto hk, auto) {
             hipLaunchKernelGGL((k_hop_coop<decltype(hk)::value>), grid, dim3(WALK_THREADS),
-                               sizeof(int64_t) * panel_cap, s, a, sorted, next, prev,
+                               sizeof(uint32_t) * panel_cap, s, a, sorted, next, prev,
                                (int64_t)n_live, hop, panel_cap, flags);
         });
         TW_HIP(scan_exclusive_u32(flags, pos, n_live, n_live_d, g->ws, s));
@@ -764,7 +845,7 @@ tw_status fill_args(tw_graph* g, int64_t num_walks, int32_t L, const tw_bias& sb
     a.ng = g->ng.as<GroupRec>();
     a.adj_rng = g->adj_rng.as<uint2>();
     a.rec = g->rec.as<NodeRec>();
-    a.fence = g->fence.as<int64_t>();
+    a.fence = g->fence.as<uint32_t>();
     a.adj = g->adj.as<int32_t>();
     a.V = g->V;
     a.num_walks = num_walks;
@@ -844,16 +925,51 @@ tw_status batch_full_walk(tw_graph* g, const WalkArgs& a, const QueueArgs& q, Er
     return TW_OK;
 }
 
+// The queue dispatch of plain walks: every start in one pass (as the
+// cooperative dispatch starts), the live walks compacted, then one
+// persistent launch of k_walk_hops over them.
+tw_status queue_hops(tw_graph* g, const WalkArgs& a, int bpc, Error& err) {
+    hipStream_t s = g->stream;
+    const int64_t W = a.num_walks;
+    if (queue_shape(g, err) != TW_OK) return err.code;
+    DevBuf* bufs32[] = {&g->c_node0, &g->c_walk0, &g->c_node2, &g->c_walk2, &g->c_flags,
+                        &g->c_pos, &g->c_prev};
+    for (DevBuf* b : bufs32) TW_HIP(ensure(*b, sizeof(uint32_t) * W));
+    TW_HIP(ensure(g->c_t0, sizeof(uint64_t) * W));
+    TW_HIP(ensure(g->c_t2, sizeof(uint64_t) * W));
+    TW_HIP(ensure(g->wq, sizeof(unsigned long long) * QUEUE_SLICES));
+    Live live{g->c_node0.as<uint32_t>(), g->c_walk0.as<uint32_t>(), g->c_t0.as<uint64_t>()};
+    Live next{g->c_node2.as<uint32_t>(), g->c_walk2.as<uint32_t>(), g->c_t2.as<uint64_t>()};
+    int32_t* prev = g->c_prev.as<int32_t>();
+    uint32_t* flags = g->c_flags.as<uint32_t>();
+    uint32_t* pos = g->c_pos.as<uint32_t>();
+    uint32_t* n_live_d = g->scal.as<uint32_t>() + SLOT_U32_N_LIVE;
+    const dim3 wgrid((unsigned)ceil_div(W, WALK_THREADS));
+    with_kinds(-1, a.start_kind, [&](auto, auto sk) {
+        hipLaunchKernelGGL((k_coop_start<decltype(sk)::value>), wgrid, dim3(WALK_THREADS), 0, s, a,
+                           next, prev, flags);
+    });
+    TW_HIP(scan_exclusive_u32(flags, pos, W, n_live_d, g->ws, s));
+    hipLaunchKernelGGL(k_compact_live, wgrid, dim3(WALK_THREADS), 0, s, flags, pos, W, next, live);
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, g->wq.as<unsigned long long>());
+    with_kinds(a.hop.kind, TW_UNIFORM, [&](auto h, auto) {
+        auto kernel = k_walk_hops<decltype(h)::value>;
+        static const int maxb = resident_bpc(kernel);  // per instantiation
+        const int b = (bpc <= 0 || bpc > maxb) ? maxb : bpc;
+        const int64_t blocks =
+            std::min<int64_t>(ceil_div(W, WALK_THREADS), (int64_t)g->cu_count * b);
+        hipLaunchKernelGGL(kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)),
+                           dim3(WALK_THREADS), 0, s, a, live, prev, n_live_d,
+                           g->wq.as<unsigned long long>());
+    });
+    TW_HIP(hipGetLastError());
+    return TW_OK;
+}
+
 // run the walks of `a` (outputs already padded) under a dispatch
 tw_status run_dispatch(tw_graph* g, const WalkArgs& a, int dispatch, int bpc, Error& err) {
     if (dispatch == TW_DISPATCH_COOP) return coop_walks(g, a, err);
-    if (dispatch == TW_DISPATCH_QUEUE) {
-        QueueArgs q{};
-        q.n_bias = 1;
-        q.bias[0] = a.hop;
-        q.out_slots = a.num_walks * (int64_t)a.L;
-        return queue_walks(g, a, q, bpc, err);
-    }
+    if (dispatch == TW_DISPATCH_QUEUE) return queue_hops(g, a, bpc, err);
     with_kinds(a.hop.kind, a.start_kind, [&](auto h, auto st) {
         hipLaunchKernelGGL((k_walk_full<decltype(h)::value, decltype(st)::value>),
                            dim3((unsigned)ceil_div(a.num_walks, WALK_THREADS)), dim3(WALK_THREADS),

@@ -107,53 +107,64 @@ __device__ __forceinline__ uint32_t count_le(const GroupRec* __restrict__ ng, ui
     return a - lo;
 }
 
+// Entries of one 8-word key window <= the query, exactly: keys below q
+// count, keys equal to q are decided by their group's timestamp (group
+// index g0 + (lo + i) * step for entry i).
+__device__ __forceinline__ uint32_t window_count(const uint32_t* win, uint32_t q, int64_t t,
+                                                 const GroupRec* __restrict__ ng, uint64_t gbase,
+                                                 uint64_t step) {
+    const uint4 a = reinterpret_cast<const uint4*>(win)[0];
+    const uint4 b = reinterpret_cast<const uint4*>(win)[1];
+    const uint32_t k[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    uint32_t lt = 0, le = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        lt += k[j] < q;
+        le += k[j] <= q;
+    }
+    for (uint32_t j = lt; j < le; ++j) lt += ng[gbase + j * step].ts <= t;
+    return lt;
+}
+
 // Gamma lookup (Sec. "Dual-Index Organization": the node's first timestamp
-// group strictly after t) through the node's fence: one aligned
-// FENCE_FAN-entry window per level from the top level in use, then one
-// aligned window of FENCE_FAN group records (one 128-byte line). Requires
-// t < r.t_last, so the result is below r.ge, and t at or after the window's
-// first timestamp, so groups evicted from the front of the segment count as
-// earlier. Returns the absolute group index. panel (nullable) holds fence
-// entries [panel_base, panel_base + panel_len) in LDS; windows inside it are
-// read from there.
+// group strictly after t) through the node's fence: the header (key base and
+// shift), then one 8-word key window per level from the top level in use
+// down to level 0. Requires t < r.t_last, so the result is below r.ge.
+// Returns the absolute group index. panel (nullable) holds fence words
+// [panel_base, panel_base + panel_len) in LDS; windows inside it are read
+// from there.
 __device__ __forceinline__ uint32_t fence_search(const GroupRec* __restrict__ ng,
-                                                 const int64_t* __restrict__ fence,
+                                                 const uint32_t* __restrict__ fence,
                                                  const NodeRec& r, int64_t t,
-                                                 const int64_t* panel, uint64_t panel_base,
+                                                 const uint32_t* panel, uint64_t panel_base,
                                                  uint32_t panel_len) {
     const int K = (int)(r.lv & 0xffu);
     if (K == 0) return r.gb + count_le(ng, r.gb, r.ge, t);
+    const uint32_t* f = fence + r.fence_off;
+    const uint4 h = *reinterpret_cast<const uint4*>(f);
+    const int64_t base = (int64_t)(((uint64_t)h.y << 32) | h.x);
+    if (t < base) return r.gb;  // every group of the segment is later
+    const uint32_t q = (uint32_t)((uint64_t)(t - base) >> h.z);
     const uint64_t cap = seg_groups(r.lv >> 8);
-    uint64_t off = r.fence_off;  // start of level K
-    for (int k = 1; k < K; ++k) off += fence_level_len(cap, k);
+    uint64_t off = fence_level_off(cap, K);
     uint64_t lo = 0;
-    for (int k = K; k >= 1; --k) {
-        const uint64_t at = off + lo;
-        const longlong2* win = reinterpret_cast<const longlong2*>(
-            at >= panel_base && at + FENCE_FAN <= panel_base + panel_len ? panel + (at - panel_base)
-                                                                          : fence + at);
-        uint32_t c = 0;
-#pragma unroll
-        for (int j = 0; j < FENCE_FAN / 2; ++j) {
-            const longlong2 v = win[j];
-            c += (v.x <= t) + (v.y <= t);
+    for (int k = K; k >= 0; --k) {
+        const uint64_t at = r.fence_off + off + lo;
+        const uint32_t* win = at >= panel_base && at + FENCE_FAN <= panel_base + panel_len
+                                  ? panel + (at - panel_base)
+                                  : fence + at;
+        const uint32_t c =
+            window_count(win, q, t, ng, r.g0 + (lo << (FENCE_LOG * k)), 1ull << (FENCE_LOG * k));
+        if (k == 0) {
+            const uint32_t res = r.g0 + (uint32_t)lo + c;
+            return res < r.gb ? r.gb : res;
         }
-        // only possible at the top level: t precedes the segment
+        // c == 0 only at the top level: t precedes the segment's first group
         if (c == 0) return r.gb;
         lo = (lo + c - 1) * FENCE_FAN;
-        if (k > 1) off -= fence_level_len(cap, k - 1);
+        off -= fence_level_len(cap, k - 1);
     }
-    const uint32_t body = r.ge - r.g0;
-    uint32_t c = 0;
-    if (lo + FENCE_FAN <= body) {
-        const GroupRec* w = ng + r.g0 + lo;
-#pragma unroll
-        for (int j = 0; j < FENCE_FAN; ++j) c += (w[j].ts <= t);
-    } else {
-        c = count_le(ng, r.g0 + (uint32_t)lo, r.ge, t);
-    }
-    const uint32_t res = r.g0 + (uint32_t)lo + c;
-    return res < r.gb ? r.gb : res;
+    return r.gb;  // not reached
 }
 
 // is w among the sorted values adj[lo, hi)?
