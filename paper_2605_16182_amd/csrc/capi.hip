@@ -33,9 +33,11 @@ tw_status guarded(const char* what, F&& f) {
 // pending device-side errors from walks: flag 0, a start node out of range;
 // flag 3, a batched walk with a length limit, bias index or row out of range
 tw_status check_device_flags(tw_graph* g) {
-    if (!g->err.p) return TW_OK;
-    uint32_t f[4] = {0, 0, 0, 0};
-    if (hipMemcpyAsync(f, g->err.p, sizeof(f), hipMemcpyDeviceToHost, g->stream) != hipSuccess ||
+    if (!g->err.p || !g->h_scal) return TW_OK;
+    // the flags land in the pinned host copy, after the scalar slots
+    uint32_t* f = static_cast<uint32_t*>(g->h_scal) + tw::SCALAR_BYTES / 4;
+    if (hipMemcpyAsync(f, g->err.p, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, g->stream) !=
+            hipSuccess ||
         hipStreamSynchronize(g->stream) != hipSuccess)
         return fail(TW_EDEVICE, "reading device error flags failed");
     if (f[0] || f[3]) {
@@ -76,6 +78,7 @@ tw_status tw_destroy(tw_graph* g) {
     return guarded("tw_destroy", [&]() -> tw_status {
         hipStreamSynchronize(g->stream);
         for (tw::DevBuf* b : g->buffers()) tw::release(*b);
+        if (g->h_scal) (void)hipHostFree(g->h_scal);
         delete g;
         return TW_OK;
     });

@@ -224,6 +224,7 @@ tw_status ensure_common(tw_graph* g, Error& err) {
         TW_HIP(hipMemsetAsync(g->err.p, 0, sizeof(uint32_t) * 4, g->stream));
     }
     TW_HIP(ensure(g->scal, SCALAR_BYTES));
+    if (!g->h_scal) TW_HIP(hipHostMalloc(&g->h_scal, SCALAR_BYTES + 16, hipHostMallocDefault));
     return TW_OK;
 }
 
@@ -281,15 +282,11 @@ tw_status finish_ts(tw_graph* g, bool gg_full, int64_t gg_old, int64_t gg_evicte
     hipLaunchKernelGGL(k_window_summary, dim3(1), dim3(1), 0, s, g->e_ts.as<int64_t>() + g->e_base,
                        g->m, summary);
     TW_HIP(hipGetLastError());
-    uint32_t groups = 0;
-    int64_t host_sum[2];
-    TW_HIP(hipMemcpyAsync(&groups, u32_slot(g, SLOT_U32_GROUPS), sizeof(groups),
-                          hipMemcpyDeviceToHost, s));
-    TW_HIP(hipMemcpyAsync(host_sum, summary, sizeof(host_sum), hipMemcpyDeviceToHost, s));
-    TW_HIP(hipStreamSynchronize(s));
+    if (pull_scalars(g, false, err) != TW_OK) return err.code;
+    const uint32_t groups = host_u32(g, SLOT_U32_GROUPS);
     g->Gg = gg_full ? (int64_t)groups : gg_old - gg_evicted + (int64_t)groups;
-    g->t_min = host_sum[0];
-    g->t_max = host_sum[1];
+    g->t_min = host_i64(g, SLOT_I64_SUMMARY);
+    g->t_max = host_i64(g, SLOT_I64_SUMMARY + 1);
     return TW_OK;
 }
 
@@ -321,12 +318,10 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
                            dim3(T), 0, s, src, dst, ts, n, g->V, g->directed ? 1 : 0, s_src, s_dst,
                            s_ts, errf + 1, mm, unsorted);
     TW_HIP(hipGetLastError());
-    unsigned long long hmm[2];
-    uint32_t herr = 0, hunsorted = 0;
-    TW_HIP(hipMemcpyAsync(hmm, mm, sizeof(hmm), hipMemcpyDeviceToHost, s));
-    TW_HIP(hipMemcpyAsync(&herr, errf + 1, sizeof(herr), hipMemcpyDeviceToHost, s));
-    TW_HIP(hipMemcpyAsync(&hunsorted, unsorted, sizeof(hunsorted), hipMemcpyDeviceToHost, s));
-    TW_HIP(hipStreamSynchronize(s));
+    if (pull_scalars(g, true, err) != TW_OK) return err.code;
+    const uint64_t hmm[2] = {(uint64_t)host_i64(g, SLOT_I64_MINMAX),
+                             (uint64_t)host_i64(g, SLOT_I64_MINMAX + 1)};
+    const uint32_t herr = host_flags(g)[1], hunsorted = host_u32(g, SLOT_U32_UNSORTED);
     if (herr) {
         err = Error{TW_ERANGE, "ingest_batch: node id outside [0, num_nodes)"};
         return err.code;
@@ -385,12 +380,10 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
     }
     TW_HIP(hipGetLastError());
     if (drop || evicting) {
-        uint32_t h2[2] = {0, 0}, hg = 0;
-        int64_t hf = INT64_MAX;
-        TW_HIP(hipMemcpyAsync(h2, sc_kept, sizeof(h2), hipMemcpyDeviceToHost, s));
-        TW_HIP(hipMemcpyAsync(&hg, sc_gev, sizeof(hg), hipMemcpyDeviceToHost, s));
-        TW_HIP(hipMemcpyAsync(&hf, first_kept, sizeof(hf), hipMemcpyDeviceToHost, s));
-        TW_HIP(hipStreamSynchronize(s));
+        if (pull_scalars(g, false, err) != TW_OK) return err.code;
+        const uint32_t h2[2] = {host_u32(g, SLOT_U32_KEPT), host_u32(g, SLOT_U32_EVICTED)};
+        const uint32_t hg = host_u32(g, SLOT_U32_GG_EVICTED);
+        const int64_t hf = host_i64(g, SLOT_I64_FIRST_KEPT);
         if (drop && sorted) {
             drop_lo = h2[0];
             kept = B - drop_lo;
@@ -538,12 +531,9 @@ tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& e
                            g->m, cutoff, sc_ev);
         hipLaunchKernelGGL(k_lower_bound, dim3(1), dim3(1), 0, s,
                            g->gg_ts.as<int64_t>() + g->gg_base, g->Gg, cutoff, sc_gev);
-        uint32_t h[2] = {0, 0};
-        TW_HIP(hipMemcpyAsync(&h[0], sc_ev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        TW_HIP(hipMemcpyAsync(&h[1], sc_gev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        TW_HIP(hipStreamSynchronize(s));
-        ev = h[0];
-        gev = h[1];
+        if (pull_scalars(g, false, err) != TW_OK) return err.code;
+        ev = host_u32(g, SLOT_U32_EVICTED);
+        gev = host_u32(g, SLOT_U32_GG_EVICTED);
     }
     if (ev > 0) {
         const int64_t m_old = g->m, gg_old = g->Gg;
@@ -574,6 +564,17 @@ tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& e
     g->last.t_min = g->t_min;
     g->last.t_max = g->t_max;
     if (n_evicted) *n_evicted = ev;
+    return TW_OK;
+}
+
+tw_status pull_scalars(tw_graph* g, bool flags, Error& err) {
+    hipStream_t s = g->stream;
+    if (ensure_common(g, err) != TW_OK) return err.code;
+    TW_HIP(hipMemcpyAsync(g->h_scal, g->scal.p, SCALAR_BYTES, hipMemcpyDeviceToHost, s));
+    if (flags)
+        TW_HIP(hipMemcpyAsync(static_cast<char*>(g->h_scal) + SCALAR_BYTES, g->err.p, 16,
+                              hipMemcpyDeviceToHost, s));
+    TW_HIP(hipStreamSynchronize(s));
     return TW_OK;
 }
 

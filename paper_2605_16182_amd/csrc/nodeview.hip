@@ -102,6 +102,10 @@ __global__ void k_empty_rec(NodeRec* __restrict__ rec, int64_t V) {
     if (v < V) rec[v] = empty_rec();
 }
 
+__global__ void k_copy_u32(const uint32_t* __restrict__ from, uint32_t* __restrict__ to) {
+    *to = *from;
+}
+
 __global__ void k_zero_u32(uint32_t* __restrict__ p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -737,10 +741,8 @@ tw_status nv_collect(tw_graph* g, const int32_t* q_src, const int32_t* q_dst, co
         TW_HIP(scan_exclusive_u32(nullptr, nullptr, 0, sl_ev, g->ws, s));
     }
     TW_HIP(hipGetLastError());
-    uint32_t h[2];
-    TW_HIP(hipMemcpyAsync(h, sl_runs, sizeof(h), hipMemcpyDeviceToHost, s));
-    TW_HIP(hipStreamSynchronize(s));
-    g->T = (int64_t)h[0] + h[1];
+    if (pull_scalars(g, false, err) != TW_OK) return err.code;
+    g->T = (int64_t)host_u32(g, SLOT_U32_RUNS) + host_u32(g, SLOT_U32_EV_NODES);
     return TW_OK;
 }
 
@@ -773,12 +775,12 @@ tw_status plan_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool re
     TW_HIP(scan_exclusive_u32(g->j_re.as<uint32_t>(), g->j_re.as<uint32_t>(), nj, sl, g->ws, s));
     TW_HIP(scan_exclusive_u32(g->j_rg.as<uint32_t>(), g->j_rg.as<uint32_t>(), nj, sl + 1, g->ws, s));
     TW_HIP(scan_exclusive_u32(g->j_rf.as<uint32_t>(), g->j_rf.as<uint32_t>(), nj, sl + 2, g->ws, s));
-    uint32_t h[4];
-    TW_HIP(hipMemcpyAsync(&h[0], g->j_off.as<uint32_t>() + nj, sizeof(uint32_t),
-                          hipMemcpyDeviceToHost, s));
-    TW_HIP(hipMemcpyAsync(&h[1], sl, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    TW_HIP(hipStreamSynchronize(s));
-    for (int i = 0; i < 4; ++i) tot[i] = h[i];
+    hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, s, g->j_off.as<uint32_t>() + nj,
+                       slot(g, SLOT_U32_OUT));
+    TW_HIP(hipGetLastError());
+    if (pull_scalars(g, false, err) != TW_OK) return err.code;
+    tot[0] = host_u32(g, SLOT_U32_OUT);
+    for (int i = 0; i < 3; ++i) tot[1 + i] = host_u32(g, SLOT_U32_REQ_E + i);
     return TW_OK;
 }
 
@@ -833,9 +835,8 @@ tw_status run_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool rew
                                g->touched.as<uint32_t>(), g->epoch, g->v_flags.as<uint32_t>());
             TW_HIP(scan_exclusive_u32(g->v_flags.as<uint32_t>(), g->v_pos.as<uint32_t>(), V,
                                       sl_act, g->ws, s));
-            uint32_t na = 0;
-            TW_HIP(hipMemcpyAsync(&na, sl_act, sizeof(na), hipMemcpyDeviceToHost, s));
-            TW_HIP(hipStreamSynchronize(s));
+            if (pull_scalars(g, false, err) != TW_OK) return err.code;
+            const uint32_t na = host_u32(g, SLOT_U32_ACTIVE);
             const int64_t all = nj + na;  // <= V: the lists hold V + 1 entries
             hipLaunchKernelGGL(k_flag_jobs, grid_for(V), dim3(T), 0, s, g->v_flags.as<uint32_t>(),
                                g->v_pos.as<uint32_t>(), V, nullptr, slot(g, SLOT_U32_RUNS),
@@ -913,10 +914,8 @@ tw_status nv_group_count(tw_graph* g, int64_t* gn, Error& err) {
                        g->ng.as<GroupRec>(), V, nullptr, g->v_flags.as<uint32_t>());
     uint32_t* sl = slot(g, SLOT_U32_GN);
     TW_HIP(scan_exclusive_u32(g->v_flags.as<uint32_t>(), g->v_pos.as<uint32_t>(), V, sl, g->ws, s));
-    uint32_t h = 0;
-    TW_HIP(hipMemcpyAsync(&h, sl, sizeof(h), hipMemcpyDeviceToHost, s));
-    TW_HIP(hipStreamSynchronize(s));
-    *gn = h;
+    if (pull_scalars(g, false, err) != TW_OK) return err.code;
+    *gn = host_u32(g, SLOT_U32_GN);
     return TW_OK;
 }
 

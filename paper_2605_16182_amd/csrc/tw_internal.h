@@ -266,6 +266,7 @@ struct tw_graph {
     tw::DevBuf v_flags, v_pos;         // per-node temporaries
     tw::DevBuf err;                    // device error flags (uint32)
     tw::DevBuf scal;                   // device scalars
+    void* h_scal = nullptr;            // pinned host copy: scal, then the 4 error flags
     tw::Workspace ws;
 
     // every device allocation of the graph
@@ -284,6 +285,20 @@ struct tw_graph {
 };
 
 namespace tw {
+
+// index.hip
+// Copy the device scalar slots (with flags: also the device error flags) to
+// the graph's pinned host copy and wait for the graph's stream.
+tw_status pull_scalars(tw_graph* g, bool flags, Error& err);
+inline uint32_t host_u32(const tw_graph* g, int k) {
+    return static_cast<const uint32_t*>(g->h_scal)[k];
+}
+inline int64_t host_i64(const tw_graph* g, int k) {
+    return static_cast<const int64_t*>(g->h_scal)[k];
+}
+inline const uint32_t* host_flags(const tw_graph* g) {
+    return static_cast<const uint32_t*>(g->h_scal) + SCALAR_BYTES / 4;
+}
 
 // nodeview.hip
 // Sort the kept batch (timestamp order) by source and list the node-view

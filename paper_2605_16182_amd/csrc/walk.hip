@@ -776,9 +776,8 @@ tw_status coop_walks(tw_graph* g, const WalkArgs& a, Error& err) {
     hipLaunchKernelGGL(k_compact_live, wgrid, dim3(WALK_THREADS), 0, s, flags, pos, W, next, live);
     TW_HIP(hipGetLastError());
     for (uint64_t hop = 1; hop + 1 < (uint64_t)a.L; ++hop) {
-        uint32_t n_live = 0;
-        TW_HIP(hipMemcpyAsync(&n_live, n_live_d, sizeof(n_live), hipMemcpyDeviceToHost, s));
-        TW_HIP(hipStreamSynchronize(s));
+        if (pull_scalars(g, false, err) != TW_OK) return err.code;
+        const uint32_t n_live = host_u32(g, SLOT_U32_N_LIVE);
         if (n_live == 0) break;
         const dim3 grid((unsigned)ceil_div(n_live, WALK_THREADS));
         TW_HIP(radix_sort_u32_kv(live.node, live.walk, live.t, sorted.node, sorted.walk, sorted.t,
