@@ -378,7 +378,7 @@ __global__ void __launch_bounds__(T) k_job_flags(const Job* __restrict__ jobs,
                                                  const int64_t* __restrict__ bts,
                                                  uint32_t* __restrict__ oflag) {
     __shared__ uint32_t jr[2];
-    const int64_t base = (int64_t)blockIdx.x * NV_TILE;
+    const int64_t base = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * NV_TILE;
     tile_jobs(off, nj, (uint64_t)base, (uint64_t)std::min<int64_t>(base + NV_TILE, total) - 1,
               jr);
     for (int u = 0; u < NV_ITEMS; ++u) {
@@ -410,7 +410,7 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
                                                  GroupRec* __restrict__ ngd,
                                                  uint32_t* __restrict__ fence) {
     __shared__ uint32_t jr[2];
-    const int64_t base = (int64_t)blockIdx.x * NV_TILE;
+    const int64_t base = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * NV_TILE;
     tile_jobs(off, nj, (uint64_t)base, (uint64_t)std::min<int64_t>(base + NV_TILE, total) - 1,
               jr);
     for (int u = 0; u < NV_ITEMS; ++u) {

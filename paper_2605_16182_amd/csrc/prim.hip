@@ -178,73 +178,173 @@ __global__ void k_flag_scatter(const uint32_t* __restrict__ flags, const int64_t
 }
 
 // ------------------------------------------------------------ radix sort
+//
+// A tile is RS_TILE consecutive items; wavefront w of its workgroup owns the
+// tile's items [w * RS_WAVE_ITEMS, (w + 1) * RS_WAVE_ITEMS), 64 per round.
+// Ranks are wavefront-private (no workgroup barrier per round): in each round
+// the lanes sharing a digit learn each other from one ballot per digit bit,
+// and the lowest of them advances the wavefront's count for that digit.
 
-template <typename K>
-__global__ void k_rs_hist(const K* __restrict__ keys, int64_t n, int shift, int nbits,
-                          uint32_t* __restrict__ hist, int64_t nblocks) {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    const uint32_t mask = (1u << nbits) - 1u;
-    int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    for (int j = 0; j < RS_ITEMS; ++j) {
-        int64_t i = base + (int64_t)j * RS_THREADS + threadIdx.x;
-        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & mask], 1u);
+constexpr int RS_WAVE_ITEMS = RS_TILE / RS_WAVES;
+constexpr int RS_RADIX = 256;  // one digit per thread of the workgroup
+static_assert(RS_RADIX == RS_THREADS, "digit tables are indexed by thread");
+
+// lanes of the wavefront whose digit equals this lane's, among valid lanes
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, int nbits) {
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
     }
-    __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    return peers;
 }
 
-// Scatter one tile to its stable positions. offs[d * nblocks + b] is the
+template <typename K>
+__global__ void __launch_bounds__(RS_THREADS)
+k_rs_hist(const K* __restrict__ keys, int64_t n, int shift, int nbits,
+          uint32_t* __restrict__ hist, int64_t nblocks) {
+    __shared__ uint32_t cnt[RS_WAVES][RS_RADIX];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int w = 0; w < RS_WAVES; ++w) cnt[w][tid] = 0;
+    __syncthreads();
+    const uint32_t mask = (1u << nbits) - 1u;
+    const uint64_t lower = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t tile = xcd_tile(blockIdx.x, (uint32_t)nblocks);
+    const int64_t wbase = (int64_t)tile * RS_TILE + (int64_t)wave * RS_WAVE_ITEMS;
+    K k[RS_ITEMS];
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const int64_t i = wbase + r * 64 + lane;
+        k[r] = i < n ? keys[i] : K(0);
+    }
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const bool valid = wbase + r * 64 + lane < n;
+        const uint32_t d = (uint32_t)(k[r] >> shift) & mask;
+        const uint64_t peers = digit_peers(d, valid, nbits);
+        if (valid && (peers & lower) == 0) cnt[wave][d] += (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < RS_WAVES; ++w) c += cnt[w][tid];
+    hist[(int64_t)tid * nblocks + tile] = c;
+}
+
+// Scatter one tile to its stable output slots. offs[d * nblocks + b] is the
 // first output slot of digit d for tile b (exclusive scan of the histogram).
+// The tile is first ordered by digit in LDS, one array at a time, so that
+// consecutive lanes write consecutive slots of each digit's run.
 template <typename K>
 __global__ void __launch_bounds__(RS_THREADS)
 k_rs_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
              const uint64_t* __restrict__ v64, int64_t n, int shift, int nbits,
              const uint32_t* __restrict__ offs, int64_t nblocks, K* __restrict__ keys_out,
              uint32_t* __restrict__ vals_out, uint64_t* __restrict__ v64_out) {
-    __shared__ uint32_t running[256];
-    __shared__ uint32_t wcnt[RS_WAVES][256];
+    __shared__ uint32_t cnt[RS_WAVES][RS_RADIX];  // wave counts, then wave starts
+    __shared__ uint32_t lstart[RS_RADIX];         // tile-local first slot of each digit
+    __shared__ uint32_t gstart[RS_RADIX];         // output slot of that first item
+    __shared__ uint64_t stage[RS_TILE];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t mask = (1u << nbits) - 1u;
-    running[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
+    const uint64_t lower = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t tile = xcd_tile(blockIdx.x, (uint32_t)nblocks);
 #pragma unroll
-    for (int w = 0; w < RS_WAVES; ++w) wcnt[w][tid] = 0;
+    for (int w = 0; w < RS_WAVES; ++w) cnt[w][tid] = 0;
+    gstart[tid] = offs[(int64_t)tid * nblocks + tile];
     __syncthreads();
-    const uint64_t lower = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    for (int r = 0; r < RS_ITEMS; ++r) {
-        int64_t i = base + (int64_t)r * RS_THREADS + tid;
-        bool valid = i < n;
-        K k = valid ? keys[i] : K(0);
-        uint32_t v = (valid && vals) ? vals[i] : 0u;
-        uint64_t v2 = (valid && v64) ? v64[i] : 0ull;
-        uint32_t d = (uint32_t)(k >> shift) & mask;
-        uint64_t peers = __ballot(valid);
-        for (int b = 0; b < nbits; ++b) {
-            bool bit = (d >> b) & 1u;
-            uint64_t bal = __ballot(bit);
-            peers &= bit ? bal : ~bal;
-        }
-        uint32_t rank = (uint32_t)__popcll(peers & lower);
-        if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = running[d] + rank;
-            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-            keys_out[pos] = k;
-            if (vals_out) vals_out[pos] = v;
-            if (v64_out) v64_out[pos] = v2;
-        }
-        __syncthreads();
-        uint32_t add = 0;
+    const int64_t tile0 = (int64_t)tile * RS_TILE;
+    const int64_t wbase = tile0 + (int64_t)wave * RS_WAVE_ITEMS;
+    const int tile_n = (int)std::min<int64_t>(RS_TILE, n - tile0);
+
+    // every input of the tile is loaded up front
+    K k[RS_ITEMS];
+    uint32_t lp[RS_ITEMS], v[RS_ITEMS];
+    uint64_t w2[RS_ITEMS];
 #pragma unroll
-        for (int w = 0; w < RS_WAVES; ++w) {
-            add += wcnt[w][tid];
-            wcnt[w][tid] = 0;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const int64_t i = wbase + r * 64 + lane;
+        k[r] = i < n ? keys[i] : K(0);
+        v[r] = (vals && i < n) ? vals[i] : 0u;
+        w2[r] = (v64 && i < n) ? v64[i] : 0ull;
+    }
+
+    // stable rank of each item among the wavefront's items of its digit
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const bool valid = wbase + r * 64 + lane < n;
+        const uint32_t d = (uint32_t)(k[r] >> shift) & mask;
+        const uint64_t peers = digit_peers(d, valid, nbits);
+        const uint32_t before = cnt[wave][d];
+        lp[r] = before + (uint32_t)__popcll(peers & lower);
+        if (valid && (peers & lower) == 0) cnt[wave][d] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+
+    // digit starts in the tile (scan over digits), then each wavefront's start
+    uint32_t wpre[RS_WAVES], tot = 0;
+#pragma unroll
+    for (int w = 0; w < RS_WAVES; ++w) {
+        wpre[w] = tot;
+        tot += cnt[w][tid];
+    }
+    uint32_t all;
+    const uint32_t ls = block_excl_scan<uint32_t>(tot, &all);
+    lstart[tid] = ls;
+#pragma unroll
+    for (int w = 0; w < RS_WAVES; ++w) cnt[w][tid] = ls + wpre[w];
+    __syncthreads();
+
+    // keys: into LDS in digit order, then out; each thread keeps the output
+    // slots of the LDS slots it wrote out for the value arrays
+    K* sk = reinterpret_cast<K*>(stage);
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        if (wbase + r * 64 + lane < n) {
+            const uint32_t d = (uint32_t)(k[r] >> shift) & mask;
+            lp[r] += cnt[wave][d];
+            sk[lp[r]] = k[r];
         }
-        running[tid] += add;
+    }
+    __syncthreads();
+    uint32_t gp[RS_ITEMS];
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const int sl = r * RS_THREADS + tid;
+        gp[r] = 0;
+        if (sl < tile_n) {
+            const K key = sk[sl];
+            const uint32_t d = (uint32_t)(key >> shift) & mask;
+            gp[r] = gstart[d] + ((uint32_t)sl - lstart[d]);
+            keys_out[gp[r]] = key;
+        }
+    }
+    if (vals) {
         __syncthreads();
+        uint32_t* sv = reinterpret_cast<uint32_t*>(stage);
+#pragma unroll
+        for (int r = 0; r < RS_ITEMS; ++r)
+            if (wbase + r * 64 + lane < n) sv[lp[r]] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RS_ITEMS; ++r) {
+            const int sl = r * RS_THREADS + tid;
+            if (sl < tile_n) vals_out[gp[r]] = sv[sl];
+        }
+    }
+    if (v64) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RS_ITEMS; ++r)
+            if (wbase + r * 64 + lane < n) stage[lp[r]] = w2[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RS_ITEMS; ++r) {
+            const int sl = r * RS_THREADS + tid;
+            if (sl < tile_n) v64_out[gp[r]] = stage[sl];
+        }
     }
 }
 

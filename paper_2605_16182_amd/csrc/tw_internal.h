@@ -102,6 +102,18 @@ __host__ __device__ inline uint32_t fence_shift(uint64_t span) {
     return s;
 }
 
+// Workgroups of a launch go to the chip's 8 XCDs in turn (workgroup i to
+// XCD i mod 8), each XCD with its own L2. Tile index of workgroup bid among
+// nb such that every XCD takes one contiguous range of tiles: neighbouring
+// tiles then share an L2, and partial cache lines at the ends of their
+// output runs merge there before they are written back.
+constexpr uint32_t NUM_XCD = 8;
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t nb) {
+    const uint32_t x = bid % NUM_XCD, q = bid / NUM_XCD;
+    const uint32_t per = nb / NUM_XCD, rem = nb % NUM_XCD;
+    return x * per + (x < rem ? x : rem) + q;
+}
+
 __host__ __device__ inline uint64_t seg_groups(uint32_t code) {
     return (uint64_t)FENCE_FAN << code;
 }
