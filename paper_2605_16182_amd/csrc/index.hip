@@ -172,13 +172,6 @@ __global__ void k_merge(const int32_t* __restrict__ a_src, const int32_t* __rest
 
 // group-start flags of a batch appended after a window whose last timestamp
 // is last_ts (has_last = 0: empty window)
-__global__ void k_append_group_flags(const int64_t* __restrict__ ts, int64_t n, int64_t last_ts,
-                                     int has_last, uint32_t* __restrict__ flags) {
-    int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
-    if (i >= n) return;
-    flags[i] = (i == 0) ? (!has_last || ts[0] != last_ts) : (ts[i] != ts[i - 1]);
-}
-
 __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
     int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
     if (i < n) p[i] = v;
@@ -267,7 +260,7 @@ tw_status build_ts_groups(tw_graph* g, Error& err) {
     const int64_t m = g->m;
     const int64_t* ts = g->e_ts.as<int64_t>() + g->e_base;
     uint32_t* G = u32_slot(g, SLOT_U32_GROUPS);
-    TW_HIP(group_starts(nullptr, ts, m, (uint32_t)g->e_base, g->gg_ts.as<int64_t>(),
+    TW_HIP(group_starts(0, 0, ts, m, (uint32_t)g->e_base, g->gg_ts.as<int64_t>(),
                         g->gg_off.as<uint32_t>(), G, g->ws, s));
     g->gg_base = 0;
     return TW_OK;
@@ -475,13 +468,9 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
             gg_full = true;
             if (build_ts_groups(g, err) != TW_OK) return err.code;
         } else if (kept > 0) {
-            TW_HIP(ensure(g->flags, sizeof(uint32_t) * (kept + 1)));
-            uint32_t* fl = g->flags.as<uint32_t>();
             uint32_t* G = u32_slot(g, SLOT_U32_GROUPS);
             const int64_t gpos = g->gg_base + (gg_old - gg_evicted);
-            hipLaunchKernelGGL(k_append_group_flags, grid_for(kept), dim3(T), 0, s, q_ts, kept,
-                               last_ts, 1, fl);
-            TW_HIP(group_starts(fl, q_ts, kept, (uint32_t)(g->e_base + na),
+            TW_HIP(group_starts(1, last_ts, q_ts, kept, (uint32_t)(g->e_base + na),
                                 g->gg_ts.as<int64_t>() + gpos, g->gg_off.as<uint32_t>() + gpos, G,
                                 g->ws, s));
         } else {

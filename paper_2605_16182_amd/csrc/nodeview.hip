@@ -16,6 +16,7 @@
 // segments, every active node is rewritten into fresh pools.
 #include <algorithm>
 
+#include "compact.h"
 #include "tw_internal.h"
 
 namespace tw {
@@ -113,29 +114,25 @@ __global__ void k_zero_u32(uint32_t* __restrict__ p, int64_t n) {
 
 // ----------------------------------------------------------- job lists
 
-__global__ void k_run_flags(const uint32_t* __restrict__ src, int64_t n,
-                            uint32_t* __restrict__ flags) {
-    const int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
-    if (i < n) flags[i] = (i == 0 || src[i] != src[i - 1]) ? 1u : 0u;
-}
-
-// one job per source run of the batch; marks the node touched
-__global__ void k_batch_jobs(const uint32_t* __restrict__ bsrc, int64_t n,
-                             const uint32_t* __restrict__ flags, const uint32_t* __restrict__ rpos,
-                             uint32_t epoch, uint32_t* __restrict__ touched,
-                             uint32_t* __restrict__ c_node, uint32_t* __restrict__ c_bf,
-                             uint32_t* __restrict__ c_be) {
-    const int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t v = bsrc[i];
-    if (flags[i]) {
-        const uint32_t r = rpos[i];
-        c_node[r] = v;
-        c_bf[r] = (uint32_t)i;
+// One job per source run of the source-sorted batch, flagged at the run's
+// last record (job k: records [c_bf[k], c_be[k])); marks the node touched.
+struct RunEndOp {
+    const uint32_t* src;
+    int64_t n;
+    uint32_t epoch;
+    uint32_t* touched;
+    uint32_t *c_node, *c_bf, *c_be;
+    __device__ bool flag(int64_t i) const { return i + 1 == n || src[i + 1] != src[i]; }
+    __device__ void emit(int64_t i, uint32_t k) const {
+        const uint32_t v = src[i];
+        c_node[k] = v;
+        c_be[k] = (uint32_t)(i + 1);
+        if (k == 0) c_bf[0] = 0;
+        if (i + 1 < n) c_bf[k + 1] = (uint32_t)(i + 1);
         touched[v] = epoch;
     }
-    if (i == n - 1 || bsrc[i + 1] != v) c_be[rpos[i] + flags[i] - 1] = (uint32_t)(i + 1);
-}
+    __device__ void end(int64_t, uint32_t) const {}
+};
 
 // flags[i] = 1 for exactly one evicted position of every source node that is
 // not a batch node yet (the first to claim the node's mark)
@@ -371,48 +368,121 @@ __device__ __forceinline__ void tile_jobs(const uint32_t* __restrict__ off, int6
     __syncthreads();
 }
 
-// group-start flag of every job output
+// Group starts of the job outputs as a bitmap (bit t & 63 of word t >> 6
+// marks output t; each round of a wavefront covers one word) and the number
+// of group starts in every tile of NV_TILE outputs.
 __global__ void __launch_bounds__(T) k_job_flags(const Job* __restrict__ jobs,
                                                  const uint32_t* __restrict__ off, int64_t nj,
                                                  int64_t total, const int64_t* __restrict__ ots,
                                                  const int64_t* __restrict__ bts,
-                                                 uint32_t* __restrict__ oflag) {
+                                                 uint64_t* __restrict__ bm,
+                                                 uint32_t* __restrict__ tcnt) {
     __shared__ uint32_t jr[2];
-    const int64_t base = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * NV_TILE;
+    __shared__ uint32_t wsum[T / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t base = (int64_t)tile * NV_TILE;
     tile_jobs(off, nj, (uint64_t)base, (uint64_t)std::min<int64_t>(base + NV_TILE, total) - 1,
               jr);
+    uint32_t c = 0;
     for (int u = 0; u < NV_ITEMS; ++u) {
-        const int64_t t = base + (int64_t)u * T + threadIdx.x;
-        if (t >= total) break;
-        const uint32_t j = job_in(off, jr[0], jr[1], (uint64_t)t);
-        const Job J = jobs[j];
-        const uint32_t i = (uint32_t)(t - off[j]);
-        const int64_t x = job_ts(J, i, ots, bts);
-        bool start;
-        if (i == 0) start = J.kind != JOB_APPEND || x != J.t_last;
-        else start = x != job_ts(J, i - 1, ots, bts);
-        oflag[t] = start ? 1u : 0u;
+        const int64_t t0 = base + (int64_t)u * T + wave * 64;  // the word's first output
+        const int64_t t = t0 + lane;
+        bool start = false;
+        if (t < total) {
+            const uint32_t j = job_in(off, jr[0], jr[1], (uint64_t)t);
+            const Job J = jobs[j];
+            const uint32_t i = (uint32_t)(t - off[j]);
+            const int64_t x = job_ts(J, i, ots, bts);
+            if (i == 0) start = J.kind != JOB_APPEND || x != J.t_last;
+            else start = x != job_ts(J, i - 1, ots, bts);
+        }
+        const uint64_t b = __ballot(start);
+        if (lane == 0 && t0 < total) bm[t0 >> 6] = b;
+        c += (uint32_t)__popcll(b);
+    }
+    if (lane == 0) wsum[wave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t sum = 0;
+#pragma unroll
+        for (int w = 0; w < T / 64; ++w) sum += wsum[w];
+        tcnt[tile] = sum;
     }
 }
 
-// every job output's edge, and the group record and level-0 fence key of
-// each group start (rank = exclusive scan of the flags)
+__device__ __forceinline__ uint64_t below(int b) { return b == 0 ? 0ull : (~0ull >> (64 - b)); }
+
+// group starts among the outputs before p (pref: each word's first rank;
+// total outputs, total_groups = all group starts)
+__device__ __forceinline__ uint32_t out_rank(const uint64_t* __restrict__ bm,
+                                             const uint32_t* __restrict__ pref, int64_t total,
+                                             uint32_t total_groups, int64_t p) {
+    if (p >= total) return total_groups;
+    return pref[p >> 6] + (uint32_t)__popcll(bm[p >> 6] & below((int)(p & 63)));
+}
+
+// Every job output's edge, and the group record and level-0 fence key of
+// each group start. A group's index in its job is its rank among the group
+// starts minus the rank at the job's first output: ranks inside the tile come
+// from its bitmap words (in LDS) and the scanned tile counts (toff); a job
+// that began in an earlier tile is the only one of its tile, so its first
+// rank is that tile's offset plus the bits before it. Stores each word's first
+// rank in pref for k_job_finish.
 __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
                                                  const uint32_t* __restrict__ off, int64_t nj,
                                                  int64_t total, const int32_t* __restrict__ odst,
                                                  const int64_t* __restrict__ ots,
                                                  const int32_t* __restrict__ bdst,
                                                  const int64_t* __restrict__ bts,
-                                                 const uint32_t* __restrict__ oflag,
-                                                 const uint32_t* __restrict__ rank,
+                                                 const uint64_t* __restrict__ bm,
+                                                 const uint32_t* __restrict__ toff,
+                                                 uint32_t* __restrict__ pref,
                                                  int32_t* __restrict__ ndst,
                                                  int64_t* __restrict__ nts,
                                                  GroupRec* __restrict__ ngd,
                                                  uint32_t* __restrict__ fence) {
+    constexpr int WORDS = NV_TILE / 64;
+    static_assert(WORDS <= 64, "one wavefront scans a tile's words");
     __shared__ uint32_t jr[2];
-    const int64_t base = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * NV_TILE;
-    tile_jobs(off, nj, (uint64_t)base, (uint64_t)std::min<int64_t>(base + NV_TILE, total) - 1,
-              jr);
+    __shared__ uint64_t sbm[WORDS];
+    __shared__ uint32_t spre[WORDS];
+    __shared__ uint32_t k_first;  // rank at the first output of a job begun earlier
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t base = (int64_t)tile * NV_TILE;
+    const int64_t last = std::min<int64_t>(base + NV_TILE, total) - 1;
+    tile_jobs(off, nj, (uint64_t)base, (uint64_t)last, jr);
+    if (wave == 0) {
+        const int64_t nw = ((last - base) >> 6) + 1;
+        const uint64_t wb = lane < nw ? bm[(base >> 6) + lane] : 0ull;
+        const uint32_t c = (uint32_t)__popcll(wb);
+        uint32_t inc = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        const uint32_t p0 = toff[tile] + inc - c;
+        if (lane < WORDS) {
+            sbm[lane] = wb;
+            spre[lane] = p0;
+        }
+        if (lane < nw) pref[(base >> 6) + lane] = p0;
+    } else if (wave == 1) {
+        const int64_t s0 = off[jr[0]];
+        if (s0 < base) {
+            const int64_t a = s0 / NV_TILE;
+            const int64_t q = s0 >> 6, wd = ((a * NV_TILE) >> 6) + lane;
+            uint32_t c = 0;
+            if (wd < q) c = (uint32_t)__popcll(bm[wd]);
+            else if (wd == q) c = (uint32_t)__popcll(bm[q] & below((int)(s0 & 63)));
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+            if (lane == 0) k_first = toff[a] + c;
+        }
+    }
+    __syncthreads();
     for (int u = 0; u < NV_ITEMS; ++u) {
         const int64_t t = base + (int64_t)u * T + threadIdx.x;
         if (t >= total) break;
@@ -424,12 +494,22 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
         const uint32_t pos = J.e_at + i;
         ndst[pos] = e.dst;
         nts[pos] = e.ts;
-        if (oflag[t]) {
+        const int lt = (int)(t - base);
+        const uint64_t word = sbm[lt >> 6];
+        if ((word >> (lt & 63)) & 1ull) {
+            const uint32_t rk = spre[lt >> 6] + (uint32_t)__popcll(word & below(lt & 63));
+            uint32_t kj;
+            if ((int64_t)jb >= base) {
+                const int lb = (int)(jb - base);
+                kj = spre[lb >> 6] + (uint32_t)__popcll(sbm[lb >> 6] & below(lb & 63));
+            } else {
+                kj = k_first;
+            }
             GroupRec g;
             g.ts = e.ts;
             g.first = pos;
             g.dst = e.dst;
-            const uint32_t gi = J.g_at + (rank[t] - rank[jb]);
+            const uint32_t gi = J.g_at + (rk - kj);
             ngd[gi] = g;
             // the group's level-0 fence key (segments of more than
             // FENCE_FAN groups have a fence)
@@ -478,13 +558,16 @@ __device__ __forceinline__ LevelWrite append_level(uint64_t n0, uint64_t n1, int
 // job writes: all of a new or restarted segment's fence, or the entries of
 // an append's new groups.
 __global__ void k_job_finish(const Job* __restrict__ jobs, const uint32_t* __restrict__ off,
-                             int64_t nj, const uint32_t* __restrict__ rank,
+                             int64_t nj, const uint64_t* __restrict__ bm,
+                             const uint32_t* __restrict__ pref, int64_t total,
+                             const uint32_t* __restrict__ total_groups,
                              const GroupRec* __restrict__ ngd, NodeRec* __restrict__ rec,
                              SegRec* __restrict__ seg, uint32_t gen, uint32_t* __restrict__ fw) {
     const int64_t j = (int64_t)blockIdx.x * T + threadIdx.x;
     if (j >= nj) return;
     const Job J = jobs[j];
-    const uint32_t newg = rank[off[j + 1]] - rank[off[j]];
+    const uint32_t tg = *total_groups;
+    const uint32_t newg = out_rank(bm, pref, total, tg, off[j + 1]) - out_rank(bm, pref, total, tg, off[j]);
     const uint32_t written = off[j + 1] - off[j];
     NodeRec r = rec[J.v];
     uint32_t f = 0;
@@ -721,11 +804,14 @@ tw_status nv_collect(tw_graph* g, const int32_t* q_src, const int32_t* q_dst, co
                                  reinterpret_cast<const uint64_t*>(q_ts), bsrc,
                                  g->bs_dst.as<uint32_t>(), g->bs_ts.as<uint64_t>(), kept, 0,
                                  bits_for((uint64_t)(g->V - 1)), g->ws, s));
-        hipLaunchKernelGGL(k_run_flags, grid_for(kept), dim3(T), 0, s, bsrc, kept, flags);
-        TW_HIP(scan_exclusive_u32(flags, pos, kept, sl_runs, g->ws, s));
-        hipLaunchKernelGGL(k_batch_jobs, grid_for(kept), dim3(T), 0, s, bsrc, kept, flags, pos,
-                           g->epoch, g->touched.as<uint32_t>(), g->c_node.as<uint32_t>(),
-                           g->c_bf.as<uint32_t>(), g->c_be.as<uint32_t>());
+        const RunEndOp op{bsrc,
+                          kept,
+                          g->epoch,
+                          g->touched.as<uint32_t>(),
+                          g->c_node.as<uint32_t>(),
+                          g->c_bf.as<uint32_t>(),
+                          g->c_be.as<uint32_t>()};
+        TW_HIP(compact(op, kept, sl_runs, g->ws.tiles, g->ws, s));
     } else {
         TW_HIP(scan_exclusive_u32(nullptr, nullptr, 0, sl_runs, g->ws, s));
     }
@@ -792,20 +878,25 @@ tw_status execute_jobs(tw_graph* g, int64_t nj, uint64_t out, const int32_t* sds
     hipStream_t s = g->stream;
     Job* jobs = g->jobs.as<Job>();
     const uint32_t* off = g->j_off.as<uint32_t>();
-    TW_HIP(ensure(g->o_flag, sizeof(uint32_t) * (out + 1)));
-    TW_HIP(ensure(g->o_rank, sizeof(uint32_t) * (out + 2)));
-    uint32_t* oflag = g->o_flag.as<uint32_t>();
-    uint32_t* rank = g->o_rank.as<uint32_t>();
+    // group-start bitmap and per-word ranks (o_flag), tile counts scanned in
+    // place (o_rank, total at [nt])
+    const int64_t words = ceil_div((int64_t)out, 64), nt = ceil_div((int64_t)out, NV_TILE);
+    TW_HIP(ensure(g->o_flag, sizeof(uint64_t) * (words + 1) + sizeof(uint32_t) * (words + 1)));
+    TW_HIP(ensure(g->o_rank, sizeof(uint32_t) * (nt + 1)));
+    uint64_t* bm = g->o_flag.as<uint64_t>();
+    uint32_t* pref = reinterpret_cast<uint32_t*>(bm + words + 1);
+    uint32_t* tcnt = g->o_rank.as<uint32_t>();
     if (out > 0)
-        hipLaunchKernelGGL(k_job_flags, dim3((unsigned)ceil_div((int64_t)out, NV_TILE)), dim3(T), 0,
-                           s, jobs, off, nj, (int64_t)out, sts, g->bs_ts.as<int64_t>(), oflag);
-    TW_HIP(scan_exclusive_u32(oflag, rank, (int64_t)out, rank + out, g->ws, s));
+        hipLaunchKernelGGL(k_job_flags, dim3((unsigned)nt), dim3(T), 0, s, jobs, off, nj,
+                           (int64_t)out, sts, g->bs_ts.as<int64_t>(), bm, tcnt);
+    TW_HIP(scan_exclusive_u32(tcnt, tcnt, nt, tcnt + nt, g->ws, s));
     if (out > 0)
-        hipLaunchKernelGGL(k_job_write, dim3((unsigned)ceil_div((int64_t)out, NV_TILE)), dim3(T), 0,
-                           s, jobs, off, nj, (int64_t)out, sdst, sts, g->bs_dst.as<int32_t>(),
-                           g->bs_ts.as<int64_t>(), oflag, rank, ddst, dts, dng, dfence);
-    hipLaunchKernelGGL(k_job_finish, grid_for(nj), dim3(T), 0, s, jobs, off, nj, rank, dng,
-                       g->rec.as<NodeRec>(), g->seg.as<SegRec>(), gen, g->j_fw.as<uint32_t>());
+        hipLaunchKernelGGL(k_job_write, dim3((unsigned)nt), dim3(T), 0, s, jobs, off, nj,
+                           (int64_t)out, sdst, sts, g->bs_dst.as<int32_t>(),
+                           g->bs_ts.as<int64_t>(), bm, tcnt, pref, ddst, dts, dng, dfence);
+    hipLaunchKernelGGL(k_job_finish, grid_for(nj), dim3(T), 0, s, jobs, off, nj, bm, pref,
+                       (int64_t)out, tcnt + nt, dng, g->rec.as<NodeRec>(), g->seg.as<SegRec>(),
+                       gen, g->j_fw.as<uint32_t>());
     TW_HIP(scan_jobs(g->j_fw.as<uint32_t>(), g->j_fw.as<uint32_t>(), nj, g->ws, s));
     hipLaunchKernelGGL(k_job_fence, dim3(FENCE_GRID), dim3(T), 0, s, jobs, g->j_fw.as<uint32_t>(),
                        nj, g->rec.as<NodeRec>(), dng, dfence);

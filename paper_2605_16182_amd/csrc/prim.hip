@@ -4,6 +4,7 @@
 // digit from one ballot per digit bit, then counts the lower ones).
 #include <algorithm>
 
+#include "compact.h"
 #include "tw_internal.h"
 
 namespace tw {
@@ -116,66 +117,23 @@ template <typename V>
 __global__ void k_set(V* p, V v) { *p = v; }
 
 
-// group-start flag of position i: flags[i], or a timestamp change when flags
-// is null
-__device__ __forceinline__ uint32_t start_flag(const uint32_t* __restrict__ flags,
-                                               const int64_t* __restrict__ ts, int64_t i) {
-    if (flags) return flags[i];
-    return (i == 0 || ts[i] != ts[i - 1]) ? 1u : 0u;
-}
-
-__global__ void k_flag_reduce(const uint32_t* __restrict__ flags, const int64_t* __restrict__ ts,
-                              int64_t n, uint32_t* __restrict__ part) {
-    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    uint32_t s = 0;
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        int64_t i = base + (int64_t)j * SCAN_THREADS + threadIdx.x;
-        if (i < n) s += start_flag(flags, ts, i);
+// group starts of a timestamp sequence (group_starts)
+struct GroupStartOp {
+    const int64_t* ts;
+    int has_last;
+    int64_t last_ts;
+    uint32_t pos_base;
+    int64_t* g_ts;
+    uint32_t* g_off;
+    __device__ bool flag(int64_t i) const {
+        return i == 0 ? (!has_last || ts[0] != last_ts) : ts[i] != ts[i - 1];
     }
-    uint32_t total;
-    block_excl_scan(s, &total);
-    if (threadIdx.x == 0) part[blockIdx.x] = total;
-}
-
-// down-sweep that scatters each group start: g_ts[k] = ts[i],
-// g_off[k] = pos_base + i for the k-th flagged position i; g_off[total] =
-// pos_base + n
-__global__ void k_flag_scatter(const uint32_t* __restrict__ flags, const int64_t* __restrict__ ts,
-                               int64_t n, const uint32_t* __restrict__ part, uint32_t pos_base,
-                               int64_t* __restrict__ g_ts, uint32_t* __restrict__ g_off,
-                               const uint32_t* total) {
-    __shared__ uint32_t tile[SCAN_TILE];
-    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        int k = j * SCAN_THREADS + threadIdx.x;
-        int64_t i = base + k;
-        tile[k] = i < n ? start_flag(flags, ts, i) : 0;
+    __device__ void emit(int64_t i, uint32_t k) const {
+        g_ts[k] = ts[i];
+        g_off[k] = pos_base + (uint32_t)i;
     }
-    __syncthreads();
-    uint32_t loc[SCAN_ITEMS];
-    uint32_t s = 0;
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        loc[j] = s;
-        s += tile[threadIdx.x * SCAN_ITEMS + j];
-    }
-    uint32_t tot;
-    uint32_t pre = block_excl_scan(s, &tot) + part[blockIdx.x];
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        const uint32_t f = tile[threadIdx.x * SCAN_ITEMS + j];
-        tile[threadIdx.x * SCAN_ITEMS + j] = f ? pre + loc[j] : UINT32_MAX;
-    }
-    __syncthreads();
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        int k = j * SCAN_THREADS + threadIdx.x;
-        int64_t i = base + k;
-        const uint32_t gk = tile[k];
-        if (i < n && gk != UINT32_MAX) {
-            g_ts[gk] = ts[i];
-            g_off[gk] = pos_base + (uint32_t)i;
-        }
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) g_off[*total] = pos_base + (uint32_t)n;
-}
+    __device__ void end(int64_t n, uint32_t total) const { g_off[total] = pos_base + (uint32_t)n; }
+};
 
 // ------------------------------------------------------------ radix sort
 //
@@ -469,19 +427,16 @@ hipError_t scan_exclusive_i32_to_u64(const int32_t* in, uint64_t* out, int64_t n
     return scan_exclusive<int32_t, uint64_t>(in, out, n, total, ws.scan_part, s);
 }
 
-hipError_t group_starts(const uint32_t* flags, const int64_t* ts, int64_t n, uint32_t pos_base,
-                        int64_t* g_ts, uint32_t* g_off, uint32_t* total, Workspace& ws,
-                        hipStream_t s) {
-    const int64_t nb = std::max<int64_t>(ceil_div(n, SCAN_TILE), 1);
-    hipError_t e = ensure(ws.scan_part, sizeof(uint32_t) * (nb + 1));
-    if (e != hipSuccess) return e;
-    uint32_t* part = ws.scan_part.as<uint32_t>();
-    hipLaunchKernelGGL(k_flag_reduce, dim3(nb), dim3(SCAN_THREADS), 0, s, flags, ts, n, part);
-    hipLaunchKernelGGL(k_scan_partials<uint32_t>, dim3(1), dim3(SCAN_THREADS), 0, s, part, nb,
-                       total);
-    hipLaunchKernelGGL(k_flag_scatter, dim3(nb), dim3(SCAN_THREADS), 0, s, flags, ts, n, part,
-                       pos_base, g_ts, g_off, total);
-    return hipGetLastError();
+hipError_t group_starts(int has_last, int64_t last_ts, const int64_t* ts, int64_t n,
+                        uint32_t pos_base, int64_t* g_ts, uint32_t* g_off, uint32_t* total,
+                        Workspace& ws, hipStream_t s) {
+    if (n <= 0) {
+        hipLaunchKernelGGL(k_set<uint32_t>, dim3(1), dim3(1), 0, s, g_off, pos_base);
+        hipLaunchKernelGGL(k_set<uint32_t>, dim3(1), dim3(1), 0, s, total, 0u);
+        return hipGetLastError();
+    }
+    const GroupStartOp op{ts, has_last, last_ts, pos_base, g_ts, g_off};
+    return compact(op, n, total, ws.tiles, ws, s);
 }
 
 hipError_t radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bit_lo, int bit_hi,

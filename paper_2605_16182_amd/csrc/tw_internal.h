@@ -163,7 +163,7 @@ struct Workspace {
     DevBuf scan_part;   // scan partial sums
     DevBuf hist;        // radix histograms
     DevBuf keys_alt, vals_alt, v64_alt;
-    DevBuf misc;        // small scalars
+    DevBuf tiles;       // per-tile counts of the two-pass compaction
 };
 
 // -------------------------------------------------------------- primitives
@@ -177,13 +177,14 @@ hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint
 hipError_t scan_exclusive_i32_to_u64(const int32_t* in, uint64_t* out, int64_t n, uint64_t* total,
                                      Workspace& ws, hipStream_t s);
 
-// Groups of a sequence: the k-th position i that starts a group (flags[i]
-// != 0, or with flags null, ts[i] != ts[i-1]) gives g_ts[k] = ts[i] and
+// Groups of a sequence of timestamps: the k-th position i that starts a group
+// (ts[i] != ts[i-1]; position 0 always, or with has_last, when ts[0] !=
+// last_ts, the timestamp before the sequence) gives g_ts[k] = ts[i] and
 // g_off[k] = pos_base + i; g_off[total] = pos_base + n; total (device) = the
 // number of groups. n may be 0.
-hipError_t group_starts(const uint32_t* flags, const int64_t* ts, int64_t n, uint32_t pos_base,
-                        int64_t* g_ts, uint32_t* g_off, uint32_t* total, Workspace& ws,
-                        hipStream_t s);
+hipError_t group_starts(int has_last, int64_t last_ts, const int64_t* ts, int64_t n,
+                        uint32_t pos_base, int64_t* g_ts, uint32_t* g_off, uint32_t* total,
+                        Workspace& ws, hipStream_t s);
 
 // Stable LSD radix sort of (keys, vals) by bits [bit_lo, bit_hi) of the key.
 // vals may be null. Result ends in keys / vals. The alternate buffers come
@@ -292,7 +293,7 @@ struct tw_graph {
                 &c_t2, &c_prev, &c_flags, &c_pos, &wq,
                 &b_src, &b_dst, &b_ts, &b_keys, &b_vals, &b_flags, &flags, &idx, &v_flags,
                 &v_pos, &err, &scal, &ws.scan_part, &ws.hist, &ws.keys_alt, &ws.vals_alt,
-                &ws.v64_alt, &ws.misc};
+                &ws.v64_alt, &ws.tiles};
     }
 };
 
