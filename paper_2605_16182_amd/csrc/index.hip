@@ -295,17 +295,38 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
         err = Error{TW_EINVAL, "window would exceed 2^32 - 2 records"};
         return err.code;
     }
-    TW_HIP(ensure(g->b_src, sizeof(int32_t) * (B + 1)));
-    TW_HIP(ensure(g->b_dst, sizeof(int32_t) * (B + 1)));
-    TW_HIP(ensure(g->b_ts, sizeof(int64_t) * (B + 1)));
+    // Staging place of the batch: the free tail of the window buffers, else
+    // the alternate buffers, else the staging buffers. A sorted batch staged
+    // in the tail is appended where it lies; one staged in the alternates
+    // becomes the window by a swap when nothing of the old window survives.
+    enum Place { IN_TAIL, IN_ALT, IN_BUF };
+    Place place = IN_BUF;
+    int32_t *s_src, *s_dst;
+    int64_t* s_ts;
+    if (B > 0 && g->e_base + g->m + B <= g->e_cap) {
+        place = IN_TAIL;
+        const int64_t at = g->e_base + g->m;
+        s_src = g->e_src.as<int32_t>() + at;
+        s_dst = g->e_dst.as<int32_t>() + at;
+        s_ts = g->e_ts.as<int64_t>() + at;
+    } else if (B > 0 && B <= g->e_cap) {
+        place = IN_ALT;
+        s_src = g->a_src.as<int32_t>();
+        s_dst = g->a_dst.as<int32_t>();
+        s_ts = g->a_ts.as<int64_t>();
+    } else {
+        TW_HIP(ensure(g->b_src, sizeof(int32_t) * (B + 1)));
+        TW_HIP(ensure(g->b_dst, sizeof(int32_t) * (B + 1)));
+        TW_HIP(ensure(g->b_ts, sizeof(int64_t) * (B + 1)));
+        s_src = g->b_src.as<int32_t>();
+        s_dst = g->b_dst.as<int32_t>();
+        s_ts = g->b_ts.as<int64_t>();
+    }
 
     unsigned long long* mm = reinterpret_cast<unsigned long long*>(i64_slot(g, SLOT_I64_MINMAX));
     uint32_t* errf = g->err.as<uint32_t>();
     uint32_t* unsorted = u32_slot(g, SLOT_U32_UNSORTED);
     hipLaunchKernelGGL(k_init_minmax, dim3(1), dim3(1), 0, s, mm, errf + 1, unsorted);
-    int32_t* s_src = g->b_src.as<int32_t>();
-    int32_t* s_dst = g->b_dst.as<int32_t>();
-    int64_t* s_ts = g->b_ts.as<int64_t>();
     if (n > 0)
         hipLaunchKernelGGL(k_stage, dim3((unsigned)std::min<int64_t>(ceil_div(n, T), 2048)),
                            dim3(T), 0, s, src, dst, ts, n, g->V, g->directed ? 1 : 0, s_src, s_dst,
@@ -428,15 +449,47 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
     const int64_t last_ts = g->t_max;
     const int64_t gg_old = g->Gg;
     bool gg_full = false;
+    // A sorted batch still lies where it was staged. In the window tail it
+    // stays there when appended after the surviving records (no late prefix
+    // in between) or when it is the whole new window, and a merge only reads
+    // it; in the alternates it stays when it is the whole new window. In any
+    // other case the update would move it over itself or overwrite it, so it
+    // is copied to the staging buffers first.
+    const bool q_tail = sorted && kept > 0 && place == IN_TAIL;
+    const bool q_alt = sorted && kept > 0 && place == IN_ALT;
+    const bool keep_tail = q_tail && (!append || na == 0 || drop_lo == 0);
+    const bool keep_alt = q_alt && append && na == 0;
+    if ((q_tail && !keep_tail) || (q_alt && !keep_alt)) {
+        TW_HIP(ensure(g->b_src, sizeof(int32_t) * (kept + 1)));
+        TW_HIP(ensure(g->b_dst, sizeof(int32_t) * (kept + 1)));
+        TW_HIP(ensure(g->b_ts, sizeof(int64_t) * (kept + 1)));
+        TW_HIP(hipMemcpyAsync(g->b_src.p, q_src, 4 * kept, hipMemcpyDeviceToDevice, s));
+        TW_HIP(hipMemcpyAsync(g->b_dst.p, q_dst, 4 * kept, hipMemcpyDeviceToDevice, s));
+        TW_HIP(hipMemcpyAsync(g->b_ts.p, q_ts, 8 * kept, hipMemcpyDeviceToDevice, s));
+        q_src = g->b_src.as<int32_t>();
+        q_dst = g->b_dst.as<int32_t>();
+        q_ts = g->b_ts.as<int64_t>();
+    }
     if (append) {
         g->e_base += evicted;
         g->gg_base += gg_evicted;
         if (na == 0) {
             g->e_base = 0;
             g->gg_base = 0;
+            if (keep_tail) {
+                g->e_base = q_src - g->e_src.as<int32_t>();
+            } else if (keep_alt) {
+                std::swap(g->e_src, g->a_src);
+                std::swap(g->e_dst, g->a_dst);
+                std::swap(g->e_ts, g->a_ts);
+                g->e_base = drop_lo;
+            }
         }
+        // the batch already lies at e_base + na (and fits: it was staged
+        // inside the buffers' capacity)
+        const bool placed = keep_tail || keep_alt;
         g->m = na;
-        if (g->e_base + m_new > g->e_cap) {
+        if (!placed && g->e_base + m_new > g->e_cap) {
             if (m_new <= g->e_cap && g->m > 0) {
                 // compact to the front of the alternate buffers
                 TW_HIP(hipMemcpyAsync(g->a_src.p, g->e_src.as<int32_t>() + g->e_base, 4 * na,
@@ -454,7 +507,7 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
             }
             gg_full = true;
         }
-        if (kept > 0) {
+        if (kept > 0 && !placed) {
             const int64_t at = g->e_base + na;
             TW_HIP(hipMemcpyAsync(g->e_src.as<int32_t>() + at, q_src, 4 * kept,
                                   hipMemcpyDeviceToDevice, s));

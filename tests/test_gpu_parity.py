@@ -291,6 +291,47 @@ def test_long_stream_compactions(sorted_arrivals):
     g.close()
 
 
+def test_sorted_batches_staged_in_place():
+    # sorted batches of mixed sizes, so that they are staged in the free tail
+    # of the window buffers, in the alternate buffers or in the staging
+    # buffers; each kind of update in turn: appended after the window, merged
+    # into its end, a late prefix under the window cut followed by records
+    # after the window, and a jump that evicts the whole window
+    torch, tw = gpu_or_skip()
+    rng = np.random.default_rng(31)
+    V, window = 101, 5_000
+    g = tw.Graph(V, window=window)
+    og = oracle.OracleGraph(V, window=window)
+    t0 = 0
+    for b in range(48):
+        n = int(rng.choice([50, 400, 1500, 5000, 20000]))
+        kind = b % 4
+        if kind == 0:
+            t = rng.integers(t0 + 1, t0 + 1001, n)
+        elif kind == 1:
+            t = rng.integers(t0 - 800, t0 + 500, n)
+        elif kind == 2:
+            late = n // 3
+            t = np.concatenate([rng.integers(t0 - 6500, t0 - 4100, late),
+                                rng.integers(t0 + 1, t0 + 999, n - late - 1), [t0 + 999]])
+        else:
+            t = rng.integers(t0 + 3 * window, t0 + 3 * window + 1000, n)
+        t = np.sort(t).astype(np.int64)
+        t0 = max(t0, int(t[-1]))
+        s = rng.integers(0, V, n).astype(np.int32)
+        d = rng.integers(0, V, n).astype(np.int32)
+        assert g.ingest_batch(*to_dev(torch, s, d, t)) == og.ingest_batch(s, d, t), b
+        _views_equal(g, og)
+        if b % 8 == 7:
+            nodes, ts, lens = g.sample_walks(300, 10, hop_bias="uniform", seed=b)
+            g.sync()
+            r = og.sample_walks(300, 10, hop_bias="uniform", seed=b)
+            assert np.array_equal(nodes.cpu().numpy(), r["nodes"])
+            assert np.array_equal(ts.cpu().numpy(), r["ts"])
+            assert np.array_equal(lens.cpu().numpy(), r["len"])
+    g.close()
+
+
 def test_fresh_graph_reports_no_error():
     # device error flags start cleared: a fresh graph's first synchronising
     # calls succeed, before and after edge-start walks
