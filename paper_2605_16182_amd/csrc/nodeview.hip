@@ -496,7 +496,22 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
         nts[pos] = e.ts;
         const int lt = (int)(t - base);
         const uint64_t word = sbm[lt >> 6];
-        if ((word >> (lt & 63)) & 1ull) {
+        const bool starts = (word >> (lt & 63)) & 1ull;
+        if (i == 0 && J.kind == JOB_APPEND && !starts) {
+            // the first new edge joins the node's last group: no longer a
+            // one-edge group
+            int32_t* d = &ngd[J.oge - 1].dst;
+            *d = *d & 0x7fffffff;
+        }
+        if (starts) {
+            // a one-edge group: the job's next output starts a group, or
+            // there is none
+            bool single = (uint64_t)t + 1 >= (uint64_t)off[j + 1];
+            if (!single) {
+                const int ln = lt + 1;
+                const uint64_t nw = ln < NV_TILE ? sbm[ln >> 6] : bm[(uint64_t)(t + 1) >> 6];
+                single = (nw >> (ln & 63)) & 1ull;
+            }
             const uint32_t rk = spre[lt >> 6] + (uint32_t)__popcll(word & below(lt & 63));
             uint32_t kj;
             if ((int64_t)jb >= base) {
@@ -508,7 +523,7 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
             GroupRec g;
             g.ts = e.ts;
             g.first = pos;
-            g.dst = e.dst;
+            g.dst = single ? (int32_t)((uint32_t)e.dst | 0x80000000u) : e.dst;
             const uint32_t gi = J.g_at + (rk - kj);
             ngd[gi] = g;
             // the group's level-0 fence key (segments of more than

@@ -16,9 +16,9 @@ namespace tw {
 constexpr int64_t TS_NONE = INT64_MIN;
 
 // One (node, timestamp) group of the node view, 16 bytes: the timestamp,
-// the pool position of the group's first edge and that edge's destination
-// (a one-edge group needs no edge load). Eight records fill one 128-byte
-// line, so a fence leaf window is one line.
+// the pool position of the group's first edge and that edge's destination,
+// with the sign bit set when the group holds that edge only (a pick of a
+// one-edge group needs neither the next record nor an edge load).
 struct alignas(16) GroupRec {
     int64_t ts;
     uint32_t first;

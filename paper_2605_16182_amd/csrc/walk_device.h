@@ -208,9 +208,9 @@ __device__ __forceinline__ Pick pick_node(const GroupRec* __restrict__ ng,
     const uint32_t n = ge - gc;
     const uint32_t k = gc + pick_group(n, kind, tau, n > 1 ? ng[gc].ts : 0, t_last, d.x0);
     const GroupRec a = ng[k];
+    if (a.dst < 0) return Pick{a.dst & 0x7fffffff, a.ts};  // a one-edge group
     const uint32_t size = (k + 1 < ge ? ng[k + 1].first : end) - a.first;
-    const int32_t dst = size == 1 ? a.dst : n_dst[a.first + (uint32_t)scale_u64(d.x1, size)];
-    return Pick{dst, a.ts};
+    return Pick{n_dst[a.first + (uint32_t)scale_u64(d.x1, size)], a.ts};
 }
 
 // The edge-store position picked among the window's Gg timestamp groups.
