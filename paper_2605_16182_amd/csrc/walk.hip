@@ -258,6 +258,7 @@ __global__ void __launch_bounds__(WALK_THREADS) k_walk_full(const WalkArgs a) {
 // its hop bias (one of up to TW_MAX_BIASES) and its output row.
 
 constexpr int QUEUE_SLICES = 8;
+constexpr int QUEUE_REFILL_MIN = 32;  // idle lanes that trigger a refill (hop-only queue)
 
 struct QueueArgs {
     unsigned long long* counters;  // QUEUE_SLICES counters, zero at launch
@@ -402,7 +403,11 @@ k_walk_hops(const WalkArgs a, Live live, const int32_t* __restrict__ prev_of,
     const HopBias hb = fixed_hop<HK>(a.hop);
     while (true) {
         const uint64_t idle = __ballot(w < 0);
-        if (idle && exhausted < QUEUE_SLICES) {
+        // refill once half the lanes are idle: a refill is an atomic round
+        // trip and three dependent loads on the wavefront's critical path,
+        // and plain walks end after a few hops
+        if (exhausted < QUEUE_SLICES &&
+            (idle == ~0ull || (idle && __popcll(idle) >= QUEUE_REFILL_MIN))) {
             const int n = __popcll(idle);
             const int leader = __ffsll((unsigned long long)idle) - 1;
             unsigned long long got = 0;

@@ -146,9 +146,39 @@ __device__ __forceinline__ uint32_t fence_search(const GroupRec* __restrict__ ng
     if (t < base) return r.gb;  // every group of the segment is later
     const uint32_t q = (uint32_t)((uint64_t)(t - base) >> h.z);
     const uint64_t cap = seg_groups(r.lv >> 8);
-    uint64_t off = fence_level_off(cap, K);
+    int k = K;
     uint64_t lo = 0;
-    for (int k = K; k >= 0; --k) {
+    // A deep fence starts lower: at level k0, whose entries are 8^k0 groups
+    // apart with 8^k0 about sqrt(n) / 4, the window around the entry that
+    // t's place between the segment's first and last timestamps predicts.
+    // When that window brackets t (a key <= t, and one > t or the level's
+    // end), the descent goes on from there; otherwise from the top.
+    const uint32_t n = r.ge - r.g0;
+    const int k0 = (31 - __clz(n) + 2) / 6;
+    if (k0 + 1 < K) {
+        const uint64_t cnt = (n + (1ull << (FENCE_LOG * k0)) - 1) >> (FENCE_LOG * k0);
+        const double fr = (double)(t - base) / (double)(r.t_last - base);
+        const uint64_t e = (uint64_t)(fr * (double)cnt);
+        uint64_t lo0 = e >= 4 ? (e - 4) & ~3ull : 0;  // 16-byte aligned
+        const uint64_t top = ((cnt + FENCE_FAN - 1) & ~(uint64_t)(FENCE_FAN - 1)) - FENCE_FAN;
+        if (lo0 > top) lo0 = top;
+        const uint64_t at = r.fence_off + fence_level_off(cap, k0) + lo0;
+        const uint32_t* win = at >= panel_base && at + FENCE_FAN <= panel_base + panel_len
+                                  ? panel + (at - panel_base)
+                                  : fence + at;
+        const uint32_t c = window_count(win, q, t, ng, r.g0 + (lo0 << (FENCE_LOG * k0)),
+                                        1ull << (FENCE_LOG * k0));
+        if (c >= 1 && (c < FENCE_FAN || lo0 + FENCE_FAN >= cnt)) {
+            if (k0 == 0) {
+                const uint32_t res = r.g0 + (uint32_t)lo0 + c;
+                return res < r.gb ? r.gb : res;
+            }
+            k = k0 - 1;
+            lo = (lo0 + c - 1) * FENCE_FAN;
+        }
+    }
+    uint64_t off = fence_level_off(cap, k);
+    for (; k >= 0; --k) {
         const uint64_t at = r.fence_off + off + lo;
         const uint32_t* win = at >= panel_base && at + FENCE_FAN <= panel_base + panel_len
                                   ? panel + (at - panel_base)
