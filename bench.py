@@ -146,8 +146,8 @@ def ingest_bytes(b_in, kept, evicted, jobs):
     (32 B), append them to the timestamp view with its group records (16 + 12
     B) and to their nodes' runs in the node view with group records (12 + 16
     B), read the sources of the evicted records (4 B), and read and write the
-    record of every node whose run changed (64 B)."""
-    return 16 * b_in + 88 * kept + 4 * evicted + 64 * jobs
+    record of every node whose run changed (2 x 48 B)."""
+    return 16 * b_in + 88 * kept + 4 * evicted + 96 * jobs
 
 
 def rebuild_bytes(b, m_old, m_new, V):

@@ -56,6 +56,7 @@ __device__ __forceinline__ NodeRec empty_rec() {
     r.gb = r.ge = r.g0 = r.ee = 0;
     r.fence_off = r.lv = 0;
     r.t_last = INT64_MIN;
+    r.kbase = r.pad = 0;
     return r;
 }
 
@@ -217,9 +218,8 @@ __global__ void k_job_setup(const uint32_t* __restrict__ c_node, const uint32_t*
         // timestamp must still have a key below UINT32_MAX
         bool keys_fit = true;
         if (has_seg && ne > 0 && k > 0 && fence_cap(seg_groups(sg.gcode)) > 0) {
-            const uint32_t* h = fence + sg.f0;
-            J.kbase = (int64_t)(((uint64_t)h[1] << 32) | h[0]);
-            J.kshift = h[2];
+            J.kbase = r.kbase;
+            J.kshift = rec_shift(r.lv);
             keys_fit = bts[J.be - 1] >= J.kbase &&
                        ((uint64_t)(bts[J.be - 1] - J.kbase) >> J.kshift) < 0xFFFFFFFFull;
         }
@@ -529,7 +529,7 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
             // the group's level-0 fence key (segments of more than
             // FENCE_FAN groups have a fence)
             if (J.gcode > 0)
-                fence[(uint64_t)J.f0 + FENCE_HDR + (gi - J.g0)] =
+                fence[(uint64_t)J.f0 + (gi - J.g0)] =
                     (uint32_t)((uint64_t)(e.ts - J.kbase) >> J.kshift);
         }
     }
@@ -550,7 +550,7 @@ __device__ __forceinline__ uint64_t pad_fan(uint64_t c) {
 // k_job_fence (k_job_write stores the level-0 keys with the group records).
 __device__ __forceinline__ uint32_t rewrite_words(uint64_t cap, uint64_t n) {
     if (fence_cap(cap) == 0) return 0;
-    uint64_t w = FENCE_HDR + pad_fan(n) - n;  // level 0: its padding only
+    uint64_t w = pad_fan(n) - n;  // level 0: its padding only
     const int K = fence_levels(cap);
     for (int k = 1; k <= K; ++k) w += pad_fan(level_count(n, k));
     return (uint32_t)w;
@@ -621,7 +621,8 @@ __global__ void k_job_finish(const Job* __restrict__ jobs, const uint32_t* __res
         }
         r.g0 = J.g0;
         r.fence_off = J.f0;
-        r.lv = (uint32_t)fence_levels(r.ge - J.g0) | (J.gcode << 8);
+        r.lv = (uint32_t)fence_levels(r.ge - J.g0) | (J.gcode << 8) | (J.kshift << 16);
+        r.kbase = J.kbase;
         r.t_last = ngd[r.ge - 1].ts;
     }
     rec[J.v] = r;
@@ -629,25 +630,18 @@ __global__ void k_job_finish(const Job* __restrict__ jobs, const uint32_t* __res
 }
 
 // Fence word u of job J (u counts the words the job writes): a rewritten
-// segment writes its header (key base and shift) and, on every level, the
-// keys and the padding; an append the keys and padding its new groups add.
-// Level-0 keys are written by k_job_write, so level 0 contributes padding only.
+// segment writes, on every level, the keys and the padding; an append the
+// keys and padding its new groups add. Level-0 keys are written by
+// k_job_write, so level 0 contributes padding only. Keys are taken under the
+// job's key base and shift (the node record carries both).
 __device__ __forceinline__ void fence_entry(const Job& J, uint32_t ge,
                                             const GroupRec* __restrict__ ngd,
                                             uint32_t* __restrict__ fence, uint64_t u) {
     const uint64_t cap = seg_groups(J.gcode);
     uint32_t* f = fence + J.f0;
     const uint64_t n = ge - J.g0;
-    if (J.kind == JOB_REWRITE) {
-        if (u < FENCE_HDR) {
-            f[u] = u == 0 ? (uint32_t)(uint64_t)J.kbase
-                          : u == 1 ? (uint32_t)((uint64_t)J.kbase >> 32) : u == 2 ? J.kshift : 0u;
-            return;
-        }
-        u -= FENCE_HDR;
-    }
     const int K = fence_levels(cap);
-    uint64_t off = FENCE_HDR;
+    uint64_t off = 0;
     for (int k = 0; k <= K; ++k) {
         uint64_t key0 = 0, nkeys, pad0, npad;
         if (J.kind == JOB_REWRITE) {

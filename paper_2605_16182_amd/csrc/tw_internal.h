@@ -25,23 +25,33 @@ struct alignas(16) GroupRec {
     int32_t dst;
 };
 
-// One record per node, 32 bytes, read with one load per hop. A node's edges
+// One record per node, 48 bytes, read at the start of every hop (three
+// independent 16-byte loads). A node's edges
 // and groups live in a segment of the edge and group pools: the live groups
 // are [gb, ge), the live edges end at ee (they start at the first edge of
 // group gb). g0 is the segment's first group (a multiple of FENCE_FAN), the
 // origin of the node's fence; fence_off is where the fence starts in the
-// fence pool; lv = levels in use | (capacity code << 8), the segment holding
-// FENCE_FAN << code groups. t_last is the last live timestamp (INT64_MIN for
-// a node without edges), so a hop that cannot continue stops after this load.
-struct alignas(32) NodeRec {
+// fence pool; lv = levels in use | (capacity code << 8) | (key shift << 16),
+// the segment holding FENCE_FAN << code groups. t_last is the last live
+// timestamp (INT64_MIN for a node without edges), so a hop that cannot
+// continue stops after this load. kbase is the fence's key base (the
+// segment's first group timestamp): with the shift here, a search needs no
+// load before its first fence window.
+struct alignas(16) NodeRec {
     uint32_t gb, ge, g0, ee;
     uint32_t fence_off, lv;
     int64_t t_last;
+    int64_t kbase;
+    int64_t pad;
 };
+static_assert(sizeof(NodeRec) == 48, "three 16-byte loads");
+__host__ __device__ inline uint32_t rec_levels(uint32_t lv) { return lv & 0xffu; }
+__host__ __device__ inline uint32_t rec_code(uint32_t lv) { return (lv >> 8) & 0xffu; }
+__host__ __device__ inline uint32_t rec_shift(uint32_t lv) { return (lv >> 16) & 0xffu; }
 
 // Fence index with 32-bit keys. A segment of capacity C > FENCE_FAN groups
-// has a fence of FENCE_HDR header words (the key base, a 64-bit timestamp,
-// in words 0-1 and the key shift in word 2) and levels k = 0..K(C): level k
+// has a fence of levels k = 0..K(C) (key base and shift are in the node
+// record): level k
 // holds the keys of groups g0 + i FENCE_FAN^k, i < ceil(C / FENCE_FAN^k),
 // padded to a multiple of FENCE_FAN words; key(g) = (ts(g) - base) >> shift,
 // and unwritten entries hold UINT32_MAX. Ingest keeps every key of a segment
@@ -56,7 +66,6 @@ struct alignas(32) NodeRec {
 // have no fence: their few groups are counted directly.
 constexpr int FENCE_FAN = 8;
 constexpr int FENCE_LOG = 3;
-constexpr int FENCE_HDR = 8;  // header words (32 bytes)
 
 // most levels a fence can have: group indices are 32-bit
 constexpr int FENCE_MAX_LEVELS = (32 + FENCE_LOG - 1) / FENCE_LOG + 1;
@@ -81,7 +90,7 @@ __host__ __device__ inline uint32_t fence_level_len(uint64_t cap, int k) {
 // total fence words of a segment of cap groups (0: no fence)
 __host__ __device__ inline uint32_t fence_cap(uint64_t cap) {
     if (cap <= (uint64_t)FENCE_FAN) return 0;
-    uint32_t s = FENCE_HDR;
+    uint32_t s = 0;
     const int K = fence_levels(cap);
     for (int k = 0; k <= K; ++k) s += fence_level_len(cap, k);
     return s;
@@ -89,7 +98,7 @@ __host__ __device__ inline uint32_t fence_cap(uint64_t cap) {
 
 // word offset of level k inside a segment's fence
 __host__ __device__ inline uint32_t fence_level_off(uint64_t cap, int k) {
-    uint32_t off = FENCE_HDR;
+    uint32_t off = 0;
     for (int j = 0; j < k; ++j) off += fence_level_len(cap, j);
     return off;
 }

@@ -671,9 +671,9 @@ k_hop_coop(const WalkArgs a, Live cur, Live nxt, int32_t* __restrict__ prev_of, 
         const NodeRec r = a.rec[node];
         const uint32_t slice = wg_uniform ? panel_cap : panel_cap / (WALK_THREADS / 64);
         uint32_t* dst = wg_uniform ? panel : panel + wave * slice;
-        const int K = (int)(r.lv & 0xffu);
+        const int K = (int)rec_levels(r.lv);
         if (K > 0) {
-            const uint64_t cap = seg_groups(r.lv >> 8);
+            const uint64_t cap = seg_groups(rec_code(r.lv));
             const uint64_t top = (uint64_t)r.fence_off + fence_level_off(cap, K) +
                                  fence_level_len(cap, K);  // end of level K
             uint64_t from = top;

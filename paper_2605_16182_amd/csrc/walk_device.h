@@ -127,9 +127,9 @@ __device__ __forceinline__ uint32_t window_count(const uint32_t* win, uint32_t q
 }
 
 // Gamma lookup (Sec. "Dual-Index Organization": the node's first timestamp
-// group strictly after t) through the node's fence: the header (key base and
-// shift), then one 8-word key window per level from the top level in use
-// down to level 0. Requires t < r.t_last, so the result is below r.ge.
+// group strictly after t) through the node's fence: with the key base and
+// shift from the node record, one 8-word key window per level from the top
+// level in use down to level 0. Requires t < r.t_last, so the result is below r.ge.
 // Returns the absolute group index. panel (nullable) holds fence words
 // [panel_base, panel_base + panel_len) in LDS; windows inside it are read
 // from there.
@@ -138,14 +138,12 @@ __device__ __forceinline__ uint32_t fence_search(const GroupRec* __restrict__ ng
                                                  const NodeRec& r, int64_t t,
                                                  const uint32_t* panel, uint64_t panel_base,
                                                  uint32_t panel_len) {
-    const int K = (int)(r.lv & 0xffu);
+    const int K = (int)rec_levels(r.lv);
     if (K == 0) return r.gb + count_le(ng, r.gb, r.ge, t);
-    const uint32_t* f = fence + r.fence_off;
-    const uint4 h = *reinterpret_cast<const uint4*>(f);
-    const int64_t base = (int64_t)(((uint64_t)h.y << 32) | h.x);
+    const int64_t base = r.kbase;
     if (t < base) return r.gb;  // every group of the segment is later
-    const uint32_t q = (uint32_t)((uint64_t)(t - base) >> h.z);
-    const uint64_t cap = seg_groups(r.lv >> 8);
+    const uint32_t q = (uint32_t)((uint64_t)(t - base) >> rec_shift(r.lv));
+    const uint64_t cap = seg_groups(rec_code(r.lv));
     int k = K;
     uint64_t lo = 0;
     // A deep fence starts lower: at level k0, whose entries are 8^k0 groups
