@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_build", "libtw_oracle.so")
 _lib = None
 
-KINDS = {"uniform": 0, "linear": 1, "exponential": 2, "node2vec": 3}
+KINDS = {"uniform": 0, "linear": 1, "exponential": 2, "node2vec": 3, "weight": 4}
 START_MODES = {"edge": 0, "node": 1}
 ST_OK, ST_EINVAL, ST_ERANGE = 0, 1, 4
 
@@ -53,6 +53,8 @@ def _load():
     lib.oracle_pick_exponential.restype = i64
     lib.oracle_exp_lambda.argtypes = [i64, i64, i64, dbl]
     lib.oracle_exp_lambda.restype = dbl
+    lib.oracle_pick_weight.argtypes = [p, i64, dbl, u64, p]
+    lib.oracle_pick_weight.restype = i64
     lib.oracle_unit_open.argtypes = [u64]
     lib.oracle_unit_open.restype = dbl
     lib.oracle_create.argtypes = [i32, i32, i64]
@@ -102,6 +104,15 @@ def pick_linear(n: int, x: int) -> int:
 def pick_exponential(n: int, lam: float, x: int):
     m = ctypes.c_double(0.0)
     i = _load().oracle_pick_exponential(n, lam, x, ctypes.byref(m))
+    return int(i), float(m.value)
+
+
+def pick_weight(ts, tau: float, x: int):
+    """Weight-based pick over candidate edges with timestamps ts (ascending):
+    (index, distance of the draw from the nearest boundary)."""
+    a = np.ascontiguousarray(ts, np.int64)
+    m = ctypes.c_double(0.0)
+    i = _load().oracle_pick_weight(_ptr(a), len(a), float(tau), x, ctypes.byref(m))
     return int(i), float(m.value)
 
 

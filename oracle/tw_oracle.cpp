@@ -22,6 +22,10 @@
  *   - the index-based closed-form pickers, Eqs. (1)-(3), and temporal
  *     node2vec by rejection on the exponential proposal with acceptance
  *     beta / max(1/p, 1, 1/q) (Sec. "Temporal Bias Sampling");
+ *   - the weight-based exponential picker, the paper's default sampler:
+ *     each candidate edge e_i of Gamma_t(v) weighs exp(t_i - t_min), the
+ *     cumulative array W over the candidates in order, and a draw u picks
+ *     the smallest k with W[k] >= u W[n-1] (Sec. "Temporal Bias Sampling");
  *   - ties on timestamps broken uniformly at random (Sec. "Design
  *     Constraints").
  *
@@ -35,6 +39,12 @@
  *   - Eq. (3) is read as the exact inverse CDF of P(i) ~ exp(lambda*i) on
  *     i = 0..n-1, with lambda = (t_last - t_first) / ((n-1) * tau), or
  *     lambda = 1 when tau <= 0;
+ *   - weight-based picker: weights exp((t_i - t_min) / tau) with tau in
+ *     timestamp units (tau <= 0: tau = 1, the printed form), evaluated as
+ *     exp((t_i - t_last) / tau) with t_last the candidates' last timestamp:
+ *     the common factor exp((t_last - t_min) / tau) cancels from u W[n-1]
+ *     and W[k], the law is unchanged and no weight overflows; u is the open
+ *     uniform U_open(x0); W is summed edge by edge in candidate order;
  *   - node2vec: beta = 1/p when the candidate is the previous node, 1 when
  *     the active window holds an edge prev -> candidate, else 1/q;
  *   - max_len counts nodes; the first pick is RNG hop 0;
@@ -59,7 +69,7 @@ typedef unsigned __int128 u128;
 const int64_t TS_NONE = std::numeric_limits<int64_t>::min();
 
 enum { ST_OK = 0, ST_EINVAL = 1, ST_ERANGE = 4 };
-enum { K_UNIFORM = 0, K_LINEAR = 1, K_EXPONENTIAL = 2, K_NODE2VEC = 3 };
+enum { K_UNIFORM = 0, K_LINEAR = 1, K_EXPONENTIAL = 2, K_NODE2VEC = 3, K_WEIGHT = 4 };
 enum { START_EDGE = 0, START_NODE = 1 };
 
 struct Edge {
@@ -161,6 +171,38 @@ int64_t pick_exponential(int64_t n, double lam, uint64_t x, double* margin) {
         *margin = std::min(std::fabs(lo), std::fabs(hi));
     }
     return i;
+}
+
+/*
+ * The weight-based picker over n candidate edges with timestamps ts[0..n)
+ * (ascending): weights exp((ts[i] - ts[n-1]) / tau), cumulative sums W
+ * edge by edge, r = u W[n-1] with u = U_open(x); returns the smallest k with
+ * W[k] >= r. margin: the distance of u from the nearest boundary W[k] /
+ * W[n-1] around the picked index (0 and 1 are not boundaries: u lies
+ * strictly between them).
+ */
+int64_t pick_weight(const int64_t* ts, int64_t n, double tau, uint64_t x, double* margin) {
+    const double sc = tau > 0.0 ? tau : 1.0;
+    std::vector<double> W((size_t)n);
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        acc += std::exp((double)(ts[i] - ts[n - 1]) / sc);
+        W[(size_t)i] = acc;
+    }
+    const double u = unit_open(x);
+    const double r = u * W[(size_t)(n - 1)];
+    int64_t lo = 0, hi = n - 1;  // smallest k with W[k] >= r
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (W[(size_t)mid] >= r) hi = mid; else lo = mid + 1;
+    }
+    if (margin) {  // interior boundaries only: u is never 0 or 1
+        const double tot = W[(size_t)(n - 1)];
+        *margin = INFINITY;
+        if (lo > 0) *margin = std::fabs(u - W[(size_t)(lo - 1)] / tot);
+        if (lo < n - 1) *margin = std::min(*margin, std::fabs(W[(size_t)lo] / tot - u));
+    }
+    return lo;
 }
 
 /* lambda of the exponential law over groups with first/last timestamps */
@@ -287,6 +329,14 @@ int64_t pick_in_groups(const std::vector<int64_t>& gts, const std::vector<int64_
     if (kind == K_UNIFORM) {
         int64_t c = goff[gc], b = goff[ge];
         return c + pick_uniform(b - c, d.x[0]);
+    }
+    if (kind == K_WEIGHT) {
+        // the candidates edge by edge, each with its group's timestamp
+        const int64_t c = goff[gc], b = goff[ge];
+        std::vector<int64_t> ets((size_t)(b - c));
+        for (int64_t k = gc; k < ge; ++k)
+            for (int64_t e = goff[k]; e < goff[k + 1]; ++e) ets[(size_t)(e - c)] = gts[k];
+        return c + pick_weight(ets.data(), b - c, tau, d.x[0], margin);
     }
     int64_t n = ge - gc, i;
     if (kind == K_LINEAR) {
@@ -415,6 +465,9 @@ int64_t oracle_pick_linear(int64_t n, uint64_t x) { return pick_linear(n, x); }
 int64_t oracle_pick_exponential(int64_t n, double lam, uint64_t x, double* margin) {
     return pick_exponential(n, lam, x, margin);
 }
+int64_t oracle_pick_weight(const int64_t* ts, int64_t n, double tau, uint64_t x, double* margin) {
+    return pick_weight(ts, n, tau, x, margin);
+}
 double oracle_exp_lambda(int64_t t_first, int64_t t_last, int64_t n, double tau) {
     return exp_lambda(t_first, t_last, n, tau);
 }
@@ -523,7 +576,7 @@ void oracle_views(void* h, int32_t* src, int32_t* dst, int64_t* ts, int64_t* g_t
  * walk_id_base + walk_idx[r]. NODE mode reads start_nodes[walk_idx[r]].
  * margin (nullable, n_out * max_len): for each output node, the distance of
  * the pick's uniform draw from the nearest CDF boundary of the exponential
- * law (infinity for exact integer picks). stats[2] = node2vec trial-cap hits,
+ * or weight-based law (infinity for exact integer picks). stats[2] = node2vec trial-cap hits,
  * node2vec trials. Returns ST_OK, ST_EINVAL or ST_ERANGE (some start node out
  * of range; those walks have length 0).
  */
@@ -534,7 +587,7 @@ int oracle_sample_walks(void* h, int32_t max_len, int32_t hop_kind, double hop_t
                         int32_t* len, double* margin, int64_t* stats, int32_t nthreads) {
     Graph& g = *static_cast<Graph*>(h);
     if (max_len < 1 || n_out < 0) return ST_EINVAL;
-    if (hop_kind < K_UNIFORM || hop_kind > K_NODE2VEC) return ST_EINVAL;
+    if (hop_kind < K_UNIFORM || hop_kind > K_WEIGHT) return ST_EINVAL;
     if (start_kind < K_UNIFORM || start_kind > K_EXPONENTIAL) return ST_EINVAL;
     if (hop_kind == K_NODE2VEC && !(p > 0.0 && q > 0.0)) return ST_EINVAL;
     if (start_mode == START_NODE && !start_nodes) return ST_EINVAL;

@@ -87,6 +87,34 @@ def exp_pick(n: int, lam: float, x: int) -> Tuple[int, float]:
     raise AssertionError
 
 
+def weight_masses(ts: List[int], tau: float) -> List[decimal.Decimal]:
+    """The weight-based sampler's weights exactly as printed: exp(t_i - t_min),
+    with tau the time scale (tau <= 0: 1)."""
+    sc = decimal.Decimal(tau if tau > 0 else 1.0)
+    return [(decimal.Decimal(t - ts[0]) / sc).exp() for t in ts]
+
+
+def weight_pick(ts: List[int], tau: float, x: int) -> Tuple[int, float]:
+    """Smallest k with W[k] >= u W[n-1] over the cumulative weights W, and the
+    distance of u from the nearest interior boundary W[k] / W[n-1]."""
+    w = weight_masses(ts, tau)
+    tot = sum(w)
+    u = decimal.Decimal(u_open(x).numerator) / decimal.Decimal(u_open(x).denominator)
+    r = u * tot
+    acc = decimal.Decimal(0)
+    for k, wk in enumerate(w):
+        lo = acc
+        acc += wk
+        if acc >= r:
+            m = decimal.Decimal("Infinity")
+            if k > 0:
+                m = u - lo / tot
+            if k < len(w) - 1:
+                m = min(m, acc / tot - u)
+            return k, float(m)
+    raise AssertionError
+
+
 def exp_lambda(t_first: int, t_last: int, n: int, tau: float) -> float:
     if tau <= 0 or n <= 1:
         return 1.0
@@ -161,6 +189,9 @@ def pick(cands, kind: str, tau: float, d: List[int]):
     """Returns (edge, margin). cands are in view order (timestamp ascending)."""
     if kind == "uniform":
         return cands[scaled(d[0], len(cands))], float("inf")
+    if kind == "weight":
+        k, margin = weight_pick([e[0] for e in cands], tau, d[0])
+        return cands[k], margin
     groups = _groups(cands)
     n = len(groups)
     margin = float("inf")
@@ -247,6 +278,12 @@ def transition_law(g: BruteGraph, cur: int, t: int, prev: Optional[int], kind: s
     if kind == "uniform":
         for e in cands:
             add((e[3], e[0]), 1.0 / len(cands))
+        return probs
+    if kind == "weight":
+        w = weight_masses([e[0] for e in cands], tau)
+        s = sum(w)
+        for e, x in zip(cands, w):
+            add((e[3], e[0]), float(x / s))
         return probs
     if kind == "linear":
         tot = n * (n + 1) / 2

@@ -185,3 +185,52 @@ def test_lambda_uniform_gaps_equal_weight_law():
 def test_unit_open_range():
     assert 0.0 < oracle.unit_open(0) < 1e-15
     assert 1.0 - 1e-15 < oracle.unit_open(2**64 - 1) < 1.0
+
+
+# ------------------------------------------------------ weight-based picker
+
+@pytest.mark.parametrize("n,gap,tau", [(2, 3, 2.0), (5, 1, 1.0), (37, 4, 10.0), (200, 7, 50.0)])
+def test_weight_equal_gaps_is_the_exponential_law(n, gap, tau):
+    # equal gaps make the weights exp(gap i / tau): the law of Eq. (3)'s exact
+    # inverse with lambda = gap / tau, evaluated by a different formula
+    ts = np.arange(n, dtype=np.int64) * gap
+    rng = np.random.default_rng(n)
+    for x in rng.integers(0, 2**64, 3000, dtype=np.uint64):
+        kw, mw = oracle.pick_weight(ts, tau, int(x))
+        ke, me = oracle.pick_exponential(n, gap / tau, int(x))
+        assert kw == ke or min(mw, me) < 1e-9, (x, kw, ke, mw, me)
+
+
+def test_weight_matches_decimal_law():
+    # random timestamps with ties against the printed definition summed in
+    # 60-digit decimal (weights exp(t_i - t_min), scale tau)
+    rng = np.random.default_rng(12)
+    for trial in range(40):
+        n = int(rng.integers(1, 30))
+        ts = np.sort(rng.integers(0, 50, n)).astype(np.int64)
+        tau = float(rng.choice([0.0, 0.7, 3.0, 25.0]))
+        for x in rng.integers(0, 2**64, 200, dtype=np.uint64):
+            k, m = oracle.pick_weight(ts, tau, int(x))
+            kb, mb = brute.weight_pick([int(t) for t in ts], tau, int(x))
+            assert k == kb or min(m, mb) < 1e-9, (trial, x, k, kb, m, mb)
+            if k == kb:
+                assert abs(m - mb) < 1e-9 or (m == mb == float("inf"))
+
+
+def test_weight_large_tau_is_uniform_over_edges():
+    # tau far above the span: every weight is 1, so k = ceil(u n) - 1
+    rng = np.random.default_rng(5)
+    for n in (1, 2, 7, 64, 1000):
+        ts = np.sort(rng.integers(0, 10**6, n)).astype(np.int64)
+        for x in rng.integers(0, 2**64, 500, dtype=np.uint64):
+            u = Fraction(2 * (int(x) >> 12) + 1, 1 << 53)
+            want = -(-(u * n).numerator // (u * n).denominator) - 1
+            k, m = oracle.pick_weight(ts, 1e300, int(x))
+            assert k == want or m < 1e-12
+
+
+def test_weight_single_candidate_and_ties():
+    assert oracle.pick_weight([7], 2.0, 12345) == (0, float("inf"))
+    # four equal timestamps: equal weights, k = ceil(4u) - 1
+    for x, want in [(0, 0), (2**62 - 1, 0), (2**62 + 2**20, 1), (2**64 - 1, 3)]:
+        assert oracle.pick_weight([5, 5, 5, 5], 3.0, x)[0] == want

@@ -50,6 +50,9 @@ CASES = [
     ("node2vec", 6.0, 0.5, 2.0, "uniform", 0.0, "edge", True, 0),
     ("node2vec", 0.0, 2.0, 0.5, "exponential", 2.0, "edge", False, 0),
     ("node2vec", 3.0, 1.0, 1.0, "linear", 0.0, "node", True, 0),
+    ("weight", 6.0, 1, 1, "uniform", 0.0, "edge", True, 0),
+    ("weight", 0.0, 1, 1, "exponential", 4.0, "node", False, 30),
+    ("weight", 40.0, 1, 1, "linear", 0.0, "edge", True, 25),
 ]
 
 
@@ -110,7 +113,8 @@ def _law_chi2(og, bg, kind, tau, p, q, W=60000, L=6, seed=5):
 
 @pytest.mark.parametrize("kind,tau,p,q", [("uniform", 0, 1, 1), ("linear", 0, 1, 1),
                                           ("exponential", 0.0, 1, 1), ("exponential", 8.0, 1, 1),
-                                          ("node2vec", 8.0, 0.5, 2.0), ("node2vec", 0.0, 2.0, 0.5)])
+                                          ("node2vec", 8.0, 0.5, 2.0), ("node2vec", 0.0, 2.0, 0.5),
+                                          ("weight", 4.0, 1, 1), ("weight", 0.0, 1, 1)])
 def test_per_hop_law_chi_square(kind, tau, p, q):
     og, bg = _tiny_graph(77, V=5, n=30, tspan=30)
     chi2, dof, states = _law_chi2(og, bg, kind, tau, p, q)
