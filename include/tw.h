@@ -58,8 +58,23 @@ typedef enum {
  *                  is accepted when U * max(1/p, 1, 1/q) < beta, beta = 1/p
  *                  if w is the previous node, 1 if the window holds an edge
  *                  previous -> w, else 1/q. At most 4096 trials per hop; a
- *                  walk that exhausts them ends there. Hop bias only. */
-typedef enum { TW_UNIFORM = 0, TW_LINEAR = 1, TW_EXPONENTIAL = 2, TW_NODE2VEC = 3 } tw_bias_kind;
+ *                  walk that exhausts them ends there. Hop bias only.
+ *  TW_WEIGHT:      the weight-based exponential picker, the paper's default
+ *                  sampler: every candidate edge weighs exp((t - t_min) /
+ *                  tau) (tau <= 0: 1), and one draw u selects the first edge
+ *                  whose cumulative weight reaches u times the total. The
+ *                  per-node cumulative weights are built on the first walk
+ *                  call after the window changes (or tau changes) and kept;
+ *                  one launch of tw_sample_walks_batch uses one tau for all
+ *                  its TW_WEIGHT biases. Hop bias only; not served by
+ *                  tw_server_submit. */
+typedef enum {
+    TW_UNIFORM = 0,
+    TW_LINEAR = 1,
+    TW_EXPONENTIAL = 2,
+    TW_NODE2VEC = 3,
+    TW_WEIGHT = 4
+} tw_bias_kind;
 
 /* TW_START_EDGE: the first edge is drawn from the whole window (timestamp
  * view) under start_bias. TW_START_NODE: walk i starts at d_start_nodes[i]

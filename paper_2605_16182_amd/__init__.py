@@ -17,8 +17,9 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtw.so")
 
-UNIFORM, LINEAR, EXPONENTIAL, NODE2VEC = 0, 1, 2, 3
-KINDS = {"uniform": UNIFORM, "linear": LINEAR, "exponential": EXPONENTIAL, "node2vec": NODE2VEC}
+UNIFORM, LINEAR, EXPONENTIAL, NODE2VEC, WEIGHT = 0, 1, 2, 3, 4
+KINDS = {"uniform": UNIFORM, "linear": LINEAR, "exponential": EXPONENTIAL, "node2vec": NODE2VEC,
+         "weight": WEIGHT}
 START_EDGE, START_NODE = 0, 1
 START_MODES = {"edge": START_EDGE, "node": START_NODE}
 DISPATCH = {"auto": 0, "full_walk": 1, "coop": 2, "queue": 3}

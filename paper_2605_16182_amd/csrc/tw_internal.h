@@ -148,6 +148,7 @@ constexpr int SLOT_U32_REQ_F = 36;     // fence entries requested
 constexpr int SLOT_U32_FENCE_W = 37;   // fence entries written by the jobs
 constexpr int SLOT_U32_GN = 38;        // node-view groups (counted on demand)
 constexpr int SLOT_U32_EXP_E = 39;     // export: edges
+constexpr int SLOT_U32_W_GROUPS = 40;  // live groups counted by the weight build
 constexpr int SCALAR_BYTES = 256;
 
 // A grow-only device allocation.
@@ -270,6 +271,11 @@ struct tw_graph {
     int64_t st_jobs = 0, st_written = 0, st_new_slots = 0, st_full = 0;
     tw::DevBuf adj, adj_rng;           // node2vec: per-node sorted destinations
     bool adj_ready = false;
+    // weight-based picker: cumulative group weights (group pool slots) for
+    // the time scale w_scale, valid while w_ready
+    tw::DevBuf cw, w_tiles;
+    bool w_ready = false;
+    double w_scale = 0.0;
 
     // cooperative dispatch: per-walk state, live list, sort buffers
     tw::DevBuf c_node0, c_walk0, c_t0, c_node1, c_walk1, c_t1, c_node2, c_walk2, c_t2;
@@ -302,7 +308,7 @@ struct tw_graph {
                 &c_t2, &c_prev, &c_flags, &c_pos, &wq,
                 &b_src, &b_dst, &b_ts, &b_keys, &b_vals, &b_flags, &flags, &idx, &v_flags,
                 &v_pos, &err, &scal, &ws.scan_part, &ws.hist, &ws.keys_alt, &ws.vals_alt,
-                &ws.v64_alt, &ws.tiles};
+                &ws.v64_alt, &ws.tiles, &cw, &w_tiles};
     }
 };
 
@@ -345,6 +351,9 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
                  int64_t n, tw_ingest_info* info, Error& err);
 tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& err);
 tw_status build_adjacency(tw_graph* g, Error& err);
+// weights.hip: cumulative group weights of the node view for the
+// weight-based picker at time scale tau (tau <= 0: 1); a no-op while built.
+tw_status build_weights(tw_graph* g, double tau, Error& err);
 tw_status init_empty(tw_graph* g, Error& err);  // empty index for a graph never ingested
 tw_status export_views(tw_graph* g, int32_t* src, int32_t* dst, int64_t* ts, int64_t* g_ts,
                        int64_t* g_off, int32_t* n_dst, int64_t* n_ts, int64_t* n_gts,

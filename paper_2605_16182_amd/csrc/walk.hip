@@ -44,6 +44,7 @@ struct WalkArgs {
     const uint32_t* fence;
     const int32_t* adj;
     const uint2* adj_rng;
+    const double* cw;  // cumulative group weights (weight-based picker)
     int32_t V;
     // parameters
     int64_t num_walks;
@@ -153,6 +154,13 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, const StartP
 __device__ __forceinline__ bool hop_pick(const WalkArgs& a, const HopBias& hb, uint64_t seed,
                                          const NodeRec& r, uint32_t gc, uint64_t id, uint64_t hop,
                                          int32_t prev, Pick& p, int32_t& nx) {
+    if (hb.kind == TW_WEIGHT) {
+        const Draw d = philox(id, hop, 0, seed);
+        p = pick_weight(a.ng, a.n_dst, a.cw, r.gb, gc, r.ge, r.ee, hb.tau > 0.0 ? hb.tau : 1.0,
+                        r.t_last, d);
+        nx = p.dst;
+        return true;
+    }
     if (hb.kind != TW_NODE2VEC) {
         const Draw d = philox(id, hop, 0, seed);
         p = pick_node(a.ng, a.n_dst, a.n_ts, gc, r.ge, r.ee, hb.kind, hb.tau, r.t_last, d);
@@ -746,6 +754,7 @@ void with_kinds(int hk, int sk, F&& f) {
         case TW_LINEAR: by_start(Kind<TW_LINEAR>{}); break;
         case TW_EXPONENTIAL: by_start(Kind<TW_EXPONENTIAL>{}); break;
         case TW_NODE2VEC: by_start(Kind<TW_NODE2VEC>{}); break;
+        case TW_WEIGHT: by_start(Kind<TW_WEIGHT>{}); break;
         default: by_start(Kind<-1>{}); break;
     }
 }
@@ -805,7 +814,7 @@ tw_status coop_walks(tw_graph* g, const WalkArgs& a, Error& err) {
 namespace {
 
 tw_status check_bias(const tw_bias& b, bool hop, Error& err) {
-    if (b.kind < TW_UNIFORM || b.kind > (hop ? TW_NODE2VEC : TW_EXPONENTIAL) || !valid_tau(b.tau)) {
+    if (b.kind < TW_UNIFORM || b.kind > (hop ? TW_WEIGHT : TW_EXPONENTIAL) || !valid_tau(b.tau)) {
         err = Error{TW_EINVAL, "sample_walks: bad bias kind or tau (start bias cannot be node2vec)"};
         return err.code;
     }
@@ -830,11 +839,15 @@ tw_status check_start(int mode, const int32_t* starts, int64_t num_walks, Error&
 }
 
 // The index part of the walk arguments and the common parameters.
+// Walk arguments over the graph's current views. node2vec: the adjacency
+// is needed; weight_tau (NaN: none) the cumulative weights at that scale.
 tw_status fill_args(tw_graph* g, int64_t num_walks, int32_t L, const tw_bias& sb, int start_mode,
                     const int32_t* starts, uint64_t seed, uint64_t base, bool node2vec,
-                    int32_t* nodes, int64_t* ts, int32_t* len, WalkArgs& a, Error& err) {
+                    double weight_tau, int32_t* nodes, int64_t* ts, int32_t* len, WalkArgs& a,
+                    Error& err) {
     if (!g->rec.p && init_empty(g, err) != TW_OK) return err.code;
     if (node2vec && g->m > 0 && build_adjacency(g, err) != TW_OK) return err.code;
+    if (!std::isnan(weight_tau) && build_weights(g, weight_tau, err) != TW_OK) return err.code;
     a = WalkArgs{};
     a.e_src = g->e_src.as<int32_t>();
     a.e_dst = g->e_dst.as<int32_t>();
@@ -851,6 +864,7 @@ tw_status fill_args(tw_graph* g, int64_t num_walks, int32_t L, const tw_bias& sb
     a.rec = g->rec.as<NodeRec>();
     a.fence = g->fence.as<uint32_t>();
     a.adj = g->adj.as<int32_t>();
+    a.cw = g->cw.as<double>();
     a.V = g->V;
     a.num_walks = num_walks;
     a.L = L;
@@ -1001,7 +1015,8 @@ tw_status prepare_plain(tw_graph* g, const tw_walk_params* p, int32_t* nodes, in
         return err.code;
     }
     if (fill_args(g, p->num_walks, p->max_len, p->start_bias, p->start_mode, p->d_start_nodes,
-                  p->seed, p->walk_id_base, p->hop_bias.kind == TW_NODE2VEC, nodes, ts, len, a,
+                  p->seed, p->walk_id_base, p->hop_bias.kind == TW_NODE2VEC,
+                  p->hop_bias.kind == TW_WEIGHT ? p->hop_bias.tau : NAN, nodes, ts, len, a,
                   err) != TW_OK)
         return err.code;
     a.hop = make_hop_bias(p->hop_bias);
@@ -1032,9 +1047,20 @@ tw_status sample_walks_batch(tw_graph* g, const tw_batch_params* p, int32_t* nod
         return err.code;
     }
     bool n2v = false;
+    double wtau = NAN;  // the weight-based biases' time scale: one per launch
     for (int b = 0; b < p->num_biases; ++b) {
-        if (check_bias(p->hop_biases[b], true, err) != TW_OK) return err.code;
-        n2v |= p->hop_biases[b].kind == TW_NODE2VEC;
+        const tw_bias& hb = p->hop_biases[b];
+        if (check_bias(hb, true, err) != TW_OK) return err.code;
+        n2v |= hb.kind == TW_NODE2VEC;
+        if (hb.kind == TW_WEIGHT) {
+            const double sc = hb.tau > 0.0 ? hb.tau : 1.0;
+            if (!std::isnan(wtau) && wtau != sc) {
+                err = Error{TW_EINVAL,
+                            "sample_walks_batch: weight-based biases of one launch need one tau"};
+                return err.code;
+            }
+            wtau = sc;
+        }
     }
     if (check_bias(p->start_bias, false, err) != TW_OK) return err.code;
     if (check_start(p->start_mode, p->d_start_nodes, p->num_walks, err) != TW_OK) return err.code;
@@ -1050,7 +1076,7 @@ tw_status sample_walks_batch(tw_graph* g, const tw_batch_params* p, int32_t* nod
     }
     WalkArgs a;
     if (fill_args(g, p->num_walks, p->max_len, p->start_bias, p->start_mode, p->d_start_nodes,
-                  p->seed, p->walk_id_base, n2v, nodes, ts, len, a, err) != TW_OK)
+                  p->seed, p->walk_id_base, n2v, wtau, nodes, ts, len, a, err) != TW_OK)
         return err.code;
     a.hop = make_hop_bias(p->hop_biases[0]);
     QueueArgs q{};
@@ -1093,6 +1119,10 @@ tw_status serve_launch(tw_graph* g, const ServeReq* reqs, int n, void* d_table, 
     ServeReqDev* tab = static_cast<ServeReqDev*>(h_table);
     for (int r = 0; r < n; ++r) {
         const ServeReq& q = reqs[r];
+        if (q.hop.kind == TW_WEIGHT) {
+            err = Error{TW_EINVAL, "serve: the weight-based picker is not served"};
+            return err.code;
+        }
         n2v |= q.hop.kind == TW_NODE2VEC;
         ServeReqDev d{};
         d.walk0 = total;
@@ -1113,8 +1143,8 @@ tw_status serve_launch(tw_graph* g, const ServeReq* reqs, int n, void* d_table, 
     }
     WalkArgs a;
     tw_bias none{TW_UNIFORM, 0.0, 1.0, 1.0};
-    if (fill_args(g, total, 1, none, TW_START_EDGE, nullptr, 0, 0, n2v, nullptr, nullptr, nullptr,
-                  a, err) != TW_OK)
+    if (fill_args(g, total, 1, none, TW_START_EDGE, nullptr, 0, 0, n2v, NAN, nullptr, nullptr,
+                  nullptr, a, err) != TW_OK)
         return err.code;
     if (queue_shape(g, err) != TW_OK) return err.code;
     TW_HIP(ensure(g->wq, sizeof(unsigned long long) * QUEUE_SLICES));

@@ -241,6 +241,36 @@ __device__ __forceinline__ Pick pick_node(const GroupRec* __restrict__ ng,
     return Pick{n_dst[a.first + (uint32_t)scale_u64(d.x1, size)], a.ts};
 }
 
+// The weight-based pick (Sec. "Temporal Bias Sampling") among groups
+// [gc, ge) of a node whose live groups start at gb and whose edges end at
+// end: cw holds the node's cumulative group weights (weights exp((ts -
+// t_last) / sc) per edge). r = u times the candidates' total weight; the
+// group is the first whose cumulative weight reaches the candidates' prefix
+// plus r (binary search), and the edge inside it the one whose share of the
+// group's weight r falls in (every edge of a group weighs the same), so one
+// draw selects the edge, as the edge-by-edge inversion does.
+__device__ __forceinline__ Pick pick_weight(const GroupRec* __restrict__ ng,
+                                            const int32_t* __restrict__ n_dst,
+                                            const double* __restrict__ cw, uint32_t gb,
+                                            uint32_t gc, uint32_t ge, uint32_t end, double sc,
+                                            int64_t t_last, const Draw& d) {
+    const double prefix = gc > gb ? cw[gc - 1] : 0.0;
+    const double target = prefix + unit_open(d.x0) * (cw[ge - 1] - prefix);
+    uint32_t lo = gc, hi = ge - 1;
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (cw[mid] >= target) hi = mid; else lo = mid + 1;
+    }
+    const GroupRec a = ng[lo];
+    if (a.dst < 0) return Pick{a.dst & 0x7fffffff, a.ts};  // a one-edge group
+    const uint32_t size = (lo + 1 < ge ? ng[lo + 1].first : end) - a.first;
+    const double below = lo > gb ? cw[lo - 1] : 0.0;
+    const double w = exp((double)(a.ts - t_last) / sc);
+    double j = ceil((target - below) / w) - 1.0;
+    j = j < 0.0 ? 0.0 : (j > (double)(size - 1) ? (double)(size - 1) : j);
+    return Pick{n_dst[a.first + (uint32_t)j], a.ts};
+}
+
 // The edge-store position picked among the window's Gg timestamp groups.
 __device__ __forceinline__ uint32_t pick_global(const int64_t* __restrict__ gg_ts,
                                                 const uint32_t* __restrict__ gg_off, uint32_t Gg,

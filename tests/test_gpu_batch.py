@@ -119,6 +119,29 @@ def test_batch_explicit_bias_indices_and_errors():
     g.close()
 
 
+@pytest.mark.parametrize("dispatch", ["queue", "full_walk"])
+def test_batch_with_weight_bias(dispatch):
+    # the weight-based picker among the other biases of one launch; two
+    # weight-based biases of one launch must share their time scale
+    torch, tw = gpu_or_skip()
+    g, og, tau = _mixed_graph(torch, tw)
+    biases = synth.mixed_biases(tau)[:4] + [("weight", tau, 1.0, 1.0), ("weight", tau, 1.0, 1.0)]
+    W, L, seed, base = 9_000, 24, 11, 50
+    lims = synth.walk_lengths(6, W, 1, L)
+    bidx = ((base + np.arange(W)) % len(biases)).astype(np.uint8)
+    nodes, ts, lens, _ = g.sample_walks_batch(W, L, biases, max_lens=to_dev(torch, lims)[0],
+                                              seed=seed, walk_id_base=base, dispatch=dispatch)
+    g.sync()
+    ref = _oracle_batch(og, W, L, biases, lims, bidx, seed, base)
+    same, boundary = compare_walks((nodes.cpu().numpy(), ts.cpu().numpy(), lens.cpu().numpy()),
+                                   ref, exact=False)
+    assert boundary <= max(2, W // 2000), (same, boundary)
+    with pytest.raises(tw.TwError) as ei:
+        g.sample_walks_batch(W, L, [("weight", tau, 1.0, 1.0), ("weight", 2 * tau, 1.0, 1.0)])
+    assert ei.value.code == tw.TW_EINVAL
+    g.close()
+
+
 @pytest.mark.parametrize("ci", range(4))
 def test_queue_dispatch_equals_full_walk(ci):
     torch, tw = gpu_or_skip()

@@ -99,6 +99,9 @@ WALK_CASES = [
     ("node2vec", 5e4, 0.5, 2.0, "uniform", 0.0, "edge"),
     ("node2vec", 5e4, 2.0, 0.5, "exponential", 5e4, "node"),
     ("node2vec", 5e4, 1.0, 1.0, "uniform", 0.0, "edge"),
+    ("weight", 5e4, 1, 1, "uniform", 0.0, "edge"),
+    ("weight", 2e4, 1, 1, "exponential", 5e4, "node"),
+    ("weight", 0.0, 1, 1, "linear", 0.0, "edge"),
 ]
 
 
@@ -329,6 +332,36 @@ def test_sorted_batches_staged_in_place():
             assert np.array_equal(nodes.cpu().numpy(), r["nodes"])
             assert np.array_equal(ts.cpu().numpy(), r["ts"])
             assert np.array_equal(lens.cpu().numpy(), r["len"])
+    g.close()
+
+
+def test_weight_walks_follow_the_window():
+    # the weight-based picker's cumulative weights are rebuilt after every
+    # change of the window (ingest, eviction) and of the time scale
+    torch, tw = gpu_or_skip()
+    rng = np.random.default_rng(41)
+    V, window = 301, 6_000
+    g = tw.Graph(V, window=window)
+    og = oracle.OracleGraph(V, window=window)
+    t0 = 0
+    for b in range(12):
+        n = int(rng.integers(2000, 8000))
+        s = rng.integers(0, V, n).astype(np.int32)
+        d = rng.integers(0, V, n).astype(np.int32)
+        t = (t0 + rng.integers(-500, 1000, n)).astype(np.int64)
+        t0 += 1000
+        assert g.ingest_batch(*to_dev(torch, s, d, t)) == og.ingest_batch(s, d, t), b
+        if b % 4 == 2:
+            cut = t0 - 4000
+            assert g.evict_before(cut) == og.evict_before(cut)
+        for tau in ((300.0, 3000.0) if b % 3 == 0 else (300.0,)):
+            nodes, ts, lens = g.sample_walks(4000, 12, hop_bias="weight", hop_tau=tau, seed=b)
+            g.sync()
+            r = og.sample_walks(4000, 12, hop_bias="weight", hop_tau=tau, seed=b,
+                                with_margin=True)
+            same, boundary = compare_walks(
+                (nodes.cpu().numpy(), ts.cpu().numpy(), lens.cpu().numpy()), r, False)
+            assert boundary <= 2, (b, tau, same, boundary)
     g.close()
 
 

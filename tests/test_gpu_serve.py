@@ -105,6 +105,9 @@ def test_server_admission_by_memory_and_errors():
     with pytest.raises(tw.TwError) as ei:
         srv.submit(3 * W, L)  # can never fit
     assert ei.value.code == tw.TW_EINVAL
+    with pytest.raises(tw.TwError) as ei:
+        srv.submit(10, L, hop_bias="weight", hop_tau=100.0)  # not served
+    assert ei.value.code == tw.TW_EINVAL
     with pytest.raises(tw.TwError):
         srv.wait(a)  # released: unknown
     srv.release(b)
