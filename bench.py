@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--batches", type=int, default=0,
                     help="stream workload: number of 10M-edge batches (0 = the whole stream)")
     ap.add_argument("--dispatch", default="auto", choices=["auto", "full_walk", "coop", "queue"])
+    ap.add_argument("--hop-bias", default=None,
+                    choices=["uniform", "linear", "exponential", "node2vec", "weight"],
+                    help="single-batch workload: hop bias in place of the workload's "
+                         "(weight: the weight-based picker, its build timed with the walks)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
     return ap.parse_args()
@@ -568,6 +572,8 @@ def main():
     if args.workload == "stream":
         gather_rate, copy_bw = (0.0, 0.0) if args.no_probe else probe_rates(torch, dev)
         return run_stream(args, torch, tw, w, dev, gather_rate, copy_bw)
+    if args.hop_bias:
+        w = dict(w, hop_bias=args.hop_bias)
     spec = w["stream"]
     t0 = time.perf_counter()
     src, dst, ts = spec.all()
@@ -589,7 +595,8 @@ def main():
 
     g = tw.Graph(spec.num_nodes, directed=spec.directed, window=w["window"])
     walk_kw = dict(hop_bias=w["hop_bias"], hop_tau=tau, start_bias=w["start_bias"],
-                   start_tau=tau, seed=42, dispatch=args.dispatch, out=out)
+                   start_tau=tau, seed=42, dispatch=args.dispatch, out=out,
+                   **({"p": 0.5, "q": 2.0} if w["hop_bias"] == "node2vec" else {}))
 
     def step(events=None):
         g.evict_before(INT64_MAX)
@@ -645,6 +652,21 @@ def main():
         ms = float(np.median(times))
         compare[disp] = {"walk_ms": ms, "walk_hops_per_s": hops / (ms * 1e-3)}
 
+    weight_build_ms = None
+    if w["hop_bias"] == "weight":
+        # the build alone: the first walk call after an ingest builds the
+        # cumulative weights, the second reuses them
+        g.evict_before(INT64_MAX)
+        g.ingest_batch(d_src, d_dst, d_ts)
+        pair = []
+        for rep in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            g.sample_walks(W, L, **dict(walk_kw, dispatch="full_walk"))
+            e1.record()
+            torch.cuda.synchronize()
+            pair.append(e0.elapsed_time(e1))
+        weight_build_ms = pair[0] - pair[1]
     wb = walk_bytes(W, hops, L, w["start_bias"], w["hop_bias"])
     st = g.index_stats()
     ib = ingest_bytes(spec.num_edges, m_active, 0, st["jobs"])
@@ -687,8 +709,12 @@ def main():
                             "hops_per_s_roof": gather_roof_hops,
                             "frac": (walk_hops_s / gather_roof_hops) if gather_roof_hops else None},
     }
+    if weight_build_ms is not None:
+        res["weight_build_ms"] = weight_build_ms
+        res["gather_roofline"]["note"] = ("weight-based hops: the binary search's reads come on "
+                                          "top of the 4 sectors counted per hop")
     g.close()
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and w["hop_bias"] != "weight":
         print("# oracle baseline ...", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(w, tau, hops)
     print(json.dumps(res), flush=True)

@@ -123,39 +123,65 @@ __device__ Seg block_seg_excl(Seg s, Seg* all) {
     return seg_add(before, lane_ex);
 }
 
-// Pass 1 (EMIT = false): every tile's combined pair into tiles[t].
-// Pass 3 (EMIT = true): the scan, with carry[t] the combination of the
-// tiles before t, into cw at the items' group slots.
-template <bool EMIT>
+// Pass 1: every tile's combined pair. Only the items from the tile's last
+// segment head on contribute to its sum; that head is the first item of the
+// node owning the tile's last item, when it lies inside the tile.
+__global__ void __launch_bounds__(T)
+k_w_tiles(const uint32_t* __restrict__ off, int64_t V, const uint32_t* __restrict__ Gp,
+          const NodeRec* __restrict__ rec, const GroupRec* __restrict__ ng, double inv_sc,
+          uint32_t* __restrict__ t_head, double* __restrict__ t_sum) {
+    __shared__ double wsum[T / 64];
+    const uint32_t G = *Gp;
+    const uint32_t tile = blockIdx.x;
+    const uint32_t base = tile * (uint32_t)W_TILE;
+    if (base >= G) return;
+    const uint32_t last = std::min<uint32_t>(base + W_TILE, G) - 1;
+    const uint32_t v = node_of(off, 0, (uint32_t)V - 1, last);  // uniform over the block
+    const uint32_t from = std::max(base, off[v]);
+    const NodeRec r = rec[v];
+    double s = 0.0;
+    for (uint32_t f = from + threadIdx.x; f <= last; f += T) {
+        const uint32_t g = r.gb + (f - off[v]);
+        const GroupRec a = ng[g];
+        const uint32_t next = g + 1 < r.ge ? ng[g + 1].first : r.ee;
+        s += (double)(next - a.first) * exp((double)(a.ts - r.t_last) * inv_sc);
+    }
+    // the block's total (the order of this sum is the build's own)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+#pragma unroll
+        for (int k = 0; k < T / 64; ++k) tot += wsum[k];
+        t_head[tile] = off[v] >= base;
+        t_sum[tile] = tot;
+    }
+}
+
+// Pass 3: the scan, with carry[t] the combination of the tiles before t,
+// into cw at the items' group slots.
 __global__ void __launch_bounds__(T)
 k_w_scan(const uint32_t* __restrict__ off, int64_t V, const uint32_t* __restrict__ Gp,
          const NodeRec* __restrict__ rec, const GroupRec* __restrict__ ng, double inv_sc,
-         uint32_t* __restrict__ t_head, double* __restrict__ t_sum,
          const uint32_t* __restrict__ c_head, const double* __restrict__ c_sum,
          double* __restrict__ cw) {
     __shared__ double w[W_TILE];
     __shared__ uint8_t head[W_TILE];
-    __shared__ uint32_t slot[EMIT ? W_TILE : 1];
+    __shared__ uint32_t slot[W_TILE];
     __shared__ uint32_t vr[2];
     const uint32_t G = *Gp;
     const uint32_t tile = blockIdx.x;
     const uint32_t base = tile * (uint32_t)W_TILE;
     if (base >= G) return;  // the grid is sized for an upper bound of G
-    tile_weights(off, V, G, rec, ng, inv_sc, base, w, head, EMIT ? slot : nullptr, vr);
+    tile_weights(off, V, G, rec, ng, inv_sc, base, w, head, slot, vr);
     // this thread's items [i0, i0 + W_ITEMS) in order
     const int i0 = threadIdx.x * W_ITEMS;
     Seg mine{0, 0.0};
     for (int k = 0; k < W_ITEMS; ++k) mine = seg_add(mine, Seg{head[i0 + k], w[i0 + k]});
     Seg all;
-    Seg pre = block_seg_excl(mine, &all);
-    if (!EMIT) {
-        if (threadIdx.x == 0) {
-            t_head[tile] = all.head;
-            t_sum[tile] = all.sum;
-        }
-        return;
-    }
-    pre = seg_add(Seg{c_head[tile], c_sum[tile]}, pre);
+    Seg pre = seg_add(Seg{c_head[tile], c_sum[tile]}, block_seg_excl(mine, &all));
     for (int k = 0; k < W_ITEMS; ++k) {
         const int i = i0 + k;
         pre = seg_add(pre, Seg{head[i], w[i]});
@@ -211,13 +237,12 @@ tw_status build_weights(tw_graph* g, double tau, Error& err) {
     double* t_sum = reinterpret_cast<double*>(c_head + nt);  // 8 nt bytes in: aligned
     double* c_sum = t_sum + nt;
     const double inv_sc = 1.0 / sc;
-    hipLaunchKernelGGL(k_w_scan<false>, dim3((unsigned)nt), dim3(T), 0, s, off, V, Gd,
-                       g->rec.as<NodeRec>(), g->ng.as<GroupRec>(), inv_sc, t_head, t_sum,
-                       nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_w_tiles, dim3((unsigned)nt), dim3(T), 0, s, off, V, Gd,
+                       g->rec.as<NodeRec>(), g->ng.as<GroupRec>(), inv_sc, t_head, t_sum);
     hipLaunchKernelGGL(k_w_carry, dim3(1), dim3(T), 0, s, Gd, t_head, t_sum, c_head, c_sum);
-    hipLaunchKernelGGL(k_w_scan<true>, dim3((unsigned)nt), dim3(T), 0, s, off, V, Gd,
-                       g->rec.as<NodeRec>(), g->ng.as<GroupRec>(), inv_sc, nullptr, nullptr,
-                       c_head, c_sum, g->cw.as<double>());
+    hipLaunchKernelGGL(k_w_scan, dim3((unsigned)nt), dim3(T), 0, s, off, V, Gd,
+                       g->rec.as<NodeRec>(), g->ng.as<GroupRec>(), inv_sc, c_head, c_sum,
+                       g->cw.as<double>());
     TW_HIP(hipGetLastError());
     g->w_ready = true;
     g->w_scale = sc;
