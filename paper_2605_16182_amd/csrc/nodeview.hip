@@ -162,6 +162,23 @@ __global__ void k_flag_jobs(const uint32_t* __restrict__ flags, const uint32_t* 
     c_be[j] = 0;
 }
 
+// One eviction-only job per flagged position (flags from k_evict_marks),
+// after the batch's jobs (their count in *runs): no batch run.
+struct EvictJobOp {
+    const uint32_t* flags;
+    const int32_t* nodes;
+    const uint32_t* runs;
+    uint32_t *c_node, *c_bf, *c_be;
+    __device__ bool flag(int64_t i) const { return flags[i] != 0; }
+    __device__ void emit(int64_t i, uint32_t k) const {
+        const uint32_t j = *runs + k;
+        c_node[j] = (uint32_t)nodes[i];
+        c_bf[j] = 0;
+        c_be[j] = 0;
+    }
+    __device__ void end(int64_t, uint32_t) const {}
+};
+
 // nodes with live edges that no job covers yet
 __global__ void k_active_flags(const NodeRec* __restrict__ rec, int64_t V,
                                const uint32_t* __restrict__ touched, uint32_t epoch,
@@ -829,10 +846,13 @@ tw_status nv_collect(tw_graph* g, const int32_t* q_src, const int32_t* q_dst, co
         const int32_t* esrc = g->e_src.as<int32_t>() + ev_from;
         hipLaunchKernelGGL(k_evict_marks, grid_for(ev_n), dim3(T), 0, s, esrc, ev_n, g->epoch,
                            g->touched.as<uint32_t>(), flags);
-        TW_HIP(scan_exclusive_u32(flags, pos, ev_n, sl_ev, g->ws, s));
-        hipLaunchKernelGGL(k_flag_jobs, grid_for(ev_n), dim3(T), 0, s, flags, pos, ev_n, esrc,
-                           sl_runs, nullptr, g->c_node.as<uint32_t>(), g->c_bf.as<uint32_t>(),
-                           g->c_be.as<uint32_t>());
+        const EvictJobOp op{flags,
+                            esrc,
+                            sl_runs,
+                            g->c_node.as<uint32_t>(),
+                            g->c_bf.as<uint32_t>(),
+                            g->c_be.as<uint32_t>()};
+        TW_HIP(compact(op, ev_n, sl_ev, g->ws.tiles, g->ws, s));
     } else {
         TW_HIP(scan_exclusive_u32(nullptr, nullptr, 0, sl_ev, g->ws, s));
     }
@@ -865,14 +885,17 @@ tw_status plan_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool re
                        g->j_cnt.as<uint32_t>(), g->j_re.as<uint32_t>(), g->j_rg.as<uint32_t>(),
                        g->j_rf.as<uint32_t>());
     TW_HIP(hipGetLastError());
-    // requests are scanned in place: j_re / j_rg / j_rf become offsets
-    TW_HIP(scan_jobs(g->j_cnt.as<uint32_t>(), g->j_off.as<uint32_t>(), nj, g->ws, s));
+    // output counts into offsets (total also at j_off[nj]); requests scanned
+    // in place: j_re / j_rg / j_rf become offsets
     uint32_t* sl = slot(g, SLOT_U32_REQ_E);
-    TW_HIP(scan_exclusive_u32(g->j_re.as<uint32_t>(), g->j_re.as<uint32_t>(), nj, sl, g->ws, s));
-    TW_HIP(scan_exclusive_u32(g->j_rg.as<uint32_t>(), g->j_rg.as<uint32_t>(), nj, sl + 1, g->ws, s));
-    TW_HIP(scan_exclusive_u32(g->j_rf.as<uint32_t>(), g->j_rf.as<uint32_t>(), nj, sl + 2, g->ws, s));
-    hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, s, g->j_off.as<uint32_t>() + nj,
-                       slot(g, SLOT_U32_OUT));
+    uint32_t* j_off = g->j_off.as<uint32_t>();
+    const uint32_t* in4[4] = {g->j_cnt.as<uint32_t>(), g->j_re.as<uint32_t>(),
+                              g->j_rg.as<uint32_t>(), g->j_rf.as<uint32_t>()};
+    uint32_t* const out4[4] = {j_off, g->j_re.as<uint32_t>(), g->j_rg.as<uint32_t>(),
+                               g->j_rf.as<uint32_t>()};
+    uint32_t* const tot4[4] = {slot(g, SLOT_U32_OUT), sl, sl + 1, sl + 2};
+    TW_HIP(scan_exclusive_u32x4(in4, out4, tot4, nj, g->ws, s));
+    hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, s, slot(g, SLOT_U32_OUT), j_off + nj);
     TW_HIP(hipGetLastError());
     if (pull_scalars(g, false, err) != TW_OK) return err.code;
     tot[0] = host_u32(g, SLOT_U32_OUT);

@@ -116,6 +116,77 @@ __global__ void k_scan_down(const In* in, V* out, int64_t n, const V* __restrict
 template <typename V>
 __global__ void k_set(V* p, V v) { *p = v; }
 
+// Four u32 scans at once (array blockIdx.y of the launch): the same three
+// steps as above, one launch each instead of one per array.
+struct Scan4 {
+    const uint32_t* in[4];
+    uint32_t* out[4];
+    uint32_t* total[4];
+};
+
+__global__ void k_scan4_reduce(const Scan4 a, int64_t n, uint32_t* __restrict__ part,
+                               int64_t nb) {
+    const int y = blockIdx.y;
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    uint32_t s = 0;
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int64_t i = base + (int64_t)j * SCAN_THREADS + threadIdx.x;
+        if (i < n) s += a.in[y][i];
+    }
+    uint32_t total;
+    block_excl_scan(s, &total);
+    if (threadIdx.x == 0) part[y * nb + blockIdx.x] = total;
+}
+
+__global__ void k_scan4_partials(const Scan4 a, uint32_t* part, int64_t nb) {
+    const int y = blockIdx.x;
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nb; base += SCAN_THREADS) {
+        int64_t i = base + threadIdx.x;
+        uint32_t v = i < nb ? part[y * nb + i] : 0;
+        uint32_t tot;
+        uint32_t ex = block_excl_scan(v, &tot);
+        uint32_t c = carry;
+        if (i < nb) part[y * nb + i] = c + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && a.total[y]) *a.total[y] = carry;
+}
+
+__global__ void k_scan4_down(const Scan4 a, int64_t n, const uint32_t* __restrict__ part,
+                             int64_t nb) {
+    __shared__ uint32_t tile[SCAN_TILE];
+    const int y = blockIdx.y;
+    const uint32_t* in = a.in[y];
+    uint32_t* out = a.out[y];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int k = j * SCAN_THREADS + threadIdx.x;
+        int64_t i = base + k;
+        tile[k] = i < n ? in[i] : 0;
+    }
+    __syncthreads();
+    uint32_t loc[SCAN_ITEMS];
+    uint32_t s = 0;
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        loc[j] = s;
+        s += tile[threadIdx.x * SCAN_ITEMS + j];
+    }
+    uint32_t tot;
+    uint32_t pre = block_excl_scan(s, &tot) + part[y * nb + blockIdx.x];
+    for (int j = 0; j < SCAN_ITEMS; ++j) tile[threadIdx.x * SCAN_ITEMS + j] = pre + loc[j];
+    __syncthreads();
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        int k = j * SCAN_THREADS + threadIdx.x;
+        int64_t i = base + k;
+        if (i < n) out[i] = tile[k];
+    }
+}
+
 
 // group starts of a timestamp sequence (group_starts)
 struct GroupStartOp {
@@ -420,6 +491,32 @@ hipError_t scan_exclusive(const In* in, V* out, int64_t n, V* total, DevBuf& par
 hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
                               Workspace& ws, hipStream_t s) {
     return scan_exclusive<uint32_t, uint32_t>(in, out, n, total, ws.scan_part, s);
+}
+
+hipError_t scan_exclusive_u32x4(const uint32_t* const in[4], uint32_t* const out[4],
+                                uint32_t* const total[4], int64_t n, Workspace& ws,
+                                hipStream_t s) {
+    Scan4 a;
+    for (int y = 0; y < 4; ++y) {
+        a.in[y] = in[y];
+        a.out[y] = out[y];
+        a.total[y] = total[y];
+    }
+    if (n <= 0) {
+        for (int y = 0; y < 4; ++y)
+            if (total[y]) hipLaunchKernelGGL(k_set<uint32_t>, dim3(1), dim3(1), 0, s, total[y], 0u);
+        return hipGetLastError();
+    }
+    const int64_t nb = ceil_div(n, SCAN_TILE);
+    hipError_t e = ensure(ws.scan_part, sizeof(uint32_t) * 4 * (nb + 1));
+    if (e != hipSuccess) return e;
+    uint32_t* part = ws.scan_part.as<uint32_t>();
+    hipLaunchKernelGGL(k_scan4_reduce, dim3((unsigned)nb, 4), dim3(SCAN_THREADS), 0, s, a, n, part,
+                       nb);
+    hipLaunchKernelGGL(k_scan4_partials, dim3(4), dim3(SCAN_THREADS), 0, s, a, part, nb);
+    hipLaunchKernelGGL(k_scan4_down, dim3((unsigned)nb, 4), dim3(SCAN_THREADS), 0, s, a, n, part,
+                       nb);
+    return hipGetLastError();
 }
 
 hipError_t scan_exclusive_i32_to_u64(const int32_t* in, uint64_t* out, int64_t n, uint64_t* total,

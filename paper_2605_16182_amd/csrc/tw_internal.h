@@ -183,6 +183,12 @@ struct Workspace {
 hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
                               Workspace& ws, hipStream_t s);
 
+// Four exclusive u32 scans of n elements at once (in[k] and out[k] may
+// alias); total[k] (device, nullable) receives the sum of array k.
+hipError_t scan_exclusive_u32x4(const uint32_t* const in[4], uint32_t* const out[4],
+                                uint32_t* const total[4], int64_t n, Workspace& ws,
+                                hipStream_t s);
+
 // out[i] = sum_{j<i} in[j] in 64 bits (in >= 0); total (nullable) = the sum.
 hipError_t scan_exclusive_i32_to_u64(const int32_t* in, uint64_t* out, int64_t n, uint64_t* total,
                                      Workspace& ws, hipStream_t s);
