@@ -70,7 +70,7 @@ def _load():
     lib.oracle_views.argtypes = [p] * 12
     lib.oracle_views.restype = None
     lib.oracle_sample_walks.argtypes = [p, i32, i32, dbl, dbl, dbl, i32, dbl, i32, p, u64, u64,
-                                        p, i64, p, p, p, p, p, i32]
+                                        p, i64, p, p, p, p, p, i32, i32]
     lib.oracle_sample_walks.restype = ctypes.c_int
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = ctypes.c_int
@@ -135,20 +135,30 @@ class OracleError(RuntimeError):
 
 
 class OracleGraph:
-    """The oracle's graph: ingest / evict / views / walks, all on the CPU."""
+    """The oracle's graph: ingest / evict / views / walks, all on the CPU.
 
-    def __init__(self, num_nodes: int, directed: bool = True, window: int = 0):
+    backward: also keep the in-view for backward walks. A directed graph
+    keeps it as a second graph fed every batch with source and destination
+    swapped (and the same evictions); an undirected graph is its own."""
+
+    def __init__(self, num_nodes: int, directed: bool = True, window: int = 0,
+                 backward: bool = False):
         self._lib = _load()
         self._h = self._lib.oracle_create(num_nodes, 1 if directed else 0, int(window))
         if not self._h:
             raise OracleError(ST_EINVAL, "create")
+        self._rev = None
+        if backward and directed:
+            self._rev = self._lib.oracle_create(num_nodes, 1, int(window))
+        self._backward = backward
         self.num_nodes = num_nodes
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h:
-            self._lib.oracle_destroy(h)
-            self._h = None
+        for name in ("_h", "_rev"):
+            h = getattr(self, name, None)
+            if h:
+                self._lib.oracle_destroy(h)
+                setattr(self, name, None)
 
     def ingest_batch(self, src, dst, ts) -> dict:
         src = np.ascontiguousarray(src, np.int32)
@@ -159,10 +169,18 @@ class OracleGraph:
         rc = self._lib.oracle_ingest(self._h, _ptr(src), _ptr(dst), _ptr(ts), len(src), _ptr(info))
         if rc != ST_OK:
             raise OracleError(rc, "ingest_batch")
+        if self._rev:
+            rinfo = np.zeros(6, np.int64)
+            rc = self._lib.oracle_ingest(self._rev, _ptr(dst), _ptr(src), _ptr(ts), len(src),
+                                         _ptr(rinfo))
+            if rc != ST_OK:
+                raise OracleError(rc, "ingest_batch (in-view)")
         keys = ("accepted", "dropped_late", "evicted", "active_edges", "t_min", "t_max")
         return dict(zip(keys, (int(v) for v in info)))
 
     def evict_before(self, cutoff: int) -> int:
+        if self._rev:
+            self._lib.oracle_evict_before(self._rev, int(cutoff))
         return int(self._lib.oracle_evict_before(self._h, int(cutoff)))
 
     def sizes(self) -> dict:
@@ -188,8 +206,13 @@ class OracleGraph:
                      start_bias: str = "uniform", start_tau: float = 0.0,
                      start_mode: str = "edge", start_nodes=None, seed: int = 42,
                      walk_id_base: int = 0, walk_idx=None, with_margin: bool = False,
-                     threads: int = 0, check: bool = True) -> dict:
-        """Walks for ids walk_idx (default: all num_walks)."""
+                     threads: int = 0, check: bool = True, direction: str = "forward") -> dict:
+        """Walks for ids walk_idx (default: all num_walks); direction
+        "backward" needs a graph created with backward=True."""
+        backward = direction == "backward"
+        if backward and not self._backward:
+            raise OracleError(ST_EINVAL, "sample_walks: created without backward")
+        h = self._rev if (backward and self._rev) else self._h
         idx = None if walk_idx is None else np.ascontiguousarray(walk_idx, np.int64)
         n_out = num_walks if idx is None else len(idx)
         sn = None if start_nodes is None else np.ascontiguousarray(start_nodes, np.int32)
@@ -199,10 +222,10 @@ class OracleGraph:
         margin = np.empty((n_out, max(max_len, 1)), np.float64) if with_margin else None
         stats = np.zeros(2, np.int64)
         rc = self._lib.oracle_sample_walks(
-            self._h, int(max_len), KINDS[hop_bias], float(hop_tau), float(p), float(q),
+            h, int(max_len), KINDS[hop_bias], float(hop_tau), float(p), float(q),
             KINDS[start_bias], float(start_tau), START_MODES[start_mode], _ptr(sn),
             int(seed), int(walk_id_base), _ptr(idx), int(n_out), _ptr(nodes), _ptr(ts),
-            _ptr(lens), _ptr(margin), _ptr(stats), int(threads))
+            _ptr(lens), _ptr(margin), _ptr(stats), int(threads), 1 if backward else 0)
         if check and rc != ST_OK:
             raise OracleError(rc, "sample_walks")
         return dict(nodes=nodes, ts=ts, len=lens, margin=margin, status=rc,

@@ -27,6 +27,9 @@
  *     cumulative array W over the candidates in order, and a draw u picks
  *     the smallest k with W[k] >= u W[n-1] (Sec. "Temporal Bias Sampling");
  *   - ties on timestamps broken uniformly at random (Sec. "Design
+ *     Constraints");
+ *   - backward walks over Gamma-_t(v) = in-edges of v with t' < t, the
+ *     backward case the paper defines by analogy (Sec. "Design
  *     Constraints").
  *
  * Readings where the paper is silent (each listed in the design notes):
@@ -45,6 +48,14 @@
  *     the common factor exp((t_last - t_min) / tau) cancels from u W[n-1]
  *     and W[k], the law is unchanged and no weight overflows; u is the open
  *     uniform U_open(x0); W is summed edge by edge in candidate order;
+ *   - backward walks run on the in-view (the node view of the graph fed the
+ *     batches with source and destination swapped; an undirected graph is
+ *     its own in-view) and are forward walks over the candidates listed in
+ *     reverse canonical order: every pick index i over n candidates (edges,
+ *     groups, the edge inside a group, the start edge or group of the whole
+ *     window) becomes n - 1 - i. Without equal timestamps this is a forward
+ *     walk on the graph with reversed edges and negated timestamps. The
+ *     weight-based picker is forward only;
  *   - node2vec: beta = 1/p when the candidate is the previous node, 1 when
  *     the active window holds an edge prev -> candidate, else 1/q;
  *   - max_len counts nodes; the first pick is RNG hop 0;
@@ -312,6 +323,7 @@ struct Params {
     Bias hop, start;
     int32_t start_mode;
     uint64_t seed, walk_id_base;
+    bool backward;
 };
 
 struct WalkStats {
@@ -321,14 +333,17 @@ struct WalkStats {
 /*
  * One biased pick over groups [gc, ge) of (gts, goff): returns the edge
  * index. Linear and exponential choose a group, then a uniform edge in it.
+ * rev: the candidates are listed in reverse order (a backward walk), so each
+ * index i among n becomes n - 1 - i.
  */
 int64_t pick_in_groups(const std::vector<int64_t>& gts, const std::vector<int64_t>& goff,
                        int64_t gc, int64_t ge, int32_t kind, double tau, const Draw& d,
-                       double* margin) {
+                       double* margin, bool rev = false) {
     if (margin) *margin = INFINITY;
     if (kind == K_UNIFORM) {
         int64_t c = goff[gc], b = goff[ge];
-        return c + pick_uniform(b - c, d.x[0]);
+        int64_t i = pick_uniform(b - c, d.x[0]);
+        return rev ? b - 1 - i : c + i;
     }
     if (kind == K_WEIGHT) {
         // the candidates edge by edge, each with its group's timestamp
@@ -345,9 +360,10 @@ int64_t pick_in_groups(const std::vector<int64_t>& gts, const std::vector<int64_
         double lam = exp_lambda(gts[gc], gts[ge - 1], n, tau);
         i = pick_exponential(n, lam, d.x[0], margin);
     }
-    int64_t k = gc + i;
+    int64_t k = rev ? ge - 1 - i : gc + i;
     int64_t size = goff[k + 1] - goff[k];
-    return goff[k] + pick_uniform(size, d.x[1]);
+    int64_t j = pick_uniform(size, d.x[1]);
+    return rev ? goff[k + 1] - 1 - j : goff[k] + j;
 }
 
 /* returns 0, or ST_ERANGE for a start node outside [0, V) */
@@ -369,7 +385,7 @@ int walk_one(const Graph& g, const Params& P, uint64_t walk_id, int32_t start_no
     if (P.start_mode == START_EDGE) {
         if (m == 0) return ST_OK;
         int64_t e = pick_in_groups(g.g_ts, g.g_off, 0, (int64_t)g.g_ts.size(), P.start.kind,
-                                   P.start.tau, d0, &mg);
+                                   P.start.tau, d0, &mg, P.backward);
         const Edge& se = g.active[e];
         nodes[0] = se.src;
         if (margin) margin[0] = mg;
@@ -389,7 +405,8 @@ int walk_one(const Graph& g, const Params& P, uint64_t walk_id, int32_t start_no
         if (L == 1) { *len_out = len; return ST_OK; }
         int64_t gb = g.n_gbeg[start_node], ge = g.n_gbeg[start_node + 1];
         if (gb == ge) { *len_out = len; return ST_OK; }
-        int64_t e = pick_in_groups(g.n_gts, g.n_goff, gb, ge, P.start.kind, P.start.tau, d0, &mg);
+        int64_t e = pick_in_groups(g.n_gts, g.n_goff, gb, ge, P.start.kind, P.start.tau, d0, &mg,
+                                   P.backward);
         nodes[1] = g.nview[e].dst;
         ts[1] = g.nview[e].ts;
         if (margin) margin[1] = mg;
@@ -401,10 +418,19 @@ int walk_one(const Graph& g, const Params& P, uint64_t walk_id, int32_t start_no
 
     for (uint64_t hop = 1; len < L; ++hop) {
         int64_t gb = g.n_gbeg[cur], ge = g.n_gbeg[cur + 1];
-        /* Gamma_t(cur): the first group with timestamp strictly after tcur */
-        int64_t gc = std::upper_bound(g.n_gts.begin() + gb, g.n_gts.begin() + ge, tcur) -
-                     g.n_gts.begin();
-        if (gc == ge) break;
+        int64_t gc;
+        if (!P.backward) {
+            /* Gamma_t(cur): the first group with timestamp strictly after tcur */
+            gc = std::upper_bound(g.n_gts.begin() + gb, g.n_gts.begin() + ge, tcur) -
+                 g.n_gts.begin();
+            if (gc == ge) break;
+        } else {
+            /* Gamma-_t(cur): the groups [gb, ge) before the first one at or after tcur */
+            ge = std::lower_bound(g.n_gts.begin() + gb, g.n_gts.begin() + ge, tcur) -
+                 g.n_gts.begin();
+            gc = gb;
+            if (gc == ge) break;
+        }
         int64_t e;
         if (P.hop.kind == K_NODE2VEC) {
             double beta_max = std::max(std::max(1.0 / P.hop.p, 1.0), 1.0 / P.hop.q);
@@ -415,7 +441,7 @@ int walk_one(const Graph& g, const Params& P, uint64_t walk_id, int32_t start_no
                 Draw d = draw(P.seed, walk_id, hop, trial);
                 double tm;
                 int64_t cand = pick_in_groups(g.n_gts, g.n_goff, gc, ge, K_EXPONENTIAL,
-                                              P.hop.tau, d, &tm);
+                                              P.hop.tau, d, &tm, P.backward);
                 worst = std::min(worst, tm);
                 int32_t w = g.nview[cand].dst;
                 double beta;
@@ -436,7 +462,8 @@ int walk_one(const Graph& g, const Params& P, uint64_t walk_id, int32_t start_no
             }
         } else {
             Draw d = draw(P.seed, walk_id, hop, 0);
-            e = pick_in_groups(g.n_gts, g.n_goff, gc, ge, P.hop.kind, P.hop.tau, d, &mg);
+            e = pick_in_groups(g.n_gts, g.n_goff, gc, ge, P.hop.kind, P.hop.tau, d, &mg,
+                               P.backward);
         }
         nodes[len] = g.nview[e].dst;
         ts[len] = g.nview[e].ts;
@@ -577,17 +604,20 @@ void oracle_views(void* h, int32_t* src, int32_t* dst, int64_t* ts, int64_t* g_t
  * margin (nullable, n_out * max_len): for each output node, the distance of
  * the pick's uniform draw from the nearest CDF boundary of the exponential
  * or weight-based law (infinity for exact integer picks). stats[2] = node2vec trial-cap hits,
- * node2vec trials. Returns ST_OK, ST_EINVAL or ST_ERANGE (some start node out
- * of range; those walks have length 0).
+ * node2vec trials. backward: a backward walk on this graph, which must be
+ * the in-view (see the header). Returns ST_OK, ST_EINVAL or ST_ERANGE (some
+ * start node out of range; those walks have length 0).
  */
 int oracle_sample_walks(void* h, int32_t max_len, int32_t hop_kind, double hop_tau, double p,
                         double q, int32_t start_kind, double start_tau, int32_t start_mode,
                         const int32_t* start_nodes, uint64_t seed, uint64_t walk_id_base,
                         const int64_t* walk_idx, int64_t n_out, int32_t* nodes, int64_t* ts,
-                        int32_t* len, double* margin, int64_t* stats, int32_t nthreads) {
+                        int32_t* len, double* margin, int64_t* stats, int32_t nthreads,
+                        int32_t backward) {
     Graph& g = *static_cast<Graph*>(h);
     if (max_len < 1 || n_out < 0) return ST_EINVAL;
     if (hop_kind < K_UNIFORM || hop_kind > K_WEIGHT) return ST_EINVAL;
+    if (backward && hop_kind == K_WEIGHT) return ST_EINVAL;
     if (start_kind < K_UNIFORM || start_kind > K_EXPONENTIAL) return ST_EINVAL;
     if (hop_kind == K_NODE2VEC && !(p > 0.0 && q > 0.0)) return ST_EINVAL;
     if (start_mode == START_NODE && !start_nodes) return ST_EINVAL;
@@ -602,6 +632,7 @@ int oracle_sample_walks(void* h, int32_t max_len, int32_t hop_kind, double hop_t
     P.start_mode = start_mode;
     P.seed = seed;
     P.walk_id_base = walk_id_base;
+    P.backward = backward != 0;
 
     int64_t cap_hits = 0, trials = 0;
     int status = ST_OK;

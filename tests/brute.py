@@ -170,6 +170,11 @@ class BruteGraph:
         """Out-edges of v strictly after t, in node-view order."""
         return [e for e in self.node_view() if e[2] == v and e[0] > t]
 
+    def gamma_before(self, v: int, t: int) -> List[Tuple[int, int, int, int]]:
+        """Candidates of a backward hop: v's edges in this graph (the in-view
+        of a backward walk) with timestamp strictly before t, canonical order."""
+        return [e for e in self.node_view() if e[2] == v and e[0] < t]
+
     def has_edge(self, u: int, w: int) -> bool:
         return any(e[2] == u and e[3] == w for e in self.edges)
 
@@ -185,8 +190,11 @@ def _groups(cands):
     return out
 
 
-def pick(cands, kind: str, tau: float, d: List[int]):
-    """Returns (edge, margin). cands are in view order (timestamp ascending)."""
+def pick(cands, kind: str, tau: float, d: List[int], backward: bool = False):
+    """Returns (edge, margin). cands are in view order (timestamp ascending);
+    a backward walk lists them in reverse and picks over that listing."""
+    if backward:
+        cands = list(reversed(cands))
     if kind == "uniform":
         return cands[scaled(d[0], len(cands))], float("inf")
     if kind == "weight":
@@ -198,7 +206,10 @@ def pick(cands, kind: str, tau: float, d: List[int]):
     if kind == "linear":
         i = linear_pick(n, d[0])
     else:
-        lam = exp_lambda(groups[0][0][0], groups[-1][0][0], n, tau)
+        # the rate from the candidates' time span (either listing order)
+        span_lo = min(grp[0][0] for grp in groups)
+        span_hi = max(grp[0][0] for grp in groups)
+        lam = exp_lambda(span_lo, span_hi, n, tau)
         if n == 1:
             i = 0
         else:
@@ -209,14 +220,16 @@ def pick(cands, kind: str, tau: float, d: List[int]):
 
 def walk(g: BruteGraph, walk_id: int, max_len: int, seed: int, hop_kind="uniform",
          hop_tau=0.0, p=1.0, q=1.0, start_kind="uniform", start_tau=0.0, start_mode="edge",
-         start_node: int = 0):
-    """One walk: (nodes, ts, min margin per position)."""
+         start_node: int = 0, backward: bool = False):
+    """One walk: (nodes, ts, min margin per position). backward: g is the
+    in-view and each hop goes to an edge strictly before the current time."""
     nodes, ts, margins = [], [], []
     d0 = philox_numpy(seed, walk_id, 0, 0)
+    bw = backward
     if start_mode == "edge":
         if not g.edges:
             return nodes, ts, margins
-        e, mg = pick(g.edges, start_kind, start_tau, d0)
+        e, mg = pick(g.edges, start_kind, start_tau, d0, bw)
         nodes.append(e[2]); ts.append(TS_NONE); margins.append(mg)
         if max_len == 1:
             return nodes, ts, margins
@@ -229,12 +242,12 @@ def walk(g: BruteGraph, walk_id: int, max_len: int, seed: int, hop_kind="uniform
         run = [e for e in g.node_view() if e[2] == start_node]
         if not run:
             return nodes, ts, margins
-        e, mg = pick(run, start_kind, start_tau, d0)
+        e, mg = pick(run, start_kind, start_tau, d0, bw)
         nodes.append(e[3]); ts.append(e[0]); margins.append(mg)
         prev, cur, t = start_node, e[3], e[0]
     hop = 1
     while len(nodes) < max_len:
-        cands = g.gamma(cur, t)
+        cands = g.gamma_before(cur, t) if bw else g.gamma(cur, t)
         if not cands:
             break
         if hop_kind == "node2vec":
@@ -242,7 +255,7 @@ def walk(g: BruteGraph, walk_id: int, max_len: int, seed: int, hop_kind="uniform
             chosen, worst = None, float("inf")
             for trial in range(4096):
                 d = philox_numpy(seed, walk_id, hop, trial)
-                e, mg = pick(cands, "exponential", hop_tau, d)
+                e, mg = pick(cands, "exponential", hop_tau, d, bw)
                 worst = min(worst, mg)
                 w = e[3]
                 beta = 1.0 / p if w == prev else (1.0 if g.has_edge(prev, w) else 1.0 / q)
@@ -253,7 +266,7 @@ def walk(g: BruteGraph, walk_id: int, max_len: int, seed: int, hop_kind="uniform
                 break
             e, mg = chosen, worst
         else:
-            e, mg = pick(cands, hop_kind, hop_tau, philox_numpy(seed, walk_id, hop, 0))
+            e, mg = pick(cands, hop_kind, hop_tau, philox_numpy(seed, walk_id, hop, 0), bw)
         nodes.append(e[3]); ts.append(e[0]); margins.append(mg)
         prev, cur, t = cur, e[3], e[0]
         hop += 1
@@ -263,9 +276,10 @@ def walk(g: BruteGraph, walk_id: int, max_len: int, seed: int, hop_kind="uniform
 # --------------------------------------------------------------- laws for chi-square
 
 def transition_law(g: BruteGraph, cur: int, t: int, prev: Optional[int], kind: str,
-                   tau: float, p: float = 1.0, q: float = 1.0):
-    """Exact probability of each next (dst, ts) pair from state (cur, t, prev)."""
-    cands = g.gamma(cur, t)
+                   tau: float, p: float = 1.0, q: float = 1.0, backward: bool = False):
+    """Exact probability of each next (dst, ts) pair from state (cur, t, prev);
+    backward: over g's edges before t, listed latest first."""
+    cands = list(reversed(g.gamma_before(cur, t))) if backward else g.gamma(cur, t)
     if not cands:
         return {}
     groups = _groups(cands)
@@ -289,7 +303,8 @@ def transition_law(g: BruteGraph, cur: int, t: int, prev: Optional[int], kind: s
         tot = n * (n + 1) / 2
         gp = [(i + 1) / tot for i in range(n)]
     else:
-        lam = exp_lambda(groups[0][0][0], groups[-1][0][0], n, tau)
+        lam = exp_lambda(min(grp[0][0] for grp in groups), max(grp[0][0] for grp in groups), n,
+                         tau)
         w = [float(x) for x in exp_masses(n, lam)]
         s = sum(w)
         gp = [x / s for x in w]
