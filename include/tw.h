@@ -76,6 +76,23 @@ typedef enum {
     TW_WEIGHT = 4
 } tw_bias_kind;
 
+/* TW_FORWARD: each hop takes an out-edge of the current node strictly after
+ * the current time (Gamma_t(v), Sec. "Design Constraints").
+ * TW_BACKWARD: each hop takes an in-edge (u, v, t') of the current node v
+ * with t' strictly before the current time t (the backward case the paper
+ * defines by analogy) and moves to u. The candidates are listed from the
+ * latest to the earliest, in reverse canonical order, and every pick index
+ * over n of them (edge, group, edge inside a group; the start edge or group
+ * of the window) is mirrored to n - 1 - i; without equal timestamps this is
+ * the forward walk on the graph with reversed edges and negated timestamps.
+ * Start edge (u, v, t) of the window: the walk starts at v, then u at t.
+ * A directed graph keeps an in-view (a second index fed every batch with
+ * source and destination swapped) from its first backward walk on, which
+ * doubles the cost of later ingests; an undirected graph is its own in-view.
+ * Backward walks run on the full-walk dispatch (AUTO or FULL_WALK); TW_WEIGHT
+ * is forward only; tw_sample_walks_batch and the server walk forward. */
+typedef enum { TW_FORWARD = 0, TW_BACKWARD = 1 } tw_direction;
+
 /* TW_START_EDGE: the first edge is drawn from the whole window (timestamp
  * view) under start_bias. TW_START_NODE: walk i starts at d_start_nodes[i]
  * and its first edge is drawn from that node's whole run under start_bias. */
@@ -123,6 +140,7 @@ typedef struct {
     uint64_t seed;               /* RNG key */
     uint64_t walk_id_base;       /* walk i uses RNG id walk_id_base + i */
     int32_t dispatch;            /* tw_dispatch */
+    int32_t direction;           /* tw_direction (tw_sample_walks only; 0: forward) */
 } tw_walk_params;
 
 /*

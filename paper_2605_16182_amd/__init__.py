@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libtw.so")
 UNIFORM, LINEAR, EXPONENTIAL, NODE2VEC, WEIGHT = 0, 1, 2, 3, 4
 KINDS = {"uniform": UNIFORM, "linear": LINEAR, "exponential": EXPONENTIAL, "node2vec": NODE2VEC,
          "weight": WEIGHT}
+DIRECTIONS = {"forward": 0, "backward": 1}
 START_EDGE, START_NODE = 0, 1
 START_MODES = {"edge": START_EDGE, "node": START_NODE}
 DISPATCH = {"auto": 0, "full_walk": 1, "coop": 2, "queue": 3}
@@ -45,7 +46,8 @@ class _WalkParams(_c.Structure):
     _fields_ = [("num_walks", _c.c_int64), ("max_len", _c.c_int32), ("hop_bias", _Bias),
                 ("start_bias", _Bias), ("start_mode", _c.c_int32),
                 ("d_start_nodes", _c.c_void_p), ("seed", _c.c_uint64),
-                ("walk_id_base", _c.c_uint64), ("dispatch", _c.c_int32)]
+                ("walk_id_base", _c.c_uint64), ("dispatch", _c.c_int32),
+                ("direction", _c.c_int32)]
 
 
 class _BatchParams(_c.Structure):
@@ -201,8 +203,10 @@ class Graph:
                      start_bias: str = "uniform", start_tau: float = 0.0,
                      start_mode: str = "edge", start_nodes: Optional[torch.Tensor] = None,
                      seed: int = 42, walk_id_base: int = 0, dispatch: str = "auto",
-                     out=None):
-        """Returns (nodes int32[W, L], ts int64[W, L], len int32[W]) on the device."""
+                     out=None, direction: str = "forward"):
+        """Returns (nodes int32[W, L], ts int64[W, L], len int32[W]) on the device.
+        direction "backward": each hop takes an in-edge strictly before the
+        current time (tw_direction)."""
         W, L = int(num_walks), int(max_len)
         if out is None:
             nodes = torch.empty((W, max(L, 1)), dtype=torch.int32, device=self.device)
@@ -215,7 +219,7 @@ class Graph:
         prm = _WalkParams(W, L, _Bias(KINDS[hop_bias], float(hop_tau), float(p), float(q)),
                           _Bias(KINDS[start_bias], float(start_tau), 1.0, 1.0),
                           START_MODES[start_mode], _ptr(start_nodes), int(seed),
-                          int(walk_id_base), DISPATCH[dispatch])
+                          int(walk_id_base), DISPATCH[dispatch], DIRECTIONS[direction])
         _check(self._lib.tw_sample_walks(self._h, _c.byref(prm), _ptr(nodes), _ptr(ts),
                                          _ptr(lens)))
         return nodes, ts, lens

@@ -32,7 +32,7 @@ tw_status guarded(const char* what, F&& f) {
 
 // pending device-side errors from walks: flag 0, a start node out of range;
 // flag 3, a batched walk with a length limit, bias index or row out of range
-tw_status check_device_flags(tw_graph* g) {
+tw_status check_flags_of(tw_graph* g) {
     if (!g->err.p || !g->h_scal) return TW_OK;
     // the flags land in the pinned host copy, after the scalar slots
     uint32_t* f = static_cast<uint32_t*>(g->h_scal) + tw::SCALAR_BYTES / 4;
@@ -49,6 +49,13 @@ tw_status check_device_flags(tw_graph* g) {
         return fail(TW_EINVAL, "a batched walk had a length limit, bias index or row out of range");
     }
     return TW_OK;
+}
+
+// the graph's flags, then its in-view's (backward walks run there)
+tw_status check_device_flags(tw_graph* g) {
+    tw_status st = check_flags_of(g);
+    if (st == TW_OK && g->rev) st = check_flags_of(g->rev);
+    return st;
 }
 
 }  // namespace
@@ -76,10 +83,7 @@ tw_status tw_create(const tw_config* cfg, tw_graph** out) {
 tw_status tw_destroy(tw_graph* g) {
     if (!g) return TW_OK;
     return guarded("tw_destroy", [&]() -> tw_status {
-        hipStreamSynchronize(g->stream);
-        for (tw::DevBuf* b : g->buffers()) tw::release(*b);
-        if (g->h_scal) (void)hipHostFree(g->h_scal);
-        delete g;
+        tw::release_graph(g);
         return TW_OK;
     });
 }
@@ -89,6 +93,7 @@ tw_status tw_set_stream(tw_graph* g, void* hip_stream) {
     if (hipStreamSynchronize(g->stream) != hipSuccess)
         return fail(TW_EDEVICE, "tw_set_stream: synchronising the old stream failed");
     g->stream = static_cast<hipStream_t>(hip_stream);
+    if (g->rev) g->rev->stream = g->stream;
     return TW_OK;
 }
 
@@ -101,7 +106,9 @@ tw_status tw_ingest_batch(tw_graph* g, const int32_t* d_src, const int32_t* d_ds
         tw_status st = check_device_flags(g);
         if (st != TW_OK) return st;
         tw::Error e{TW_OK, ""};
-        return report(tw::ingest(g, d_src, d_dst, d_ts, n, info, e), e);
+        if (tw::ingest(g, d_src, d_dst, d_ts, n, info, e) == TW_OK && g->rev)
+            tw::ingest(g->rev, d_dst, d_src, d_ts, n, nullptr, e);  // the in-view
+        return report(e.code, e);
     });
 }
 
@@ -111,7 +118,9 @@ tw_status tw_evict_before(tw_graph* g, int64_t t_cutoff, int64_t* n_evicted) {
         tw_status st = check_device_flags(g);
         if (st != TW_OK) return st;
         tw::Error e{TW_OK, ""};
-        return report(tw::evict_before(g, t_cutoff, n_evicted, e), e);
+        if (tw::evict_before(g, t_cutoff, n_evicted, e) == TW_OK && g->rev)
+            tw::evict_before(g->rev, t_cutoff, nullptr, e);  // the in-view
+        return report(e.code, e);
     });
 }
 
@@ -281,7 +290,7 @@ int64_t tw_device_bytes(const tw_graph* g) {
 
     int64_t total = 0;
     for (const tw::DevBuf* b : const_cast<tw_graph*>(g)->buffers()) total += (int64_t)b->bytes;
-    return total;
+    return total + (g->rev ? tw_device_bytes(g->rev) : 0);
 }
 
 const char* tw_last_error(void) { return g_last_error.c_str(); }

@@ -609,6 +609,46 @@ tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& e
     return TW_OK;
 }
 
+tw_status backward_view(tw_graph* g, tw_graph** out, Error& err) {
+    if (!g->directed) {
+        *out = g;
+        return TW_OK;
+    }
+    if (!g->rev) {
+        if (!g->rec.p && init_empty(g, err) != TW_OK) return err.code;
+        tw_graph* r = new tw_graph();
+        r->V = g->V;
+        r->directed = true;
+        r->window = g->window;
+        r->stream = g->stream;
+        r->device = g->device;
+        // the same clock: late drops and cuts of later batches agree
+        r->t_now = g->t_now;
+        r->has_time = g->has_time;
+        g->rev = r;
+        // the window's records, source and destination swapped, in one batch
+        // (in canonical order, so ties keep their arrival order)
+        if (g->m > 0 &&
+            ingest(r, g->e_dst.as<int32_t>() + g->e_base, g->e_src.as<int32_t>() + g->e_base,
+                   g->e_ts.as<int64_t>() + g->e_base, g->m, nullptr, err) != TW_OK) {
+            release_graph(r);
+            g->rev = nullptr;
+            return err.code;
+        }
+    }
+    *out = g->rev;
+    return TW_OK;
+}
+
+void release_graph(tw_graph* g) {
+    if (!g) return;
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    release_graph(g->rev);
+    for (DevBuf* b : g->buffers()) release(*b);
+    if (g->h_scal) (void)hipHostFree(g->h_scal);
+    delete g;
+}
+
 tw_status pull_scalars(tw_graph* g, bool flags, Error& err) {
     hipStream_t s = g->stream;
     if (ensure_common(g, err) != TW_OK) return err.code;

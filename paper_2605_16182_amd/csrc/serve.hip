@@ -347,8 +347,8 @@ tw_status server_create(tw_graph* g, const tw_server_config* cfg, tw_server** ou
 
 tw_status server_submit(tw_server* S, const tw_walk_params* p, uint64_t* id, Error& err) {
     if (check_walk_params(p, err) != TW_OK) return err.code;
-    if (p->hop_bias.kind == TW_WEIGHT) {
-        err = Error{TW_EINVAL, "server_submit: the weight-based picker is not served"};
+    if (p->hop_bias.kind == TW_WEIGHT || p->direction != TW_FORWARD) {
+        err = Error{TW_EINVAL, "server_submit: served walks are forward, without TW_WEIGHT"};
         return err.code;
     }
     if (!id) {

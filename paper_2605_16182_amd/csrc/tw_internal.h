@@ -282,6 +282,9 @@ struct tw_graph {
     tw::DevBuf cw, w_tiles;
     bool w_ready = false;
     double w_scale = 0.0;
+    // backward walks of a directed graph: the in-view, a graph fed every
+    // batch with source and destination swapped (null until first needed)
+    tw_graph* rev = nullptr;
 
     // cooperative dispatch: per-walk state, live list, sort buffers
     tw::DevBuf c_node0, c_walk0, c_t0, c_node1, c_walk1, c_t1, c_node2, c_walk2, c_t2;
@@ -357,6 +360,12 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
                  int64_t n, tw_ingest_info* info, Error& err);
 tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& err);
 tw_status build_adjacency(tw_graph* g, Error& err);
+// The graph whose node view holds the in-edges (backward walks): g itself
+// when undirected, else g->rev, created from g's window on first use and
+// fed every later ingest and eviction.
+tw_status backward_view(tw_graph* g, tw_graph** out, Error& err);
+// Releases a graph's device and pinned memory (and its in-view's).
+void release_graph(tw_graph* g);
 // weights.hip: cumulative group weights of the node view for the
 // weight-based picker at time scale tau (tau <= 0: 1); a no-op while built.
 tw_status build_weights(tw_graph* g, double tau, Error& err);

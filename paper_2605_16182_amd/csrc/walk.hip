@@ -100,19 +100,21 @@ struct StartState {
 };
 
 // First pick of walk w: EDGE mode draws from the whole window, NODE mode from
-// the start node's run; writes output positions 0 and 1.
+// the start node's run; writes output positions 0 and 1. rev: a backward
+// walk (candidates listed in reverse).
 __device__ __forceinline__ StartState walk_start(const WalkArgs& a, const StartParams& sp, int64_t w,
                                                  uint64_t id, int32_t L, int32_t* out_n,
-                                                 int64_t* out_t) {
+                                                 int64_t* out_t, bool rev = false) {
     StartState st{0, 0, 0, 0};
     const Draw d0 = philox(id, 0, 0, sp.seed);
     if (sp.mode == TW_START_EDGE) {
         if (a.m == 0) return st;
         uint32_t e;
         if (sp.kind == TW_UNIFORM) {
-            e = a.e_base + (uint32_t)scale_u64(d0.x0, a.m);
+            const uint32_t i = (uint32_t)scale_u64(d0.x0, a.m);
+            e = a.e_base + (rev ? a.m - 1 - i : i);
         } else {
-            e = pick_global(a.gg_ts, a.gg_off, a.Gg, sp.kind, sp.tau, d0);
+            e = pick_global(a.gg_ts, a.gg_off, a.Gg, sp.kind, sp.tau, d0, rev);
         }
         const int32_t s = a.e_src[e], t_dst = a.e_dst[e];
         const int64_t t = a.e_ts[e];
@@ -137,7 +139,8 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, const StartP
     if (L == 1) return st;
     const NodeRec r = a.rec[v0];
     if (r.gb == r.ge) return st;
-    Pick p = pick_node(a.ng, a.n_dst, a.n_ts, r.gb, r.ge, r.ee, sp.kind, sp.tau, r.t_last, d0);
+    Pick p =
+        pick_node(a.ng, a.n_dst, a.n_ts, r.gb, r.ge, r.ee, sp.kind, sp.tau, r.t_last, d0, rev);
     const int32_t nx = p.dst;
     out_n[1] = nx;
     out_t[1] = p.t;
@@ -243,6 +246,73 @@ __global__ void __launch_bounds__(WALK_THREADS) k_walk_full(const WalkArgs a) {
             Pick p;
             int32_t nx;
             if (!hop_pick(a, hb, a.seed, r, gc, id, hop, prev, p, nx)) break;
+            out_n[len] = nx;
+            out_t[len] = p.t;
+            ++len;
+            prev = cur;
+            cur = nx;
+            tcur = p.t;
+        }
+    }
+    finish_walk(a, w, len);
+}
+
+// Backward walks (Gamma-_t(v): in-edges of v with t' < t, the backward case
+// of Sec. "Design Constraints") on the in-view: the candidates of a hop at
+// node v and time t are the groups [gb, hi) of v before the first group at
+// or after t, listed from the latest, so every pick index is mirrored.
+__device__ __forceinline__ bool back_pick(const WalkArgs& a, const HopBias& hb, uint64_t seed,
+                                          const NodeRec& r, uint32_t hi, uint64_t id,
+                                          uint64_t hop, int32_t prev, Pick& p, int32_t& nx) {
+    const uint32_t end = hi < r.ge ? a.ng[hi].first : r.ee;  // the candidates' edges end
+    const int64_t t_hi =
+        (hb.kind == TW_EXPONENTIAL || hb.kind == TW_NODE2VEC) ? a.ng[hi - 1].ts : 0;
+    if (hb.kind != TW_NODE2VEC) {
+        const Draw d = philox(id, hop, 0, seed);
+        p = pick_node(a.ng, a.n_dst, a.n_ts, r.gb, hi, end, hb.kind, hb.tau, t_hi, d, true);
+        nx = p.dst;
+        return true;
+    }
+    // in the in-view, prev -> cur is an edge: prev has an adjacency range
+    const uint2 rp = a.adj_rng[prev];
+    for (uint32_t trial = 0; trial < N2V_MAX_TRIALS; ++trial) {
+        const Draw d = philox(id, hop, trial, seed);
+        p = pick_node(a.ng, a.n_dst, a.n_ts, r.gb, hi, end, TW_EXPONENTIAL, hb.tau, t_hi, d, true);
+        nx = p.dst;
+        double beta;
+        if (nx == prev) beta = hb.inv_p;
+        else if (sorted_contains(a.adj, rp.x, rp.y, nx)) beta = 1.0;
+        else beta = hb.inv_q;
+        if (unit_closed_open(d.x2) * hb.beta_max < beta) return true;
+    }
+    atomicAdd(&a.err[2], 1u);
+    return false;
+}
+
+// One backward walk per thread (full-walk form).
+template <int HK, int SK>
+__global__ void __launch_bounds__(WALK_THREADS) k_walk_back(const WalkArgs a) {
+    const int64_t w = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
+    if (w >= a.num_walks) return;
+    const uint64_t id = a.base + (uint64_t)w;
+    int32_t* out_n = a.nodes + w * a.L;
+    int64_t* out_t = a.ts + w * a.L;
+    StartState st = walk_start(a, fixed_start<SK>(start_of(a)), w, id, a.L, out_n, out_t, true);
+    const HopBias hb = fixed_hop<HK>(a.hop);
+    int32_t len = st.len, cur = st.cur, prev = st.prev;
+    int64_t tcur = st.t;
+    if (len >= 2) {
+        for (uint64_t hop = 1; len < a.L; ++hop) {
+            const NodeRec r = a.rec[cur];
+            if (r.gb == r.ge) break;  // no in-edge at all
+            // the first group at or after tcur (first with a timestamp > tcur - 1)
+            const uint32_t hi = tcur - 1 >= r.t_last
+                                    ? r.ge
+                                    : fence_search(a.ng, a.fence, r, tcur - 1, nullptr, 0, 0);
+            if (hi == r.gb) break;  // Gamma- is empty
+            Pick p;
+            int32_t nx;
+            if (!back_pick(a, hb, a.seed, r, hi, id, hop, prev, p, nx)) break;
             out_n[len] = nx;
             out_t[len] = p.t;
             ++len;
@@ -1025,8 +1095,39 @@ tw_status prepare_plain(tw_graph* g, const tw_walk_params* p, int32_t* nodes, in
 
 }  // namespace
 
+// Backward walks: the full-walk kernel k_walk_back on the in-view.
+tw_status sample_backward(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int64_t* ts,
+                          int32_t* len, Error& err) {
+    if (p->hop_bias.kind == TW_WEIGHT) {
+        err = Error{TW_EINVAL, "sample_walks: the weight-based picker walks forward only"};
+        return err.code;
+    }
+    if (p->dispatch != TW_DISPATCH_AUTO && p->dispatch != TW_DISPATCH_FULL_WALK) {
+        err = Error{TW_EINVAL, "sample_walks: backward walks run on the full-walk dispatch"};
+        return err.code;
+    }
+    tw_graph* b = nullptr;
+    if (backward_view(g, &b, err) != TW_OK) return err.code;
+    WalkArgs a;
+    if (prepare_plain(b, p, nodes, ts, len, a, err) != TW_OK) return err.code;
+    if (p->num_walks == 0) return TW_OK;
+    launch_fill(b, nodes, ts, p->num_walks * (int64_t)p->max_len);
+    const dim3 grid((unsigned)ceil_div(p->num_walks, WALK_THREADS));
+    with_kinds(a.hop.kind, a.start_kind, [&](auto h, auto sk) {
+        hipLaunchKernelGGL((k_walk_back<decltype(h)::value, decltype(sk)::value>), grid,
+                           dim3(WALK_THREADS), 0, b->stream, a);
+    });
+    TW_HIP(hipGetLastError());
+    return TW_OK;
+}
+
 tw_status sample_walks(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int64_t* ts,
                        int32_t* len, Error& err) {
+    if (p && p->direction == TW_BACKWARD) return sample_backward(g, p, nodes, ts, len, err);
+    if (p && p->direction != TW_FORWARD) {
+        err = Error{TW_EINVAL, "sample_walks: bad direction"};
+        return err.code;
+    }
     WalkArgs a;
     if (prepare_plain(g, p, nodes, ts, len, a, err) != TW_OK) return err.code;
     if (p->num_walks == 0) return TW_OK;
@@ -1183,8 +1284,8 @@ tw_status row_offsets(tw_graph* g, const int32_t* max_len, int64_t n, int64_t* r
 
 tw_status autotune(tw_graph* g, const tw_walk_params* p, int64_t sample, int32_t* nodes,
                    int64_t* ts, int32_t* len, int32_t best[2], Error& err) {
-    if (!p || sample < 1) {
-        err = Error{TW_EINVAL, "autotune: need parameters and sample_walks >= 1"};
+    if (!p || sample < 1 || p->direction != TW_FORWARD) {
+        err = Error{TW_EINVAL, "autotune: need forward parameters and sample_walks >= 1"};
         return err.code;
     }
     tw_walk_params q = *p;

@@ -223,22 +223,28 @@ struct Pick {
     int64_t t;
 };
 
+// rev: a backward walk lists the candidates in reverse, so every index i
+// among n (the edge, the group, the edge inside the group) becomes n - 1 - i.
+// t_last is the timestamp of the last candidate group ge - 1.
 __device__ __forceinline__ Pick pick_node(const GroupRec* __restrict__ ng,
                                           const int32_t* __restrict__ n_dst,
                                           const int64_t* __restrict__ n_ts, uint32_t gc,
                                           uint32_t ge, uint32_t end, int kind, double tau,
-                                          int64_t t_last, const Draw& d) {
+                                          int64_t t_last, const Draw& d, bool rev = false) {
     if (kind == TW_UNIFORM) {
         const uint32_t c = ng[gc].first;
-        const uint32_t e = c + (uint32_t)scale_u64(d.x0, end - c);
+        const uint32_t i = (uint32_t)scale_u64(d.x0, end - c);
+        const uint32_t e = rev ? end - 1 - i : c + i;
         return Pick{n_dst[e], n_ts[e]};
     }
     const uint32_t n = ge - gc;
-    const uint32_t k = gc + pick_group(n, kind, tau, n > 1 ? ng[gc].ts : 0, t_last, d.x0);
+    const uint32_t i = pick_group(n, kind, tau, n > 1 ? ng[gc].ts : 0, t_last, d.x0);
+    const uint32_t k = rev ? ge - 1 - i : gc + i;
     const GroupRec a = ng[k];
     if (a.dst < 0) return Pick{a.dst & 0x7fffffff, a.ts};  // a one-edge group
     const uint32_t size = (k + 1 < ge ? ng[k + 1].first : end) - a.first;
-    return Pick{n_dst[a.first + (uint32_t)scale_u64(d.x1, size)], a.ts};
+    const uint32_t j = (uint32_t)scale_u64(d.x1, size);
+    return Pick{n_dst[a.first + (rev ? size - 1 - j : j)], a.ts};
 }
 
 // The weight-based pick (Sec. "Temporal Bias Sampling") among groups
@@ -274,10 +280,13 @@ __device__ __forceinline__ Pick pick_weight(const GroupRec* __restrict__ ng,
 // The edge-store position picked among the window's Gg timestamp groups.
 __device__ __forceinline__ uint32_t pick_global(const int64_t* __restrict__ gg_ts,
                                                 const uint32_t* __restrict__ gg_off, uint32_t Gg,
-                                                int kind, double tau, const Draw& d) {
-    const uint32_t k = pick_group(Gg, kind, tau, Gg > 1 ? gg_ts[0] : 0, gg_ts[Gg - 1], d.x0);
+                                                int kind, double tau, const Draw& d,
+                                                bool rev = false) {
+    const uint32_t i = pick_group(Gg, kind, tau, Gg > 1 ? gg_ts[0] : 0, gg_ts[Gg - 1], d.x0);
+    const uint32_t k = rev ? Gg - 1 - i : i;
     const uint32_t b0 = gg_off[k], b1 = gg_off[k + 1];
-    return b0 + (uint32_t)scale_u64(d.x1, b1 - b0);
+    const uint32_t j = (uint32_t)scale_u64(d.x1, b1 - b0);
+    return rev ? b1 - 1 - j : b0 + j;
 }
 
 }  // namespace tw

@@ -365,6 +365,86 @@ def test_weight_walks_follow_the_window():
     g.close()
 
 
+BACK_CASES = [
+    # hop, hop tau, p, q, start, start tau, mode
+    ("uniform", 0.0, 1, 1, "uniform", 0.0, "edge"),
+    ("linear", 0.0, 1, 1, "linear", 0.0, "node"),
+    ("exponential", 5e4, 1, 1, "exponential", 1e5, "edge"),
+    ("exponential", 0.0, 1, 1, "uniform", 0.0, "node"),
+    ("node2vec", 5e4, 0.5, 2.0, "uniform", 0.0, "edge"),
+]
+
+
+@pytest.mark.parametrize("ci", range(len(BACK_CASES)),
+                         ids=["-".join(map(str, c[:1] + c[4:])) for c in BACK_CASES])
+@pytest.mark.parametrize("directed", [True, False])
+def test_backward_walk_parity(ci, directed):
+    torch, tw = gpu_or_skip()
+    hk, ht, p, q, sk, st, mode = BACK_CASES[ci]
+    V, m = 4000, 60000
+    w = synth.scaled("tiny", V, m)
+    w["stream"].directed = directed
+    src, dst, ts = w["stream"].all()
+    g = tw.Graph(V, directed=directed)
+    og = oracle.OracleGraph(V, directed=directed, backward=True)
+    g.ingest_batch(*to_dev(torch, src, dst, ts))
+    og.ingest_batch(src, dst, ts)
+    W, L, seed, base = 20000, 16, 43, 9
+    starts = synth.start_nodes(10, W, V)
+    kw = dict(hop_bias=hk, hop_tau=ht, p=p, q=q, start_bias=sk, start_tau=st, start_mode=mode,
+              seed=seed, walk_id_base=base)
+    nodes, tts, lens = g.sample_walks(W, L, start_nodes=to_dev(torch, starts)[0],
+                                      direction="backward", **kw)
+    g.sync()
+    r = og.sample_walks(W, L, start_nodes=starts, with_margin=True, direction="backward", **kw)
+    exact = hk in ("uniform", "linear") and sk in ("uniform", "linear")
+    same, boundary = compare_walks((nodes.cpu().numpy(), tts.cpu().numpy(), lens.cpu().numpy()),
+                                   r, exact)
+    print(f"backward {hk}/{sk}/{mode} directed={directed}: {same}/{W} identical, "
+          f"{boundary} at a boundary; mean length {float(r['len'].mean()):.2f}")
+    assert boundary <= max(2, W // 2000)
+    assert float(r["len"].mean()) > 2.5
+    g.close()
+
+
+def test_backward_walks_follow_the_stream():
+    # the in-view is created mid-stream from the window, then fed every batch
+    # and eviction; forward walks are unchanged by it
+    torch, tw = gpu_or_skip()
+    rng = np.random.default_rng(71)
+    V, window = 401, 5_000
+    g = tw.Graph(V, window=window)
+    og = oracle.OracleGraph(V, window=window, backward=True)
+    t0 = 0
+    for b in range(14):
+        n = int(rng.integers(2000, 9000))
+        s = rng.integers(0, V, n).astype(np.int32)
+        d = rng.integers(0, V, n).astype(np.int32)
+        t = (t0 + rng.integers(-700, 1000, n)).astype(np.int64)
+        t0 += 1000
+        assert g.ingest_batch(*to_dev(torch, s, d, t)) == og.ingest_batch(s, d, t), b
+        if b % 5 == 3:
+            cut = t0 - 3500
+            assert g.evict_before(cut) == og.evict_before(cut)
+        if b < 4:
+            continue  # the in-view appears at batch 4
+        for direction in ("backward", "forward"):
+            nodes, ts, lens = g.sample_walks(3000, 10, hop_bias="linear", seed=b,
+                                             direction=direction)
+            g.sync()
+            r = og.sample_walks(3000, 10, hop_bias="linear", seed=b, direction=direction)
+            assert np.array_equal(nodes.cpu().numpy(), r["nodes"]), (b, direction)
+            assert np.array_equal(ts.cpu().numpy(), r["ts"]), (b, direction)
+            assert np.array_equal(lens.cpu().numpy(), r["len"]), (b, direction)
+    with pytest.raises(tw.TwError) as ei:
+        g.sample_walks(10, 5, hop_bias="weight", hop_tau=5.0, direction="backward")
+    assert ei.value.code == tw.TW_EINVAL
+    with pytest.raises(tw.TwError) as ei:
+        g.sample_walks(10, 5, dispatch="coop", direction="backward")
+    assert ei.value.code == tw.TW_EINVAL
+    g.close()
+
+
 def test_fresh_graph_reports_no_error():
     # device error flags start cleared: a fresh graph's first synchronising
     # calls succeed, before and after edge-start walks
