@@ -47,6 +47,9 @@ def parse():
                     choices=["uniform", "linear", "exponential", "node2vec", "weight"],
                     help="single-batch workload: hop bias in place of the workload's "
                          "(weight: the weight-based picker, its build timed with the walks)")
+    ap.add_argument("--direction", default="forward", choices=["forward", "backward"],
+                    help="single-batch workload: backward walks (in-edges before the current "
+                         "time); the in-view's update is part of every timed ingest")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
     return ap.parse_args()
@@ -596,6 +599,7 @@ def main():
     g = tw.Graph(spec.num_nodes, directed=spec.directed, window=w["window"])
     walk_kw = dict(hop_bias=w["hop_bias"], hop_tau=tau, start_bias=w["start_bias"],
                    start_tau=tau, seed=42, dispatch=args.dispatch, out=out,
+                   direction=args.direction,
                    **({"p": 0.5, "q": 2.0} if w["hop_bias"] == "node2vec" else {}))
 
     def step(events=None):
@@ -637,7 +641,7 @@ def main():
     # walk phase alone under each dispatch (index built once): plain full-walk
     # against the cooperative per-step regrouping
     compare = {}
-    for disp in ("full_walk", "coop"):
+    for disp in ("full_walk", "coop") if args.direction == "forward" else ("full_walk",):
         kw = dict(walk_kw, dispatch=disp)
         times = []
         for rep in range(4):
@@ -688,7 +692,8 @@ def main():
         "vs_baseline": None,
         "dtype": "int64+f64",
         "data": "synthetic",
-        "config": describe(args.workload, w, tau),
+        "config": dict(describe(args.workload, w, tau),
+                       **({"direction": "backward"} if args.direction == "backward" else {})),
         "dispatch": args.dispatch,
         "hops_per_step": hops,
         "plain_vs_tuned": compare,
@@ -714,7 +719,7 @@ def main():
         res["gather_roofline"]["note"] = ("weight-based hops: the binary search's reads come on "
                                           "top of the 4 sectors counted per hop")
     g.close()
-    if not args.no_cpu_baseline and w["hop_bias"] != "weight":
+    if not args.no_cpu_baseline and w["hop_bias"] != "weight" and args.direction == "forward":
         print("# oracle baseline ...", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(w, tau, hops)
     print(json.dumps(res), flush=True)
