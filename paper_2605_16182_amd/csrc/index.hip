@@ -221,12 +221,11 @@ tw_status ensure_common(tw_graph* g, Error& err) {
     return TW_OK;
 }
 
-// Capacity of the edge-store buffers for a window of `need` records; growing
-// copies the window to the front of the new buffers (e_base = 0).
-tw_status reserve_window(tw_graph* g, int64_t need, Error& err) {
-    if (need <= g->e_cap) return TW_OK;
-    int64_t cap = std::max<int64_t>(need, 2 * g->e_cap);
-    cap = std::max<int64_t>(cap, need + need / 2 + 1024);
+// Moves the window to the front of edge-store buffers of at least `cap`
+// records (e_base = 0). The capacity recorded is what every buffer of the
+// timestamp view holds, so the allocator's rounding is not wasted. The global
+// groups must be rebuilt afterwards.
+tw_status grow_window(tw_graph* g, int64_t cap, Error& err) {
     cap = std::min<int64_t>(cap, (int64_t)UINT32_MAX - 1);
     TW_HIP(ensure(g->a_src, sizeof(int32_t) * cap));
     TW_HIP(ensure(g->a_dst, sizeof(int32_t) * cap));
@@ -248,9 +247,38 @@ tw_status reserve_window(tw_graph* g, int64_t need, Error& err) {
     TW_HIP(ensure(g->a_ts, sizeof(int64_t) * cap));
     TW_HIP(ensure(g->gg_ts, sizeof(int64_t) * (cap + 2)));
     TW_HIP(ensure(g->gg_off, sizeof(uint32_t) * (cap + 2)));
+    int64_t held = (int64_t)UINT32_MAX - 1;
+    for (const DevBuf* b : {&g->e_src, &g->e_dst, &g->a_src, &g->a_dst})
+        held = std::min<int64_t>(held, (int64_t)(b->bytes / 4));
+    for (const DevBuf* b : {&g->e_ts, &g->a_ts})
+        held = std::min<int64_t>(held, (int64_t)(b->bytes / 8));
+    held = std::min<int64_t>(held, (int64_t)(g->gg_ts.bytes / 8) - 2);
+    held = std::min<int64_t>(held, (int64_t)(g->gg_off.bytes / 4) - 2);
     g->e_base = 0;
-    g->e_cap = cap;
+    g->e_cap = held;
     return TW_OK;
+}
+
+// Capacity of the edge-store buffers for a window of `need` records; growing
+// copies the window to the front of the new buffers (e_base = 0).
+tw_status reserve_window(tw_graph* g, int64_t need, Error& err) {
+    if (need <= g->e_cap) return TW_OK;
+    int64_t cap = std::max<int64_t>(need, 2 * g->e_cap);
+    cap = std::max<int64_t>(cap, need + need / 2 + 1024);
+    return grow_window(g, cap, err);
+}
+
+// Whether the device has room to grow the timestamp view to `cap` records
+// (edge store, its alternates and the global groups: 44 bytes a record),
+// keeping 1 GiB free.
+bool window_growth_fits(tw_graph* g, int64_t cap) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    const int64_t extra = std::max<int64_t>(cap - g->e_cap, 0) * 44;
+    return (int64_t)free_b > extra + (1ll << 30);
 }
 
 // Global timestamp groups of the whole window, from scratch (gg_base = 0).
@@ -490,7 +518,15 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
         const bool placed = keep_tail || keep_alt;
         g->m = na;
         if (!placed && g->e_base + m_new > g->e_cap) {
-            if (m_new <= g->e_cap && g->m > 0) {
+            // After a move to the front, the free tail should take about as
+            // many records as the window holds, so that a record is moved
+            // about once while it is in the window: a tighter buffer grows
+            // instead (when the device has room), which moves it as well.
+            const int64_t roomy = 2 * m_new + kept;
+            const bool grow = roomy > g->e_cap && window_growth_fits(g, roomy);
+            if (grow) {
+                if (grow_window(g, roomy, err) != TW_OK) return err.code;
+            } else if (m_new <= g->e_cap && g->m > 0) {
                 // compact to the front of the alternate buffers
                 TW_HIP(hipMemcpyAsync(g->a_src.p, g->e_src.as<int32_t>() + g->e_base, 4 * na,
                                       hipMemcpyDeviceToDevice, s));

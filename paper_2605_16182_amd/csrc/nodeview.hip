@@ -373,43 +373,78 @@ __device__ __forceinline__ uint32_t job_in(const uint32_t* __restrict__ off, uin
     return a - 1;
 }
 
-// The jobs covering a tile of NV_TILE consecutive outputs (or entries),
-// found by thread 0; the tile's items go to consecutive lanes, so reads and
-// writes of the per-node runs coalesce.
-__device__ __forceinline__ void tile_jobs(const uint32_t* __restrict__ off, int64_t nj,
-                                          uint64_t base, uint64_t last, uint32_t* jr) {
-    if (threadIdx.x == 0) {
-        jr[0] = job_of(off, (uint32_t)nj, base);
-        jr[1] = job_of(off, (uint32_t)nj, last);
-    }
-    __syncthreads();
+// First job of every tile of NV_TILE outputs (the job holding the tile's
+// first output), one thread per tile; tf[nt] = nj - 1 closes the last range.
+__global__ void k_tile_first(const uint32_t* __restrict__ off, int64_t nj, int64_t nt,
+                             uint32_t* __restrict__ tf) {
+    const int64_t b = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (b > nt) return;
+    tf[b] = b == nt ? (uint32_t)(nj - 1) : job_of(off, (uint32_t)nj, (uint64_t)b * NV_TILE);
 }
+
+// The jobs that may cover a tile of NV_TILE consecutive outputs (or entries):
+// the tile's items go to consecutive lanes, so reads and writes of the
+// per-node runs coalesce. Their offsets off[j0 .. j1 + 1] are staged in LDS
+// when they fit (the job lookups of the tile then stay in LDS).
+constexpr int OFF_LDS = 2 * NV_TILE + 2;
+
+struct TileJobs {
+    uint32_t j0, j1;
+    bool staged;
+
+    __device__ TileJobs(const uint32_t* __restrict__ tf, uint32_t tile,
+                        const uint32_t* __restrict__ off, uint32_t* soff) {
+        j0 = tf[tile];
+        j1 = tf[tile + 1];
+        const uint32_t cnt = j1 - j0 + 2;
+        staged = cnt <= (uint32_t)OFF_LDS;
+        if (staged)
+            for (uint32_t i = threadIdx.x; i < cnt; i += T) soff[i] = off[j0 + i];
+        __syncthreads();
+    }
+    // the job holding output t of the tile
+    __device__ uint32_t job(const uint32_t* __restrict__ off, const uint32_t* soff,
+                            uint64_t t) const {
+        if (!staged) return job_in(off, j0, j1, t);
+        uint32_t a = 1, b = j1 - j0 + 1;  // last k with soff[k] <= t (soff[0] <= t)
+        while (a < b) {
+            const uint32_t mid = a + ((b - a) >> 1);
+            if ((uint64_t)soff[mid] <= t) a = mid + 1; else b = mid;
+        }
+        return j0 + a - 1;
+    }
+    // off[j] for a job j of the tile's range, or j1 + 1
+    __device__ uint32_t start(const uint32_t* __restrict__ off, const uint32_t* soff,
+                              uint32_t j) const {
+        return staged ? soff[j - j0] : off[j];
+    }
+};
 
 // Group starts of the job outputs as a bitmap (bit t & 63 of word t >> 6
 // marks output t; each round of a wavefront covers one word) and the number
 // of group starts in every tile of NV_TILE outputs.
 __global__ void __launch_bounds__(T) k_job_flags(const Job* __restrict__ jobs,
-                                                 const uint32_t* __restrict__ off, int64_t nj,
+                                                 const uint32_t* __restrict__ off,
+                                                 const uint32_t* __restrict__ tf,
                                                  int64_t total, const int64_t* __restrict__ ots,
                                                  const int64_t* __restrict__ bts,
                                                  uint64_t* __restrict__ bm,
                                                  uint32_t* __restrict__ tcnt) {
-    __shared__ uint32_t jr[2];
+    __shared__ uint32_t soff[OFF_LDS];
     __shared__ uint32_t wsum[T / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t base = (int64_t)tile * NV_TILE;
-    tile_jobs(off, nj, (uint64_t)base, (uint64_t)std::min<int64_t>(base + NV_TILE, total) - 1,
-              jr);
+    const TileJobs tj(tf, tile, off, soff);
     uint32_t c = 0;
     for (int u = 0; u < NV_ITEMS; ++u) {
         const int64_t t0 = base + (int64_t)u * T + wave * 64;  // the word's first output
         const int64_t t = t0 + lane;
         bool start = false;
         if (t < total) {
-            const uint32_t j = job_in(off, jr[0], jr[1], (uint64_t)t);
+            const uint32_t j = tj.job(off, soff, (uint64_t)t);
             const Job J = jobs[j];
-            const uint32_t i = (uint32_t)(t - off[j]);
+            const uint32_t i = (uint32_t)(t - tj.start(off, soff, j));
             const int64_t x = job_ts(J, i, ots, bts);
             if (i == 0) start = J.kind != JOB_APPEND || x != J.t_last;
             else start = x != job_ts(J, i - 1, ots, bts);
@@ -447,7 +482,8 @@ __device__ __forceinline__ uint32_t out_rank(const uint64_t* __restrict__ bm,
 // rank is that tile's offset plus the bits before it. Stores each word's first
 // rank in pref for k_job_finish.
 __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
-                                                 const uint32_t* __restrict__ off, int64_t nj,
+                                                 const uint32_t* __restrict__ off,
+                                                 const uint32_t* __restrict__ tf,
                                                  int64_t total, const int32_t* __restrict__ odst,
                                                  const int64_t* __restrict__ ots,
                                                  const int32_t* __restrict__ bdst,
@@ -461,7 +497,7 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
                                                  uint32_t* __restrict__ fence) {
     constexpr int WORDS = NV_TILE / 64;
     static_assert(WORDS <= 64, "one wavefront scans a tile's words");
-    __shared__ uint32_t jr[2];
+    __shared__ uint32_t soff[OFF_LDS];
     __shared__ uint64_t sbm[WORDS];
     __shared__ uint32_t spre[WORDS];
     __shared__ uint32_t k_first;  // rank at the first output of a job begun earlier
@@ -469,7 +505,7 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t base = (int64_t)tile * NV_TILE;
     const int64_t last = std::min<int64_t>(base + NV_TILE, total) - 1;
-    tile_jobs(off, nj, (uint64_t)base, (uint64_t)last, jr);
+    const TileJobs tj(tf, tile, off, soff);
     if (wave == 0) {
         const int64_t nw = ((last - base) >> 6) + 1;
         const uint64_t wb = lane < nw ? bm[(base >> 6) + lane] : 0ull;
@@ -487,7 +523,7 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
         }
         if (lane < nw) pref[(base >> 6) + lane] = p0;
     } else if (wave == 1) {
-        const int64_t s0 = off[jr[0]];
+        const int64_t s0 = tj.start(off, soff, tj.j0);
         if (s0 < base) {
             const int64_t a = s0 / NV_TILE;
             const int64_t q = s0 >> 6, wd = ((a * NV_TILE) >> 6) + lane;
@@ -503,9 +539,9 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
     for (int u = 0; u < NV_ITEMS; ++u) {
         const int64_t t = base + (int64_t)u * T + threadIdx.x;
         if (t >= total) break;
-        const uint32_t j = job_in(off, jr[0], jr[1], (uint64_t)t);
+        const uint32_t j = tj.job(off, soff, (uint64_t)t);
         const Job J = jobs[j];
-        const uint32_t jb = off[j];
+        const uint32_t jb = tj.start(off, soff, j);
         const uint32_t i = (uint32_t)(t - jb);
         const Elem e = job_elem(J, i, odst, ots, bdst, bts);
         const uint32_t pos = J.e_at + i;
@@ -523,7 +559,7 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
         if (starts) {
             // a one-edge group: the job's next output starts a group, or
             // there is none
-            bool single = (uint64_t)t + 1 >= (uint64_t)off[j + 1];
+            bool single = (uint64_t)t + 1 >= (uint64_t)tj.start(off, soff, j + 1);
             if (!single) {
                 const int ln = lt + 1;
                 const uint64_t nw = ln < NV_TILE ? sbm[ln >> 6] : bm[(uint64_t)(t + 1) >> 6];
@@ -649,10 +685,12 @@ __global__ void k_job_finish(const Job* __restrict__ jobs, const uint32_t* __res
 // Fence word u of job J (u counts the words the job writes): a rewritten
 // segment writes, on every level, the keys and the padding; an append the
 // keys and padding its new groups add. Level-0 keys are written by
-// k_job_write, so level 0 contributes padding only. Keys are taken under the
-// job's key base and shift (the node record carries both).
+// k_job_write, so level 0 contributes padding only; the key of entry i on
+// level k is the level-0 key of group i * FENCE_FAN^k (keys are taken under
+// the key base and shift of the segment, which an append keeps), read from
+// level 0: four keys per 128-byte line on level 1, where the group records
+// would give one.
 __device__ __forceinline__ void fence_entry(const Job& J, uint32_t ge,
-                                            const GroupRec* __restrict__ ngd,
                                             uint32_t* __restrict__ fence, uint64_t u) {
     const uint64_t cap = seg_groups(J.gcode);
     uint32_t* f = fence + J.f0;
@@ -675,8 +713,7 @@ __device__ __forceinline__ void fence_entry(const Job& J, uint32_t ge,
         if (k == 0) nkeys = 0;
         if (u < nkeys) {
             const uint64_t i = key0 + u;
-            f[off + i] = (uint32_t)((uint64_t)(ngd[J.g0 + (i << (FENCE_LOG * k))].ts - J.kbase) >>
-                                    J.kshift);
+            f[off + i] = f[i << (FENCE_LOG * k)];
             return;
         }
         u -= nkeys;
@@ -689,25 +726,35 @@ __device__ __forceinline__ void fence_entry(const Job& J, uint32_t ge,
     }
 }
 
+// First job of every tile of the fence entries (total = foff[nj], on the
+// device), as k_tile_first; grid-stride.
+__global__ void k_tile_first_dev(const uint32_t* __restrict__ foff, int64_t nj,
+                                 uint32_t* __restrict__ tf) {
+    const uint64_t nt = ((uint64_t)foff[nj] + NV_TILE - 1) / NV_TILE;
+    for (uint64_t b = (uint64_t)blockIdx.x * T + threadIdx.x; b <= nt;
+         b += (uint64_t)gridDim.x * T)
+        tf[b] = b == nt ? (uint32_t)(nj - 1) : job_of(foff, (uint32_t)nj, b * NV_TILE);
+}
+
 // the fence entries of the jobs (total = foff[nj]), tiles of NV_TILE
 // entries, grid-stride
 __global__ void __launch_bounds__(T) k_job_fence(const Job* __restrict__ jobs,
-                                                 const uint32_t* __restrict__ foff, int64_t nj,
+                                                 const uint32_t* __restrict__ foff,
+                                                 const uint32_t* __restrict__ tf, int64_t nj,
                                                  const NodeRec* __restrict__ rec,
-                                                 const GroupRec* __restrict__ ngd,
                                                  uint32_t* __restrict__ fence) {
-    __shared__ uint32_t jr[2];
+    __shared__ uint32_t soff[OFF_LDS];
     const uint64_t total = foff[nj];
-    for (uint64_t base = (uint64_t)blockIdx.x * NV_TILE; base < total;
-         base += (uint64_t)gridDim.x * NV_TILE) {
-        __syncthreads();  // jr of the previous tile is no longer read
-        tile_jobs(foff, nj, base, std::min<uint64_t>(base + NV_TILE, total) - 1, jr);
+    for (uint64_t tile = blockIdx.x; tile * NV_TILE < total; tile += gridDim.x) {
+        __syncthreads();  // the previous tile's offsets are no longer read
+        const uint64_t base = tile * NV_TILE;
+        const TileJobs tj(tf, (uint32_t)tile, foff, soff);
         for (int u = 0; u < NV_ITEMS; ++u) {
             const uint64_t t = base + (uint64_t)u * T + threadIdx.x;
             if (t >= total) break;
-            const uint32_t j = job_in(foff, jr[0], jr[1], t);
+            const uint32_t j = tj.job(foff, soff, t);
             const Job J = jobs[j];
-            fence_entry(J, rec[J.v].ge, ngd, fence, t - foff[j]);
+            fence_entry(J, rec[J.v].ge, fence, t - tj.start(foff, soff, j));
         }
     }
 }
@@ -916,23 +963,37 @@ tw_status execute_jobs(tw_graph* g, int64_t nj, uint64_t out, const int32_t* sds
     const int64_t words = ceil_div((int64_t)out, 64), nt = ceil_div((int64_t)out, NV_TILE);
     TW_HIP(ensure(g->o_flag, sizeof(uint64_t) * (words + 1) + sizeof(uint32_t) * (words + 1)));
     TW_HIP(ensure(g->o_rank, sizeof(uint32_t) * (nt + 1)));
+    TW_HIP(ensure(g->o_tf, sizeof(uint32_t) * (nt + 1)));
     uint64_t* bm = g->o_flag.as<uint64_t>();
     uint32_t* pref = reinterpret_cast<uint32_t*>(bm + words + 1);
     uint32_t* tcnt = g->o_rank.as<uint32_t>();
-    if (out > 0)
-        hipLaunchKernelGGL(k_job_flags, dim3((unsigned)nt), dim3(T), 0, s, jobs, off, nj,
+    uint32_t* tf = g->o_tf.as<uint32_t>();
+    if (out > 0) {
+        hipLaunchKernelGGL(k_tile_first, grid_for(nt + 1), dim3(T), 0, s, off, nj, nt, tf);
+        hipLaunchKernelGGL(k_job_flags, dim3((unsigned)nt), dim3(T), 0, s, jobs, off, tf,
                            (int64_t)out, sts, g->bs_ts.as<int64_t>(), bm, tcnt);
+    }
     TW_HIP(scan_exclusive_u32(tcnt, tcnt, nt, tcnt + nt, g->ws, s));
     if (out > 0)
-        hipLaunchKernelGGL(k_job_write, dim3((unsigned)nt), dim3(T), 0, s, jobs, off, nj,
+        hipLaunchKernelGGL(k_job_write, dim3((unsigned)nt), dim3(T), 0, s, jobs, off, tf,
                            (int64_t)out, sdst, sts, g->bs_dst.as<int32_t>(),
                            g->bs_ts.as<int64_t>(), bm, tcnt, pref, ddst, dts, dng, dfence);
     hipLaunchKernelGGL(k_job_finish, grid_for(nj), dim3(T), 0, s, jobs, off, nj, bm, pref,
                        (int64_t)out, tcnt + nt, dng, g->rec.as<NodeRec>(), g->seg.as<SegRec>(),
                        gen, g->j_fw.as<uint32_t>());
     TW_HIP(scan_jobs(g->j_fw.as<uint32_t>(), g->j_fw.as<uint32_t>(), nj, g->ws, s));
-    hipLaunchKernelGGL(k_job_fence, dim3(FENCE_GRID), dim3(T), 0, s, jobs, g->j_fw.as<uint32_t>(),
-                       nj, g->rec.as<NodeRec>(), dng, dfence);
+    if (nj > 0) {
+        // every fence word a job writes is a distinct word of the pool
+        const uint64_t fcap = (dfence == g->fence.as<uint32_t>() ? g->fence.bytes
+                                                                  : g->afence.bytes) /
+                              sizeof(uint32_t);
+        TW_HIP(ensure(g->f_tf, sizeof(uint32_t) * (fcap / NV_TILE + 2)));
+        hipLaunchKernelGGL(k_tile_first_dev, dim3(FENCE_GRID / 8), dim3(T), 0, s,
+                           g->j_fw.as<uint32_t>(), nj, g->f_tf.as<uint32_t>());
+        hipLaunchKernelGGL(k_job_fence, dim3(FENCE_GRID), dim3(T), 0, s, jobs,
+                           g->j_fw.as<uint32_t>(), g->f_tf.as<uint32_t>(), nj,
+                           g->rec.as<NodeRec>(), dfence);
+    }
     TW_HIP(hipGetLastError());
     return TW_OK;
 }

@@ -3,6 +3,7 @@
 // from wave ballots (each lane learns which lanes of its wavefront share its
 // digit from one ballot per digit bit, then counts the lower ones).
 #include <algorithm>
+#include <type_traits>
 
 #include "compact.h"
 #include "tw_internal.h"
@@ -212,21 +213,30 @@ struct GroupStartOp {
 // tile's items [w * RS_WAVE_ITEMS, (w + 1) * RS_WAVE_ITEMS), 64 per round.
 // Ranks are wavefront-private (no workgroup barrier per round): in each round
 // the lanes sharing a digit learn each other from one ballot per digit bit,
-// and the lowest of them advances the wavefront's count for that digit.
+// and the lowest of them advances the wavefront's count for that digit. (LDS
+// atomics in the histogram pass measured slower on source-id keys, whose
+// skew makes many lanes of a wavefront hit one counter.)
 
 constexpr int RS_WAVE_ITEMS = RS_TILE / RS_WAVES;
 constexpr int RS_RADIX = 256;  // one digit per thread of the workgroup
 static_assert(RS_RADIX == RS_THREADS, "digit tables are indexed by thread");
 
-// lanes of the wavefront whose digit equals this lane's, among valid lanes
+// lanes of the wavefront whose digit (of nbits <= 8 bits) equals this lane's,
+// among valid lanes: one ballot per digit bit; a lane collects the lanes
+// whose bit differs from its own and keeps the others
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, int nbits) {
-    uint64_t peers = __ballot(valid);
-    for (int b = 0; b < nbits; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t bal = __ballot(bit);
-        peers &= bit ? bal : ~bal;
+    const uint64_t live = __ballot(valid);
+    uint64_t differ = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        if (b < nbits) {
+            // all ones when the bit is set (a signed one-bit field extract)
+            const uint32_t m = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
+            const uint64_t bal = __ballot(m != 0u);
+            differ |= bal ^ (((uint64_t)m << 32) | m);
+        }
     }
-    return peers;
+    return live & ~differ;
 }
 
 template <typename K>
@@ -266,16 +276,19 @@ k_rs_hist(const K* __restrict__ keys, int64_t n, int shift, int nbits,
 // first output slot of digit d for tile b (exclusive scan of the histogram).
 // The tile is first ordered by digit in LDS, one array at a time, so that
 // consecutive lanes write consecutive slots of each digit's run.
-template <typename K>
+// W64: the items carry a 64-bit payload (v64); without it the LDS staging
+// area is as wide as the widest of key and 32-bit value.
+template <typename K, bool W64>
 __global__ void __launch_bounds__(RS_THREADS)
 k_rs_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
              const uint64_t* __restrict__ v64, int64_t n, int shift, int nbits,
              const uint32_t* __restrict__ offs, int64_t nblocks, K* __restrict__ keys_out,
              uint32_t* __restrict__ vals_out, uint64_t* __restrict__ v64_out) {
+    using Stage = std::conditional_t<W64 || sizeof(K) == 8, uint64_t, uint32_t>;
     __shared__ uint32_t cnt[RS_WAVES][RS_RADIX];  // wave counts, then wave starts
     __shared__ uint32_t lstart[RS_RADIX];         // tile-local first slot of each digit
     __shared__ uint32_t gstart[RS_RADIX];         // output slot of that first item
-    __shared__ uint64_t stage[RS_TILE];
+    __shared__ Stage stage[RS_TILE];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t mask = (1u << nbits) - 1u;
     const uint64_t lower = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -291,13 +304,13 @@ k_rs_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
     // every input of the tile is loaded up front
     K k[RS_ITEMS];
     uint32_t lp[RS_ITEMS], v[RS_ITEMS];
-    uint64_t w2[RS_ITEMS];
+    uint64_t w2[W64 ? RS_ITEMS : 1];
 #pragma unroll
     for (int r = 0; r < RS_ITEMS; ++r) {
         const int64_t i = wbase + r * 64 + lane;
         k[r] = i < n ? keys[i] : K(0);
         v[r] = (vals && i < n) ? vals[i] : 0u;
-        w2[r] = (v64 && i < n) ? v64[i] : 0ull;
+        if constexpr (W64) w2[r] = i < n ? v64[i] : 0ull;
     }
 
     // stable rank of each item among the wavefront's items of its digit
@@ -363,7 +376,7 @@ k_rs_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
             if (sl < tile_n) vals_out[gp[r]] = sv[sl];
         }
     }
-    if (v64) {
+    if constexpr (W64) {
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < RS_ITEMS; ++r)
@@ -427,9 +440,13 @@ hipError_t radix_sort_impl(const K* kin0, const uint32_t* vin0, const uint64_t* 
                            hist, nblocks);
         if ((e = scan_exclusive_u32(hist, hist, 256 * nblocks, nullptr, ws, s)) != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_rs_scatter<K>, dim3(nblocks), dim3(RS_THREADS), 0, s, ki,
-                           has_v ? vi : nullptr, has_w ? wi : nullptr, n, sh, nb, hist, nblocks,
-                           ko, vo, wo);
+        if (has_w)
+            hipLaunchKernelGGL((k_rs_scatter<K, true>), dim3(nblocks), dim3(RS_THREADS), 0, s,
+                               ki, has_v ? vi : nullptr, wi, n, sh, nb, hist, nblocks, ko, vo, wo);
+        else
+            hipLaunchKernelGGL((k_rs_scatter<K, false>), dim3(nblocks), dim3(RS_THREADS), 0, s,
+                               ki, has_v ? vi : nullptr, nullptr, n, sh, nb, hist, nblocks, ko, vo,
+                               nullptr);
         ki = ko;
         vi = vo;
         wi = wo;

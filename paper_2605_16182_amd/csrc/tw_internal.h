@@ -271,6 +271,7 @@ struct tw_graph {
     tw::DevBuf c_node, c_bf, c_be;     // job candidates: node, batch run
     tw::DevBuf jobs, j_cnt, j_off, j_re, j_rg, j_rf, j_fw;
     tw::DevBuf o_flag, o_rank;         // per written edge: group start, rank
+    tw::DevBuf o_tf, f_tf;             // first job of every tile of written edges, fence words
     int64_t T = 0;                     // jobs collected for the next update
     // counters of the last update: jobs, edges written, edge slots of new
     // segments, whether every active node was rewritten
@@ -312,7 +313,7 @@ struct tw_graph {
                 &n_dst, &n_ts, &ng, &fence, &an_dst, &an_ts, &ang, &afence,
                 &rec, &seg, &touched, &bs_src, &bs_dst, &bs_ts, &q_src, &q_dst, &q_ts,
                 &c_node, &c_bf, &c_be, &jobs, &j_cnt, &j_off, &j_re, &j_rg, &j_rf, &j_fw,
-                &o_flag, &o_rank, &adj, &adj_rng,
+                &o_flag, &o_rank, &o_tf, &f_tf, &adj, &adj_rng,
                 &c_node0, &c_walk0, &c_t0, &c_node1, &c_walk1, &c_t1, &c_node2, &c_walk2,
                 &c_t2, &c_prev, &c_flags, &c_pos, &wq,
                 &b_src, &b_dst, &b_ts, &b_keys, &b_vals, &b_flags, &flags, &idx, &v_flags,
