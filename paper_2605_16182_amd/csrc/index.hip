@@ -463,8 +463,10 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
     const int64_t m_old = g->m;
     if (evicting && evicted == m_old) {
         if (nv_reset(g, err) != TW_OK) return err.code;
-        if (nv_collect(g, q_src, q_dst, q_ts, kept, 0, 0, err) != TW_OK) return err.code;
-    } else if (nv_collect(g, q_src, q_dst, q_ts, kept, g->e_base, evicted, err) != TW_OK) {
+        if (nv_collect(g, q_src, q_dst, q_ts, kept, bmin, bmax, 0, 0, err) != TW_OK)
+            return err.code;
+    } else if (nv_collect(g, q_src, q_dst, q_ts, kept, bmin, bmax, g->e_base, evicted, err) !=
+               TW_OK) {
         return err.code;
     }
 
@@ -617,7 +619,8 @@ tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& e
         const int64_t m_old = g->m, gg_old = g->Gg;
         if (ev == m_old) {
             if (nv_reset(g, err) != TW_OK) return err.code;
-        } else if (nv_collect(g, nullptr, nullptr, nullptr, 0, g->e_base, ev, err) != TW_OK) {
+        } else if (nv_collect(g, nullptr, nullptr, nullptr, 0, 0, 0, g->e_base, ev, err) !=
+                   TW_OK) {
             return err.code;
         }
         g->e_base += ev;

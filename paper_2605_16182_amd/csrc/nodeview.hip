@@ -192,13 +192,44 @@ __global__ void k_active_flags(const NodeRec* __restrict__ rec, int64_t V,
 
 // ------------------------------------------------------------- jobs
 
+struct Elem {
+    int32_t dst;
+    int64_t ts;
+};
+
+// The source-sorted batch: (dst, ts) arrays, or one packed word per record,
+// (ts - base) << 32 | dst, when the batch's time span fits 32 bits (ts then
+// holds the words).
+struct BatchRuns {
+    const int32_t* dst;
+    const int64_t* ts;
+    int64_t base;
+    int packed;
+
+    __device__ __forceinline__ int64_t t(uint32_t i) const {
+        return packed ? base + (int64_t)((uint64_t)ts[i] >> 32) : ts[i];
+    }
+    __device__ __forceinline__ Elem elem(uint32_t i) const {
+        if (packed) {
+            const uint64_t w = (uint64_t)ts[i];
+            return Elem{(int32_t)(uint32_t)w, base + (int64_t)(w >> 32)};
+        }
+        return Elem{dst[i], ts[i]};
+    }
+};
+
+BatchRuns batch_runs(const tw_graph* g) {
+    return BatchRuns{g->bs_dst.as<int32_t>(), g->bs_ts.as<int64_t>(), g->bs_base,
+                     g->bs_packed ? 1 : 0};
+}
+
 // Plan of every job: eviction of the node's groups older than cut, then the
 // kind, the written edge count and the slots a new segment needs.
 __global__ void k_job_setup(const uint32_t* __restrict__ c_node, const uint32_t* __restrict__ c_bf,
                             const uint32_t* __restrict__ c_be, int64_t nj,
                             const NodeRec* __restrict__ rec, const SegRec* __restrict__ seg,
                             const GroupRec* __restrict__ ng, const uint32_t* __restrict__ fence,
-                            const int64_t* __restrict__ bts,
+                            const BatchRuns b,
                             int evicting, int64_t cut, int rewrite_all, uint32_t gen,
                             Job* __restrict__ jobs, uint32_t* __restrict__ cnt,
                             uint32_t* __restrict__ req_e, uint32_t* __restrict__ req_g,
@@ -230,15 +261,16 @@ __global__ void k_job_setup(const uint32_t* __restrict__ c_node, const uint32_t*
     J.f0 = sg.f0;
     uint32_t c = 0, re = 0, rg = 0, rf = 0;
     if ((k > 0 || rewrite_all) && ne + k > 0) {
-        const bool after = ne == 0 || k == 0 || bts[J.bf] >= J.t_last;
+        const bool after = ne == 0 || k == 0 || b.t(J.bf) >= J.t_last;
         // an append keeps the segment's key base and shift: its last
         // timestamp must still have a key below UINT32_MAX
         bool keys_fit = true;
         if (has_seg && ne > 0 && k > 0 && fence_cap(seg_groups(sg.gcode)) > 0) {
             J.kbase = r.kbase;
             J.kshift = rec_shift(r.lv);
-            keys_fit = bts[J.be - 1] >= J.kbase &&
-                       ((uint64_t)(bts[J.be - 1] - J.kbase) >> J.kshift) < 0xFFFFFFFFull;
+            const int64_t t_end = b.t(J.be - 1);
+            keys_fit = t_end >= J.kbase &&
+                       ((uint64_t)(t_end - J.kbase) >> J.kshift) < 0xFFFFFFFFull;
         }
         if (!rewrite_all && has_seg && ne > 0 && after && keys_fit &&
             (uint64_t)J.oe + k <= (uint64_t)sg.e0 + sg.ecap &&
@@ -279,8 +311,8 @@ __global__ void k_job_setup(const uint32_t* __restrict__ c_node, const uint32_t*
                 hi = r.t_last;
             }
             if (k > 0) {
-                lo = std::min(lo, bts[J.bf]);
-                hi = std::max(hi, bts[J.be - 1]);
+                lo = std::min(lo, b.t(J.bf));
+                hi = std::max(hi, b.t(J.be - 1));
             }
             J.kbase = lo;
             J.kshift = fence_shift((uint64_t)(hi - lo));
@@ -309,26 +341,22 @@ __global__ void k_job_place(Job* __restrict__ jobs, int64_t nj, const uint32_t* 
     jobs[j] = J;
 }
 
-struct Elem {
-    int32_t dst;
-    int64_t ts;
-};
 
 // Element i of a merging job's run (stable merge of the surviving old run
 // and the batch run, old first on equal timestamps): returns true when it is
 // old element *k, else batch element *k.
 __device__ __forceinline__ bool merge_pick(const Job& J, uint32_t i,
                                            const int64_t* __restrict__ ots,
-                                           const int64_t* __restrict__ bts, uint32_t* k) {
+                                           const BatchRuns& bt, uint32_t* k) {
     const uint32_t na = J.oe - J.ob, nb = J.be - J.bf;
     // a = old elements among the first i outputs
     uint32_t lo = i > nb ? i - nb : 0, hi = i < na ? i : na;
     while (lo < hi) {
         const uint32_t a = lo + ((hi - lo) >> 1);
-        if (ots[J.ob + a] <= bts[J.bf + (i - a - 1)]) lo = a + 1; else hi = a;
+        if (ots[J.ob + a] <= bt.t(J.bf + (i - a - 1))) lo = a + 1; else hi = a;
     }
     const uint32_t a = lo, b = i - lo;
-    if (a < na && (b >= nb || ots[J.ob + a] <= bts[J.bf + b])) {
+    if (a < na && (b >= nb || ots[J.ob + a] <= bt.t(J.bf + b))) {
         *k = a;
         return true;
     }
@@ -339,27 +367,26 @@ __device__ __forceinline__ bool merge_pick(const Job& J, uint32_t i,
 // element i of job J's written run
 __device__ __forceinline__ Elem job_elem(const Job& J, uint32_t i, const int32_t* __restrict__ odst,
                                          const int64_t* __restrict__ ots,
-                                         const int32_t* __restrict__ bdst,
-                                         const int64_t* __restrict__ bts) {
-    if (J.kind == JOB_APPEND) return Elem{bdst[J.bf + i], bts[J.bf + i]};
+                                         const BatchRuns& bt) {
+    if (J.kind == JOB_APPEND) return bt.elem(J.bf + i);
     const uint32_t na = J.oe - J.ob;
     if (!J.merge) {
         if (i < na) return Elem{odst[J.ob + i], ots[J.ob + i]};
-        return Elem{bdst[J.bf + i - na], bts[J.bf + i - na]};
+        return bt.elem(J.bf + i - na);
     }
     uint32_t k;
-    if (merge_pick(J, i, ots, bts, &k)) return Elem{odst[J.ob + k], ots[J.ob + k]};
-    return Elem{bdst[J.bf + k], bts[J.bf + k]};
+    if (merge_pick(J, i, ots, bt, &k)) return Elem{odst[J.ob + k], ots[J.ob + k]};
+    return bt.elem(J.bf + k);
 }
 
 // timestamp of element i of job J's written run
 __device__ __forceinline__ int64_t job_ts(const Job& J, uint32_t i, const int64_t* __restrict__ ots,
-                                          const int64_t* __restrict__ bts) {
-    if (J.kind == JOB_APPEND) return bts[J.bf + i];
+                                          const BatchRuns& bt) {
+    if (J.kind == JOB_APPEND) return bt.t(J.bf + i);
     const uint32_t na = J.oe - J.ob;
-    if (!J.merge) return i < na ? ots[J.ob + i] : bts[J.bf + i - na];
+    if (!J.merge) return i < na ? ots[J.ob + i] : bt.t(J.bf + i - na);
     uint32_t k;
-    return merge_pick(J, i, ots, bts, &k) ? ots[J.ob + k] : bts[J.bf + k];
+    return merge_pick(J, i, ots, bt, &k) ? ots[J.ob + k] : bt.t(J.bf + k);
 }
 
 // last j in [lo, hi] with off[j] <= t (off[lo] <= t)
@@ -427,8 +454,7 @@ __global__ void __launch_bounds__(T) k_job_flags(const Job* __restrict__ jobs,
                                                  const uint32_t* __restrict__ off,
                                                  const uint32_t* __restrict__ tf,
                                                  int64_t total, const int64_t* __restrict__ ots,
-                                                 const int64_t* __restrict__ bts,
-                                                 uint64_t* __restrict__ bm,
+                                                 const BatchRuns bt, uint64_t* __restrict__ bm,
                                                  uint32_t* __restrict__ tcnt) {
     __shared__ uint32_t soff[OFF_LDS];
     __shared__ uint32_t wsum[T / 64];
@@ -445,9 +471,9 @@ __global__ void __launch_bounds__(T) k_job_flags(const Job* __restrict__ jobs,
             const uint32_t j = tj.job(off, soff, (uint64_t)t);
             const Job J = jobs[j];
             const uint32_t i = (uint32_t)(t - tj.start(off, soff, j));
-            const int64_t x = job_ts(J, i, ots, bts);
+            const int64_t x = job_ts(J, i, ots, bt);
             if (i == 0) start = J.kind != JOB_APPEND || x != J.t_last;
-            else start = x != job_ts(J, i - 1, ots, bts);
+            else start = x != job_ts(J, i - 1, ots, bt);
         }
         const uint64_t b = __ballot(start);
         if (lane == 0 && t0 < total) bm[t0 >> 6] = b;
@@ -486,8 +512,7 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
                                                  const uint32_t* __restrict__ tf,
                                                  int64_t total, const int32_t* __restrict__ odst,
                                                  const int64_t* __restrict__ ots,
-                                                 const int32_t* __restrict__ bdst,
-                                                 const int64_t* __restrict__ bts,
+                                                 const BatchRuns bt,
                                                  const uint64_t* __restrict__ bm,
                                                  const uint32_t* __restrict__ toff,
                                                  uint32_t* __restrict__ pref,
@@ -543,7 +568,7 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
         const Job J = jobs[j];
         const uint32_t jb = tj.start(off, soff, j);
         const uint32_t i = (uint32_t)(t - jb);
-        const Elem e = job_elem(J, i, odst, ots, bdst, bts);
+        const Elem e = job_elem(J, i, odst, ots, bt);
         const uint32_t pos = J.e_at + i;
         ndst[pos] = e.dst;
         nts[pos] = e.ts;
@@ -848,7 +873,8 @@ tw_status nv_reset(tw_graph* g, Error& err) {
 }
 
 tw_status nv_collect(tw_graph* g, const int32_t* q_src, const int32_t* q_dst, const int64_t* q_ts,
-                     int64_t kept, int64_t ev_from, int64_t ev_n, Error& err) {
+                     int64_t kept, int64_t ts_lo, int64_t ts_hi, int64_t ev_from, int64_t ev_n,
+                     Error& err) {
     hipStream_t s = g->stream;
     if (++g->epoch == 0) {  // wrapped: clear the marks
         hipLaunchKernelGGL(k_zero_u32, grid_for(g->V), dim3(T), 0, s, g->touched.as<uint32_t>(),
@@ -868,16 +894,27 @@ tw_status nv_collect(tw_graph* g, const int32_t* q_src, const int32_t* q_dst, co
     uint32_t* pos = g->idx.as<uint32_t>();
     uint32_t* sl_runs = slot(g, SLOT_U32_RUNS);
     uint32_t* sl_ev = slot(g, SLOT_U32_EV_NODES);
+    // a batch whose timestamps span less than 2^32 travels through the sort
+    // as one packed word per record instead of 12 bytes
+    g->bs_packed = kept > 0 && ts_hi >= ts_lo && (uint64_t)ts_hi - (uint64_t)ts_lo < (1ull << 32);
+    g->bs_base = g->bs_packed ? ts_lo : 0;
     TW_HIP(ensure(g->bs_src, sizeof(uint32_t) * (kept + 1)));
-    TW_HIP(ensure(g->bs_dst, sizeof(int32_t) * (kept + 1)));
+    if (!g->bs_packed) TW_HIP(ensure(g->bs_dst, sizeof(int32_t) * (kept + 1)));
     TW_HIP(ensure(g->bs_ts, sizeof(int64_t) * (kept + 1)));
     if (kept > 0) {
         uint32_t* bsrc = g->bs_src.as<uint32_t>();
-        TW_HIP(radix_sort_u32_kv(reinterpret_cast<const uint32_t*>(q_src),
-                                 reinterpret_cast<const uint32_t*>(q_dst),
-                                 reinterpret_cast<const uint64_t*>(q_ts), bsrc,
-                                 g->bs_dst.as<uint32_t>(), g->bs_ts.as<uint64_t>(), kept, 0,
-                                 bits_for((uint64_t)(g->V - 1)), g->ws, s));
+        const int vbits = bits_for((uint64_t)(g->V - 1));
+        if (g->bs_packed)
+            TW_HIP(radix_sort_u32_pack(reinterpret_cast<const uint32_t*>(q_src),
+                                       reinterpret_cast<const uint32_t*>(q_dst),
+                                       reinterpret_cast<const uint64_t*>(q_ts), (uint64_t)ts_lo,
+                                       bsrc, g->bs_ts.as<uint64_t>(), kept, 0, vbits, g->ws, s));
+        else
+            TW_HIP(radix_sort_u32_kv(reinterpret_cast<const uint32_t*>(q_src),
+                                     reinterpret_cast<const uint32_t*>(q_dst),
+                                     reinterpret_cast<const uint64_t*>(q_ts), bsrc,
+                                     g->bs_dst.as<uint32_t>(), g->bs_ts.as<uint64_t>(), kept, 0,
+                                     vbits, g->ws, s));
         const RunEndOp op{bsrc,
                           kept,
                           g->epoch,
@@ -927,8 +964,7 @@ tw_status plan_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool re
     hipLaunchKernelGGL(k_job_setup, grid_for(nj), dim3(T), 0, s, g->c_node.as<uint32_t>(),
                        g->c_bf.as<uint32_t>(), g->c_be.as<uint32_t>(), nj, g->rec.as<NodeRec>(),
                        g->seg.as<SegRec>(), g->ng.as<GroupRec>(), g->fence.as<uint32_t>(),
-                       g->bs_ts.as<int64_t>(),
-                       evicting ? 1 : 0, cut, rewrite_all ? 1 : 0, gen, g->jobs.as<Job>(),
+                       batch_runs(g), evicting ? 1 : 0, cut, rewrite_all ? 1 : 0, gen, g->jobs.as<Job>(),
                        g->j_cnt.as<uint32_t>(), g->j_re.as<uint32_t>(), g->j_rg.as<uint32_t>(),
                        g->j_rf.as<uint32_t>());
     TW_HIP(hipGetLastError());
@@ -971,13 +1007,13 @@ tw_status execute_jobs(tw_graph* g, int64_t nj, uint64_t out, const int32_t* sds
     if (out > 0) {
         hipLaunchKernelGGL(k_tile_first, grid_for(nt + 1), dim3(T), 0, s, off, nj, nt, tf);
         hipLaunchKernelGGL(k_job_flags, dim3((unsigned)nt), dim3(T), 0, s, jobs, off, tf,
-                           (int64_t)out, sts, g->bs_ts.as<int64_t>(), bm, tcnt);
+                           (int64_t)out, sts, batch_runs(g), bm, tcnt);
     }
     TW_HIP(scan_exclusive_u32(tcnt, tcnt, nt, tcnt + nt, g->ws, s));
     if (out > 0)
         hipLaunchKernelGGL(k_job_write, dim3((unsigned)nt), dim3(T), 0, s, jobs, off, tf,
-                           (int64_t)out, sdst, sts, g->bs_dst.as<int32_t>(),
-                           g->bs_ts.as<int64_t>(), bm, tcnt, pref, ddst, dts, dng, dfence);
+                           (int64_t)out, sdst, sts, batch_runs(g), bm, tcnt, pref, ddst, dts, dng,
+                           dfence);
     hipLaunchKernelGGL(k_job_finish, grid_for(nj), dim3(T), 0, s, jobs, off, nj, bm, pref,
                        (int64_t)out, tcnt + nt, dng, g->rec.as<NodeRec>(), g->seg.as<SegRec>(),
                        gen, g->j_fw.as<uint32_t>());

@@ -277,13 +277,16 @@ k_rs_hist(const K* __restrict__ keys, int64_t n, int shift, int nbits,
 // The tile is first ordered by digit in LDS, one array at a time, so that
 // consecutive lanes write consecutive slots of each digit's run.
 // W64: the items carry a 64-bit payload (v64); without it the LDS staging
-// area is as wide as the widest of key and 32-bit value.
-template <typename K, bool W64>
+// area is as wide as the widest of key and 32-bit value. PACK (with W64):
+// the 32-bit value and the 64-bit payload (a timestamp) are read and leave
+// packed as one 64-bit payload, (v64 - pack_base) << 32 | val.
+template <typename K, bool W64, bool PACK>
 __global__ void __launch_bounds__(RS_THREADS)
 k_rs_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
              const uint64_t* __restrict__ v64, int64_t n, int shift, int nbits,
              const uint32_t* __restrict__ offs, int64_t nblocks, K* __restrict__ keys_out,
-             uint32_t* __restrict__ vals_out, uint64_t* __restrict__ v64_out) {
+             uint32_t* __restrict__ vals_out, uint64_t* __restrict__ v64_out, uint64_t pack_base) {
+    static_assert(W64 || !PACK, "packing needs the 64-bit payload");
     using Stage = std::conditional_t<W64 || sizeof(K) == 8, uint64_t, uint32_t>;
     __shared__ uint32_t cnt[RS_WAVES][RS_RADIX];  // wave counts, then wave starts
     __shared__ uint32_t lstart[RS_RADIX];         // tile-local first slot of each digit
@@ -310,7 +313,8 @@ k_rs_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
         const int64_t i = wbase + r * 64 + lane;
         k[r] = i < n ? keys[i] : K(0);
         v[r] = (vals && i < n) ? vals[i] : 0u;
-        if constexpr (W64) w2[r] = i < n ? v64[i] : 0ull;
+        if constexpr (PACK) w2[r] = i < n ? ((v64[i] - pack_base) << 32) | v[r] : 0ull;
+        else if constexpr (W64) w2[r] = i < n ? v64[i] : 0ull;
     }
 
     // stable rank of each item among the wavefront's items of its digit
@@ -363,7 +367,7 @@ k_rs_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
             keys_out[gp[r]] = key;
         }
     }
-    if (vals) {
+    if (!PACK && vals) {
         __syncthreads();
         uint32_t* sv = reinterpret_cast<uint32_t*>(stage);
 #pragma unroll
@@ -390,6 +394,18 @@ k_rs_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
     }
 }
 
+// keys copied and (val, v64) packed as in k_rs_scatter<.., PACK>, for sorts
+// with no pass to do it
+template <typename K>
+__global__ void k_pack_payload(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                               const uint64_t* __restrict__ win, int64_t n, uint64_t base,
+                               K* __restrict__ kout, uint64_t* __restrict__ wout) {
+    const int64_t i = (int64_t)blockIdx.x * SCAN_THREADS + threadIdx.x;
+    if (i >= n) return;
+    kout[i] = kin[i];
+    wout[i] = ((win[i] - base) << 32) | vin[i];
+}
+
 // Sort (kin, vin, win) into (kout, vout, wout). Inputs are only read; when
 // they alias the outputs the sort works in place. Passes alternate between
 // the outputs and the workspace buffers, arranged so that the last pass
@@ -398,9 +414,16 @@ k_rs_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
 template <typename K>
 hipError_t radix_sort_impl(const K* kin0, const uint32_t* vin0, const uint64_t* win0, K* kout,
                            uint32_t* vout, uint64_t* wout, int64_t n, int bit_lo, int bit_hi,
-                           Workspace& ws, hipStream_t s) {
+                           Workspace& ws, hipStream_t s, bool pack = false,
+                           uint64_t pack_base = 0) {
     hipError_t e;
     const bool has_v = vout != nullptr, has_w = wout != nullptr;
+    if (pack && (bit_hi <= bit_lo || n <= 1)) {
+        if (n <= 0) return hipSuccess;
+        hipLaunchKernelGGL((k_pack_payload<K>), dim3((unsigned)ceil_div(n, (int64_t)SCAN_THREADS)),
+                           dim3(SCAN_THREADS), 0, s, kin0, vin0, win0, n, pack_base, kout, wout);
+        return hipGetLastError();
+    }
     if (bit_hi <= bit_lo || n <= 1) {
         if (n > 0 && kin0 != kout) {
             if ((e = hipMemcpyAsync(kout, kin0, sizeof(K) * n, hipMemcpyDeviceToDevice, s)))
@@ -440,13 +463,18 @@ hipError_t radix_sort_impl(const K* kin0, const uint32_t* vin0, const uint64_t* 
                            hist, nblocks);
         if ((e = scan_exclusive_u32(hist, hist, 256 * nblocks, nullptr, ws, s)) != hipSuccess)
             return e;
-        if (has_w)
-            hipLaunchKernelGGL((k_rs_scatter<K, true>), dim3(nblocks), dim3(RS_THREADS), 0, s,
-                               ki, has_v ? vi : nullptr, wi, n, sh, nb, hist, nblocks, ko, vo, wo);
+        if (pack && p == 0)
+            hipLaunchKernelGGL((k_rs_scatter<K, true, true>), dim3(nblocks), dim3(RS_THREADS), 0,
+                               s, ki, vi, wi, n, sh, nb, hist, nblocks, ko, nullptr, wo,
+                               pack_base);
+        else if (has_w)
+            hipLaunchKernelGGL((k_rs_scatter<K, true, false>), dim3(nblocks), dim3(RS_THREADS), 0,
+                               s, ki, has_v ? vi : nullptr, wi, n, sh, nb, hist, nblocks, ko, vo,
+                               wo, 0ull);
         else
-            hipLaunchKernelGGL((k_rs_scatter<K, false>), dim3(nblocks), dim3(RS_THREADS), 0, s,
-                               ki, has_v ? vi : nullptr, nullptr, n, sh, nb, hist, nblocks, ko, vo,
-                               nullptr);
+            hipLaunchKernelGGL((k_rs_scatter<K, false, false>), dim3(nblocks), dim3(RS_THREADS),
+                               0, s, ki, has_v ? vi : nullptr, nullptr, n, sh, nb, hist, nblocks,
+                               ko, vo, nullptr, 0ull);
         ki = ko;
         vi = vo;
         wi = wo;
@@ -569,6 +597,13 @@ hipError_t radix_sort_u32_kv(const uint32_t* kin, const uint32_t* vin, const uin
                              uint32_t* kout, uint32_t* vout, uint64_t* wout, int64_t n, int bit_lo,
                              int bit_hi, Workspace& ws, hipStream_t s) {
     return radix_sort_impl<uint32_t>(kin, vin, win, kout, vout, wout, n, bit_lo, bit_hi, ws, s);
+}
+
+hipError_t radix_sort_u32_pack(const uint32_t* kin, const uint32_t* vin, const uint64_t* win,
+                               uint64_t base, uint32_t* kout, uint64_t* pout, int64_t n,
+                               int bit_lo, int bit_hi, Workspace& ws, hipStream_t s) {
+    return radix_sort_impl<uint32_t>(kin, vin, win, kout, nullptr, pout, n, bit_lo, bit_hi, ws, s,
+                                     true, base);
 }
 
 }  // namespace tw

@@ -216,6 +216,12 @@ hipError_t radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bit_lo,
 hipError_t radix_sort_u32_kv(const uint32_t* kin, const uint32_t* vin, const uint64_t* win,
                              uint32_t* kout, uint32_t* vout, uint64_t* wout, int64_t n, int bit_lo,
                              int bit_hi, Workspace& ws, hipStream_t s);
+// The same sort with the 32-bit and 64-bit payloads leaving packed as one:
+// pout[i] = (win - base) << 32 | vin (win - base must fit 32 bits). Fewer
+// bytes move in every pass after the first.
+hipError_t radix_sort_u32_pack(const uint32_t* kin, const uint32_t* vin, const uint64_t* win,
+                               uint64_t base, uint32_t* kout, uint64_t* pout, int64_t n,
+                               int bit_lo, int bit_hi, Workspace& ws, hipStream_t s);
 
 // Bits needed to represent values in [0, x].
 inline int bits_for(uint64_t x) {
@@ -267,6 +273,8 @@ struct tw_graph {
     uint32_t epoch = 0;
     // node-view jobs (one per touched node) and their temporaries
     tw::DevBuf bs_src, bs_dst, bs_ts;  // batch sorted by source
+    bool bs_packed = false;            // bs_ts holds (ts - bs_base) << 32 | dst
+    int64_t bs_base = 0;
     tw::DevBuf q_src, q_dst, q_ts;     // batch sorted by timestamp (unsorted input)
     tw::DevBuf c_node, c_bf, c_be;     // job candidates: node, batch run
     tw::DevBuf jobs, j_cnt, j_off, j_re, j_rg, j_rf, j_fw;
@@ -343,8 +351,10 @@ inline const uint32_t* host_flags(const tw_graph* g) {
 // jobs: the batch's source nodes, then the nodes that lose edges to the
 // eviction of window positions [ev_from, ev_from + ev_n) of the timestamp
 // view, which must still hold the evicted records.
+// [ts_lo, ts_hi] bounds the kept records' timestamps.
 tw_status nv_collect(tw_graph* g, const int32_t* q_src, const int32_t* q_dst, const int64_t* q_ts,
-                     int64_t kept, int64_t ev_from, int64_t ev_n, Error& err);
+                     int64_t kept, int64_t ts_lo, int64_t ts_hi, int64_t ev_from, int64_t ev_n,
+                     Error& err);
 // Apply the collected jobs: evict edges older than cut (when evicting),
 // append or rewrite every job node's run, its groups, fence and record.
 tw_status nv_apply(tw_graph* g, bool evicting, int64_t cut, Error& err);

@@ -54,6 +54,39 @@ def test_stream_index_parity_small(directed, window):
     g.close()
 
 
+@pytest.mark.parametrize("directed", [True, False])
+def test_wide_and_narrow_timestamp_spans(directed):
+    # a batch whose timestamps span 2^32 or more is sorted by source with
+    # 12-byte records, a narrower one as packed 8-byte words; mixed batches
+    # (late ones merged into the runs) must give the same index and walks
+    torch, tw = gpu_or_skip()
+    rng = np.random.default_rng(23 + directed)
+    V = 97
+    g = tw.Graph(V, directed=directed)
+    og = oracle.OracleGraph(V, directed=directed)
+    t_base = 1 << 40
+    for b in range(8):
+        n = int(rng.integers(200, 3000))
+        src = rng.integers(0, V, n).astype(np.int32)
+        dst = rng.integers(0, V, n).astype(np.int32)
+        wide = b % 3 != 1
+        span = (1 << 34) if wide else 5000
+        ts = (t_base + rng.integers(-span, span, n)).astype(np.int64)
+        t_base += span // 2
+        s_, d_, t_ = to_dev(torch, src, dst, ts)
+        assert g.ingest_batch(s_, d_, t_) == og.ingest_batch(src, dst, ts), b
+        _views_equal(g, og)
+    W, L = 4000, 12
+    for kind in ("uniform", "linear"):
+        nodes, tts, lens = g.sample_walks(W, L, hop_bias=kind, start_bias=kind, seed=5)
+        g.sync()
+        r = og.sample_walks(W, L, hop_bias=kind, start_bias=kind, seed=5)
+        assert np.array_equal(lens.cpu().numpy(), r["len"])
+        assert np.array_equal(nodes.cpu().numpy(), r["nodes"])
+        assert np.array_equal(tts.cpu().numpy(), r["ts"])
+    g.close()
+
+
 def test_index_parity_multi_tile_ragged():
     # several radix / scan tiles (4096) with a ragged tail, duplicate timestamps
     torch, tw = gpu_or_skip()
