@@ -10,7 +10,13 @@
 // writes several times over.
 //
 // An Op provides
+//   static constexpr bool kHoist;    // evaluate every round's flag first
 //   __device__ bool flag(int64_t i) const;                  // i < n
+// With kHoist, flag is also evaluated (and its result dropped) at i = n - 1
+// for the lanes past the end, so that every round's loads issue
+// unconditionally and stay in flight together: flag must then read only
+// inside [0, n) without branching around its loads. (This pays for 4-byte
+// flag inputs; with 8-byte ones the rounds already keep the memory busy.)
 //   __device__ void emit(int64_t i, uint32_t k) const;      // flagged i
 //   __device__ void end(int64_t n, uint32_t total) const;   // once, after all
 // end() runs in pass two on the lane holding item n - 1.
@@ -33,9 +39,20 @@ k_ct_count(const Op op, int64_t n, uint32_t* __restrict__ cnt) {
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t wb = (int64_t)tile * CT_TILE + (int64_t)wave * CT_WAVE;
     uint32_t c = 0;
-    for (int r = 0; r < CT_ROUNDS; ++r) {
-        const int64_t i = wb + r * 64 + lane;
-        c += (uint32_t)__popcll(__ballot(i < n && op.flag(i)));
+    if constexpr (Op::kHoist) {
+        bool f[CT_ROUNDS];
+#pragma unroll
+        for (int r = 0; r < CT_ROUNDS; ++r) {
+            const int64_t i = wb + r * 64 + lane;
+            f[r] = op.flag(i < n ? i : n - 1) && i < n;
+        }
+#pragma unroll
+        for (int r = 0; r < CT_ROUNDS; ++r) c += (uint32_t)__popcll(__ballot(f[r]));
+    } else {
+        for (int r = 0; r < CT_ROUNDS; ++r) {
+            const int64_t i = wb + r * 64 + lane;
+            c += (uint32_t)__popcll(__ballot(i < n && op.flag(i)));
+        }
     }
     if (lane == 0) wsum[wave] = c;
     __syncthreads();
@@ -56,11 +73,21 @@ k_ct_emit(const Op op, int64_t n, const uint32_t* __restrict__ off) {
     const int64_t wb = (int64_t)tile * CT_TILE + (int64_t)wave * CT_WAVE;
     const uint64_t lower = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     uint32_t bits = 0, c = 0;  // this lane's flags (bit r: round r); the wave's count
-    for (int r = 0; r < CT_ROUNDS; ++r) {
-        const int64_t i = wb + r * 64 + lane;
-        const bool f = i < n && op.flag(i);
-        bits |= (uint32_t)f << r;
-        c += (uint32_t)__popcll(__ballot(f));
+    if constexpr (Op::kHoist) {
+#pragma unroll
+        for (int r = 0; r < CT_ROUNDS; ++r) {
+            const int64_t i = wb + r * 64 + lane;
+            bits |= (uint32_t)(op.flag(i < n ? i : n - 1) && i < n) << r;
+        }
+#pragma unroll
+        for (int r = 0; r < CT_ROUNDS; ++r) c += (uint32_t)__popcll(__ballot((bits >> r) & 1u));
+    } else {
+        for (int r = 0; r < CT_ROUNDS; ++r) {
+            const int64_t i = wb + r * 64 + lane;
+            const bool f = i < n && op.flag(i);
+            bits |= (uint32_t)f << r;
+            c += (uint32_t)__popcll(__ballot(f));
+        }
     }
     if (lane == 0) wsum[wave] = c;
     __syncthreads();

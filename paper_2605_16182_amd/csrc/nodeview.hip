@@ -123,7 +123,11 @@ struct RunEndOp {
     uint32_t epoch;
     uint32_t* touched;
     uint32_t *c_node, *c_bf, *c_be;
-    __device__ bool flag(int64_t i) const { return i + 1 == n || src[i + 1] != src[i]; }
+    static constexpr bool kHoist = true;
+    __device__ bool flag(int64_t i) const {
+        const uint32_t a = src[i], b = src[i + 1 < n ? i + 1 : i];  // no branch around loads
+        return i + 1 == n || a != b;
+    }
     __device__ void emit(int64_t i, uint32_t k) const {
         const uint32_t v = src[i];
         c_node[k] = v;
@@ -169,6 +173,7 @@ struct EvictJobOp {
     const int32_t* nodes;
     const uint32_t* runs;
     uint32_t *c_node, *c_bf, *c_be;
+    static constexpr bool kHoist = true;
     __device__ bool flag(int64_t i) const { return flags[i] != 0; }
     __device__ void emit(int64_t i, uint32_t k) const {
         const uint32_t j = *runs + k;

@@ -197,6 +197,7 @@ struct GroupStartOp {
     uint32_t pos_base;
     int64_t* g_ts;
     uint32_t* g_off;
+    static constexpr bool kHoist = false;
     __device__ bool flag(int64_t i) const {
         return i == 0 ? (!has_last || ts[0] != last_ts) : ts[i] != ts[i - 1];
     }
