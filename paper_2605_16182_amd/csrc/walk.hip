@@ -226,9 +226,13 @@ __global__ void k_fill_outputs(int32_t* __restrict__ nodes, int64_t* __restrict_
 }
 
 // One full walk per thread: the full-walk baseline (Sec. "The Full-Walk
-// Baseline").
+// Baseline"). The walk is bound by dependent random loads, so waves in flight
+// count: the exponential pickers' FP64 code is held to 5 waves per SIMD (a
+// few registers spill), node2vec (more live state) keeps its own allocation.
 template <int HK, int SK>
-__global__ void __launch_bounds__(WALK_THREADS) k_walk_full(const WalkArgs a) {
+__global__ void __launch_bounds__(WALK_THREADS)
+__attribute__((amdgpu_waves_per_eu(HK == TW_NODE2VEC || HK < 0 ? 1 : 5)))
+k_walk_full(const WalkArgs a) {
     const int64_t w = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
     if (w >= a.num_walks) return;
     const uint64_t id = a.base + (uint64_t)w;
