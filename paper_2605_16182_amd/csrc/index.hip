@@ -86,18 +86,6 @@ __global__ void k_init_minmax(unsigned long long* scalars, uint32_t* err, uint32
     *unsorted = 0u;
 }
 
-// first index of the sorted ts[0..n) with ts >= cut, and ts at that index
-__global__ void k_sorted_cut(const int64_t* __restrict__ ts, int64_t n, int64_t cut,
-                             uint32_t* pos, int64_t* first_ts) {
-    int64_t lo = 0, hi = n;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (ts[mid] < cut) lo = mid + 1; else hi = mid;
-    }
-    *pos = (uint32_t)lo;
-    *first_ts = lo < n ? ts[lo] : INT64_MAX;
-}
-
 // keep flag of staged records for the late-edge drop
 __global__ void k_keep_flags(const int64_t* __restrict__ ts, int64_t n, int64_t cut,
                              uint32_t* __restrict__ flags) {
@@ -138,6 +126,62 @@ __global__ void k_lower_bound(const int64_t* __restrict__ ts, int64_t n, int64_t
         if (ts[mid] < cut) lo = mid + 1; else hi = mid;
     }
     *out = (uint32_t)lo;
+}
+
+// The window cut of an ingest from the staged batch's range (the same
+// arithmetic as the host's once it reads the range back), and in parallel
+// the three searches it needs: thread 0 the late prefix of a sorted batch
+// (its length and first kept timestamp), thread 1 the evicted prefix of the
+// window, thread 2 that of the global groups. Each writes its default (no
+// late record, nothing evicted) when its condition does not hold, so one
+// read-back serves the whole decision.
+__global__ void k_cut_counts(const unsigned long long* __restrict__ mm,
+                             const uint32_t* __restrict__ unsorted, int has_time, int64_t t_now,
+                             int64_t window, const int64_t* __restrict__ b_ts, int64_t B,
+                             const int64_t* __restrict__ w_ts, int64_t m, int64_t t_min,
+                             const int64_t* __restrict__ gg_ts, int64_t Gg, uint32_t* sc_kept,
+                             int64_t* first_kept, uint32_t* sc_ev, uint32_t* sc_gev) {
+    const int64_t bmin = unord(mm[0]), bmax = unord(mm[1]);
+    const int64_t now = B > 0 ? (has_time ? (t_now > bmax ? t_now : bmax) : bmax) : t_now;
+    const bool timed = has_time || B > 0;
+    const bool windowed = window > 0 && timed;
+    const int64_t cut = !windowed ? INT64_MIN
+                        : (now < INT64_MIN + window ? INT64_MIN : now - window);
+    const int64_t* ts = nullptr;
+    int64_t n = 0;
+    uint32_t* out = nullptr;
+    if (threadIdx.x == 0) {
+        if (windowed && B > 0 && bmin < cut && *unsorted == 0u) {
+            ts = b_ts;
+            n = B;
+        } else {
+            *sc_kept = 0u;
+            *first_kept = bmin;
+            return;
+        }
+    } else if (threadIdx.x == 1 || threadIdx.x == 2) {
+        out = threadIdx.x == 1 ? sc_ev : sc_gev;
+        if (windowed && m > 0 && t_min < cut) {
+            ts = threadIdx.x == 1 ? w_ts : gg_ts;
+            n = threadIdx.x == 1 ? m : Gg;
+        } else {
+            *out = 0u;
+            return;
+        }
+    } else {
+        return;
+    }
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (ts[mid] < cut) lo = mid + 1; else hi = mid;
+    }
+    if (threadIdx.x == 0) {
+        *sc_kept = (uint32_t)lo;
+        *first_kept = lo < n ? ts[lo] : INT64_MAX;
+    } else {
+        *out = (uint32_t)lo;
+    }
 }
 
 // Merge-path merge of A = old window (from a_begin) and B = sorted batch.
@@ -359,6 +403,18 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
         hipLaunchKernelGGL(k_stage, dim3((unsigned)std::min<int64_t>(ceil_div(n, T), 2048)),
                            dim3(T), 0, s, src, dst, ts, n, g->V, g->directed ? 1 : 0, s_src, s_dst,
                            s_ts, errf + 1, mm, unsorted);
+    // the window's cut and its searches run on the device before the first
+    // read-back (results for the cases that need them; defaults otherwise)
+    uint32_t* sc_kept = u32_slot(g, SLOT_U32_KEPT);
+    uint32_t* sc_ev = u32_slot(g, SLOT_U32_EVICTED);
+    uint32_t* sc_gev = u32_slot(g, SLOT_U32_GG_EVICTED);
+    int64_t* first_kept = i64_slot(g, SLOT_I64_FIRST_KEPT);
+    if (g->window > 0)
+        hipLaunchKernelGGL(k_cut_counts, dim3(1), dim3(64), 0, s, mm, unsorted,
+                           g->has_time ? 1 : 0, g->t_now, g->window, s_ts, B,
+                           g->e_ts.as<int64_t>() + g->e_base, g->m, g->t_min,
+                           g->gg_ts.as<int64_t>() + g->gg_base, g->Gg, sc_kept, first_kept, sc_ev,
+                           sc_gev);
     TW_HIP(hipGetLastError());
     if (pull_scalars(g, true, err) != TW_OK) return err.code;
     const uint64_t hmm[2] = {(uint64_t)host_i64(g, SLOT_I64_MINMAX),
@@ -381,10 +437,6 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
     const bool windowed = g->window > 0 && g->has_time;
     int64_t cut = INT64_MIN;
     if (windowed) cut = (g->t_now < INT64_MIN + g->window) ? INT64_MIN : g->t_now - g->window;
-    uint32_t* sc_kept = u32_slot(g, SLOT_U32_KEPT);
-    uint32_t* sc_ev = u32_slot(g, SLOT_U32_EVICTED);
-    uint32_t* sc_gev = u32_slot(g, SLOT_U32_GG_EVICTED);
-    int64_t* first_kept = i64_slot(g, SLOT_I64_FIRST_KEPT);
     const bool drop = windowed && B > 0 && bmin < cut;
     const bool evicting = windowed && g->m > 0 && g->t_min < cut;
     int64_t kept = B, evicted = 0, gg_evicted = 0, batch_first = bmin, drop_lo = 0;
@@ -392,9 +444,10 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
     uint64_t* keys = nullptr;
     uint32_t* vals = nullptr;
     if (drop && sorted) {
-        // late records of a sorted batch are a prefix
-        hipLaunchKernelGGL(k_sorted_cut, dim3(1), dim3(1), 0, s, s_ts, B, cut, sc_kept,
-                           first_kept);
+        // late records of a sorted batch are a prefix (its length came back)
+        drop_lo = host_u32(g, SLOT_U32_KEPT);
+        kept = B - drop_lo;
+        batch_first = host_i64(g, SLOT_I64_FIRST_KEPT);
     } else if (!sorted && B > 0) {
         TW_HIP(ensure(g->b_keys, sizeof(uint64_t) * (B + 1)));
         TW_HIP(ensure(g->b_vals, sizeof(uint32_t) * (B + 1)));
@@ -415,29 +468,14 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
         }
     }
     if (evicting) {
-        hipLaunchKernelGGL(k_lower_bound, dim3(1), dim3(1), 0, s, g->e_ts.as<int64_t>() + g->e_base,
-                           g->m, cut, sc_ev);
-        hipLaunchKernelGGL(k_lower_bound, dim3(1), dim3(1), 0, s,
-                           g->gg_ts.as<int64_t>() + g->gg_base, g->Gg, cut, sc_gev);
+        evicted = host_u32(g, SLOT_U32_EVICTED);
+        gg_evicted = host_u32(g, SLOT_U32_GG_EVICTED);
     }
     TW_HIP(hipGetLastError());
-    if (drop || evicting) {
+    if (drop && !sorted) {
         if (pull_scalars(g, false, err) != TW_OK) return err.code;
-        const uint32_t h2[2] = {host_u32(g, SLOT_U32_KEPT), host_u32(g, SLOT_U32_EVICTED)};
-        const uint32_t hg = host_u32(g, SLOT_U32_GG_EVICTED);
-        const int64_t hf = host_i64(g, SLOT_I64_FIRST_KEPT);
-        if (drop && sorted) {
-            drop_lo = h2[0];
-            kept = B - drop_lo;
-            batch_first = hf;
-        } else if (drop) {
-            kept = h2[0];
-            batch_first = cut;  // a lower bound of the kept records
-        }
-        if (evicting) {
-            evicted = h2[1];
-            gg_evicted = hg;
-        }
+        kept = host_u32(g, SLOT_U32_KEPT);
+        batch_first = cut;  // a lower bound of the kept records
     }
 
     // the kept batch records in timestamp order (stable)
