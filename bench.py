@@ -9,7 +9,8 @@ Default workload ("single"): directed graph, 2M nodes, 100M edges, source and
 destination Zipf(1.2), sorted Poisson arrivals (mean gap 10); 4M walks of at
 most 80 nodes, exponential start and hop bias with tau = 0.1 x time span.
 
-Prints one JSON line (see the design doc for every field).
+Prints one JSON line: the metric and its value, the timed steps, the
+workload, the rooflines of the dominant kernels and the oracle's baseline.
 """
 from __future__ import annotations
 
@@ -556,7 +557,7 @@ def run_serve(args, torch, tw, w, dev, gather_rate):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
