@@ -7,8 +7,10 @@
 //   timestamp view (the edge store):   e_src e_dst e_ts, the window at
 //                                      [e_base, e_base + m) of buffers with
 //                                      room to append
-//   its timestamp groups:              gg_ts gg_off at [gg_base, gg_base + Gg],
-//                                      offsets are edge-store positions
+//   its timestamp groups:              gg_off at [gg_base, gg_base + Gg],
+//                                      edge-store positions of each group's
+//                                      first record (its timestamp is that
+//                                      record's), then the end
 //
 // One ingest: stage (validate, mirror, min/max, sortedness) -> late drop and
 // eviction counts -> (unsorted batch only) stable radix sort by timestamp ->
@@ -117,70 +119,81 @@ __global__ void k_gather_batch(const uint32_t* __restrict__ vals, int64_t n,
     o_ts[i] = s_ts[j];
 }
 
-// number of entries of ts[0..n) below cut, into *out
-__global__ void k_lower_bound(const int64_t* __restrict__ ts, int64_t n, int64_t cut,
-                              uint32_t* out) {
-    int64_t lo = 0, hi = n;
+// timestamps of the global groups (their first records')
+__global__ void k_group_ts(const int64_t* __restrict__ e_ts, const uint32_t* __restrict__ gg_off,
+                           int64_t Gg, int64_t* __restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (k < Gg) out[k] = e_ts[gg_off[k]];
+}
+
+// Evicted prefix of the window (records with ts < cut: ev) and of its
+// global groups (groups whose first record is evicted: the groups end at
+// record boundaries of equal timestamps, so these are the groups that start
+// before w_base + ev).
+__device__ void evicted_prefix(const int64_t* __restrict__ w_ts, int64_t m, int64_t cut,
+                               const uint32_t* __restrict__ gg_off, int64_t Gg, int64_t w_base,
+                               uint32_t* sc_ev, uint32_t* sc_gev) {
+    int64_t lo = 0, hi = m;
     while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (ts[mid] < cut) lo = mid + 1; else hi = mid;
+        const int64_t mid = (lo + hi) >> 1;
+        if (w_ts[mid] < cut) lo = mid + 1; else hi = mid;
     }
-    *out = (uint32_t)lo;
+    const uint64_t end = (uint64_t)(w_base + lo);
+    int64_t a = 0, b = Gg;
+    while (a < b) {
+        const int64_t mid = (a + b) >> 1;
+        if ((uint64_t)gg_off[mid] < end) a = mid + 1; else b = mid;
+    }
+    *sc_ev = (uint32_t)lo;
+    *sc_gev = (uint32_t)a;
+}
+
+__global__ void k_evict_counts(const int64_t* __restrict__ w_ts, int64_t m, int64_t cut,
+                               const uint32_t* __restrict__ gg_off, int64_t Gg, int64_t w_base,
+                               uint32_t* sc_ev, uint32_t* sc_gev) {
+    evicted_prefix(w_ts, m, cut, gg_off, Gg, w_base, sc_ev, sc_gev);
 }
 
 // The window cut of an ingest from the staged batch's range (the same
 // arithmetic as the host's once it reads the range back), and in parallel
-// the three searches it needs: thread 0 the late prefix of a sorted batch
-// (its length and first kept timestamp), thread 1 the evicted prefix of the
-// window, thread 2 that of the global groups. Each writes its default (no
-// late record, nothing evicted) when its condition does not hold, so one
-// read-back serves the whole decision.
+// the searches it needs: thread 0 the late prefix of a sorted batch (its
+// length and first kept timestamp), thread 1 the evicted prefix of the
+// window and of its global groups. Each writes its default (no late record,
+// nothing evicted) when its condition does not hold, so one read-back serves
+// the whole decision.
 __global__ void k_cut_counts(const unsigned long long* __restrict__ mm,
                              const uint32_t* __restrict__ unsorted, int has_time, int64_t t_now,
                              int64_t window, const int64_t* __restrict__ b_ts, int64_t B,
                              const int64_t* __restrict__ w_ts, int64_t m, int64_t t_min,
-                             const int64_t* __restrict__ gg_ts, int64_t Gg, uint32_t* sc_kept,
-                             int64_t* first_kept, uint32_t* sc_ev, uint32_t* sc_gev) {
+                             const uint32_t* __restrict__ gg_off, int64_t Gg, int64_t w_base,
+                             uint32_t* sc_kept, int64_t* first_kept, uint32_t* sc_ev,
+                             uint32_t* sc_gev) {
     const int64_t bmin = unord(mm[0]), bmax = unord(mm[1]);
     const int64_t now = B > 0 ? (has_time ? (t_now > bmax ? t_now : bmax) : bmax) : t_now;
     const bool timed = has_time || B > 0;
     const bool windowed = window > 0 && timed;
     const int64_t cut = !windowed ? INT64_MIN
                         : (now < INT64_MIN + window ? INT64_MIN : now - window);
-    const int64_t* ts = nullptr;
-    int64_t n = 0;
-    uint32_t* out = nullptr;
     if (threadIdx.x == 0) {
         if (windowed && B > 0 && bmin < cut && *unsorted == 0u) {
-            ts = b_ts;
-            n = B;
+            int64_t lo = 0, hi = B;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (b_ts[mid] < cut) lo = mid + 1; else hi = mid;
+            }
+            *sc_kept = (uint32_t)lo;
+            *first_kept = lo < B ? b_ts[lo] : INT64_MAX;
         } else {
             *sc_kept = 0u;
             *first_kept = bmin;
-            return;
         }
-    } else if (threadIdx.x == 1 || threadIdx.x == 2) {
-        out = threadIdx.x == 1 ? sc_ev : sc_gev;
+    } else if (threadIdx.x == 1) {
         if (windowed && m > 0 && t_min < cut) {
-            ts = threadIdx.x == 1 ? w_ts : gg_ts;
-            n = threadIdx.x == 1 ? m : Gg;
+            evicted_prefix(w_ts, m, cut, gg_off, Gg, w_base, sc_ev, sc_gev);
         } else {
-            *out = 0u;
-            return;
+            *sc_ev = 0u;
+            *sc_gev = 0u;
         }
-    } else {
-        return;
-    }
-    int64_t lo = 0, hi = n;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (ts[mid] < cut) lo = mid + 1; else hi = mid;
-    }
-    if (threadIdx.x == 0) {
-        *sc_kept = (uint32_t)lo;
-        *first_kept = lo < n ? ts[lo] : INT64_MAX;
-    } else {
-        *out = (uint32_t)lo;
     }
 }
 
@@ -289,14 +302,12 @@ tw_status grow_window(tw_graph* g, int64_t cap, Error& err) {
     TW_HIP(ensure(g->a_src, sizeof(int32_t) * cap));
     TW_HIP(ensure(g->a_dst, sizeof(int32_t) * cap));
     TW_HIP(ensure(g->a_ts, sizeof(int64_t) * cap));
-    TW_HIP(ensure(g->gg_ts, sizeof(int64_t) * (cap + 2)));
     TW_HIP(ensure(g->gg_off, sizeof(uint32_t) * (cap + 2)));
     int64_t held = (int64_t)UINT32_MAX - 1;
     for (const DevBuf* b : {&g->e_src, &g->e_dst, &g->a_src, &g->a_dst})
         held = std::min<int64_t>(held, (int64_t)(b->bytes / 4));
     for (const DevBuf* b : {&g->e_ts, &g->a_ts})
         held = std::min<int64_t>(held, (int64_t)(b->bytes / 8));
-    held = std::min<int64_t>(held, (int64_t)(g->gg_ts.bytes / 8) - 2);
     held = std::min<int64_t>(held, (int64_t)(g->gg_off.bytes / 4) - 2);
     g->e_base = 0;
     g->e_cap = held;
@@ -332,8 +343,8 @@ tw_status build_ts_groups(tw_graph* g, Error& err) {
     const int64_t m = g->m;
     const int64_t* ts = g->e_ts.as<int64_t>() + g->e_base;
     uint32_t* G = u32_slot(g, SLOT_U32_GROUPS);
-    TW_HIP(group_starts(0, 0, ts, m, (uint32_t)g->e_base, g->gg_ts.as<int64_t>(),
-                        g->gg_off.as<uint32_t>(), G, g->ws, s));
+    TW_HIP(group_starts(0, 0, ts, m, (uint32_t)g->e_base, g->gg_off.as<uint32_t>(), G, g->ws,
+                        s));
     g->gg_base = 0;
     return TW_OK;
 }
@@ -413,8 +424,8 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
         hipLaunchKernelGGL(k_cut_counts, dim3(1), dim3(64), 0, s, mm, unsorted,
                            g->has_time ? 1 : 0, g->t_now, g->window, s_ts, B,
                            g->e_ts.as<int64_t>() + g->e_base, g->m, g->t_min,
-                           g->gg_ts.as<int64_t>() + g->gg_base, g->Gg, sc_kept, first_kept, sc_ev,
-                           sc_gev);
+                           g->gg_off.as<uint32_t>() + g->gg_base, g->Gg, g->e_base, sc_kept,
+                           first_kept, sc_ev, sc_gev);
     TW_HIP(hipGetLastError());
     if (pull_scalars(g, true, err) != TW_OK) return err.code;
     const uint64_t hmm[2] = {(uint64_t)host_i64(g, SLOT_I64_MINMAX),
@@ -600,8 +611,7 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
             uint32_t* G = u32_slot(g, SLOT_U32_GROUPS);
             const int64_t gpos = g->gg_base + (gg_old - gg_evicted);
             TW_HIP(group_starts(1, last_ts, q_ts, kept, (uint32_t)(g->e_base + na),
-                                g->gg_ts.as<int64_t>() + gpos, g->gg_off.as<uint32_t>() + gpos, G,
-                                g->ws, s));
+                                g->gg_off.as<uint32_t>() + gpos, G, g->ws, s));
         } else {
             // eviction only: the groups keep their offsets
             hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(T), 0, s, u32_slot(g, SLOT_U32_GROUPS), 1,
@@ -645,10 +655,9 @@ tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& e
     if (g->m > 0 && g->t_min < cutoff) {
         uint32_t* sc_ev = u32_slot(g, SLOT_U32_EVICTED);
         uint32_t* sc_gev = u32_slot(g, SLOT_U32_GG_EVICTED);
-        hipLaunchKernelGGL(k_lower_bound, dim3(1), dim3(1), 0, s, g->e_ts.as<int64_t>() + g->e_base,
-                           g->m, cutoff, sc_ev);
-        hipLaunchKernelGGL(k_lower_bound, dim3(1), dim3(1), 0, s,
-                           g->gg_ts.as<int64_t>() + g->gg_base, g->Gg, cutoff, sc_gev);
+        hipLaunchKernelGGL(k_evict_counts, dim3(1), dim3(1), 0, s,
+                           g->e_ts.as<int64_t>() + g->e_base, g->m, cutoff,
+                           g->gg_off.as<uint32_t>() + g->gg_base, g->Gg, g->e_base, sc_ev, sc_gev);
         if (pull_scalars(g, false, err) != TW_OK) return err.code;
         ev = host_u32(g, SLOT_U32_EVICTED);
         gev = host_u32(g, SLOT_U32_GG_EVICTED);
@@ -778,7 +787,9 @@ tw_status export_views(tw_graph* g, int32_t* src, int32_t* dst, int64_t* ts, int
     TW_HIP(cp(src, g->e_src.as<int32_t>() + g->e_base, sizeof(int32_t) * m));
     TW_HIP(cp(dst, g->e_dst.as<int32_t>() + g->e_base, sizeof(int32_t) * m));
     TW_HIP(cp(ts, g->e_ts.as<int64_t>() + g->e_base, sizeof(int64_t) * m));
-    TW_HIP(cp(g_ts, g->gg_ts.as<int64_t>() + g->gg_base, sizeof(int64_t) * g->Gg));
+    if (g_ts && g->Gg > 0)
+        hipLaunchKernelGGL(k_group_ts, grid_for(g->Gg), dim3(T), 0, s, g->e_ts.as<int64_t>(),
+                           g->gg_off.as<uint32_t>() + g->gg_base, g->Gg, g_ts);
     if (g_off)
         hipLaunchKernelGGL(k_widen, grid_for(g->Gg + 1), dim3(T), 0, s,
                            g->gg_off.as<uint32_t>() + g->gg_base, g->Gg + 1, g_off, g->e_base);

@@ -195,16 +195,12 @@ struct GroupStartOp {
     int has_last;
     int64_t last_ts;
     uint32_t pos_base;
-    int64_t* g_ts;
     uint32_t* g_off;
     static constexpr bool kHoist = false;
     __device__ bool flag(int64_t i) const {
         return i == 0 ? (!has_last || ts[0] != last_ts) : ts[i] != ts[i - 1];
     }
-    __device__ void emit(int64_t i, uint32_t k) const {
-        g_ts[k] = ts[i];
-        g_off[k] = pos_base + (uint32_t)i;
-    }
+    __device__ void emit(int64_t i, uint32_t k) const { g_off[k] = pos_base + (uint32_t)i; }
     __device__ void end(int64_t n, uint32_t total) const { g_off[total] = pos_base + (uint32_t)n; }
 };
 
@@ -571,14 +567,14 @@ hipError_t scan_exclusive_i32_to_u64(const int32_t* in, uint64_t* out, int64_t n
 }
 
 hipError_t group_starts(int has_last, int64_t last_ts, const int64_t* ts, int64_t n,
-                        uint32_t pos_base, int64_t* g_ts, uint32_t* g_off, uint32_t* total,
-                        Workspace& ws, hipStream_t s) {
+                        uint32_t pos_base, uint32_t* g_off, uint32_t* total, Workspace& ws,
+                        hipStream_t s) {
     if (n <= 0) {
         hipLaunchKernelGGL(k_set<uint32_t>, dim3(1), dim3(1), 0, s, g_off, pos_base);
         hipLaunchKernelGGL(k_set<uint32_t>, dim3(1), dim3(1), 0, s, total, 0u);
         return hipGetLastError();
     }
-    const GroupStartOp op{ts, has_last, last_ts, pos_base, g_ts, g_off};
+    const GroupStartOp op{ts, has_last, last_ts, pos_base, g_off};
     return compact(op, n, total, ws.tiles, ws, s);
 }
 

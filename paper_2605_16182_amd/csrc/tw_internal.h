@@ -195,12 +195,12 @@ hipError_t scan_exclusive_i32_to_u64(const int32_t* in, uint64_t* out, int64_t n
 
 // Groups of a sequence of timestamps: the k-th position i that starts a group
 // (ts[i] != ts[i-1]; position 0 always, or with has_last, when ts[0] !=
-// last_ts, the timestamp before the sequence) gives g_ts[k] = ts[i] and
-// g_off[k] = pos_base + i; g_off[total] = pos_base + n; total (device) = the
-// number of groups. n may be 0.
+// last_ts, the timestamp before the sequence) gives g_off[k] = pos_base + i;
+// g_off[total] = pos_base + n; total (device) = the number of groups. A
+// group's timestamp is that of its first position. n may be 0.
 hipError_t group_starts(int has_last, int64_t last_ts, const int64_t* ts, int64_t n,
-                        uint32_t pos_base, int64_t* g_ts, uint32_t* g_off, uint32_t* total,
-                        Workspace& ws, hipStream_t s);
+                        uint32_t pos_base, uint32_t* g_off, uint32_t* total, Workspace& ws,
+                        hipStream_t s);
 
 // Stable LSD radix sort of (keys, vals) by bits [bit_lo, bit_hi) of the key.
 // vals may be null. Result ends in keys / vals. The alternate buffers come
@@ -248,8 +248,10 @@ struct tw_graph {
 
     // host mirrors of the index sizes. The window occupies positions
     // [e_base, e_base + m) of the edge-store buffers (capacity e_cap); its
-    // timestamp groups occupy [gg_base, gg_base + Gg) of gg_ts / gg_off, whose
-    // offsets are edge-store buffer positions.
+    // timestamp groups occupy [gg_base, gg_base + Gg] of gg_off: edge-store
+    // buffer positions of each group's first record (and the end); a group's
+    // timestamp is that record's, and t_min / t_max are the window's first
+    // and last timestamps.
     int64_t m = 0, Gg = 0;
     int64_t e_base = 0, e_cap = 0, gg_base = 0;
     int64_t t_min = 0, t_max = 0;
@@ -257,7 +259,7 @@ struct tw_graph {
 
     // timestamp view (the edge store) and its alternate for merges
     tw::DevBuf e_src, e_dst, e_ts, a_src, a_dst, a_ts;
-    tw::DevBuf gg_ts, gg_off;          // global timestamp groups
+    tw::DevBuf gg_off;                 // global timestamp groups
 
     // node view: per-node segments of the edge pool (n_dst, n_ts), the
     // group pool (ng, GroupRec) and the fence pool (fence). New segments are
@@ -317,7 +319,7 @@ struct tw_graph {
 
     // every device allocation of the graph
     std::vector<tw::DevBuf*> buffers() {
-        return {&e_src, &e_dst, &e_ts, &a_src, &a_dst, &a_ts, &gg_ts, &gg_off,
+        return {&e_src, &e_dst, &e_ts, &a_src, &a_dst, &a_ts, &gg_off,
                 &n_dst, &n_ts, &ng, &fence, &an_dst, &an_ts, &ang, &afence,
                 &rec, &seg, &touched, &bs_src, &bs_dst, &bs_ts, &q_src, &q_dst, &q_ts,
                 &c_node, &c_bf, &c_be, &jobs, &j_cnt, &j_off, &j_re, &j_rg, &j_rf, &j_fw,

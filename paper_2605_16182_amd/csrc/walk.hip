@@ -33,8 +33,8 @@ struct WalkArgs {
     const int32_t* e_src;
     const int32_t* e_dst;
     const int64_t* e_ts;
-    const int64_t* gg_ts;
-    const uint32_t* gg_off;
+    const uint32_t* gg_off;  // first record of each timestamp group, then the end
+    int64_t w_first, w_last;  // the window's first and last timestamps
     uint32_t m, Gg, e_base;  // the window is e_*[e_base, e_base + m)
     // node view
     const int32_t* n_dst;
@@ -114,7 +114,7 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, const StartP
             const uint32_t i = (uint32_t)scale_u64(d0.x0, a.m);
             e = a.e_base + (rev ? a.m - 1 - i : i);
         } else {
-            e = pick_global(a.gg_ts, a.gg_off, a.Gg, sp.kind, sp.tau, d0, rev);
+            e = pick_global(a.gg_off, a.Gg, a.w_first, a.w_last, sp.kind, sp.tau, d0, rev);
         }
         const int32_t s = a.e_src[e], t_dst = a.e_dst[e];
         const int64_t t = a.e_ts[e];
@@ -932,7 +932,8 @@ tw_status fill_args(tw_graph* g, int64_t num_walks, int32_t L, const tw_bias& sb
     a.e_src = g->e_src.as<int32_t>();
     a.e_dst = g->e_dst.as<int32_t>();
     a.e_ts = g->e_ts.as<int64_t>();
-    a.gg_ts = g->gg_ts.as<int64_t>() + g->gg_base;
+    a.w_first = g->t_min;
+    a.w_last = g->t_max;
     a.gg_off = g->gg_off.as<uint32_t>() + g->gg_base;
     a.e_base = (uint32_t)g->e_base;
     a.m = (uint32_t)g->m;

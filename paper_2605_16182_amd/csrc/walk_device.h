@@ -278,11 +278,10 @@ __device__ __forceinline__ Pick pick_weight(const GroupRec* __restrict__ ng,
 }
 
 // The edge-store position picked among the window's Gg timestamp groups.
-__device__ __forceinline__ uint32_t pick_global(const int64_t* __restrict__ gg_ts,
-                                                const uint32_t* __restrict__ gg_off, uint32_t Gg,
-                                                int kind, double tau, const Draw& d,
-                                                bool rev = false) {
-    const uint32_t i = pick_group(Gg, kind, tau, Gg > 1 ? gg_ts[0] : 0, gg_ts[Gg - 1], d.x0);
+__device__ __forceinline__ uint32_t pick_global(const uint32_t* __restrict__ gg_off, uint32_t Gg,
+                                                int64_t t_first, int64_t t_last, int kind,
+                                                double tau, const Draw& d, bool rev = false) {
+    const uint32_t i = pick_group(Gg, kind, tau, Gg > 1 ? t_first : 0, t_last, d.x0);
     const uint32_t k = rev ? Gg - 1 - i : i;
     const uint32_t b0 = gg_off[k], b1 = gg_off[k + 1];
     const uint32_t j = (uint32_t)scale_u64(d.x1, b1 - b0);
