@@ -151,11 +151,11 @@ def walk_bytes(walks, hops, max_len, start_bias, hop_bias):
 def ingest_bytes(b_in, kept, evicted, jobs):
     """Algorithmic bytes of one incremental ingest: read the batch (16 B per
     input record), one read+write pass to order the kept records by source
-    (32 B), append them to the timestamp view with its group records (16 + 12
+    (32 B), append them to the timestamp view with its group starts (16 + 4
     B) and to their nodes' runs in the node view with group records (12 + 16
     B), read the sources of the evicted records (4 B), and read and write the
     record of every node whose run changed (2 x 48 B)."""
-    return 16 * b_in + 88 * kept + 4 * evicted + 96 * jobs
+    return 16 * b_in + 80 * kept + 4 * evicted + 96 * jobs
 
 
 def rebuild_bytes(b, m_old, m_new, V):
