@@ -609,11 +609,22 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
             g.dst = single ? (int32_t)((uint32_t)e.dst | 0x80000000u) : e.dst;
             const uint32_t gi = J.g_at + (rk - kj);
             ngd[gi] = g;
-            // the group's level-0 fence key (segments of more than
-            // FENCE_FAN groups have a fence)
-            if (J.gcode > 0)
-                fence[(uint64_t)J.f0 + (gi - J.g0)] =
-                    (uint32_t)((uint64_t)(e.ts - J.kbase) >> J.kshift);
+            // the group's fence keys (segments of more than FENCE_FAN groups
+            // have a fence): level 0 holds every group's, level k that of
+            // every FENCE_FAN^k-th group
+            if (J.gcode > 0) {
+                const uint32_t rel = gi - J.g0;
+                const uint32_t key = (uint32_t)((uint64_t)(e.ts - J.kbase) >> J.kshift);
+                const uint64_t cap = seg_groups(J.gcode);
+                uint32_t* f = fence + J.f0;
+                f[rel] = key;
+                const int K = fence_levels(cap);
+                uint64_t off = 0;
+                for (int k = 1; k <= K && (rel & ((1u << (FENCE_LOG * k)) - 1u)) == 0; ++k) {
+                    off += fence_level_len(cap, k - 1);
+                    f[off + (rel >> (FENCE_LOG * k))] = key;
+                }
+            }
         }
     }
 }
@@ -630,18 +641,19 @@ __device__ __forceinline__ uint64_t pad_fan(uint64_t c) {
 }
 
 // Fence words a rewrite of a segment of cap groups with n in use leaves to
-// k_job_fence (k_job_write stores the level-0 keys with the group records).
+// k_job_fence: the padding of every level (k_job_write stores the keys with
+// the group records).
 __device__ __forceinline__ uint32_t rewrite_words(uint64_t cap, uint64_t n) {
     if (fence_cap(cap) == 0) return 0;
-    uint64_t w = pad_fan(n) - n;  // level 0: its padding only
+    uint64_t w = 0;
     const int K = fence_levels(cap);
-    for (int k = 1; k <= K; ++k) w += pad_fan(level_count(n, k));
+    for (int k = 0; k <= K; ++k) w += pad_fan(level_count(n, k)) - level_count(n, k);
     return (uint32_t)w;
 }
 
 // What an append from n0 to n1 groups in use writes at level k: keys of the
-// entries [key0, key0 + nkeys), UINT32_MAX at [pad0, pad0 + npad). The
-// level-0 keys are k_job_write's; k_job_fence writes the rest.
+// entries [key0, key0 + nkeys) (k_job_write, with the new groups' records),
+// UINT32_MAX at [pad0, pad0 + npad) (k_job_fence).
 struct LevelWrite {
     uint64_t key0, nkeys, pad0, npad;
 };
@@ -680,10 +692,8 @@ __global__ void k_job_finish(const Job* __restrict__ jobs, const uint32_t* __res
             r.ee = J.oe + written;
             if (fence_cap(cap) > 0) {
                 const int K = fence_levels(cap);
-                for (int k = 0; k <= K; ++k) {
-                    const LevelWrite lw = append_level(J.oge - J.g0, r.ge - J.g0, k);
-                    f += (uint32_t)((k > 0 ? lw.nkeys : 0) + lw.npad);
-                }
+                for (int k = 0; k <= K; ++k)
+                    f += (uint32_t)append_level(J.oge - J.g0, r.ge - J.g0, k).npad;
             }
         } else {
             r.gb = J.g0;
@@ -712,14 +722,10 @@ __global__ void k_job_finish(const Job* __restrict__ jobs, const uint32_t* __res
     fw[j] = f;
 }
 
-// Fence word u of job J (u counts the words the job writes): a rewritten
-// segment writes, on every level, the keys and the padding; an append the
-// keys and padding its new groups add. Level-0 keys are written by
-// k_job_write, so level 0 contributes padding only; the key of entry i on
-// level k is the level-0 key of group i * FENCE_FAN^k (keys are taken under
-// the key base and shift of the segment, which an append keeps), read from
-// level 0: four keys per 128-byte line on level 1, where the group records
-// would give one.
+// Fence word u of job J (u counts the words the job writes): the padding
+// that a rewritten segment needs on every level, or that an append's new
+// groups move. k_job_write stores every level's keys with the group
+// records, so only padding is left here.
 __device__ __forceinline__ void fence_entry(const Job& J, uint32_t ge,
                                             uint32_t* __restrict__ fence, uint64_t u) {
     const uint64_t cap = seg_groups(J.gcode);
@@ -728,25 +734,15 @@ __device__ __forceinline__ void fence_entry(const Job& J, uint32_t ge,
     const int K = fence_levels(cap);
     uint64_t off = 0;
     for (int k = 0; k <= K; ++k) {
-        uint64_t key0 = 0, nkeys, pad0, npad;
+        uint64_t pad0, npad;
         if (J.kind == JOB_REWRITE) {
-            nkeys = level_count(n, k);
-            pad0 = nkeys;
-            npad = pad_fan(nkeys) - nkeys;
+            pad0 = level_count(n, k);
+            npad = pad_fan(pad0) - pad0;
         } else {
             const LevelWrite lw = append_level(J.oge - J.g0, n, k);
-            key0 = lw.key0;
-            nkeys = lw.nkeys;
             pad0 = lw.pad0;
             npad = lw.npad;
         }
-        if (k == 0) nkeys = 0;
-        if (u < nkeys) {
-            const uint64_t i = key0 + u;
-            f[off + i] = f[i << (FENCE_LOG * k)];
-            return;
-        }
-        u -= nkeys;
         if (u < npad) {
             f[off + pad0 + u] = 0xFFFFFFFFu;
             return;
