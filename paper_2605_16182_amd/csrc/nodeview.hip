@@ -15,6 +15,7 @@
 // Only new groups add fence entries. When a pool has no room for the new
 // segments, every active node is rewritten into fresh pools.
 #include <algorithm>
+#include <type_traits>
 
 #include "compact.h"
 #include "tw_internal.h"
@@ -434,21 +435,29 @@ struct TileJobs {
             for (uint32_t i = threadIdx.x; i < cnt; i += T) soff[i] = off[j0 + i];
         __syncthreads();
     }
-    // the job holding output t of the tile
+    // The job holding output t of the tile. S = staged (uniform over the
+    // workgroup): the kernels run their rounds in one code path per case, so
+    // that a lookup is an LDS read or a global read, never a generic one.
+    template <bool S>
     __device__ uint32_t job(const uint32_t* __restrict__ off, const uint32_t* soff,
                             uint64_t t) const {
-        if (!staged) return job_in(off, j0, j1, t);
-        uint32_t a = 1, b = j1 - j0 + 1;  // last k with soff[k] <= t (soff[0] <= t)
-        while (a < b) {
-            const uint32_t mid = a + ((b - a) >> 1);
-            if ((uint64_t)soff[mid] <= t) a = mid + 1; else b = mid;
+        if constexpr (!S) {
+            return job_in(off, j0, j1, t);
+        } else {
+            uint32_t a = 1, b = j1 - j0 + 1;  // last k with soff[k] <= t (soff[0] <= t)
+            while (a < b) {
+                const uint32_t mid = a + ((b - a) >> 1);
+                if ((uint64_t)soff[mid] <= t) a = mid + 1; else b = mid;
+            }
+            return j0 + a - 1;
         }
-        return j0 + a - 1;
     }
     // off[j] for a job j of the tile's range, or j1 + 1
+    template <bool S>
     __device__ uint32_t start(const uint32_t* __restrict__ off, const uint32_t* soff,
                               uint32_t j) const {
-        return staged ? soff[j - j0] : off[j];
+        if constexpr (S) return soff[j - j0];
+        else return off[j];
     }
 };
 
@@ -467,23 +476,28 @@ __global__ void __launch_bounds__(T) k_job_flags(const Job* __restrict__ jobs,
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t base = (int64_t)tile * NV_TILE;
     const TileJobs tj(tf, tile, off, soff);
-    uint32_t c = 0;
-    for (int u = 0; u < NV_ITEMS; ++u) {
-        const int64_t t0 = base + (int64_t)u * T + wave * 64;  // the word's first output
-        const int64_t t = t0 + lane;
-        bool start = false;
-        if (t < total) {
-            const uint32_t j = tj.job(off, soff, (uint64_t)t);
-            const Job J = jobs[j];
-            const uint32_t i = (uint32_t)(t - tj.start(off, soff, j));
-            const int64_t x = job_ts(J, i, ots, bt);
-            if (i == 0) start = J.kind != JOB_APPEND || x != J.t_last;
-            else start = x != job_ts(J, i - 1, ots, bt);
+    auto rounds = [&](auto staged) {
+        constexpr bool S = decltype(staged)::value;
+        uint32_t c = 0;
+        for (int u = 0; u < NV_ITEMS; ++u) {
+            const int64_t t0 = base + (int64_t)u * T + wave * 64;  // the word's first output
+            const int64_t t = t0 + lane;
+            bool start = false;
+            if (t < total) {
+                const uint32_t j = tj.template job<S>(off, soff, (uint64_t)t);
+                const Job J = jobs[j];
+                const uint32_t i = (uint32_t)(t - tj.template start<S>(off, soff, j));
+                const int64_t x = job_ts(J, i, ots, bt);
+                if (i == 0) start = J.kind != JOB_APPEND || x != J.t_last;
+                else start = x != job_ts(J, i - 1, ots, bt);
+            }
+            const uint64_t b = __ballot(start);
+            if (lane == 0 && t0 < total) bm[t0 >> 6] = b;
+            c += (uint32_t)__popcll(b);
         }
-        const uint64_t b = __ballot(start);
-        if (lane == 0 && t0 < total) bm[t0 >> 6] = b;
-        c += (uint32_t)__popcll(b);
-    }
+        return c;
+    };
+    const uint32_t c = tj.staged ? rounds(std::true_type{}) : rounds(std::false_type{});
     if (lane == 0) wsum[wave] = c;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -553,7 +567,8 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
         }
         if (lane < nw) pref[(base >> 6) + lane] = p0;
     } else if (wave == 1) {
-        const int64_t s0 = tj.start(off, soff, tj.j0);
+        const int64_t s0 = tj.staged ? tj.start<true>(off, soff, tj.j0)
+                                     : tj.start<false>(off, soff, tj.j0);
         if (s0 < base) {
             const int64_t a = s0 / NV_TILE;
             const int64_t q = s0 >> 6, wd = ((a * NV_TILE) >> 6) + lane;
@@ -566,67 +581,81 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
         }
     }
     __syncthreads();
-    for (int u = 0; u < NV_ITEMS; ++u) {
-        const int64_t t = base + (int64_t)u * T + threadIdx.x;
-        if (t >= total) break;
-        const uint32_t j = tj.job(off, soff, (uint64_t)t);
-        const Job J = jobs[j];
-        const uint32_t jb = tj.start(off, soff, j);
-        const uint32_t i = (uint32_t)(t - jb);
-        const Elem e = job_elem(J, i, odst, ots, bt);
-        const uint32_t pos = J.e_at + i;
-        ndst[pos] = e.dst;
-        nts[pos] = e.ts;
-        const int lt = (int)(t - base);
-        const uint64_t word = sbm[lt >> 6];
-        const bool starts = (word >> (lt & 63)) & 1ull;
-        if (i == 0 && J.kind == JOB_APPEND && !starts) {
-            // the first new edge joins the node's last group: no longer a
-            // one-edge group
-            int32_t* d = &ngd[J.oge - 1].dst;
-            *d = *d & 0x7fffffff;
-        }
-        if (starts) {
-            // a one-edge group: the job's next output starts a group, or
-            // there is none
-            bool single = (uint64_t)t + 1 >= (uint64_t)tj.start(off, soff, j + 1);
-            if (!single) {
-                const int ln = lt + 1;
-                const uint64_t nw = ln < NV_TILE ? sbm[ln >> 6] : bm[(uint64_t)(t + 1) >> 6];
-                single = (nw >> (ln & 63)) & 1ull;
+    auto rounds = [&](auto staged) {
+        constexpr bool S = decltype(staged)::value;
+        for (int u = 0; u < NV_ITEMS; ++u) {
+            const int64_t t = base + (int64_t)u * T + threadIdx.x;
+            if (t >= total) break;
+            const uint32_t j = tj.template job<S>(off, soff, (uint64_t)t);
+            const Job J = jobs[j];
+            const uint32_t jb = tj.template start<S>(off, soff, j);
+            const uint32_t i = (uint32_t)(t - jb);
+            const Elem e = job_elem(J, i, odst, ots, bt);
+            const uint32_t pos = J.e_at + i;
+            ndst[pos] = e.dst;
+            nts[pos] = e.ts;
+            const int lt = (int)(t - base);
+            const uint64_t word = sbm[lt >> 6];
+            const bool starts = (word >> (lt & 63)) & 1ull;
+            if (i == 0 && J.kind == JOB_APPEND && !starts) {
+                // the first new edge joins the node's last group: no longer a
+                // one-edge group
+                int32_t* d = &ngd[J.oge - 1].dst;
+                *d = *d & 0x7fffffff;
             }
-            const uint32_t rk = spre[lt >> 6] + (uint32_t)__popcll(word & below(lt & 63));
-            uint32_t kj;
-            if ((int64_t)jb >= base) {
-                const int lb = (int)(jb - base);
-                kj = spre[lb >> 6] + (uint32_t)__popcll(sbm[lb >> 6] & below(lb & 63));
-            } else {
-                kj = k_first;
-            }
-            GroupRec g;
-            g.ts = e.ts;
-            g.first = pos;
-            g.dst = single ? (int32_t)((uint32_t)e.dst | 0x80000000u) : e.dst;
-            const uint32_t gi = J.g_at + (rk - kj);
-            ngd[gi] = g;
-            // the group's fence keys (segments of more than FENCE_FAN groups
-            // have a fence): level 0 holds every group's, level k that of
-            // every FENCE_FAN^k-th group
-            if (J.gcode > 0) {
-                const uint32_t rel = gi - J.g0;
-                const uint32_t key = (uint32_t)((uint64_t)(e.ts - J.kbase) >> J.kshift);
-                const uint64_t cap = seg_groups(J.gcode);
-                uint32_t* f = fence + J.f0;
-                f[rel] = key;
-                const int K = fence_levels(cap);
-                uint64_t off = 0;
-                for (int k = 1; k <= K && (rel & ((1u << (FENCE_LOG * k)) - 1u)) == 0; ++k) {
-                    off += fence_level_len(cap, k - 1);
-                    f[off + (rel >> (FENCE_LOG * k))] = key;
+            if (starts) {
+                // a one-edge group: the job's next output starts a group, or
+                // there is none
+                bool single =
+                    (uint64_t)t + 1 >= (uint64_t)tj.template start<S>(off, soff, j + 1);
+                if (!single) {
+                    const int ln = lt + 1;
+                    uint64_t nw;
+                    if (ln < NV_TILE) {
+                        nw = sbm[ln >> 6];
+                    } else {  // the next tile's first word, read as two halves so
+                              // that the two reads stay an LDS and a global one
+                        const uint32_t* h =
+                            reinterpret_cast<const uint32_t*>(bm + ((uint64_t)(t + 1) >> 6));
+                        nw = (uint64_t)h[0] | ((uint64_t)h[1] << 32);
+                    }
+                    single = (nw >> (ln & 63)) & 1ull;
+                }
+                const uint32_t rk = spre[lt >> 6] + (uint32_t)__popcll(word & below(lt & 63));
+                uint32_t kj;
+                if ((int64_t)jb >= base) {
+                    const int lb = (int)(jb - base);
+                    kj = spre[lb >> 6] + (uint32_t)__popcll(sbm[lb >> 6] & below(lb & 63));
+                } else {
+                    kj = k_first;
+                }
+                GroupRec g;
+                g.ts = e.ts;
+                g.first = pos;
+                g.dst = single ? (int32_t)((uint32_t)e.dst | 0x80000000u) : e.dst;
+                const uint32_t gi = J.g_at + (rk - kj);
+                ngd[gi] = g;
+                // the group's fence keys (segments of more than FENCE_FAN groups
+                // have a fence): level 0 holds every group's, level k that of
+                // every FENCE_FAN^k-th group
+                if (J.gcode > 0) {
+                    const uint32_t rel = gi - J.g0;
+                    const uint32_t key = (uint32_t)((uint64_t)(e.ts - J.kbase) >> J.kshift);
+                    const uint64_t cap = seg_groups(J.gcode);
+                    uint32_t* f = fence + J.f0;
+                    f[rel] = key;
+                    const int K = fence_levels(cap);
+                    uint64_t off = 0;
+                    for (int k = 1; k <= K && (rel & ((1u << (FENCE_LOG * k)) - 1u)) == 0; ++k) {
+                        off += fence_level_len(cap, k - 1);
+                        f[off + (rel >> (FENCE_LOG * k))] = key;
+                    }
                 }
             }
         }
-    }
+    };
+    if (tj.staged) rounds(std::true_type{});
+    else rounds(std::false_type{});
 }
 
 // Level k of a segment with n groups in use holds the keys of its entries
@@ -775,13 +804,18 @@ __global__ void __launch_bounds__(T) k_job_fence(const Job* __restrict__ jobs,
         __syncthreads();  // the previous tile's offsets are no longer read
         const uint64_t base = tile * NV_TILE;
         const TileJobs tj(tf, (uint32_t)tile, foff, soff);
-        for (int u = 0; u < NV_ITEMS; ++u) {
-            const uint64_t t = base + (uint64_t)u * T + threadIdx.x;
-            if (t >= total) break;
-            const uint32_t j = tj.job(foff, soff, t);
-            const Job J = jobs[j];
-            fence_entry(J, rec[J.v].ge, fence, t - tj.start(foff, soff, j));
-        }
+        auto rounds = [&](auto staged) {
+            constexpr bool S = decltype(staged)::value;
+            for (int u = 0; u < NV_ITEMS; ++u) {
+                const uint64_t t = base + (uint64_t)u * T + threadIdx.x;
+                if (t >= total) break;
+                const uint32_t j = tj.template job<S>(foff, soff, t);
+                const Job J = jobs[j];
+                fence_entry(J, rec[J.v].ge, fence, t - tj.template start<S>(foff, soff, j));
+            }
+        };
+        if (tj.staged) rounds(std::true_type{});
+        else rounds(std::false_type{});
     }
 }
 
