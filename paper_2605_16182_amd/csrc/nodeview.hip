@@ -41,16 +41,19 @@ struct alignas(32) SegRec {
 
 enum : uint32_t { JOB_EVICT = 0, JOB_APPEND = 1, JOB_REWRITE = 2 };
 
-struct Job {
-    uint32_t v, kind, merge, fresh;  // node; kind; runs interleave; needs a new segment
-    uint32_t ob, oe, ogb, oge;       // surviving old edges / groups
-    uint32_t bf, be;                 // batch run in the source-sorted batch
-    uint32_t e0, ecap, g0, gcode, f0;  // the segment after the job
-    uint32_t e_at, g_at;             // first written edge / first new group
-    uint32_t kshift;                 // fence key shift of the segment after the job
-    int64_t t_last;                  // last surviving old timestamp (INT64_MIN: none)
+// Fields are grouped in 16-byte words by the kernels that read them per
+// output (a job's outputs read the same words from consecutive lanes): the
+// run's place (every output), the writer's targets, the fence keys.
+struct alignas(16) Job {
+    uint32_t kind, merge, ob, oe;    // kind; runs interleave; surviving old edges
+    uint32_t bf, e_at, g_at, oge;    // batch run start; first written edge / new group; old end
+    uint32_t gcode, f0, g0, kshift;  // the segment after the job and its fence key shift
     int64_t kbase;                   // fence key base of the segment after the job
+    int64_t t_last;                  // last surviving old timestamp (INT64_MIN: none)
+    uint32_t v, fresh, ogb, be;      // node; needs a new segment; surviving old groups; run end
+    uint32_t e0, ecap, pad0, pad1;   // the segment after the job
 };
+static_assert(sizeof(Job) == 96, "six 16-byte words");
 
 __device__ __forceinline__ NodeRec empty_rec() {
     NodeRec r;
