@@ -450,8 +450,11 @@ hipError_t radix_sort_impl(const K* kin0, const uint32_t* vin0, const uint64_t* 
     const uint32_t* vi = vin0;
     const uint64_t* wi = win0;
     for (int p = 0; p < passes; ++p) {
-        int sh = bit_lo + 8 * p;
-        int nb = bit_hi - sh < 8 ? bit_hi - sh : 8;
+        // the bits split evenly over the passes: fewer digits per pass than
+        // 8 where that needs no extra pass (longer runs per digit in a tile)
+        const int per = (bit_hi - bit_lo + passes - 1) / passes;
+        int sh = bit_lo + per * p;
+        int nb = bit_hi - sh < per ? bit_hi - sh : per;
         bool to_out = copy_back ? (p % 2 == 1) : ((passes - 1 - p) % 2 == 0);
         K* ko = to_out ? kout : ka;
         uint32_t* vo = to_out ? vout : va;
