@@ -19,6 +19,7 @@
 
 #include "compact.h"
 #include "tw_internal.h"
+#include "walk_device.h"
 
 namespace tw {
 namespace {
@@ -80,16 +81,6 @@ __device__ __forceinline__ uint32_t group_code(uint64_t n) {
     uint32_t c = 0;
     while (seg_groups(c) < want) ++c;
     return c;
-}
-
-// first group in [lo, hi) with timestamp >= t
-__device__ __forceinline__ uint32_t lower_bound_groups(const GroupRec* __restrict__ ng,
-                                                       uint32_t lo, uint32_t hi, int64_t t) {
-    while (lo < hi) {
-        const uint32_t mid = lo + ((hi - lo) >> 1);
-        if (ng[mid].ts < t) lo = mid + 1; else hi = mid;
-    }
-    return lo;
 }
 
 // last index j in [0, n) with off[j] <= t (off ascending, off[0] <= t)
@@ -252,7 +243,11 @@ __global__ void k_job_setup(const uint32_t* __restrict__ c_node, const uint32_t*
     const NodeRec r = rec[J.v];
     uint32_t gb = r.gb;
     const uint32_t ge = r.ge;
-    if (evicting && gb < ge && ng[gb].ts < cut) gb = lower_bound_groups(ng, gb, ge, cut);
+    // the first group at or after cut: through the node's fence (a hub's
+    // eviction then costs a few window reads, not a binary search over its
+    // groups); everything goes when the last timestamp precedes cut
+    if (evicting && gb < ge && ng[gb].ts < cut)
+        gb = r.t_last < cut ? ge : fence_search(ng, fence, r, cut - 1, nullptr, 0, 0);
     J.ogb = gb;
     J.oge = ge;
     J.oe = r.ee;
