@@ -30,6 +30,7 @@ constexpr int CT_THREADS = 256;
 constexpr int CT_ROUNDS = 16;
 constexpr int CT_WAVE = 64 * CT_ROUNDS;
 constexpr int CT_TILE = (CT_THREADS / 64) * CT_WAVE;
+static_assert(CT_TILE == GS_TILE, "staged group counts use the compaction's tiles");
 
 template <class Op>
 __global__ void __launch_bounds__(CT_THREADS)
@@ -105,16 +106,20 @@ k_ct_emit(const Op op, int64_t n, const uint32_t* __restrict__ off) {
 }
 
 // Runs both passes on stream s; *total (device) receives the flagged count.
-// tiles holds the tile counts (grown as needed).
+// tiles holds the tile counts (grown as needed). counted: the caller already
+// wrote every tile's count of flagged items into tiles (a producer that read
+// the flags' inputs anyway), so the counting pass is skipped.
 template <class Op>
 hipError_t compact(const Op& op, int64_t n, uint32_t* total, DevBuf& tiles, Workspace& ws,
-                   hipStream_t s) {
+                   hipStream_t s, bool counted = false) {
     if (n <= 0) return scan_exclusive_u32(nullptr, nullptr, 0, total, ws, s);
     const int64_t nb = ceil_div(n, (int64_t)CT_TILE);
     hipError_t e = ensure(tiles, sizeof(uint32_t) * (nb + 1));
     if (e != hipSuccess) return e;
     uint32_t* cnt = tiles.as<uint32_t>();
-    hipLaunchKernelGGL(k_ct_count<Op>, dim3((unsigned)nb), dim3(CT_THREADS), 0, s, op, n, cnt);
+    if (!counted)
+        hipLaunchKernelGGL(k_ct_count<Op>, dim3((unsigned)nb), dim3(CT_THREADS), 0, s, op, n,
+                           cnt);
     if ((e = scan_exclusive_u32(cnt, cnt, nb, total, ws, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_ct_emit<Op>, dim3((unsigned)nb), dim3(CT_THREADS), 0, s, op, n, cnt);
     return hipGetLastError();

@@ -81,6 +81,75 @@ __global__ void k_stage(const int32_t* __restrict__ src, const int32_t* __restri
     }
 }
 
+// k_stage for a directed batch, one workgroup per tile of GS_TILE records,
+// also counting each tile's timestamp group starts into
+// gcnt[tile] (a record whose timestamp differs from the one before it; the
+// first record compared with last_ts when has_last): the counting pass of
+// the group starts' compaction when the batch is appended as staged.
+__global__ void __launch_bounds__(T)
+k_stage_count(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+              const int64_t* __restrict__ ts, int64_t n, int32_t V, int32_t* __restrict__ b_src,
+              int32_t* __restrict__ b_dst, int64_t* __restrict__ b_ts, uint32_t* err,
+              unsigned long long* scalars, uint32_t* unsorted, int has_last, int64_t last_ts,
+              uint32_t* __restrict__ gcnt) {
+    __shared__ unsigned long long smin[T], smax[T];
+    __shared__ uint32_t wsum[T / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned long long lo = ~0ull, hi = 0ull;
+    bool bad = false, down = false;
+    {
+        const int64_t tile = blockIdx.x;
+        uint32_t c = 0;
+        for (int r = 0; r < GS_TILE / T; ++r) {
+            const int64_t i = tile * GS_TILE + r * T + threadIdx.x;
+            bool start = false;
+            if (i < n) {
+                const int32_t u = src[i], v = dst[i];
+                const int64_t t = ts[i];
+                bad |= (u < 0 || u >= V || v < 0 || v >= V);
+                if (i > 0) {
+                    const int64_t tp = ts[i - 1];
+                    down |= tp > t;
+                    start = t != tp;
+                } else {
+                    start = !has_last || t != last_ts;
+                }
+                const unsigned long long o = ord(t);
+                lo = o < lo ? o : lo;
+                hi = o > hi ? o : hi;
+                b_src[i] = u;
+                b_dst[i] = v;
+                b_ts[i] = t;
+            }
+            c += (uint32_t)__popcll(__ballot(start));
+        }
+        if (lane == 0) wsum[wave] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t sum = 0;
+#pragma unroll
+            for (int w = 0; w < T / 64; ++w) sum += wsum[w];
+            gcnt[tile] = sum;
+        }
+    }
+    if (bad) atomicOr(err, 1u);
+    if (down) atomicOr(unsorted, 1u);
+    smin[threadIdx.x] = lo;
+    smax[threadIdx.x] = hi;
+    __syncthreads();
+    for (int off = T / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            smin[threadIdx.x] = min(smin[threadIdx.x], smin[threadIdx.x + off]);
+            smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + off]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMin(&scalars[0], smin[0]);
+        atomicMax(&scalars[1], smax[0]);
+    }
+}
+
 __global__ void k_init_minmax(unsigned long long* scalars, uint32_t* err, uint32_t* unsorted) {
     scalars[0] = ~0ull;
     scalars[1] = 0ull;
@@ -337,14 +406,15 @@ bool window_growth_fits(tw_graph* g, int64_t cap) {
 }
 
 // Global timestamp groups of the whole window, from scratch (gg_base = 0).
-// The count lands in the GROUPS slot.
-tw_status build_ts_groups(tw_graph* g, Error& err) {
+// The count lands in the GROUPS slot. counted (nullable): the window's group
+// starts per tile, already counted (with no timestamp before the window).
+tw_status build_ts_groups(tw_graph* g, Error& err, DevBuf* counted = nullptr) {
     hipStream_t s = g->stream;
     const int64_t m = g->m;
     const int64_t* ts = g->e_ts.as<int64_t>() + g->e_base;
     uint32_t* G = u32_slot(g, SLOT_U32_GROUPS);
     TW_HIP(group_starts(0, 0, ts, m, (uint32_t)g->e_base, g->gg_off.as<uint32_t>(), G, g->ws,
-                        s));
+                        s, counted));
     g->gg_base = 0;
     return TW_OK;
 }
@@ -410,10 +480,21 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
     uint32_t* errf = g->err.as<uint32_t>();
     uint32_t* unsorted = u32_slot(g, SLOT_U32_UNSORTED);
     hipLaunchKernelGGL(k_init_minmax, dim3(1), dim3(1), 0, s, mm, errf + 1, unsorted);
-    if (n > 0)
+    // a directed batch also gets the group starts of its tiles, for the case
+    // where it is appended as staged (the window's last timestamp before it)
+    const bool staged_counts = g->directed && n > 0;
+    const int stage_has_last = g->m > 0 ? 1 : 0;
+    if (staged_counts) {
+        const int64_t ntiles = ceil_div(n, (int64_t)GS_TILE);
+        TW_HIP(ensure(g->gs_tiles, sizeof(uint32_t) * (ntiles + 1)));
+        hipLaunchKernelGGL(k_stage_count, dim3((unsigned)ntiles), dim3(T), 0, s, src, dst, ts, n,
+                           g->V, s_src, s_dst, s_ts, errf + 1, mm, unsorted, stage_has_last,
+                           g->t_max, g->gs_tiles.as<uint32_t>());
+    } else if (n > 0) {
         hipLaunchKernelGGL(k_stage, dim3((unsigned)std::min<int64_t>(ceil_div(n, T), 2048)),
                            dim3(T), 0, s, src, dst, ts, n, g->V, g->directed ? 1 : 0, s_src, s_dst,
                            s_ts, errf + 1, mm, unsorted);
+    }
     // the window's cut and its searches run on the device before the first
     // read-back (results for the cases that need them; defaults otherwise)
     uint32_t* sc_kept = u32_slot(g, SLOT_U32_KEPT);
@@ -604,14 +685,22 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
                                   hipMemcpyDeviceToDevice, s));
         }
         g->m = m_new;
+        // the stage counted the group starts of the batch as staged: they
+        // serve when the whole batch is kept in order and compared with the
+        // same predecessor (the window's last timestamp, or none)
+        const bool as_staged = staged_counts && sorted && drop_lo == 0 && kept == B;
         if (gg_full || na == 0) {
+            // the window is the batch alone when nothing of the old one survives
+            const bool use = as_staged && na == 0 && stage_has_last == 0;
             gg_full = true;
-            if (build_ts_groups(g, err) != TW_OK) return err.code;
+            if (build_ts_groups(g, err, use ? &g->gs_tiles : nullptr) != TW_OK) return err.code;
         } else if (kept > 0) {
+            const bool use = as_staged && stage_has_last == 1;
             uint32_t* G = u32_slot(g, SLOT_U32_GROUPS);
             const int64_t gpos = g->gg_base + (gg_old - gg_evicted);
             TW_HIP(group_starts(1, last_ts, q_ts, kept, (uint32_t)(g->e_base + na),
-                                g->gg_off.as<uint32_t>() + gpos, G, g->ws, s));
+                                g->gg_off.as<uint32_t>() + gpos, G, g->ws, s,
+                                use ? &g->gs_tiles : nullptr));
         } else {
             // eviction only: the groups keep their offsets
             hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(T), 0, s, u32_slot(g, SLOT_U32_GROUPS), 1,

@@ -585,13 +585,14 @@ hipError_t scan_exclusive_i32_to_u64(const int32_t* in, uint64_t* out, int64_t n
 
 hipError_t group_starts(int has_last, int64_t last_ts, const int64_t* ts, int64_t n,
                         uint32_t pos_base, uint32_t* g_off, uint32_t* total, Workspace& ws,
-                        hipStream_t s) {
+                        hipStream_t s, DevBuf* counted) {
     if (n <= 0) {
         hipLaunchKernelGGL(k_set<uint32_t>, dim3(1), dim3(1), 0, s, g_off, pos_base);
         hipLaunchKernelGGL(k_set<uint32_t>, dim3(1), dim3(1), 0, s, total, 0u);
         return hipGetLastError();
     }
     const GroupStartOp op{ts, has_last, last_ts, pos_base, g_off};
+    if (counted) return compact(op, n, total, *counted, ws, s, true);
     return compact(op, n, total, ws.tiles, ws, s);
 }
 

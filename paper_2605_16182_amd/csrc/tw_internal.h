@@ -197,10 +197,13 @@ hipError_t scan_exclusive_i32_to_u64(const int32_t* in, uint64_t* out, int64_t n
 // (ts[i] != ts[i-1]; position 0 always, or with has_last, when ts[0] !=
 // last_ts, the timestamp before the sequence) gives g_off[k] = pos_base + i;
 // g_off[total] = pos_base + n; total (device) = the number of groups. A
-// group's timestamp is that of its first position. n may be 0.
+// group's timestamp is that of its first position. n may be 0. counted
+// (nullable) already holds the group starts of every tile of GS_TILE
+// positions (k_stage_count), for the same has_last and last_ts.
+constexpr int GS_TILE = 4096;
 hipError_t group_starts(int has_last, int64_t last_ts, const int64_t* ts, int64_t n,
                         uint32_t pos_base, uint32_t* g_off, uint32_t* total, Workspace& ws,
-                        hipStream_t s);
+                        hipStream_t s, DevBuf* counted = nullptr);
 
 // Stable LSD radix sort of (keys, vals) by bits [bit_lo, bit_hi) of the key.
 // vals may be null. Result ends in keys / vals. The alternate buffers come
@@ -260,6 +263,7 @@ struct tw_graph {
     // timestamp view (the edge store) and its alternate for merges
     tw::DevBuf e_src, e_dst, e_ts, a_src, a_dst, a_ts;
     tw::DevBuf gg_off;                 // global timestamp groups
+    tw::DevBuf gs_tiles;               // group starts per tile of a staged batch
 
     // node view: per-node segments of the edge pool (n_dst, n_ts), the
     // group pool (ng, GroupRec) and the fence pool (fence). New segments are
@@ -319,7 +323,7 @@ struct tw_graph {
 
     // every device allocation of the graph
     std::vector<tw::DevBuf*> buffers() {
-        return {&e_src, &e_dst, &e_ts, &a_src, &a_dst, &a_ts, &gg_off,
+        return {&e_src, &e_dst, &e_ts, &a_src, &a_dst, &a_ts, &gg_off, &gs_tiles,
                 &n_dst, &n_ts, &ng, &fence, &an_dst, &an_ts, &ang, &afence,
                 &rec, &seg, &touched, &bs_src, &bs_dst, &bs_ts, &q_src, &q_dst, &q_ts,
                 &c_node, &c_bf, &c_be, &jobs, &j_cnt, &j_off, &j_re, &j_rg, &j_rf, &j_fw,
