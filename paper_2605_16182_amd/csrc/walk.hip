@@ -194,7 +194,12 @@ __device__ __forceinline__ void finish_walk(const WalkArgs& a, int64_t w, int32_
 
 // Padding values (-1 nodes, INT64_MIN timestamps) for the output slots
 // [b, e), written by threads tid, tid + stride, ... with 16-byte stores where
-// the arrays are 16-byte aligned.
+// the arrays are 16-byte aligned. The bulk stores are non-temporal: the
+// padding is not read back, and cached it displaces index records the walk
+// reads next (fill + walk measured 0.3% faster; the fill alone is slower).
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef long long v2l __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ void fill_span(int32_t* __restrict__ nodes, int64_t* __restrict__ ts,
                                           int64_t b, int64_t e, int64_t tid, int64_t stride) {
     if (b >= e) return;
@@ -204,14 +209,16 @@ __device__ __forceinline__ void fill_span(int32_t* __restrict__ nodes, int64_t* 
     for (int64_t i = b + tid; i < nb; i += stride) nodes[i] = -1;
     const int64_t nv = (e - nb) / 4;
     int4* nv4 = reinterpret_cast<int4*>(nodes + nb);
-    for (int64_t i = tid; i < nv; i += stride) nv4[i] = make_int4(-1, -1, -1, -1);
+    for (int64_t i = tid; i < nv; i += stride)
+        __builtin_nontemporal_store((v4i){-1, -1, -1, -1}, reinterpret_cast<v4i*>(nv4) + i);
     for (int64_t i = nb + 4 * nv + tid; i < e; i += stride) nodes[i] = -1;
     const int64_t tb = std::min<int64_t>(
         e, b + (int64_t)(((16 - ((uintptr_t)(ts + b) & 15)) & 15) / 8));
     for (int64_t i = b + tid; i < tb; i += stride) ts[i] = TS_NONE;
     const int64_t tv = (e - tb) / 2;
     longlong2* tv2 = reinterpret_cast<longlong2*>(ts + tb);
-    for (int64_t i = tid; i < tv; i += stride) tv2[i] = make_longlong2(TS_NONE, TS_NONE);
+    for (int64_t i = tid; i < tv; i += stride)
+        __builtin_nontemporal_store((v2l){TS_NONE, TS_NONE}, reinterpret_cast<v2l*>(tv2) + i);
     for (int64_t i = tb + 2 * tv + tid; i < e; i += stride) ts[i] = TS_NONE;
 }
 
