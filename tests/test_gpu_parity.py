@@ -368,6 +368,43 @@ def test_sorted_batches_staged_in_place():
     g.close()
 
 
+@pytest.mark.parametrize("directed", [True, False])
+def test_sorted_batches_continuing_the_last_timestamp(directed):
+    # sorted batches whose first timestamp equals the window's last one: the
+    # batch's first record continues the window's last timestamp group, so
+    # the group starts counted while the batch is staged must compare it with
+    # the window's last record; batch sizes span several 4096-record tiles,
+    # end raggedly, and some batches hold that one timestamp only
+    torch, tw = gpu_or_skip()
+    rng = np.random.default_rng(53 + directed)
+    V = 211
+    g = tw.Graph(V, directed=directed)
+    og = oracle.OracleGraph(V, directed=directed)
+    t_last = 100
+    for b in range(14):
+        n = int(rng.choice([1, 63, 4096, 4097, 9000, 13001]))
+        if b % 5 == 4:
+            t = np.full(n, t_last, np.int64)
+        else:
+            t = np.sort(rng.integers(t_last, t_last + 300, n)).astype(np.int64)
+            t[0] = t_last
+        t_last = int(t[-1])
+        s = rng.integers(0, V, n).astype(np.int32)
+        d = rng.integers(0, V, n).astype(np.int32)
+        assert g.ingest_batch(*to_dev(torch, s, d, t)) == og.ingest_batch(s, d, t), b
+        _views_equal(g, og)
+    for kind in ("uniform", "exponential"):
+        nodes, ts, lens = g.sample_walks(500, 12, hop_bias=kind, hop_tau=50.0, start_bias=kind,
+                                         start_tau=50.0, seed=9)
+        g.sync()
+        r = og.sample_walks(500, 12, hop_bias=kind, hop_tau=50.0, start_bias=kind,
+                            start_tau=50.0, seed=9, with_margin=True)
+        same, boundary = compare_walks((nodes.cpu().numpy(), ts.cpu().numpy(),
+                                        lens.cpu().numpy()), r, kind == "uniform")
+        assert boundary <= 2 and same >= 490, (kind, same, boundary)
+    g.close()
+
+
 def test_weight_walks_follow_the_window():
     # the weight-based picker's cumulative weights are rebuilt after every
     # change of the window (ingest, eviction) and of the time scale
