@@ -1,16 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the streaming temporal-walk hot path on one MI355X.
 
-One step = one pass of the whole path over one batch of synthetic input that
-is already resident in HBM: empty the window, ingest the batch (validate,
-sort, merge, rebuild both views of the dual index), then sample the walks.
+Default workload ("stream"): a 1B-edge synthetic stream (50M nodes, source
+and destination Zipf(1.3), bursty Poisson arrivals) ingested in 100 batches
+of 10M edges under a sliding window of 2e9 time units (about 200M active
+edges once full). One step is one batch: ingest (validate, sort, evict to
+the window, update both views of the dual index), an explicit eviction, then
+2M walks of at most 40 nodes (uniform start edge, linear hops). The first
+batches fill the window untimed; then --warmup untimed batches and --steps
+timed ones. Inputs are resident in HBM before anything is timed.
 
-Default workload ("single"): directed graph, 2M nodes, 100M edges, source and
-destination Zipf(1.2), sorted Poisson arrivals (mean gap 10); 4M walks of at
-most 80 nodes, exponential start and hop bias with tau = 0.1 x time span.
+Other workloads: "single" (2M nodes, 100M edges in one batch, 4M
+exponential walks of length 80), "mixed" (batched walks of uneven lengths
+and six hop biases in one persistent launch), "serve" (the serving loop),
+"tiny".
 
 Prints one JSON line: the metric and its value, the timed steps, the
-workload, the rooflines of the dominant kernels and the oracle's baseline.
+workload, the roofline of the dominant kernel, the whole step against the
+HBM roofline, and the oracle's baseline on the host cores.
 """
 from __future__ import annotations
 
@@ -35,9 +42,9 @@ INT64_MAX = (1 << 63) - 1
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="single",
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="stream",
                     choices=["single", "tiny", "stream", "mixed", "serve"])
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="serve workload: seconds of real-time arrivals")
@@ -52,6 +59,8 @@ def parse():
                     help="single-batch workload: backward walks (in-edges before the current "
                          "time); the in-view's update is part of every timed ingest")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-single", action="store_true",
+                    help="stream workload: skip the single-batch figures that follow it")
     ap.add_argument("--no-probe", action="store_true")
     return ap.parse_args()
 
@@ -114,7 +123,8 @@ def probe_rates(torch, dev):
 
 WALK_SOURCES = ("paper_2605_16182_amd/csrc/walk.hip", "paper_2605_16182_amd/csrc/walk_device.h",
                 "paper_2605_16182_amd/csrc/tw_internal.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_traffic_single_100M.txt")
+TRAFFIC_FILES = {"single": os.path.join(ROOT, "profiles", "walk_traffic_single_100M.txt"),
+                 "stream": os.path.join(ROOT, "profiles", "walk_traffic_stream_1B.txt")}
 
 
 def walk_source_hash():
@@ -130,22 +140,25 @@ def measured_traffic(workload):
     """HBM bytes of one walk launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size),
     or None when that summary does not describe the current walk sources."""
-    if workload != "single" or not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILES.get(workload)
+    if path is None or not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         rec = json.loads(fh.read().split("\n---\n")[0])
     if rec.get("source_sha256") != walk_source_hash():
         return None
     return rec["fetch_bytes"] + rec["write_bytes"]
 
 
-def walk_bytes(walks, hops, max_len, start_bias, hop_bias):
-    """Algorithmic bytes of one walk launch: random 64 B sectors per start and
-    per hop (node record, search leaf, group bounds, chosen edge; uniform
-    picks need no group bounds) plus the walk-major output rows."""
-    start = 3 if start_bias == "uniform" else 4
+def walk_bytes(walks, hops, hop_bias):
+    """Algorithmic bytes of one walk launch: every hop (the start edge
+    included) reads 4 random 64 B sectors (node record, search leaf, group
+    bounds, chosen edge; 3 for a uniform pick, which needs no group bounds)
+    and writes 12 B of output (node and timestamp); every walk also writes
+    its length and first node (8 B). Padding slots of the output rows are
+    not counted."""
     per_hop = 3 if hop_bias == "uniform" else 4
-    return walks * start * SECTOR + hops * per_hop * SECTOR + walks * (12 * max_len + 4)
+    return hops * (per_hop * SECTOR + 12) + walks * 8
 
 
 def ingest_bytes(b_in, kept, evicted, jobs):
@@ -201,135 +214,254 @@ def cpu_baseline(w, tau, gpu_hops_per_step):
     }
 
 
-def stream_cpu_baseline(w, n_batches, hops_per_batch):
-    """The oracle on the stream's first batches: ingest (single-threaded) and
-    1% of each batch's walk ids (OpenMP), scaled to the GPU's hop count."""
+def stream_cpu_baseline(w, gpu_hops_per_batch, first_batches, steady):
+    """The oracle on the stream: the first batches (the window filling) and
+    the steady-state batches in `steady` ({1-based batch: (window content
+    before it, the batch)}; the state before each is set up untimed by one
+    ingest of the window content: for a stream whose timestamps never
+    decrease the index is a function of the window content). Each batch is
+    timed for ingest + evict + the view rebuild (single-threaded, as the
+    oracle runs) and for walks on 1% of the walk ids, on one thread and on
+    every host core."""
     import oracle
     spec = w["stream"]
-    og = oracle.OracleGraph(spec.num_nodes, directed=spec.directed, window=w["window"])
-    t_ing = t_walk = 0.0
-    hops = 0
-    nw = max(1000, w["walks"] // 100)
-    idx = np.arange(0, w["walks"], w["walks"] // nw)[:nw]
+    B, W, L, window = w["batch_edges"], w["walks"], w["max_len"], w["window"]
     threads = oracle.threads()
-    for b, (s, d, t) in enumerate(spec.batches(w["batch_edges"])):
-        if b >= n_batches:
-            break
+    idx = np.arange(0, W, 100, dtype=np.int64)  # 1% of the walk ids
+    kw = dict(hop_bias=w["hop_bias"], start_bias=w["start_bias"], walk_idx=idx)
+
+    def one(og, b, s, d, t):
         t0 = time.perf_counter()
-        og.ingest_batch(s, d, t)
-        og.evict_before(-(1 << 63))
-        og.sizes()
-        t_ing += time.perf_counter() - t0
+        info = og.ingest_batch(s, d, t)
+        og.evict_before(info["t_max"] - window)
+        og.sizes()  # builds the views
+        t_ing = time.perf_counter() - t0
         t0 = time.perf_counter()
-        r = og.sample_walks(w["walks"], w["max_len"], hop_bias=w["hop_bias"],
-                            start_bias=w["start_bias"], seed=b, walk_idx=idx, threads=threads)
-        t_walk += time.perf_counter() - t0
-        hops += int(np.maximum(r["len"] - 1, 0).sum())
-    hop_rate = hops / t_walk
-    per_batch = t_ing / n_batches + hops_per_batch / hop_rate
-    return {"value": hops_per_batch / per_batch, "unit": "hops/s", "cores": threads,
-            "kind": "oracle", "ingest_edges_per_s": n_batches * w["batch_edges"] / t_ing,
-            "walk_hops_per_s": hop_rate,
-            "sample": (f"oracle on the first {n_batches} batches of the stream (ingest "
-                       f"single-threaded, window still filling) and {len(idx)} walk ids (1%) per "
-                       f"batch with {threads} OpenMP threads; hop rate applied to the GPU's mean "
-                       f"hops per steady-state batch")}
+        og.sample_walks(W, L, seed=b, threads=1, **kw)
+        t_w1 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        r = og.sample_walks(W, L, seed=b, threads=threads, **kw)
+        t_wn = time.perf_counter() - t0
+        hops = int(np.maximum(r["len"] - 1, 0).sum())
+        return t_ing, hops / t_w1, hops / t_wn
+
+    rows = {}
+    og = oracle.OracleGraph(spec.num_nodes, directed=spec.directed, window=window)
+    for b, (s, d, t) in enumerate(first_batches):
+        rows[b + 1] = one(og, b, s, d, t)
+    del og
+    for sb, (content, nxt) in sorted(steady.items()):
+        og = oracle.OracleGraph(spec.num_nodes, directed=spec.directed, window=window)
+        og.ingest_batch(*content)
+        rows[sb] = one(og, sb - 1, *nxt)
+        del og
+    first = len(first_batches)
+    ss = [rows[b] for b in steady]
+    t_ing = float(np.mean([r[0] for r in ss]))
+    rate1 = float(np.mean([r[1] for r in ss]))
+    rate_n = float(np.mean([r[2] for r in ss]))
+    per_batch = t_ing + gpu_hops_per_batch / rate_n
+    return {
+        "value": gpu_hops_per_batch / per_batch, "unit": "hops/s", "cores": threads,
+        "kind": "oracle",
+        "ingest_edges_per_s": B / t_ing, "walk_hops_per_s": rate_n,
+        "walk_hops_per_s_single_thread": rate1,
+        "per_batch": {str(b): {"ingest_evict_views_s": r[0], "walk_hops_per_s_1_thread": r[1],
+                               f"walk_hops_per_s_{threads}_threads": r[2]}
+                      for b, r in sorted(rows.items())},
+        "sample": (f"oracle on stream batches 1-{first} (window filling) and "
+                   f"{', '.join(map(str, sorted(steady)))} (window full; the state before each set up "
+                   f"untimed by one ingest of the window content): ingest + evict + view "
+                   f"rebuild single-threaded; walks on 1% of the walk ids ({len(idx)}), timed "
+                   f"on 1 thread and on {threads}; value = the GPU's hops per steady-state "
+                   f"batch over (oracle ingest + those hops at the {threads}-thread rate)"),
+    }
+
+
+def h2d_ms(torch, dev, batch):
+    """Host-to-device copy of one batch from pinned host memory (median of 3)."""
+    host = [torch.from_numpy(a).pin_memory() for a in batch]
+    devs = [torch.empty_like(h, device=dev) for h in host]
+    times = []
+    for _ in range(4):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for h, d in zip(host, devs):
+            d.copy_(h, non_blocking=True)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return float(np.median(times[1:]))
+
+
+WALK_KERNEL = "k_walk_full"
 
 
 def run_stream(args, torch, tw, w, dev, gather_rate, copy_bw):
-    """Streaming window: ingest 10M-edge batches under the sliding window,
-    evict, then sample the batch's walks; every batch is timed."""
+    """Streaming window, the default workload: a 1B-edge stream in 100
+    batches of 10M edges under a 2e9 window. Per batch: ingest (which
+    evicts to the window), an explicit evict_before(t_max - window), then the
+    batch's walks. One step is one batch: the first batches fill the window
+    untimed, then `warmup` untimed batches, then `steps` timed batches."""
     spec = w["stream"]
     B = w["batch_edges"]
-    nb = spec.num_edges // B if args.batches <= 0 else args.batches
+    total = spec.num_edges // B if args.batches <= 0 else args.batches
+    K, Wu = args.steps, args.warmup
+    if K < 1 or K + Wu > total:
+        raise SystemExit(f"stream: need 1 <= steps and steps + warmup <= {total} batches")
+    fill = total - K - Wu
     t0 = time.perf_counter()
-    batches = []
+    batches, host_keep = [], {}
+    # host copies for the oracle baseline: the first batches, and the window
+    # content before each steady-state batch it times (with that batch)
+    want_cpu = not args.no_cpu_baseline
+    first_n = min(5, total)
+    steady_at = [b for b in (96,) if b <= total] if total >= 96 else [total]
+    first_host, window_host, steady_host = [], [], {}
     for b, (s, d, t) in enumerate(spec.batches(B)):
-        if b >= nb:
+        if b >= total:
             break
         batches.append((torch.from_numpy(s).to(dev), torch.from_numpy(d).to(dev),
                         torch.from_numpy(t).to(dev)))
+        if b == total - 1:
+            host_keep["last"] = (s, d, t)
+        if want_cpu:
+            if b < first_n:
+                first_host.append((s, d, t))
+            if b + 1 in steady_at and window_host:
+                content = tuple(np.concatenate([x[i] for x in window_host]) for i in range(3))
+                lo = int(np.searchsorted(content[2], int(window_host[-1][2][-1]) - w["window"]))
+                steady_host[b + 1] = (tuple(x[lo:] for x in content), (s, d, t))
+            window_host.append((s, d, t))
+            cut = int(t[-1]) - w["window"]
+            while window_host and int(window_host[0][2][-1]) < cut:
+                window_host.pop(0)
         if b % 10 == 0:
             print(f"# generated batch {b}", file=sys.stderr, flush=True)
-    print(f"# {nb} batches resident in HBM ({time.perf_counter() - t0:.1f}s)", file=sys.stderr,
-          flush=True)
+    del window_host
+    gen_s = time.perf_counter() - t0
+    print(f"# {total} batches resident in HBM ({gen_s:.1f}s)", file=sys.stderr, flush=True)
     W, L = w["walks"], w["max_len"]
     out = (torch.empty((W, L), dtype=torch.int32, device=dev),
            torch.empty((W, L), dtype=torch.int64, device=dev))
     # every batch's walk lengths are kept and its hops counted after the
     # timed region, so that no counting runs between the batches
-    lens_all = torch.empty((nb, W), dtype=torch.int32, device=dev)
+    lens_all = torch.empty((total, W), dtype=torch.int32, device=dev)
     g = tw.Graph(spec.num_nodes, directed=spec.directed, window=w["window"])
-    m_dev = []
-    per_batch = []  # (accepted, evicted, node-view jobs, compaction) of every ingest
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(nb)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for b, (s, d, t) in enumerate(batches):
+    per_batch = []  # (accepted, evicted, node-view jobs, compaction, active) of every ingest
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(total)]
+
+    def batch(b):
+        s, d, t = batches[b]
         e = evs[b]
         e[0].record()
         info = g.ingest_batch(s, d, t)
         st = g.index_stats()  # host counters of the ingest just done
-        per_batch.append((info["accepted"], info["evicted"], st["jobs"], st["full_rewrite"]))
+        per_batch.append((info["accepted"], info["evicted"], st["jobs"], st["full_rewrite"],
+                          info["active_edges"]))
         e[1].record()
         g.evict_before(info["t_max"] - w["window"])
         e[2].record()
         g.sample_walks(W, L, hop_bias=w["hop_bias"], start_bias=w["start_bias"], seed=b,
                        dispatch=args.dispatch, out=(out[0], out[1], lens_all[b]))
         e[3].record()
-        m_dev.append(info["active_edges"])
+
+    for b in range(fill + Wu):
+        batch(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in range(fill + Wu, total):
+        batch(b)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    timed = slice(fill + Wu, total)
     hops = (lens_all - 1).clamp_min(0).sum(1, dtype=torch.int64).cpu().numpy()
     ing = np.array([e[0].elapsed_time(e[1]) for e in evs])
     ev = np.array([e[1].elapsed_time(e[2]) for e in evs])
     wk = np.array([e[2].elapsed_time(e[3]) for e in evs])
-    # steady state: the window has filled (the last 80% of the batches)
-    ss = slice(nb // 5, nb) if nb >= 5 else slice(0, nb)
+    pb = np.array(per_batch, dtype=np.float64)
+    hops_t = float(np.mean(hops[timed]))
+    ing_t, ev_t, wk_t = (float(np.mean(x[timed])) for x in (ing, ev, wk))
+    step_ms = ing_t + ev_t + wk_t
+    m_t = float(np.mean(pb[timed, 4]))
+
+    # walk phase alone under each dispatch on the final window (plain
+    # full-walk against the work queue and the cooperative regrouping)
+    compare = {}
+    last = total - 1
+    for disp in ("full_walk", "queue", "coop"):
+        times = []
+        for rep in range(4):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            g.sample_walks(W, L, hop_bias=w["hop_bias"], start_bias=w["start_bias"], seed=last,
+                           dispatch=disp, out=(out[0], out[1], lens_all[last]))
+            e1.record()
+            torch.cuda.synchronize()
+            if rep:
+                times.append(e0.elapsed_time(e1))
+        h = int((lens_all[last] - 1).clamp_min(0).sum(dtype=torch.int64).item())
+        assert h == int(hops[last]), f"{disp} walks differ in length"
+        ms = float(np.median(times))
+        compare[disp] = {"walk_ms": ms, "walk_hops_per_s": h / (ms * 1e-3)}
+    g.close()
+    del batches
+    torch.cuda.empty_cache()
+    h2d = h2d_ms(torch, dev, host_keep["last"])
+
+    wb = walk_bytes(W, hops_t, w["hop_bias"])
+    ib = ingest_bytes(B, float(np.mean(pb[timed, 0])), float(np.mean(pb[timed, 1])),
+                      float(np.mean(pb[timed, 2])))
+    rb = rebuild_bytes(B, m_t, m_t, spec.num_nodes)
+    peak = HBM_PEAK_GBS * 1e9
     per_hop = 3 if w["hop_bias"] == "uniform" else 4
-    m_ss = float(np.mean(m_dev[ss]))
-    pb = np.array(per_batch, dtype=np.float64)[ss]
-    ib = ingest_bytes(B, float(pb[:, 0].mean()), float(pb[:, 1].mean()), float(pb[:, 2].mean()))
-    rb = rebuild_bytes(B, m_ss, m_ss, spec.num_nodes)
-    roof_ing = ib / copy_bw * 1e3 if copy_bw else None
-    roof_walk = float(np.mean(hops[ss])) / (gather_rate / per_hop) * 1e3 if gather_rate else None
-    meas = float(np.mean(ing[ss] + ev[ss] + wk[ss]))
     res = {
         "metric": METRIC,
-        "value": float(hops.sum()) / wall,
+        "value": float(hops[timed].sum()) / wall,
         "unit": "hops/s",
-        "n_gpus": 1, "steps": nb, "warmup": 0,
-        "ms_per_step": wall * 1e3 / nb,
+        "n_gpus": 1, "steps": K, "warmup": Wu,
+        "ms_per_step": wall * 1e3 / K,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int64+f64", "data": "synthetic",
-        "config": describe("stream", w, 0.0) | {"batches": nb, "batch_edges": B},
+        "config": describe("stream", w, 0.0) | {
+            "batches": total, "batch_edges": B, "window_fill_batches": fill,
+            "timed_batches": f"{fill + Wu + 1}..{total}"},
         "dispatch": args.dispatch,
-        "steady_state": {
-            "batches": f"{ss.start}..{nb - 1}",
-            "active_edges": m_ss,
-            "ingest_ms": float(np.mean(ing[ss])), "evict_ms": float(np.mean(ev[ss])),
-            "walk_ms": float(np.mean(wk[ss])), "hops_per_batch": float(np.mean(hops[ss])),
-            "ingest_edges_per_s": B / (float(np.mean(ing[ss])) * 1e-3),
-            "walk_hops_per_s": float(np.mean(hops[ss])) / (float(np.mean(wk[ss])) * 1e-3),
-            "node_view_jobs": float(pb[:, 2].mean()), "evicted": float(pb[:, 1].mean()),
-            "compactions": int(pb[:, 3].sum()),
-        },
-        "roofline": {"bound": "hbm", "ingest_roof_ms": roof_ing, "walk_roof_ms": roof_walk,
-                     "measured_ms": meas,
-                     "frac": ((roof_ing + roof_walk) / meas) if roof_ing and roof_walk else None,
-                     "ingest_algorithmic_bytes": ib, "copy_GBps_measured": copy_bw / 1e9,
-                     "random_sectors_per_s": gather_rate},
-        # the same measurement against an ingest that rebuilds both views
-        "roofline_rebuild_model": {
-            "ingest_roof_ms": rb / copy_bw * 1e3 if copy_bw else None,
-            "ingest_bytes": rb,
-            "frac": ((rb / copy_bw * 1e3 + roof_walk) / meas) if copy_bw and roof_walk else None},
+        "hops_per_step": hops_t,
+        "active_edges": m_t,
+        "ingest_ms": ing_t, "evict_ms": ev_t, "walk_ms": wk_t,
+        "ingest_edges_per_s": B / ((ing_t + ev_t) * 1e-3),
+        "ingest_edges_per_s_with_h2d": B / ((ing_t + ev_t + h2d) * 1e-3),
+        "h2d_ms": h2d,
+        "walk_hops_per_s": hops_t / (wk_t * 1e-3),
+        "node_view_jobs": float(np.mean(pb[timed, 2])),
+        "compactions": int(pb[timed, 3].sum()),
+        "plain_vs_tuned": compare,
+        "roofline": {"bound": "hbm", "kernel": WALK_KERNEL,
+                     "achieved": wb / (wk_t * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": wb / (wk_t * 1e-3) / peak, "traffic": measured_traffic("stream"),
+                     "algorithmic_bytes": wb,
+                     "bytes_model": f"hops x ({per_hop} x 64 + 12) + walks x 8"},
+        # the whole batch against 8 TB/s: the ingest as a rebuild of both
+        # views would move it, plus the walks
+        "roofline_step": {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "ingest_bytes_rebuild_model": rb, "walk_bytes": wb,
+                          "roof_ms": (rb + wb) / peak * 1e3, "measured_ms": step_ms,
+                          "frac": (rb + wb) / peak * 1e3 / step_ms},
+        "roofline_step_incremental": {"ingest_bytes": ib, "walk_bytes": wb,
+                                      "roof_ms": (ib + wb) / peak * 1e3,
+                                      "frac": (ib + wb) / peak * 1e3 / step_ms},
+        "roofline_step_probed": {
+            "copy_GBps_measured": copy_bw / 1e9, "random_sectors_per_s": gather_rate,
+            "ingest_roof_ms": ib / copy_bw * 1e3 if copy_bw else None,
+            "walk_roof_ms": hops_t * per_hop / gather_rate * 1e3 if gather_rate else None,
+            "frac": ((ib / copy_bw + hops_t * per_hop / gather_rate) * 1e3 / step_ms)
+            if copy_bw and gather_rate else None},
     }
-    g.close()
     if not args.no_cpu_baseline:
         print("# oracle baseline ...", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = stream_cpu_baseline(w, 3, float(np.mean(hops[ss])))
-    print(json.dumps(res), flush=True)
+        res["cpu_baseline"] = stream_cpu_baseline(w, hops_t, first_host, steady_host)
+    return res
 
 
 def run_mixed(args, torch, tw, w, dev, gather_rate):
@@ -557,30 +689,12 @@ def run_serve(args, torch, tw, w, dev, gather_rate):
     print(json.dumps(res), flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
-    import torch
-    import synth
-    import paper_2605_16182_amd as tw
-
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
-    w = synth.workload(args.workload)
-    if args.workload == "serve":
-        gather_rate, _ = (0.0, 0.0) if args.no_probe else probe_rates(torch, dev)
-        return run_serve(args, torch, tw, w, dev, gather_rate)
-    if args.workload == "mixed":
-        gather_rate, _ = (0.0, 0.0) if args.no_probe else probe_rates(torch, dev)
-        return run_mixed(args, torch, tw, w, dev, gather_rate)
-    if args.workload == "stream":
-        gather_rate, copy_bw = (0.0, 0.0) if args.no_probe else probe_rates(torch, dev)
-        return run_stream(args, torch, tw, w, dev, gather_rate, copy_bw)
+def run_single(args, torch, tw, w, dev, gather_rate, copy_bw):
+    """One batch at scale (the "single" workload): each step empties the
+    window, ingests the whole 100M-edge batch and samples the 4M walks."""
     if args.hop_bias:
         w = dict(w, hop_bias=args.hop_bias)
+    name = args.workload if args.workload != "stream" else "single"
     spec = w["stream"]
     t0 = time.perf_counter()
     src, dst, ts = spec.all()
@@ -595,11 +709,6 @@ def main():
            torch.empty((W, L), dtype=torch.int64, device=dev),
            torch.empty(W, dtype=torch.int32, device=dev))
     print(f"# inputs generated in {gen_s:.1f}s; span {span}; tau {tau}", file=sys.stderr, flush=True)
-
-    gather_rate, copy_bw = (0.0, 0.0) if args.no_probe else probe_rates(torch, dev)
-    print(f"# probe: {gather_rate / 1e9:.2f} G random sectors/s, copy {copy_bw / 1e9:.0f} GB/s",
-          file=sys.stderr, flush=True)
-
     g = tw.Graph(spec.num_nodes, directed=spec.directed, window=w["window"])
     walk_kw = dict(hop_bias=w["hop_bias"], hop_tau=tau, start_bias=w["start_bias"],
                    start_tau=tau, seed=42, dispatch=args.dispatch, out=out,
@@ -675,7 +784,7 @@ def main():
             torch.cuda.synchronize()
             pair.append(e0.elapsed_time(e1))
         weight_build_ms = pair[0] - pair[1]
-    wb = walk_bytes(W, hops, L, w["start_bias"], w["hop_bias"])
+    wb = walk_bytes(W, hops, w["hop_bias"])
     st = g.index_stats()
     ib = ingest_bytes(spec.num_edges, m_active, 0, st["jobs"])
     walk_gbs = wb / (walk_ms * 1e-3) / 1e9
@@ -696,7 +805,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int64+f64",
         "data": "synthetic",
-        "config": dict(describe(args.workload, w, tau),
+        "config": dict(describe(name, w, tau),
                        **({"direction": "backward"} if args.direction == "backward" else {})),
         "dispatch": args.dispatch,
         "hops_per_step": hops,
@@ -705,9 +814,9 @@ def main():
         "ingest_ms": ingest_ms,
         "walk_hops_per_s": walk_hops_s,
         "ingest_edges_per_s": spec.num_edges / (ingest_ms * 1e-3),
-        "roofline": {"bound": "hbm", "kernel": "walk launch (k_fill_outputs + k_walk_full)",
+        "roofline": {"bound": "hbm", "kernel": WALK_KERNEL,
                      "achieved": walk_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": walk_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
+                     "frac": walk_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(name),
                      "algorithmic_bytes": wb},
         "roofline_ingest": {"bound": "hbm", "achieved": ingest_gbs, "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": ingest_gbs / HBM_PEAK_GBS,
@@ -726,7 +835,46 @@ def main():
     if not args.no_cpu_baseline and w["hop_bias"] != "weight" and args.direction == "forward":
         print("# oracle baseline ...", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(w, tau, hops)
-    print(json.dumps(res), flush=True)
+    return res
+
+
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import synth
+    import paper_2605_16182_amd as tw
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    w = synth.workload(args.workload)
+    gather_rate, copy_bw = (0.0, 0.0) if args.no_probe else probe_rates(torch, dev)
+    print(f"# probe: {gather_rate / 1e9:.2f} G random sectors/s, copy {copy_bw / 1e9:.0f} GB/s",
+          file=sys.stderr, flush=True)
+    if args.workload == "serve":
+        return run_serve(args, torch, tw, w, dev, gather_rate)
+    if args.workload == "mixed":
+        return run_mixed(args, torch, tw, w, dev, gather_rate)
+    if args.workload == "stream":
+        res = run_stream(args, torch, tw, w, dev, gather_rate, copy_bw)
+        if not args.no_single:
+            # the single-batch workload's figures beside the stream's (its
+            # own timed steps, after the stream's)
+            one = argparse.Namespace(**{**vars(args), "steps": 5, "warmup": 1,
+                                        "no_cpu_baseline": True})
+            r = run_single(one, torch, tw, synth.workload("single"), dev, gather_rate, copy_bw)
+            res["single_batch"] = {k: r[k] for k in (
+                "config", "ms_per_step", "value", "hops_per_step", "walk_ms", "ingest_ms",
+                "walk_hops_per_s", "ingest_edges_per_s", "plain_vs_tuned", "roofline",
+                "gather_roofline")}
+        print(json.dumps(res), flush=True)
+        return
+    print(json.dumps(run_single(args, torch, tw, w, dev, gather_rate, copy_bw)), flush=True)
 
 
 if __name__ == "__main__":

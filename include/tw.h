@@ -313,6 +313,7 @@ typedef struct {
     double queue_ms;      /* submission to launch */
     double latency_ms;    /* submission to completion seen by the worker */
     tw_ingest_info ingest;/* ingest batches: the counts of that ingest */
+    int64_t trial_cap_hits; /* walks of the request that node2vec's trial cap ended */
 } tw_request_result;
 
 typedef struct {

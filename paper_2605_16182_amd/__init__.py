@@ -73,7 +73,8 @@ class _ServerConfig(_c.Structure):
 class _RequestResult(_c.Structure):
     _fields_ = [("status", _c.c_int), ("d_nodes", _c.c_void_p), ("d_ts", _c.c_void_p),
                 ("d_len", _c.c_void_p), ("num_walks", _c.c_int64), ("max_len", _c.c_int32),
-                ("queue_ms", _c.c_double), ("latency_ms", _c.c_double), ("ingest", _Info)]
+                ("queue_ms", _c.c_double), ("latency_ms", _c.c_double), ("ingest", _Info),
+                ("trial_cap_hits", _c.c_int64)]
 
 
 class _ServerCounters(_c.Structure):
@@ -401,7 +402,8 @@ class Server:
         self._keep.pop(rid, None)
         return {"status": int(out.status), "num_walks": int(out.num_walks),
                 "max_len": int(out.max_len), "queue_ms": out.queue_ms,
-                "latency_ms": out.latency_ms, "ingest": _info(out.ingest)}
+                "latency_ms": out.latency_ms, "ingest": _info(out.ingest),
+                "trial_cap_hits": int(out.trial_cap_hits)}
 
     def result(self, rid: int):
         """(nodes, ts, len) of a finished request, copied into new tensors."""

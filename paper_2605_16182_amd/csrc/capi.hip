@@ -58,6 +58,15 @@ tw_status check_device_flags(tw_graph* g) {
     return st;
 }
 
+// A graph whose last ingest or eviction failed midway holds a partly
+// updated index: every later call that reads or changes it is refused.
+tw_status refuse_broken(const tw_graph* g, const char* what) {
+    if (!g->broken) return TW_OK;
+    return fail(TW_EDEVICE, std::string(what) +
+                                ": the graph is unusable (an ingest or eviction failed midway, "
+                                "out of device memory); destroy it");
+}
+
 }  // namespace
 
 extern "C" {
@@ -103,24 +112,22 @@ tw_status tw_ingest_batch(tw_graph* g, const int32_t* d_src, const int32_t* d_ds
     if (n < 0 || (n > 0 && (!d_src || !d_dst || !d_ts)))
         return fail(TW_EINVAL, "tw_ingest_batch: need n >= 0 and non-null arrays");
     return guarded("tw_ingest_batch", [&]() -> tw_status {
-        tw_status st = check_device_flags(g);
+        tw_status st = refuse_broken(g, "tw_ingest_batch");
+        if (st == TW_OK) st = check_device_flags(g);
         if (st != TW_OK) return st;
         tw::Error e{TW_OK, ""};
-        if (tw::ingest(g, d_src, d_dst, d_ts, n, info, e) == TW_OK && g->rev)
-            tw::ingest(g->rev, d_dst, d_src, d_ts, n, nullptr, e);  // the in-view
-        return report(e.code, e);
+        return report(tw::ingest_views(g, d_src, d_dst, d_ts, n, info, e), e);
     });
 }
 
 tw_status tw_evict_before(tw_graph* g, int64_t t_cutoff, int64_t* n_evicted) {
     if (!g) return fail(TW_EINVAL, "tw_evict_before: null graph");
     return guarded("tw_evict_before", [&]() -> tw_status {
-        tw_status st = check_device_flags(g);
+        tw_status st = refuse_broken(g, "tw_evict_before");
+        if (st == TW_OK) st = check_device_flags(g);
         if (st != TW_OK) return st;
         tw::Error e{TW_OK, ""};
-        if (tw::evict_before(g, t_cutoff, n_evicted, e) == TW_OK && g->rev)
-            tw::evict_before(g->rev, t_cutoff, nullptr, e);  // the in-view
-        return report(e.code, e);
+        return report(tw::evict_views(g, t_cutoff, n_evicted, e), e);
     });
 }
 
@@ -128,6 +135,7 @@ tw_status tw_sample_walks(tw_graph* g, const tw_walk_params* params, int32_t* d_
                           int64_t* d_ts, int32_t* d_len) {
     if (!g) return fail(TW_EINVAL, "tw_sample_walks: null graph");
     return guarded("tw_sample_walks", [&]() -> tw_status {
+        if (refuse_broken(g, "tw_sample_walks") != TW_OK) return TW_EDEVICE;
         tw::Error e{TW_OK, ""};
         return report(tw::sample_walks(g, params, d_nodes, d_ts, d_len, e), e);
     });
@@ -137,6 +145,7 @@ tw_status tw_sample_walks_batch(tw_graph* g, const tw_batch_params* params, int3
                                 int64_t* d_ts, int32_t* d_len) {
     if (!g) return fail(TW_EINVAL, "tw_sample_walks_batch: null graph");
     return guarded("tw_sample_walks_batch", [&]() -> tw_status {
+        if (refuse_broken(g, "tw_sample_walks_batch") != TW_OK) return TW_EDEVICE;
         tw::Error e{TW_OK, ""};
         return report(tw::sample_walks_batch(g, params, d_nodes, d_ts, d_len, e), e);
     });
@@ -155,6 +164,7 @@ tw_status tw_autotune(tw_graph* g, const tw_walk_params* params, int64_t sample_
                       int32_t* d_nodes, int64_t* d_ts, int32_t* d_len, int32_t best[2]) {
     if (!g) return fail(TW_EINVAL, "tw_autotune: null graph");
     return guarded("tw_autotune", [&]() -> tw_status {
+        if (refuse_broken(g, "tw_autotune") != TW_OK) return TW_EDEVICE;
         tw::Error e{TW_OK, ""};
         return report(tw::autotune(g, params, sample_walks, d_nodes, d_ts, d_len, best, e), e);
     });
@@ -162,6 +172,7 @@ tw_status tw_autotune(tw_graph* g, const tw_walk_params* params, int64_t sample_
 
 tw_status tw_server_create(tw_graph* g, const tw_server_config* cfg, tw_server** out) {
     return guarded("tw_server_create", [&]() -> tw_status {
+        if (g && refuse_broken(g, "tw_server_create") != TW_OK) return TW_EDEVICE;
         tw::Error e{TW_OK, ""};
         return report(tw::server_create(g, cfg, out, e), e);
     });
@@ -247,6 +258,7 @@ tw_status tw_view_sizes(tw_graph* g, int64_t out[4]) {
     if (hipStreamSynchronize(g->stream) != hipSuccess)
         return fail(TW_EDEVICE, "tw_view_sizes: stream synchronisation failed");
     return guarded("tw_view_sizes", [&]() -> tw_status {
+        if (refuse_broken(g, "tw_view_sizes") != TW_OK) return TW_EDEVICE;
         tw::Error e{TW_OK, ""};
         if (!g->rec.p && tw::init_empty(g, e) != TW_OK) return report(e.code, e);
         int64_t gn = 0;
@@ -264,6 +276,7 @@ tw_status tw_export_views(tw_graph* g, int32_t* src, int32_t* dst, int64_t* ts, 
                           int64_t* n_goff, int64_t* n_ebeg, int64_t* n_gbeg) {
     if (!g) return fail(TW_EINVAL, "tw_export_views: null graph");
     return guarded("tw_export_views", [&]() -> tw_status {
+        if (refuse_broken(g, "tw_export_views") != TW_OK) return TW_EDEVICE;
         tw::Error e{TW_OK, ""};
         if (!g->rec.p && tw::init_empty(g, e) != TW_OK) return report(e.code, e);
         return report(tw::export_views(g, src, dst, ts, g_ts, g_off, n_dst, n_ts, n_gts, n_goff,

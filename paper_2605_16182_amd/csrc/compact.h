@@ -114,7 +114,7 @@ hipError_t compact(const Op& op, int64_t n, uint32_t* total, DevBuf& tiles, Work
                    hipStream_t s, bool counted = false) {
     if (n <= 0) return scan_exclusive_u32(nullptr, nullptr, 0, total, ws, s);
     const int64_t nb = ceil_div(n, (int64_t)CT_TILE);
-    hipError_t e = ensure(tiles, sizeof(uint32_t) * (nb + 1));
+    hipError_t e = ensure(tiles, sizeof(uint32_t) * (nb + 1), s);
     if (e != hipSuccess) return e;
     uint32_t* cnt = tiles.as<uint32_t>();
     if (!counted)

@@ -339,10 +339,10 @@ int64_t* i64_slot(tw_graph* g, int k) { return g->scal.as<int64_t>() + k; }
 tw_status ensure_common(tw_graph* g, Error& err) {
     if (!g->err.p) {
         // device error flags start cleared
-        TW_HIP(ensure(g->err, sizeof(uint32_t) * 4));
+        TW_HIP(ensure(g->err, sizeof(uint32_t) * 4, g->stream));
         TW_HIP(hipMemsetAsync(g->err.p, 0, sizeof(uint32_t) * 4, g->stream));
     }
-    TW_HIP(ensure(g->scal, SCALAR_BYTES));
+    TW_HIP(ensure(g->scal, SCALAR_BYTES, g->stream));
     if (!g->h_scal) TW_HIP(hipHostMalloc(&g->h_scal, SCALAR_BYTES + 16, hipHostMallocDefault));
     return TW_OK;
 }
@@ -353,9 +353,9 @@ tw_status ensure_common(tw_graph* g, Error& err) {
 // groups must be rebuilt afterwards.
 tw_status grow_window(tw_graph* g, int64_t cap, Error& err) {
     cap = std::min<int64_t>(cap, (int64_t)UINT32_MAX - 1);
-    TW_HIP(ensure(g->a_src, sizeof(int32_t) * cap));
-    TW_HIP(ensure(g->a_dst, sizeof(int32_t) * cap));
-    TW_HIP(ensure(g->a_ts, sizeof(int64_t) * cap));
+    TW_HIP(ensure(g->a_src, sizeof(int32_t) * cap, g->stream));
+    TW_HIP(ensure(g->a_dst, sizeof(int32_t) * cap, g->stream));
+    TW_HIP(ensure(g->a_ts, sizeof(int64_t) * cap, g->stream));
     hipStream_t s = g->stream;
     if (g->m > 0) {
         TW_HIP(hipMemcpyAsync(g->a_src.p, g->e_src.as<int32_t>() + g->e_base, 4 * g->m,
@@ -368,10 +368,10 @@ tw_status grow_window(tw_graph* g, int64_t cap, Error& err) {
     std::swap(g->e_src, g->a_src);
     std::swap(g->e_dst, g->a_dst);
     std::swap(g->e_ts, g->a_ts);
-    TW_HIP(ensure(g->a_src, sizeof(int32_t) * cap));
-    TW_HIP(ensure(g->a_dst, sizeof(int32_t) * cap));
-    TW_HIP(ensure(g->a_ts, sizeof(int64_t) * cap));
-    TW_HIP(ensure(g->gg_off, sizeof(uint32_t) * (cap + 2)));
+    TW_HIP(ensure(g->a_src, sizeof(int32_t) * cap, g->stream));
+    TW_HIP(ensure(g->a_dst, sizeof(int32_t) * cap, g->stream));
+    TW_HIP(ensure(g->a_ts, sizeof(int64_t) * cap, g->stream));
+    TW_HIP(ensure(g->gg_off, sizeof(uint32_t) * (cap + 2), g->stream));
     int64_t held = (int64_t)UINT32_MAX - 1;
     for (const DevBuf* b : {&g->e_src, &g->e_dst, &g->a_src, &g->a_dst})
         held = std::min<int64_t>(held, (int64_t)(b->bytes / 4));
@@ -438,8 +438,8 @@ tw_status finish_ts(tw_graph* g, bool gg_full, int64_t gg_old, int64_t gg_evicte
 
 }  // namespace
 
-tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int64_t* ts,
-                 int64_t n, tw_ingest_info* info, Error& err) {
+tw_status ingest_prepare(tw_graph* g, const int32_t* src, const int32_t* dst, const int64_t* ts,
+                         int64_t n, IngestPlan& P, Error& err) {
     hipStream_t s = g->stream;
     if (ensure_common(g, err) != TW_OK) return err.code;
     if (!g->rec.p && init_empty(g, err) != TW_OK) return err.code;
@@ -452,25 +452,24 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
     // the alternate buffers, else the staging buffers. A sorted batch staged
     // in the tail is appended where it lies; one staged in the alternates
     // becomes the window by a swap when nothing of the old window survives.
-    enum Place { IN_TAIL, IN_ALT, IN_BUF };
-    Place place = IN_BUF;
+    int place = IngestPlan::IN_BUF;
     int32_t *s_src, *s_dst;
     int64_t* s_ts;
     if (B > 0 && g->e_base + g->m + B <= g->e_cap) {
-        place = IN_TAIL;
+        place = IngestPlan::IN_TAIL;
         const int64_t at = g->e_base + g->m;
         s_src = g->e_src.as<int32_t>() + at;
         s_dst = g->e_dst.as<int32_t>() + at;
         s_ts = g->e_ts.as<int64_t>() + at;
     } else if (B > 0 && B <= g->e_cap) {
-        place = IN_ALT;
+        place = IngestPlan::IN_ALT;
         s_src = g->a_src.as<int32_t>();
         s_dst = g->a_dst.as<int32_t>();
         s_ts = g->a_ts.as<int64_t>();
     } else {
-        TW_HIP(ensure(g->b_src, sizeof(int32_t) * (B + 1)));
-        TW_HIP(ensure(g->b_dst, sizeof(int32_t) * (B + 1)));
-        TW_HIP(ensure(g->b_ts, sizeof(int64_t) * (B + 1)));
+        TW_HIP(ensure(g->b_src, sizeof(int32_t) * (B + 1), g->stream));
+        TW_HIP(ensure(g->b_dst, sizeof(int32_t) * (B + 1), g->stream));
+        TW_HIP(ensure(g->b_ts, sizeof(int64_t) * (B + 1), g->stream));
         s_src = g->b_src.as<int32_t>();
         s_dst = g->b_dst.as<int32_t>();
         s_ts = g->b_ts.as<int64_t>();
@@ -486,7 +485,7 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
     const int stage_has_last = g->m > 0 ? 1 : 0;
     if (staged_counts) {
         const int64_t ntiles = ceil_div(n, (int64_t)GS_TILE);
-        TW_HIP(ensure(g->gs_tiles, sizeof(uint32_t) * (ntiles + 1)));
+        TW_HIP(ensure(g->gs_tiles, sizeof(uint32_t) * (ntiles + 1), g->stream));
         hipLaunchKernelGGL(k_stage_count, dim3((unsigned)ntiles), dim3(T), 0, s, src, dst, ts, n,
                            g->V, s_src, s_dst, s_ts, errf + 1, mm, unsorted, stage_has_last,
                            g->t_max, g->gs_tiles.as<uint32_t>());
@@ -516,19 +515,21 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
         err = Error{TW_ERANGE, "ingest_batch: node id outside [0, num_nodes)"};
         return err.code;
     }
-    int64_t bmin = 0, bmax = 0;
+    // the clock advances only when the ingest completes
+    int64_t bmin = 0, bmax = 0, t_now = g->t_now;
+    bool has_time = g->has_time;
     if (n > 0) {
         bmin = unord(hmm[0]);
         bmax = unord(hmm[1]);
-        g->t_now = g->has_time ? std::max(g->t_now, bmax) : bmax;
-        g->has_time = true;
+        t_now = has_time ? std::max(t_now, bmax) : bmax;
+        has_time = true;
     }
     const bool sorted = hunsorted == 0;
 
     // window cut, late drop and eviction counts
-    const bool windowed = g->window > 0 && g->has_time;
+    const bool windowed = g->window > 0 && has_time;
     int64_t cut = INT64_MIN;
-    if (windowed) cut = (g->t_now < INT64_MIN + g->window) ? INT64_MIN : g->t_now - g->window;
+    if (windowed) cut = (t_now < INT64_MIN + g->window) ? INT64_MIN : t_now - g->window;
     const bool drop = windowed && B > 0 && bmin < cut;
     const bool evicting = windowed && g->m > 0 && g->t_min < cut;
     int64_t kept = B, evicted = 0, gg_evicted = 0, batch_first = bmin, drop_lo = 0;
@@ -541,13 +542,13 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
         kept = B - drop_lo;
         batch_first = host_i64(g, SLOT_I64_FIRST_KEPT);
     } else if (!sorted && B > 0) {
-        TW_HIP(ensure(g->b_keys, sizeof(uint64_t) * (B + 1)));
-        TW_HIP(ensure(g->b_vals, sizeof(uint32_t) * (B + 1)));
+        TW_HIP(ensure(g->b_keys, sizeof(uint64_t) * (B + 1), g->stream));
+        TW_HIP(ensure(g->b_vals, sizeof(uint32_t) * (B + 1), g->stream));
         keys = g->b_keys.as<uint64_t>();
         vals = g->b_vals.as<uint32_t>();
         if (drop) {
-            TW_HIP(ensure(g->b_flags, sizeof(uint32_t) * (B + 1)));
-            TW_HIP(ensure(g->idx, sizeof(uint32_t) * (B + 1)));
+            TW_HIP(ensure(g->b_flags, sizeof(uint32_t) * (B + 1), g->stream));
+            TW_HIP(ensure(g->idx, sizeof(uint32_t) * (B + 1), g->stream));
             uint32_t* fl = g->b_flags.as<uint32_t>();
             uint32_t* pos = g->idx.as<uint32_t>();
             hipLaunchKernelGGL(k_keep_flags, grid_for(B), dim3(T), 0, s, s_ts, B, cut, fl);
@@ -577,9 +578,9 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
     if (!sorted && kept > 0) {
         int kb = bits_for((uint64_t)(bmax - key_base));
         TW_HIP(radix_sort_u64(keys, vals, kept, 0, kb, g->ws, s));
-        TW_HIP(ensure(g->q_src, sizeof(int32_t) * (kept + 1)));
-        TW_HIP(ensure(g->q_dst, sizeof(int32_t) * (kept + 1)));
-        TW_HIP(ensure(g->q_ts, sizeof(int64_t) * (kept + 1)));
+        TW_HIP(ensure(g->q_src, sizeof(int32_t) * (kept + 1), g->stream));
+        TW_HIP(ensure(g->q_dst, sizeof(int32_t) * (kept + 1), g->stream));
+        TW_HIP(ensure(g->q_ts, sizeof(int64_t) * (kept + 1), g->stream));
         hipLaunchKernelGGL(k_gather_batch, grid_for(kept), dim3(T), 0, s, vals, kept, s_src, s_dst,
                            s_ts, g->q_src.as<int32_t>(), g->q_dst.as<int32_t>(),
                            g->q_ts.as<int64_t>());
@@ -589,15 +590,63 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
     }
 
     // node-view jobs, while the evicted records are still in the window
-    // buffers. Evicting the whole window empties the node view instead.
-    const int64_t m_old = g->m;
-    if (evicting && evicted == m_old) {
-        if (nv_reset(g, err) != TW_OK) return err.code;
-        if (nv_collect(g, q_src, q_dst, q_ts, kept, bmin, bmax, 0, 0, err) != TW_OK)
-            return err.code;
-    } else if (nv_collect(g, q_src, q_dst, q_ts, kept, bmin, bmax, g->e_base, evicted, err) !=
-               TW_OK) {
+    // buffers (none when the whole window goes: the node view is emptied)
+    const bool evict_all = evicting && evicted == g->m;
+    if (nv_collect(g, q_src, q_dst, q_ts, kept, bmin, bmax, evict_all ? 0 : g->e_base,
+                   evict_all ? 0 : evicted, err) != TW_OK)
         return err.code;
+    P = IngestPlan{};
+    P.n = n;
+    P.B = B;
+    P.place = place;
+    P.s_src = s_src;
+    P.s_dst = s_dst;
+    P.s_ts = s_ts;
+    P.q_src = q_src;
+    P.q_dst = q_dst;
+    P.q_ts = q_ts;
+    P.staged_counts = staged_counts;
+    P.stage_has_last = stage_has_last;
+    P.bmin = bmin;
+    P.t_now = t_now;
+    P.has_time = has_time;
+    P.sorted = sorted;
+    P.evicting = evicting;
+    P.evict_all = evict_all;
+    P.cut = cut;
+    P.kept = kept;
+    P.evicted = evicted;
+    P.gg_evicted = gg_evicted;
+    P.batch_first = batch_first;
+    P.drop_lo = drop_lo;
+    P.m_old = g->m;
+    P.e_base = g->e_base;
+    P.epoch = g->epoch;
+    return TW_OK;
+}
+
+tw_status ingest_apply(tw_graph* g, const IngestPlan& P, tw_ingest_info* info, Error& err) {
+    hipStream_t s = g->stream;
+    if (P.m_old != g->m || P.e_base != g->e_base || P.epoch != g->epoch) {
+        err = Error{TW_EINVAL, "ingest: the index changed between planning and applying a batch"};
+        return err.code;
+    }
+    const int64_t B = P.B, kept = P.kept, evicted = P.evicted, gg_evicted = P.gg_evicted;
+    const int64_t batch_first = P.batch_first, drop_lo = P.drop_lo, cut = P.cut;
+    const bool sorted = P.sorted, evicting = P.evicting, staged_counts = P.staged_counts;
+    const int stage_has_last = P.stage_has_last;
+    const int place = P.place;
+    const int32_t* q_src = P.q_src;
+    const int32_t* q_dst = P.q_dst;
+    const int64_t* q_ts = P.q_ts;
+    // From here on the index changes in place: a failure before the end
+    // leaves the graph marked unusable (every later call refuses it).
+    g->broken = true;
+    const int64_t m_old = g->m;
+    if (P.evict_all) {
+        const int64_t jobs = g->T;  // the batch's jobs, collected by the plan
+        if (nv_reset(g, err) != TW_OK) return err.code;
+        g->T = jobs;
     }
 
     // timestamp view: a batch that starts at or after the window's last
@@ -615,14 +664,14 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
     // it; in the alternates it stays when it is the whole new window. In any
     // other case the update would move it over itself or overwrite it, so it
     // is copied to the staging buffers first.
-    const bool q_tail = sorted && kept > 0 && place == IN_TAIL;
-    const bool q_alt = sorted && kept > 0 && place == IN_ALT;
+    const bool q_tail = sorted && kept > 0 && place == IngestPlan::IN_TAIL;
+    const bool q_alt = sorted && kept > 0 && place == IngestPlan::IN_ALT;
     const bool keep_tail = q_tail && (!append || na == 0 || drop_lo == 0);
     const bool keep_alt = q_alt && append && na == 0;
     if ((q_tail && !keep_tail) || (q_alt && !keep_alt)) {
-        TW_HIP(ensure(g->b_src, sizeof(int32_t) * (kept + 1)));
-        TW_HIP(ensure(g->b_dst, sizeof(int32_t) * (kept + 1)));
-        TW_HIP(ensure(g->b_ts, sizeof(int64_t) * (kept + 1)));
+        TW_HIP(ensure(g->b_src, sizeof(int32_t) * (kept + 1), g->stream));
+        TW_HIP(ensure(g->b_dst, sizeof(int32_t) * (kept + 1), g->stream));
+        TW_HIP(ensure(g->b_ts, sizeof(int64_t) * (kept + 1), g->stream));
         TW_HIP(hipMemcpyAsync(g->b_src.p, q_src, 4 * kept, hipMemcpyDeviceToDevice, s));
         TW_HIP(hipMemcpyAsync(g->b_dst.p, q_dst, 4 * kept, hipMemcpyDeviceToDevice, s));
         TW_HIP(hipMemcpyAsync(g->b_ts.p, q_ts, 8 * kept, hipMemcpyDeviceToDevice, s));
@@ -726,6 +775,9 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
     if (nv_apply(g, evicting && evicted < m_old, cut, err) != TW_OK) return err.code;
     if (finish_ts(g, gg_full, gg_old, gg_evicted, err) != TW_OK) return err.code;
 
+    g->t_now = P.t_now;
+    g->has_time = P.has_time;
+    g->broken = false;
     g->last.accepted = kept;
     g->last.dropped_late = B - kept;
     g->last.evicted = evicted;
@@ -734,6 +786,13 @@ tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int6
     g->last.t_max = g->t_max;
     if (info) *info = g->last;
     return TW_OK;
+}
+
+tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int64_t* ts,
+                 int64_t n, tw_ingest_info* info, Error& err) {
+    IngestPlan P;
+    if (ingest_prepare(g, src, dst, ts, n, P, err) != TW_OK) return err.code;
+    return ingest_apply(g, P, info, err);
 }
 
 tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& err) {
@@ -753,6 +812,7 @@ tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& e
     }
     if (ev > 0) {
         const int64_t m_old = g->m, gg_old = g->Gg;
+        g->broken = true;  // cleared when the eviction completes
         if (ev == m_old) {
             if (nv_reset(g, err) != TW_OK) return err.code;
         } else if (nv_collect(g, nullptr, nullptr, nullptr, 0, 0, 0, g->e_base, ev, err) !=
@@ -773,6 +833,7 @@ tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& e
             if (nv_apply(g, true, cutoff, err) != TW_OK) return err.code;
         }
         if (finish_ts(g, gg_full, gg_old, gev, err) != TW_OK) return err.code;
+        g->broken = false;
     }
     g->last.accepted = 0;
     g->last.dropped_late = 0;
@@ -817,11 +878,40 @@ tw_status backward_view(tw_graph* g, tw_graph** out, Error& err) {
 
 void release_graph(tw_graph* g) {
     if (!g) return;
-    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    (void)hipStreamSynchronize(g->stream);
     release_graph(g->rev);
-    for (DevBuf* b : g->buffers()) release(*b);
+    for (DevBuf* b : g->buffers()) release(*b, g->stream);
+    (void)hipStreamSynchronize(g->stream);
     if (g->h_scal) (void)hipHostFree(g->h_scal);
     delete g;
+}
+
+tw_status ingest_views(tw_graph* g, const int32_t* src, const int32_t* dst, const int64_t* ts,
+                       int64_t n, tw_ingest_info* info, Error& err) {
+    if (ingest(g, src, dst, ts, n, info, err) != TW_OK) return err.code;
+    if (g->rev) {
+        // the in-view takes the batch with source and destination swapped;
+        // if that fails it is dropped and rebuilt from the window on the next
+        // backward walk, so the graph stays consistent either way
+        Error e{TW_OK, ""};
+        if (ingest(g->rev, dst, src, ts, n, nullptr, e) != TW_OK) {
+            release_graph(g->rev);
+            g->rev = nullptr;
+        }
+    }
+    return TW_OK;
+}
+
+tw_status evict_views(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& err) {
+    if (evict_before(g, cutoff, n_evicted, err) != TW_OK) return err.code;
+    if (g->rev) {
+        Error e{TW_OK, ""};
+        if (evict_before(g->rev, cutoff, nullptr, e) != TW_OK) {
+            release_graph(g->rev);
+            g->rev = nullptr;
+        }
+    }
+    return TW_OK;
 }
 
 tw_status pull_scalars(tw_graph* g, bool flags, Error& err) {
@@ -848,9 +938,9 @@ tw_status build_adjacency(tw_graph* g, Error& err) {
     if (g->adj_ready) return TW_OK;
     hipStream_t s = g->stream;
     const int64_t m = g->m;
-    TW_HIP(ensure(g->adj, sizeof(int32_t) * (m + 1)));
-    TW_HIP(ensure(g->adj_rng, sizeof(uint2) * g->V));
-    TW_HIP(ensure(g->b_keys, sizeof(uint64_t) * (m + 1)));
+    TW_HIP(ensure(g->adj, sizeof(int32_t) * (m + 1), g->stream));
+    TW_HIP(ensure(g->adj_rng, sizeof(uint2) * g->V, g->stream));
+    TW_HIP(ensure(g->b_keys, sizeof(uint64_t) * (m + 1), g->stream));
     uint64_t* keys = g->b_keys.as<uint64_t>();
     hipLaunchKernelGGL(k_adj_keys, grid_for(m), dim3(T), 0, s, g->e_src.as<int32_t>() + g->e_base,
                        g->e_dst.as<int32_t>() + g->e_base, m, keys);

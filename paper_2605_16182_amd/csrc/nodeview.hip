@@ -881,16 +881,16 @@ tw_status run_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool rew
 
 tw_status nv_reset(tw_graph* g, Error& err) {
     const int64_t V = g->V;
-    TW_HIP(ensure(g->rec, sizeof(NodeRec) * V));
+    TW_HIP(ensure(g->rec, sizeof(NodeRec) * V, g->stream));
     if (!g->seg.p) {
         // generation 0 marks every segment void (pool_gen starts above 0)
-        TW_HIP(ensure(g->seg, sizeof(SegRec) * V));
+        TW_HIP(ensure(g->seg, sizeof(SegRec) * V, g->stream));
         const int64_t words = V * (int64_t)(sizeof(SegRec) / sizeof(uint32_t));
         hipLaunchKernelGGL(k_zero_u32, grid_for(words), dim3(T), 0, g->stream,
                            g->seg.as<uint32_t>(), words);
     }
     if (!g->touched.p) {
-        TW_HIP(ensure(g->touched, sizeof(uint32_t) * V));
+        TW_HIP(ensure(g->touched, sizeof(uint32_t) * V, g->stream));
         hipLaunchKernelGGL(k_zero_u32, grid_for(V), dim3(T), 0, g->stream,
                            g->touched.as<uint32_t>(), V);
     }
@@ -917,12 +917,12 @@ tw_status nv_collect(tw_graph* g, const int32_t* q_src, const int32_t* q_dst, co
     // a node is one job at most, so V + 1 entries hold any job list (also
     // the full rewrite's, which appends to this one)
     const int64_t cand = (int64_t)g->V + 1;
-    TW_HIP(ensure(g->c_node, sizeof(uint32_t) * cand));
-    TW_HIP(ensure(g->c_bf, sizeof(uint32_t) * cand));
-    TW_HIP(ensure(g->c_be, sizeof(uint32_t) * cand));
+    TW_HIP(ensure(g->c_node, sizeof(uint32_t) * cand, g->stream));
+    TW_HIP(ensure(g->c_bf, sizeof(uint32_t) * cand, g->stream));
+    TW_HIP(ensure(g->c_be, sizeof(uint32_t) * cand, g->stream));
     const int64_t nf = std::max(kept, ev_n);
-    TW_HIP(ensure(g->flags, sizeof(uint32_t) * (nf + 1)));
-    TW_HIP(ensure(g->idx, sizeof(uint32_t) * (nf + 1)));
+    TW_HIP(ensure(g->flags, sizeof(uint32_t) * (nf + 1), g->stream));
+    TW_HIP(ensure(g->idx, sizeof(uint32_t) * (nf + 1), g->stream));
     uint32_t* flags = g->flags.as<uint32_t>();
     uint32_t* pos = g->idx.as<uint32_t>();
     uint32_t* sl_runs = slot(g, SLOT_U32_RUNS);
@@ -931,9 +931,9 @@ tw_status nv_collect(tw_graph* g, const int32_t* q_src, const int32_t* q_dst, co
     // as one packed word per record instead of 12 bytes
     g->bs_packed = kept > 0 && ts_hi >= ts_lo && (uint64_t)ts_hi - (uint64_t)ts_lo < (1ull << 32);
     g->bs_base = g->bs_packed ? ts_lo : 0;
-    TW_HIP(ensure(g->bs_src, sizeof(uint32_t) * (kept + 1)));
-    if (!g->bs_packed) TW_HIP(ensure(g->bs_dst, sizeof(int32_t) * (kept + 1)));
-    TW_HIP(ensure(g->bs_ts, sizeof(int64_t) * (kept + 1)));
+    TW_HIP(ensure(g->bs_src, sizeof(uint32_t) * (kept + 1), g->stream));
+    if (!g->bs_packed) TW_HIP(ensure(g->bs_dst, sizeof(int32_t) * (kept + 1), g->stream));
+    TW_HIP(ensure(g->bs_ts, sizeof(int64_t) * (kept + 1), g->stream));
     if (kept > 0) {
         uint32_t* bsrc = g->bs_src.as<uint32_t>();
         const int vbits = bits_for((uint64_t)(g->V - 1));
@@ -982,9 +982,9 @@ tw_status nv_collect(tw_graph* g, const int32_t* q_src, const int32_t* q_dst, co
 namespace {
 
 tw_status ensure_jobs(tw_graph* g, int64_t nj, Error& err) {
-    TW_HIP(ensure(g->jobs, sizeof(Job) * (nj + 1)));
+    TW_HIP(ensure(g->jobs, sizeof(Job) * (nj + 1), g->stream));
     DevBuf* b[] = {&g->j_cnt, &g->j_off, &g->j_re, &g->j_rg, &g->j_rf, &g->j_fw};
-    for (DevBuf* p : b) TW_HIP(ensure(*p, sizeof(uint32_t) * (nj + 2)));
+    for (DevBuf* p : b) TW_HIP(ensure(*p, sizeof(uint32_t) * (nj + 2), g->stream));
     return TW_OK;
 }
 
@@ -1030,9 +1030,9 @@ tw_status execute_jobs(tw_graph* g, int64_t nj, uint64_t out, const int32_t* sds
     // group-start bitmap and per-word ranks (o_flag), tile counts scanned in
     // place (o_rank, total at [nt])
     const int64_t words = ceil_div((int64_t)out, 64), nt = ceil_div((int64_t)out, NV_TILE);
-    TW_HIP(ensure(g->o_flag, sizeof(uint64_t) * (words + 1) + sizeof(uint32_t) * (words + 1)));
-    TW_HIP(ensure(g->o_rank, sizeof(uint32_t) * (nt + 1)));
-    TW_HIP(ensure(g->o_tf, sizeof(uint32_t) * (nt + 1)));
+    TW_HIP(ensure(g->o_flag, sizeof(uint64_t) * (words + 1) + sizeof(uint32_t) * (words + 1), g->stream));
+    TW_HIP(ensure(g->o_rank, sizeof(uint32_t) * (nt + 1), g->stream));
+    TW_HIP(ensure(g->o_tf, sizeof(uint32_t) * (nt + 1), g->stream));
     uint64_t* bm = g->o_flag.as<uint64_t>();
     uint32_t* pref = reinterpret_cast<uint32_t*>(bm + words + 1);
     uint32_t* tcnt = g->o_rank.as<uint32_t>();
@@ -1056,7 +1056,7 @@ tw_status execute_jobs(tw_graph* g, int64_t nj, uint64_t out, const int32_t* sds
         const uint64_t fcap = (dfence == g->fence.as<uint32_t>() ? g->fence.bytes
                                                                   : g->afence.bytes) /
                               sizeof(uint32_t);
-        TW_HIP(ensure(g->f_tf, sizeof(uint32_t) * (fcap / NV_TILE + 2)));
+        TW_HIP(ensure(g->f_tf, sizeof(uint32_t) * (fcap / NV_TILE + 2), g->stream));
         hipLaunchKernelGGL(k_tile_first_dev, dim3(FENCE_GRID / 8), dim3(T), 0, s,
                            g->j_fw.as<uint32_t>(), nj, g->f_tf.as<uint32_t>());
         hipLaunchKernelGGL(k_job_fence, dim3(FENCE_GRID), dim3(T), 0, s, jobs,
@@ -1082,8 +1082,8 @@ tw_status run_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool rew
             g->pf_top + (int64_t)tot[3] > g->pf_cap) {
             // no room: list every other active node and rewrite all of them
             const int64_t V = g->V;
-            TW_HIP(ensure(g->v_flags, sizeof(uint32_t) * (V + 1)));
-            TW_HIP(ensure(g->v_pos, sizeof(uint32_t) * (V + 1)));
+            TW_HIP(ensure(g->v_flags, sizeof(uint32_t) * (V + 1), g->stream));
+            TW_HIP(ensure(g->v_pos, sizeof(uint32_t) * (V + 1), g->stream));
             uint32_t* sl_act = slot(g, SLOT_U32_ACTIVE);
             hipLaunchKernelGGL(k_active_flags, grid_for(V), dim3(T), 0, s, g->rec.as<NodeRec>(), V,
                                g->touched.as<uint32_t>(), g->epoch, g->v_flags.as<uint32_t>());
@@ -1120,10 +1120,10 @@ tw_status run_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool rew
         err = Error{TW_ENOMEM, "node view: pools would exceed 2^32 slots"};
         return err.code;
     }
-    TW_HIP(ensure(g->an_dst, sizeof(int32_t) * ce));
-    TW_HIP(ensure(g->an_ts, sizeof(int64_t) * ce));
-    TW_HIP(ensure(g->ang, sizeof(GroupRec) * cg));
-    TW_HIP(ensure(g->afence, sizeof(uint32_t) * cf));
+    TW_HIP(ensure(g->an_dst, sizeof(int32_t) * ce, g->stream));
+    TW_HIP(ensure(g->an_ts, sizeof(int64_t) * ce, g->stream));
+    TW_HIP(ensure(g->ang, sizeof(GroupRec) * cg, g->stream));
+    TW_HIP(ensure(g->afence, sizeof(uint32_t) * cf, g->stream));
     hipLaunchKernelGGL(k_job_place, grid_for(nj), dim3(T), 0, s, g->jobs.as<Job>(), nj,
                        g->j_re.as<uint32_t>(), g->j_rg.as<uint32_t>(), g->j_rf.as<uint32_t>(), 0u,
                        0u, 0u);
@@ -1163,8 +1163,8 @@ tw_status nv_apply(tw_graph* g, bool evicting, int64_t cut, Error& err) {
 tw_status nv_group_count(tw_graph* g, int64_t* gn, Error& err) {
     hipStream_t s = g->stream;
     const int64_t V = g->V;
-    TW_HIP(ensure(g->v_flags, sizeof(uint32_t) * (V + 1)));
-    TW_HIP(ensure(g->v_pos, sizeof(uint32_t) * (V + 1)));
+    TW_HIP(ensure(g->v_flags, sizeof(uint32_t) * (V + 1), g->stream));
+    TW_HIP(ensure(g->v_pos, sizeof(uint32_t) * (V + 1), g->stream));
     hipLaunchKernelGGL(k_node_counts, grid_for(V), dim3(T), 0, s, g->rec.as<NodeRec>(),
                        g->ng.as<GroupRec>(), V, nullptr, g->v_flags.as<uint32_t>());
     uint32_t* sl = slot(g, SLOT_U32_GN);
@@ -1178,10 +1178,10 @@ tw_status nv_export(tw_graph* g, int32_t* n_dst, int64_t* n_ts, int64_t* n_gts, 
                     int64_t* n_ebeg, int64_t* n_gbeg, Error& err) {
     hipStream_t s = g->stream;
     const int64_t V = g->V, m = g->m;
-    TW_HIP(ensure(g->v_flags, sizeof(uint32_t) * (V + 1)));
-    TW_HIP(ensure(g->v_pos, sizeof(uint32_t) * (V + 1)));
-    TW_HIP(ensure(g->idx, sizeof(uint32_t) * (V + 2)));
-    TW_HIP(ensure(g->flags, sizeof(uint32_t) * (V + 2)));
+    TW_HIP(ensure(g->v_flags, sizeof(uint32_t) * (V + 1), g->stream));
+    TW_HIP(ensure(g->v_pos, sizeof(uint32_t) * (V + 1), g->stream));
+    TW_HIP(ensure(g->idx, sizeof(uint32_t) * (V + 2), g->stream));
+    TW_HIP(ensure(g->flags, sizeof(uint32_t) * (V + 2), g->stream));
     uint32_t* ecnt = g->v_flags.as<uint32_t>();
     uint32_t* gcnt = g->v_pos.as<uint32_t>();
     uint32_t* ebeg = g->idx.as<uint32_t>();

@@ -440,9 +440,9 @@ hipError_t radix_sort_impl(const K* kin0, const uint32_t* vin0, const uint64_t* 
     }
     const int passes = (int)ceil_div(bit_hi - bit_lo, 8);
     const bool in_place = (const void*)kin0 == (const void*)kout;
-    if ((e = ensure(ws.keys_alt, sizeof(K) * n)) != hipSuccess) return e;
-    if (has_v && (e = ensure(ws.vals_alt, sizeof(uint32_t) * n)) != hipSuccess) return e;
-    if (has_w && (e = ensure(ws.v64_alt, sizeof(uint64_t) * n)) != hipSuccess) return e;
+    if ((e = ensure(ws.keys_alt, sizeof(K) * n, s)) != hipSuccess) return e;
+    if (has_v && (e = ensure(ws.vals_alt, sizeof(uint32_t) * n, s)) != hipSuccess) return e;
+    if (has_w && (e = ensure(ws.v64_alt, sizeof(uint64_t) * n, s)) != hipSuccess) return e;
     K* ka = ws.keys_alt.as<K>();
     uint32_t* va = has_v ? ws.vals_alt.as<uint32_t>() : nullptr;
     uint64_t* wa = has_w ? ws.v64_alt.as<uint64_t>() : nullptr;
@@ -452,7 +452,7 @@ hipError_t radix_sort_impl(const K* kin0, const uint32_t* vin0, const uint64_t* 
     auto run = [&](auto items) -> hipError_t {
         constexpr int I = decltype(items)::value;
         const int64_t nblocks = ceil_div(n, (int64_t)RS_THREADS * I);
-        hipError_t r = ensure(ws.hist, sizeof(uint32_t) * 256 * nblocks);
+        hipError_t r = ensure(ws.hist, sizeof(uint32_t) * 256 * nblocks, s);
         if (r != hipSuccess) return r;
         uint32_t* hist = ws.hist.as<uint32_t>();
         const K* ki = kin0;
@@ -503,53 +503,70 @@ hipError_t radix_sort_impl(const K* kin0, const uint32_t* vin0, const uint64_t* 
 
 }  // namespace
 
-hipError_t ensure(DevBuf& b, size_t bytes) {
+hipError_t ensure(DevBuf& b, size_t bytes, hipStream_t s) {
     if (bytes <= b.bytes) return hipSuccess;
-    size_t want = bytes + bytes / 4 + 256;
-    if (b.p) {
-        // the old block may still be read by enqueued kernels
-        hipError_t e = hipDeviceSynchronize();
-        if (e != hipSuccess) return e;
-        e = hipFree(b.p);
-        b.p = nullptr;
-        b.bytes = 0;
-        if (e != hipSuccess) return e;
-    }
-    hipError_t e = hipMalloc(&b.p, want);
+    const size_t want = bytes + bytes / 4 + 256;
+    // Stream-ordered growth: the new block is taken before the old one is
+    // given back, so a failed growth leaves the buffer as it was, and the old
+    // block returns to the pool only after the work already enqueued on s
+    // (which may still read it) has run. Nothing waits on the host.
+    void* p = nullptr;
+    hipError_t e = hipMallocAsync(&p, want, s);
     if (e != hipSuccess) {
-        b.p = nullptr;
+        (void)hipGetLastError();
         return e;
     }
+    if (b.p) {
+        e = hipFreeAsync(b.p, s);
+        if (e != hipSuccess) {
+            (void)hipFreeAsync(p, s);
+            return e;
+        }
+    }
+    b.p = p;
     b.bytes = want;
     return hipSuccess;
 }
 
-void release(DevBuf& b) {
-    if (b.p) (void)hipFree(b.p);
+void release(DevBuf& b, hipStream_t s) {
+    if (b.p) (void)hipFreeAsync(b.p, s);
     b.p = nullptr;
     b.bytes = 0;
 }
 
 template <typename In, typename V>
-hipError_t scan_exclusive(const In* in, V* out, int64_t n, V* total, DevBuf& part_buf,
-                          hipStream_t s) {
+hipError_t scan_core(const In* in, V* out, int64_t n, V* total, V* part, hipStream_t s) {
     if (n <= 0) {
         if (total) hipLaunchKernelGGL(k_set<V>, dim3(1), dim3(1), 0, s, total, (V)0);
         return hipGetLastError();
     }
-    int64_t nb = ceil_div(n, SCAN_TILE);
-    hipError_t e = ensure(part_buf, sizeof(V) * (nb + 1));
-    if (e != hipSuccess) return e;
-    V* part = part_buf.as<V>();
+    const int64_t nb = ceil_div(n, SCAN_TILE);
     hipLaunchKernelGGL((k_scan_reduce<In, V>), dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, part);
     hipLaunchKernelGGL(k_scan_partials<V>, dim3(1), dim3(SCAN_THREADS), 0, s, part, nb, total);
     hipLaunchKernelGGL((k_scan_down<In, V>), dim3(nb), dim3(SCAN_THREADS), 0, s, in, out, n, part);
     return hipGetLastError();
 }
 
+template <typename In, typename V>
+hipError_t scan_exclusive(const In* in, V* out, int64_t n, V* total, DevBuf& part_buf,
+                          hipStream_t s) {
+    if (n > 0) {
+        const hipError_t e = ensure(part_buf, sizeof(V) * (ceil_div(n, SCAN_TILE) + 1), s);
+        if (e != hipSuccess) return e;
+    }
+    return scan_core<In, V>(in, out, n, total, part_buf.as<V>(), s);
+}
+
 hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
                               Workspace& ws, hipStream_t s) {
     return scan_exclusive<uint32_t, uint32_t>(in, out, n, total, ws.scan_part, s);
+}
+
+int64_t scan_parts_u32(int64_t n) { return ceil_div(std::max<int64_t>(n, 1), SCAN_TILE) + 1; }
+
+hipError_t scan_exclusive_u32_into(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
+                                   uint32_t* part, hipStream_t s) {
+    return scan_core<uint32_t, uint32_t>(in, out, n, total, part, s);
 }
 
 hipError_t scan_exclusive_u32x4(const uint32_t* const in[4], uint32_t* const out[4],
@@ -567,7 +584,7 @@ hipError_t scan_exclusive_u32x4(const uint32_t* const in[4], uint32_t* const out
         return hipGetLastError();
     }
     const int64_t nb = ceil_div(n, SCAN_TILE);
-    hipError_t e = ensure(ws.scan_part, sizeof(uint32_t) * 4 * (nb + 1));
+    hipError_t e = ensure(ws.scan_part, sizeof(uint32_t) * 4 * (nb + 1), s);
     if (e != hipSuccess) return e;
     uint32_t* part = ws.scan_part.as<uint32_t>();
     hipLaunchKernelGGL(k_scan4_reduce, dim3((unsigned)nb, 4), dim3(SCAN_THREADS), 0, s, a, n, part,

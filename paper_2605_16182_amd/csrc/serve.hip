@@ -92,6 +92,7 @@ struct Item {
     const int64_t* its = nullptr;
     int64_t n = 0;
     tw_ingest_info info{};
+    int64_t cap_hits = 0;  // node2vec walks that ended at the trial cap
     Clock::time_point t_submit, t_start, t_done;
 };
 
@@ -117,6 +118,8 @@ struct tw_server {
     void* h_tables = nullptr;  // pinned staging of the tables
     unsigned long long* d_hops = nullptr;  // per slot
     unsigned long long* h_hops = nullptr;  // pinned per slot
+    uint32_t* d_err = nullptr;             // per slot: two words per request of the launch
+    uint32_t* h_err = nullptr;             // pinned copy
     hipEvent_t ev[MAX_INFLIGHT] = {};
     bool slot_busy[MAX_INFLIGHT] = {};
     size_t table_bytes = 0;
@@ -140,16 +143,27 @@ namespace {
 
 __global__ void k_zero_u64(unsigned long long* p) { *p = 0; }
 
+__global__ void k_zero_words(uint32_t* p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+constexpr int ERR_WORDS = 2 * MAX_REQ_PER_LAUNCH;  // per launch slot
+
 // launches whose event has completed, in order
 void retire(tw_server* S) {
     while (!S->inflight.empty()) {
         Launch& L = S->inflight.front();
         if (hipEventQuery(S->ev[L.slot]) != hipSuccess) break;
         const auto now = Clock::now();
-        for (uint64_t id : L.ids) {
-            Item& it = S->items[id];
+        const uint32_t* ew = S->h_err + (size_t)L.slot * ERR_WORDS;
+        for (size_t r = 0; r < L.ids.size(); ++r) {
+            Item& it = S->items[L.ids[r]];
             it.state = ST_DONE;
             it.t_done = now;
+            // a start node out of range fails the request (its walks read
+            // length 0 there); walks ended by node2vec's trial cap are counted
+            if (ew[2 * r]) it.status = TW_ERANGE;
+            it.cap_hits = ew[2 * r + 1];
             S->latencies.push_back(ms_between(it.t_submit, now));
             ++S->requests_done;
             S->walks_done += it.p.num_walks;
@@ -192,7 +206,8 @@ void worker_loop(tw_server* S) {
             lk.unlock();
             tw::Error e{TW_OK, ""};
             tw_ingest_info info{};
-            const tw_status st = tw::ingest(S->g, src, dst, its, n, &info, e);
+            // the graph and its in-view (if backward walks created one)
+            const tw_status st = tw::ingest_views(S->g, src, dst, its, n, &info, e);
             lk.lock();
             Item& done = S->items[id];
             done.status = st;
@@ -251,11 +266,16 @@ void worker_loop(tw_server* S) {
                 hipStream_t s = S->g->stream;
                 char* dt = static_cast<char*>(S->d_tables) + slot * S->table_bytes;
                 char* ht = static_cast<char*>(S->h_tables) + slot * S->table_bytes;
+                uint32_t* de = S->d_err + (size_t)slot * ERR_WORDS;
+                const int nw = 2 * (int)reqs.size();
                 hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, S->d_hops + slot);
+                hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, s, de, nw);
                 tw_status st = tw::serve_launch(S->g, reqs.data(), (int)reqs.size(), dt, ht,
-                                                S->d_hops + slot, e);
+                                                S->d_hops + slot, de, e);
                 if (st == TW_OK &&
                     (hipMemcpyAsync(S->h_hops + slot, S->d_hops + slot, sizeof(unsigned long long),
+                                    hipMemcpyDeviceToHost, s) != hipSuccess ||
+                     hipMemcpyAsync(S->h_err + (size_t)slot * ERR_WORDS, de, sizeof(uint32_t) * nw,
                                     hipMemcpyDeviceToHost, s) != hipSuccess ||
                      hipEventRecord(S->ev[slot], s) != hipSuccess))
                     st = TW_EDEVICE;
@@ -311,8 +331,10 @@ tw_status server_create(tw_graph* g, const tw_server_config* cfg, tw_server** ou
         if (S->arena_base) (void)hipFree(S->arena_base);
         if (S->d_tables) (void)hipFree(S->d_tables);
         if (S->d_hops) (void)hipFree(S->d_hops);
+        if (S->d_err) (void)hipFree(S->d_err);
         if (S->h_tables) (void)hipHostFree(S->h_tables);
         if (S->h_hops) (void)hipHostFree(S->h_hops);
+        if (S->h_err) (void)hipHostFree(S->h_err);
         for (hipEvent_t& e : S->ev)
             if (e) (void)hipEventDestroy(e);
         delete S;
@@ -325,6 +347,11 @@ tw_status server_create(tw_graph* g, const tw_server_config* cfg, tw_server** ou
             hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&S->h_hops),
                       sizeof(unsigned long long) * MAX_INFLIGHT, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&S->d_err),
+                  sizeof(uint32_t) * ERR_WORDS * MAX_INFLIGHT) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&S->h_err),
+                      sizeof(uint32_t) * ERR_WORDS * MAX_INFLIGHT, hipHostMallocDefault) !=
             hipSuccess) {
         hipGetLastError();
         cleanup();
@@ -420,6 +447,7 @@ tw_status server_wait(tw_server* S, uint64_t id, int64_t timeout_us, tw_request_
         out->queue_ms = ms_between(it.t_submit, it.t_start);
         out->latency_ms = ms_between(it.t_submit, it.t_done);
         out->ingest = it.info;
+        out->trial_cap_hits = it.cap_hits;
     }
     return TW_OK;
 }
@@ -508,8 +536,10 @@ tw_status server_destroy(tw_server* S, Error& err) {
     (void)hipFree(S->arena_base);
     (void)hipFree(S->d_tables);
     (void)hipFree(S->d_hops);
+    (void)hipFree(S->d_err);
     (void)hipHostFree(S->h_tables);
     (void)hipHostFree(S->h_hops);
+    (void)hipHostFree(S->h_err);
     for (hipEvent_t e : S->ev) (void)hipEventDestroy(e);
     delete S;
     (void)err;

@@ -165,8 +165,11 @@ struct Error {
     std::string msg;
 };
 
-hipError_t ensure(DevBuf& b, size_t bytes);  // keeps contents only if no growth
-void release(DevBuf& b);
+// Room for `bytes` in b, growing it in the order of stream s (contents are
+// kept only if it does not grow; a failed growth leaves b unchanged).
+hipError_t ensure(DevBuf& b, size_t bytes, hipStream_t s);
+// Returns b's block to the device pool after the work enqueued on s.
+void release(DevBuf& b, hipStream_t s);
 
 // Scratch space reused by the primitives.
 struct Workspace {
@@ -182,6 +185,12 @@ struct Workspace {
 // n may be 0. in and out may alias.
 hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
                               Workspace& ws, hipStream_t s);
+
+// The same scan with caller-provided room for its partial sums (at least
+// scan_parts_u32(n) words at part): it allocates nothing.
+int64_t scan_parts_u32(int64_t n);
+hipError_t scan_exclusive_u32_into(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
+                                   uint32_t* part, hipStream_t s);
 
 // Four exclusive u32 scans of n elements at once (in[k] and out[k] may
 // alias); total[k] (device, nullable) receives the sum of array k.
@@ -248,6 +257,9 @@ struct tw_graph {
 
     bool has_time = false;
     int64_t t_now = 0;
+    // set while an ingest or eviction changes the index in place; still set
+    // after one that failed midway, which leaves the graph unusable
+    bool broken = false;
 
     // host mirrors of the index sizes. The window occupies positions
     // [e_base, e_base + m) of the edge-store buffers (capacity e_cap); its
@@ -375,7 +387,37 @@ tw_status nv_export(tw_graph* g, int32_t* n_dst, int64_t* n_ts, int64_t* n_gts, 
 // index.hip
 tw_status ingest(tw_graph* g, const int32_t* src, const int32_t* dst, const int64_t* ts,
                  int64_t n, tw_ingest_info* info, Error& err);
+// An ingest in two parts. ingest_prepare stages, validates, sorts the batch
+// and collects the node-view jobs: it writes only ingest buffers and the
+// free tail of the window buffers, so walks over the current index may run
+// meanwhile. ingest_apply then changes the index in place (nothing else may
+// change it in between; walks must not run during it).
+struct IngestPlan {
+    enum { IN_TAIL = 0, IN_ALT = 1, IN_BUF = 2 };  // where the batch was staged
+    int64_t n = 0, B = 0;
+    int place = IN_BUF;
+    int32_t* s_src = nullptr;
+    int32_t* s_dst = nullptr;
+    int64_t* s_ts = nullptr;
+    const int32_t* q_src = nullptr;  // kept records in timestamp order
+    const int32_t* q_dst = nullptr;
+    const int64_t* q_ts = nullptr;
+    bool staged_counts = false;
+    int stage_has_last = 0;
+    int64_t bmin = 0, t_now = 0;
+    bool has_time = false, sorted = true, evicting = false, evict_all = false;
+    int64_t cut = 0, kept = 0, evicted = 0, gg_evicted = 0, batch_first = 0, drop_lo = 0;
+    int64_t m_old = 0, e_base = 0;  // the window the plan was made against
+    uint32_t epoch = 0;
+};
+tw_status ingest_prepare(tw_graph* g, const int32_t* src, const int32_t* dst, const int64_t* ts,
+                         int64_t n, IngestPlan& P, Error& err);
+tw_status ingest_apply(tw_graph* g, const IngestPlan& P, tw_ingest_info* info, Error& err);
 tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& err);
+// ingest / evict_before on the graph and on its in-view (when it has one)
+tw_status ingest_views(tw_graph* g, const int32_t* src, const int32_t* dst, const int64_t* ts,
+                       int64_t n, tw_ingest_info* info, Error& err);
+tw_status evict_views(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& err);
 tw_status build_adjacency(tw_graph* g, Error& err);
 // The graph whose node view holds the in-edges (backward walks): g itself
 // when undirected, else g->rev, created from g's window on first use and
@@ -422,9 +464,11 @@ tw_status check_walk_params(const tw_walk_params* p, Error& err);
 // copy has run).
 size_t serve_table_bytes(int n);
 // Enqueue the padding and the walks of n requests (1..1024) in one launch;
-// *d_hops accumulates the launch's hops.
+// *d_hops accumulates the launch's hops; request r's error words are
+// d_err[2 r] (a start node out of range) and d_err[2 r + 1] (node2vec
+// trial-cap hits), which the caller clears before the launch.
 tw_status serve_launch(tw_graph* g, const ServeReq* reqs, int n, void* d_table, void* h_table,
-                       unsigned long long* d_hops, Error& err);
+                       unsigned long long* d_hops, uint32_t* d_err, Error& err);
 
 // serve.hip
 tw_status server_create(tw_graph* g, const tw_server_config* cfg, tw_server** out, Error& err);

@@ -97,15 +97,19 @@ struct StartState {
     int32_t len;   // nodes written so far
     int32_t cur, prev;
     int64_t t;
+    int32_t first; // the node at position 0 (when len >= 1)
 };
 
 // First pick of walk w: EDGE mode draws from the whole window, NODE mode from
-// the start node's run; writes output positions 0 and 1. rev: a backward
-// walk (candidates listed in reverse).
+// the start node's run; writes output positions 0 and 1 (out_n null: writes
+// nothing, the caller takes them from the state). rev: a backward walk
+// (candidates listed in reverse). A start node out of range sets
+// *range_flag (the graph's flag word when null).
 __device__ __forceinline__ StartState walk_start(const WalkArgs& a, const StartParams& sp, int64_t w,
                                                  uint64_t id, int32_t L, int32_t* out_n,
-                                                 int64_t* out_t, bool rev = false) {
-    StartState st{0, 0, 0, 0};
+                                                 int64_t* out_t, bool rev = false,
+                                                 uint32_t* range_flag = nullptr) {
+    StartState st{0, 0, 0, 0, -1};
     const Draw d0 = philox(id, 0, 0, sp.seed);
     if (sp.mode == TW_START_EDGE) {
         if (a.m == 0) return st;
@@ -118,11 +122,14 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, const StartP
         }
         const int32_t s = a.e_src[e], t_dst = a.e_dst[e];
         const int64_t t = a.e_ts[e];
-        out_n[0] = s;
+        if (out_n) out_n[0] = s;
+        st.first = s;
         st.len = 1;
         if (L == 1) return st;
-        out_n[1] = t_dst;
-        out_t[1] = t;
+        if (out_n) {
+            out_n[1] = t_dst;
+            out_t[1] = t;
+        }
         st.len = 2;
         st.prev = s;
         st.cur = t_dst;
@@ -131,10 +138,11 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, const StartP
     }
     const int32_t v0 = sp.nodes[w];
     if (v0 < 0 || v0 >= a.V) {
-        atomicOr(&a.err[0], 1u);
+        atomicOr(range_flag ? range_flag : &a.err[0], 1u);
         return st;
     }
-    out_n[0] = v0;
+    if (out_n) out_n[0] = v0;
+    st.first = v0;
     st.len = 1;
     if (L == 1) return st;
     const NodeRec r = a.rec[v0];
@@ -142,8 +150,10 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, const StartP
     Pick p =
         pick_node(a.ng, a.n_dst, a.n_ts, r.gb, r.ge, r.ee, sp.kind, sp.tau, r.t_last, d0, rev);
     const int32_t nx = p.dst;
-    out_n[1] = nx;
-    out_t[1] = p.t;
+    if (out_n) {
+        out_n[1] = nx;
+        out_t[1] = p.t;
+    }
     st.len = 2;
     st.prev = v0;
     st.cur = nx;
@@ -153,10 +163,12 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, const StartP
 
 // The pick of hop `hop` among groups [gc, r.ge) of node cur (previous node
 // prev): the hop bias, or node2vec's rejection loop. Returns false when
-// node2vec exhausts its trials (the walk ends).
+// node2vec exhausts its trials (the walk ends; counted in *cap_count, the
+// graph's counter word when null).
 __device__ __forceinline__ bool hop_pick(const WalkArgs& a, const HopBias& hb, uint64_t seed,
                                          const NodeRec& r, uint32_t gc, uint64_t id, uint64_t hop,
-                                         int32_t prev, Pick& p, int32_t& nx) {
+                                         int32_t prev, Pick& p, int32_t& nx,
+                                         uint32_t* cap_count = nullptr) {
     if (hb.kind == TW_WEIGHT) {
         const Draw d = philox(id, hop, 0, seed);
         p = pick_weight(a.ng, a.n_dst, a.cw, r.gb, gc, r.ge, r.ee, hb.tau > 0.0 ? hb.tau : 1.0,
@@ -182,7 +194,7 @@ __device__ __forceinline__ bool hop_pick(const WalkArgs& a, const HopBias& hb, u
         else beta = hb.inv_q;
         if (unit_closed_open(d.x2) * hb.beta_max < beta) return true;
     }
-    atomicAdd(&a.err[2], 1u);
+    atomicAdd(cap_count ? cap_count : &a.err[2], 1u);
     return false;
 }
 
@@ -232,12 +244,55 @@ __global__ void k_fill_outputs(int32_t* __restrict__ nodes, int64_t* __restrict_
               (int64_t)gridDim.x * blockDim.x);
 }
 
+// The last four output slots of a walk in registers (a shift register, so
+// no slot is ever indexed at run time): when a walk has filled slots
+// 4k..4k+3 they leave as one 16-byte store of nodes and two of timestamps.
+struct RowChunk {
+    int32_t n0 = -1, n1 = -1, n2 = -1, n3 = -1;
+    int64_t t0 = TS_NONE, t1 = TS_NONE, t2 = TS_NONE, t3 = TS_NONE;
+    __device__ __forceinline__ void push(int32_t v, int64_t t) {
+        n0 = n1;
+        n1 = n2;
+        n2 = n3;
+        n3 = v;
+        t0 = t1;
+        t1 = t2;
+        t2 = t3;
+        t3 = t;
+    }
+    // slots [at, at + 4) of a row; both pointers 16-byte aligned there
+    __device__ __forceinline__ void store(int32_t* __restrict__ on, int64_t* __restrict__ ot,
+                                          int32_t at) const {
+        *reinterpret_cast<int4*>(on + at) = make_int4(n0, n1, n2, n3);
+        *reinterpret_cast<longlong2*>(ot + at) = make_longlong2(t0, t1);
+        *reinterpret_cast<longlong2*>(ot + at + 2) = make_longlong2(t2, t3);
+    }
+};
+
+// Ends a row whose first len slots were pushed through c (and stored up to
+// the last multiple of 4): the partial chunk is completed with padding, then
+// every slot up to L (a multiple of 4) is padded with 16-byte stores.
+__device__ __forceinline__ void finish_row(RowChunk& c, int32_t* __restrict__ on,
+                                           int64_t* __restrict__ ot, int32_t len, int32_t L) {
+    int32_t at = len & ~3;
+    if (len & 3) {
+        for (int32_t k = len & 3; k < 4; ++k) c.push(-1, TS_NONE);
+        c.store(on, ot, at);
+        at += 4;
+    }
+    const RowChunk pad;
+    for (; at < L; at += 4) pad.store(on, ot, at);
+}
+
 // One full walk per thread: the full-walk baseline (Sec. "The Full-Walk
 // Baseline"). The walk is bound by dependent random loads, so waves in flight
 // count: the exponential pickers' FP64 code is held to 5 waves per SIMD and
 // the mixed-kind instantiation to 4 (a few registers spill); node2vec (more
-// live state) keeps its own allocation.
-template <int HK, int SK>
+// live state) keeps its own allocation. ROWS: the walk writes its whole
+// output row itself, four slots per store, padding included (rows of a
+// multiple of 4 slots, 16-byte aligned outputs); otherwise the rows were
+// pre-filled with padding and the walk writes the slots it reaches.
+template <int HK, int SK, bool ROWS>
 __global__ void __launch_bounds__(WALK_THREADS)
 __attribute__((amdgpu_waves_per_eu(HK == TW_NODE2VEC ? 1 : HK < 0 ? 4 : 5)))
 k_walk_full(const WalkArgs a) {
@@ -246,7 +301,13 @@ k_walk_full(const WalkArgs a) {
     const uint64_t id = a.base + (uint64_t)w;
     int32_t* out_n = a.nodes + w * a.L;
     int64_t* out_t = a.ts + w * a.L;
-    StartState st = walk_start(a, fixed_start<SK>(start_of(a)), w, id, a.L, out_n, out_t);
+    StartState st = walk_start(a, fixed_start<SK>(start_of(a)), w, id, a.L,
+                               ROWS ? nullptr : out_n, out_t);
+    RowChunk c;
+    if (ROWS) {
+        if (st.len >= 1) c.push(st.first, TS_NONE);
+        if (st.len >= 2) c.push(st.cur, st.t);
+    }
     const HopBias hb = fixed_hop<HK>(a.hop);
     int32_t len = st.len, cur = st.cur, prev = st.prev;
     int64_t tcur = st.t;
@@ -258,14 +319,20 @@ k_walk_full(const WalkArgs a) {
             Pick p;
             int32_t nx;
             if (!hop_pick(a, hb, a.seed, r, gc, id, hop, prev, p, nx)) break;
-            out_n[len] = nx;
-            out_t[len] = p.t;
+            if (ROWS) {
+                c.push(nx, p.t);
+                if (((len + 1) & 3) == 0) c.store(out_n, out_t, len - 3);
+            } else {
+                out_n[len] = nx;
+                out_t[len] = p.t;
+            }
             ++len;
             prev = cur;
             cur = nx;
             tcur = p.t;
         }
     }
+    if (ROWS) finish_row(c, out_n, out_t, len, a.L);
     finish_walk(a, w, len);
 }
 
@@ -581,6 +648,7 @@ struct ServeReqDev {
     int32_t* nodes;
     int64_t* ts;
     int32_t* len;
+    uint32_t* err;  // the request's own words: [0] start node out of range, [1] trial-cap hits
 };
 
 __global__ void __launch_bounds__(WALK_THREADS)
@@ -601,6 +669,7 @@ k_walk_serve(const WalkArgs a, const ServeReqDev* __restrict__ reqs, int nreq,
     int32_t* out_n = nullptr;
     int64_t* out_t = nullptr;
     int32_t* out_len = nullptr;
+    uint32_t* rerr = nullptr;
     StartParams sp{};
     uint64_t seed = 0;
     HopBias hb{};
@@ -635,7 +704,8 @@ k_walk_serve(const WalkArgs a, const ServeReqDev* __restrict__ reqs, int nreq,
                     out_n = R.nodes + i * (int64_t)R.L;
                     out_t = R.ts + i * (int64_t)R.L;
                     out_len = R.len + i;
-                    const StartState st = walk_start(a, sp, i, id, lim, out_n, out_t);
+                    rerr = R.err;
+                    const StartState st = walk_start(a, sp, i, id, lim, out_n, out_t, false, rerr);
                     len = st.len;
                     cur = st.cur;
                     prev = st.prev;
@@ -664,7 +734,7 @@ k_walk_serve(const WalkArgs a, const ServeReqDev* __restrict__ reqs, int nreq,
                 const uint32_t gc = fence_search(a.ng, a.fence, r, tcur, nullptr, 0, 0);
                 Pick p;
                 int32_t nx;
-                if (hop_pick(a, hb, seed, r, gc, id, hop, prev, p, nx)) {
+                if (hop_pick(a, hb, seed, r, gc, id, hop, prev, p, nx, rerr + 1)) {
                     out_n[len] = nx;
                     out_t[len] = p.t;
                     ++len;
@@ -853,10 +923,10 @@ tw_status coop_walks(tw_graph* g, const WalkArgs& a, Error& err) {
     const int64_t W = a.num_walks;
     DevBuf* bufs32[] = {&g->c_node0, &g->c_walk0, &g->c_node1, &g->c_walk1, &g->c_node2,
                         &g->c_walk2, &g->c_flags, &g->c_pos, &g->c_prev};
-    for (DevBuf* b : bufs32) TW_HIP(ensure(*b, sizeof(uint32_t) * W));
-    TW_HIP(ensure(g->c_t0, sizeof(uint64_t) * W));
-    TW_HIP(ensure(g->c_t1, sizeof(uint64_t) * W));
-    TW_HIP(ensure(g->c_t2, sizeof(uint64_t) * W));
+    for (DevBuf* b : bufs32) TW_HIP(ensure(*b, sizeof(uint32_t) * W, g->stream));
+    TW_HIP(ensure(g->c_t0, sizeof(uint64_t) * W, g->stream));
+    TW_HIP(ensure(g->c_t1, sizeof(uint64_t) * W, g->stream));
+    TW_HIP(ensure(g->c_t2, sizeof(uint64_t) * W, g->stream));
     // live (compacted) -> sorted (by node) -> next (after the hop) -> live
     Live live{g->c_node0.as<uint32_t>(), g->c_walk0.as<uint32_t>(), g->c_t0.as<uint64_t>()};
     Live sorted{g->c_node1.as<uint32_t>(), g->c_walk1.as<uint32_t>(), g->c_t1.as<uint64_t>()};
@@ -1001,7 +1071,7 @@ int resident_bpc(K kernel) {
 
 tw_status queue_walks(tw_graph* g, const WalkArgs& a, const QueueArgs& q0, int bpc, Error& err) {
     if (queue_shape(g, err) != TW_OK) return err.code;
-    TW_HIP(ensure(g->wq, sizeof(unsigned long long) * QUEUE_SLICES));
+    TW_HIP(ensure(g->wq, sizeof(unsigned long long) * QUEUE_SLICES, g->stream));
     QueueArgs q = q0;
     q.counters = g->wq.as<unsigned long long>();
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, g->stream, q.counters);
@@ -1031,55 +1101,96 @@ tw_status batch_full_walk(tw_graph* g, const WalkArgs& a, const QueueArgs& q, Er
     return TW_OK;
 }
 
+// Per-call lists of the queue dispatch of plain walks: the walks alive after
+// their start (current node, walk, time) before and after compaction, each
+// walk's previous node, the alive flags and their scan, the live count, the
+// scan's partial sums (scan_parts_u32(walks) words) and the queue counters.
+struct HopLists {
+    Live live, next;
+    int32_t* prev;
+    uint32_t* flags;
+    uint32_t* pos;
+    uint32_t* n_live;
+    uint32_t* scan_part;
+    unsigned long long* counters;
+};
+
 // The queue dispatch of plain walks: every start in one pass (as the
 // cooperative dispatch starts), the live walks compacted, then one
-// persistent launch of k_walk_hops over them.
-tw_status queue_hops(tw_graph* g, const WalkArgs& a, int bpc, Error& err) {
+// persistent launch of k_walk_hops over them. Allocates nothing.
+tw_status queue_hops_in(tw_graph* g, const WalkArgs& a, int bpc, const HopLists& h,
+                        Error& err) {
     hipStream_t s = g->stream;
     const int64_t W = a.num_walks;
     if (queue_shape(g, err) != TW_OK) return err.code;
-    DevBuf* bufs32[] = {&g->c_node0, &g->c_walk0, &g->c_node2, &g->c_walk2, &g->c_flags,
-                        &g->c_pos, &g->c_prev};
-    for (DevBuf* b : bufs32) TW_HIP(ensure(*b, sizeof(uint32_t) * W));
-    TW_HIP(ensure(g->c_t0, sizeof(uint64_t) * W));
-    TW_HIP(ensure(g->c_t2, sizeof(uint64_t) * W));
-    TW_HIP(ensure(g->wq, sizeof(unsigned long long) * QUEUE_SLICES));
-    Live live{g->c_node0.as<uint32_t>(), g->c_walk0.as<uint32_t>(), g->c_t0.as<uint64_t>()};
-    Live next{g->c_node2.as<uint32_t>(), g->c_walk2.as<uint32_t>(), g->c_t2.as<uint64_t>()};
-    int32_t* prev = g->c_prev.as<int32_t>();
-    uint32_t* flags = g->c_flags.as<uint32_t>();
-    uint32_t* pos = g->c_pos.as<uint32_t>();
-    uint32_t* n_live_d = g->scal.as<uint32_t>() + SLOT_U32_N_LIVE;
     const dim3 wgrid((unsigned)ceil_div(W, WALK_THREADS));
     with_kinds(-1, a.start_kind, [&](auto, auto sk) {
         hipLaunchKernelGGL((k_coop_start<decltype(sk)::value>), wgrid, dim3(WALK_THREADS), 0, s, a,
-                           next, prev, flags);
+                           h.next, h.prev, h.flags);
     });
-    TW_HIP(scan_exclusive_u32(flags, pos, W, n_live_d, g->ws, s));
-    hipLaunchKernelGGL(k_compact_live, wgrid, dim3(WALK_THREADS), 0, s, flags, pos, W, next, live);
-    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, g->wq.as<unsigned long long>());
-    with_kinds(a.hop.kind, TW_UNIFORM, [&](auto h, auto) {
-        auto kernel = k_walk_hops<decltype(h)::value>;
+    TW_HIP(scan_exclusive_u32_into(h.flags, h.pos, W, h.n_live, h.scan_part, s));
+    hipLaunchKernelGGL(k_compact_live, wgrid, dim3(WALK_THREADS), 0, s, h.flags, h.pos, W, h.next,
+                       h.live);
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, h.counters);
+    with_kinds(a.hop.kind, TW_UNIFORM, [&](auto hk, auto) {
+        auto kernel = k_walk_hops<decltype(hk)::value>;
         static const int maxb = resident_bpc(kernel);  // per instantiation
         const int b = (bpc <= 0 || bpc > maxb) ? maxb : bpc;
         const int64_t blocks =
             std::min<int64_t>(ceil_div(W, WALK_THREADS), (int64_t)g->cu_count * b);
         hipLaunchKernelGGL(kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)),
-                           dim3(WALK_THREADS), 0, s, a, live, prev, n_live_d,
-                           g->wq.as<unsigned long long>());
+                           dim3(WALK_THREADS), 0, s, a, h.live, h.prev, h.n_live, h.counters);
     });
     TW_HIP(hipGetLastError());
     return TW_OK;
 }
 
-// run the walks of `a` (outputs already padded) under a dispatch
+// The same with the lists in the graph's buffers (grown as needed).
+tw_status queue_hops(tw_graph* g, const WalkArgs& a, int bpc, Error& err) {
+    const int64_t W = a.num_walks;
+    DevBuf* bufs32[] = {&g->c_node0, &g->c_walk0, &g->c_node2, &g->c_walk2, &g->c_flags,
+                        &g->c_pos, &g->c_prev};
+    for (DevBuf* b : bufs32) TW_HIP(ensure(*b, sizeof(uint32_t) * W, g->stream));
+    TW_HIP(ensure(g->c_t0, sizeof(uint64_t) * W, g->stream));
+    TW_HIP(ensure(g->c_t2, sizeof(uint64_t) * W, g->stream));
+    TW_HIP(ensure(g->wq, sizeof(unsigned long long) * QUEUE_SLICES, g->stream));
+    TW_HIP(ensure(g->ws.scan_part, sizeof(uint32_t) * scan_parts_u32(W), g->stream));
+    HopLists h;
+    h.live = Live{g->c_node0.as<uint32_t>(), g->c_walk0.as<uint32_t>(), g->c_t0.as<uint64_t>()};
+    h.next = Live{g->c_node2.as<uint32_t>(), g->c_walk2.as<uint32_t>(), g->c_t2.as<uint64_t>()};
+    h.prev = g->c_prev.as<int32_t>();
+    h.flags = g->c_flags.as<uint32_t>();
+    h.pos = g->c_pos.as<uint32_t>();
+    h.n_live = g->scal.as<uint32_t>() + SLOT_U32_N_LIVE;
+    h.scan_part = g->ws.scan_part.as<uint32_t>();
+    h.counters = g->wq.as<unsigned long long>();
+    return queue_hops_in(g, a, bpc, h, err);
+}
+
+// Whether the full-walk kernel writes whole output rows itself (four slots
+// per 16-byte store, padding included): rows of a multiple of 4 slots and
+// 16-byte aligned outputs.
+bool own_rows(const WalkArgs& a) {
+    return a.L % 4 == 0 && (reinterpret_cast<uintptr_t>(a.nodes) & 15) == 0 &&
+           (reinterpret_cast<uintptr_t>(a.ts) & 15) == 0;
+}
+
+// run the walks of `a` under a dispatch; the output rows are padded first
+// unless the walk kernel writes them whole
 tw_status run_dispatch(tw_graph* g, const WalkArgs& a, int dispatch, int bpc, Error& err) {
+    if (dispatch != TW_DISPATCH_FULL_WALK || !own_rows(a))
+        launch_fill(g, a.nodes, a.ts, a.num_walks * (int64_t)a.L);
     if (dispatch == TW_DISPATCH_COOP) return coop_walks(g, a, err);
     if (dispatch == TW_DISPATCH_QUEUE) return queue_hops(g, a, bpc, err);
+    const bool rows = own_rows(a);
     with_kinds(a.hop.kind, a.start_kind, [&](auto h, auto st) {
-        hipLaunchKernelGGL((k_walk_full<decltype(h)::value, decltype(st)::value>),
-                           dim3((unsigned)ceil_div(a.num_walks, WALK_THREADS)), dim3(WALK_THREADS),
-                           0, g->stream, a);
+        const dim3 grid((unsigned)ceil_div(a.num_walks, WALK_THREADS));
+        if (rows)
+            hipLaunchKernelGGL((k_walk_full<decltype(h)::value, decltype(st)::value, true>), grid,
+                               dim3(WALK_THREADS), 0, g->stream, a);
+        else
+            hipLaunchKernelGGL((k_walk_full<decltype(h)::value, decltype(st)::value, false>),
+                               grid, dim3(WALK_THREADS), 0, g->stream, a);
     });
     TW_HIP(hipGetLastError());
     return TW_OK;
@@ -1149,7 +1260,6 @@ tw_status sample_walks(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int
     WalkArgs a;
     if (prepare_plain(g, p, nodes, ts, len, a, err) != TW_OK) return err.code;
     if (p->num_walks == 0) return TW_OK;
-    launch_fill(g, nodes, ts, p->num_walks * (int64_t)p->max_len);
     int dispatch = p->dispatch;
     // AUTO: the autotuned choice, else the full-walk kernel
     if (dispatch == TW_DISPATCH_AUTO)
@@ -1228,7 +1338,7 @@ tw_status check_walk_params(const tw_walk_params* p, Error& err) {
 size_t serve_table_bytes(int n) { return sizeof(ServeReqDev) * (size_t)std::max(n, 1); }
 
 tw_status serve_launch(tw_graph* g, const ServeReq* reqs, int n, void* d_table, void* h_table,
-                       unsigned long long* d_hops, Error& err) {
+                       unsigned long long* d_hops, uint32_t* d_err, Error& err) {
     if (n < 1 || n > SERVE_MAX_REQ) {
         err = Error{TW_EINVAL, "serve: 1..1024 requests per launch"};
         return err.code;
@@ -1257,6 +1367,7 @@ tw_status serve_launch(tw_graph* g, const ServeReq* reqs, int n, void* d_table, 
         d.nodes = q.nodes;
         d.ts = q.ts;
         d.len = q.len;
+        d.err = d_err + 2 * r;
         tab[r] = d;
         total += q.count;
     }
@@ -1266,7 +1377,7 @@ tw_status serve_launch(tw_graph* g, const ServeReq* reqs, int n, void* d_table, 
                   nullptr, a, err) != TW_OK)
         return err.code;
     if (queue_shape(g, err) != TW_OK) return err.code;
-    TW_HIP(ensure(g->wq, sizeof(unsigned long long) * QUEUE_SLICES));
+    TW_HIP(ensure(g->wq, sizeof(unsigned long long) * QUEUE_SLICES, g->stream));
     TW_HIP(hipMemcpyAsync(d_table, h_table, sizeof(ServeReqDev) * n, hipMemcpyHostToDevice,
                           g->stream));
     for (int r = 0; r < n; ++r)
@@ -1328,7 +1439,6 @@ tw_status autotune(tw_graph* g, const tw_walk_params* p, int64_t sample, int32_t
     for (const Cand& c : cands) {
         float ms_min = 0.0f;
         for (int rep = 0; rep < 3; ++rep) {  // the first run warms up
-            launch_fill(g, nodes, ts, q.num_walks * (int64_t)q.max_len);
             hipEventRecord(e0, g->stream);
             if (run_dispatch(g, a, c.dispatch, c.bpc, err) != TW_OK) {
                 hipEventDestroy(e0);

@@ -216,8 +216,8 @@ tw_status build_weights(tw_graph* g, double tau, Error& err) {
     if (g->w_ready && g->w_scale == sc) return TW_OK;
     hipStream_t s = g->stream;
     const int64_t V = g->V;
-    TW_HIP(ensure(g->v_flags, sizeof(uint32_t) * (V + 1)));
-    TW_HIP(ensure(g->v_pos, sizeof(uint32_t) * (V + 1)));
+    TW_HIP(ensure(g->v_flags, sizeof(uint32_t) * (V + 1), g->stream));
+    TW_HIP(ensure(g->v_pos, sizeof(uint32_t) * (V + 1), g->stream));
     uint32_t* cnt = g->v_flags.as<uint32_t>();
     uint32_t* off = g->v_pos.as<uint32_t>();
     uint32_t* Gd = g->scal.as<uint32_t>() + SLOT_U32_W_GROUPS;
@@ -230,8 +230,8 @@ tw_status build_weights(tw_graph* g, double tau, Error& err) {
         err = Error{TW_ENOMEM, "weight build: too many groups"};
         return err.code;
     }
-    TW_HIP(ensure(g->cw, sizeof(double) * std::max<int64_t>(g->pg_cap, 1)));
-    TW_HIP(ensure(g->w_tiles, (sizeof(uint32_t) + sizeof(double)) * 2 * nt));
+    TW_HIP(ensure(g->cw, sizeof(double) * std::max<int64_t>(g->pg_cap, 1), g->stream));
+    TW_HIP(ensure(g->w_tiles, (sizeof(uint32_t) + sizeof(double)) * 2 * nt, g->stream));
     uint32_t* t_head = g->w_tiles.as<uint32_t>();
     uint32_t* c_head = t_head + nt;
     double* t_sum = reinterpret_cast<double*>(c_head + nt);  // 8 nt bytes in: aligned

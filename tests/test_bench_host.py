@@ -20,12 +20,15 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 
 def test_walk_bytes_model():
-    # per walk: a start pick (3 sectors uniform, 4 biased) and its output
-    # row (12 B a slot plus the 4-byte length); per hop 3 or 4 sectors
+    # per hop (the start edge included): 4 random 64 B sectors for a biased
+    # pick, 3 for a uniform one, and 12 B of output; per walk its length and
+    # first node (8 B); padding slots are not counted
     S = bench.SECTOR
-    assert bench.walk_bytes(1, 0, 1, "uniform", "uniform") == 3 * S + 12 + 4
-    assert bench.walk_bytes(2, 5, 10, "exponential", "linear") == 2 * 4 * S + 5 * 4 * S + 2 * 124
-    assert bench.walk_bytes(0, 7, 3, "uniform", "uniform") == 7 * 3 * S
+    assert bench.walk_bytes(1, 0, "uniform") == 8
+    assert bench.walk_bytes(2, 5, "linear") == 5 * (4 * S + 12) + 16
+    assert bench.walk_bytes(0, 7, "uniform") == 7 * (3 * S + 12)
+    # the stream workload's linear hops: 268 B each
+    assert bench.walk_bytes(0, 1, "linear") == 268
 
 
 def test_ingest_bytes_models():
@@ -43,16 +46,16 @@ def test_ingest_bytes_models():
 def test_traffic_summary_is_tied_to_the_walk_sources(tmp_path, monkeypatch):
     # the committed summary counts only while the walk sources hash to its
     # value: a changed hash turns traffic into None
-    with open(bench.TRAFFIC_FILE) as fh:
+    with open(bench.TRAFFIC_FILES["single"]) as fh:
         head, tail = fh.read().split("\n---\n", 1)
     rec = json.loads(head)
     assert rec["fetch_bytes"] > 0 and rec["write_bytes"] > 0
     assert set(rec) >= {"kernel", "workload", "fetch_scale", "write_scale", "source_sha256"}
     t = bench.measured_traffic("single")
     assert t is None or t == rec["fetch_bytes"] + rec["write_bytes"]
-    assert bench.measured_traffic("stream") is None
+    assert bench.measured_traffic("mixed") is None
     fake = tmp_path / "traffic.txt"
     rec["source_sha256"] = "0" * 64
     fake.write_text(json.dumps(rec) + "\n---\n" + tail)
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(fake))
+    monkeypatch.setitem(bench.TRAFFIC_FILES, "single", str(fake))
     assert bench.measured_traffic("single") is None

@@ -80,7 +80,9 @@ def test_batch_mixed_parity(ragged, start_mode, dispatch):
             gt[i, :lims[i]] = ft[r[i]:r[i + 1]]
     else:
         gn, gt = nodes.cpu().numpy(), ts.cpu().numpy()
-    same, boundary = compare_walks((gn, gt, lens.cpu().numpy()), ref, exact=False)
+    same, boundary = compare_walks((gn, gt, lens.cpu().numpy()), ref, exact=False,
+                                   label=f"batch {dispatch} ragged={ragged} {start_mode}",
+                                   kind="mixed")
     print(f"batch {dispatch} ragged={ragged} {start_mode}: {same}/{W} identical, "
           f"{boundary} at a boundary")
     assert boundary <= max(2, W // 2000)

@@ -89,7 +89,8 @@ def test_single_batch_full_scale():
     sel = torch.from_numpy(idx).to(nodes.device)
     gpu = (nodes.index_select(0, sel).cpu().numpy(), wts.index_select(0, sel).cpu().numpy(),
            lens.index_select(0, sel).cpu().numpy())
-    same, boundary = compare_walks(gpu, r, exact=False)
+    same, boundary = compare_walks(gpu, r, exact=False, label="single full scale (sampled ids)",
+                                   kind="exponential")
     print(f"single full scale: {same}/{len(idx)} sampled walks identical, {boundary} at a "
           f"CDF boundary")
     assert boundary <= max(2, len(idx) // 2000)
@@ -143,4 +144,83 @@ def test_stream_window_full_scale():
     assert np.array_equal(nodes.index_select(0, sel).cpu().numpy(), r["nodes"])
     assert np.array_equal(wts.index_select(0, sel).cpu().numpy(), r["ts"])
     assert np.array_equal(lens.index_select(0, sel).cpu().numpy(), r["len"])
+    g.close()
+
+
+def _ragged_properties(torch, nodes, ts, lens, row, lims, V):
+    """The per-walk properties of _walk_properties on packed rows: walk i owns
+    slots [row[i], row[i] + lims[i])."""
+    W = lens.numel()
+    lim = lims.to(torch.int64)
+    assert int((lens < 0).sum()) == 0 and bool((lens.to(torch.int64) <= lim).all())
+    owner = torch.repeat_interleave(torch.arange(W, device=nodes.device), lim)
+    pos = torch.arange(owner.numel(), device=nodes.device) - row[:-1].index_select(0, owner)
+    inside = pos < lens.to(torch.int64).index_select(0, owner)
+    assert bool(((nodes >= 0) & (nodes < V))[inside].all())
+    assert bool((nodes[~inside] == -1).all())
+    assert bool((ts[~inside] == INT64_MIN).all())
+    assert bool((ts.index_select(0, row[:-1]) == INT64_MIN).all())
+    nxt = torch.zeros_like(inside)
+    nxt[:-1] = inside[1:] & (pos[1:] >= 2)
+    assert bool((ts[1:] > ts[:-1])[nxt[:-1]].all())
+    del owner, pos, inside, nxt
+
+
+@pytest.mark.timeout(900)
+def test_mixed_batch_full_scale():
+    # 1M nodes, 20M undirected edges (40M records), Zipf-Mandelbrot 1.5 with
+    # rank offset 200 (hubs of about 1e5 edges); 8M walks with lengths
+    # uniform in [5, 120] and six hop biases (walk id mod 6) in one work-queue
+    # launch on packed rows, as the mixed-batch benchmark runs it
+    torch, tw = gpu_or_skip()
+    w = synth.workload("mixed")
+    spec = w["stream"]
+    src, dst, ts = spec.all()
+    deg = np.bincount(np.concatenate([src, dst]), minlength=spec.num_nodes)
+    assert 5e4 < deg.max() < 5e5, deg.max()
+    tau = float(w["tau_frac"] * int(ts.max() - ts.min()))
+    g = tw.Graph(spec.num_nodes, directed=spec.directed)
+    info = g.ingest_batch(*to_dev(torch, src, dst, ts))
+    assert info["active_edges"] == 2 * spec.num_edges
+    W, L = w["walks"], w["max_len"]
+    lims_np = synth.walk_lengths(4, W, w["min_len"], L)
+    lims = to_dev(torch, lims_np)[0]
+    biases = synth.mixed_biases(tau)
+    rows = g.row_offsets(lims)
+    nodes, wts, lens, row = g.sample_walks_batch(W, L, biases, max_lens=lims, seed=42,
+                                                 ragged=True, rows=rows, dispatch="queue")
+    g.sync()
+    _ragged_properties(torch, nodes, wts, lens, row, lims, spec.num_nodes)
+    og = oracle.OracleGraph(spec.num_nodes, directed=spec.directed)
+    og.ingest_batch(src, dst, ts)
+    del src, dst, ts
+    rng = np.random.default_rng(9)
+    row_np = row.cpu().numpy()
+    for b, (kind, ht, p, q) in enumerate(biases):
+        ids = np.arange(b, W, len(biases), dtype=np.int64)
+        idx = np.unique(np.concatenate([ids[:4], ids[-4:], rng.choice(ids, 4096, False)]))
+        r = og.sample_walks(W, L, hop_bias=kind, hop_tau=ht, p=p, q=q, seed=42, walk_idx=idx,
+                            with_margin=True, threads=oracle.threads())
+        assert r["cap_hits"] == 0
+        lim = lims_np[idx]
+        gn = np.full((len(idx), L), -1, np.int32)
+        gt = np.full((len(idx), L), INT64_MIN, np.int64)
+        sel = torch.from_numpy(np.concatenate([np.arange(row_np[i], row_np[i] + lim[k])
+                                               for k, i in enumerate(idx)])).to(nodes.device)
+        fn, ft = nodes.index_select(0, sel).cpu().numpy(), wts.index_select(0, sel).cpu().numpy()
+        o = 0
+        for k in range(len(idx)):
+            gn[k, :lim[k]] = fn[o:o + lim[k]]
+            gt[k, :lim[k]] = ft[o:o + lim[k]]
+            o += lim[k]
+        for k in range(len(idx)):  # the oracle's walk cut to the limit
+            r["nodes"][k, lim[k]:] = -1
+            r["ts"][k, lim[k]:] = INT64_MIN
+            r["len"][k] = min(r["len"][k], lim[k])
+        gl = lens.index_select(0, torch.from_numpy(idx).to(nodes.device)).cpu().numpy()
+        same, boundary = compare_walks((gn, gt, gl), r, exact=kind in ("uniform", "linear"),
+                                       label=f"mixed full scale {kind}({p},{q})", kind=kind)
+        print(f"mixed full scale {kind}({p},{q}): {same}/{len(idx)} identical, {boundary} at a "
+              f"CDF boundary; mean length {float(r['len'].mean()):.1f}")
+        assert boundary <= max(2, len(idx) // 2000)
     g.close()

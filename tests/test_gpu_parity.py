@@ -165,7 +165,8 @@ def test_walk_parity(ci, directed, dispatch):
                         with_margin=True)
     exact = hk in ("uniform", "linear") and sk in ("uniform", "linear")
     same, boundary = compare_walks((nodes.cpu().numpy(), tts.cpu().numpy(), lens.cpu().numpy()),
-                                   r, exact)
+                                   r, exact, label=f"walk_parity {dispatch} directed={directed} "
+                                                   f"{hk}/{sk}/{mode}", kind=hk)
     hops = int(np.maximum(r["len"] - 1, 0).sum())
     print(f"{dispatch} {hk}/{sk}/{mode}: {same}/{W} identical, boundary mismatches {boundary} "
           f"({boundary / max(hops, 1):.2e} per hop)")
@@ -430,7 +431,8 @@ def test_weight_walks_follow_the_window():
             r = og.sample_walks(4000, 12, hop_bias="weight", hop_tau=tau, seed=b,
                                 with_margin=True)
             same, boundary = compare_walks(
-                (nodes.cpu().numpy(), ts.cpu().numpy(), lens.cpu().numpy()), r, False)
+                (nodes.cpu().numpy(), ts.cpu().numpy(), lens.cpu().numpy()), r, False,
+                label=f"weight window batch {b} tau {tau}", kind="weight")
             assert boundary <= 2, (b, tau, same, boundary)
     g.close()
 
@@ -469,7 +471,8 @@ def test_backward_walk_parity(ci, directed):
     r = og.sample_walks(W, L, start_nodes=starts, with_margin=True, direction="backward", **kw)
     exact = hk in ("uniform", "linear") and sk in ("uniform", "linear")
     same, boundary = compare_walks((nodes.cpu().numpy(), tts.cpu().numpy(), lens.cpu().numpy()),
-                                   r, exact)
+                                   r, exact, label=f"backward directed={directed} {hk}/{sk}/{mode}",
+                                   kind=hk)
     print(f"backward {hk}/{sk}/{mode} directed={directed}: {same}/{W} identical, "
           f"{boundary} at a boundary; mean length {float(r['len'].mean()):.2f}")
     assert boundary <= max(2, W // 2000)

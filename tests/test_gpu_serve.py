@@ -161,3 +161,142 @@ def test_server_concurrent_submitters():
     g2.sync()
     g.close()
     g2.close()
+
+
+def _served_case(V, tau, torch, seed0, starts):
+    """Requests of every hop kind, EDGE and NODE starts, sizes that share and
+    split launches."""
+    kinds = [("uniform", 0.0, 1.0, 1.0), ("linear", 0.0, 1.0, 1.0),
+             ("exponential", tau, 1.0, 1.0), ("node2vec", tau, 0.5, 2.0),
+             ("node2vec", tau, 2.0, 0.5), ("node2vec", tau, 1.0, 1.0)]
+    reqs = []
+    for j in range(7):
+        kind, ht, p, q = kinds[(seed0 + j) % len(kinds)]
+        r = dict(num_walks=[700, 3000, 150, 12_000, 1200, 450, 5000][j],
+                 max_len=[10, 40, 80, 12, 25, 6, 30][j], hop_bias=kind, hop_tau=ht, p=p, q=q,
+                 seed=seed0 * 100 + j, walk_id_base=37 * j)
+        if j % 3 == 1:
+            r.update(start_mode="node", start_nodes=starts)
+        if j % 2 == 0:
+            r.update(start_bias="exponential", start_tau=tau)
+        reqs.append(r)
+    return reqs
+
+
+def test_served_mix_matches_oracle():
+    # ingest batches interleaved with 21 requests through one server; each
+    # request's walks are compared with the oracle's on that request's epoch
+    # window (the batches submitted before it), on sampled walk ids, under
+    # the boundary tolerance
+    import oracle
+    from gpu_util import compare_walks
+    torch, tw = gpu_or_skip()
+    V, n = 6000, 50_000
+    bs = _stream(V, 4, n)
+    span = int(bs[0][2][-1] - bs[0][2][0])
+    window = int(1.5 * span)
+    tau = 0.1 * window
+    dev = [to_dev(torch, *b) for b in bs]
+    starts_np = synth.start_nodes(31, 12_000, V)
+    starts = to_dev(torch, starts_np)[0]
+    torch.cuda.synchronize()
+    g = tw.Graph(V, window=window)
+    srv = tw.Server(g, arena_bytes=512 << 20, max_walks_per_launch=8_000, max_inflight=3)
+    plan = []  # (epoch, request params, id)
+    ingests = [srv.ingest(*dev[0]), srv.ingest(*dev[1])]
+    for ep in (2, 3, 4):
+        for r in _served_case(V, tau, torch, ep, starts):
+            plan.append((ep, r, srv.submit(**r)))
+        if ep < 4:
+            ingests.append(srv.ingest(*dev[ep]))
+    results = {rid: srv.result(rid) for _, _, rid in plan}
+    for i in ingests:
+        assert srv.wait(i)["status"] == tw.TW_OK
+    for _, _, rid in plan:
+        assert srv.wait(rid)["status"] == tw.TW_OK
+    st = srv.stats()
+    assert st["requests_done"] == len(plan) >= 20
+    assert st["launches"] < len(plan)  # requests shared launches
+    srv.close()
+    g.close()
+    og = oracle.OracleGraph(V, window=window)
+    og.ingest_batch(*bs[0])
+    epoch = 1
+    rng = np.random.default_rng(5)
+    totals = {}
+    for ep, r, rid in plan:
+        while epoch < ep:
+            og.ingest_batch(*bs[epoch])
+            epoch += 1
+        W, L = r["num_walks"], r["max_len"]
+        idx = np.unique(np.concatenate([[0, W - 1], rng.integers(0, W, 600)])).astype(np.int64)
+        kw = {k: v for k, v in r.items() if k not in ("num_walks", "max_len", "start_nodes")}
+        if r.get("start_mode") == "node":
+            kw["start_nodes"] = starts_np
+        ref = og.sample_walks(W, L, walk_idx=idx, with_margin=True, **kw)
+        nodes, ts, lens = (x.cpu().numpy() for x in results[rid])
+        exact = r["hop_bias"] in ("uniform", "linear") and r.get("start_bias") is None
+        same, boundary = compare_walks((nodes[idx], ts[idx], lens[idx]), ref, exact,
+                                       label=f"served epoch {ep} {r['hop_bias']} "
+                                             f"{r.get('start_mode', 'edge')}",
+                                       kind=r["hop_bias"])
+        totals[r["hop_bias"]] = totals.get(r["hop_bias"], 0) + boundary
+        assert boundary <= 2, (ep, r["hop_bias"], same, boundary)
+
+
+def test_served_out_of_range_start_fails_only_its_request():
+    torch, tw = gpu_or_skip()
+    V = 2000
+    (s, d, t), = _stream(V, 1, 20_000)
+    dev = to_dev(torch, s, d, t)
+    bad = to_dev(torch, np.array([3, V + 5, 7], np.int32))[0]
+    torch.cuda.synchronize()
+    g = tw.Graph(V)
+    srv = tw.Server(g, arena_bytes=64 << 20)
+    srv.wait(srv.ingest(*dev))
+    ok1 = srv.submit(500, 8, hop_bias="linear", seed=1)
+    bad_id = srv.submit(3, 8, start_mode="node", start_nodes=bad, seed=2)
+    ok2 = srv.submit(500, 8, hop_bias="uniform", seed=3)
+    assert srv.wait(ok1)["status"] == tw.TW_OK
+    assert srv.wait(bad_id)["status"] == tw.TW_ERANGE
+    assert srv.wait(ok2)["status"] == tw.TW_OK
+    for i in (ok1, bad_id, ok2):
+        srv.release(i)
+    # the graph's own flags are untouched: later calls succeed
+    assert srv.wait(srv.ingest(*dev))["status"] == tw.TW_OK
+    srv.close()
+    g.ingest_batch(*dev)
+    g.sync()
+    g.close()
+
+
+def test_backward_walks_after_a_server_session():
+    # the in-view of a directed graph receives the batches the server ingests
+    import oracle
+    from gpu_util import compare_walks
+    torch, tw = gpu_or_skip()
+    V, n = 3000, 30_000
+    bs = _stream(V, 3, n)
+    dev = [to_dev(torch, *b) for b in bs]
+    torch.cuda.synchronize()
+    g = tw.Graph(V)
+    og = oracle.OracleGraph(V, backward=True)
+    g.ingest_batch(*dev[0])
+    og.ingest_batch(*bs[0])
+    g.sample_walks(100, 5, direction="backward")  # creates the in-view
+    g.sync()
+    srv = tw.Server(g, arena_bytes=64 << 20)
+    for b in dev[1:]:
+        assert srv.wait(srv.ingest(*b))["status"] == tw.TW_OK
+    srv.close()
+    for b in bs[1:]:
+        og.ingest_batch(*b)
+    W, L = 5000, 12
+    nodes, ts, lens = g.sample_walks(W, L, hop_bias="linear", direction="backward", seed=4)
+    g.sync()
+    ref = og.sample_walks(W, L, hop_bias="linear", direction="backward", seed=4,
+                          with_margin=True)
+    same, boundary = compare_walks((nodes.cpu().numpy(), ts.cpu().numpy(), lens.cpu().numpy()),
+                                   ref, exact=True)
+    assert same == W
+    g.close()
