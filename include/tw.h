@@ -281,6 +281,38 @@ tw_status tw_autotune(tw_graph* g, const tw_walk_params* params, int64_t sample_
                       int32_t* d_nodes, int64_t* d_ts, int32_t* d_len, int32_t best[2]);
 
 /* ------------------------------------------------------------------------
+ * Allocation-free walks, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.
+ */
+
+/* Most walks one tw_sample_walks_noalloc call takes. */
+#define TW_NOALLOC_MAX_WALKS 262144
+
+/*
+ * The walks of tw_sample_walks with TW_DISPATCH_QUEUE (the same results),
+ * with no device allocation, free or memset: the call's lists (live walks
+ * and their previous nodes, alive flags and their scan, the work-queue
+ * counters; 44 bytes a walk, 11.5 MB in all) live in one array that the
+ * library holds on every device it runs on until the process ends, set up by
+ * tw_create. Every clearing is a kernel, so the call can be captured in a
+ * HIP graph. Arguments and outputs as tw_sample_walks; params->dispatch is
+ * ignored. Stream-ordered, no synchronisation.
+ * All calls on one device share the array and each call's kernels consume
+ * what its own earlier kernels wrote there: calls that overlap on one device
+ * (other streams, other host threads, replays of captured graphs running
+ * concurrently) race and give wrong walks. Serialise them.
+ * Returns TW_EINVAL, nothing enqueued, for num_walks > TW_NOALLOC_MAX_WALKS,
+ * backward walks, a TW_WEIGHT hop bias (its weights are built lazily), a
+ * graph that has not ingested yet, a TW_NODE2VEC hop bias while the node2vec
+ * adjacency of the current window is not built (one tw_sample_walks call
+ * with a node2vec bias after the last ingest or eviction builds it), and for
+ * every bad parameter tw_sample_walks rejects.
+ */
+tw_status tw_sample_walks_noalloc(tw_graph* g, const tw_walk_params* params, int32_t* d_nodes,
+                                  int64_t* d_ts, int32_t* d_len);
+
+/* ------------------------------------------------------------------------
  * Serving: continuous batching of walk requests interleaved with ingestion.
  *
  * A server owns a graph (the caller must not use the graph directly while

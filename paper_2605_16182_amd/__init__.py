@@ -26,6 +26,7 @@ START_MODES = {"edge": START_EDGE, "node": START_NODE}
 DISPATCH = {"auto": 0, "full_walk": 1, "coop": 2, "queue": 3}
 DISPATCH_NAMES = {v: k for k, v in DISPATCH.items()}
 MAX_BIASES = 8
+MAX_NOALLOC_WALKS = 262144  # TW_NOALLOC_MAX_WALKS
 TW_OK, TW_EINVAL, TW_ENOMEM, TW_EDEVICE, TW_ERANGE, TW_ETIMEOUT = 0, 1, 2, 3, 4, 5
 TS_NONE = -(1 << 63)
 
@@ -102,6 +103,7 @@ def lib():
         "tw_ingest_batch": ([P, P, P, P, I64, _c.POINTER(_Info)], _c.c_int),
         "tw_evict_before": ([P, I64, _c.POINTER(I64)], _c.c_int),
         "tw_sample_walks": ([P, _c.POINTER(_WalkParams), P, P, P], _c.c_int),
+        "tw_sample_walks_noalloc": ([P, _c.POINTER(_WalkParams), P, P, P], _c.c_int),
         "tw_sync": ([P], _c.c_int),
         "tw_stats": ([P, _c.POINTER(_Info)], _c.c_int),
         "tw_view_sizes": ([P, _c.POINTER(I64)], _c.c_int),
@@ -223,6 +225,26 @@ class Graph:
                           int(walk_id_base), DISPATCH[dispatch], DIRECTIONS[direction])
         _check(self._lib.tw_sample_walks(self._h, _c.byref(prm), _ptr(nodes), _ptr(ts),
                                          _ptr(lens)))
+        return nodes, ts, lens
+
+    def sample_walks_noalloc(self, num_walks: int, max_len: int, out, hop_bias: str = "uniform",
+                             hop_tau: float = 0.0, p: float = 1.0, q: float = 1.0,
+                             start_bias: str = "uniform", start_tau: float = 0.0,
+                             start_mode: str = "edge", start_nodes: Optional[torch.Tensor] = None,
+                             seed: int = 42, walk_id_base: int = 0):
+        """tw_sample_walks_noalloc into the caller's out = (nodes int32[W, L],
+        ts int64[W, L], len int32[W]): the queue dispatch's walks with no
+        device allocation (at most MAX_NOALLOC_WALKS walks)."""
+        W, L = int(num_walks), int(max_len)
+        nodes, ts, lens = out
+        if start_nodes is not None:
+            assert start_nodes.dtype == torch.int32 and start_nodes.numel() >= W
+        prm = _WalkParams(W, L, _Bias(KINDS[hop_bias], float(hop_tau), float(p), float(q)),
+                          _Bias(KINDS[start_bias], float(start_tau), 1.0, 1.0),
+                          START_MODES[start_mode], _ptr(start_nodes), int(seed),
+                          int(walk_id_base), DISPATCH["queue"], DIRECTIONS["forward"])
+        _check(self._lib.tw_sample_walks_noalloc(self._h, _c.byref(prm), _ptr(nodes), _ptr(ts),
+                                                 _ptr(lens)))
         return nodes, ts, lens
 
     def sample_walks_batch(self, num_walks: int, max_len: int, hop_biases,

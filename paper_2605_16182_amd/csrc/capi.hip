@@ -84,6 +84,12 @@ tw_status tw_create(const tw_config* cfg, tw_graph** out) {
             delete g;
             return fail(TW_EDEVICE, "tw_create: no HIP device");
         }
+        // the device array of tw_sample_walks_noalloc, with the device current
+        tw::Error e{TW_OK, ""};
+        if (tw::noalloc_setup(g->device, e) != TW_OK) {
+            delete g;
+            return report(e.code, e);
+        }
         *out = g;
         return TW_OK;
     });
@@ -138,6 +144,16 @@ tw_status tw_sample_walks(tw_graph* g, const tw_walk_params* params, int32_t* d_
         if (refuse_broken(g, "tw_sample_walks") != TW_OK) return TW_EDEVICE;
         tw::Error e{TW_OK, ""};
         return report(tw::sample_walks(g, params, d_nodes, d_ts, d_len, e), e);
+    });
+}
+
+tw_status tw_sample_walks_noalloc(tw_graph* g, const tw_walk_params* params, int32_t* d_nodes,
+                                  int64_t* d_ts, int32_t* d_len) {
+    if (!g) return fail(TW_EINVAL, "tw_sample_walks_noalloc: null graph");
+    return guarded("tw_sample_walks_noalloc", [&]() -> tw_status {
+        if (refuse_broken(g, "tw_sample_walks_noalloc") != TW_OK) return TW_EDEVICE;
+        tw::Error e{TW_OK, ""};
+        return report(tw::sample_walks_noalloc(g, params, d_nodes, d_ts, d_len, e), e);
     });
 }
 

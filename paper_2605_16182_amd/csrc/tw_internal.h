@@ -442,6 +442,11 @@ tw_status row_offsets(tw_graph* g, const int32_t* max_len, int64_t n, int64_t* r
                       int64_t* total, Error& err);
 tw_status autotune(tw_graph* g, const tw_walk_params* p, int64_t sample, int32_t* nodes,
                    int64_t* ts, int32_t* len, int32_t best[2], Error& err);
+// allocation-free walks: set-up once per device (device current), the call
+tw_status noalloc_setup(int device, Error& err);
+int64_t noalloc_scratch_bytes();
+tw_status sample_walks_noalloc(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int64_t* ts,
+                               int32_t* len, Error& err);
 
 // One request of a serving launch: count walks of max_len nodes written to
 // rows of width max_len at nodes / ts, lengths at len (validated by the

@@ -4,6 +4,7 @@
 // same walks.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -1323,6 +1324,136 @@ tw_status sample_walks_batch(tw_graph* g, const tw_batch_params* p, int32_t* nod
     launch_fill(g, nodes, ts, slots);
     if (p->dispatch == TW_DISPATCH_FULL_WALK) return batch_full_walk(g, a, q, err);
     return queue_walks(g, a, q, g->auto_bpc, err);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free walks: the queue dispatch of plain walks (queue_hops_in)
+// with its per-call lists in one file-scope device array, for callers that
+// cannot allocate device memory.
+
+namespace {
+
+constexpr int64_t NA_MAX = TW_NOALLOC_MAX_WALKS;
+constexpr int64_t na_round(int64_t b) { return (b + 255) / 256 * 256; }
+// byte offsets of the lists of NA_MAX walks inside the array
+constexpr int64_t NA_NODE0 = 0;
+constexpr int64_t NA_WALK0 = NA_NODE0 + na_round(4 * NA_MAX);
+constexpr int64_t NA_T0 = NA_WALK0 + na_round(4 * NA_MAX);
+constexpr int64_t NA_NODE2 = NA_T0 + na_round(8 * NA_MAX);
+constexpr int64_t NA_WALK2 = NA_NODE2 + na_round(4 * NA_MAX);
+constexpr int64_t NA_T2 = NA_WALK2 + na_round(4 * NA_MAX);
+constexpr int64_t NA_PREV = NA_T2 + na_round(8 * NA_MAX);
+constexpr int64_t NA_FLAGS = NA_PREV + na_round(4 * NA_MAX);
+constexpr int64_t NA_POS = NA_FLAGS + na_round(4 * NA_MAX);
+constexpr int64_t NA_NLIVE = NA_POS + na_round(4 * NA_MAX);
+constexpr int64_t NA_COUNTERS = NA_NLIVE + 256;
+constexpr int64_t NA_PART = NA_COUNTERS + na_round(8 * QUEUE_SLICES);
+// the scan's partial sums: one word per 256 walks bounds scan_parts_u32
+// (tiles of at least 256 elements, plus one); checked at set-up
+constexpr int64_t NA_PART_WORDS = NA_MAX / 256 + 2;
+constexpr int64_t NA_BYTES = NA_PART + na_round(4 * NA_PART_WORDS);
+
+// The lists of every allocation-free call on a device. Host code never
+// passes this name to a kernel: it stands for the device array only in
+// device code and in hipGetSymbolAddress, whose result (per device) is
+// what the kernels receive.
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+constexpr int NA_DEVICES = 64;
+std::mutex na_mu;
+void* na_ptr[NA_DEVICES] = {};
+
+template <typename T>
+T* na_at(void* base, int64_t off) {
+    return reinterpret_cast<T*>(static_cast<unsigned char*>(base) + off);
+}
+
+}  // namespace
+
+// Once per device, with that device current: the device address of the
+// array (each device holds its own copy).
+tw_status noalloc_setup(int device, Error& err) {
+    if (device < 0 || device >= NA_DEVICES) {
+        err = Error{TW_EDEVICE, "allocation-free walks: device ordinal out of range"};
+        return err.code;
+    }
+    if (scan_parts_u32(NA_MAX) > NA_PART_WORDS) {
+        err = Error{TW_EDEVICE, "allocation-free walks: scan partials exceed their space"};
+        return err.code;
+    }
+    std::lock_guard<std::mutex> lk(na_mu);
+    if (na_ptr[device]) return TW_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        err = Error{TW_EDEVICE, std::string("allocation-free walks: hipGetSymbolAddress failed: ") +
+                                    hipGetErrorString(e)};
+        return err.code;
+    }
+    na_ptr[device] = p;
+    return TW_OK;
+}
+
+int64_t noalloc_scratch_bytes() { return NA_BYTES; }
+
+tw_status sample_walks_noalloc(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int64_t* ts,
+                               int32_t* len, Error& err) {
+    if (!p) {
+        err = Error{TW_EINVAL, "sample_walks_noalloc: null params"};
+        return err.code;
+    }
+    if (p->num_walks > NA_MAX) {
+        err = Error{TW_EINVAL, "sample_walks_noalloc: num_walks exceeds TW_NOALLOC_MAX_WALKS (" +
+                                   std::to_string(NA_MAX) + ")"};
+        return err.code;
+    }
+    if (p->direction != TW_FORWARD) {
+        err = Error{TW_EINVAL, "sample_walks_noalloc: forward walks only"};
+        return err.code;
+    }
+    if (p->hop_bias.kind == TW_WEIGHT) {
+        err = Error{TW_EINVAL, "sample_walks_noalloc: TW_WEIGHT needs its weights built (allocates)"};
+        return err.code;
+    }
+    // nothing may be built lazily: an index must exist, and node2vec needs
+    // the adjacency of the current window
+    if (!g->rec.p) {
+        err = Error{TW_EINVAL, "sample_walks_noalloc: the graph holds no index yet (ingest first)"};
+        return err.code;
+    }
+    if (p->hop_bias.kind == TW_NODE2VEC && g->m > 0 && !g->adj_ready) {
+        err = Error{TW_EINVAL,
+                    "sample_walks_noalloc: the node2vec adjacency of the current window is not "
+                    "built (one tw_sample_walks call with a node2vec bias builds it)"};
+        return err.code;
+    }
+    void* base = nullptr;
+    if (g->device >= 0 && g->device < NA_DEVICES) {
+        std::lock_guard<std::mutex> lk(na_mu);
+        base = na_ptr[g->device];
+    }
+    if (!base) {
+        err = Error{TW_EDEVICE, "sample_walks_noalloc: no device array for the graph's device"};
+        return err.code;
+    }
+    WalkArgs a;
+    if (prepare_plain(g, p, nodes, ts, len, a, err) != TW_OK) return err.code;
+    if (p->num_walks == 0) return TW_OK;
+    HopLists h;
+    h.live = Live{na_at<uint32_t>(base, NA_NODE0), na_at<uint32_t>(base, NA_WALK0),
+                  na_at<uint64_t>(base, NA_T0)};
+    h.next = Live{na_at<uint32_t>(base, NA_NODE2), na_at<uint32_t>(base, NA_WALK2),
+                  na_at<uint64_t>(base, NA_T2)};
+    h.prev = na_at<int32_t>(base, NA_PREV);
+    h.flags = na_at<uint32_t>(base, NA_FLAGS);
+    h.pos = na_at<uint32_t>(base, NA_POS);
+    h.n_live = na_at<uint32_t>(base, NA_NLIVE);
+    h.scan_part = na_at<uint32_t>(base, NA_PART);
+    h.counters = na_at<unsigned long long>(base, NA_COUNTERS);
+    // the queue dispatch pads the rows first, as tw_sample_walks does
+    launch_fill(g, a.nodes, a.ts, a.num_walks * (int64_t)a.L);
+    return queue_hops_in(g, a, g->auto_bpc, h, err);
 }
 
 tw_status check_walk_params(const tw_walk_params* p, Error& err) {
