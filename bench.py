@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="stream",
                     choices=["single", "tiny", "stream", "mixed", "serve"])
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="serve workload: seconds of real-time arrivals")
     ap.add_argument("--batches", type=int, default=0,
                     help="stream workload: number of 10M-edge batches (0 = the whole stream)")
@@ -216,13 +216,13 @@ def cpu_baseline(w, tau, gpu_hops_per_step):
 
 def stream_cpu_baseline(w, gpu_hops_per_batch, first_batches, steady):
     """The oracle on the stream: the first batches (the window filling) and
-    the steady-state batches in `steady` ({1-based batch: (window content
-    before it, the batch)}; the state before each is set up untimed by one
-    ingest of the window content: for a stream whose timestamps never
-    decrease the index is a function of the window content). Each batch is
-    timed for ingest + evict + the view rebuild (single-threaded, as the
-    oracle runs) and for walks on 1% of the walk ids, on one thread and on
-    every host core."""
+    the steady-state batches in `steady` ({1-based first batch: (window
+    content before it, [that batch and the ones after it])}; the state before
+    the first is set up untimed by one ingest of the window content: for a
+    stream whose timestamps never decrease the index is a function of the
+    window content). Each batch is timed for ingest + evict + the view
+    rebuild (single-threaded, as the oracle runs) and for walks on 1% of the
+    walk ids, on one thread and on every host core."""
     import oracle
     spec = w["stream"]
     B, W, L, window = w["batch_edges"], w["walks"], w["max_len"], w["window"]
@@ -253,10 +253,13 @@ def stream_cpu_baseline(w, gpu_hops_per_batch, first_batches, steady):
     for sb, (content, nxt) in sorted(steady.items()):
         og = oracle.OracleGraph(spec.num_nodes, directed=spec.directed, window=window)
         og.ingest_batch(*content)
-        rows[sb] = one(og, sb - 1, *nxt)
+        for k, batch in enumerate(nxt):
+            rows[sb + k] = one(og, sb + k - 1, *batch)
+            print(f"# oracle batch {sb + k}", file=sys.stderr, flush=True)
         del og
     first = len(first_batches)
-    ss = [rows[b] for b in steady]
+    steady_ids = sorted(b for b in rows if b > first)
+    ss = [rows[b] for b in steady_ids]
     t_ing = float(np.mean([r[0] for r in ss]))
     rate1 = float(np.mean([r[1] for r in ss]))
     rate_n = float(np.mean([r[2] for r in ss]))
@@ -270,7 +273,7 @@ def stream_cpu_baseline(w, gpu_hops_per_batch, first_batches, steady):
                                f"walk_hops_per_s_{threads}_threads": r[2]}
                       for b, r in sorted(rows.items())},
         "sample": (f"oracle on stream batches 1-{first} (window filling) and "
-                   f"{', '.join(map(str, sorted(steady)))} (window full; the state before each set up "
+                   f"{steady_ids[0]}-{steady_ids[-1]} (window full; the state before the first set up "
                    f"untimed by one ingest of the window content): ingest + evict + view "
                    f"rebuild single-threaded; walks on 1% of the walk ids ({len(idx)}), timed "
                    f"on 1 thread and on {threads}; value = the GPU's hops per steady-state "
@@ -292,6 +295,39 @@ def h2d_ms(torch, dev, batch):
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1))
     return float(np.median(times[1:]))
+
+
+COOP_SWEEP = [  # (regroup, wave_min, panel, sync) of the cooperative dispatch
+    (0, 64, 4096, 1), (0, 64, 4096, 4), (0, 16, 4096, 4), (0, 16, 8192, 4), (0, 1, 2048, 4),
+    (1, 64, 2048, 1), (1, 64, 2048, 4), (1, 64, 2048, 16)]
+
+
+def dispatch_sweep(torch, g, W, L, walk_kw, hops_ref):
+    """The walk launch under every queue shape and cooperative setting
+    (tw_set_tuning, then the AUTO dispatch): median of 3 timed runs after
+    one untimed; every setting must give the same walk lengths."""
+    out = walk_kw["out"]
+    saved = g.tuning()
+    rows = []
+    cands = [dict(dispatch="queue", queue_bpc=b) for b in (0, 4, 2)] + [
+        dict(dispatch="coop", coop_regroup=r, coop_wave_min=wm, coop_panel=p, coop_sync=sy)
+        for r, wm, p, sy in COOP_SWEEP]
+    for c in cands:
+        g.set_tuning(**c)
+        times = []
+        for rep in range(4):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            g.sample_walks(W, L, **dict(walk_kw, dispatch="auto"))
+            e1.record()
+            torch.cuda.synchronize()
+            if rep:
+                times.append(e0.elapsed_time(e1))
+        h = int((out[2].to(torch.int64) - 1).clamp_min(0).sum().item())
+        assert h == hops_ref, f"{c} walks differ in length"
+        rows.append(dict(c, walk_ms=float(np.median(times))))
+    g.set_tuning(**{k: v for k, v in saved.items()})
+    return rows
 
 
 WALK_KERNEL = "k_walk_full"
@@ -316,7 +352,8 @@ def run_stream(args, torch, tw, w, dev, gather_rate, copy_bw):
     # content before each steady-state batch it times (with that batch)
     want_cpu = not args.no_cpu_baseline
     first_n = min(5, total)
-    steady_at = [b for b in (96,) if b <= total] if total >= 96 else [total]
+    # steady state: batches 96-100 of the 100 (or the last ones of a shorter run)
+    steady_first = max(min(96, total - 4), first_n + 1)
     first_host, window_host, steady_host = [], [], {}
     for b, (s, d, t) in enumerate(spec.batches(B)):
         if b >= total:
@@ -328,10 +365,12 @@ def run_stream(args, torch, tw, w, dev, gather_rate, copy_bw):
         if want_cpu:
             if b < first_n:
                 first_host.append((s, d, t))
-            if b + 1 in steady_at and window_host:
+            if b + 1 == steady_first and window_host:
                 content = tuple(np.concatenate([x[i] for x in window_host]) for i in range(3))
                 lo = int(np.searchsorted(content[2], int(window_host[-1][2][-1]) - w["window"]))
-                steady_host[b + 1] = (tuple(x[lo:] for x in content), (s, d, t))
+                steady_host[b + 1] = (tuple(x[lo:] for x in content), [])
+            if steady_host and b + 1 >= steady_first:
+                steady_host[steady_first][1].append((s, d, t))
             window_host.append((s, d, t))
             cut = int(t[-1]) - w["window"]
             while window_host and int(window_host[0][2][-1]) < cut:
@@ -511,6 +550,34 @@ def run_mixed(args, torch, tw, w, dev, gather_rate):
         res_d[disp] = {"walk_ms": ms, "walk_hops_per_s": hops / (ms * 1e-3),
                        "ms_per_step": wall * 1e3 / args.steps}
     g.sync()
+    # plain exponential walks on this hub-heavy graph under each dispatch,
+    # then under the autotuner's choice (the dispatch plane's tunables)
+    Wp, Lp = 2_000_000, 40
+    pout = (out[0][:Wp * Lp].view(Wp, Lp), out[1][:Wp * Lp].view(Wp, Lp), out[2][:Wp])
+    pkw = dict(hop_bias="exponential", hop_tau=tau, start_bias="uniform", seed=42, out=pout)
+    plain = {}
+    phops = None
+    for disp in ("full_walk", "queue", "coop", "tuned"):
+        if disp == "tuned":
+            plain["tuning"] = g.autotune(Wp, Lp, sample=Wp, **{k: v for k, v in pkw.items()
+                                                                if k != "out"})
+            plain["tuning"] = g.tuning()
+        times = []
+        for rep in range(4):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            g.sample_walks(Wp, Lp, dispatch="auto" if disp == "tuned" else disp, **pkw)
+            e1.record()
+            torch.cuda.synchronize()
+            if rep:
+                times.append(e0.elapsed_time(e1))
+        h = int((pout[2].to(torch.int64) - 1).clamp_min(0).sum().item())
+        assert phops is None or h == phops, f"{disp} walks differ in length"
+        phops = h
+        ms = float(np.median(times))
+        plain[disp] = {"walk_ms": ms, "walk_hops_per_s": h / (ms * 1e-3)}
+    plain["walks"], plain["max_len"], plain["hops"] = Wp, Lp, phops
+    plain["sweep"] = dispatch_sweep(torch, g, Wp, Lp, pkw, phops)
     q = res_d["queue"]
     roof = gather_rate / 4 if gather_rate else None
     res = {
@@ -525,6 +592,7 @@ def run_mixed(args, torch, tw, w, dev, gather_rate):
         "dispatch": "queue",
         "hops_per_step": hops,
         "batched_vs_plain": res_d,
+        "plain_walks_by_dispatch": plain,
         "ingest_ms": ingest_ms,
         "ingest_edges_per_s": spec.num_edges * (1 if spec.directed else 2) / (ingest_ms * 1e-3),
         "gather_roofline": {"random_sectors_per_s": gather_rate, "sectors_per_hop": 4,
@@ -535,41 +603,20 @@ def run_mixed(args, torch, tw, w, dev, gather_rate):
     print(json.dumps(res), flush=True)
 
 
-def run_serve(args, torch, tw, w, dev, gather_rate):
-    """Serving loop in real time: the stream's first 40 s of edges are
-    ingested up front; then, for --serve-seconds of wall time, 5M edges/s
-    arrive in 100 ms batches and walk requests arrive Poisson at 2k/s (walk
-    count log-uniform in [1e2, 1e5], length 10, 40 or 80, a random hop bias),
-    all through one tw_server. Reports sustained hops/s and request latency."""
+def serve_phase(torch, tw, srv, batches, rate_req, seconds, tau, seed):
+    """One real-time serving phase through `srv`: `batches` (resident, one
+    per 100 ms) are ingested on schedule while walk requests arrive Poisson at
+    rate_req per second (walk count log-uniform in [1e2, 1e5], length 10, 40
+    or 80, a random hop bias). Returns the phase's counts and latencies."""
     import threading
-    import synth
-    spec = w["stream"]
-    rate = w["edges_per_s"]
-    warm_edges = int(40 * rate)
-    live_s = args.serve_seconds
-    step = int(rate * 0.1)
-    nb = int(live_s / 0.1)
-    gen = spec.batches(step)
-    warm = [next(gen) for _ in range(warm_edges // step)]
-    s0, d0, t0_ = (np.concatenate([b[k] for b in warm]) for k in range(3))
-    del warm
-    g = tw.Graph(spec.num_nodes, directed=spec.directed, window=w["window"])
-    info = g.ingest_batch(*(torch.from_numpy(a).to(dev) for a in (s0, d0, t0_)))
-    del s0, d0, t0_
-    tau = 0.1 * float(w["window"])
-    live = [tuple(torch.from_numpy(a).to(dev) for a in next(gen)) for _ in range(nb)]
-    torch.cuda.synchronize()
-    print(f"# warm window {info['active_edges']} edges; {nb} live batches of {step}",
-          file=sys.stderr, flush=True)
-    rng = np.random.default_rng(7)
-    n_req = rng.poisson(w["requests_per_s"] * live_s)
-    arrivals = np.sort(rng.uniform(0.0, live_s, n_req))
+    rng = np.random.default_rng(seed)
+    n_req = rng.poisson(rate_req * seconds)
+    arrivals = np.sort(rng.uniform(0.0, seconds, n_req))
     counts = np.exp(rng.uniform(np.log(1e2), np.log(1e5), n_req)).astype(np.int64)
     lens = rng.choice([10, 40, 80], n_req)
     kinds = rng.choice(["uniform", "linear", "exponential", "node2vec"], n_req)
-    srv = tw.Server(g, arena_bytes=w["arena_bytes"], max_walks_per_launch=1 << 20,
-                    max_inflight=2)
-    done_lat = []
+    before = srv.stats()
+    lat, ing_lat = [], []
     submitted = []
     cond = threading.Condition()
     finished = [False]
@@ -585,25 +632,26 @@ def run_serve(args, torch, tw, w, dev, gather_rate):
                 rid, is_req = submitted[k]
             r = srv.wait(rid)
             if is_req:
-                done_lat.append(r["latency_ms"])
+                lat.append(r["latency_ms"])
                 srv.release(rid)
+            else:
+                ing_lat.append(r["latency_ms"])
             k += 1
 
     th = threading.Thread(target=reaper)
     th.start()
-    events = sorted([(i * 0.1, 0, i) for i in range(len(live))] +
+    events = sorted([(i * 0.1, 0, i) for i in range(len(batches))] +
                     [(float(a), 1, i) for i, a in enumerate(arrivals)])
-    offered_walks = int(counts.sum())
     t_start = time.perf_counter()
     for when, kind, i in events:
         now = time.perf_counter() - t_start
         if when > now:
             time.sleep(when - now)
         if kind == 0:
-            rid = srv.ingest(*live[i])
+            rid = srv.ingest(*batches[i])
         else:
             rid = srv.submit(int(counts[i]), int(lens[i]), hop_bias=str(kinds[i]), hop_tau=tau,
-                             p=0.5, q=2.0, seed=int(i), walk_id_base=0)
+                             p=0.5, q=2.0, seed=int(seed * 1_000_003 + i), walk_id_base=0)
         with cond:
             submitted.append((rid, kind == 1))
             cond.notify()
@@ -613,21 +661,96 @@ def run_serve(args, torch, tw, w, dev, gather_rate):
     th.join()
     wall = time.perf_counter() - t_start
     st = srv.stats()
-    srv.close()
-    lat = np.array(done_lat)
-    hops_s = st["hops_done"] / wall
+    lat = np.array(lat)
+    hops = st["hops_done"] - before["hops_done"]
+    return {"requests_per_s": rate_req, "seconds": seconds, "requests": int(n_req),
+            "offered_walks": int(counts.sum()), "walks": int(st["walks_done"] - before["walks_done"]),
+            "hops": int(hops), "wall_s": wall, "hops_per_s": hops / wall,
+            "launches": int(st["launches"] - before["launches"]),
+            "ingests": len(ing_lat), "ingested_edges": int(sum(b[0].numel() for b in batches)),
+            "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+            "max_ms": float(lat.max()) if len(lat) else None,
+            "ingest_p50_ms": float(np.percentile(ing_lat, 50)) if ing_lat else None,
+            "ingest_p99_ms": float(np.percentile(ing_lat, 99)) if ing_lat else None}
 
-    # saturation: a burst of requests submitted at once through a server,
-    # against the same requests as one tw_sample_walks call each
+
+def run_serve(args, torch, tw, w, dev, gather_rate):
+    """Serving loop in real time on the 300M-edge stream (5M edges/s, 10M
+    nodes, Zipf 1.2, 60 s window): the first 40 s of edges are ingested up
+    front; then, for --serve-seconds of wall time (20: the rest of the 300M
+    edges), 5M edges/s arrive in 100 ms batches and walk requests arrive
+    Poisson at 2k/s, all through one tw_server, whose ingest thread plans each
+    batch while the walks before it run. Reports sustained hops/s and request
+    latency; then a saturation sweep (the stream continues, requests at 2x to
+    16x the rate for 3 s each) and a burst of 2,000 requests served against
+    the same requests as one tw_sample_walks call each."""
+    spec = w["stream"]
+    rate = w["edges_per_s"]
+    warm_edges = int(40 * rate)
+    live_s = args.serve_seconds
+    step = int(rate * 0.1)
+    sweep = [2, 4, 8, 16]
+    sweep_s = 3.0
+    nb = int(round(live_s / 0.1))
+    nsweep = int(round(sweep_s / 0.1))
+    # the sweep continues the stream past its 300M edges (every element is a
+    # function of its index, so the first 300M are the workload's)
+    import dataclasses
+    gen = dataclasses.replace(spec, num_edges=spec.num_edges + len(sweep) * nsweep * step
+                              ).batches(step)
+    warm = [next(gen) for _ in range(warm_edges // step)]
+    s0, d0, t0_ = (np.concatenate([b[k] for b in warm]) for k in range(3))
+    del warm
+    g = tw.Graph(spec.num_nodes, directed=spec.directed, window=w["window"])
+    info = g.ingest_batch(*(torch.from_numpy(a).to(dev) for a in (s0, d0, t0_)))
+    del s0, d0, t0_
+
+    def resident(k):
+        out = []
+        for _ in range(k):
+            try:
+                out.append(tuple(torch.from_numpy(a).to(dev) for a in next(gen)))
+            except StopIteration:
+                break
+        return out
+
+    tau = 0.1 * float(w["window"])
+    live = resident(nb)
+    torch.cuda.synchronize()
+    print(f"# warm window {info['active_edges']} edges; {len(live)} live batches of {step}",
+          file=sys.stderr, flush=True)
+    srv = tw.Server(g, arena_bytes=w["arena_bytes"], max_walks_per_launch=1 << 20,
+                    max_inflight=2)
+    main = serve_phase(torch, tw, srv, live, w["requests_per_s"], live_s, tau, seed=7)
+    del live
+    print(f"# served {main['requests']} requests: p50 {main['p50_ms']:.2f} ms, "
+          f"p99 {main['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+    sat = []
+    for k, mult in enumerate(sweep):
+        more = resident(nsweep)
+        torch.cuda.synchronize()
+        r = serve_phase(torch, tw, srv, more, w["requests_per_s"] * mult, sweep_s, tau,
+                        seed=100 + k)
+        del more
+        sat.append(r)
+        print(f"# {r['requests_per_s']} requests/s: {r['hops_per_s'] / 1e9:.2f} G hops/s, "
+              f"p50 {r['p50_ms']:.2f} ms, p99 {r['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+    srv.close()
+
+    # a burst of requests submitted at once through a server, against the
+    # same requests as one tw_sample_walks call each
+    rng = np.random.default_rng(11)
     nburst = 2000
-    bidx = np.arange(nburst) % max(n_req, 1)
+    counts = np.exp(rng.uniform(np.log(1e2), np.log(1e5), nburst)).astype(np.int64)
+    lens = rng.choice([10, 40, 80], nburst)
+    kinds = rng.choice(["uniform", "linear", "exponential", "node2vec"], nburst)
     burst = [dict(num_walks=int(counts[i]), max_len=int(lens[i]), hop_bias=str(kinds[i]),
-                  hop_tau=tau, p=0.5, q=2.0, seed=int(i), walk_id_base=0) for i in bidx]
+                  hop_tau=tau, p=0.5, q=2.0, seed=int(i), walk_id_base=0) for i in range(nburst)]
     srv = tw.Server(g, arena_bytes=w["arena_bytes"], max_walks_per_launch=1 << 20,
                     max_inflight=2)
     t0 = time.perf_counter()
     ids = [srv.submit(**r) for r in burst]
-    bhops = 0
     for rid in ids:
         srv.wait(rid)
         srv.release(rid)
@@ -655,28 +778,31 @@ def run_serve(args, torch, tw, w, dev, gather_rate):
     g.sync()
     t_plain = time.perf_counter() - t0
     plain_hops = int((lens_all - 1).clamp_min(0).sum(dtype=torch.int64).item())
+    active = g.stats()["active_edges"]
     g.close()
     assert plain_hops == bst["hops_done"], "served and plain walks differ"
+    # saturation: the highest offered rate whose hops/s still follows the
+    # offered load (within 10%) with p99 under 100 ms
+    ok = [r for r in [main] + sat
+          if r["p99_ms"] is not None and r["p99_ms"] < 100.0 and r["walks"] >= 0.9 * r["offered_walks"]]
     res = {
-        "metric": METRIC, "value": hops_s, "unit": "hops/s", "n_gpus": 1,
-        "steps": int(st["launches"]), "warmup": 0, "ms_per_step": wall * 1e3 / max(st["launches"], 1),
+        "metric": METRIC, "value": main["hops_per_s"], "unit": "hops/s", "n_gpus": 1,
+        "steps": int(main["launches"]), "warmup": 0,
+        "ms_per_step": main["wall_s"] * 1e3 / max(main["launches"], 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int64+f64", "data": "synthetic",
         "config": {"workload": "serve", "nodes": spec.num_nodes, "src_zipf": spec.src_s,
-                   "window_ns": w["window"], "edges_per_s": rate, "warm_edges": warm_edges,
+                   "stream_edges": spec.num_edges, "window_ns": w["window"],
+                   "edges_per_s": rate, "warm_edges": warm_edges,
                    "requests_per_s": w["requests_per_s"], "walks_per_request": "log-uniform 1e2..1e5",
                    "max_len": [10, 40, 80], "hop_biases": ["uniform", "linear", "exponential",
                                                            "node2vec(0.5,2)"],
                    "seconds": live_s},
-        "serving": {"requests": int(st["requests_done"]), "walks": int(st["walks_done"]),
-                    "offered_walks": offered_walks, "hops": int(st["hops_done"]),
-                    "launches": int(st["launches"]), "ingests": int(st["ingests"]),
-                    "ingested_edges": int(len(live) * step), "wall_s": wall,
-                    "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
-                    "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
-                    "max_ms": float(lat.max()) if len(lat) else None,
-                    "server_p50_ms": st["p50_ms"], "server_p99_ms": st["p99_ms"],
-                    "active_edges_at_start": info["active_edges"]},
+        "serving": main | {"active_edges_at_start": info["active_edges"],
+                           "active_edges_at_end": active},
+        "saturation": {"phases": sat,
+                       "highest_rate_served": max(r["requests_per_s"] for r in ok) if ok else None,
+                       "rule": "hops/s within 10% of the offered walks and p99 < 100 ms"},
         "batched_vs_plain": {
             "requests": nburst, "walks": int(bst["walks_done"]), "hops": plain_hops,
             "served": {"seconds": t_served, "hops_per_s": plain_hops / t_served,
@@ -684,7 +810,7 @@ def run_serve(args, torch, tw, w, dev, gather_rate):
             "plain_per_request": {"seconds": t_plain, "hops_per_s": plain_hops / t_plain,
                                   "launches": nburst}},
         "gather_roofline": {"random_sectors_per_s": gather_rate, "sectors_per_hop": 4,
-                            "frac": hops_s / (gather_rate / 4) if gather_rate else None},
+                            "frac": main["hops_per_s"] / (gather_rate / 4) if gather_rate else None},
     }
     print(json.dumps(res), flush=True)
 
@@ -752,9 +878,9 @@ def run_single(args, torch, tw, w, dev, gather_rate, copy_bw):
     m_active = g.view_sizes()["m"]
 
     # walk phase alone under each dispatch (index built once): plain full-walk
-    # against the cooperative per-step regrouping
+    # against the work queue and the cooperative per-step regrouping
     compare = {}
-    for disp in ("full_walk", "coop") if args.direction == "forward" else ("full_walk",):
+    for disp in ("full_walk", "queue", "coop") if args.direction == "forward" else ("full_walk",):
         kw = dict(walk_kw, dispatch=disp)
         times = []
         for rep in range(4):
@@ -769,6 +895,8 @@ def run_single(args, torch, tw, w, dev, gather_rate, copy_bw):
         ms = float(np.median(times))
         compare[disp] = {"walk_ms": ms, "walk_hops_per_s": hops / (ms * 1e-3)}
 
+    sweep = (dispatch_sweep(torch, g, W, L, walk_kw, hops)
+             if args.direction == "forward" and w["hop_bias"] != "weight" else None)
     weight_build_ms = None
     if w["hop_bias"] == "weight":
         # the build alone: the first walk call after an ingest builds the
@@ -810,6 +938,7 @@ def run_single(args, torch, tw, w, dev, gather_rate, copy_bw):
         "dispatch": args.dispatch,
         "hops_per_step": hops,
         "plain_vs_tuned": compare,
+        "dispatch_sweep": sweep,
         "walk_ms": walk_ms,
         "ingest_ms": ingest_ms,
         "walk_hops_per_s": walk_hops_s,
@@ -870,8 +999,8 @@ def main():
             r = run_single(one, torch, tw, synth.workload("single"), dev, gather_rate, copy_bw)
             res["single_batch"] = {k: r[k] for k in (
                 "config", "ms_per_step", "value", "hops_per_step", "walk_ms", "ingest_ms",
-                "walk_hops_per_s", "ingest_edges_per_s", "plain_vs_tuned", "roofline",
-                "gather_roofline")}
+                "walk_hops_per_s", "ingest_edges_per_s", "plain_vs_tuned", "dispatch_sweep",
+                "roofline", "gather_roofline")}
         print(json.dumps(res), flush=True)
         return
     print(json.dumps(run_single(args, torch, tw, w, dev, gather_rate, copy_bw)), flush=True)

@@ -201,9 +201,21 @@ tw_status tw_set_stream(tw_graph* g, void* hip_stream);
  * view in place, and the node-and-timestamp view for the nodes the batch or
  * the eviction touches.
  * d_src, d_dst: int32[n]; d_ts: int64[n]; device memory, any alignment.
- * info (nullable) receives the counts. The call synchronises the stream.
+ * info (nullable) receives the counts. The call synchronises the stream
+ * (it sizes its launches from counts it reads back); the first read-back
+ * also brings the error flags of earlier walks: a pending one is reported
+ * (TW_ERANGE, TW_EINVAL, see tw_sample_walks) and cleared, and the batch is
+ * not ingested.
  * Returns TW_ERANGE, with the graph unchanged, if any id is outside
- * [0, num_nodes); TW_ENOMEM, graph unchanged, if the device is full.
+ * [0, num_nodes). The batch is staged, validated, sorted and its node-view
+ * jobs collected before the index changes: TW_ENOMEM (device full) in that
+ * part leaves the graph unchanged. A failure while the index is being
+ * updated (device full while a pool or buffer grows, a HIP error) leaves it
+ * partly updated: the call returns TW_ENOMEM or TW_EDEVICE and every later
+ * call that reads or changes the index returns TW_EDEVICE (destroy the
+ * graph). A backward in-view
+ * (tw_direction) that fails to take the batch is dropped and rebuilt from
+ * the window by the next backward walk.
  */
 tw_status tw_ingest_batch(tw_graph* g, const int32_t* d_src, const int32_t* d_dst,
                           const int64_t* d_ts, int64_t n, tw_ingest_info* info);
@@ -212,9 +224,24 @@ tw_status tw_ingest_batch(tw_graph* g, const int32_t* d_src, const int32_t* d_ds
  * Remove every window record with timestamp < t_cutoff from both views and
  * rebuild the offsets (Sec. "Dual-Index Organization": eviction is a prefix
  * of the timestamp view). Idempotent. Does not move t_now.
- * n_evicted (nullable) receives the count. Synchronises the stream.
+ * n_evicted (nullable) receives the count. With nothing to evict (an empty
+ * window, or t_cutoff <= its first timestamp) the call returns at once: no
+ * device work, no synchronisation. Otherwise it synchronises the stream and
+ * first reports a pending device-side error of earlier walks.
  */
 tw_status tw_evict_before(tw_graph* g, int64_t t_cutoff, int64_t* n_evicted);
+
+/*
+ * Build the TW_WEIGHT picker's cumulative weights for time scale tau at
+ * every later ingest and eviction (the weight stage of the paper's ingest,
+ * Table 4), so the first weight-based walk after an update does not build
+ * them; tau NaN: stop (the first weight-based walk after an update builds
+ * them, the default). The weights also serve walks at another tau only after
+ * a rebuild, which such a walk makes itself. A build that fails at ingest
+ * leaves the weights to the next weight-based walk. Host-side setting, no
+ * synchronisation. Returns TW_EINVAL for a null graph or an infinite tau.
+ */
+tw_status tw_set_ingest_weights(tw_graph* g, double tau);
 
 /*
  * Sample params->num_walks walks (Sec. "Temporal Bias Sampling", "Hierarchical
@@ -269,13 +296,44 @@ tw_status tw_row_offsets(tw_graph* g, const int32_t* d_max_len, int64_t n, int64
                          int64_t* total);
 
 /*
- * Time the dispatches of tw_sample_walks (full-walk, cooperative, queue with
- * several launch shapes) on the current window for these parameters, with
- * num_walks cut to at most sample_walks, and keep the fastest as the
- * graph's TW_DISPATCH_AUTO choice. d_nodes / d_ts / d_len: scratch of the
- * sizes tw_sample_walks needs for the timed walk count. best (nullable)
- * receives the chosen tw_dispatch and, for the queue, its workgroups per
- * compute unit in best[1]. Synchronises.
+ * How TW_DISPATCH_AUTO and the cooperative dispatch run (Sec.
+ * "Hierarchical Cooperative Scheduling", Sec. "Parameter Tuning"):
+ *  dispatch:      what TW_DISPATCH_AUTO runs (FULL_WALK, COOP or QUEUE)
+ *  queue_bpc:     queue workgroups per compute unit (0: as many as fit)
+ *  coop_regroup:  per step, 0 = stable sort of the live walks by node, 1 = none
+ *                 (in-order compaction only)
+ *  coop_wave_min: lanes of a wavefront at its first lane's node that make it
+ *                 read the node record once and stage the top of the node's
+ *                 fence in LDS (the wavefront tier, 1..64); a workgroup whose
+ *                 four wavefronts do so for one node stages a panel of
+ *                 coop_panel words (the workgroup tier)
+ *  coop_panel:    LDS fence words of a workgroup (64..8192, multiple of 64)
+ *  coop_sync:     steps between read-backs of the live count (1..64); launches
+ *                 in between cover the last count read
+ * Defaults: FULL_WALK, 0, 0, 64, 4096, 1. The result of a walk never depends
+ * on them.
+ */
+typedef struct {
+    int32_t dispatch, queue_bpc, coop_regroup, coop_wave_min, coop_panel, coop_sync;
+} tw_tuning;
+
+/* Read the graph's tuning. Host-side. TW_EINVAL for null arguments. */
+tw_status tw_get_tuning(const tw_graph* g, tw_tuning* out);
+
+/* Set it (AUTO is not a valid dispatch here). TW_EINVAL for values outside
+ * the ranges above. Host-side. */
+tw_status tw_set_tuning(tw_graph* g, const tw_tuning* t);
+
+/*
+ * Time the dispatches of tw_sample_walks on the current window for these
+ * parameters, with num_walks cut to at most sample_walks: full-walk, the
+ * queue at 3 launch shapes, and the cooperative dispatch over its tunables
+ * (sorted regroup: wave_min 64 or 16, panel 2048 or 8192 words, read-back
+ * every step or every 4; no regroup, read-back every step or every 4), and
+ * keep the fastest as the graph's tuning (tw_get_tuning reads it).
+ * d_nodes / d_ts / d_len: scratch of the sizes tw_sample_walks needs for the
+ * timed walk count. best (nullable) receives the chosen tw_dispatch and, for
+ * the queue, its workgroups per compute unit in best[1]. Synchronises.
  */
 tw_status tw_autotune(tw_graph* g, const tw_walk_params* params, int64_t sample_walks,
                       int32_t* d_nodes, int64_t* d_ts, int32_t* d_len, int32_t best[2]);
@@ -316,23 +374,35 @@ tw_status tw_sample_walks_noalloc(tw_graph* g, const tw_walk_params* params, int
  * Serving: continuous batching of walk requests interleaved with ingestion.
  *
  * A server owns a graph (the caller must not use the graph directly while
- * the server exists) and a worker thread. Requests (tw_walk_params, dispatch
- * ignored) and ingest batches are queued in submission order. The worker
- * applies ingest batches in that order, and packs consecutive requests into
- * one work-queue launch (up to max_walks_per_launch walks, 1024 requests)
- * as soon as their outputs fit in the output arena, without waiting for the
- * launch before it (up to max_inflight launches enqueued). Every request
+ * the server exists), a worker thread and an ingest thread with a stream of
+ * its own. Requests (tw_walk_params, dispatch ignored) and ingest batches
+ * are queued in submission order. The worker packs consecutive requests
+ * into one work-queue launch on the graph's stream (up to
+ * max_walks_per_launch walks, 1024 requests) as soon as their outputs are
+ * placed, without waiting for the launch before it (up to max_inflight
+ * launches enqueued). A batch that reaches the front is planned (staged,
+ * validated, sorted, its node-view jobs collected) on the ingest stream
+ * while the launches before it still run, and the index is changed after
+ * they finish; the launches after it wait for that update. Every request
  * sees exactly the ingest batches submitted before it (its index epoch), and
  * its walks are the ones tw_sample_walks gives on that window with the same
  * parameters: requests sharing a launch do not change each other's result.
+ * Outputs are placed in the output arena; when a request fits none of its
+ * chunks, a chunk is added while the device keeps hbm_reserve_bytes free
+ * (admission by free device memory), else the request waits for releases.
  * Functions may be called from any host thread.
  */
 typedef struct tw_server tw_server;
 
 typedef struct {
-    int64_t arena_bytes;          /* device memory for request outputs, allocated at create */
+    int64_t arena_bytes;          /* device memory for request outputs, allocated at create;
+                                     also the least size of a chunk added later */
     int64_t max_walks_per_launch; /* walks of one launch (a larger request runs alone) */
     int32_t max_inflight;         /* launches enqueued at once, 1..8 */
+    int64_t hbm_reserve_bytes;    /* admission by free device memory: when a request's
+                                     outputs fit no arena chunk, a chunk is added if
+                                     hipMemGetInfo shows this much free after it (room
+                                     for the index to grow); < 0: the arena stays fixed */
 } tw_server_config;
 
 typedef struct {
@@ -352,6 +422,8 @@ typedef struct {
     int64_t requests_done, walks_done, hops_done, launches, ingests;
     double p50_ms, p99_ms, max_ms, mean_ms; /* request latency, submission to completion */
     double wall_s;        /* seconds since create */
+    int64_t arena_bytes;  /* output memory held now (every chunk) */
+    int64_t arena_chunks_added; /* chunks added after create (admission by free memory) */
 } tw_server_counters;
 
 /* Start a server on g. Allocates the arena and the launch tables (TW_ENOMEM
@@ -360,11 +432,14 @@ tw_status tw_server_create(tw_graph* g, const tw_server_config* cfg, tw_server**
 
 /* Queue a walk request; *id names it. d_start_nodes (NODE mode) must stay
  * valid until the request finishes. Returns TW_EINVAL for bad parameters or
- * a request whose outputs can never fit in the arena. */
+ * a request whose outputs can never fit in a fixed arena
+ * (hbm_reserve_bytes < 0). */
 tw_status tw_server_submit(tw_server* s, const tw_walk_params* req, uint64_t* id);
 
-/* Queue an ingest batch (as tw_ingest_batch); the arrays must stay valid
- * until it finishes. *id names it. */
+/* Queue an ingest batch (as tw_ingest_batch). The arrays must already hold
+ * the batch on the device when it is submitted (the ingest stream reads them
+ * without ordering against the caller's streams) and stay valid until it
+ * finishes. *id names it. */
 tw_status tw_server_ingest(tw_server* s, const int32_t* d_src, const int32_t* d_dst,
                            const int64_t* d_ts, int64_t n, uint64_t* id);
 

@@ -66,9 +66,14 @@ class _Info(_c.Structure):
                                           "active_edges", "t_min", "t_max")]
 
 
+class _Tuning(_c.Structure):
+    _fields_ = [(k, _c.c_int32) for k in ("dispatch", "queue_bpc", "coop_regroup",
+                                          "coop_wave_min", "coop_panel", "coop_sync")]
+
+
 class _ServerConfig(_c.Structure):
     _fields_ = [("arena_bytes", _c.c_int64), ("max_walks_per_launch", _c.c_int64),
-                ("max_inflight", _c.c_int32)]
+                ("max_inflight", _c.c_int32), ("hbm_reserve_bytes", _c.c_int64)]
 
 
 class _RequestResult(_c.Structure):
@@ -81,7 +86,8 @@ class _RequestResult(_c.Structure):
 class _ServerCounters(_c.Structure):
     _fields_ = [(k, _c.c_int64) for k in ("requests_done", "walks_done", "hops_done",
                                           "launches", "ingests")] + \
-               [(k, _c.c_double) for k in ("p50_ms", "p99_ms", "max_ms", "mean_ms", "wall_s")]
+               [(k, _c.c_double) for k in ("p50_ms", "p99_ms", "max_ms", "mean_ms", "wall_s")] + \
+               [(k, _c.c_int64) for k in ("arena_bytes", "arena_chunks_added")]
 
 
 _lib = None
@@ -104,6 +110,9 @@ def lib():
         "tw_evict_before": ([P, I64, _c.POINTER(I64)], _c.c_int),
         "tw_sample_walks": ([P, _c.POINTER(_WalkParams), P, P, P], _c.c_int),
         "tw_sample_walks_noalloc": ([P, _c.POINTER(_WalkParams), P, P, P], _c.c_int),
+        "tw_set_ingest_weights": ([P, _c.c_double], _c.c_int),
+        "tw_get_tuning": ([P, _c.POINTER(_Tuning)], _c.c_int),
+        "tw_set_tuning": ([P, _c.POINTER(_Tuning)], _c.c_int),
         "tw_sync": ([P], _c.c_int),
         "tw_stats": ([P, _c.POINTER(_Info)], _c.c_int),
         "tw_view_sizes": ([P, _c.POINTER(I64)], _c.c_int),
@@ -195,6 +204,12 @@ class Graph:
         _check(self._lib.tw_ingest_batch(self._h, _ptr(src), _ptr(dst), _ptr(ts), n,
                                          _c.byref(info)))
         return _info(info)
+
+    def set_ingest_weights(self, tau: Optional[float]):
+        """Build the weight-based picker's weights at every ingest and
+        eviction for this tau (None: on the first weight-based walk)."""
+        _check(self._lib.tw_set_ingest_weights(self._h, float("nan") if tau is None
+                                               else float(tau)))
 
     def evict_before(self, cutoff: int) -> int:
         n = _c.c_int64(0)
@@ -327,6 +342,20 @@ class Graph:
                                      _ptr(lens), best))
         return {"dispatch": DISPATCH_NAMES[int(best[0])], "blocks_per_cu": int(best[1])}
 
+    def tuning(self) -> dict:
+        """The dispatch tuning (tw_tuning); dispatch as a name."""
+        t = _Tuning()
+        _check(self._lib.tw_get_tuning(self._h, _c.byref(t)))
+        d = {k: getattr(t, k) for k, _ in _Tuning._fields_}
+        d["dispatch"] = DISPATCH_NAMES[d["dispatch"]]
+        return d
+
+    def set_tuning(self, dispatch: str = "full_walk", queue_bpc: int = 0, coop_regroup: int = 0,
+                   coop_wave_min: int = 64, coop_panel: int = 4096, coop_sync: int = 1):
+        t = _Tuning(DISPATCH[dispatch], int(queue_bpc), int(coop_regroup), int(coop_wave_min),
+                    int(coop_panel), int(coop_sync))
+        _check(self._lib.tw_set_tuning(self._h, _c.byref(t)))
+
     def sync(self):
         _check(self._lib.tw_sync(self._h))
 
@@ -379,11 +408,15 @@ class Server:
     exists."""
 
     def __init__(self, graph: Graph, arena_bytes: int = 1 << 30,
-                 max_walks_per_launch: int = 1 << 21, max_inflight: int = 2):
+                 max_walks_per_launch: int = 1 << 21, max_inflight: int = 2,
+                 hbm_reserve_bytes: int = 8 << 30):
+        """hbm_reserve_bytes < 0: a fixed arena; else more arena chunks are
+        added while the device keeps that much memory free."""
         self._lib = lib()
         self.graph = graph
         self.device = graph.device
-        cfg = _ServerConfig(int(arena_bytes), int(max_walks_per_launch), int(max_inflight))
+        cfg = _ServerConfig(int(arena_bytes), int(max_walks_per_launch), int(max_inflight),
+                            int(hbm_reserve_bytes))
         h = _c.c_void_p()
         _check(self._lib.tw_server_create(graph._h, _c.byref(cfg), _c.byref(h)))
         self._h = h

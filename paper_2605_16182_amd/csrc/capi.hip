@@ -119,10 +119,12 @@ tw_status tw_ingest_batch(tw_graph* g, const int32_t* d_src, const int32_t* d_ds
         return fail(TW_EINVAL, "tw_ingest_batch: need n >= 0 and non-null arrays");
     return guarded("tw_ingest_batch", [&]() -> tw_status {
         tw_status st = refuse_broken(g, "tw_ingest_batch");
-        if (st == TW_OK) st = check_device_flags(g);
+        // the graph's own flags come back with the batch's first read-back;
+        // the in-view's (backward walks) are read here
+        if (st == TW_OK && g->rev) st = check_flags_of(g->rev);
         if (st != TW_OK) return st;
         tw::Error e{TW_OK, ""};
-        return report(tw::ingest_views(g, d_src, d_dst, d_ts, n, info, e), e);
+        return report(tw::ingest_views(g, d_src, d_dst, d_ts, n, info, e, nullptr, true), e);
     });
 }
 
@@ -130,11 +132,39 @@ tw_status tw_evict_before(tw_graph* g, int64_t t_cutoff, int64_t* n_evicted) {
     if (!g) return fail(TW_EINVAL, "tw_evict_before: null graph");
     return guarded("tw_evict_before", [&]() -> tw_status {
         tw_status st = refuse_broken(g, "tw_evict_before");
-        if (st == TW_OK) st = check_device_flags(g);
+        if (st != TW_OK) return st;
+        // nothing to evict: no device work and no synchronisation
+        if (g->m == 0 || t_cutoff <= g->t_min) {
+            g->last.accepted = 0;
+            g->last.dropped_late = 0;
+            g->last.evicted = 0;
+            if (n_evicted) *n_evicted = 0;
+            return TW_OK;
+        }
+        st = check_device_flags(g);
         if (st != TW_OK) return st;
         tw::Error e{TW_OK, ""};
         return report(tw::evict_views(g, t_cutoff, n_evicted, e), e);
     });
+}
+
+tw_status tw_set_ingest_weights(tw_graph* g, double tau) {
+    if (!g) return fail(TW_EINVAL, "tw_set_ingest_weights: null graph");
+    if (std::isinf(tau)) return fail(TW_EINVAL, "tw_set_ingest_weights: tau must be finite or NaN");
+    g->ingest_weight_tau = tau;
+    return TW_OK;
+}
+
+tw_status tw_get_tuning(const tw_graph* g, tw_tuning* out) {
+    if (!g || !out) return fail(TW_EINVAL, "tw_get_tuning: null argument");
+    *out = tw::get_tuning(g);
+    return TW_OK;
+}
+
+tw_status tw_set_tuning(tw_graph* g, const tw_tuning* t) {
+    if (!g) return fail(TW_EINVAL, "tw_set_tuning: null graph");
+    tw::Error e{TW_OK, ""};
+    return report(tw::set_tuning(g, t, e), e);
 }
 
 tw_status tw_sample_walks(tw_graph* g, const tw_walk_params* params, int32_t* d_nodes,

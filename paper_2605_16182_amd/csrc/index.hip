@@ -439,7 +439,7 @@ tw_status finish_ts(tw_graph* g, bool gg_full, int64_t gg_old, int64_t gg_evicte
 }  // namespace
 
 tw_status ingest_prepare(tw_graph* g, const int32_t* src, const int32_t* dst, const int64_t* ts,
-                         int64_t n, IngestPlan& P, Error& err) {
+                         int64_t n, IngestPlan& P, Error& err, bool walk_flags) {
     hipStream_t s = g->stream;
     if (ensure_common(g, err) != TW_OK) return err.code;
     if (!g->rec.p && init_empty(g, err) != TW_OK) return err.code;
@@ -511,6 +511,19 @@ tw_status ingest_prepare(tw_graph* g, const int32_t* src, const int32_t* dst, co
     const uint64_t hmm[2] = {(uint64_t)host_i64(g, SLOT_I64_MINMAX),
                              (uint64_t)host_i64(g, SLOT_I64_MINMAX + 1)};
     const uint32_t herr = host_flags(g)[1], hunsorted = host_u32(g, SLOT_U32_UNSORTED);
+    if (walk_flags && (host_flags(g)[0] || host_flags(g)[3])) {
+        // errors of earlier walks, read back with this batch's counts: they
+        // are reported (and cleared) instead of ingesting
+        const bool range = host_flags(g)[0] != 0;
+        uint32_t* d = g->err.as<uint32_t>();
+        TW_HIP(hipMemsetAsync(d, 0, sizeof(uint32_t), s));
+        TW_HIP(hipMemsetAsync(d + 3, 0, sizeof(uint32_t), s));
+        TW_HIP(hipStreamSynchronize(s));
+        err = range ? Error{TW_ERANGE, "a walk start node was outside [0, num_nodes)"}
+                    : Error{TW_EINVAL,
+                            "a batched walk had a length limit, bias index or row out of range"};
+        return err.code;
+    }
     if (herr) {
         err = Error{TW_ERANGE, "ingest_batch: node id outside [0, num_nodes)"};
         return err.code;
@@ -886,9 +899,28 @@ void release_graph(tw_graph* g) {
     delete g;
 }
 
+// The weight-based picker's cumulative weights, rebuilt with the index
+// when the graph asks for them at ingest. A failed build leaves them to the
+// next weight-based walk, which builds them itself.
+static void ingest_weights(tw_graph* g) {
+    if (std::isnan(g->ingest_weight_tau) || g->m == 0) return;
+    Error e{TW_OK, ""};
+    if (build_weights(g, g->ingest_weight_tau, e) != TW_OK) {
+        (void)hipGetLastError();
+        g->w_ready = false;
+    }
+}
+
 tw_status ingest_views(tw_graph* g, const int32_t* src, const int32_t* dst, const int64_t* ts,
-                       int64_t n, tw_ingest_info* info, Error& err) {
-    if (ingest(g, src, dst, ts, n, info, err) != TW_OK) return err.code;
+                       int64_t n, tw_ingest_info* info, Error& err, hipEvent_t before_apply,
+                       bool walk_flags) {
+    IngestPlan P;
+    if (ingest_prepare(g, src, dst, ts, n, P, err, walk_flags) != TW_OK) return err.code;
+    // the index changes only after the event: work it marks (walks over the
+    // current index) may run while the batch is planned
+    if (before_apply) TW_HIP(hipStreamWaitEvent(g->stream, before_apply, 0));
+    if (ingest_apply(g, P, info, err) != TW_OK) return err.code;
+    ingest_weights(g);
     if (g->rev) {
         // the in-view takes the batch with source and destination swapped;
         // if that fails it is dropped and rebuilt from the window on the next
@@ -904,6 +936,7 @@ tw_status ingest_views(tw_graph* g, const int32_t* src, const int32_t* dst, cons
 
 tw_status evict_views(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& err) {
     if (evict_before(g, cutoff, n_evicted, err) != TW_OK) return err.code;
+    ingest_weights(g);
     if (g->rev) {
         Error e{TW_OK, ""};
         if (evict_before(g->rev, cutoff, nullptr, e) != TW_OK) {

@@ -2,13 +2,20 @@
 // ingestion (the request loop of the C ABI's tw_server_* calls).
 //
 // Submissions (walk requests and ingest batches) enter one FIFO. A worker
-// thread owns the graph: it applies an ingest batch when it reaches the
-// front, and packs the consecutive requests at the front into one serving
-// launch (walk.hip, k_walk_serve) once their outputs fit in the arena, while
-// earlier launches may still run (continuous batching, up to max_inflight
-// launches enqueued). A request therefore sees exactly the batches submitted
-// before it. Completion is observed through one HIP event per launch;
-// latency runs from submission to the worker seeing that event.
+// thread packs the consecutive requests at the front into one serving launch
+// (walk.hip, k_walk_serve) on the graph's stream once their outputs are
+// placed, while earlier launches may still run (continuous batching, up to
+// max_inflight launches enqueued). An ingest batch at the front goes to an
+// ingest thread, which plans it on a stream of its own while the walks of
+// the current index still run (ingest_prepare reads the index and writes
+// only ingest buffers), and changes the index after an event that marks
+// every walk launch enqueued before the batch; the walk launches after it
+// wait for the update. A request therefore sees exactly the batches
+// submitted before it (its index epoch). Request outputs live in arena
+// chunks: the first is allocated at create, more are added while the device
+// keeps a reserve of free memory. Completion is observed through one HIP
+// event per launch; latency runs from submission to the worker seeing that
+// event.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -82,6 +89,7 @@ struct Item {
     tw_status status = TW_OK;
     // request
     tw_walk_params p{};
+    int chunk = -1;  // arena chunk of the outputs
     size_t off = SIZE_MAX, bytes = 0;
     int32_t* nodes = nullptr;
     int64_t* ts = nullptr;
@@ -112,8 +120,24 @@ size_t request_bytes(const tw_walk_params& p) {
 struct tw_server {
     tw_graph* g = nullptr;
     tw_server_config cfg{};
-    char* arena_base = nullptr;
-    Arena arena;
+    // output arena chunks (base, first-fit free list)
+    std::vector<char*> chunk_base;
+    std::vector<Arena> chunk;
+    int64_t arena_total = 0;
+    hipStream_t s_walk = nullptr;  // the graph's stream: walk launches
+    hipStream_t s_ing = nullptr;   // the ingest thread's stream
+    hipEvent_t ev_walks = nullptr;    // every walk launch enqueued before an ingest
+    hipEvent_t ev_applied = nullptr;  // the last ingest's index update
+    hipEvent_t ev_scratch = nullptr;  // walk-side use of the ingest workspaces
+    bool scratch_pending = false;     // ev_scratch recorded since the last ingest began
+    bool applied_pending = false;     // the next walk launch waits for ev_applied
+    bool ing_busy = false;            // an ingest batch is with the ingest thread
+    bool ing_taken = false;           // ... and the thread has started it
+    bool ing_wait_scratch = false;
+    uint64_t ing_id = 0;
+    bool ing_stop = false;
+    std::thread ingester;
+    std::condition_variable cv_ing;
     void* d_tables = nullptr;  // MAX_INFLIGHT launch tables
     void* h_tables = nullptr;  // pinned staging of the tables
     unsigned long long* d_hops = nullptr;  // per slot
@@ -135,6 +159,7 @@ struct tw_server {
 
     // counters
     int64_t requests_done = 0, walks_done = 0, hops_done = 0, launches = 0, ingests = 0;
+    int64_t chunks_added = 0;
     std::vector<double> latencies;
     Clock::time_point t0;
 };
@@ -186,38 +211,121 @@ void finish_failed(tw_server* S, const std::vector<uint64_t>& ids, tw_status st)
     S->cv_done.notify_all();
 }
 
+// A place for `bytes` of request outputs: a free range of a chunk, else a
+// new chunk when the device keeps hbm_reserve_bytes free after it (never
+// when hbm_reserve_bytes < 0). Called with the lock held.
+bool place_outputs(tw_server* S, size_t bytes, int* chunk, size_t* off) {
+    for (size_t c = 0; c < S->chunk.size(); ++c) {
+        const size_t o = S->chunk[c].alloc(bytes);
+        if (o != SIZE_MAX) {
+            *chunk = (int)c;
+            *off = o;
+            return true;
+        }
+    }
+    if (S->cfg.hbm_reserve_bytes < 0) return false;
+    const size_t want = std::max(round_up(bytes), (size_t)S->cfg.arena_bytes / ALIGN * ALIGN);
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if ((int64_t)free_b < (int64_t)want + S->cfg.hbm_reserve_bytes) return false;
+    char* base = nullptr;
+    if (hipMalloc(reinterpret_cast<void**>(&base), want) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    S->chunk_base.push_back(base);
+    S->chunk.emplace_back();
+    S->chunk.back().reset(want);
+    S->arena_total += (int64_t)want;
+    ++S->chunks_added;
+    *chunk = (int)S->chunk.size() - 1;
+    *off = S->chunk.back().alloc(bytes);
+    return *off != SIZE_MAX;
+}
+
+// The ingest thread: plans each batch handed to it on s_ing while the walks
+// enqueued before it run, then updates the index after ev_walks.
+void ingest_loop(tw_server* S) {
+    (void)hipSetDevice(S->g->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        S->cv_ing.wait(lk, [&]() { return S->ing_stop || (S->ing_busy && !S->ing_taken); });
+        if (!(S->ing_busy && !S->ing_taken)) break;  // stopping, nothing handed over
+        S->ing_taken = true;
+        const uint64_t id = S->ing_id;
+        Item& it = S->items[id];
+        const int32_t* src = it.src;
+        const int32_t* dst = it.dst;
+        const int64_t* its = it.its;
+        const int64_t n = it.n;
+        const bool wait_scratch = S->ing_wait_scratch;
+        lk.unlock();
+        tw_graph* g = S->g;
+        tw::Error e{TW_OK, ""};
+        tw_ingest_info info{};
+        // the worker launches nothing while the batch is here, so the graph
+        // is this thread's until it hands the batch back
+        g->stream = S->s_ing;
+        if (g->rev) g->rev->stream = S->s_ing;
+        tw_status st = TW_OK;
+        if (wait_scratch && hipStreamWaitEvent(S->s_ing, S->ev_scratch, 0) != hipSuccess)
+            st = TW_EDEVICE;
+        if (st == TW_OK) st = tw::ingest_views(g, src, dst, its, n, &info, e, S->ev_walks);
+        if (hipEventRecord(S->ev_applied, S->s_ing) != hipSuccess && st == TW_OK) st = TW_EDEVICE;
+        g->stream = S->s_walk;
+        if (g->rev) g->rev->stream = S->s_walk;
+        lk.lock();
+        Item& done = S->items[id];
+        done.status = st;
+        done.info = info;
+        done.state = ST_DONE;
+        done.t_done = Clock::now();
+        ++S->ingests;
+        S->ing_busy = false;
+        S->ing_taken = false;
+        S->applied_pending = true;
+        S->cv_done.notify_all();
+        S->cv_work.notify_all();
+    }
+}
+
 void worker_loop(tw_server* S) {
     (void)hipSetDevice(S->g->device);
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
         retire(S);
-        if (S->stop && S->fifo.empty() && S->inflight.empty()) break;
+        if (S->stop && S->fifo.empty() && S->inflight.empty() && !S->ing_busy) break;
         bool progressed = false;
         if (!S->fifo.empty() && S->items[S->fifo.front()].ingest) {
-            const uint64_t id = S->fifo.front();
-            S->fifo.pop_front();
-            Item& it = S->items[id];
-            it.state = ST_RUNNING;
-            it.t_start = Clock::now();
-            const int32_t* src = it.src;
-            const int32_t* dst = it.dst;
-            const int64_t* its = it.its;
-            const int64_t n = it.n;
-            lk.unlock();
-            tw::Error e{TW_OK, ""};
-            tw_ingest_info info{};
-            // the graph and its in-view (if backward walks created one)
-            const tw_status st = tw::ingest_views(S->g, src, dst, its, n, &info, e);
-            lk.lock();
-            Item& done = S->items[id];
-            done.status = st;
-            done.info = info;
-            done.state = ST_DONE;
-            done.t_done = Clock::now();
-            ++S->ingests;
-            S->cv_done.notify_all();
-            progressed = true;
-        } else if (!S->fifo.empty() && (int)S->inflight.size() < S->cfg.max_inflight) {
+            if (!S->ing_busy) {
+                // hand the batch over; it updates the index after every
+                // walk launch enqueued so far
+                const uint64_t id = S->fifo.front();
+                S->fifo.pop_front();
+                Item& it = S->items[id];
+                it.state = ST_RUNNING;
+                it.t_start = Clock::now();
+                if (hipEventRecord(S->ev_walks, S->s_walk) != hipSuccess) {
+                    (void)hipGetLastError();
+                    it.state = ST_DONE;
+                    it.status = TW_EDEVICE;
+                    it.t_done = Clock::now();
+                    S->cv_done.notify_all();
+                } else {
+                    S->ing_busy = true;
+                    S->ing_taken = false;
+                    S->ing_id = id;
+                    S->ing_wait_scratch = S->scratch_pending;
+                    S->scratch_pending = false;
+                    S->cv_ing.notify_one();
+                }
+                progressed = true;
+            }
+        } else if (!S->fifo.empty() && !S->ing_busy &&
+                   (int)S->inflight.size() < S->cfg.max_inflight) {
             // admit the consecutive requests at the front that fit
             std::vector<uint64_t> ids;
             int64_t walks = 0;
@@ -225,11 +333,13 @@ void worker_loop(tw_server* S) {
                 Item& it = S->items[S->fifo.front()];
                 if (it.ingest) break;
                 if (!ids.empty() && walks + it.p.num_walks > S->cfg.max_walks_per_launch) break;
-                const size_t off = S->arena.alloc(it.bytes);
-                if (off == SIZE_MAX) break;  // wait for outputs to be released
+                int c = -1;
+                size_t off = SIZE_MAX;
+                if (!place_outputs(S, it.bytes, &c, &off)) break;  // wait for releases
+                it.chunk = c;
                 it.off = off;
                 const size_t slots = (size_t)it.p.num_walks * (size_t)it.p.max_len;
-                char* base = S->arena_base + off;
+                char* base = S->chunk_base[c] + off;
                 it.nodes = reinterpret_cast<int32_t*>(base);
                 it.ts = reinterpret_cast<int64_t*>(base + round_up(4 * slots));
                 it.len = reinterpret_cast<int32_t*>(base + round_up(4 * slots) +
@@ -261,17 +371,33 @@ void worker_loop(tw_server* S) {
                     r.len = it.len;
                     reqs.push_back(r);
                 }
+                const bool wait_applied = S->applied_pending;
+                S->applied_pending = false;
                 lk.unlock();
                 tw::Error e{TW_OK, ""};
-                hipStream_t s = S->g->stream;
+                hipStream_t s = S->s_walk;
                 char* dt = static_cast<char*>(S->d_tables) + slot * S->table_bytes;
                 char* ht = static_cast<char*>(S->h_tables) + slot * S->table_bytes;
                 uint32_t* de = S->d_err + (size_t)slot * ERR_WORDS;
                 const int nw = 2 * (int)reqs.size();
-                hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, S->d_hops + slot);
-                hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, s, de, nw);
-                tw_status st = tw::serve_launch(S->g, reqs.data(), (int)reqs.size(), dt, ht,
-                                                S->d_hops + slot, de, e);
+                tw_status st = TW_OK;
+                // the walks of a new epoch start after its index update
+                if (wait_applied && hipStreamWaitEvent(s, S->ev_applied, 0) != hipSuccess)
+                    st = TW_EDEVICE;
+                const bool adj_before = S->g->adj_ready;
+                // an index whose update failed midway serves nothing
+                if (st == TW_OK && S->g->broken) st = TW_EDEVICE;
+                if (st == TW_OK) {
+                    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, S->d_hops + slot);
+                    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, s, de, nw);
+                    st = tw::serve_launch(S->g, reqs.data(), (int)reqs.size(), dt, ht,
+                                          S->d_hops + slot, de, e);
+                }
+                // a node2vec adjacency built here used the ingest workspaces:
+                // the next batch is planned after it
+                const bool built = !adj_before && S->g->adj_ready;
+                if (st == TW_OK && built && hipEventRecord(S->ev_scratch, s) != hipSuccess)
+                    st = TW_EDEVICE;
                 if (st == TW_OK &&
                     (hipMemcpyAsync(S->h_hops + slot, S->d_hops + slot, sizeof(unsigned long long),
                                     hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -280,6 +406,7 @@ void worker_loop(tw_server* S) {
                      hipEventRecord(S->ev[slot], s) != hipSuccess))
                     st = TW_EDEVICE;
                 lk.lock();
+                if (built) S->scratch_pending = true;
                 if (st != TW_OK) {
                     S->slot_busy[slot] = false;
                     finish_failed(S, ids, st);
@@ -290,11 +417,15 @@ void worker_loop(tw_server* S) {
                 progressed = true;
             }
         }
-        if (!progressed && S->stop && S->inflight.empty() && !S->fifo.empty()) {
+        if (!progressed && S->stop && S->inflight.empty() && !S->ing_busy && !S->fifo.empty() &&
+            !S->items[S->fifo.front()].ingest) {
             // stopping with requests whose outputs cannot be placed (the
             // arena holds unreleased results): fail them instead of waiting
-            std::vector<uint64_t> rest(S->fifo.begin(), S->fifo.end());
-            S->fifo.clear();
+            std::vector<uint64_t> rest;
+            while (!S->fifo.empty() && !S->items[S->fifo.front()].ingest) {
+                rest.push_back(S->fifo.front());
+                S->fifo.pop_front();
+            }
             finish_failed(S, rest, TW_ENOMEM);
             continue;
         }
@@ -309,6 +440,8 @@ void worker_loop(tw_server* S) {
             }
         }
     }
+    S->ing_stop = true;
+    S->cv_ing.notify_all();
 }
 
 }  // namespace
@@ -326,9 +459,11 @@ tw_status server_create(tw_graph* g, const tw_server_config* cfg, tw_server** ou
     tw_server* S = new tw_server();
     S->g = g;
     S->cfg = *cfg;
+    S->s_walk = g->stream;
     S->table_bytes = round_up(serve_table_bytes(MAX_REQ_PER_LAUNCH));
+    char* base0 = nullptr;
     auto cleanup = [&]() {
-        if (S->arena_base) (void)hipFree(S->arena_base);
+        if (base0) (void)hipFree(base0);
         if (S->d_tables) (void)hipFree(S->d_tables);
         if (S->d_hops) (void)hipFree(S->d_hops);
         if (S->d_err) (void)hipFree(S->d_err);
@@ -337,9 +472,13 @@ tw_status server_create(tw_graph* g, const tw_server_config* cfg, tw_server** ou
         if (S->h_err) (void)hipHostFree(S->h_err);
         for (hipEvent_t& e : S->ev)
             if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : {S->ev_walks, S->ev_applied, S->ev_scratch})
+            if (e) (void)hipEventDestroy(e);
+        if (S->s_ing) (void)hipStreamDestroy(S->s_ing);
         delete S;
     };
-    if (hipMalloc(reinterpret_cast<void**>(&S->arena_base), (size_t)cfg->arena_bytes) != hipSuccess ||
+    const size_t arena = (size_t)cfg->arena_bytes / ALIGN * ALIGN;
+    if (hipMalloc(reinterpret_cast<void**>(&base0), arena) != hipSuccess ||
         hipMalloc(&S->d_tables, S->table_bytes * MAX_INFLIGHT) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&S->d_hops), sizeof(unsigned long long) * MAX_INFLIGHT) !=
             hipSuccess ||
@@ -358,16 +497,25 @@ tw_status server_create(tw_graph* g, const tw_server_config* cfg, tw_server** ou
         err = Error{TW_ENOMEM, "server_create: device or pinned allocation failed"};
         return err.code;
     }
-    for (hipEvent_t& e : S->ev) {
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-            cleanup();
-            err = Error{TW_EDEVICE, "server_create: event creation failed"};
-            return err.code;
-        }
+    bool ok = true;
+    for (hipEvent_t& e : S->ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    for (hipEvent_t* e : {&S->ev_walks, &S->ev_applied, &S->ev_scratch})
+        ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+    // the ingest stream keeps the default priority, like the graph's
+    ok = ok && hipStreamCreateWithFlags(&S->s_ing, hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        cleanup();
+        err = Error{TW_EDEVICE, "server_create: event or stream creation failed"};
+        return err.code;
     }
-    S->arena.reset((size_t)cfg->arena_bytes / ALIGN * ALIGN);
+    S->chunk_base.push_back(base0);
+    S->chunk.emplace_back();
+    S->chunk.back().reset(arena);
+    S->arena_total = (int64_t)arena;
     S->t0 = Clock::now();
     S->worker = std::thread(worker_loop, S);
+    S->ingester = std::thread(ingest_loop, S);
     *out = S;
     return TW_OK;
 }
@@ -383,8 +531,8 @@ tw_status server_submit(tw_server* S, const tw_walk_params* p, uint64_t* id, Err
         return err.code;
     }
     const size_t bytes = request_bytes(*p);
-    if (bytes > (size_t)S->cfg.arena_bytes / ALIGN * ALIGN) {
-        err = Error{TW_EINVAL, "server_submit: the request's outputs exceed the arena"};
+    if (S->cfg.hbm_reserve_bytes < 0 && bytes > (size_t)S->cfg.arena_bytes / ALIGN * ALIGN) {
+        err = Error{TW_EINVAL, "server_submit: the request's outputs exceed the fixed arena"};
         return err.code;
     }
     std::lock_guard<std::mutex> lk(S->mu);
@@ -459,7 +607,8 @@ tw_status server_release(tw_server* S, uint64_t id, Error& err) {
         err = Error{TW_EINVAL, "server_release: unknown or unfinished request"};
         return err.code;
     }
-    if (found->second.off != SIZE_MAX) S->arena.release(found->second.off, found->second.bytes);
+    if (found->second.off != SIZE_MAX)
+        S->chunk[found->second.chunk].release(found->second.off, found->second.bytes);
     S->items.erase(found);
     S->cv_work.notify_one();  // memory for waiting requests
     return TW_OK;
@@ -507,6 +656,8 @@ tw_status server_stats(tw_server* S, tw_server_counters* out, Error& err) {
     out->hops_done = S->hops_done;
     out->launches = S->launches;
     out->ingests = S->ingests;
+    out->arena_bytes = S->arena_total;
+    out->arena_chunks_added = S->chunks_added;
     out->wall_s = std::chrono::duration<double>(Clock::now() - S->t0).count();
     if (!S->latencies.empty()) {
         std::vector<double> v = S->latencies;
@@ -532,8 +683,17 @@ tw_status server_destroy(tw_server* S, Error& err) {
         S->cv_work.notify_all();
     }
     if (S->worker.joinable()) S->worker.join();
-    (void)hipStreamSynchronize(S->g->stream);
-    (void)hipFree(S->arena_base);
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->ing_stop = true;
+        S->cv_ing.notify_all();
+    }
+    if (S->ingester.joinable()) S->ingester.join();
+    (void)hipStreamSynchronize(S->s_ing);
+    (void)hipStreamSynchronize(S->s_walk);
+    // later calls on the graph are ordered after the last index update
+    (void)hipStreamWaitEvent(S->s_walk, S->ev_applied, 0);
+    for (char* b : S->chunk_base) (void)hipFree(b);
     (void)hipFree(S->d_tables);
     (void)hipFree(S->d_hops);
     (void)hipFree(S->d_err);
@@ -541,6 +701,8 @@ tw_status server_destroy(tw_server* S, Error& err) {
     (void)hipHostFree(S->h_hops);
     (void)hipHostFree(S->h_err);
     for (hipEvent_t e : S->ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {S->ev_walks, S->ev_applied, S->ev_scratch}) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(S->s_ing);
     delete S;
     (void)err;
     return TW_OK;

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -309,6 +310,9 @@ struct tw_graph {
     tw::DevBuf cw, w_tiles;
     bool w_ready = false;
     double w_scale = 0.0;
+    // the time scale whose weights every ingest and eviction rebuilds (NaN:
+    // none; the first weight-based walk after a change builds them)
+    double ingest_weight_tau = NAN;
     // backward walks of a directed graph: the in-view, a graph fed every
     // batch with source and destination swapped (null until first needed)
     tw_graph* rev = nullptr;
@@ -316,7 +320,14 @@ struct tw_graph {
     // cooperative dispatch: per-walk state, live list, sort buffers
     tw::DevBuf c_node0, c_walk0, c_t0, c_node1, c_walk1, c_t1, c_node2, c_walk2, c_t2;
     tw::DevBuf c_prev, c_flags, c_pos;
-    uint32_t coop_panel = 4096;        // LDS panel entries per workgroup
+    // tunables of the cooperative dispatch (tw_autotune sets them): LDS
+    // panel entries per workgroup, lanes of a wavefront at one node that
+    // engage the wavefront tier, regroup per step (0: stable sort by node,
+    // 1: none), steps between read-backs of the live count
+    uint32_t coop_panel = 4096;
+    int coop_wave_min = 64;
+    int coop_regroup = 0;
+    int coop_sync = 1;
     // queue dispatch: slice counters; compute units; the dispatch AUTO runs
     // (0: full-walk until tw_autotune chooses) and the queue's workgroups per CU
     tw::DevBuf wq;
@@ -410,13 +421,18 @@ struct IngestPlan {
     int64_t m_old = 0, e_base = 0;  // the window the plan was made against
     uint32_t epoch = 0;
 };
+// walk_flags: report (and clear) the error flags earlier walks left on the
+// graph, read back with the batch's counts, instead of ingesting
 tw_status ingest_prepare(tw_graph* g, const int32_t* src, const int32_t* dst, const int64_t* ts,
-                         int64_t n, IngestPlan& P, Error& err);
+                         int64_t n, IngestPlan& P, Error& err, bool walk_flags = false);
 tw_status ingest_apply(tw_graph* g, const IngestPlan& P, tw_ingest_info* info, Error& err);
 tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& err);
-// ingest / evict_before on the graph and on its in-view (when it has one)
+// ingest / evict_before on the graph and on its in-view (when it has one).
+// before_apply (nullable): the graph's stream waits for it between planning
+// the batch and changing the index.
 tw_status ingest_views(tw_graph* g, const int32_t* src, const int32_t* dst, const int64_t* ts,
-                       int64_t n, tw_ingest_info* info, Error& err);
+                       int64_t n, tw_ingest_info* info, Error& err,
+                       hipEvent_t before_apply = nullptr, bool walk_flags = false);
 tw_status evict_views(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& err);
 tw_status build_adjacency(tw_graph* g, Error& err);
 // The graph whose node view holds the in-edges (backward walks): g itself
@@ -442,6 +458,9 @@ tw_status row_offsets(tw_graph* g, const int32_t* max_len, int64_t n, int64_t* r
                       int64_t* total, Error& err);
 tw_status autotune(tw_graph* g, const tw_walk_params* p, int64_t sample, int32_t* nodes,
                    int64_t* ts, int32_t* len, int32_t best[2], Error& err);
+tw_tuning get_tuning(const tw_graph* g);
+void set_tuning_fields(tw_graph* g, const tw_tuning& t);
+tw_status set_tuning(tw_graph* g, const tw_tuning* t, Error& err);
 // allocation-free walks: set-up once per device (device current), the call
 tw_status noalloc_setup(int device, Error& err);
 int64_t noalloc_scratch_bytes();

@@ -547,8 +547,10 @@ struct Live {
 // Hops of the live walks after their start (k_coop_start and
 // k_compact_live leave them in `live`, n_live of them): the work queue
 // without the start pick, so a lane that takes a walk only loads its state
-// and the kernel keeps the registers of the full-walk kernel.
-template <int HK>
+// and the kernel keeps the registers of the full-walk kernel. ROWS: each
+// lane writes its walk's whole output row, four slots per store, padding
+// included (as k_walk_full); otherwise the rows were pre-filled.
+template <int HK, bool ROWS>
 __global__ void __launch_bounds__(WALK_THREADS)
 k_walk_hops(const WalkArgs a, Live live, const int32_t* __restrict__ prev_of,
             const uint32_t* __restrict__ n_live_p, unsigned long long* counters) {
@@ -563,6 +565,7 @@ k_walk_hops(const WalkArgs a, Live live, const int32_t* __restrict__ prev_of,
     int64_t tcur = 0;
     int32_t* out_n = nullptr;
     int64_t* out_t = nullptr;
+    RowChunk c;
     const HopBias hb = fixed_hop<HK>(a.hop);
     while (true) {
         const uint64_t idle = __ballot(w < 0);
@@ -591,6 +594,12 @@ k_walk_hops(const WalkArgs a, Live live, const int32_t* __restrict__ prev_of,
                     out_t = a.ts + w * (int64_t)a.L;
                     len = 2;
                     hop = 1;
+                    if (ROWS) {
+                        // positions 0 and 1: the start edge's source and target
+                        c = RowChunk();
+                        c.push(prev, TS_NONE);
+                        c.push(cur, tcur);
+                    }
                 }
             }
             if (lo + (int64_t)got + n >= hi) {
@@ -610,8 +619,13 @@ k_walk_hops(const WalkArgs a, Live live, const int32_t* __restrict__ prev_of,
                 Pick p;
                 int32_t nx;
                 if (hop_pick(a, hb, a.seed, r, gc, id, hop, prev, p, nx)) {
-                    out_n[len] = nx;
-                    out_t[len] = p.t;
+                    if (ROWS) {
+                        c.push(nx, p.t);
+                        if (((len + 1) & 3) == 0) c.store(out_n, out_t, len - 3);
+                    } else {
+                        out_n[len] = nx;
+                        out_t[len] = p.t;
+                    }
                     ++len;
                     ++hop;
                     prev = cur;
@@ -621,6 +635,7 @@ k_walk_hops(const WalkArgs a, Live live, const int32_t* __restrict__ prev_of,
                 }
             }
             if (done) {
+                if (ROWS) finish_row(c, out_n, out_t, len, a.L);
                 a.len[w] = len;
                 w = -1;
             }
@@ -772,15 +787,19 @@ k_walk_serve(const WalkArgs a, const ServeReqDev* __restrict__ reqs, int nreq,
 
 // Live walks of one step, structure of arrays in one order: current node,
 // walk index, time of arrival.
-template <int SK>
+// ROWS: the rows are not pre-filled; a walk that ends at its start writes
+// its whole padded row here, and the hop kernel writes the rows of the others.
+template <int SK, bool ROWS = false>
 __global__ void __launch_bounds__(WALK_THREADS) k_coop_start(const WalkArgs a, Live nx,
                                                               int32_t* __restrict__ prev,
                                                               uint32_t* __restrict__ alive) {
     const int64_t w = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
     if (w >= a.num_walks) return;
     const uint64_t id = a.base + (uint64_t)w;
-    StartState st = walk_start(a, fixed_start<SK>(start_of(a)), w, id, a.L, a.nodes + w * a.L,
-                               a.ts + w * a.L);
+    int32_t* out_n = a.nodes + w * a.L;
+    int64_t* out_t = a.ts + w * a.L;
+    StartState st = walk_start(a, fixed_start<SK>(start_of(a)), w, id, a.L,
+                               ROWS ? nullptr : out_n, out_t);
     bool live = st.len >= 2 && st.len < a.L;
     if (live) {
         nx.node[w] = (uint32_t)st.cur;
@@ -788,6 +807,12 @@ __global__ void __launch_bounds__(WALK_THREADS) k_coop_start(const WalkArgs a, L
         nx.t[w] = (uint64_t)st.t;
         prev[w] = st.prev;
     } else {
+        if (ROWS) {
+            RowChunk c;
+            if (st.len >= 1) c.push(st.first, TS_NONE);
+            if (st.len >= 2) c.push(st.cur, st.t);
+            finish_row(c, out_n, out_t, st.len, a.L);
+        }
         finish_walk(a, w, st.len);
     }
     alive[w] = live ? 1u : 0u;
@@ -805,38 +830,47 @@ __global__ void k_compact_live(const uint32_t* __restrict__ flags, const uint32_
     }
 }
 
-// One hop for the n live walks of `cur`, sorted by node. Results go to `nx`
-// at the same positions, with alive[i] set for walks that continue.
+// One hop for the live walks of `cur` (*n_live of the n_ub entries; the
+// rest are idle), in node order when the step sorted them. Results go to
+// `nx` at the same positions, with alive[i] set for walks that continue (0
+// for idle entries). A wavefront engages the wavefront tier for the node of
+// its first lane when at least wave_min of its lanes are at that node: the
+// record is read once and the top levels of the node's fence are staged in
+// LDS for those lanes; a workgroup whose four wavefronts engage it for one
+// node stages a panel four times larger.
 template <int HK>
 __global__ void __launch_bounds__(WALK_THREADS)
-k_hop_coop(const WalkArgs a, Live cur, Live nxt, int32_t* __restrict__ prev_of, int64_t n,
-           uint64_t hop, uint32_t panel_cap, uint32_t* __restrict__ alive) {
+k_hop_coop(const WalkArgs a, Live cur, Live nxt, int32_t* __restrict__ prev_of,
+           const uint32_t* __restrict__ n_live, int64_t n_ub, uint64_t hop, uint32_t panel_cap,
+           int wave_min, uint32_t* __restrict__ alive) {
     extern __shared__ __align__(16) uint32_t panel[];
     __shared__ int32_t wave_node[WALK_THREADS / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
-    const bool valid = i < n;
+    const bool valid = i < (int64_t)*n_live;
     const int32_t v = valid ? (int32_t)cur.node[i] : -1;
     const int32_t v0 = __shfl(v, 0, 64);
-    const bool wave_uniform = __ballot(valid && v == v0) == ~0ull;
-    if (lane == 0) wave_node[wave] = wave_uniform ? v0 : -1;
+    const int at_v0 = __popcll(__ballot(valid && v == v0));
+    const bool wave_tier = v0 >= 0 && at_v0 >= wave_min;
+    if (lane == 0) wave_node[wave] = wave_tier ? v0 : -1;
     __syncthreads();
-    bool wg_uniform = wave_node[0] >= 0;
+    bool wg_tier = wave_node[0] >= 0;
 #pragma unroll
-    for (int k = 1; k < WALK_THREADS / 64; ++k) wg_uniform &= wave_node[k] == wave_node[0];
+    for (int k = 1; k < WALK_THREADS / 64; ++k) wg_tier &= wave_node[k] == wave_node[0];
 
     // stage the top levels of the node's fence: the whole panel for a
-    // uniform workgroup, a quarter of it per uniform wavefront otherwise.
+    // workgroup of one node, a quarter of it per wavefront otherwise.
     // Levels are stored bottom-up, so levels K down to some m are one
     // contiguous range.
     const uint32_t* my_panel = nullptr;
     uint64_t my_base = 0;
     uint32_t my_cap = 0;
-    if (wg_uniform || wave_uniform) {
-        const int32_t node = wg_uniform ? wave_node[0] : v0;
-        const NodeRec r = a.rec[node];
-        const uint32_t slice = wg_uniform ? panel_cap : panel_cap / (WALK_THREADS / 64);
-        uint32_t* dst = wg_uniform ? panel : panel + wave * slice;
+    int32_t panel_node = -1;
+    if (wg_tier || wave_tier) {
+        panel_node = wg_tier ? wave_node[0] : v0;
+        const NodeRec r = a.rec[panel_node];
+        const uint32_t slice = wg_tier ? panel_cap : panel_cap / (WALK_THREADS / 64);
+        uint32_t* dst = wg_tier ? panel : panel + wave * slice;
         const int K = (int)rec_levels(r.lv);
         if (K > 0) {
             const uint64_t cap = seg_groups(rec_code(r.lv));
@@ -851,13 +885,21 @@ k_hop_coop(const WalkArgs a, Live cur, Live nxt, int32_t* __restrict__ prev_of, 
             my_base = from;
             my_cap = (uint32_t)(top - from);
         }
-        const int first = wg_uniform ? threadIdx.x : lane;
-        const int stride = wg_uniform ? WALK_THREADS : 64;
+        const int first = wg_tier ? threadIdx.x : lane;
+        const int stride = wg_tier ? WALK_THREADS : 64;
         for (uint32_t j = first; j < my_cap; j += stride) dst[j] = a.fence[my_base + j];
         my_panel = dst;
     }
     __syncthreads();
-    if (!valid) return;
+    if (!valid) {
+        if (i < n_ub) alive[i] = 0u;
+        return;
+    }
+    if (v != panel_node) {
+        my_panel = nullptr;
+        my_base = 0;
+        my_cap = 0;
+    }
 
     const uint32_t w = cur.walk[i];
     const uint64_t id = a.base + (uint64_t)w;
@@ -891,6 +933,14 @@ k_hop_coop(const WalkArgs a, Live cur, Live nxt, int32_t* __restrict__ prev_of, 
     alive[i] = live ? 1u : 0u;
 }
 
+// entries [*n_live, n_ub) of a live list get a node id above every real
+// one, so a sort by node leaves them last
+__global__ void k_live_tail(Live live, const uint32_t* __restrict__ n_live, int64_t n_ub,
+                            uint32_t sentinel) {
+    const int64_t i = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
+    if (i < n_ub && i >= (int64_t)*n_live) live.node[i] = sentinel;
+}
+
 bool valid_tau(double t) { return std::isfinite(t); }
 
 template <int V>
@@ -917,8 +967,11 @@ void with_kinds(int hk, int sk, F&& f) {
     }
 }
 
-// Host loop of the cooperative dispatch: one synchronisation per step (the
-// live count), then sort by node -> hop -> in-order compaction.
+// Host loop of the cooperative dispatch: per step, regroup the live walks
+// by node (a stable sort, or none), one hop, in-order compaction. The live
+// count is read back every coop_sync steps; in between, launches cover the
+// last count read (an upper bound) and their threads past the device count
+// idle.
 tw_status coop_walks(tw_graph* g, const WalkArgs& a, Error& err) {
     hipStream_t s = g->stream;
     const int64_t W = a.num_walks;
@@ -936,8 +989,10 @@ tw_status coop_walks(tw_graph* g, const WalkArgs& a, Error& err) {
     uint32_t* flags = g->c_flags.as<uint32_t>();
     uint32_t* pos = g->c_pos.as<uint32_t>();
     uint32_t* n_live_d = g->scal.as<uint32_t>() + SLOT_U32_N_LIVE;
-    const int vbits = bits_for((uint64_t)(g->V - 1));
+    // node ids and the sentinel V sort in bits_for(V) bits
+    const int vbits = bits_for((uint64_t)g->V);
     const uint32_t panel_cap = g->coop_panel;
+    const int sync_every = std::max(g->coop_sync, 1);
     const dim3 wgrid((unsigned)ceil_div(W, WALK_THREADS));
 
     with_kinds(-1, a.start_kind, [&](auto, auto sk) {
@@ -947,21 +1002,31 @@ tw_status coop_walks(tw_graph* g, const WalkArgs& a, Error& err) {
     TW_HIP(scan_exclusive_u32(flags, pos, W, n_live_d, g->ws, s));
     hipLaunchKernelGGL(k_compact_live, wgrid, dim3(WALK_THREADS), 0, s, flags, pos, W, next, live);
     TW_HIP(hipGetLastError());
+    int64_t n_ub = W;
     for (uint64_t hop = 1; hop + 1 < (uint64_t)a.L; ++hop) {
-        if (pull_scalars(g, false, err) != TW_OK) return err.code;
-        const uint32_t n_live = host_u32(g, SLOT_U32_N_LIVE);
-        if (n_live == 0) break;
-        const dim3 grid((unsigned)ceil_div(n_live, WALK_THREADS));
-        TW_HIP(radix_sort_u32_kv(live.node, live.walk, live.t, sorted.node, sorted.walk, sorted.t,
-                                 n_live, 0, vbits, g->ws, s));
+        if ((hop - 1) % (uint64_t)sync_every == 0) {
+            if (pull_scalars(g, false, err) != TW_OK) return err.code;
+            n_ub = host_u32(g, SLOT_U32_N_LIVE);
+            if (n_ub == 0) break;
+        }
+        const dim3 grid((unsigned)ceil_div(n_ub, WALK_THREADS));
+        Live in = live;
+        if (g->coop_regroup == 0) {
+            if (sync_every > 1)
+                hipLaunchKernelGGL(k_live_tail, grid, dim3(WALK_THREADS), 0, s, live, n_live_d,
+                                   n_ub, (uint32_t)g->V);
+            TW_HIP(radix_sort_u32_kv(live.node, live.walk, live.t, sorted.node, sorted.walk,
+                                     sorted.t, n_ub, 0, vbits, g->ws, s));
+            in = sorted;
+        }
         with_kinds(a.hop.kind, TW_UNIFORM, [&](auto hk, auto) {
             hipLaunchKernelGGL((k_hop_coop<decltype(hk)::value>), grid, dim3(WALK_THREADS),
-                               sizeof(uint32_t) * panel_cap, s, a, sorted, next, prev,
-                               (int64_t)n_live, hop, panel_cap, flags);
+                               sizeof(uint32_t) * panel_cap, s, a, in, next, prev, n_live_d,
+                               n_ub, hop, panel_cap, g->coop_wave_min, flags);
         });
-        TW_HIP(scan_exclusive_u32(flags, pos, n_live, n_live_d, g->ws, s));
-        hipLaunchKernelGGL(k_compact_live, grid, dim3(WALK_THREADS), 0, s, flags, pos,
-                           (int64_t)n_live, next, live);
+        TW_HIP(scan_exclusive_u32(flags, pos, n_ub, n_live_d, g->ws, s));
+        hipLaunchKernelGGL(k_compact_live, grid, dim3(WALK_THREADS), 0, s, flags, pos, n_ub, next,
+                           live);
         TW_HIP(hipGetLastError());
     }
     return TW_OK;
@@ -1102,6 +1167,14 @@ tw_status batch_full_walk(tw_graph* g, const WalkArgs& a, const QueueArgs& q, Er
     return TW_OK;
 }
 
+// Whether the full-walk and queue kernels write whole output rows themselves (four slots
+// per 16-byte store, padding included): rows of a multiple of 4 slots and
+// 16-byte aligned outputs.
+bool own_rows(const WalkArgs& a) {
+    return a.L % 4 == 0 && (reinterpret_cast<uintptr_t>(a.nodes) & 15) == 0 &&
+           (reinterpret_cast<uintptr_t>(a.ts) & 15) == 0;
+}
+
 // Per-call lists of the queue dispatch of plain walks: the walks alive after
 // their start (current node, walk, time) before and after compaction, each
 // walk's previous node, the alive flags and their scan, the live count, the
@@ -1125,22 +1198,32 @@ tw_status queue_hops_in(tw_graph* g, const WalkArgs& a, int bpc, const HopLists&
     const int64_t W = a.num_walks;
     if (queue_shape(g, err) != TW_OK) return err.code;
     const dim3 wgrid((unsigned)ceil_div(W, WALK_THREADS));
+    const bool rows = own_rows(a);
     with_kinds(-1, a.start_kind, [&](auto, auto sk) {
-        hipLaunchKernelGGL((k_coop_start<decltype(sk)::value>), wgrid, dim3(WALK_THREADS), 0, s, a,
-                           h.next, h.prev, h.flags);
+        if (rows)
+            hipLaunchKernelGGL((k_coop_start<decltype(sk)::value, true>), wgrid,
+                               dim3(WALK_THREADS), 0, s, a, h.next, h.prev, h.flags);
+        else
+            hipLaunchKernelGGL((k_coop_start<decltype(sk)::value, false>), wgrid,
+                               dim3(WALK_THREADS), 0, s, a, h.next, h.prev, h.flags);
     });
     TW_HIP(scan_exclusive_u32_into(h.flags, h.pos, W, h.n_live, h.scan_part, s));
     hipLaunchKernelGGL(k_compact_live, wgrid, dim3(WALK_THREADS), 0, s, h.flags, h.pos, W, h.next,
                        h.live);
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, h.counters);
     with_kinds(a.hop.kind, TW_UNIFORM, [&](auto hk, auto) {
-        auto kernel = k_walk_hops<decltype(hk)::value>;
-        static const int maxb = resident_bpc(kernel);  // per instantiation
-        const int b = (bpc <= 0 || bpc > maxb) ? maxb : bpc;
-        const int64_t blocks =
-            std::min<int64_t>(ceil_div(W, WALK_THREADS), (int64_t)g->cu_count * b);
-        hipLaunchKernelGGL(kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)),
-                           dim3(WALK_THREADS), 0, s, a, h.live, h.prev, h.n_live, h.counters);
+        auto launch = [&](auto kernel) {
+            static const int maxb = resident_bpc(kernel);  // per instantiation
+            const int b = (bpc <= 0 || bpc > maxb) ? maxb : bpc;
+            const int64_t blocks =
+                std::min<int64_t>(ceil_div(W, WALK_THREADS), (int64_t)g->cu_count * b);
+            hipLaunchKernelGGL(kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)),
+                               dim3(WALK_THREADS), 0, s, a, h.live, h.prev, h.n_live, h.counters);
+        };
+        if (rows)
+            launch(k_walk_hops<decltype(hk)::value, true>);
+        else
+            launch(k_walk_hops<decltype(hk)::value, false>);
     });
     TW_HIP(hipGetLastError());
     return TW_OK;
@@ -1168,18 +1251,11 @@ tw_status queue_hops(tw_graph* g, const WalkArgs& a, int bpc, Error& err) {
     return queue_hops_in(g, a, bpc, h, err);
 }
 
-// Whether the full-walk kernel writes whole output rows itself (four slots
-// per 16-byte store, padding included): rows of a multiple of 4 slots and
-// 16-byte aligned outputs.
-bool own_rows(const WalkArgs& a) {
-    return a.L % 4 == 0 && (reinterpret_cast<uintptr_t>(a.nodes) & 15) == 0 &&
-           (reinterpret_cast<uintptr_t>(a.ts) & 15) == 0;
-}
 
 // run the walks of `a` under a dispatch; the output rows are padded first
 // unless the walk kernel writes them whole
 tw_status run_dispatch(tw_graph* g, const WalkArgs& a, int dispatch, int bpc, Error& err) {
-    if (dispatch != TW_DISPATCH_FULL_WALK || !own_rows(a))
+    if ((dispatch != TW_DISPATCH_FULL_WALK && dispatch != TW_DISPATCH_QUEUE) || !own_rows(a))
         launch_fill(g, a.nodes, a.ts, a.num_walks * (int64_t)a.L);
     if (dispatch == TW_DISPATCH_COOP) return coop_walks(g, a, err);
     if (dispatch == TW_DISPATCH_QUEUE) return queue_hops(g, a, bpc, err);
@@ -1451,8 +1527,9 @@ tw_status sample_walks_noalloc(tw_graph* g, const tw_walk_params* p, int32_t* no
     h.n_live = na_at<uint32_t>(base, NA_NLIVE);
     h.scan_part = na_at<uint32_t>(base, NA_PART);
     h.counters = na_at<unsigned long long>(base, NA_COUNTERS);
-    // the queue dispatch pads the rows first, as tw_sample_walks does
-    launch_fill(g, a.nodes, a.ts, a.num_walks * (int64_t)a.L);
+    // the rows are padded first unless the kernels write them whole, as in
+    // tw_sample_walks
+    if (!own_rows(a)) launch_fill(g, a.nodes, a.ts, a.num_walks * (int64_t)a.L);
     return queue_hops_in(g, a, g->auto_bpc, h, err);
 }
 
@@ -1553,27 +1630,43 @@ tw_status autotune(tw_graph* g, const tw_walk_params* p, int64_t sample, int32_t
     WalkArgs a;
     if (prepare_plain(g, &q, nodes, ts, len, a, err) != TW_OK) return err.code;
     if (q.num_walks == 0) return TW_OK;
-    struct Cand {
-        int dispatch, bpc;
-    };
     if (queue_shape(g, err) != TW_OK) return err.code;
-    // queue launch shapes: as many workgroups as fit (0), or 4 or 2 per CU
-    std::vector<Cand> cands{{TW_DISPATCH_FULL_WALK, 0}, {TW_DISPATCH_COOP, 0},
-                            {TW_DISPATCH_QUEUE, 0}, {TW_DISPATCH_QUEUE, 4},
-                            {TW_DISPATCH_QUEUE, 2}};
+    // full-walk; the queue at three launch shapes (as many workgroups as
+    // fit, 4 or 2 per CU); the cooperative dispatch over its regroup, the
+    // lanes that engage the wavefront tier, the LDS panel and the read-back
+    // cadence of the live count
+    std::vector<tw_tuning> cands;
+    const tw_tuning base{TW_DISPATCH_FULL_WALK, 0, 0, 64, 4096, 1};
+    cands.push_back(base);
+    for (int bpc : {0, 4, 2}) {
+        tw_tuning c = base;
+        c.dispatch = TW_DISPATCH_QUEUE;
+        c.queue_bpc = bpc;
+        cands.push_back(c);
+    }
+    for (int regroup : {0, 1})
+        for (int wave_min : {64, 16})
+            for (int panel : {2048, 8192})
+                for (int sync : {1, 4}) {
+                    if (regroup == 1 && (wave_min != 64 || panel != 2048)) continue;
+                    cands.push_back(tw_tuning{TW_DISPATCH_COOP, 0, regroup, wave_min, panel, sync});
+                }
+    const tw_tuning saved = get_tuning(g);
     hipEvent_t e0, e1;
     TW_HIP(hipEventCreate(&e0));
     TW_HIP(hipEventCreate(&e1));
     float best_ms = 0.0f;
-    Cand pick{TW_DISPATCH_FULL_WALK, 0};
+    tw_tuning pick = base;
     bool first = true;
-    for (const Cand& c : cands) {
+    for (const tw_tuning& c : cands) {
+        set_tuning_fields(g, c);
         float ms_min = 0.0f;
         for (int rep = 0; rep < 3; ++rep) {  // the first run warms up
             hipEventRecord(e0, g->stream);
-            if (run_dispatch(g, a, c.dispatch, c.bpc, err) != TW_OK) {
+            if (run_dispatch(g, a, c.dispatch, c.queue_bpc, err) != TW_OK) {
                 hipEventDestroy(e0);
                 hipEventDestroy(e1);
+                set_tuning_fields(g, saved);
                 return err.code;
             }
             hipEventRecord(e1, g->stream);
@@ -1590,12 +1683,38 @@ tw_status autotune(tw_graph* g, const tw_walk_params* p, int64_t sample, int32_t
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    g->auto_dispatch = pick.dispatch;
-    g->auto_bpc = pick.bpc;
+    set_tuning_fields(g, pick);
     if (best) {
         best[0] = pick.dispatch;
-        best[1] = pick.bpc;
+        best[1] = pick.queue_bpc;
     }
+    return TW_OK;
+}
+
+tw_tuning get_tuning(const tw_graph* g) {
+    return tw_tuning{g->auto_dispatch ? g->auto_dispatch : TW_DISPATCH_FULL_WALK, g->auto_bpc,
+                     g->coop_regroup, g->coop_wave_min, (int32_t)g->coop_panel, g->coop_sync};
+}
+
+void set_tuning_fields(tw_graph* g, const tw_tuning& t) {
+    g->auto_dispatch = t.dispatch;
+    g->auto_bpc = t.queue_bpc;
+    g->coop_regroup = t.coop_regroup;
+    g->coop_wave_min = t.coop_wave_min;
+    g->coop_panel = (uint32_t)t.coop_panel;
+    g->coop_sync = t.coop_sync;
+}
+
+tw_status set_tuning(tw_graph* g, const tw_tuning* t, Error& err) {
+    if (!t || t->dispatch < TW_DISPATCH_FULL_WALK || t->dispatch > TW_DISPATCH_QUEUE ||
+        t->queue_bpc < 0 || t->coop_regroup < 0 || t->coop_regroup > 1 || t->coop_wave_min < 1 ||
+        t->coop_wave_min > 64 || t->coop_panel < 64 || t->coop_panel > 8192 ||
+        t->coop_panel % 64 != 0 || t->coop_sync < 1 || t->coop_sync > 64) {
+        err = Error{TW_EINVAL, "set_tuning: dispatch FULL_WALK..QUEUE, queue_bpc >= 0, regroup 0 or "
+                               "1, wave_min 1..64, panel 64..8192 in steps of 64, sync 1..64"};
+        return err.code;
+    }
+    set_tuning_fields(g, *t);
     return TW_OK;
 }
 

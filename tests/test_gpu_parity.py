@@ -293,6 +293,51 @@ def test_dispatches_agree_on_lengths_and_edge_cases(L):
     g.close()
 
 
+COOP_TUNINGS = [
+    # regroup, wave_min, panel, sync
+    (0, 64, 4096, 1), (0, 1, 64, 1), (0, 16, 8192, 4), (0, 40, 2048, 7),
+    (1, 64, 2048, 1), (1, 8, 512, 4), (1, 1, 8192, 64),
+]
+
+
+@pytest.mark.parametrize("ci", range(len(COOP_TUNINGS)),
+                         ids=["-".join(map(str, c)) for c in COOP_TUNINGS])
+@pytest.mark.parametrize("hop", ["linear", "node2vec"])
+def test_coop_tunings_equal_full_walk(ci, hop):
+    # every setting of the cooperative dispatch's tunables gives the walks
+    # of the full-walk kernel byte for byte (the RNG is keyed by walk and
+    # hop), on a hub-heavy graph whose hubs engage the wavefront and
+    # workgroup tiers; uniform walks also against the oracle
+    torch, tw = gpu_or_skip()
+    regroup, wave_min, panel, sync = COOP_TUNINGS[ci]
+    w = synth.scaled("mixed", 4000, 200_000)
+    spec = w["stream"]
+    s, d, t = spec.all()
+    g = tw.Graph(4000, directed=spec.directed)
+    g.ingest_batch(*to_dev(torch, s, d, t))
+    tau = 0.1 * float(t.max() - t.min())
+    kw = dict(hop_bias=hop, hop_tau=tau, p=0.5, q=2.0, start_bias="linear", seed=21,
+              walk_id_base=3)
+    ref = [x.cpu().numpy() for x in g.sample_walks(20_000, 30, dispatch="full_walk", **kw)]
+    g.set_tuning("coop", coop_regroup=regroup, coop_wave_min=wave_min, coop_panel=panel,
+                 coop_sync=sync)
+    assert g.tuning()["coop_sync"] == sync
+    got = [x.cpu().numpy() for x in g.sample_walks(20_000, 30, dispatch="auto", **kw)]
+    g.sync()
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+    if hop == "linear":
+        og = oracle.OracleGraph(4000, directed=spec.directed)
+        og.ingest_batch(s, d, t)
+        idx = np.arange(0, 20_000, 7)
+        r = og.sample_walks(20_000, 30, walk_idx=idx, with_margin=True,
+                            **{k: v for k, v in kw.items() if k not in ("p", "q", "hop_tau")})
+        assert compare_walks(tuple(x[idx] for x in got), r, exact=True) == (len(idx), 0)
+    with pytest.raises(tw.TwError):
+        g.set_tuning("coop", coop_panel=100)  # not a multiple of 64
+    g.close()
+
+
 @pytest.mark.parametrize("sorted_arrivals", [True, False])
 def test_long_stream_compactions(sorted_arrivals):
     # many batches under a short window: the window's start moves through
@@ -406,13 +451,17 @@ def test_sorted_batches_continuing_the_last_timestamp(directed):
     g.close()
 
 
-def test_weight_walks_follow_the_window():
+@pytest.mark.parametrize("at_ingest", [False, True])
+def test_weight_walks_follow_the_window(at_ingest):
     # the weight-based picker's cumulative weights are rebuilt after every
-    # change of the window (ingest, eviction) and of the time scale
+    # change of the window (ingest, eviction) and of the time scale, either
+    # by the first weight-based walk or by the ingest itself
     torch, tw = gpu_or_skip()
     rng = np.random.default_rng(41)
     V, window = 301, 6_000
     g = tw.Graph(V, window=window)
+    if at_ingest:
+        g.set_ingest_weights(300.0)
     og = oracle.OracleGraph(V, window=window)
     t0 = 0
     for b in range(12):
@@ -432,8 +481,9 @@ def test_weight_walks_follow_the_window():
                                 with_margin=True)
             same, boundary = compare_walks(
                 (nodes.cpu().numpy(), ts.cpu().numpy(), lens.cpu().numpy()), r, False,
-                label=f"weight window batch {b} tau {tau}", kind="weight")
+                label=f"weight window batch {b} tau {tau} at ingest {at_ingest}", kind="weight")
             assert boundary <= 2, (b, tau, same, boundary)
+    g.set_ingest_weights(None)
     g.close()
 
 
@@ -532,6 +582,34 @@ def test_fresh_graph_reports_no_error():
         g.sync()
         g.ingest_batch(s, d, t + 100)
         g.close()
+
+
+def test_walk_errors_reported_by_the_next_ingest():
+    # a walk's out-of-range start node is reported by the next ingest, which
+    # then ingests nothing; an eviction with nothing to evict neither
+    # synchronises nor reports it
+    torch, tw = gpu_or_skip()
+    w = synth.scaled("tiny", 500, 6000)
+    s, d, t = w["stream"].all()
+    half = len(s) // 2
+    g = tw.Graph(500, window=int(t.max()) // 2)
+    og = oracle.OracleGraph(500, window=int(t.max()) // 2)
+    order = np.argsort(t, kind="stable")
+    s, d, t = s[order], d[order], t[order]
+    g.ingest_batch(*to_dev(torch, s[:half], d[:half], t[:half]))
+    og.ingest_batch(s[:half], d[:half], t[:half])
+    bad = to_dev(torch, np.array([3, 900], np.int32))[0]
+    g.sample_walks(2, 4, start_mode="node", start_nodes=bad)
+    assert g.evict_before(int(t[0]) - 1) == 0  # nothing to evict: no report
+    batch = to_dev(torch, s[half:], d[half:], t[half:])
+    with pytest.raises(tw.TwError) as ei:
+        g.ingest_batch(*batch)
+    assert ei.value.code == tw.TW_ERANGE
+    _views_equal(g, og)  # nothing ingested
+    assert g.ingest_batch(*batch) == og.ingest_batch(s[half:], d[half:], t[half:])
+    _views_equal(g, og)
+    g.sync()
+    g.close()
 
 
 def test_deep_fence_hub():

@@ -89,7 +89,9 @@ def test_server_admission_by_memory_and_errors():
     g = tw.Graph(V)
     W, L = 10_000, 20
     one = 4 * W * L + 8 * W * L + 4 * W + 3 * 256  # one request's outputs, aligned
-    srv = tw.Server(g, arena_bytes=one + one // 2, max_walks_per_launch=1 << 20)
+    # a fixed arena: admission by the arena alone
+    srv = tw.Server(g, arena_bytes=one + one // 2, max_walks_per_launch=1 << 20,
+                    hbm_reserve_bytes=-1)
     srv.wait(srv.ingest(*dev))
     a = srv.submit(W, L, hop_bias="linear", seed=1)
     b = srv.submit(W, L, hop_bias="linear", seed=2)
@@ -119,6 +121,50 @@ def test_server_admission_by_memory_and_errors():
     g2.sync()
     g.close()
     g2.close()
+
+
+def test_server_admission_by_free_device_memory():
+    # the same two requests with a reserve the device can keep: the second
+    # gets an arena chunk of its own instead of waiting; with a reserve no
+    # device has, it waits for the first one's release
+    torch, tw = gpu_or_skip()
+    V = 3000
+    (s, d, t), = _stream(V, 1, 30_000)
+    dev = to_dev(torch, s, d, t)
+    torch.cuda.synchronize()
+    W, L = 10_000, 20
+    one = 4 * W * L + 8 * W * L + 4 * W + 3 * 256
+    for reserve, grows in ((1 << 30, True), (1 << 50, False)):
+        g = tw.Graph(V)
+        srv = tw.Server(g, arena_bytes=one + one // 2, max_walks_per_launch=1 << 20,
+                        hbm_reserve_bytes=reserve)
+        srv.wait(srv.ingest(*dev))
+        a = srv.submit(W, L, hop_bias="linear", seed=1)
+        b = srv.submit(W, L, hop_bias="linear", seed=2)
+        c = srv.submit(3 * W, L, hop_bias="uniform", seed=3)  # larger than the first chunk
+        assert srv.wait(a) is not None
+        if grows:
+            assert srv.wait(b, timeout_s=30.0) is not None
+            assert srv.wait(c, timeout_s=30.0) is not None
+            st = srv.stats()
+            assert st["arena_chunks_added"] >= 2 and st["arena_bytes"] > one + one // 2
+        else:
+            assert srv.wait(b, timeout_s=0.3) is None
+            srv.release(a)
+            assert srv.wait(b, timeout_s=30.0) is not None
+            assert srv.wait(c, timeout_s=0.3) is None  # fits no chunk, none added
+            assert srv.stats()["arena_chunks_added"] == 0
+        got = {k: srv.result(k) for k in (b,) + ((a, c) if grows else ())}
+        srv.close()
+        g.close()
+        g2 = tw.Graph(V)
+        g2.ingest_batch(*dev)
+        _same(got[b], g2.sample_walks(W, L, hop_bias="linear", seed=2))
+        if grows:
+            _same(got[a], g2.sample_walks(W, L, hop_bias="linear", seed=1))
+            _same(got[c], g2.sample_walks(3 * W, L, hop_bias="uniform", seed=3))
+        g2.sync()
+        g2.close()
 
 
 def test_server_concurrent_submitters():
