@@ -15,8 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build", "tw")
 LIB = os.path.join(HERE, "libtw.so")
-SOURCES = ["prim.hip", "index.hip", "nodeview.hip", "weights.hip", "walk.hip", "serve.hip",
-           "capi.hip"]
+SOURCES = ["prim.hip", "index.hip", "nodeview.hip", "weights.hip", "adjacency.hip", "walk.hip",
+           "serve.hip", "capi.hip"]
 # roofline probes for the benchmark, a separate library
 PROBE_LIB = os.path.join(HERE, "libtw_probe.so")
 PROBE_SOURCES = ["probe.hip"]

@@ -303,25 +303,6 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
-// node2vec adjacency keys (source << 32 | destination) of the window
-__global__ void k_adj_keys(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
-                           int64_t m, uint64_t* __restrict__ keys) {
-    int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
-    if (i < m) keys[i] = ((uint64_t)(uint32_t)src[i] << 32) | (uint32_t)dst[i];
-}
-
-// destinations in (source, destination) order and each source's range
-__global__ void k_adj_extract(const uint64_t* __restrict__ keys, int64_t m,
-                              int32_t* __restrict__ adj, uint2* __restrict__ rng) {
-    int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
-    if (i >= m) return;
-    const uint64_t k = keys[i];
-    adj[i] = (int32_t)(uint32_t)k;
-    const uint32_t v = (uint32_t)(k >> 32);
-    if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != v) rng[v].x = (uint32_t)i;
-    if (i == m - 1 || (uint32_t)(keys[i + 1] >> 32) != v) rng[v].y = (uint32_t)(i + 1);
-}
-
 __global__ void k_widen(const uint32_t* __restrict__ in, int64_t n, int64_t* __restrict__ out,
                         int64_t minus) {
     int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
@@ -656,6 +637,11 @@ tw_status ingest_apply(tw_graph* g, const IngestPlan& P, tw_ingest_info* info, E
     // leaves the graph marked unusable (every later call refuses it).
     g->broken = true;
     const int64_t m_old = g->m;
+    // the node2vec pairs: the evicted prefix of the window down, the kept
+    // batch records up (both still where the plan found them)
+    if (adj_update(g, g->e_src.as<int32_t>() + g->e_base, g->e_dst.as<int32_t>() + g->e_base,
+                   evicted, q_src, q_dst, kept, err) != TW_OK)
+        return err.code;
     if (P.evict_all) {
         const int64_t jobs = g->T;  // the batch's jobs, collected by the plan
         if (nv_reset(g, err) != TW_OK) return err.code;
@@ -826,6 +812,9 @@ tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& e
     if (ev > 0) {
         const int64_t m_old = g->m, gg_old = g->Gg;
         g->broken = true;  // cleared when the eviction completes
+        if (adj_update(g, g->e_src.as<int32_t>() + g->e_base, g->e_dst.as<int32_t>() + g->e_base,
+                       ev, nullptr, nullptr, 0, err) != TW_OK)
+            return err.code;
         if (ev == m_old) {
             if (nv_reset(g, err) != TW_OK) return err.code;
         } else if (nv_collect(g, nullptr, nullptr, nullptr, 0, 0, 0, g->e_base, ev, err) !=
@@ -965,26 +954,6 @@ tw_status init_empty(tw_graph* g, Error& err) {
     if (nv_reset(g, err) != TW_OK) return err.code;
     if (build_ts_groups(g, err) != TW_OK) return err.code;
     return finish_ts(g, true, 0, 0, err);
-}
-
-tw_status build_adjacency(tw_graph* g, Error& err) {
-    if (g->adj_ready) return TW_OK;
-    hipStream_t s = g->stream;
-    const int64_t m = g->m;
-    TW_HIP(ensure(g->adj, sizeof(int32_t) * (m + 1), g->stream));
-    TW_HIP(ensure(g->adj_rng, sizeof(uint2) * g->V, g->stream));
-    TW_HIP(ensure(g->b_keys, sizeof(uint64_t) * (m + 1), g->stream));
-    uint64_t* keys = g->b_keys.as<uint64_t>();
-    hipLaunchKernelGGL(k_adj_keys, grid_for(m), dim3(T), 0, s, g->e_src.as<int32_t>() + g->e_base,
-                       g->e_dst.as<int32_t>() + g->e_base, m, keys);
-    int vb = bits_for((uint64_t)(g->V - 1));
-    TW_HIP(radix_sort_u64(keys, nullptr, m, 0, vb, g->ws, s));
-    TW_HIP(radix_sort_u64(keys, nullptr, m, 32, 32 + vb, g->ws, s));
-    hipLaunchKernelGGL(k_adj_extract, grid_for(m), dim3(T), 0, s, keys, m, g->adj.as<int32_t>(),
-                       g->adj_rng.as<uint2>());
-    TW_HIP(hipGetLastError());
-    g->adj_ready = true;
-    return TW_OK;
 }
 
 tw_status export_views(tw_graph* g, int32_t* src, int32_t* dst, int64_t* ts, int64_t* g_ts,

@@ -900,7 +900,6 @@ tw_status nv_reset(tw_graph* g, Error& err) {
     g->st_jobs = g->st_written = g->st_new_slots = g->st_full = 0;
     ++g->pool_gen;  // every segment is void
     g->T = 0;
-    g->adj_ready = false;
     g->w_ready = false;
     return TW_OK;
 }
@@ -1155,7 +1154,6 @@ tw_status nv_apply(tw_graph* g, bool evicting, int64_t cut, Error& err) {
     g->st_jobs = g->st_written = g->st_new_slots = g->st_full = 0;
     if (g->T == 0) return TW_OK;
     if (run_jobs(g, g->T, evicting, cut, false, err) != TW_OK) return err.code;
-    g->adj_ready = false;
     g->w_ready = false;
     return TW_OK;
 }

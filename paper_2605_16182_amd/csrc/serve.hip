@@ -128,12 +128,9 @@ struct tw_server {
     hipStream_t s_ing = nullptr;   // the ingest thread's stream
     hipEvent_t ev_walks = nullptr;    // every walk launch enqueued before an ingest
     hipEvent_t ev_applied = nullptr;  // the last ingest's index update
-    hipEvent_t ev_scratch = nullptr;  // walk-side use of the ingest workspaces
-    bool scratch_pending = false;     // ev_scratch recorded since the last ingest began
     bool applied_pending = false;     // the next walk launch waits for ev_applied
     bool ing_busy = false;            // an ingest batch is with the ingest thread
     bool ing_taken = false;           // ... and the thread has started it
-    bool ing_wait_scratch = false;
     uint64_t ing_id = 0;
     bool ing_stop = false;
     std::thread ingester;
@@ -261,7 +258,6 @@ void ingest_loop(tw_server* S) {
         const int32_t* dst = it.dst;
         const int64_t* its = it.its;
         const int64_t n = it.n;
-        const bool wait_scratch = S->ing_wait_scratch;
         lk.unlock();
         tw_graph* g = S->g;
         tw::Error e{TW_OK, ""};
@@ -270,10 +266,7 @@ void ingest_loop(tw_server* S) {
         // is this thread's until it hands the batch back
         g->stream = S->s_ing;
         if (g->rev) g->rev->stream = S->s_ing;
-        tw_status st = TW_OK;
-        if (wait_scratch && hipStreamWaitEvent(S->s_ing, S->ev_scratch, 0) != hipSuccess)
-            st = TW_EDEVICE;
-        if (st == TW_OK) st = tw::ingest_views(g, src, dst, its, n, &info, e, S->ev_walks);
+        tw_status st = tw::ingest_views(g, src, dst, its, n, &info, e, S->ev_walks);
         if (hipEventRecord(S->ev_applied, S->s_ing) != hipSuccess && st == TW_OK) st = TW_EDEVICE;
         g->stream = S->s_walk;
         if (g->rev) g->rev->stream = S->s_walk;
@@ -318,8 +311,6 @@ void worker_loop(tw_server* S) {
                     S->ing_busy = true;
                     S->ing_taken = false;
                     S->ing_id = id;
-                    S->ing_wait_scratch = S->scratch_pending;
-                    S->scratch_pending = false;
                     S->cv_ing.notify_one();
                 }
                 progressed = true;
@@ -384,7 +375,6 @@ void worker_loop(tw_server* S) {
                 // the walks of a new epoch start after its index update
                 if (wait_applied && hipStreamWaitEvent(s, S->ev_applied, 0) != hipSuccess)
                     st = TW_EDEVICE;
-                const bool adj_before = S->g->adj_ready;
                 // an index whose update failed midway serves nothing
                 if (st == TW_OK && S->g->broken) st = TW_EDEVICE;
                 if (st == TW_OK) {
@@ -393,11 +383,6 @@ void worker_loop(tw_server* S) {
                     st = tw::serve_launch(S->g, reqs.data(), (int)reqs.size(), dt, ht,
                                           S->d_hops + slot, de, e);
                 }
-                // a node2vec adjacency built here used the ingest workspaces:
-                // the next batch is planned after it
-                const bool built = !adj_before && S->g->adj_ready;
-                if (st == TW_OK && built && hipEventRecord(S->ev_scratch, s) != hipSuccess)
-                    st = TW_EDEVICE;
                 if (st == TW_OK &&
                     (hipMemcpyAsync(S->h_hops + slot, S->d_hops + slot, sizeof(unsigned long long),
                                     hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -406,7 +391,6 @@ void worker_loop(tw_server* S) {
                      hipEventRecord(S->ev[slot], s) != hipSuccess))
                     st = TW_EDEVICE;
                 lk.lock();
-                if (built) S->scratch_pending = true;
                 if (st != TW_OK) {
                     S->slot_busy[slot] = false;
                     finish_failed(S, ids, st);
@@ -472,7 +456,7 @@ tw_status server_create(tw_graph* g, const tw_server_config* cfg, tw_server** ou
         if (S->h_err) (void)hipHostFree(S->h_err);
         for (hipEvent_t& e : S->ev)
             if (e) (void)hipEventDestroy(e);
-        for (hipEvent_t e : {S->ev_walks, S->ev_applied, S->ev_scratch})
+        for (hipEvent_t e : {S->ev_walks, S->ev_applied})
             if (e) (void)hipEventDestroy(e);
         if (S->s_ing) (void)hipStreamDestroy(S->s_ing);
         delete S;
@@ -499,7 +483,7 @@ tw_status server_create(tw_graph* g, const tw_server_config* cfg, tw_server** ou
     }
     bool ok = true;
     for (hipEvent_t& e : S->ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
-    for (hipEvent_t* e : {&S->ev_walks, &S->ev_applied, &S->ev_scratch})
+    for (hipEvent_t* e : {&S->ev_walks, &S->ev_applied})
         ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
     // the ingest stream keeps the default priority, like the graph's
     ok = ok && hipStreamCreateWithFlags(&S->s_ing, hipStreamNonBlocking) == hipSuccess;
@@ -701,7 +685,7 @@ tw_status server_destroy(tw_server* S, Error& err) {
     (void)hipHostFree(S->h_hops);
     (void)hipHostFree(S->h_err);
     for (hipEvent_t e : S->ev) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {S->ev_walks, S->ev_applied, S->ev_scratch}) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {S->ev_walks, S->ev_applied}) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(S->s_ing);
     delete S;
     (void)err;

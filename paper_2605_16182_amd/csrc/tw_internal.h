@@ -128,6 +128,27 @@ __host__ __device__ inline uint64_t seg_groups(uint32_t code) {
     return (uint64_t)FENCE_FAN << code;
 }
 
+// node2vec adjacency: an open-addressing table (linear probing) of the
+// window's (source, destination) pairs, each with its record count; a pair
+// whose count fell to 0 keeps its slot until the table is rebuilt.
+struct __align__(16) AdjSlot {
+    uint64_t key;  // source << 32 | destination, or ADJ_EMPTY
+    uint32_t cnt;
+    uint32_t pad;
+};
+constexpr uint64_t ADJ_EMPTY = ~0ull;
+
+__host__ __device__ inline uint64_t adj_key(int32_t src, int32_t dst) {
+    return ((uint64_t)(uint32_t)src << 32) | (uint32_t)dst;
+}
+
+// the SplitMix64 output mix (Steele, Lea, Flood, OOPSLA 2014)
+__host__ __device__ inline uint64_t adj_hash(uint64_t k) {
+    k = (k ^ (k >> 30)) * 0xBF58476D1CE4E5B9ull;
+    k = (k ^ (k >> 27)) * 0x94D049BB133111EBull;
+    return k ^ (k >> 31);
+}
+
 // Slots of the graph's device scalar buffer (256 bytes): u32 indices
 // (SLOT_U32_*) and int64 indices (SLOT_I64_*, byte offset 8 k).
 constexpr int SLOT_I64_MINMAX = 0;     // batch min / max timestamp (ordered u64) in [0], [1]
@@ -303,7 +324,12 @@ struct tw_graph {
     // counters of the last update: jobs, edges written, edge slots of new
     // segments, whether every active node was rewritten
     int64_t st_jobs = 0, st_written = 0, st_new_slots = 0, st_full = 0;
-    tw::DevBuf adj, adj_rng;           // node2vec: per-node sorted destinations
+    // node2vec: the pair table (adj_mask + 1 slots, a power of two), valid
+    // for the current window while adj_ready; adj_used bounds the slots
+    // holding a key (the pairs inserted since the build, with repeats)
+    tw::DevBuf adj_tab;
+    uint64_t adj_mask = 0;
+    int64_t adj_used = 0;
     bool adj_ready = false;
     // weight-based picker: cumulative group weights (group pool slots) for
     // the time scale w_scale, valid while w_ready
@@ -350,7 +376,7 @@ struct tw_graph {
                 &n_dst, &n_ts, &ng, &fence, &an_dst, &an_ts, &ang, &afence,
                 &rec, &seg, &touched, &bs_src, &bs_dst, &bs_ts, &q_src, &q_dst, &q_ts,
                 &c_node, &c_bf, &c_be, &jobs, &j_cnt, &j_off, &j_re, &j_rg, &j_rf, &j_fw,
-                &o_flag, &o_rank, &o_tf, &f_tf, &adj, &adj_rng,
+                &o_flag, &o_rank, &o_tf, &f_tf, &adj_tab,
                 &c_node0, &c_walk0, &c_t0, &c_node1, &c_walk1, &c_t1, &c_node2, &c_walk2,
                 &c_t2, &c_prev, &c_flags, &c_pos, &wq,
                 &b_src, &b_dst, &b_ts, &b_keys, &b_vals, &b_flags, &flags, &idx, &v_flags,
@@ -434,7 +460,13 @@ tw_status ingest_views(tw_graph* g, const int32_t* src, const int32_t* dst, cons
                        int64_t n, tw_ingest_info* info, Error& err,
                        hipEvent_t before_apply = nullptr, bool walk_flags = false);
 tw_status evict_views(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& err);
+// adjacency.hip: the node2vec pair table of the window, built when first
+// needed; adj_update keeps it current at an ingest or eviction (the evicted
+// window records counted down, the kept batch records up) or drops it when
+// it would fill past three quarters (the next node2vec walk rebuilds it)
 tw_status build_adjacency(tw_graph* g, Error& err);
+tw_status adj_update(tw_graph* g, const int32_t* ev_src, const int32_t* ev_dst, int64_t ev_n,
+                     const int32_t* add_src, const int32_t* add_dst, int64_t add_n, Error& err);
 // The graph whose node view holds the in-edges (backward walks): g itself
 // when undirected, else g->rev, created from g's window on first use and
 // fed every later ingest and eviction.
@@ -490,7 +522,8 @@ size_t serve_table_bytes(int n);
 // Enqueue the padding and the walks of n requests (1..1024) in one launch;
 // *d_hops accumulates the launch's hops; request r's error words are
 // d_err[2 r] (a start node out of range) and d_err[2 r + 1] (node2vec
-// trial-cap hits), which the caller clears before the launch.
+// trial-cap hits), which the caller clears before the launch (d_err holds
+// at least 4 words). One large request runs the full-walk kernel.
 tw_status serve_launch(tw_graph* g, const ServeReq* reqs, int n, void* d_table, void* h_table,
                        unsigned long long* d_hops, uint32_t* d_err, Error& err);
 

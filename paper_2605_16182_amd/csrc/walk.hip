@@ -43,8 +43,8 @@ struct WalkArgs {
     const GroupRec* ng;
     const NodeRec* rec;
     const uint32_t* fence;
-    const int32_t* adj;
-    const uint2* adj_rng;
+    const AdjSlot* adj_tab;  // node2vec pair table (adj_mask + 1 slots)
+    uint64_t adj_mask;
     const double* cw;  // cumulative group weights (weight-based picker)
     int32_t V;
     // parameters
@@ -183,7 +183,6 @@ __device__ __forceinline__ bool hop_pick(const WalkArgs& a, const HopBias& hb, u
         nx = p.dst;
         return true;
     }
-    const uint2 rp = a.adj_rng[prev];  // prev has edges: prev -> cur is one
     for (uint32_t trial = 0; trial < N2V_MAX_TRIALS; ++trial) {
         const Draw d = philox(id, hop, trial, seed);
         p = pick_node(a.ng, a.n_dst, a.n_ts, gc, r.ge, r.ee, TW_EXPONENTIAL, hb.tau, r.t_last,
@@ -191,7 +190,7 @@ __device__ __forceinline__ bool hop_pick(const WalkArgs& a, const HopBias& hb, u
         nx = p.dst;
         double beta;
         if (nx == prev) beta = hb.inv_p;
-        else if (sorted_contains(a.adj, rp.x, rp.y, nx)) beta = 1.0;
+        else if (adj_has(a.adj_tab, a.adj_mask, prev, nx)) beta = 1.0;
         else beta = hb.inv_q;
         if (unit_closed_open(d.x2) * hb.beta_max < beta) return true;
     }
@@ -353,15 +352,14 @@ __device__ __forceinline__ bool back_pick(const WalkArgs& a, const HopBias& hb, 
         nx = p.dst;
         return true;
     }
-    // in the in-view, prev -> cur is an edge: prev has an adjacency range
-    const uint2 rp = a.adj_rng[prev];
+    // the edge candidate -> prev of the graph is prev -> candidate here
     for (uint32_t trial = 0; trial < N2V_MAX_TRIALS; ++trial) {
         const Draw d = philox(id, hop, trial, seed);
         p = pick_node(a.ng, a.n_dst, a.n_ts, r.gb, hi, end, TW_EXPONENTIAL, hb.tau, t_hi, d, true);
         nx = p.dst;
         double beta;
         if (nx == prev) beta = hb.inv_p;
-        else if (sorted_contains(a.adj, rp.x, rp.y, nx)) beta = 1.0;
+        else if (adj_has(a.adj_tab, a.adj_mask, prev, nx)) beta = 1.0;
         else beta = hb.inv_q;
         if (unit_closed_open(d.x2) * hb.beta_max < beta) return true;
     }
@@ -1084,10 +1082,11 @@ tw_status fill_args(tw_graph* g, int64_t num_walks, int32_t L, const tw_bias& sb
     a.n_dst = g->n_dst.as<int32_t>();
     a.n_ts = g->n_ts.as<int64_t>();
     a.ng = g->ng.as<GroupRec>();
-    a.adj_rng = g->adj_rng.as<uint2>();
+
     a.rec = g->rec.as<NodeRec>();
     a.fence = g->fence.as<uint32_t>();
-    a.adj = g->adj.as<int32_t>();
+    a.adj_tab = g->adj_tab.as<AdjSlot>();
+    a.adj_mask = g->adj_mask;
     a.cw = g->cw.as<double>();
     a.V = g->V;
     a.num_walks = num_walks;
@@ -1545,11 +1544,61 @@ tw_status check_walk_params(const tw_walk_params* p, Error& err) {
 
 size_t serve_table_bytes(int n) { return sizeof(ServeReqDev) * (size_t)std::max(n, 1); }
 
+// hops of n walks from their lengths, added to *out
+__global__ void k_sum_hops(const int32_t* __restrict__ len, int64_t n,
+                           unsigned long long* out) {
+    uint64_t h = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        h += len[i] > 1 ? (uint64_t)(len[i] - 1) : 0;
+    for (int off = 32; off > 0; off >>= 1) h += __shfl_down(h, off, 64);
+    if ((threadIdx.x & 63) == 0 && h) atomicAdd(out, (unsigned long long)h);
+}
+
+// error words of a one-request launch run by the full-walk kernel: it
+// counts trial-cap hits in word 2, the request's layout has them in word 1
+__global__ void k_err_words(uint32_t* e, int finish) {
+    if (threadIdx.x == 0) {
+        if (finish) {
+            e[1] = e[2];
+            e[2] = 0u;
+        } else {
+            e[2] = 0u;
+        }
+    }
+}
+
+// Requests of at least this many walks launched alone run the full-walk
+// kernel on their own rows (the fastest dispatch for one rectangular batch).
+constexpr int64_t SERVE_FULL_MIN = 1 << 16;
+
 tw_status serve_launch(tw_graph* g, const ServeReq* reqs, int n, void* d_table, void* h_table,
                        unsigned long long* d_hops, uint32_t* d_err, Error& err) {
     if (n < 1 || n > SERVE_MAX_REQ) {
         err = Error{TW_EINVAL, "serve: 1..1024 requests per launch"};
         return err.code;
+    }
+    if (n == 1 && reqs[0].count >= SERVE_FULL_MIN && reqs[0].hop.kind != TW_WEIGHT) {
+        const ServeReq& q = reqs[0];
+        WalkArgs a;
+        if (fill_args(g, q.count, q.max_len, q.start, q.start_mode, q.start_nodes, q.seed, q.base,
+                      q.hop.kind == TW_NODE2VEC, NAN, q.nodes, q.ts, q.len, a, err) != TW_OK)
+            return err.code;
+        if (own_rows(a)) {
+            a.hop = make_hop_bias(q.hop);
+            a.err = d_err;  // [0] start node out of range, [2] trial-cap hits
+            hipLaunchKernelGGL(k_err_words, dim3(1), dim3(64), 0, g->stream, d_err, 0);
+            const dim3 grid((unsigned)ceil_div(q.count, WALK_THREADS));
+            with_kinds(a.hop.kind, a.start_kind, [&](auto h, auto st) {
+                hipLaunchKernelGGL((k_walk_full<decltype(h)::value, decltype(st)::value, true>),
+                                   grid, dim3(WALK_THREADS), 0, g->stream, a);
+            });
+            hipLaunchKernelGGL(k_err_words, dim3(1), dim3(64), 0, g->stream, d_err, 1);
+            hipLaunchKernelGGL(k_sum_hops, dim3(1024), dim3(256), 0, g->stream, q.len, q.count,
+                               d_hops);
+            TW_HIP(hipGetLastError());
+            return TW_OK;
+        }
     }
     bool n2v = false;
     int64_t total = 0;

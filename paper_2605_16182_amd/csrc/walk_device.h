@@ -195,42 +195,17 @@ __device__ __forceinline__ uint32_t fence_search(const GroupRec* __restrict__ ng
     return r.gb;  // not reached
 }
 
-// is w among the sorted values adj[lo, hi)? Node ids are spread about
-// uniformly over [0, V) (the inputs map ranks to ids by a bijection), so a
-// node's sorted destinations are found by interpolation: each probe lands
-// where w's value predicts between the two bracketing values, about
-// log log n dependent reads for n destinations, against log n for a binary
-// search; after a few probes the rest of the bracket is bisected, so the
-// worst case stays logarithmic. The answer does not depend on the path.
-__device__ __forceinline__ bool sorted_contains(const int32_t* __restrict__ adj, uint32_t lo,
-                                                uint32_t hi, int32_t w) {
-    if (lo >= hi) return false;
-    // bracket (lo, hi) with known values va = adj[lo] < w < vb = adj[hi]
-    hi -= 1;
-    const int32_t va0 = adj[lo], vb0 = adj[hi];
-    if (w <= va0 || w >= vb0) return w == va0 || w == vb0;
-    int64_t va = va0, vb = vb0;
-    for (int k = 0; k < 4 && hi - lo > 8; ++k) {
-        const double f = (double)((int64_t)w - va) / (double)(vb - va);
-        uint32_t mid = lo + 1 + (uint32_t)(f * (double)(hi - lo - 1));
-        if (mid >= hi) mid = hi - 1;
-        const int32_t v = adj[mid];
-        if (v == w) return true;
-        if (v < w) {
-            lo = mid;
-            va = v;
-        } else {
-            hi = mid;
-            vb = v;
-        }
-    }
-    // bisect the open interval (lo, hi)
-    uint32_t a = lo + 1, b = hi;
-    while (a < b) {
-        const uint32_t mid = a + ((b - a) >> 1);
-        const int32_t v = adj[mid];
-        if (v == w) return true;
-        if (v < w) a = mid + 1; else b = mid;
+// Does the window hold an edge src -> dst (node2vec's adjacency test)? One
+// probe sequence of the pair table: the pair's slot (its count > 0 while
+// records of the pair are in the window) or an empty slot first.
+__device__ __forceinline__ bool adj_has(const AdjSlot* __restrict__ tab, uint64_t mask,
+                                        int32_t src, int32_t dst) {
+    const uint64_t k = adj_key(src, dst);
+    uint64_t j = adj_hash(k) & mask;
+    for (uint64_t probe = 0; probe <= mask; ++probe, j = (j + 1) & mask) {
+        const AdjSlot e = tab[j];
+        if (e.key == k) return e.cnt > 0;
+        if (e.key == ADJ_EMPTY) return false;
     }
     return false;
 }

@@ -233,6 +233,42 @@ def test_windowed_stream_walks_parity():
     g.close()
 
 
+@pytest.mark.parametrize("directed", [True, False])
+def test_node2vec_pairs_follow_the_window(directed):
+    # node2vec's pair table is built by the first node2vec walk and then kept
+    # current by every ingest and eviction (unsorted batches, late drops,
+    # explicit evictions); a small window on a few nodes makes pairs leave
+    # and come back, and fills the table past three quarters so it is also
+    # rebuilt; every batch's node2vec walks against the oracle's
+    from gpu_util import compare_walks
+    torch, tw = gpu_or_skip()
+    rng = np.random.default_rng(61)
+    V, window = 40, 3_000
+    g = tw.Graph(V, directed=directed, window=window)
+    og = oracle.OracleGraph(V, directed=directed, window=window)
+    t0 = 0
+    for b in range(16):
+        n = int(rng.integers(100, 400))
+        s = rng.integers(0, V, n).astype(np.int32)
+        d = rng.integers(0, V, n).astype(np.int32)
+        t = (t0 + rng.integers(-300, 1000, n)).astype(np.int64)
+        t0 += 1000
+        assert g.ingest_batch(*to_dev(torch, s, d, t)) == og.ingest_batch(s, d, t), b
+        if b % 5 == 3:
+            cut = t0 - 1500
+            assert g.evict_before(cut) == og.evict_before(cut)
+        for p_, q_ in ((0.5, 2.0), (2.0, 0.25)):
+            kw = dict(hop_bias="node2vec", hop_tau=200.0, p=p_, q=q_, seed=b)
+            nodes, ts, lens = g.sample_walks(3000, 12, **kw)
+            g.sync()
+            r = og.sample_walks(3000, 12, with_margin=True, **kw)
+            same, boundary = compare_walks(
+                (nodes.cpu().numpy(), ts.cpu().numpy(), lens.cpu().numpy()), r, False,
+                label=f"node2vec pairs batch {b} directed={directed}", kind="node2vec")
+            assert boundary <= 2, (b, same, boundary)
+    g.close()
+
+
 @pytest.mark.parametrize("groups", [1, 15, 16, 17, 255, 256, 257, 4097, 70_001])
 def test_fence_search_depths(groups):
     # one hub whose out-edges all loop back to itself, so every hop searches

@@ -167,6 +167,53 @@ def test_server_admission_by_free_device_memory():
         g2.close()
 
 
+def test_server_large_requests_alone():
+    # a request of 2^16 walks or more launched alone runs the full-walk
+    # kernel on its own rows (rows of a multiple of 4 slots): its walks, hop
+    # count and error words must match the plain walks and the other path
+    torch, tw = gpu_or_skip()
+    V = 4000
+    (s, d, t), = _stream(V, 1, 60_000)
+    dev = to_dev(torch, s, d, t)
+    tau = 0.1 * float(t[-1] - t[0])
+    starts_np = synth.start_nodes(9, 70_000, V)
+    starts_np[123] = V + 7  # out of range: the request fails with TW_ERANGE
+    starts = to_dev(torch, starts_np)[0]
+    torch.cuda.synchronize()
+    g = tw.Graph(V)
+    # one request per launch: the next one would pass the walk cap
+    srv = tw.Server(g, arena_bytes=1 << 30, max_walks_per_launch=80_000, max_inflight=1)
+    srv.wait(srv.ingest(*dev))
+    reqs = [dict(num_walks=70_000, max_len=16, hop_bias="linear", seed=1),
+            dict(num_walks=70_000, max_len=18, hop_bias="exponential", hop_tau=tau, seed=2),
+            dict(num_walks=80_000, max_len=12, hop_bias="node2vec", hop_tau=tau, p=0.5, q=2.0,
+                 seed=3)]
+    ids = [srv.submit(**r) for r in reqs]
+    bad = srv.submit(70_000, 8, start_mode="node", start_nodes=starts, seed=4)
+    got = [srv.result(i) for i in ids]
+    assert srv.wait(bad)["status"] == tw.TW_ERANGE
+    for i in ids:
+        r = srv.wait(i)
+        assert r["status"] == tw.TW_OK and r["trial_cap_hits"] == 0
+    st = srv.stats()
+    hops = sum(int((x[2].to(torch.int64) - 1).clamp_min(0).sum()) for x in got)
+    srv.close()
+    g.close()
+    g2 = tw.Graph(V)
+    g2.ingest_batch(*dev)
+    plain_hops = 0
+    for r, x in zip(reqs, got):
+        ref = g2.sample_walks(**r)
+        _same(x, ref)
+        plain_hops += int((ref[2].to(torch.int64) - 1).clamp_min(0).sum())
+    assert hops == plain_hops
+    g2.sample_walks(70_000, 8, start_mode="node", start_nodes=starts, seed=4)
+    with pytest.raises(tw.TwError):
+        g2.sync()
+    assert st["hops_done"] >= hops  # the failed request's walks count too
+    g2.close()
+
+
 def test_server_concurrent_submitters():
     # requests from two host threads at once, small and mixed: every result
     # equals the plain walks of its own parameters
