@@ -406,9 +406,11 @@ def run_stream(args, torch, tw, w, dev, gather_rate, copy_bw):
     # steady state: batches 96-100 of the 100 (or the last ones of a shorter run)
     steady_first = max(min(96, total - 4), first_n + 1)
     first_host, window_host, steady_host = [], [], {}
+    t_now = []  # the clock after each batch (its largest timestamp so far), host-side
     for b, (s, d, t) in enumerate(spec.batches(B)):
         if b >= total:
             break
+        t_now.append(max(int(t.max()), t_now[-1] if t_now else int(t.max())))
         batches.append((torch.from_numpy(s).to(dev), torch.from_numpy(d).to(dev),
                         torch.from_numpy(t).to(dev)))
         if b == total - 1:
@@ -445,12 +447,13 @@ def run_stream(args, torch, tw, w, dev, gather_rate, copy_bw):
         s, d, t = batches[b]
         e = evs[b]
         e[0].record()
-        info = g.ingest_batch(s, d, t)
-        st = g.index_stats()  # host counters of the ingest just done
-        per_batch.append((info["accepted"], info["evicted"], st["jobs"], st["full_rewrite"],
-                          info["active_edges"]))
+        g.ingest_batch(s, d, t, info=False)  # the window's range stays on the device
+        lu = g.last_update()  # host counters of the ingest just done
+        st = g.index_stats()
+        per_batch.append((lu["accepted"], lu["evicted"], st["jobs"], st["full_rewrite"],
+                          lu["active_edges"]))
         e[1].record()
-        g.evict_before(info["t_max"] - w["window"])
+        g.evict_before(t_now[b] - w["window"])
         e[2].record()
         g.sample_walks(W, L, hop_bias=w["hop_bias"], start_bias=w["start_bias"], seed=b,
                        dispatch=args.dispatch, out=(out[0], out[1], lens_all[b]))

@@ -201,11 +201,14 @@ tw_status tw_set_stream(tw_graph* g, void* hip_stream);
  * view in place, and the node-and-timestamp view for the nodes the batch or
  * the eviction touches.
  * d_src, d_dst: int32[n]; d_ts: int64[n]; device memory, any alignment.
- * info (nullable) receives the counts. The call synchronises the stream
- * (it sizes its launches from counts it reads back); the first read-back
- * also brings the error flags of earlier walks: a pending one is reported
- * (TW_ERANGE, TW_EINVAL, see tw_sample_walks) and cleared, and the batch is
- * not ingested.
+ * info (nullable) receives the counts and the window's timestamp range;
+ * with info NULL the range is computed on the device and read back with the
+ * next read-back the library makes anyway (one synchronisation fewer). The
+ * call synchronises the stream (it sizes its launches from counts it reads
+ * back: three read-backs, four with info); the first read-back also brings
+ * the error flags of earlier walks: a pending one is reported (TW_ERANGE,
+ * TW_EINVAL, see tw_sample_walks) and cleared, and the batch is not
+ * ingested.
  * Returns TW_ERANGE, with the graph unchanged, if any id is outside
  * [0, num_nodes). The batch is staged, validated, sorted and its node-view
  * jobs collected before the index changes: TW_ENOMEM (device full) in that
@@ -260,6 +263,13 @@ tw_status tw_set_ingest_weights(tw_graph* g, double tau);
  */
 tw_status tw_sample_walks(tw_graph* g, const tw_walk_params* params, int32_t* d_nodes,
                           int64_t* d_ts, int32_t* d_len);
+
+/*
+ * Counts of the last ingest_batch or evict_before, host-side, no
+ * synchronisation: out[0] records accepted, out[1] dropped as late, out[2]
+ * evicted, out[3] records in the window now. TW_EINVAL for null arguments.
+ */
+tw_status tw_last_update(const tw_graph* g, int64_t out[4]);
 
 /*
  * Counters of the last index update (ingest_batch or evict_before), for

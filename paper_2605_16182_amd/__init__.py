@@ -111,6 +111,7 @@ def lib():
         "tw_sample_walks": ([P, _c.POINTER(_WalkParams), P, P, P], _c.c_int),
         "tw_sample_walks_noalloc": ([P, _c.POINTER(_WalkParams), P, P, P], _c.c_int),
         "tw_set_ingest_weights": ([P, _c.c_double], _c.c_int),
+        "tw_last_update": ([P, _c.POINTER(I64)], _c.c_int),
         "tw_get_tuning": ([P, _c.POINTER(_Tuning)], _c.c_int),
         "tw_set_tuning": ([P, _c.POINTER(_Tuning)], _c.c_int),
         "tw_sync": ([P], _c.c_int),
@@ -196,14 +197,23 @@ class Graph:
         _check(self._lib.tw_set_stream(self._h, _c.c_void_p(stream.cuda_stream)))
         self.stream = stream
 
-    def ingest_batch(self, src: torch.Tensor, dst: torch.Tensor, ts: torch.Tensor) -> dict:
+    def ingest_batch(self, src: torch.Tensor, dst: torch.Tensor, ts: torch.Tensor,
+                     info: bool = True) -> Optional[dict]:
+        """The batch's counts and the window's range (info=False: None, and
+        the window summary stays on the device; one read-back fewer)."""
         assert src.dtype == torch.int32 and dst.dtype == torch.int32 and ts.dtype == torch.int64
         n = src.numel()
         assert dst.numel() == n and ts.numel() == n
-        info = _Info()
+        out = _Info() if info else None
         _check(self._lib.tw_ingest_batch(self._h, _ptr(src), _ptr(dst), _ptr(ts), n,
-                                         _c.byref(info)))
-        return _info(info)
+                                         _c.byref(out) if info else None))
+        return _info(out) if info else None
+
+    def last_update(self) -> dict:
+        """Counts of the last ingest or eviction, host-side (tw_last_update)."""
+        out = (_c.c_int64 * 4)()
+        _check(self._lib.tw_last_update(self._h, out))
+        return dict(zip(("accepted", "dropped_late", "evicted", "active_edges"), map(int, out)))
 
     def set_ingest_weights(self, tau: Optional[float]):
         """Build the weight-based picker's weights at every ingest and

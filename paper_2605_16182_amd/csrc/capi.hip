@@ -133,8 +133,9 @@ tw_status tw_evict_before(tw_graph* g, int64_t t_cutoff, int64_t* n_evicted) {
     return guarded("tw_evict_before", [&]() -> tw_status {
         tw_status st = refuse_broken(g, "tw_evict_before");
         if (st != TW_OK) return st;
-        // nothing to evict: no device work and no synchronisation
-        if (g->m == 0 || t_cutoff <= g->t_min) {
+        // nothing to evict: no device work and no synchronisation (with the
+        // window summary still on the device, its host-known lower bound)
+        if (g->m == 0 || t_cutoff <= (g->sum_stale ? g->t_min_lb : g->t_min)) {
             g->last.accepted = 0;
             g->last.dropped_late = 0;
             g->last.evicted = 0;
@@ -292,6 +293,8 @@ tw_status tw_sync(tw_graph* g) {
 tw_status tw_stats(tw_graph* g, tw_ingest_info* info) {
     if (!g || !info) return fail(TW_EINVAL, "tw_stats: null argument");
     tw_status st = tw_sync(g);
+    tw::Error e{TW_OK, ""};
+    if (st == TW_OK && tw::refresh_summary(g, e) != TW_OK) st = report(e.code, e);
     *info = g->last;
     info->active_edges = g->m;
     info->t_min = g->t_min;
@@ -309,6 +312,7 @@ tw_status tw_view_sizes(tw_graph* g, int64_t out[4]) {
         if (!g->rec.p && tw::init_empty(g, e) != TW_OK) return report(e.code, e);
         int64_t gn = 0;
         if (tw::nv_group_count(g, &gn, e) != TW_OK) return report(e.code, e);
+        if (tw::refresh_summary(g, e) != TW_OK) return report(e.code, e);
         out[0] = g->m;
         out[1] = g->Gg;
         out[2] = gn;
@@ -329,6 +333,15 @@ tw_status tw_export_views(tw_graph* g, int32_t* src, int32_t* dst, int64_t* ts, 
                                        n_ebeg, n_gbeg, e),
                       e);
     });
+}
+
+tw_status tw_last_update(const tw_graph* g, int64_t out[4]) {
+    if (!g || !out) return fail(TW_EINVAL, "tw_last_update: null argument");
+    out[0] = g->last.accepted;
+    out[1] = g->last.dropped_late;
+    out[2] = g->last.evicted;
+    out[3] = g->m;
+    return TW_OK;
 }
 
 tw_status tw_index_stats(const tw_graph* g, int64_t out[8]) {

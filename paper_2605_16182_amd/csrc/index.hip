@@ -90,8 +90,8 @@ __global__ void __launch_bounds__(T)
 k_stage_count(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
               const int64_t* __restrict__ ts, int64_t n, int32_t V, int32_t* __restrict__ b_src,
               int32_t* __restrict__ b_dst, int64_t* __restrict__ b_ts, uint32_t* err,
-              unsigned long long* scalars, uint32_t* unsorted, int has_last, int64_t last_ts,
-              uint32_t* __restrict__ gcnt) {
+              unsigned long long* scalars, uint32_t* unsorted, int has_last,
+              const int64_t* last_ts_p, uint32_t* __restrict__ gcnt) {
     __shared__ unsigned long long smin[T], smax[T];
     __shared__ uint32_t wsum[T / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -112,7 +112,7 @@ k_stage_count(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
                     down |= tp > t;
                     start = t != tp;
                 } else {
-                    start = !has_last || t != last_ts;
+                    start = !has_last || t != *last_ts_p;
                 }
                 const unsigned long long o = ord(t);
                 lo = o < lo ? o : lo;
@@ -217,10 +217,11 @@ __device__ void evicted_prefix(const int64_t* __restrict__ w_ts, int64_t m, int6
     *sc_gev = (uint32_t)a;
 }
 
+// Gg from the window summary slot (written by the last update)
 __global__ void k_evict_counts(const int64_t* __restrict__ w_ts, int64_t m, int64_t cut,
-                               const uint32_t* __restrict__ gg_off, int64_t Gg, int64_t w_base,
-                               uint32_t* sc_ev, uint32_t* sc_gev) {
-    evicted_prefix(w_ts, m, cut, gg_off, Gg, w_base, sc_ev, sc_gev);
+                               const uint32_t* __restrict__ gg_off, const int64_t* gg_p,
+                               int64_t w_base, uint32_t* sc_ev, uint32_t* sc_gev) {
+    evicted_prefix(w_ts, m, cut, gg_off, *gg_p, w_base, sc_ev, sc_gev);
 }
 
 // The window cut of an ingest from the staged batch's range (the same
@@ -233,8 +234,9 @@ __global__ void k_evict_counts(const int64_t* __restrict__ w_ts, int64_t m, int6
 __global__ void k_cut_counts(const unsigned long long* __restrict__ mm,
                              const uint32_t* __restrict__ unsorted, int has_time, int64_t t_now,
                              int64_t window, const int64_t* __restrict__ b_ts, int64_t B,
-                             const int64_t* __restrict__ w_ts, int64_t m, int64_t t_min,
-                             const uint32_t* __restrict__ gg_off, int64_t Gg, int64_t w_base,
+                             const int64_t* __restrict__ w_ts, int64_t m,
+                             const int64_t* summary, const uint32_t* __restrict__ gg_off,
+                             const int64_t* gg_p, int64_t w_base,
                              uint32_t* sc_kept, int64_t* first_kept, uint32_t* sc_ev,
                              uint32_t* sc_gev) {
     const int64_t bmin = unord(mm[0]), bmax = unord(mm[1]);
@@ -257,8 +259,8 @@ __global__ void k_cut_counts(const unsigned long long* __restrict__ mm,
             *first_kept = bmin;
         }
     } else if (threadIdx.x == 1) {
-        if (windowed && m > 0 && t_min < cut) {
-            evicted_prefix(w_ts, m, cut, gg_off, Gg, w_base, sc_ev, sc_gev);
+        if (windowed && m > 0 && summary[0] < cut) {
+            evicted_prefix(w_ts, m, cut, gg_off, *gg_p, w_base, sc_ev, sc_gev);
         } else {
             *sc_ev = 0u;
             *sc_gev = 0u;
@@ -309,9 +311,15 @@ __global__ void k_widen(const uint32_t* __restrict__ in, int64_t n, int64_t* __r
     if (i < n) out[i] = (int64_t)in[i] - minus;
 }
 
-__global__ void k_window_summary(const int64_t* __restrict__ ts, int64_t m, int64_t* out) {
+// the window's first and last timestamps and its global group count: the
+// groups just counted (all of them when gg_full, else those appended after
+// the gg_kept surviving ones)
+__global__ void k_window_summary(const int64_t* __restrict__ ts, int64_t m, int64_t* out,
+                                 int gg_full, int64_t gg_kept, const uint32_t* groups,
+                                 int64_t* gg_out) {
     out[0] = m > 0 ? ts[0] : 0;
     out[1] = m > 0 ? ts[m - 1] : 0;
+    *gg_out = gg_full ? (int64_t)*groups : gg_kept + (int64_t)*groups;
 }
 
 uint32_t* u32_slot(tw_graph* g, int k) { return g->scal.as<uint32_t>() + k; }
@@ -400,20 +408,18 @@ tw_status build_ts_groups(tw_graph* g, Error& err, DevBuf* counted = nullptr) {
     return TW_OK;
 }
 
-// Window timestamp range and global group count after an update; one
-// synchronisation. Gg is taken from the GROUPS slot when gg_full, else it is
-// gg_old - gg_evicted + GROUPS (appended groups).
+// Window timestamp range and global group count after an update, computed
+// on the device: Gg is the GROUPS slot when gg_full, else gg_old -
+// gg_evicted + GROUPS (appended groups). No synchronisation: the host
+// mirrors follow with the next read-back of the slots.
 tw_status finish_ts(tw_graph* g, bool gg_full, int64_t gg_old, int64_t gg_evicted, Error& err) {
     hipStream_t s = g->stream;
-    int64_t* summary = i64_slot(g, SLOT_I64_SUMMARY);
     hipLaunchKernelGGL(k_window_summary, dim3(1), dim3(1), 0, s, g->e_ts.as<int64_t>() + g->e_base,
-                       g->m, summary);
+                       g->m, i64_slot(g, SLOT_I64_SUMMARY), gg_full ? 1 : 0,
+                       gg_old - gg_evicted, u32_slot(g, SLOT_U32_GROUPS),
+                       i64_slot(g, SLOT_I64_GG));
     TW_HIP(hipGetLastError());
-    if (pull_scalars(g, false, err) != TW_OK) return err.code;
-    const uint32_t groups = host_u32(g, SLOT_U32_GROUPS);
-    g->Gg = gg_full ? (int64_t)groups : gg_old - gg_evicted + (int64_t)groups;
-    g->t_min = host_i64(g, SLOT_I64_SUMMARY);
-    g->t_max = host_i64(g, SLOT_I64_SUMMARY + 1);
+    g->sum_stale = true;
     return TW_OK;
 }
 
@@ -469,7 +475,7 @@ tw_status ingest_prepare(tw_graph* g, const int32_t* src, const int32_t* dst, co
         TW_HIP(ensure(g->gs_tiles, sizeof(uint32_t) * (ntiles + 1), g->stream));
         hipLaunchKernelGGL(k_stage_count, dim3((unsigned)ntiles), dim3(T), 0, s, src, dst, ts, n,
                            g->V, s_src, s_dst, s_ts, errf + 1, mm, unsorted, stage_has_last,
-                           g->t_max, g->gs_tiles.as<uint32_t>());
+                           i64_slot(g, SLOT_I64_SUMMARY) + 1, g->gs_tiles.as<uint32_t>());
     } else if (n > 0) {
         hipLaunchKernelGGL(k_stage, dim3((unsigned)std::min<int64_t>(ceil_div(n, T), 2048)),
                            dim3(T), 0, s, src, dst, ts, n, g->V, g->directed ? 1 : 0, s_src, s_dst,
@@ -484,9 +490,10 @@ tw_status ingest_prepare(tw_graph* g, const int32_t* src, const int32_t* dst, co
     if (g->window > 0)
         hipLaunchKernelGGL(k_cut_counts, dim3(1), dim3(64), 0, s, mm, unsorted,
                            g->has_time ? 1 : 0, g->t_now, g->window, s_ts, B,
-                           g->e_ts.as<int64_t>() + g->e_base, g->m, g->t_min,
-                           g->gg_off.as<uint32_t>() + g->gg_base, g->Gg, g->e_base, sc_kept,
-                           first_kept, sc_ev, sc_gev);
+                           g->e_ts.as<int64_t>() + g->e_base, g->m,
+                           i64_slot(g, SLOT_I64_SUMMARY), g->gg_off.as<uint32_t>() + g->gg_base,
+                           i64_slot(g, SLOT_I64_GG), g->e_base, sc_kept, first_kept, sc_ev,
+                           sc_gev);
     TW_HIP(hipGetLastError());
     if (pull_scalars(g, true, err) != TW_OK) return err.code;
     const uint64_t hmm[2] = {(uint64_t)host_i64(g, SLOT_I64_MINMAX),
@@ -776,14 +783,20 @@ tw_status ingest_apply(tw_graph* g, const IngestPlan& P, tw_ingest_info* info, E
 
     g->t_now = P.t_now;
     g->has_time = P.has_time;
+    // every window record is at or after the cut now
+    if (P.cut > g->t_min_lb) g->t_min_lb = P.cut;
     g->broken = false;
     g->last.accepted = kept;
     g->last.dropped_late = B - kept;
     g->last.evicted = evicted;
     g->last.active_edges = g->m;
-    g->last.t_min = g->t_min;
-    g->last.t_max = g->t_max;
-    if (info) *info = g->last;
+    if (info) {
+        // the caller asked for the window's range: read the summary back
+        if (refresh_summary(g, err) != TW_OK) return err.code;
+        g->last.t_min = g->t_min;
+        g->last.t_max = g->t_max;
+        *info = g->last;
+    }
     return TW_OK;
 }
 
@@ -799,12 +812,13 @@ tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& e
     if (ensure_common(g, err) != TW_OK) return err.code;
     if (!g->rec.p && init_empty(g, err) != TW_OK) return err.code;
     int64_t ev = 0, gev = 0;
-    if (g->m > 0 && g->t_min < cutoff) {
+    if (g->m > 0 && cutoff > (g->sum_stale ? g->t_min_lb : g->t_min)) {
         uint32_t* sc_ev = u32_slot(g, SLOT_U32_EVICTED);
         uint32_t* sc_gev = u32_slot(g, SLOT_U32_GG_EVICTED);
         hipLaunchKernelGGL(k_evict_counts, dim3(1), dim3(1), 0, s,
                            g->e_ts.as<int64_t>() + g->e_base, g->m, cutoff,
-                           g->gg_off.as<uint32_t>() + g->gg_base, g->Gg, g->e_base, sc_ev, sc_gev);
+                           g->gg_off.as<uint32_t>() + g->gg_base, i64_slot(g, SLOT_I64_GG),
+                           g->e_base, sc_ev, sc_gev);
         if (pull_scalars(g, false, err) != TW_OK) return err.code;
         ev = host_u32(g, SLOT_U32_EVICTED);
         gev = host_u32(g, SLOT_U32_GG_EVICTED);
@@ -837,12 +851,11 @@ tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& e
         if (finish_ts(g, gg_full, gg_old, gev, err) != TW_OK) return err.code;
         g->broken = false;
     }
+    if (cutoff > g->t_min_lb) g->t_min_lb = cutoff;
     g->last.accepted = 0;
     g->last.dropped_late = 0;
     g->last.evicted = ev;
     g->last.active_edges = g->m;
-    g->last.t_min = g->t_min;
-    g->last.t_max = g->t_max;
     if (n_evicted) *n_evicted = ev;
     return TW_OK;
 }
@@ -944,7 +957,19 @@ tw_status pull_scalars(tw_graph* g, bool flags, Error& err) {
         TW_HIP(hipMemcpyAsync(static_cast<char*>(g->h_scal) + SCALAR_BYTES, g->err.p, 16,
                               hipMemcpyDeviceToHost, s));
     TW_HIP(hipStreamSynchronize(s));
+    if (g->sum_stale) {
+        // the slots of the last finished update came back too
+        g->t_min = host_i64(g, SLOT_I64_SUMMARY);
+        g->t_max = host_i64(g, SLOT_I64_SUMMARY + 1);
+        g->Gg = host_i64(g, SLOT_I64_GG);
+        g->sum_stale = false;
+    }
     return TW_OK;
+}
+
+tw_status refresh_summary(tw_graph* g, Error& err) {
+    if (!g->sum_stale) return TW_OK;
+    return pull_scalars(g, false, err);
 }
 
 tw_status init_empty(tw_graph* g, Error& err) {
@@ -961,6 +986,7 @@ tw_status export_views(tw_graph* g, int32_t* src, int32_t* dst, int64_t* ts, int
                        int64_t* n_goff, int64_t* n_ebeg, int64_t* n_gbeg, Error& err) {
     hipStream_t s = g->stream;
     const int64_t m = g->m;
+    if (refresh_summary(g, err) != TW_OK) return err.code;
     auto cp = [&](void* d, const void* sp, size_t bytes) -> hipError_t {
         if (!d || bytes == 0) return hipSuccess;
         return hipMemcpyAsync(d, sp, bytes, hipMemcpyDeviceToDevice, s);

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdint>
 #include <cmath>
 #include <string>
@@ -155,6 +156,7 @@ constexpr int SLOT_I64_MINMAX = 0;     // batch min / max timestamp (ordered u64
 constexpr int SLOT_U32_GROUPS = 4;     // groups counted by the last timestamp-group scan
 constexpr int SLOT_U32_UNSORTED = 6;   // batch not in timestamp order
 constexpr int SLOT_I64_SUMMARY = 4;    // [4] t_min, [5] t_max of the window
+constexpr int SLOT_I64_GG = 6;         // global timestamp groups of the window
 constexpr int SLOT_U32_KEPT = 24;      // kept batch records / late-prefix length
 constexpr int SLOT_U32_EVICTED = 25;   // evicted window records
 constexpr int SLOT_I64_FIRST_KEPT = 13;
@@ -292,6 +294,12 @@ struct tw_graph {
     int64_t m = 0, Gg = 0;
     int64_t e_base = 0, e_cap = 0, gg_base = 0;
     int64_t t_min = 0, t_max = 0;
+    // Gg, t_min and t_max of an update are computed on the device (scalar
+    // slots SLOT_I64_GG, SLOT_I64_SUMMARY) and reach these mirrors with the
+    // next read-back of the slots (sum_stale until then); t_min_lb is a
+    // host-known lower bound of the window's first timestamp meanwhile
+    bool sum_stale = false;
+    int64_t t_min_lb = INT64_MIN;
     tw_ingest_info last{};
 
     // timestamp view (the edge store) and its alternate for merges
@@ -391,6 +399,8 @@ namespace tw {
 // Copy the device scalar slots (with flags: also the device error flags) to
 // the graph's pinned host copy and wait for the graph's stream.
 tw_status pull_scalars(tw_graph* g, bool flags, Error& err);
+// the window summary on the host: a read-back of the slots when it is stale
+tw_status refresh_summary(tw_graph* g, Error& err);
 inline uint32_t host_u32(const tw_graph* g, int k) {
     return static_cast<const uint32_t*>(g->h_scal)[k];
 }

@@ -620,6 +620,48 @@ def test_fresh_graph_reports_no_error():
         g.close()
 
 
+@pytest.mark.parametrize("directed", [True, False])
+def test_ingest_without_info(directed):
+    # ingests that leave the window's range and group count on the device
+    # (no info requested): explicit evictions, biased start picks (which read
+    # them on the device) and the counts must match the oracle's, and the
+    # range is read back on request
+    from gpu_util import compare_walks
+    torch, tw = gpu_or_skip()
+    rng = np.random.default_rng(17)
+    V, window = 400, 5_000
+    g = tw.Graph(V, directed=directed, window=window)
+    og = oracle.OracleGraph(V, directed=directed, window=window)
+    t0 = 0
+    for b in range(10):
+        n = int(rng.integers(1000, 3000))
+        s = rng.integers(0, V, n).astype(np.int32)
+        d = rng.integers(0, V, n).astype(np.int32)
+        t = (t0 + rng.integers(-400, 1000, n)).astype(np.int64)
+        t0 += 1000
+        assert g.ingest_batch(*to_dev(torch, s, d, t), info=False) is None
+        oi = og.ingest_batch(s, d, t)
+        lu = g.last_update()
+        assert (lu["accepted"], lu["dropped_late"], lu["evicted"], lu["active_edges"]) == (
+            oi["accepted"], oi["dropped_late"], oi["evicted"], oi["active_edges"]), b
+        cut = t0 - window + (300 if b % 3 == 0 else -2000)  # sometimes nothing to evict
+        assert g.evict_before(cut) == og.evict_before(cut), b
+        for kind in ("linear", "exponential"):
+            nodes, ts, lens = g.sample_walks(2000, 8, hop_bias="uniform", start_bias=kind,
+                                             start_tau=300.0, seed=b)
+            g.sync()
+            r = og.sample_walks(2000, 8, hop_bias="uniform", start_bias=kind, start_tau=300.0,
+                                seed=b, with_margin=True)
+            same, boundary = compare_walks(
+                (nodes.cpu().numpy(), ts.cpu().numpy(), lens.cpu().numpy()), r, kind == "linear")
+            assert boundary <= 2, (b, kind, same, boundary)
+    st = g.stats()
+    ots = og.views()["ts"]
+    assert (st["t_min"], st["t_max"], st["active_edges"]) == (int(ots[0]), int(ots[-1]), len(ots))
+    _views_equal(g, og)
+    g.close()
+
+
 def test_walk_errors_reported_by_the_next_ingest():
     # a walk's out-of-range start node is reported by the next ingest, which
     # then ingests nothing; an eviction with nothing to evict neither
