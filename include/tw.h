@@ -89,8 +89,9 @@ typedef enum {
  * A directed graph keeps an in-view (a second index fed every batch with
  * source and destination swapped) from its first backward walk on, which
  * doubles the cost of later ingests; an undirected graph is its own in-view.
- * Backward walks run on the full-walk dispatch (AUTO or FULL_WALK); TW_WEIGHT
- * is forward only; tw_sample_walks_batch and the server walk forward. */
+ * Backward walks run on the full-walk dispatch (AUTO or FULL_WALK) or the work
+ * queue (QUEUE), in tw_sample_walks and tw_sample_walks_batch; TW_WEIGHT is
+ * forward only, and the server walks forward. */
 typedef enum { TW_FORWARD = 0, TW_BACKWARD = 1 } tw_direction;
 
 /* TW_START_EDGE: the first edge is drawn from the whole window (timestamp
@@ -140,7 +141,7 @@ typedef struct {
     uint64_t seed;               /* RNG key */
     uint64_t walk_id_base;       /* walk i uses RNG id walk_id_base + i */
     int32_t dispatch;            /* tw_dispatch */
-    int32_t direction;           /* tw_direction (tw_sample_walks only; 0: forward) */
+    int32_t direction;           /* tw_direction (0: forward) */
 } tw_walk_params;
 
 /*
@@ -171,6 +172,8 @@ typedef struct {
     int32_t dispatch;            /* TW_DISPATCH_QUEUE (AUTO means it), or
                                     TW_DISPATCH_FULL_WALK: one thread per walk, no
                                     queue (the plain form, for comparison) */
+    int32_t direction;           /* tw_direction (0: forward); backward walks take
+                                    no TW_WEIGHT bias */
 } tw_batch_params;
 
 typedef struct {

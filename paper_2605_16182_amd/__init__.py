@@ -58,7 +58,8 @@ class _BatchParams(_c.Structure):
                 ("start_bias", _Bias), ("start_mode", _c.c_int32),
                 ("d_start_nodes", _c.c_void_p), ("seed", _c.c_uint64),
                 ("walk_id_base", _c.c_uint64), ("d_row", _c.c_void_p),
-                ("out_slots", _c.c_int64), ("dispatch", _c.c_int32)]
+                ("out_slots", _c.c_int64), ("dispatch", _c.c_int32),
+                ("direction", _c.c_int32)]
 
 
 class _Info(_c.Structure):
@@ -278,7 +279,8 @@ class Graph:
                            start_bias: str = "uniform", start_tau: float = 0.0,
                            start_mode: str = "edge", start_nodes: Optional[torch.Tensor] = None,
                            seed: int = 42, walk_id_base: int = 0, ragged: bool = False,
-                           dispatch: str = "queue", rows=None, out=None):
+                           dispatch: str = "queue", rows=None, out=None,
+                           direction: str = "forward"):
         """Walks of uneven lengths and mixed hop biases in one persistent
         launch. hop_biases: list of (kind, tau, p, q); max_lens: int32[W] or
         None; bias_idx: uint8[W] or None (walk id mod len(hop_biases)).
@@ -286,7 +288,7 @@ class Graph:
         with ragged=True, packed rows starting at row[i] (int64[W + 1]; pass
         rows=(row, total) from row_offsets to skip computing them).
         dispatch "queue" (persistent work queue) or "full_walk" (one thread
-        per walk, no queue)."""
+        per walk, no queue); direction "forward" or "backward"."""
         W, L = int(num_walks), int(max_len)
         nb = len(hop_biases)  # the library rejects 0 or more than MAX_BIASES
         biases = (_Bias * MAX_BIASES)()
@@ -315,7 +317,7 @@ class Graph:
                            _Bias(KINDS[start_bias], float(start_tau), 1.0, 1.0),
                            START_MODES[start_mode], _ptr(start_nodes), int(seed),
                            int(walk_id_base), _ptr(row), slots if ragged else 0,
-                           DISPATCH[dispatch])
+                           DISPATCH[dispatch], DIRECTIONS[direction])
         _check(self._lib.tw_sample_walks_batch(self._h, _c.byref(prm), _ptr(nodes), _ptr(ts),
                                                _ptr(lens)))
         if not ragged:

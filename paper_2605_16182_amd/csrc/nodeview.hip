@@ -495,7 +495,31 @@ __global__ void __launch_bounds__(T) k_job_flags(const Job* __restrict__ jobs,
         }
         return c;
     };
-    const uint32_t c = tj.staged ? rounds(std::true_type{}) : rounds(std::false_type{});
+    // a tile inside one job (a hub's run): the job is read once, as uniform
+    // loads, and no output looks its job up
+    auto one_job = [&]() {
+        const Job J = jobs[tj.j0];
+        const uint32_t jb = off[tj.j0];
+        uint32_t c = 0;
+        for (int u = 0; u < NV_ITEMS; ++u) {
+            const int64_t t0 = base + (int64_t)u * T + wave * 64;
+            const int64_t t = t0 + lane;
+            bool start = false;
+            if (t < total) {
+                const uint32_t i = (uint32_t)(t - jb);
+                const int64_t x = job_ts(J, i, ots, bt);
+                if (i == 0) start = J.kind != JOB_APPEND || x != J.t_last;
+                else start = x != job_ts(J, i - 1, ots, bt);
+            }
+            const uint64_t b = __ballot(start);
+            if (lane == 0 && t0 < total) bm[t0 >> 6] = b;
+            c += (uint32_t)__popcll(b);
+        }
+        return c;
+    };
+    const uint32_t c = tj.j0 == tj.j1 ? one_job()
+                       : tj.staged   ? rounds(std::true_type{})
+                                     : rounds(std::false_type{});
     if (lane == 0) wsum[wave] = c;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -579,14 +603,17 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
         }
     }
     __syncthreads();
-    auto rounds = [&](auto staged) {
-        constexpr bool S = decltype(staged)::value;
+    // M: 0 = job lookups in global memory, 1 = in LDS, 2 = the tile lies in
+    // one job (a hub's run), read once as uniform loads
+    auto rounds = [&](auto mode) {
+        constexpr int M = decltype(mode)::value;
+        constexpr bool S = M == 1;
         for (int u = 0; u < NV_ITEMS; ++u) {
             const int64_t t = base + (int64_t)u * T + threadIdx.x;
             if (t >= total) break;
-            const uint32_t j = tj.template job<S>(off, soff, (uint64_t)t);
+            const uint32_t j = M == 2 ? tj.j0 : tj.template job<S>(off, soff, (uint64_t)t);
             const Job J = jobs[j];
-            const uint32_t jb = tj.template start<S>(off, soff, j);
+            const uint32_t jb = M == 2 ? off[tj.j0] : tj.template start<S>(off, soff, j);
             const uint32_t i = (uint32_t)(t - jb);
             const Elem e = job_elem(J, i, odst, ots, bt);
             const uint32_t pos = J.e_at + i;
@@ -605,7 +632,8 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
                 // a one-edge group: the job's next output starts a group, or
                 // there is none
                 bool single =
-                    (uint64_t)t + 1 >= (uint64_t)tj.template start<S>(off, soff, j + 1);
+                    (uint64_t)t + 1 >= (uint64_t)(M == 2 ? off[tj.j0 + 1]
+                                                         : tj.template start<S>(off, soff, j + 1));
                 if (!single) {
                     const int ln = lt + 1;
                     uint64_t nw;
@@ -652,8 +680,9 @@ __global__ void __launch_bounds__(T) k_job_write(const Job* __restrict__ jobs,
             }
         }
     };
-    if (tj.staged) rounds(std::true_type{});
-    else rounds(std::false_type{});
+    if (tj.j0 == tj.j1) rounds(std::integral_constant<int, 2>{});
+    else if (tj.staged) rounds(std::integral_constant<int, 1>{});
+    else rounds(std::integral_constant<int, 0>{});
 }
 
 // Level k of a segment with n groups in use holds the keys of its entries

@@ -462,8 +462,9 @@ __global__ void k_queue_reset(unsigned long long* counters) {
 }
 
 // REFILL = false is the same per-walk work without the queue: thread i runs
-// walk i only (the full-walk form of a batch).
-template <bool REFILL, int HK, int SK>
+// walk i only (the full-walk form of a batch). REV: backward walks on the
+// in-view (each hop as in k_walk_back).
+template <bool REFILL, int HK, int SK, bool REV = false>
 // The instantiation for mixed hop kinds (HK < 0) carries every picker's
 // registers (about 160 VGPRs, 3 waves per SIMD); it is held to 4 waves, which
 // spills a few registers and measured 11 % faster on mixed batches.
@@ -515,8 +516,8 @@ k_walk_queue(const WalkArgs a, const QueueArgs q) {
                         hb = fixed_hop<HK>(q.bias[b]);
                         out_n = a.nodes + row;
                         out_t = a.ts + row;
-                        const StartState st =
-                            walk_start(a, fixed_start<SK>(start_of(a)), w, id, lim, out_n, out_t);
+                        const StartState st = walk_start(a, fixed_start<SK>(start_of(a)), w, id,
+                                                         lim, out_n, out_t, REV);
                         len = st.len;
                         cur = st.cur;
                         prev = st.prev;
@@ -543,11 +544,25 @@ k_walk_queue(const WalkArgs a, const QueueArgs q) {
         if (w >= 0) {
             bool done = true;
             const NodeRec r = a.rec[cur];
-            if (tcur < r.t_last) {  // else Gamma_t(cur) is empty
-                const uint32_t gc = fence_search(a.ng, a.fence, r, tcur, nullptr, 0, 0);
+            // forward: Gamma_t(cur) is empty when t >= the last timestamp;
+            // backward: when cur has no in-edge or none before t
+            bool live = REV ? r.gb != r.ge : tcur < r.t_last;
+            uint32_t g = 0;
+            if (live) {
+                if (REV) {
+                    g = tcur - 1 >= r.t_last
+                            ? r.ge
+                            : fence_search(a.ng, a.fence, r, tcur - 1, nullptr, 0, 0);
+                    live = g != r.gb;
+                } else {
+                    g = fence_search(a.ng, a.fence, r, tcur, nullptr, 0, 0);
+                }
+            }
+            if (live) {
                 Pick p;
                 int32_t nx;
-                if (hop_pick(a, hb, a.seed, r, gc, id, hop, prev, p, nx)) {
+                if (REV ? back_pick(a, hb, a.seed, r, g, id, hop, prev, p, nx)
+                        : hop_pick(a, hb, a.seed, r, g, id, hop, prev, p, nx)) {
                     out_n[len] = nx;
                     out_t[len] = p.t;
                     ++len;
@@ -1167,7 +1182,18 @@ int resident_bpc(K kernel) {
     return std::max(nb, 1);
 }
 
-tw_status queue_walks(tw_graph* g, const WalkArgs& a, const QueueArgs& q0, int bpc, Error& err) {
+// Calls f with the direction as a compile-time constant. Backward walks
+// never take the weight-based picker (refused before any launch), so its
+// backward instantiations are not built.
+template <typename F>
+void with_direction(bool rev, int hk, F&& f) {
+    if (!rev) f(std::false_type{});
+    else if (hk != TW_WEIGHT) f(std::true_type{});
+}
+
+// rev: backward walks (a is the in-view's)
+tw_status queue_walks(tw_graph* g, const WalkArgs& a, const QueueArgs& q0, int bpc, Error& err,
+                      bool rev = false) {
     if (queue_shape(g, err) != TW_OK) return err.code;
     TW_HIP(ensure(g->wq, sizeof(unsigned long long) * QUEUE_SLICES, g->stream));
     QueueArgs q = q0;
@@ -1175,25 +1201,32 @@ tw_status queue_walks(tw_graph* g, const WalkArgs& a, const QueueArgs& q0, int b
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, g->stream, q.counters);
     const int hk = q.n_bias == 1 ? q.bias[0].kind : -1;
     with_kinds(hk, a.start_kind, [&](auto h, auto st) {
-        auto kernel = k_walk_queue<true, decltype(h)::value, decltype(st)::value>;
-        static const int maxb = resident_bpc(kernel);  // per instantiation
-        const int b = (bpc <= 0 || bpc > maxb) ? maxb : bpc;
-        const int64_t blocks =
-            std::min<int64_t>(ceil_div(a.num_walks, WALK_THREADS), (int64_t)g->cu_count * b);
-        hipLaunchKernelGGL(kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)),
-                           dim3(WALK_THREADS), 0, g->stream, a, q);
+        with_direction(rev, decltype(h)::value, [&](auto r) {
+            auto kernel =
+                k_walk_queue<true, decltype(h)::value, decltype(st)::value, decltype(r)::value>;
+            static const int maxb = resident_bpc(kernel);  // per instantiation
+            const int b = (bpc <= 0 || bpc > maxb) ? maxb : bpc;
+            const int64_t blocks =
+                std::min<int64_t>(ceil_div(a.num_walks, WALK_THREADS), (int64_t)g->cu_count * b);
+            hipLaunchKernelGGL(kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)),
+                               dim3(WALK_THREADS), 0, g->stream, a, q);
+        });
     });
     TW_HIP(hipGetLastError());
     return TW_OK;
 }
 
 // the batch with one thread per walk and no queue
-tw_status batch_full_walk(tw_graph* g, const WalkArgs& a, const QueueArgs& q, Error& err) {
+tw_status batch_full_walk(tw_graph* g, const WalkArgs& a, const QueueArgs& q, Error& err,
+                          bool rev = false) {
     const int hk = q.n_bias == 1 ? q.bias[0].kind : -1;
     with_kinds(hk, a.start_kind, [&](auto h, auto st) {
-        hipLaunchKernelGGL((k_walk_queue<false, decltype(h)::value, decltype(st)::value>),
-                           dim3((unsigned)ceil_div(a.num_walks, WALK_THREADS)), dim3(WALK_THREADS),
-                           0, g->stream, a, q);
+        with_direction(rev, decltype(h)::value, [&](auto r) {
+            hipLaunchKernelGGL((k_walk_queue<false, decltype(h)::value, decltype(st)::value,
+                                             decltype(r)::value>),
+                               dim3((unsigned)ceil_div(a.num_walks, WALK_THREADS)),
+                               dim3(WALK_THREADS), 0, g->stream, a, q);
+        });
     });
     TW_HIP(hipGetLastError());
     return TW_OK;
@@ -1333,15 +1366,17 @@ tw_status prepare_plain(tw_graph* g, const tw_walk_params* p, int32_t* nodes, in
 
 }  // namespace
 
-// Backward walks: the full-walk kernel k_walk_back on the in-view.
+// Backward walks on the in-view: the full-walk kernel k_walk_back (AUTO,
+// FULL_WALK) or the work queue (QUEUE).
 tw_status sample_backward(tw_graph* g, const tw_walk_params* p, int32_t* nodes, int64_t* ts,
                           int32_t* len, Error& err) {
     if (p->hop_bias.kind == TW_WEIGHT) {
         err = Error{TW_EINVAL, "sample_walks: the weight-based picker walks forward only"};
         return err.code;
     }
-    if (p->dispatch != TW_DISPATCH_AUTO && p->dispatch != TW_DISPATCH_FULL_WALK) {
-        err = Error{TW_EINVAL, "sample_walks: backward walks run on the full-walk dispatch"};
+    if (p->dispatch == TW_DISPATCH_COOP) {
+        err = Error{TW_EINVAL,
+                    "sample_walks: backward walks run on the full-walk or the queue dispatch"};
         return err.code;
     }
     tw_graph* b = nullptr;
@@ -1350,6 +1385,14 @@ tw_status sample_backward(tw_graph* g, const tw_walk_params* p, int32_t* nodes, 
     if (prepare_plain(b, p, nodes, ts, len, a, err) != TW_OK) return err.code;
     if (p->num_walks == 0) return TW_OK;
     launch_fill(b, nodes, ts, p->num_walks * (int64_t)p->max_len);
+    if (p->dispatch == TW_DISPATCH_QUEUE) {
+        // the work queue with the one hop bias
+        QueueArgs q{};
+        q.n_bias = 1;
+        q.bias[0] = a.hop;
+        q.out_slots = p->num_walks * (int64_t)p->max_len;
+        return queue_walks(b, a, q, g->auto_bpc, err, true);
+    }
     const dim3 grid((unsigned)ceil_div(p->num_walks, WALK_THREADS));
     with_kinds(a.hop.kind, a.start_kind, [&](auto h, auto sk) {
         hipLaunchKernelGGL((k_walk_back<decltype(h)::value, decltype(sk)::value>), grid,
@@ -1407,13 +1450,25 @@ tw_status sample_walks_batch(tw_graph* g, const tw_batch_params* p, int32_t* nod
         err = Error{TW_EINVAL, "sample_walks_batch: dispatch must be AUTO, QUEUE or FULL_WALK"};
         return err.code;
     }
+    if (p->direction != TW_FORWARD && p->direction != TW_BACKWARD) {
+        err = Error{TW_EINVAL, "sample_walks_batch: bad direction"};
+        return err.code;
+    }
+    const bool rev = p->direction == TW_BACKWARD;
+    if (rev && !std::isnan(wtau)) {
+        err = Error{TW_EINVAL, "sample_walks_batch: the weight-based picker walks forward only"};
+        return err.code;
+    }
     if (p->num_walks == 0) return TW_OK;
     if (!nodes || !ts || !len) {
         err = Error{TW_EINVAL, "sample_walks_batch: null output"};
         return err.code;
     }
+    // backward walks run on the in-view, on the same stream
+    tw_graph* vg = g;
+    if (rev && backward_view(g, &vg, err) != TW_OK) return err.code;
     WalkArgs a;
-    if (fill_args(g, p->num_walks, p->max_len, p->start_bias, p->start_mode, p->d_start_nodes,
+    if (fill_args(vg, p->num_walks, p->max_len, p->start_bias, p->start_mode, p->d_start_nodes,
                   p->seed, p->walk_id_base, n2v, wtau, nodes, ts, len, a, err) != TW_OK)
         return err.code;
     a.hop = make_hop_bias(p->hop_biases[0]);
@@ -1429,9 +1484,9 @@ tw_status sample_walks_batch(tw_graph* g, const tw_batch_params* p, int32_t* nod
     }
     const int64_t slots = p->out_slots > 0 ? p->out_slots : p->num_walks * (int64_t)p->max_len;
     q.out_slots = slots;
-    launch_fill(g, nodes, ts, slots);
-    if (p->dispatch == TW_DISPATCH_FULL_WALK) return batch_full_walk(g, a, q, err);
-    return queue_walks(g, a, q, g->auto_bpc, err);
+    launch_fill(vg, nodes, ts, slots);
+    if (p->dispatch == TW_DISPATCH_FULL_WALK) return batch_full_walk(vg, a, q, err, rev);
+    return queue_walks(vg, a, q, g->auto_bpc, err, rev);
 }
 
 // ---------------------------------------------------------------------------

@@ -29,7 +29,8 @@ def _mixed_graph(torch, tw, V=3000, m=40_000):
     return g, og, tau
 
 
-def _oracle_batch(og, W, L, biases, lims, bidx, seed, base, start_mode="edge", starts=None):
+def _oracle_batch(og, W, L, biases, lims, bidx, seed, base, start_mode="edge", starts=None,
+                  direction="forward"):
     """Oracle walks of a batch: every bias group at length L, then each walk
     cut to its limit."""
     nodes = np.full((W, L), -1, np.int32)
@@ -42,7 +43,7 @@ def _oracle_batch(og, W, L, biases, lims, bidx, seed, base, start_mode="edge", s
             continue
         r = og.sample_walks(W, L, hop_bias=kind, hop_tau=tau, p=p, q=q, start_mode=start_mode,
                             start_nodes=starts, seed=seed, walk_id_base=base, walk_idx=idx,
-                            with_margin=True)
+                            with_margin=True, direction=direction)
         nodes[idx], ts[idx], lens[idx], margin[idx] = r["nodes"], r["ts"], r["len"], r["margin"]
     for i in range(W):
         k = lims[i]
@@ -86,6 +87,46 @@ def test_batch_mixed_parity(ragged, start_mode, dispatch):
     print(f"batch {dispatch} ragged={ragged} {start_mode}: {same}/{W} identical, "
           f"{boundary} at a boundary")
     assert boundary <= max(2, W // 2000)
+    g.close()
+
+
+@pytest.mark.parametrize("dispatch", ["queue", "full_walk"])
+@pytest.mark.parametrize("directed", [True, False])
+def test_batch_backward_parity(directed, dispatch):
+    # backward walks of uneven lengths and mixed biases on the in-view (a
+    # directed graph builds it on this first backward call)
+    torch, tw = gpu_or_skip()
+    V, m = 3000, 40_000
+    w = synth.scaled("mixed", V, m)
+    spec = w["stream"]
+    spec.directed = directed
+    s, d, t = spec.all()
+    g = tw.Graph(V, directed=directed)
+    g.ingest_batch(*to_dev(torch, s, d, t))
+    og = oracle.OracleGraph(V, directed=directed, backward=True)
+    og.ingest_batch(s, d, t)
+    tau = 0.1 * float(t.max() - t.min())
+    biases = synth.mixed_biases(tau)
+    W, L, seed, base = 12_000, 24, 17, 300
+    lims = synth.walk_lengths(5, W, 1, L)
+    bidx = ((base + np.arange(W)) % len(biases)).astype(np.uint8)
+    nodes, ts, lens, _ = g.sample_walks_batch(W, L, biases, max_lens=to_dev(torch, lims)[0],
+                                              seed=seed, walk_id_base=base, dispatch=dispatch,
+                                              direction="backward")
+    g.sync()
+    ref = _oracle_batch(og, W, L, biases, lims, bidx, seed, base, direction="backward")
+    same, boundary = compare_walks((nodes.cpu().numpy(), ts.cpu().numpy(), lens.cpu().numpy()),
+                                   ref, exact=False,
+                                   label=f"backward batch {dispatch} directed={directed}",
+                                   kind="mixed")
+    print(f"backward batch {dispatch} directed={directed}: {same}/{W} identical, "
+          f"{boundary} at a boundary; mean length {float(ref['len'].mean()):.2f}")
+    assert boundary <= max(2, W // 2000)
+    assert float(ref["len"].mean()) > 2.5
+    # the weight-based picker walks forward only
+    with pytest.raises(tw.TwError) as ei:
+        g.sample_walks_batch(10, 5, [("weight", 5.0, 1.0, 1.0)], direction="backward")
+    assert ei.value.code == tw.TW_EINVAL
     g.close()
 
 

@@ -553,7 +553,11 @@ def test_backward_walk_parity(ci, directed):
               seed=seed, walk_id_base=base)
     nodes, tts, lens = g.sample_walks(W, L, start_nodes=to_dev(torch, starts)[0],
                                       direction="backward", **kw)
+    # the work queue runs the same walks
+    qn, qt, ql = g.sample_walks(W, L, start_nodes=to_dev(torch, starts)[0],
+                                direction="backward", dispatch="queue", **kw)
     g.sync()
+    assert torch.equal(qn, nodes) and torch.equal(qt, tts) and torch.equal(ql, lens)
     r = og.sample_walks(W, L, start_nodes=starts, with_margin=True, direction="backward", **kw)
     exact = hk in ("uniform", "linear") and sk in ("uniform", "linear")
     same, boundary = compare_walks((nodes.cpu().numpy(), tts.cpu().numpy(), lens.cpu().numpy()),
