@@ -288,6 +288,41 @@ __device__ __forceinline__ void finish_row(RowChunk& c, int32_t* __restrict__ on
     for (; at < L; at += 4) pad.store(on, ot, at);
 }
 
+// A lane's current four output slots in LDS, slot p in row p & 3 of the
+// lane's column (registers the FP64 pickers need instead): when slots
+// 4k..4k+3 are complete they leave as one 16-byte store of nodes and two of
+// timestamps. Each lane touches its own column only.
+struct RowRing {
+    int32_t (*n)[WALK_THREADS];
+    int64_t (*t)[WALK_THREADS];
+    int tid;
+    __device__ __forceinline__ void put(int32_t p, int32_t v, int64_t x) const {
+        n[p & 3][tid] = v;
+        t[p & 3][tid] = x;
+    }
+    // slots [at, at + 4) of a row; both pointers 16-byte aligned there
+    __device__ __forceinline__ void flush(int32_t* __restrict__ on, int64_t* __restrict__ ot,
+                                          int32_t at) const {
+        *reinterpret_cast<int4*>(on + at) = make_int4(n[0][tid], n[1][tid], n[2][tid], n[3][tid]);
+        *reinterpret_cast<longlong2*>(ot + at) = make_longlong2(t[0][tid], t[1][tid]);
+        *reinterpret_cast<longlong2*>(ot + at + 2) = make_longlong2(t[2][tid], t[3][tid]);
+    }
+    // ends a row of len slots (stored up to the last multiple of 4): the
+    // partial chunk is completed with padding, then every slot up to L (a
+    // multiple of 4) is padded with 16-byte stores
+    __device__ __forceinline__ void finish(int32_t* __restrict__ on, int64_t* __restrict__ ot,
+                                           int32_t len, int32_t L) const {
+        int32_t at = len & ~3;
+        if (len & 3) {
+            for (int32_t k = len & 3; k < 4; ++k) put(k, -1, TS_NONE);
+            flush(on, ot, at);
+            at += 4;
+        }
+        const RowChunk pad;
+        for (; at < L; at += 4) pad.store(on, ot, at);
+    }
+};
+
 // One full walk per thread: the full-walk baseline (Sec. "The Full-Walk
 // Baseline"). The walk is bound by dependent random loads, so waves in flight
 // count: the exponential pickers' FP64 code is held to 5 waves per SIMD and
@@ -313,18 +348,10 @@ k_walk_full(const WalkArgs a) {
     // 100M-edge graph)
     __shared__ int32_t ring_n[4][WALK_THREADS];
     __shared__ int64_t ring_t[4][WALK_THREADS];
-    const int tid = threadIdx.x;
-    auto flush = [&](int32_t at) {
-        *reinterpret_cast<int4*>(out_n + at) =
-            make_int4(ring_n[0][tid], ring_n[1][tid], ring_n[2][tid], ring_n[3][tid]);
-        *reinterpret_cast<longlong2*>(out_t + at) = make_longlong2(ring_t[0][tid], ring_t[1][tid]);
-        *reinterpret_cast<longlong2*>(out_t + at + 2) = make_longlong2(ring_t[2][tid], ring_t[3][tid]);
-    };
+    const RowRing ring{ring_n, ring_t, (int)threadIdx.x};
     if (ROWS) {
-        ring_n[0][tid] = st.len >= 1 ? st.first : -1;
-        ring_t[0][tid] = TS_NONE;
-        ring_n[1][tid] = st.len >= 2 ? st.cur : -1;
-        ring_t[1][tid] = st.len >= 2 ? st.t : TS_NONE;
+        ring.put(0, st.len >= 1 ? st.first : -1, TS_NONE);
+        ring.put(1, st.len >= 2 ? st.cur : -1, st.len >= 2 ? st.t : TS_NONE);
     }
     const HopBias hb = fixed_hop<HK>(a.hop);
     int32_t len = st.len, cur = st.cur, prev = st.prev;
@@ -338,9 +365,8 @@ k_walk_full(const WalkArgs a) {
             int32_t nx;
             if (!hop_pick(a, hb, a.seed, r, gc, id, hop, prev, p, nx)) break;
             if (ROWS) {
-                ring_n[len & 3][tid] = nx;
-                ring_t[len & 3][tid] = p.t;
-                if ((len & 3) == 3) flush(len - 3);
+                ring.put(len, nx, p.t);
+                if ((len & 3) == 3) ring.flush(out_n, out_t, len - 3);
             } else {
                 out_n[len] = nx;
                 out_t[len] = p.t;
@@ -351,19 +377,7 @@ k_walk_full(const WalkArgs a) {
             tcur = p.t;
         }
     }
-    if (ROWS) {
-        int32_t at = len & ~3;
-        if (len & 3) {
-            for (int32_t k = len & 3; k < 4; ++k) {
-                ring_n[k][tid] = -1;
-                ring_t[k][tid] = TS_NONE;
-            }
-            flush(at);
-            at += 4;
-        }
-        const RowChunk pad;
-        for (; at < a.L; at += 4) pad.store(out_n, out_t, at);
-    }
+    if (ROWS) ring.finish(out_n, out_t, len, a.L);
     finish_walk(a, w, len);
 }
 
@@ -593,11 +607,19 @@ struct Live {
 // without the start pick, so a lane that takes a walk only loads its state
 // and the kernel keeps the registers of the full-walk kernel. ROWS: each
 // lane writes its walk's whole output row, four slots per store, padding
-// included (as k_walk_full); otherwise the rows were pre-filled.
+// included; otherwise the rows were pre-filled. node2vec and mixed kinds
+// keep a walk's current four slots in an LDS ring (as k_walk_full) and are
+// held to 4 waves per SIMD: 4.47 ms against 5.00 with the slots in
+// registers at 3 waves (2M walks of length 40, 100M-edge graph). The other
+// kinds keep the slots in registers at the occupancy their registers give:
+// there the ring and more waves measured slower (exponential 5.33 against
+// 4.98 ms at 5 waves, linear 2.45 against 2.30 at 8).
 template <int HK, bool ROWS>
 __global__ void __launch_bounds__(WALK_THREADS)
+__attribute__((amdgpu_waves_per_eu(HK == TW_NODE2VEC || HK < 0 ? 4 : 1)))
 k_walk_hops(const WalkArgs a, Live live, const int32_t* __restrict__ prev_of,
             const uint32_t* __restrict__ n_live_p, unsigned long long* counters) {
+    constexpr bool RING = HK == TW_NODE2VEC || HK < 0;
     const int lane = threadIdx.x & 63;
     const int64_t W = *n_live_p;
     const int64_t slice_len = (W + QUEUE_SLICES - 1) / QUEUE_SLICES;
@@ -607,9 +629,16 @@ k_walk_hops(const WalkArgs a, Live live, const int32_t* __restrict__ prev_of,
     uint64_t id = 0, hop = 0;
     int32_t len = 0, cur = 0, prev = 0;
     int64_t tcur = 0;
+    __shared__ int32_t ring_n[RING ? 4 : 1][WALK_THREADS];
+    __shared__ int64_t ring_t[RING ? 4 : 1][WALK_THREADS];
+    const RowRing ring{ring_n, ring_t, (int)threadIdx.x};
+    RowChunk c;
+    // the walk's output row: kept as pointers (fewer instructions), or
+    // recomputed from w where registers are short (RING)
     int32_t* out_n = nullptr;
     int64_t* out_t = nullptr;
-    RowChunk c;
+    auto row_n = [&]() { return RING ? a.nodes + w * (int64_t)a.L : out_n; };
+    auto row_t = [&]() { return RING ? a.ts + w * (int64_t)a.L : out_t; };
     const HopBias hb = fixed_hop<HK>(a.hop);
     while (true) {
         const uint64_t idle = __ballot(w < 0);
@@ -634,12 +663,17 @@ k_walk_hops(const WalkArgs a, Live live, const int32_t* __restrict__ prev_of,
                     tcur = (int64_t)live.t[j];
                     prev = prev_of[w];
                     id = a.base + (uint64_t)w;
-                    out_n = a.nodes + w * (int64_t)a.L;
-                    out_t = a.ts + w * (int64_t)a.L;
+                    if (!RING) {
+                        out_n = a.nodes + w * (int64_t)a.L;
+                        out_t = a.ts + w * (int64_t)a.L;
+                    }
                     len = 2;
                     hop = 1;
-                    if (ROWS) {
-                        // positions 0 and 1: the start edge's source and target
+                    // positions 0 and 1: the start edge's source and target
+                    if (ROWS && RING) {
+                        ring.put(0, prev, TS_NONE);
+                        ring.put(1, cur, tcur);
+                    } else if (ROWS) {
                         c = RowChunk();
                         c.push(prev, TS_NONE);
                         c.push(cur, tcur);
@@ -663,12 +697,15 @@ k_walk_hops(const WalkArgs a, Live live, const int32_t* __restrict__ prev_of,
                 Pick p;
                 int32_t nx;
                 if (hop_pick(a, hb, a.seed, r, gc, id, hop, prev, p, nx)) {
-                    if (ROWS) {
+                    if (ROWS && RING) {
+                        ring.put(len, nx, p.t);
+                        if ((len & 3) == 3) ring.flush(row_n(), row_t(), len - 3);
+                    } else if (ROWS) {
                         c.push(nx, p.t);
-                        if (((len + 1) & 3) == 0) c.store(out_n, out_t, len - 3);
+                        if ((len & 3) == 3) c.store(row_n(), row_t(), len - 3);
                     } else {
-                        out_n[len] = nx;
-                        out_t[len] = p.t;
+                        row_n()[len] = nx;
+                        row_t()[len] = p.t;
                     }
                     ++len;
                     ++hop;
@@ -679,7 +716,8 @@ k_walk_hops(const WalkArgs a, Live live, const int32_t* __restrict__ prev_of,
                 }
             }
             if (done) {
-                if (ROWS) finish_row(c, out_n, out_t, len, a.L);
+                if (ROWS && RING) ring.finish(row_n(), row_t(), len, a.L);
+                else if (ROWS) finish_row(c, row_n(), row_t(), len, a.L);
                 a.len[w] = len;
                 w = -1;
             }
