@@ -91,8 +91,25 @@ __global__ void k_scan_partials(V* part, int64_t nb, V* total) {
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
-template <typename In, typename V>
-__global__ void k_scan_down(const In* in, V* out, int64_t n, const V* __restrict__ part) {
+// sum of part[0, b) over the block (every thread gets it)
+template <typename V>
+__device__ inline V block_prefix_of(const V* __restrict__ part, int64_t b) {
+    V p = 0;
+    for (int64_t i = threadIdx.x; i < b; i += SCAN_THREADS) p += part[i];
+    V all;
+    block_excl_scan(p, &all);
+    return all;
+}
+
+// SUM: the block's prefix is summed from the raw partials of the blocks
+// before it (one launch fewer; for at most SCAN_SUM_MAX_BLOCKS blocks, whose
+// partials stay in L2), and the last block writes the total (nullable);
+// otherwise part holds the scanned partials.
+constexpr int64_t SCAN_SUM_MAX_BLOCKS = 4096;
+
+template <typename In, typename V, bool SUM>
+__global__ void k_scan_down(const In* in, V* out, int64_t n, const V* __restrict__ part,
+                            V* total) {
     __shared__ V tile[SCAN_TILE];
     int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
     for (int j = 0; j < SCAN_ITEMS; ++j) {
@@ -108,7 +125,10 @@ __global__ void k_scan_down(const In* in, V* out, int64_t n, const V* __restrict
         s += tile[threadIdx.x * SCAN_ITEMS + j];
     }
     V tot;
-    V pre = block_excl_scan(s, &tot) + part[blockIdx.x];
+    const V ex = block_excl_scan(s, &tot);
+    const V bp = SUM ? block_prefix_of(part, blockIdx.x) : part[blockIdx.x];
+    const V pre = ex + bp;
+    if (SUM && total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total = bp + tot;
     for (int j = 0; j < SCAN_ITEMS; ++j) tile[threadIdx.x * SCAN_ITEMS + j] = pre + loc[j];
     __syncthreads();
     for (int j = 0; j < SCAN_ITEMS; ++j) {
@@ -121,8 +141,8 @@ __global__ void k_scan_down(const In* in, V* out, int64_t n, const V* __restrict
 template <typename V>
 __global__ void k_set(V* p, V v) { *p = v; }
 
-// Four u32 scans at once (array blockIdx.y of the launch): the same three
-// steps as above, one launch each instead of one per array.
+// Four u32 scans at once (array blockIdx.y of the launch): the same steps
+// as above, one launch each instead of one per array.
 struct Scan4 {
     const uint32_t* in[4];
     uint32_t* out[4];
@@ -162,6 +182,7 @@ __global__ void k_scan4_partials(const Scan4 a, uint32_t* part, int64_t nb) {
     if (threadIdx.x == 0 && a.total[y]) *a.total[y] = carry;
 }
 
+template <bool SUM>
 __global__ void k_scan4_down(const Scan4 a, int64_t n, const uint32_t* __restrict__ part,
                              int64_t nb) {
     __shared__ uint32_t tile[SCAN_TILE];
@@ -182,7 +203,12 @@ __global__ void k_scan4_down(const Scan4 a, int64_t n, const uint32_t* __restric
         s += tile[threadIdx.x * SCAN_ITEMS + j];
     }
     uint32_t tot;
-    uint32_t pre = block_excl_scan(s, &tot) + part[y * nb + blockIdx.x];
+    const uint32_t ex = block_excl_scan(s, &tot);
+    const uint32_t bp =
+        SUM ? block_prefix_of(part + y * nb, blockIdx.x) : part[y * nb + blockIdx.x];
+    const uint32_t pre = ex + bp;
+    if (SUM && a.total[y] && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1)
+        *a.total[y] = bp + tot;
     for (int j = 0; j < SCAN_ITEMS; ++j) tile[threadIdx.x * SCAN_ITEMS + j] = pre + loc[j];
     __syncthreads();
     for (int j = 0; j < SCAN_ITEMS; ++j) {
@@ -219,17 +245,25 @@ struct GroupStartOp {
 // atomics in the histogram pass measured slower on source-id keys, whose
 // skew makes many lanes of a wavefront hit one counter.)
 
-constexpr int RS_RADIX = 256;  // one digit per thread of the workgroup
-static_assert(RS_RADIX == RS_THREADS, "digit tables are indexed by thread");
+// Digits of up to 8 bits (256 digits, one per thread of the workgroup) or,
+// for sorts whose key bits take one pass fewer that way, up to 9 bits (512
+// digits, two per thread: 2 tid and 2 tid + 1).
+template <int RADIX>
+struct Digits {
+    static_assert(RADIX == RS_THREADS || RADIX == 2 * RS_THREADS, "one or two digits a thread");
+    static constexpr int PER = RADIX / RS_THREADS;
+    static constexpr int BITS = RADIX == 512 ? 9 : 8;
+};
 
-// lanes of the wavefront whose digit (of nbits <= 8 bits) equals this lane's,
-// among valid lanes: one ballot per digit bit; a lane collects the lanes
-// whose bit differs from its own and keeps the others
+// lanes of the wavefront whose digit (of nbits <= MAXB bits) equals this
+// lane's, among valid lanes: one ballot per digit bit; a lane collects the
+// lanes whose bit differs from its own and keeps the others
+template <int MAXB>
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, int nbits) {
     const uint64_t live = __ballot(valid);
     uint64_t differ = 0;
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < MAXB; ++b) {
         if (b < nbits) {
             // all ones when the bit is set (a signed one-bit field extract)
             const uint32_t m = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
@@ -240,15 +274,18 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, int nbit
     return live & ~differ;
 }
 
-template <typename K, int ITEMS>
+template <typename K, int ITEMS, int RADIX>
 __global__ void __launch_bounds__(RS_THREADS)
 k_rs_hist(const K* __restrict__ keys, int64_t n, int shift, int nbits,
           uint32_t* __restrict__ hist, int64_t nblocks) {
+    using D = Digits<RADIX>;
     constexpr int TILE = RS_THREADS * ITEMS, WAVE_ITEMS = TILE / RS_WAVES;
-    __shared__ uint32_t cnt[RS_WAVES][RS_RADIX];
+    __shared__ uint32_t cnt[RS_WAVES][RADIX];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 #pragma unroll
-    for (int w = 0; w < RS_WAVES; ++w) cnt[w][tid] = 0;
+    for (int w = 0; w < RS_WAVES; ++w)
+#pragma unroll
+        for (int q = 0; q < D::PER; ++q) cnt[w][tid * D::PER + q] = 0;
     __syncthreads();
     const uint32_t mask = (1u << nbits) - 1u;
     const uint64_t lower = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -264,14 +301,18 @@ k_rs_hist(const K* __restrict__ keys, int64_t n, int shift, int nbits,
     for (int r = 0; r < ITEMS; ++r) {
         const bool valid = wbase + r * 64 + lane < n;
         const uint32_t d = (uint32_t)(k[r] >> shift) & mask;
-        const uint64_t peers = digit_peers(d, valid, nbits);
+        const uint64_t peers = digit_peers<D::BITS>(d, valid, nbits);
         if (valid && (peers & lower) == 0) cnt[wave][d] += (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    uint32_t c = 0;
 #pragma unroll
-    for (int w = 0; w < RS_WAVES; ++w) c += cnt[w][tid];
-    hist[(int64_t)tid * nblocks + tile] = c;
+    for (int q = 0; q < D::PER; ++q) {
+        const int d = tid * D::PER + q;
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < RS_WAVES; ++w) c += cnt[w][d];
+        hist[(int64_t)d * nblocks + tile] = c;
+    }
 }
 
 // Scatter one tile to its stable output slots. offs[d * nblocks + b] is the
@@ -282,26 +323,31 @@ k_rs_hist(const K* __restrict__ keys, int64_t n, int shift, int nbits,
 // area is as wide as the widest of key and 32-bit value. PACK (with W64):
 // the 32-bit value and the 64-bit payload (a timestamp) are read and leave
 // packed as one 64-bit payload, (v64 - pack_base) << 32 | val.
-template <typename K, bool W64, bool PACK, int ITEMS>
+template <typename K, bool W64, bool PACK, int ITEMS, int RADIX>
 __global__ void __launch_bounds__(RS_THREADS)
 k_rs_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
              const uint64_t* __restrict__ v64, int64_t n, int shift, int nbits,
              const uint32_t* __restrict__ offs, int64_t nblocks, K* __restrict__ keys_out,
              uint32_t* __restrict__ vals_out, uint64_t* __restrict__ v64_out, uint64_t pack_base) {
     static_assert(W64 || !PACK, "packing needs the 64-bit payload");
+    using D = Digits<RADIX>;
     constexpr int TILE = RS_THREADS * ITEMS, WAVE_ITEMS = TILE / RS_WAVES;
     using Stage = std::conditional_t<W64 || sizeof(K) == 8, uint64_t, uint32_t>;
-    __shared__ uint32_t cnt[RS_WAVES][RS_RADIX];  // wave counts, then wave starts
-    __shared__ uint32_t lstart[RS_RADIX];         // tile-local first slot of each digit
-    __shared__ uint32_t gstart[RS_RADIX];         // output slot of that first item
+    __shared__ uint32_t cnt[RS_WAVES][RADIX];  // wave counts, then wave starts
+    __shared__ uint32_t lstart[RADIX];         // tile-local first slot of each digit
+    __shared__ uint32_t gstart[RADIX];         // output slot of that first item
     __shared__ Stage stage[TILE];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t mask = (1u << nbits) - 1u;
     const uint64_t lower = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint32_t tile = xcd_tile(blockIdx.x, (uint32_t)nblocks);
 #pragma unroll
-    for (int w = 0; w < RS_WAVES; ++w) cnt[w][tid] = 0;
-    gstart[tid] = offs[(int64_t)tid * nblocks + tile];
+    for (int q = 0; q < D::PER; ++q) {
+        const int d = tid * D::PER + q;
+#pragma unroll
+        for (int w = 0; w < RS_WAVES; ++w) cnt[w][d] = 0;
+        gstart[d] = offs[(int64_t)d * nblocks + tile];
+    }
     __syncthreads();
     const int64_t tile0 = (int64_t)tile * TILE;
     const int64_t wbase = tile0 + (int64_t)wave * WAVE_ITEMS;
@@ -325,7 +371,7 @@ k_rs_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
     for (int r = 0; r < ITEMS; ++r) {
         const bool valid = wbase + r * 64 + lane < n;
         const uint32_t d = (uint32_t)(k[r] >> shift) & mask;
-        const uint64_t peers = digit_peers(d, valid, nbits);
+        const uint64_t peers = digit_peers<D::BITS>(d, valid, nbits);
         const uint32_t before = cnt[wave][d];
         lp[r] = before + (uint32_t)__popcll(peers & lower);
         if (valid && (peers & lower) == 0) cnt[wave][d] = before + (uint32_t)__popcll(peers);
@@ -333,17 +379,27 @@ k_rs_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
     __syncthreads();
 
     // digit starts in the tile (scan over digits), then each wavefront's start
-    uint32_t wpre[RS_WAVES], tot = 0;
+    uint32_t wpre[D::PER][RS_WAVES], tot[D::PER], sum = 0;
 #pragma unroll
-    for (int w = 0; w < RS_WAVES; ++w) {
-        wpre[w] = tot;
-        tot += cnt[w][tid];
+    for (int q = 0; q < D::PER; ++q) {
+        tot[q] = 0;
+#pragma unroll
+        for (int w = 0; w < RS_WAVES; ++w) {
+            wpre[q][w] = tot[q];
+            tot[q] += cnt[w][tid * D::PER + q];
+        }
+        sum += tot[q];
     }
     uint32_t all;
-    const uint32_t ls = block_excl_scan<uint32_t>(tot, &all);
-    lstart[tid] = ls;
+    uint32_t ls = block_excl_scan<uint32_t>(sum, &all);
 #pragma unroll
-    for (int w = 0; w < RS_WAVES; ++w) cnt[w][tid] = ls + wpre[w];
+    for (int q = 0; q < D::PER; ++q) {
+        const int d = tid * D::PER + q;
+        lstart[d] = ls;
+#pragma unroll
+        for (int w = 0; w < RS_WAVES; ++w) cnt[w][d] = ls + wpre[q][w];
+        ls += tot[q];
+    }
     __syncthreads();
 
     // keys: into LDS in digit order, then out; each thread keeps the output
@@ -438,7 +494,9 @@ hipError_t radix_sort_impl(const K* kin0, const uint32_t* vin0, const uint64_t* 
         }
         return hipSuccess;
     }
-    const int passes = (int)ceil_div(bit_hi - bit_lo, 8);
+    // 9-bit digits where they save a pass (26-bit node ids: 3 passes, not 4)
+    const bool wide = ceil_div(bit_hi - bit_lo, 9) < ceil_div(bit_hi - bit_lo, 8);
+    const int passes = (int)ceil_div(bit_hi - bit_lo, wide ? 9 : 8);
     const bool in_place = (const void*)kin0 == (const void*)kout;
     if ((e = ensure(ws.keys_alt, sizeof(K) * n, s)) != hipSuccess) return e;
     if (has_v && (e = ensure(ws.vals_alt, sizeof(uint32_t) * n, s)) != hipSuccess) return e;
@@ -449,10 +507,11 @@ hipError_t radix_sort_impl(const K* kin0, const uint32_t* vin0, const uint64_t* 
     // destination of pass p (0-based): the outputs when (passes - 1 - p) is
     // even, else the alternates; an in-place sort must start in the alternates
     const bool copy_back = in_place && (passes % 2 == 1);
-    auto run = [&](auto items) -> hipError_t {
+    auto run = [&](auto items, auto radix) -> hipError_t {
         constexpr int I = decltype(items)::value;
+        constexpr int R = decltype(radix)::value;
         const int64_t nblocks = ceil_div(n, (int64_t)RS_THREADS * I);
-        hipError_t r = ensure(ws.hist, sizeof(uint32_t) * 256 * nblocks, s);
+        hipError_t r = ensure(ws.hist, sizeof(uint32_t) * R * nblocks, s);
         if (r != hipSuccess) return r;
         uint32_t* hist = ws.hist.as<uint32_t>();
         const K* ki = kin0;
@@ -468,20 +527,20 @@ hipError_t radix_sort_impl(const K* kin0, const uint32_t* vin0, const uint64_t* 
             K* ko = to_out ? kout : ka;
             uint32_t* vo = to_out ? vout : va;
             uint64_t* wo = to_out ? wout : wa;
-            hipLaunchKernelGGL((k_rs_hist<K, I>), dim3(nblocks), dim3(RS_THREADS), 0, s, ki, n,
-                               sh, nb, hist, nblocks);
-            if ((r = scan_exclusive_u32(hist, hist, 256 * nblocks, nullptr, ws, s)) != hipSuccess)
+            hipLaunchKernelGGL((k_rs_hist<K, I, R>), dim3(nblocks), dim3(RS_THREADS), 0, s, ki,
+                               n, sh, nb, hist, nblocks);
+            if ((r = scan_exclusive_u32(hist, hist, R * nblocks, nullptr, ws, s)) != hipSuccess)
                 return r;
             if (pack && p == 0)
-                hipLaunchKernelGGL((k_rs_scatter<K, true, true, I>), dim3(nblocks),
+                hipLaunchKernelGGL((k_rs_scatter<K, true, true, I, R>), dim3(nblocks),
                                    dim3(RS_THREADS), 0, s, ki, vi, wi, n, sh, nb, hist, nblocks,
                                    ko, nullptr, wo, pack_base);
             else if (has_w)
-                hipLaunchKernelGGL((k_rs_scatter<K, true, false, I>), dim3(nblocks),
+                hipLaunchKernelGGL((k_rs_scatter<K, true, false, I, R>), dim3(nblocks),
                                    dim3(RS_THREADS), 0, s, ki, has_v ? vi : nullptr, wi, n, sh,
                                    nb, hist, nblocks, ko, vo, wo, 0ull);
             else
-                hipLaunchKernelGGL((k_rs_scatter<K, false, false, I>), dim3(nblocks),
+                hipLaunchKernelGGL((k_rs_scatter<K, false, false, I, R>), dim3(nblocks),
                                    dim3(RS_THREADS), 0, s, ki, has_v ? vi : nullptr, nullptr, n,
                                    sh, nb, hist, nblocks, ko, vo, nullptr, 0ull);
             ki = ko;
@@ -490,8 +549,12 @@ hipError_t radix_sort_impl(const K* kin0, const uint32_t* vin0, const uint64_t* 
         }
         return hipSuccess;
     };
-    e = n <= RS_SMALL ? run(std::integral_constant<int, RS_ITEMS_SMALL>{})
-                      : run(std::integral_constant<int, RS_ITEMS>{});
+    using R8 = std::integral_constant<int, 256>;
+    using R9 = std::integral_constant<int, 512>;
+    using Small = std::integral_constant<int, RS_ITEMS_SMALL>;
+    using Large = std::integral_constant<int, RS_ITEMS>;
+    if (n <= RS_SMALL) e = wide ? run(Small{}, R9{}) : run(Small{}, R8{});
+    else e = wide ? run(Large{}, R9{}) : run(Large{}, R8{});
     if (e != hipSuccess) return e;
     if (copy_back) {
         if ((e = hipMemcpyAsync(kout, ka, sizeof(K) * n, hipMemcpyDeviceToDevice, s))) return e;
@@ -542,8 +605,14 @@ hipError_t scan_core(const In* in, V* out, int64_t n, V* total, V* part, hipStre
     }
     const int64_t nb = ceil_div(n, SCAN_TILE);
     hipLaunchKernelGGL((k_scan_reduce<In, V>), dim3(nb), dim3(SCAN_THREADS), 0, s, in, n, part);
-    hipLaunchKernelGGL(k_scan_partials<V>, dim3(1), dim3(SCAN_THREADS), 0, s, part, nb, total);
-    hipLaunchKernelGGL((k_scan_down<In, V>), dim3(nb), dim3(SCAN_THREADS), 0, s, in, out, n, part);
+    if (nb <= SCAN_SUM_MAX_BLOCKS) {
+        hipLaunchKernelGGL((k_scan_down<In, V, true>), dim3(nb), dim3(SCAN_THREADS), 0, s, in,
+                           out, n, part, total);
+    } else {
+        hipLaunchKernelGGL(k_scan_partials<V>, dim3(1), dim3(SCAN_THREADS), 0, s, part, nb, total);
+        hipLaunchKernelGGL((k_scan_down<In, V, false>), dim3(nb), dim3(SCAN_THREADS), 0, s, in,
+                           out, n, part, nullptr);
+    }
     return hipGetLastError();
 }
 
@@ -589,9 +658,14 @@ hipError_t scan_exclusive_u32x4(const uint32_t* const in[4], uint32_t* const out
     uint32_t* part = ws.scan_part.as<uint32_t>();
     hipLaunchKernelGGL(k_scan4_reduce, dim3((unsigned)nb, 4), dim3(SCAN_THREADS), 0, s, a, n, part,
                        nb);
-    hipLaunchKernelGGL(k_scan4_partials, dim3(4), dim3(SCAN_THREADS), 0, s, a, part, nb);
-    hipLaunchKernelGGL(k_scan4_down, dim3((unsigned)nb, 4), dim3(SCAN_THREADS), 0, s, a, n, part,
-                       nb);
+    if (nb <= SCAN_SUM_MAX_BLOCKS) {
+        hipLaunchKernelGGL(k_scan4_down<true>, dim3((unsigned)nb, 4), dim3(SCAN_THREADS), 0, s, a,
+                           n, part, nb);
+    } else {
+        hipLaunchKernelGGL(k_scan4_partials, dim3(4), dim3(SCAN_THREADS), 0, s, a, part, nb);
+        hipLaunchKernelGGL(k_scan4_down<false>, dim3((unsigned)nb, 4), dim3(SCAN_THREADS), 0, s, a,
+                           n, part, nb);
+    }
     return hipGetLastError();
 }
 

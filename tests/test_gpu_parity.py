@@ -101,6 +101,21 @@ def test_index_parity_multi_tile_ragged():
     g.close()
 
 
+@pytest.mark.parametrize("V,spread", [(300, 200), (100_003, 60_000), (5003, 50_000_000)])
+def test_index_parity_nine_bit_digits(V, spread):
+    # sorts whose key bits take one radix pass fewer with 9-bit digits: node
+    # ids of 9 and 17 bits, timestamp keys of 17 and 27 bits (unsorted batches)
+    torch, tw = gpu_or_skip()
+    rng = np.random.default_rng(V + spread)
+    g = tw.Graph(V)
+    og = oracle.OracleGraph(V)
+    for s, d, t in _stream_batches(rng, V, 4, 40_000, 90_001, 1000, spread):
+        s_, d_, t_ = to_dev(torch, s, d, t)
+        assert g.ingest_batch(s_, d_, t_) == og.ingest_batch(s, d, t)
+    _views_equal(g, og)
+    g.close()
+
+
 def test_ingest_rejects_out_of_range_ids():
     torch, tw = gpu_or_skip()
     g = tw.Graph(10)
