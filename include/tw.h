@@ -275,6 +275,21 @@ tw_status tw_sample_walks(tw_graph* g, const tw_walk_params* params, int32_t* d_
 tw_status tw_last_update(const tw_graph* g, int64_t out[4]);
 
 /*
+ * Where the graph's device buffers lie, as one value, with whether the
+ * node2vec pair table and the weight-based picker's weights are current. A
+ * walk launch (tw_sample_walks with the full-walk or queue dispatch,
+ * tw_sample_walks_batch, tw_sample_walks_noalloc) recorded in a HIP graph
+ * reads the window from device-side state that every update keeps current:
+ * replayed after later tw_ingest_batch / tw_evict_before calls it gives the
+ * walks an eager call would give, while this value equals the one read when
+ * the launch was recorded. When it differs (a buffer grew or moved, the
+ * window moved, the pair table or the weights were dropped), record the
+ * launch again after an eager call. Host-side, no synchronisation. TW_EINVAL
+ * for null arguments.
+ */
+tw_status tw_walk_layout(const tw_graph* g, uint64_t* out);
+
+/*
  * Counters of the last index update (ingest_batch or evict_before), for
  * measurement: out[0] nodes whose run in the node-and-timestamp view changed
  * (appended, evicted or rewritten), out[1] node-view edges written, out[2]

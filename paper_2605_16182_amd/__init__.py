@@ -113,6 +113,7 @@ def lib():
         "tw_sample_walks_noalloc": ([P, _c.POINTER(_WalkParams), P, P, P], _c.c_int),
         "tw_set_ingest_weights": ([P, _c.c_double], _c.c_int),
         "tw_last_update": ([P, _c.POINTER(I64)], _c.c_int),
+        "tw_walk_layout": ([P, _c.POINTER(_c.c_uint64)], _c.c_int),
         "tw_get_tuning": ([P, _c.POINTER(_Tuning)], _c.c_int),
         "tw_set_tuning": ([P, _c.POINTER(_Tuning)], _c.c_int),
         "tw_sync": ([P], _c.c_int),
@@ -401,6 +402,13 @@ class Graph:
         _check(self._lib.tw_export_views(self._h, *(_ptr(t[k]) if t[k].numel() else None
                                                     for k in order)))
         return t
+
+    def walk_layout(self) -> int:
+        """Where the device buffers lie (see tw_walk_layout): a recorded walk
+        launch replays correctly while this value is unchanged."""
+        out = _c.c_uint64(0)
+        _check(self._lib.tw_walk_layout(self._h, _c.byref(out)))
+        return int(out.value)
 
     def index_stats(self) -> dict:
         """Counters of the last index update (see tw_index_stats)."""

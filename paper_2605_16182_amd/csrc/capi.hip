@@ -3,6 +3,8 @@
 #include <new>
 #include <string>
 
+#include <cstring>
+
 #include "tw_internal.h"
 
 namespace {
@@ -341,6 +343,37 @@ tw_status tw_last_update(const tw_graph* g, int64_t out[4]) {
     out[1] = g->last.dropped_late;
     out[2] = g->last.evicted;
     out[3] = g->m;
+    return TW_OK;
+}
+
+namespace {
+
+// FNV-1a over the words that decide what a recorded walk launch reads
+uint64_t layout_of(const tw_graph* g) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t x) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= (x >> (8 * k)) & 0xffu;
+            h *= 1099511628211ull;
+        }
+    };
+    for (const tw::DevBuf* b : const_cast<tw_graph*>(g)->buffers())
+        mix(reinterpret_cast<uintptr_t>(b->p));
+    mix(g->adj_ready ? 1u : 0u);
+    mix(g->adj_mask);
+    mix(g->w_ready ? 1u : 0u);
+    uint64_t ws;
+    std::memcpy(&ws, &g->w_scale, sizeof ws);
+    mix(ws);
+    mix(g->rev ? layout_of(g->rev) : 0u);
+    return h;
+}
+
+}  // namespace
+
+tw_status tw_walk_layout(const tw_graph* g, uint64_t* out) {
+    if (!g || !out) return fail(TW_EINVAL, "tw_walk_layout: null argument");
+    *out = layout_of(g);
     return TW_OK;
 }
 

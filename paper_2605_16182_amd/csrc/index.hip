@@ -313,13 +313,19 @@ __global__ void k_widen(const uint32_t* __restrict__ in, int64_t n, int64_t* __r
 
 // the window's first and last timestamps and its global group count: the
 // groups just counted (all of them when gg_full, else those appended after
-// the gg_kept surviving ones)
+// the gg_kept surviving ones); and where the window lies in the timestamp
+// view (win: e_base, m, gg_base), so that a walk launch recorded in a HIP
+// graph reads the current window when it is replayed
 __global__ void k_window_summary(const int64_t* __restrict__ ts, int64_t m, int64_t* out,
                                  int gg_full, int64_t gg_kept, const uint32_t* groups,
-                                 int64_t* gg_out) {
+                                 int64_t* gg_out, int64_t e_base, int64_t gg_base,
+                                 int64_t* win) {
     out[0] = m > 0 ? ts[0] : 0;
     out[1] = m > 0 ? ts[m - 1] : 0;
     *gg_out = gg_full ? (int64_t)*groups : gg_kept + (int64_t)*groups;
+    win[0] = e_base;
+    win[1] = m;
+    win[2] = gg_base;
 }
 
 uint32_t* u32_slot(tw_graph* g, int k) { return g->scal.as<uint32_t>() + k; }
@@ -417,7 +423,8 @@ tw_status finish_ts(tw_graph* g, bool gg_full, int64_t gg_old, int64_t gg_evicte
     hipLaunchKernelGGL(k_window_summary, dim3(1), dim3(1), 0, s, g->e_ts.as<int64_t>() + g->e_base,
                        g->m, i64_slot(g, SLOT_I64_SUMMARY), gg_full ? 1 : 0,
                        gg_old - gg_evicted, u32_slot(g, SLOT_U32_GROUPS),
-                       i64_slot(g, SLOT_I64_GG));
+                       i64_slot(g, SLOT_I64_GG), g->e_base, g->gg_base,
+                       i64_slot(g, SLOT_I64_WIN));
     TW_HIP(hipGetLastError());
     g->sum_stale = true;
     return TW_OK;

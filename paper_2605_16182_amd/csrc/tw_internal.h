@@ -157,6 +157,7 @@ constexpr int SLOT_U32_GROUPS = 4;     // groups counted by the last timestamp-g
 constexpr int SLOT_U32_UNSORTED = 6;   // batch not in timestamp order
 constexpr int SLOT_I64_SUMMARY = 4;    // [4] t_min, [5] t_max of the window
 constexpr int SLOT_I64_GG = 6;         // global timestamp groups of the window
+constexpr int SLOT_I64_WIN = 7;        // [7] e_base, [8] m, [9] gg_base of the timestamp view
 constexpr int SLOT_U32_KEPT = 24;      // kept batch records / late-prefix length
 constexpr int SLOT_U32_EVICTED = 25;   // evicted window records
 constexpr int SLOT_I64_FIRST_KEPT = 13;

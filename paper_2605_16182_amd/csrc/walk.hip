@@ -34,12 +34,14 @@ struct WalkArgs {
     const int32_t* e_src;
     const int32_t* e_dst;
     const int64_t* e_ts;
-    const uint32_t* gg_off;  // first record of each timestamp group, then the end
-    // the window's first and last timestamps and its global group count,
-    // read from the graph's scalar slots (the last update wrote them there)
+    const uint32_t* gg_off;  // first record of each timestamp group (from gg_base), then the end
+    // read from the graph's scalar slots, where the last update wrote them: the
+    // window's first and last timestamps, its global group count, and
+    // win = (e_base, m, gg_base): the window is e_*[e_base, e_base + m), its
+    // groups start at gg_off[gg_base]
     const int64_t* wsum;
     const int64_t* wgg;
-    uint32_t m, e_base;  // the window is e_*[e_base, e_base + m)
+    const int64_t* win;
     // node view
     const int32_t* n_dst;
     const int64_t* n_ts;
@@ -116,14 +118,15 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, const StartP
     StartState st{0, 0, 0, 0, -1};
     const Draw d0 = philox(id, 0, 0, sp.seed);
     if (sp.mode == TW_START_EDGE) {
-        if (a.m == 0) return st;
+        const uint32_t m = (uint32_t)a.win[1];
+        if (m == 0) return st;
         uint32_t e;
         if (sp.kind == TW_UNIFORM) {
-            const uint32_t i = (uint32_t)scale_u64(d0.x0, a.m);
-            e = a.e_base + (rev ? a.m - 1 - i : i);
+            const uint32_t i = (uint32_t)scale_u64(d0.x0, m);
+            e = (uint32_t)a.win[0] + (rev ? m - 1 - i : i);
         } else {
-            e = pick_global(a.gg_off, (uint32_t)*a.wgg, a.wsum[0], a.wsum[1], sp.kind, sp.tau, d0,
-                            rev);
+            e = pick_global(a.gg_off + a.win[2], (uint32_t)*a.wgg, a.wsum[0], a.wsum[1], sp.kind,
+                            sp.tau, d0, rev);
         }
         const int32_t s = a.e_src[e], t_dst = a.e_dst[e];
         const int64_t t = a.e_ts[e];
@@ -1162,9 +1165,8 @@ tw_status fill_args(tw_graph* g, int64_t num_walks, int32_t L, const tw_bias& sb
     a.e_ts = g->e_ts.as<int64_t>();
     a.wsum = g->scal.as<int64_t>() + SLOT_I64_SUMMARY;
     a.wgg = g->scal.as<int64_t>() + SLOT_I64_GG;
-    a.gg_off = g->gg_off.as<uint32_t>() + g->gg_base;
-    a.e_base = (uint32_t)g->e_base;
-    a.m = (uint32_t)g->m;
+    a.gg_off = g->gg_off.as<uint32_t>();
+    a.win = g->scal.as<int64_t>() + SLOT_I64_WIN;
     a.n_dst = g->n_dst.as<int32_t>();
     a.n_ts = g->n_ts.as<int64_t>();
     a.ng = g->ng.as<GroupRec>();

@@ -262,3 +262,75 @@ def test_walk_launch_graph_replay(dispatch):
             assert np.array_equal(a, b.cpu().numpy()), f"replay {rep} differs"
     del graph
     g.close()
+
+
+@pytest.mark.parametrize("mode", ["full_walk", "queue", "noalloc", "batch"])
+def test_walk_graph_replays_over_a_stream(mode):
+    # a walk launch recorded once in a HIP graph reads the window from
+    # device-side state that every update keeps current: replayed after each
+    # later batch (ingest and eviction run eagerly in between) it must equal
+    # an eager call with the same parameters; when the buffers moved
+    # (walk_layout changed) the launch is recorded again
+    torch, tw = gpu_or_skip()
+    rng = np.random.default_rng(31)
+    V, window = 3001, 40_000
+    cap = torch.cuda.Stream()
+    g = tw.Graph(V, window=window, stream=cap)
+    W, L, tau = 20_000, 16, 8_000.0
+    biases = [("uniform", 0.0, 1.0, 1.0), ("linear", 0.0, 1.0, 1.0),
+              ("exponential", tau, 1.0, 1.0), ("node2vec", tau, 0.5, 2.0)]
+    lims = to_dev(torch, synth.walk_lengths(6, W, 2, L))[0]
+
+    def alloc():
+        return (torch.empty((W, L), dtype=torch.int32, device="cuda"),
+                torch.empty((W, L), dtype=torch.int64, device="cuda"),
+                torch.empty(W, dtype=torch.int32, device="cuda"))
+
+    def walk(out, seed):
+        kw = dict(hop_bias="exponential", hop_tau=tau, start_bias="exponential",
+                  start_tau=tau, seed=seed)
+        if mode == "batch":
+            g.sample_walks_batch(W, L, biases, max_lens=lims, seed=seed, out=out)
+        elif mode == "noalloc":
+            g.sample_walks_noalloc(W, L, out, **kw)
+        else:
+            g.sample_walks(W, L, dispatch=mode, out=out, **kw)
+
+    eager_out, graph_out = alloc(), alloc()
+    graph, token, records, replays = None, None, 0, 0
+    t0 = 0
+    for b in range(14):
+        n = int(rng.integers(20_000, 40_000))
+        s = rng.integers(0, V, n).astype(np.int32)
+        d = rng.integers(0, V, n).astype(np.int32)
+        t = np.sort(t0 + rng.integers(0, 5_000, n)).astype(np.int64)
+        t0 += 5_000
+        torch.cuda.synchronize()
+        g.ingest_batch(*to_dev(torch, s, d, t))
+        if b % 4 == 3:
+            g.evict_before(t0 - window // 2)
+        if b < 2:
+            continue
+        walk(eager_out, 77)
+        g.sync()
+        eager = [x.cpu().numpy().copy() for x in eager_out]
+        if graph is None or g.walk_layout() != token:
+            del graph
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=cap):
+                walk(graph_out, 77)
+            token = g.walk_layout()
+            records += 1
+            continue
+        for x in graph_out:
+            x.fill_(7)  # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, x in zip(eager, graph_out):
+            assert np.array_equal(a, x.cpu().numpy()), f"batch {b}: replay differs"
+        replays += 1
+    print(f"walk graph {mode}: {records} recordings, {replays} replays checked")
+    assert replays >= 3
+    del graph
+    g.close()
