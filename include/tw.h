@@ -208,7 +208,7 @@ tw_status tw_set_stream(tw_graph* g, void* hip_stream);
  * with info NULL the range is computed on the device and read back with the
  * next read-back the library makes anyway (one synchronisation fewer). The
  * call synchronises the stream (it sizes its launches from counts it reads
- * back: three read-backs, four with info); the first read-back also brings
+ * back: two read-backs, three with info); the first read-back also brings
  * the error flags of earlier walks: a pending one is reported (TW_ERANGE,
  * TW_EINVAL, see tw_sample_walks) and cleared, and the batch is not
  * ingested.

@@ -103,6 +103,13 @@ __global__ void k_copy_u32(const uint32_t* __restrict__ from, uint32_t* __restri
     *to = *from;
 }
 
+// to[n] = *from, n = n_dev[0] + n_dev[1] capped at cap
+__global__ void k_copy_u32_at(const uint32_t* __restrict__ from, uint32_t* __restrict__ to,
+                              const uint32_t* __restrict__ n_dev, int64_t cap) {
+    const int64_t n = (int64_t)n_dev[0] + (int64_t)n_dev[1];
+    to[n < cap ? n : cap] = *from;
+}
+
 __global__ void k_zero_u32(uint32_t* __restrict__ p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -225,8 +232,11 @@ BatchRuns batch_runs(const tw_graph* g) {
 
 // Plan of every job: eviction of the node's groups older than cut, then the
 // kind, the written edge count and the slots a new segment needs.
+// nj jobs, or, with nj_dev, nj_dev[0] + nj_dev[1] of them (counted on the
+// device, at most nj)
 __global__ void k_job_setup(const uint32_t* __restrict__ c_node, const uint32_t* __restrict__ c_bf,
                             const uint32_t* __restrict__ c_be, int64_t nj,
+                            const uint32_t* __restrict__ nj_dev,
                             const NodeRec* __restrict__ rec, const SegRec* __restrict__ seg,
                             const GroupRec* __restrict__ ng, const uint32_t* __restrict__ fence,
                             const BatchRuns b,
@@ -235,6 +245,10 @@ __global__ void k_job_setup(const uint32_t* __restrict__ c_node, const uint32_t*
                             uint32_t* __restrict__ req_e, uint32_t* __restrict__ req_g,
                             uint32_t* __restrict__ req_f) {
     const int64_t j = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (nj_dev) {
+        const int64_t c = (int64_t)nj_dev[0] + (int64_t)nj_dev[1];
+        if (c < nj) nj = c;
+    }
     if (j >= nj) return;
     Job J{};
     J.v = c_node[j];
@@ -474,38 +488,20 @@ __global__ void __launch_bounds__(T) k_job_flags(const Job* __restrict__ jobs,
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t base = (int64_t)tile * NV_TILE;
     const TileJobs tj(tf, tile, off, soff);
-    auto rounds = [&](auto staged) {
-        constexpr bool S = decltype(staged)::value;
+    // M: 0 = job lookups in global memory, 1 = in LDS, 2 = the tile lies in
+    // one job (a hub's run), read once as uniform loads
+    auto rounds = [&](auto mode) {
+        constexpr int M = decltype(mode)::value;
+        constexpr bool S = M == 1;
         uint32_t c = 0;
         for (int u = 0; u < NV_ITEMS; ++u) {
             const int64_t t0 = base + (int64_t)u * T + wave * 64;  // the word's first output
             const int64_t t = t0 + lane;
             bool start = false;
             if (t < total) {
-                const uint32_t j = tj.template job<S>(off, soff, (uint64_t)t);
+                const uint32_t j = M == 2 ? tj.j0 : tj.template job<S>(off, soff, (uint64_t)t);
                 const Job J = jobs[j];
-                const uint32_t i = (uint32_t)(t - tj.template start<S>(off, soff, j));
-                const int64_t x = job_ts(J, i, ots, bt);
-                if (i == 0) start = J.kind != JOB_APPEND || x != J.t_last;
-                else start = x != job_ts(J, i - 1, ots, bt);
-            }
-            const uint64_t b = __ballot(start);
-            if (lane == 0 && t0 < total) bm[t0 >> 6] = b;
-            c += (uint32_t)__popcll(b);
-        }
-        return c;
-    };
-    // a tile inside one job (a hub's run): the job is read once, as uniform
-    // loads, and no output looks its job up
-    auto one_job = [&]() {
-        const Job J = jobs[tj.j0];
-        const uint32_t jb = off[tj.j0];
-        uint32_t c = 0;
-        for (int u = 0; u < NV_ITEMS; ++u) {
-            const int64_t t0 = base + (int64_t)u * T + wave * 64;
-            const int64_t t = t0 + lane;
-            bool start = false;
-            if (t < total) {
+                const uint32_t jb = M == 2 ? off[tj.j0] : tj.template start<S>(off, soff, j);
                 const uint32_t i = (uint32_t)(t - jb);
                 const int64_t x = job_ts(J, i, ots, bt);
                 if (i == 0) start = J.kind != JOB_APPEND || x != J.t_last;
@@ -517,9 +513,9 @@ __global__ void __launch_bounds__(T) k_job_flags(const Job* __restrict__ jobs,
         }
         return c;
     };
-    const uint32_t c = tj.j0 == tj.j1 ? one_job()
-                       : tj.staged   ? rounds(std::true_type{})
-                                     : rounds(std::false_type{});
+    const uint32_t c = tj.j0 == tj.j1 ? rounds(std::integral_constant<int, 2>{})
+                       : tj.staged   ? rounds(std::integral_constant<int, 1>{})
+                                     : rounds(std::integral_constant<int, 0>{});
     if (lane == 0) wsum[wave] = c;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -903,8 +899,8 @@ hipError_t scan_jobs(const uint32_t* in, uint32_t* out, int64_t n, Workspace& ws
     return scan_exclusive_u32(in, out, n, out + n, ws, s);
 }
 
-tw_status run_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool rewrite_all,
-                   Error& err);
+tw_status run_jobs(tw_graph* g, int64_t nj, bool counted, bool evicting, int64_t cut,
+                   bool rewrite_all, Error& err);
 
 }  // namespace
 
@@ -1002,8 +998,9 @@ tw_status nv_collect(tw_graph* g, const int32_t* q_src, const int32_t* q_dst, co
         TW_HIP(scan_exclusive_u32(nullptr, nullptr, 0, sl_ev, g->ws, s));
     }
     TW_HIP(hipGetLastError());
-    if (pull_scalars(g, false, err) != TW_OK) return err.code;
-    g->T = (int64_t)host_u32(g, SLOT_U32_RUNS) + host_u32(g, SLOT_U32_EV_NODES);
+    // the job count stays on the device (the plan reads it back with its
+    // totals); a node is one job at most
+    g->T = std::min<int64_t>(kept + ev_n, (int64_t)g->V + 1);
     return TW_OK;
 }
 
@@ -1016,14 +1013,24 @@ tw_status ensure_jobs(tw_graph* g, int64_t nj, Error& err) {
     return TW_OK;
 }
 
-// Plan nj jobs and scan their outputs and requests; returns the totals
-// {written edges, edge slots, group slots, fence entries}. Synchronises.
-tw_status plan_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool rewrite_all,
-                    uint32_t gen, uint64_t tot[4], Error& err) {
+// Plan the jobs and scan their outputs and requests; returns the totals
+// {written edges, edge slots, group slots, fence entries}. counted: nj is a
+// bound and the count is on the device (SLOT_U32_RUNS + SLOT_U32_EV_NODES):
+// the launches cover a capacity (twice the last update's jobs, at least 1M,
+// at most nj), read the count on the device and it comes back with the
+// totals in one read-back, which sets nj; a count above the capacity is
+// planned again. Synchronises.
+tw_status plan_jobs(tw_graph* g, int64_t& nj, bool counted, bool evicting, int64_t cut,
+                    bool rewrite_all, uint32_t gen, uint64_t tot[4], Error& err) {
     hipStream_t s = g->stream;
-    if (ensure_jobs(g, nj, err) != TW_OK) return err.code;
-    hipLaunchKernelGGL(k_job_setup, grid_for(nj), dim3(T), 0, s, g->c_node.as<uint32_t>(),
-                       g->c_bf.as<uint32_t>(), g->c_be.as<uint32_t>(), nj, g->rec.as<NodeRec>(),
+    const uint32_t* nj_dev = counted ? slot(g, SLOT_U32_RUNS) : nullptr;  // [0] runs, [1] nodes
+    static_assert(SLOT_U32_EV_NODES == SLOT_U32_RUNS + 1, "the job count is two adjacent words");
+    const int64_t cap =
+        counted ? std::min<int64_t>(nj, std::max<int64_t>(2 * g->jobs_last, 1 << 20)) : nj;
+    if (ensure_jobs(g, cap, err) != TW_OK) return err.code;
+    hipLaunchKernelGGL(k_job_setup, grid_for(cap), dim3(T), 0, s, g->c_node.as<uint32_t>(),
+                       g->c_bf.as<uint32_t>(), g->c_be.as<uint32_t>(), cap, nj_dev,
+                       g->rec.as<NodeRec>(),
                        g->seg.as<SegRec>(), g->ng.as<GroupRec>(), g->fence.as<uint32_t>(),
                        batch_runs(g), evicting ? 1 : 0, cut, rewrite_all ? 1 : 0, gen, g->jobs.as<Job>(),
                        g->j_cnt.as<uint32_t>(), g->j_re.as<uint32_t>(), g->j_rg.as<uint32_t>(),
@@ -1038,12 +1045,26 @@ tw_status plan_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool re
     uint32_t* const out4[4] = {j_off, g->j_re.as<uint32_t>(), g->j_rg.as<uint32_t>(),
                                g->j_rf.as<uint32_t>()};
     uint32_t* const tot4[4] = {slot(g, SLOT_U32_OUT), sl, sl + 1, sl + 2};
-    TW_HIP(scan_exclusive_u32x4(in4, out4, tot4, nj, g->ws, s));
-    hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, s, slot(g, SLOT_U32_OUT), j_off + nj);
+    TW_HIP(scan_exclusive_u32x4(in4, out4, tot4, cap, g->ws, s, nj_dev));
+    if (counted)
+        hipLaunchKernelGGL(k_copy_u32_at, dim3(1), dim3(1), 0, s, slot(g, SLOT_U32_OUT), j_off,
+                           nj_dev, cap);
+    else
+        hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, s, slot(g, SLOT_U32_OUT), j_off + nj);
     TW_HIP(hipGetLastError());
     if (pull_scalars(g, false, err) != TW_OK) return err.code;
+    if (counted) {
+        const int64_t n = (int64_t)host_u32(g, SLOT_U32_RUNS) + host_u32(g, SLOT_U32_EV_NODES);
+        if (n > nj) {
+            err = Error{TW_EDEVICE, "node view: more jobs than the batch can make"};
+            return err.code;
+        }
+        nj = n;
+        if (n > cap) return plan_jobs(g, nj, false, evicting, cut, rewrite_all, gen, tot, err);
+    }
     tot[0] = host_u32(g, SLOT_U32_OUT);
     for (int i = 0; i < 3; ++i) tot[1 + i] = host_u32(g, SLOT_U32_REQ_E + i);
+    g->jobs_last = nj;
     return TW_OK;
 }
 
@@ -1095,12 +1116,15 @@ tw_status execute_jobs(tw_graph* g, int64_t nj, uint64_t out, const int32_t* sds
     return TW_OK;
 }
 
-tw_status run_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool rewrite_all,
-                   Error& err) {
+// counted: nj bounds the jobs, whose count is on the device (plan_jobs)
+tw_status run_jobs(tw_graph* g, int64_t nj, bool counted, bool evicting, int64_t cut,
+                   bool rewrite_all, Error& err) {
     hipStream_t s = g->stream;
     uint64_t tot[4];
     const uint32_t gen = rewrite_all ? g->pool_gen + 1 : g->pool_gen;
-    if (plan_jobs(g, nj, evicting, cut, rewrite_all, gen, tot, err) != TW_OK) return err.code;
+    if (plan_jobs(g, nj, counted, evicting, cut, rewrite_all, gen, tot, err) != TW_OK)
+        return err.code;
+    if (nj == 0) return TW_OK;
     g->st_jobs = nj;
     g->st_written = (int64_t)tot[0];
     g->st_new_slots = (int64_t)tot[1];
@@ -1125,7 +1149,7 @@ tw_status run_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool rew
                                slot(g, SLOT_U32_EV_NODES), g->c_node.as<uint32_t>(),
                                g->c_bf.as<uint32_t>(), g->c_be.as<uint32_t>());
             TW_HIP(hipGetLastError());
-            return run_jobs(g, all, evicting, cut, true, err);
+            return run_jobs(g, all, false, evicting, cut, true, err);
         }
         hipLaunchKernelGGL(k_job_place, grid_for(nj), dim3(T), 0, s, g->jobs.as<Job>(), nj,
                            g->j_re.as<uint32_t>(), g->j_rg.as<uint32_t>(), g->j_rf.as<uint32_t>(),
@@ -1182,7 +1206,7 @@ tw_status run_jobs(tw_graph* g, int64_t nj, bool evicting, int64_t cut, bool rew
 tw_status nv_apply(tw_graph* g, bool evicting, int64_t cut, Error& err) {
     g->st_jobs = g->st_written = g->st_new_slots = g->st_full = 0;
     if (g->T == 0) return TW_OK;
-    if (run_jobs(g, g->T, evicting, cut, false, err) != TW_OK) return err.code;
+    if (run_jobs(g, g->T, true, evicting, cut, false, err) != TW_OK) return err.code;
     g->w_ready = false;
     return TW_OK;
 }

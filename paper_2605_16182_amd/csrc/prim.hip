@@ -149,8 +149,17 @@ struct Scan4 {
     uint32_t* total[4];
 };
 
-__global__ void k_scan4_reduce(const Scan4 a, int64_t n, uint32_t* __restrict__ part,
-                               int64_t nb) {
+// the element count of a scan: n, or, with n_dev, n_dev[0] + n_dev[1]
+// (counted on the device) capped at n
+__device__ inline int64_t scan_count(int64_t n, const uint32_t* n_dev) {
+    if (!n_dev) return n;
+    const int64_t c = (int64_t)n_dev[0] + (int64_t)n_dev[1];
+    return c < n ? c : n;
+}
+
+__global__ void k_scan4_reduce(const Scan4 a, int64_t cap, uint32_t* __restrict__ part,
+                               int64_t nb, const uint32_t* n_dev) {
+    const int64_t n = scan_count(cap, n_dev);
     const int y = blockIdx.y;
     int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
     uint32_t s = 0;
@@ -183,8 +192,9 @@ __global__ void k_scan4_partials(const Scan4 a, uint32_t* part, int64_t nb) {
 }
 
 template <bool SUM>
-__global__ void k_scan4_down(const Scan4 a, int64_t n, const uint32_t* __restrict__ part,
-                             int64_t nb) {
+__global__ void k_scan4_down(const Scan4 a, int64_t cap, const uint32_t* __restrict__ part,
+                             int64_t nb, const uint32_t* n_dev) {
+    const int64_t n = scan_count(cap, n_dev);
     __shared__ uint32_t tile[SCAN_TILE];
     const int y = blockIdx.y;
     const uint32_t* in = a.in[y];
@@ -640,7 +650,7 @@ hipError_t scan_exclusive_u32_into(const uint32_t* in, uint32_t* out, int64_t n,
 
 hipError_t scan_exclusive_u32x4(const uint32_t* const in[4], uint32_t* const out[4],
                                 uint32_t* const total[4], int64_t n, Workspace& ws,
-                                hipStream_t s) {
+                                hipStream_t s, const uint32_t* n_dev) {
     Scan4 a;
     for (int y = 0; y < 4; ++y) {
         a.in[y] = in[y];
@@ -657,14 +667,14 @@ hipError_t scan_exclusive_u32x4(const uint32_t* const in[4], uint32_t* const out
     if (e != hipSuccess) return e;
     uint32_t* part = ws.scan_part.as<uint32_t>();
     hipLaunchKernelGGL(k_scan4_reduce, dim3((unsigned)nb, 4), dim3(SCAN_THREADS), 0, s, a, n, part,
-                       nb);
+                       nb, n_dev);
     if (nb <= SCAN_SUM_MAX_BLOCKS) {
         hipLaunchKernelGGL(k_scan4_down<true>, dim3((unsigned)nb, 4), dim3(SCAN_THREADS), 0, s, a,
-                           n, part, nb);
+                           n, part, nb, n_dev);
     } else {
         hipLaunchKernelGGL(k_scan4_partials, dim3(4), dim3(SCAN_THREADS), 0, s, a, part, nb);
         hipLaunchKernelGGL(k_scan4_down<false>, dim3((unsigned)nb, 4), dim3(SCAN_THREADS), 0, s, a,
-                           n, part, nb);
+                           n, part, nb, n_dev);
     }
     return hipGetLastError();
 }

@@ -219,9 +219,11 @@ hipError_t scan_exclusive_u32_into(const uint32_t* in, uint32_t* out, int64_t n,
 
 // Four exclusive u32 scans of n elements at once (in[k] and out[k] may
 // alias); total[k] (device, nullable) receives the sum of array k.
+// n_dev (nullable): the arrays hold n_dev[0] + n_dev[1] elements, counted on
+// the device and at most n
 hipError_t scan_exclusive_u32x4(const uint32_t* const in[4], uint32_t* const out[4],
                                 uint32_t* const total[4], int64_t n, Workspace& ws,
-                                hipStream_t s);
+                                hipStream_t s, const uint32_t* n_dev = nullptr);
 
 // out[i] = sum_{j<i} in[j] in 64 bits (in >= 0); total (nullable) = the sum.
 hipError_t scan_exclusive_i32_to_u64(const int32_t* in, uint64_t* out, int64_t n, uint64_t* total,
@@ -329,7 +331,9 @@ struct tw_graph {
     tw::DevBuf jobs, j_cnt, j_off, j_re, j_rg, j_rf, j_fw;
     tw::DevBuf o_flag, o_rank;         // per written edge: group start, rank
     tw::DevBuf o_tf, f_tf;             // first job of every tile of written edges, fence words
-    int64_t T = 0;                     // jobs collected for the next update
+    int64_t T = 0;         // at most this many jobs collected for the next update; their
+                           // count is on the device (SLOT_U32_RUNS + SLOT_U32_EV_NODES)
+    int64_t jobs_last = 0; // jobs of the last update (sizes the next plan's launches)
     // counters of the last update: jobs, edges written, edge slots of new
     // segments, whether every active node was rewritten
     int64_t st_jobs = 0, st_written = 0, st_new_slots = 0, st_full = 0;
