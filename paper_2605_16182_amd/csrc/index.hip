@@ -195,29 +195,47 @@ __global__ void k_group_ts(const int64_t* __restrict__ e_ts, const uint32_t* __r
     if (k < Gg) out[k] = e_ts[gg_off[k]];
 }
 
+// The first index of [0, n) where a monotone predicate (true, then false)
+// is false, searched by one wavefront: each round the 64 lanes probe 64
+// evenly spaced positions of the remaining range at once and keep the part
+// between the last true and the first false probe, so a search over 2^28
+// records takes 5 dependent loads instead of 28. Every lane returns it.
+template <typename P>
+__device__ int64_t wave_lower_bound(int64_t n, P pred) {
+    const int lane = threadIdx.x & 63;
+    int64_t lo = 0, hi = n;  // the answer lies in [lo, hi]
+    while (lo < hi) {
+        const int64_t step = (hi - lo + 63) / 64;
+        const int64_t pos = lo + (int64_t)lane * step;
+        const uint64_t yes = __ballot(pos < hi && pred(pos));
+        const int64_t k = __popcll(yes);  // probes 0 .. k - 1 hold
+        if (k == 0) return lo;
+        const int64_t last = lo + (k - 1) * step;
+        const int64_t next = lo + k * step;
+        lo = last + 1;
+        hi = next < hi ? next : hi;
+    }
+    return lo;
+}
+
 // Evicted prefix of the window (records with ts < cut: ev) and of its
 // global groups (groups whose first record is evicted: the groups end at
 // record boundaries of equal timestamps, so these are the groups that start
-// before w_base + ev).
+// before w_base + ev). One wavefront; lane 0 writes.
 __device__ void evicted_prefix(const int64_t* __restrict__ w_ts, int64_t m, int64_t cut,
                                const uint32_t* __restrict__ gg_off, int64_t Gg, int64_t w_base,
                                uint32_t* sc_ev, uint32_t* sc_gev) {
-    int64_t lo = 0, hi = m;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (w_ts[mid] < cut) lo = mid + 1; else hi = mid;
+    const int64_t ev = wave_lower_bound(m, [&](int64_t i) { return w_ts[i] < cut; });
+    const uint64_t end = (uint64_t)(w_base + ev);
+    const int64_t gev =
+        wave_lower_bound(Gg, [&](int64_t i) { return (uint64_t)gg_off[i] < end; });
+    if ((threadIdx.x & 63) == 0) {
+        *sc_ev = (uint32_t)ev;
+        *sc_gev = (uint32_t)gev;
     }
-    const uint64_t end = (uint64_t)(w_base + lo);
-    int64_t a = 0, b = Gg;
-    while (a < b) {
-        const int64_t mid = (a + b) >> 1;
-        if ((uint64_t)gg_off[mid] < end) a = mid + 1; else b = mid;
-    }
-    *sc_ev = (uint32_t)lo;
-    *sc_gev = (uint32_t)a;
 }
 
-// Gg from the window summary slot (written by the last update)
+// Gg from the window summary slot (written by the last update); one wavefront
 __global__ void k_evict_counts(const int64_t* __restrict__ w_ts, int64_t m, int64_t cut,
                                const uint32_t* __restrict__ gg_off, const int64_t* gg_p,
                                int64_t w_base, uint32_t* sc_ev, uint32_t* sc_gev) {
@@ -225,10 +243,10 @@ __global__ void k_evict_counts(const int64_t* __restrict__ w_ts, int64_t m, int6
 }
 
 // The window cut of an ingest from the staged batch's range (the same
-// arithmetic as the host's once it reads the range back), and in parallel
-// the searches it needs: thread 0 the late prefix of a sorted batch (its
-// length and first kept timestamp), thread 1 the evicted prefix of the
-// window and of its global groups. Each writes its default (no late record,
+// arithmetic as the host's once it reads the range back), and the searches
+// it needs, each by the whole wavefront: the late prefix of a sorted batch
+// (its length and first kept timestamp), the evicted prefix of the window
+// and of its global groups. Each writes its default (no late record,
 // nothing evicted) when its condition does not hold, so one read-back serves
 // the whole decision.
 __global__ void k_cut_counts(const unsigned long long* __restrict__ mm,
@@ -245,26 +263,22 @@ __global__ void k_cut_counts(const unsigned long long* __restrict__ mm,
     const bool windowed = window > 0 && timed;
     const int64_t cut = !windowed ? INT64_MIN
                         : (now < INT64_MIN + window ? INT64_MIN : now - window);
-    if (threadIdx.x == 0) {
-        if (windowed && B > 0 && bmin < cut && *unsorted == 0u) {
-            int64_t lo = 0, hi = B;
-            while (lo < hi) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (b_ts[mid] < cut) lo = mid + 1; else hi = mid;
-            }
+    const bool lane0 = threadIdx.x == 0;
+    if (windowed && B > 0 && bmin < cut && *unsorted == 0u) {
+        const int64_t lo = wave_lower_bound(B, [&](int64_t i) { return b_ts[i] < cut; });
+        if (lane0) {
             *sc_kept = (uint32_t)lo;
             *first_kept = lo < B ? b_ts[lo] : INT64_MAX;
-        } else {
-            *sc_kept = 0u;
-            *first_kept = bmin;
         }
-    } else if (threadIdx.x == 1) {
-        if (windowed && m > 0 && summary[0] < cut) {
-            evicted_prefix(w_ts, m, cut, gg_off, *gg_p, w_base, sc_ev, sc_gev);
-        } else {
-            *sc_ev = 0u;
-            *sc_gev = 0u;
-        }
+    } else if (lane0) {
+        *sc_kept = 0u;
+        *first_kept = bmin;
+    }
+    if (windowed && m > 0 && summary[0] < cut) {
+        evicted_prefix(w_ts, m, cut, gg_off, *gg_p, w_base, sc_ev, sc_gev);
+    } else if (lane0) {
+        *sc_ev = 0u;
+        *sc_gev = 0u;
     }
 }
 
@@ -822,7 +836,7 @@ tw_status evict_before(tw_graph* g, int64_t cutoff, int64_t* n_evicted, Error& e
     if (g->m > 0 && cutoff > (g->sum_stale ? g->t_min_lb : g->t_min)) {
         uint32_t* sc_ev = u32_slot(g, SLOT_U32_EVICTED);
         uint32_t* sc_gev = u32_slot(g, SLOT_U32_GG_EVICTED);
-        hipLaunchKernelGGL(k_evict_counts, dim3(1), dim3(1), 0, s,
+        hipLaunchKernelGGL(k_evict_counts, dim3(1), dim3(64), 0, s,
                            g->e_ts.as<int64_t>() + g->e_base, g->m, cutoff,
                            g->gg_off.as<uint32_t>() + g->gg_base, i64_slot(g, SLOT_I64_GG),
                            g->e_base, sc_ev, sc_gev);
