@@ -65,9 +65,9 @@ typedef enum {
  *                  whose cumulative weight reaches u times the total. The
  *                  per-node cumulative weights are built on the first walk
  *                  call after the window changes (or tau changes) and kept;
- *                  one launch of tw_sample_walks_batch uses one tau for all
- *                  its TW_WEIGHT biases. Hop bias only; not served by
- *                  tw_server_submit. */
+ *                  one launch of tw_sample_walks_batch (or of the server)
+ *                  uses one tau for all its TW_WEIGHT biases. Hop bias
+ *                  only; forward only. */
 typedef enum {
     TW_UNIFORM = 0,
     TW_LINEAR = 1,
@@ -90,8 +90,8 @@ typedef enum {
  * source and destination swapped) from its first backward walk on, which
  * doubles the cost of later ingests; an undirected graph is its own in-view.
  * Backward walks run on the full-walk dispatch (AUTO or FULL_WALK) or the work
- * queue (QUEUE), in tw_sample_walks and tw_sample_walks_batch; TW_WEIGHT is
- * forward only, and the server walks forward. */
+ * queue (QUEUE), in tw_sample_walks and tw_sample_walks_batch, and in the
+ * server (tw_server_submit); TW_WEIGHT is forward only. */
 typedef enum { TW_FORWARD = 0, TW_BACKWARD = 1 } tw_direction;
 
 /* TW_START_EDGE: the first edge is drawn from the whole window (timestamp
@@ -459,9 +459,12 @@ typedef struct {
 tw_status tw_server_create(tw_graph* g, const tw_server_config* cfg, tw_server** out);
 
 /* Queue a walk request; *id names it. d_start_nodes (NODE mode) must stay
- * valid until the request finishes. Returns TW_EINVAL for bad parameters or
- * a request whose outputs can never fit in a fixed arena
- * (hbm_reserve_bytes < 0). */
+ * valid until the request finishes. Any hop bias and either direction
+ * (TW_WEIGHT forward only); a launch holds requests of one direction, and
+ * its TW_WEIGHT requests share one tau (a request that differs starts the
+ * next launch). The first backward request builds the graph's in-view from
+ * the window. Returns TW_EINVAL for bad parameters or a request whose
+ * outputs can never fit in a fixed arena (hbm_reserve_bytes < 0). */
 tw_status tw_server_submit(tw_server* s, const tw_walk_params* req, uint64_t* id);
 
 /* Queue an ingest batch (as tw_ingest_batch). The arrays must already hold

@@ -446,12 +446,12 @@ class Server:
                hop_tau: float = 0.0, p: float = 1.0, q: float = 1.0,
                start_bias: str = "uniform", start_tau: float = 0.0, start_mode: str = "edge",
                start_nodes: Optional[torch.Tensor] = None, seed: int = 42,
-               walk_id_base: int = 0) -> int:
+               walk_id_base: int = 0, direction: str = "forward") -> int:
         prm = _WalkParams(int(num_walks), int(max_len),
                           _Bias(KINDS[hop_bias], float(hop_tau), float(p), float(q)),
                           _Bias(KINDS[start_bias], float(start_tau), 1.0, 1.0),
                           START_MODES[start_mode], _ptr(start_nodes), int(seed),
-                          int(walk_id_base), 0)
+                          int(walk_id_base), 0, DIRECTIONS[direction])
         rid = _c.c_uint64(0)
         _check(self._lib.tw_server_submit(self._h, _c.byref(prm), _c.byref(rid)))
         if start_nodes is not None:

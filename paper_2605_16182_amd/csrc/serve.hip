@@ -317,13 +317,22 @@ void worker_loop(tw_server* S) {
             }
         } else if (!S->fifo.empty() && !S->ing_busy &&
                    (int)S->inflight.size() < S->cfg.max_inflight) {
-            // admit the consecutive requests at the front that fit
+            // admit the consecutive requests at the front that fit: one
+            // direction a launch, and one time scale for its weight-based ones
             std::vector<uint64_t> ids;
             int64_t walks = 0;
+            const bool rev = S->items[S->fifo.front()].p.direction == TW_BACKWARD;
+            double wscale = 0.0;  // 0: no weight-based request yet
             while (!S->fifo.empty() && (int)ids.size() < MAX_REQ_PER_LAUNCH) {
                 Item& it = S->items[S->fifo.front()];
                 if (it.ingest) break;
                 if (!ids.empty() && walks + it.p.num_walks > S->cfg.max_walks_per_launch) break;
+                if ((it.p.direction == TW_BACKWARD) != rev) break;
+                if (it.p.hop_bias.kind == TW_WEIGHT) {
+                    const double sc = it.p.hop_bias.tau > 0.0 ? it.p.hop_bias.tau : 1.0;
+                    if (wscale != 0.0 && sc != wscale) break;
+                    wscale = sc;
+                }
                 int c = -1;
                 size_t off = SIZE_MAX;
                 if (!place_outputs(S, it.bytes, &c, &off)) break;  // wait for releases
@@ -377,11 +386,15 @@ void worker_loop(tw_server* S) {
                     st = TW_EDEVICE;
                 // an index whose update failed midway serves nothing
                 if (st == TW_OK && S->g->broken) st = TW_EDEVICE;
+                // backward requests walk the in-view (made from the window on
+                // the first one; no batch is being ingested meanwhile)
+                tw_graph* gl = S->g;
+                if (st == TW_OK && rev && tw::backward_view(S->g, &gl, e) != TW_OK) st = e.code;
                 if (st == TW_OK) {
                     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, S->d_hops + slot);
                     hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, s, de, nw);
-                    st = tw::serve_launch(S->g, reqs.data(), (int)reqs.size(), dt, ht,
-                                          S->d_hops + slot, de, e);
+                    st = tw::serve_launch(gl, reqs.data(), (int)reqs.size(), dt, ht,
+                                          S->d_hops + slot, de, rev, e);
                 }
                 if (st == TW_OK &&
                     (hipMemcpyAsync(S->h_hops + slot, S->d_hops + slot, sizeof(unsigned long long),
@@ -506,8 +519,12 @@ tw_status server_create(tw_graph* g, const tw_server_config* cfg, tw_server** ou
 
 tw_status server_submit(tw_server* S, const tw_walk_params* p, uint64_t* id, Error& err) {
     if (check_walk_params(p, err) != TW_OK) return err.code;
-    if (p->hop_bias.kind == TW_WEIGHT || p->direction != TW_FORWARD) {
-        err = Error{TW_EINVAL, "server_submit: served walks are forward, without TW_WEIGHT"};
+    if (p->direction != TW_FORWARD && p->direction != TW_BACKWARD) {
+        err = Error{TW_EINVAL, "server_submit: bad direction"};
+        return err.code;
+    }
+    if (p->hop_bias.kind == TW_WEIGHT && p->direction != TW_FORWARD) {
+        err = Error{TW_EINVAL, "server_submit: the weight-based picker walks forward only"};
         return err.code;
     }
     if (!id) {

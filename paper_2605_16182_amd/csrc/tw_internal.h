@@ -538,9 +538,11 @@ size_t serve_table_bytes(int n);
 // *d_hops accumulates the launch's hops; request r's error words are
 // d_err[2 r] (a start node out of range) and d_err[2 r + 1] (node2vec
 // trial-cap hits), which the caller clears before the launch (d_err holds
-// at least 4 words). One large request runs the full-walk kernel.
+// at least 4 words). One large forward request runs the full-walk kernel.
+// rev: backward requests (g is the in-view). Weight-based requests of one
+// launch share one time scale (tau).
 tw_status serve_launch(tw_graph* g, const ServeReq* reqs, int n, void* d_table, void* h_table,
-                       unsigned long long* d_hops, uint32_t* d_err, Error& err);
+                       unsigned long long* d_hops, uint32_t* d_err, bool rev, Error& err);
 
 // serve.hip
 tw_status server_create(tw_graph* g, const tw_server_config* cfg, tw_server** out, Error& err);

@@ -390,7 +390,8 @@ k_walk_full(const WalkArgs a) {
 // or after t, listed from the latest, so every pick index is mirrored.
 __device__ __forceinline__ bool back_pick(const WalkArgs& a, const HopBias& hb, uint64_t seed,
                                           const NodeRec& r, uint32_t hi, uint64_t id,
-                                          uint64_t hop, int32_t prev, Pick& p, int32_t& nx) {
+                                          uint64_t hop, int32_t prev, Pick& p, int32_t& nx,
+                                          uint32_t* cap_count = nullptr) {
     const uint32_t end = hi < r.ge ? a.ng[hi].first : r.ee;  // the candidates' edges end
     const int64_t t_hi =
         (hb.kind == TW_EXPONENTIAL || hb.kind == TW_NODE2VEC) ? a.ng[hi - 1].ts : 0;
@@ -411,7 +412,7 @@ __device__ __forceinline__ bool back_pick(const WalkArgs& a, const HopBias& hb, 
         else beta = hb.inv_q;
         if (unit_closed_open(d.x2) * hb.beta_max < beta) return true;
     }
-    atomicAdd(&a.err[2], 1u);
+    atomicAdd(cap_count ? cap_count : &a.err[2], 1u);
     return false;
 }
 
@@ -755,6 +756,8 @@ struct ServeReqDev {
 // every picker's registers (about 180 VGPRs): held to 3 waves per SIMD
 // (a burst of 2,000 mixed requests: 3.53 G hops/s, against 3.37 at the 2
 // waves 180 VGPRs allow and 3.34 at 4, which spills 47 registers)
+// REV: backward requests on the in-view (each hop as in k_walk_back).
+template <bool REV>
 __global__ void __launch_bounds__(WALK_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
 k_walk_serve(const WalkArgs a, const ServeReqDev* __restrict__ reqs, int nreq,
              unsigned long long* counters, unsigned long long* hops_out) {
@@ -809,7 +812,7 @@ k_walk_serve(const WalkArgs a, const ServeReqDev* __restrict__ reqs, int nreq,
                     out_t = R.ts + i * (int64_t)R.L;
                     out_len = R.len + i;
                     rerr = R.err;
-                    const StartState st = walk_start(a, sp, i, id, lim, out_n, out_t, false, rerr);
+                    const StartState st = walk_start(a, sp, i, id, lim, out_n, out_t, REV, rerr);
                     len = st.len;
                     cur = st.cur;
                     prev = st.prev;
@@ -834,11 +837,25 @@ k_walk_serve(const WalkArgs a, const ServeReqDev* __restrict__ reqs, int nreq,
         if (w >= 0) {
             bool done = true;
             const NodeRec r = a.rec[cur];
-            if (tcur < r.t_last) {
-                const uint32_t gc = fence_search(a.ng, a.fence, r, tcur, nullptr, 0, 0);
+            // forward: Gamma_t(cur) is empty when t >= the last timestamp;
+            // backward: when cur has no in-edge or none before t
+            bool live = REV ? r.gb != r.ge : tcur < r.t_last;
+            uint32_t g = 0;
+            if (live) {
+                if (REV) {
+                    g = tcur - 1 >= r.t_last
+                            ? r.ge
+                            : fence_search(a.ng, a.fence, r, tcur - 1, nullptr, 0, 0);
+                    live = g != r.gb;
+                } else {
+                    g = fence_search(a.ng, a.fence, r, tcur, nullptr, 0, 0);
+                }
+            }
+            if (live) {
                 Pick p;
                 int32_t nx;
-                if (hop_pick(a, hb, seed, r, gc, id, hop, prev, p, nx, rerr + 1)) {
+                if (REV ? back_pick(a, hb, seed, r, g, id, hop, prev, p, nx, rerr + 1)
+                        : hop_pick(a, hb, seed, r, g, id, hop, prev, p, nx, rerr + 1)) {
                     out_n[len] = nx;
                     out_t[len] = p.t;
                     ++len;
@@ -1701,12 +1718,12 @@ __global__ void k_err_words(uint32_t* e, int finish) {
 constexpr int64_t SERVE_FULL_MIN = 1 << 16;
 
 tw_status serve_launch(tw_graph* g, const ServeReq* reqs, int n, void* d_table, void* h_table,
-                       unsigned long long* d_hops, uint32_t* d_err, Error& err) {
+                       unsigned long long* d_hops, uint32_t* d_err, bool rev, Error& err) {
     if (n < 1 || n > SERVE_MAX_REQ) {
         err = Error{TW_EINVAL, "serve: 1..1024 requests per launch"};
         return err.code;
     }
-    if (n == 1 && reqs[0].count >= SERVE_FULL_MIN && reqs[0].hop.kind != TW_WEIGHT) {
+    if (!rev && n == 1 && reqs[0].count >= SERVE_FULL_MIN && reqs[0].hop.kind != TW_WEIGHT) {
         const ServeReq& q = reqs[0];
         WalkArgs a;
         if (fill_args(g, q.count, q.max_len, q.start, q.start_mode, q.start_nodes, q.seed, q.base,
@@ -1729,13 +1746,19 @@ tw_status serve_launch(tw_graph* g, const ServeReq* reqs, int n, void* d_table, 
         }
     }
     bool n2v = false;
+    double wtau = NAN;  // the weight-based requests' time scale: one per launch
     int64_t total = 0;
     ServeReqDev* tab = static_cast<ServeReqDev*>(h_table);
     for (int r = 0; r < n; ++r) {
         const ServeReq& q = reqs[r];
         if (q.hop.kind == TW_WEIGHT) {
-            err = Error{TW_EINVAL, "serve: the weight-based picker is not served"};
-            return err.code;
+            const double sc = q.hop.tau > 0.0 ? q.hop.tau : 1.0;
+            if (rev || (!std::isnan(wtau) && wtau != sc)) {
+                err = Error{TW_EINVAL, "serve: weight-based requests of one launch need one "
+                                       "tau and walk forward"};
+                return err.code;
+            }
+            wtau = sc;
         }
         n2v |= q.hop.kind == TW_NODE2VEC;
         ServeReqDev d{};
@@ -1758,7 +1781,7 @@ tw_status serve_launch(tw_graph* g, const ServeReq* reqs, int n, void* d_table, 
     }
     WalkArgs a;
     tw_bias none{TW_UNIFORM, 0.0, 1.0, 1.0};
-    if (fill_args(g, total, 1, none, TW_START_EDGE, nullptr, 0, 0, n2v, NAN, nullptr, nullptr,
+    if (fill_args(g, total, 1, none, TW_START_EDGE, nullptr, 0, 0, n2v, wtau, nullptr, nullptr,
                   nullptr, a, err) != TW_OK)
         return err.code;
     if (queue_shape(g, err) != TW_OK) return err.code;
@@ -1773,9 +1796,13 @@ tw_status serve_launch(tw_graph* g, const ServeReq* reqs, int n, void* d_table, 
     if (total > 0) {
         const int64_t blocks = std::min<int64_t>(ceil_div(total, WALK_THREADS),
                                                  (int64_t)g->cu_count * g->queue_bpc_max);
-        hipLaunchKernelGGL(k_walk_serve, dim3((unsigned)blocks), dim3(WALK_THREADS), 0, g->stream,
-                           a, static_cast<const ServeReqDev*>(d_table), n,
-                           g->wq.as<unsigned long long>(), d_hops);
+        const ServeReqDev* tab_d = static_cast<const ServeReqDev*>(d_table);
+        if (rev)
+            hipLaunchKernelGGL(k_walk_serve<true>, dim3((unsigned)blocks), dim3(WALK_THREADS), 0,
+                               g->stream, a, tab_d, n, g->wq.as<unsigned long long>(), d_hops);
+        else
+            hipLaunchKernelGGL(k_walk_serve<false>, dim3((unsigned)blocks), dim3(WALK_THREADS), 0,
+                               g->stream, a, tab_d, n, g->wq.as<unsigned long long>(), d_hops);
     }
     TW_HIP(hipGetLastError());
     return TW_OK;

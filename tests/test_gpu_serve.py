@@ -108,7 +108,8 @@ def test_server_admission_by_memory_and_errors():
         srv.submit(3 * W, L)  # can never fit
     assert ei.value.code == tw.TW_EINVAL
     with pytest.raises(tw.TwError) as ei:
-        srv.submit(10, L, hop_bias="weight", hop_tau=100.0)  # not served
+        # the weight-based picker walks forward only
+        srv.submit(10, L, hop_bias="weight", hop_tau=100.0, direction="backward")
     assert ei.value.code == tw.TW_EINVAL
     with pytest.raises(tw.TwError):
         srv.wait(a)  # released: unknown
@@ -393,3 +394,72 @@ def test_backward_walks_after_a_server_session():
                                    ref, exact=True)
     assert same == W
     g.close()
+
+
+def test_served_backward_and_weight_requests_match_oracle():
+    # backward requests (the first one makes the in-view from the window; the
+    # server's later batches reach it) and weight-based requests (two time
+    # scales: they take separate launches) mixed with forward ones, each
+    # compared with the oracle on its epoch window
+    import oracle
+    from gpu_util import compare_walks
+    torch, tw = gpu_or_skip()
+    V, n = 4000, 40_000
+    bs = _stream(V, 3, n)
+    span = int(bs[0][2][-1] - bs[0][2][0])
+    window = int(1.5 * span)
+    tau = 0.1 * window
+    dev = [to_dev(torch, *b) for b in bs]
+    torch.cuda.synchronize()
+    g = tw.Graph(V, window=window)
+    srv = tw.Server(g, arena_bytes=256 << 20, max_walks_per_launch=6_000, max_inflight=3)
+    cases = [dict(hop_bias="linear", direction="backward"),
+             dict(hop_bias="weight", hop_tau=tau),
+             dict(hop_bias="exponential", hop_tau=tau, direction="backward",
+                  start_bias="exponential", start_tau=tau),
+             dict(hop_bias="uniform"),
+             dict(hop_bias="weight", hop_tau=2 * tau),
+             dict(hop_bias="node2vec", hop_tau=tau, p=0.5, q=2.0, direction="backward"),
+             dict(hop_bias="weight", hop_tau=tau),
+             dict(hop_bias="uniform", direction="backward")]
+    plan = []
+    ingests = [srv.ingest(*dev[0]), srv.ingest(*dev[1])]
+    for ep in (2, 3):
+        for j, c in enumerate(cases):
+            r = dict(num_walks=[900, 2500, 400, 3000][j % 4], max_len=[12, 20, 30, 8][j % 4],
+                     seed=ep * 50 + j, walk_id_base=11 * j, **c)
+            plan.append((ep, r, srv.submit(**r)))
+        if ep == 2:
+            ingests.append(srv.ingest(*dev[2]))
+    results = {rid: srv.result(rid) for _, _, rid in plan}
+    for i in ingests:
+        assert srv.wait(i)["status"] == tw.TW_OK
+    for _, _, rid in plan:
+        assert srv.wait(rid)["status"] == tw.TW_OK
+    # a backward weight-based request is refused at submission
+    with pytest.raises(tw.TwError) as ei:
+        srv.submit(10, 5, hop_bias="weight", hop_tau=tau, direction="backward")
+    assert ei.value.code == tw.TW_EINVAL
+    srv.close()
+    g.close()
+    og = oracle.OracleGraph(V, window=window, backward=True)
+    og.ingest_batch(*bs[0])
+    og.ingest_batch(*bs[1])
+    epoch = 2
+    rng = np.random.default_rng(9)
+    for ep, r, rid in plan:
+        while epoch < ep:
+            og.ingest_batch(*bs[epoch])
+            epoch += 1
+        W, L = r["num_walks"], r["max_len"]
+        idx = np.unique(np.concatenate([[0, W - 1], rng.integers(0, W, 500)])).astype(np.int64)
+        kw = {k: v for k, v in r.items() if k not in ("num_walks", "max_len")}
+        ref = og.sample_walks(W, L, walk_idx=idx, with_margin=True, **kw)
+        nodes, ts, lens = (x.cpu().numpy() for x in results[rid])
+        exact = r["hop_bias"] in ("uniform", "linear") and r.get("start_bias") is None
+        same, boundary = compare_walks((nodes[idx], ts[idx], lens[idx]), ref, exact,
+                                       label=f"served {r.get('direction', 'forward')} "
+                                             f"{r['hop_bias']} epoch {ep}",
+                                       kind=r["hop_bias"])
+        assert boundary <= 2, (ep, r, same, boundary)
+        assert float(ref["len"].mean()) > 1.5, (ep, r)
