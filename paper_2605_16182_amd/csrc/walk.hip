@@ -155,8 +155,9 @@ __device__ __forceinline__ StartState walk_start(const WalkArgs& a, const StartP
     if (L == 1) return st;
     const NodeRec r = a.rec[v0];
     if (r.gb == r.ge) return st;
-    Pick p =
-        pick_node(a.ng, a.n_dst, a.n_ts, r.gb, r.ge, r.ee, sp.kind, sp.tau, r.t_last, d0, rev);
+    const int64_t t_first = reads_first_ts(sp.kind) ? a.ng[r.gb].ts : 0;
+    Pick p = pick_node(a.ng, a.n_dst, a.n_ts, r.gb, r.ge, r.ee, sp.kind, sp.tau, t_first,
+                       r.t_last, d0, rev);
     const int32_t nx = p.dst;
     if (out_n) {
         out_n[1] = nx;
@@ -186,14 +187,17 @@ __device__ __forceinline__ bool hop_pick(const WalkArgs& a, const HopBias& hb, u
     }
     if (hb.kind != TW_NODE2VEC) {
         const Draw d = philox(id, hop, 0, seed);
-        p = pick_node(a.ng, a.n_dst, a.n_ts, gc, r.ge, r.ee, hb.kind, hb.tau, r.t_last, d);
+        const int64_t t_first = reads_first_ts(hb.kind) ? group_ts(a.ng, a.fence, r, gc) : 0;
+        p = pick_node(a.ng, a.n_dst, a.n_ts, gc, r.ge, r.ee, hb.kind, hb.tau, t_first, r.t_last,
+                      d);
         nx = p.dst;
         return true;
     }
+    const int64_t t_first = group_ts(a.ng, a.fence, r, gc);
     for (uint32_t trial = 0; trial < N2V_MAX_TRIALS; ++trial) {
         const Draw d = philox(id, hop, trial, seed);
-        p = pick_node(a.ng, a.n_dst, a.n_ts, gc, r.ge, r.ee, TW_EXPONENTIAL, hb.tau, r.t_last,
-                      d);
+        p = pick_node(a.ng, a.n_dst, a.n_ts, gc, r.ge, r.ee, TW_EXPONENTIAL, hb.tau, t_first,
+                      r.t_last, d);
         nx = p.dst;
         double beta;
         if (nx == prev) beta = hb.inv_p;
@@ -328,15 +332,18 @@ struct RowRing {
 
 // One full walk per thread: the full-walk baseline (Sec. "The Full-Walk
 // Baseline"). The walk is bound by dependent random loads, so waves in flight
-// count: the exponential pickers' FP64 code is held to 5 waves per SIMD and
-// the mixed-kind instantiation to 4 (a few registers spill); node2vec (more
-// live state) keeps its own allocation. ROWS: the walk writes its whole
+// count: the closed-form and weight pickers are held to 5 waves per SIMD, the
+// exponential picker's FP64 code and the mixed-kind instantiation to 4 (no
+// spills; 5 waves spill 14 registers there); node2vec (more live state) keeps
+// its own allocation. ROWS: the walk writes its whole
 // output row itself, four slots per store, padding included (rows of a
 // multiple of 4 slots, 16-byte aligned outputs); otherwise the rows were
 // pre-filled with padding and the walk writes the slots it reaches.
 template <int HK, int SK, bool ROWS>
 __global__ void __launch_bounds__(WALK_THREADS)
-__attribute__((amdgpu_waves_per_eu(HK == TW_NODE2VEC ? 1 : HK < 0 ? 4 : 5)))
+__attribute__((amdgpu_waves_per_eu(HK == TW_NODE2VEC                 ? 1
+                                     : HK < 0 || HK == TW_EXPONENTIAL ? 4
+                                                                      : 5)))
 k_walk_full(const WalkArgs a) {
     const int64_t w = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
     if (w >= a.num_walks) return;
@@ -393,18 +400,21 @@ __device__ __forceinline__ bool back_pick(const WalkArgs& a, const HopBias& hb, 
                                           uint64_t hop, int32_t prev, Pick& p, int32_t& nx,
                                           uint32_t* cap_count = nullptr) {
     const uint32_t end = hi < r.ge ? a.ng[hi].first : r.ee;  // the candidates' edges end
-    const int64_t t_hi =
-        (hb.kind == TW_EXPONENTIAL || hb.kind == TW_NODE2VEC) ? a.ng[hi - 1].ts : 0;
+    const bool rate = reads_first_ts(hb.kind);
+    const int64_t t_lo = rate ? a.ng[r.gb].ts : 0;
+    const int64_t t_hi = rate ? a.ng[hi - 1].ts : 0;
     if (hb.kind != TW_NODE2VEC) {
         const Draw d = philox(id, hop, 0, seed);
-        p = pick_node(a.ng, a.n_dst, a.n_ts, r.gb, hi, end, hb.kind, hb.tau, t_hi, d, true);
+        p = pick_node(a.ng, a.n_dst, a.n_ts, r.gb, hi, end, hb.kind, hb.tau, t_lo, t_hi, d,
+                      true);
         nx = p.dst;
         return true;
     }
     // the edge candidate -> prev of the graph is prev -> candidate here
     for (uint32_t trial = 0; trial < N2V_MAX_TRIALS; ++trial) {
         const Draw d = philox(id, hop, trial, seed);
-        p = pick_node(a.ng, a.n_dst, a.n_ts, r.gb, hi, end, TW_EXPONENTIAL, hb.tau, t_hi, d, true);
+        p = pick_node(a.ng, a.n_dst, a.n_ts, r.gb, hi, end, TW_EXPONENTIAL, hb.tau, t_lo, t_hi,
+                      d, true);
         nx = p.dst;
         double beta;
         if (nx == prev) beta = hb.inv_p;

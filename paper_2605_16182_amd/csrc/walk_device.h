@@ -217,6 +217,23 @@ __device__ __forceinline__ uint32_t pick_group(uint32_t n, int kind, double tau,
     return pick_exponential(n, exp_lambda(t_first, t_last, n, tau), x);
 }
 
+// Does a pick of this kind read its first candidate's timestamp?
+__device__ __forceinline__ bool reads_first_ts(int kind) {
+    return kind == TW_EXPONENTIAL || kind == TW_NODE2VEC;
+}
+
+// Timestamp of group g of node record r. Level 0 of a fence starts it and
+// keys every group of the segment, so with unshifted keys the timestamp is
+// the key base plus g's level-0 key: a word of the window a search ending
+// near g has just read, where g's group record is another line.
+__device__ __forceinline__ int64_t group_ts(const GroupRec* __restrict__ ng,
+                                           const uint32_t* __restrict__ fence, const NodeRec& r,
+                                           uint32_t g) {
+    if (rec_levels(r.lv) > 0 && rec_shift(r.lv) == 0)
+        return r.kbase + (int64_t)fence[(uint64_t)r.fence_off + (g - r.g0)];
+    return ng[g].ts;
+}
+
 // A pick in the node view among the groups [gc, ge) of a node whose edges
 // end at `end`: uniform over the edges, or biased over the groups and then
 // uniform inside the group. A group record carries the destination of the
@@ -228,12 +245,14 @@ struct Pick {
 
 // rev: a backward walk lists the candidates in reverse, so every index i
 // among n (the edge, the group, the edge inside the group) becomes n - 1 - i.
-// t_last is the timestamp of the last candidate group ge - 1.
+// t_first and t_last are the timestamps of the first and the last candidate
+// group, gc and ge - 1 (t_first is read by the exponential picker only).
 __device__ __forceinline__ Pick pick_node(const GroupRec* __restrict__ ng,
                                           const int32_t* __restrict__ n_dst,
                                           const int64_t* __restrict__ n_ts, uint32_t gc,
                                           uint32_t ge, uint32_t end, int kind, double tau,
-                                          int64_t t_last, const Draw& d, bool rev = false) {
+                                          int64_t t_first, int64_t t_last, const Draw& d,
+                                          bool rev = false) {
     if (kind == TW_UNIFORM) {
         const uint32_t c = ng[gc].first;
         const uint32_t i = (uint32_t)scale_u64(d.x0, end - c);
@@ -241,7 +260,7 @@ __device__ __forceinline__ Pick pick_node(const GroupRec* __restrict__ ng,
         return Pick{n_dst[e], n_ts[e]};
     }
     const uint32_t n = ge - gc;
-    const uint32_t i = pick_group(n, kind, tau, n > 1 ? ng[gc].ts : 0, t_last, d.x0);
+    const uint32_t i = pick_group(n, kind, tau, n > 1 ? t_first : 0, t_last, d.x0);
     const uint32_t k = rev ? ge - 1 - i : gc + i;
     const GroupRec a = ng[k];
     if (a.dst < 0) return Pick{a.dst & 0x7fffffff, a.ts};  // a one-edge group
