@@ -84,6 +84,20 @@ def test_wide_and_narrow_timestamp_spans(directed):
         assert np.array_equal(lens.cpu().numpy(), r["len"])
         assert np.array_equal(nodes.cpu().numpy(), r["nodes"])
         assert np.array_equal(tts.cpu().numpy(), r["ts"])
+    # every node's run here spans more than 2^30 time units, so its fence
+    # keys are shifted and the exponential rate reads the first candidate's
+    # timestamp from its group record (the other tests' graphs, with narrower
+    # spans, read it from the level-0 fence key)
+    for kind, tau in (("exponential", 3.0e8), ("exponential", 2.0e3), ("node2vec", 3.0e8)):
+        kw = dict(hop_bias=kind, hop_tau=tau, start_bias="exponential", start_tau=tau, seed=6,
+                  **({"p": 0.5, "q": 2.0} if kind == "node2vec" else {}))
+        for disp in ("full_walk", "queue"):
+            nodes, tts, lens = g.sample_walks(W, L, dispatch=disp, **kw)
+            g.sync()
+            r = og.sample_walks(W, L, with_margin=True, **kw)
+            compare_walks((nodes.cpu().numpy(), tts.cpu().numpy(), lens.cpu().numpy()), r,
+                          exact=False, label=f"spans/{directed}/{kind}/{tau:g}/{disp}",
+                          kind=kind)
     g.close()
 
 
@@ -318,6 +332,19 @@ def test_fence_search_depths(groups):
         assert np.array_equal(nodes.cpu().numpy(), r["nodes"])
         assert np.array_equal(tts.cpu().numpy(), r["ts"])
         assert np.array_equal(lens.cpu().numpy(), r["len"])
+    # the exponential rate takes the first candidate's timestamp from its
+    # level-0 fence key (the keys are unshifted here) at every fence depth
+    tau = 0.1 * float(ts_groups[-1] - ts_groups[0] + 1)
+    for kind, dispatch in (("exponential", "full_walk"), ("exponential", "queue"),
+                           ("exponential", "coop"), ("node2vec", "full_walk")):
+        kw = dict(hop_bias=kind, hop_tau=tau, start_bias="exponential", start_tau=tau,
+                  start_mode="node", seed=7, **({"p": 0.5, "q": 2.0} if kind == "node2vec" else {}))
+        nodes, tts, lens = g.sample_walks(W, L, start_nodes=to_dev(torch, starts)[0],
+                                          dispatch=dispatch, **kw)
+        g.sync()
+        r = og.sample_walks(W, L, start_nodes=starts, with_margin=True, **kw)
+        compare_walks((nodes.cpu().numpy(), tts.cpu().numpy(), lens.cpu().numpy()), r,
+                      exact=False, label=f"fence/{groups}/{kind}/{dispatch}", kind=kind)
     g.close()
 
 
@@ -731,4 +758,12 @@ def test_deep_fence_hub():
         r = og.sample_walks(W, L, hop_bias=kind, start_bias=kind, seed=13)
         assert np.array_equal(nodes.cpu().numpy(), r["nodes"])
         assert np.array_equal(tts.cpu().numpy(), r["ts"])
+    tau = 0.1 * float(t[:G].max() - t[:G].min())
+    kw = dict(hop_bias="exponential", hop_tau=tau, start_bias="exponential", start_tau=tau,
+              seed=14)
+    nodes, tts, lens = g.sample_walks(W, L, **kw)
+    g.sync()
+    r = og.sample_walks(W, L, with_margin=True, **kw)
+    compare_walks((nodes.cpu().numpy(), tts.cpu().numpy(), lens.cpu().numpy()), r,
+                  exact=False, label="deep_fence_hub/exponential", kind="exponential")
     g.close()
