@@ -181,7 +181,7 @@ __device__ __forceinline__ bool hop_pick(const WalkArgs& a, const HopBias& hb, u
     if (hb.kind == TW_WEIGHT) {
         const Draw d = philox(id, hop, 0, seed);
         p = pick_weight(a.ng, a.n_dst, a.cw, r.gb, gc, r.ge, r.ee, hb.tau > 0.0 ? hb.tau : 1.0,
-                        r.t_last, d);
+                        group_ts(a.ng, a.fence, r, gc), r.t_last, d);
         nx = p.dst;
         return true;
     }
@@ -332,18 +332,19 @@ struct RowRing {
 
 // One full walk per thread: the full-walk baseline (Sec. "The Full-Walk
 // Baseline"). The walk is bound by dependent random loads, so waves in flight
-// count: the closed-form and weight pickers are held to 5 waves per SIMD, the
-// exponential picker's FP64 code and the mixed-kind instantiation to 4 (no
-// spills; 5 waves spill 14 registers there); node2vec (more live state) keeps
-// its own allocation. ROWS: the walk writes its whole
-// output row itself, four slots per store, padding included (rows of a
-// multiple of 4 slots, 16-byte aligned outputs); otherwise the rows were
+// count: the uniform and linear pickers are held to 5 waves per SIMD (they
+// fit 8), the exponential and weight pickers' FP64 code and the mixed-kind
+// instantiation to 4 (no spills; 5 waves spill 14-16 registers there);
+// node2vec (more live state) keeps its own allocation. ROWS: the walk writes
+// its whole output row itself, four slots per store, padding included (rows
+// of a multiple of 4 slots, 16-byte aligned outputs); otherwise the rows were
 // pre-filled with padding and the walk writes the slots it reaches.
 template <int HK, int SK, bool ROWS>
 __global__ void __launch_bounds__(WALK_THREADS)
-__attribute__((amdgpu_waves_per_eu(HK == TW_NODE2VEC                 ? 1
-                                     : HK < 0 || HK == TW_EXPONENTIAL ? 4
-                                                                      : 5)))
+__attribute__((amdgpu_waves_per_eu(HK == TW_NODE2VEC ? 1
+                                     : HK < 0 || HK == TW_EXPONENTIAL || HK == TW_WEIGHT
+                                         ? 4
+                                         : 5)))
 k_walk_full(const WalkArgs a) {
     const int64_t w = (int64_t)blockIdx.x * WALK_THREADS + threadIdx.x;
     if (w >= a.num_walks) return;

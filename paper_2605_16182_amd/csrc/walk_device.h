@@ -274,20 +274,61 @@ __device__ __forceinline__ Pick pick_node(const GroupRec* __restrict__ ng,
 // end: cw holds the node's cumulative group weights (weights exp((ts -
 // t_last) / sc) per edge). r = u times the candidates' total weight; the
 // group is the first whose cumulative weight reaches the candidates' prefix
-// plus r (binary search), and the edge inside it the one whose share of the
-// group's weight r falls in (every edge of a group weighs the same), so one
-// draw selects the edge, as the edge-by-edge inversion does.
+// plus r (the last candidate when rounding leaves none), and the edge inside
+// it the one whose share of the group's weight r falls in (every edge of a
+// group weighs the same), so one draw selects the edge, as the edge-by-edge
+// inversion does. t_first is the timestamp of group gc.
+//
+// The search starts at a predicted group: with evenly spaced timestamps the
+// group weights grow by a constant factor, and the closed-form exponential
+// picker with the rate that spacing gives returns the group sought. From
+// there a galloping search (steps 1, 2, 4, ... toward the answer, then
+// bisection of the last step) finds the first group reaching the target;
+// cumulative weights never decrease, so the result is the one a bisection
+// of all candidates gives, in a few reads near the prediction instead of
+// log2(candidates) dependent reads.
 __device__ __forceinline__ Pick pick_weight(const GroupRec* __restrict__ ng,
                                             const int32_t* __restrict__ n_dst,
                                             const double* __restrict__ cw, uint32_t gb,
                                             uint32_t gc, uint32_t ge, uint32_t end, double sc,
-                                            int64_t t_last, const Draw& d) {
+                                            int64_t t_first, int64_t t_last, const Draw& d) {
     const double prefix = gc > gb ? cw[gc - 1] : 0.0;
     const double target = prefix + unit_open(d.x0) * (cw[ge - 1] - prefix);
-    uint32_t lo = gc, hi = ge - 1;
+    // reaches(g): group g is at or past the answer (always true for the last)
+    const uint32_t last = ge - 1;
+    auto reaches = [&](uint32_t g) { return g == last || cw[g] >= target; };
+    uint32_t lo = gc, hi = last;
+    const uint32_t n = ge - gc;
+    if (n > 8) {
+        const uint32_t p = gc + pick_exponential(n, exp_lambda(t_first, t_last, n, sc), d.x0);
+        uint32_t step = 1;
+        if (reaches(p)) {
+            hi = p;
+            while (hi > gc) {
+                const uint32_t q = hi - gc > step ? hi - step : gc;
+                if (!reaches(q)) {
+                    lo = q + 1;
+                    break;
+                }
+                hi = q;
+                step <<= 1;
+            }
+        } else {
+            lo = p + 1;
+            while (true) {
+                const uint32_t q = last - lo > step ? lo + step : last;
+                if (reaches(q)) {
+                    hi = q;
+                    break;
+                }
+                lo = q + 1;
+                step <<= 1;
+            }
+        }
+    }
     while (lo < hi) {
         const uint32_t mid = lo + ((hi - lo) >> 1);
-        if (cw[mid] >= target) hi = mid; else lo = mid + 1;
+        if (reaches(mid)) hi = mid; else lo = mid + 1;
     }
     const GroupRec a = ng[lo];
     if (a.dst < 0) return Pick{a.dst & 0x7fffffff, a.ts};  // a one-edge group

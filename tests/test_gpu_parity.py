@@ -529,6 +529,44 @@ def test_sorted_batches_continuing_the_last_timestamp(directed):
     g.close()
 
 
+@pytest.mark.parametrize("groups", [9, 100, 5_000, 100_000])
+def test_weight_search_on_uneven_timestamps(groups):
+    # a hub whose group timestamps grow as the cube of their rank (gaps far
+    # from even), some groups of two edges: the weight picker's search starts
+    # at the group an even spacing predicts and must gallop from there to
+    # the group a bisection of all candidates finds
+    torch, tw = gpu_or_skip()
+    rng = np.random.default_rng(groups + 5)
+    V = 3
+    t_groups = (np.arange(1, groups + 1, dtype=np.int64) ** 3) * 7
+    reps = np.where(rng.random(groups) < 0.2, 2, 1)
+    t = np.repeat(t_groups, reps)
+    src = np.full(len(t), 1, np.int32)
+    dst = np.where(rng.random(len(t)) < 0.8, 1, 2).astype(np.int32)
+    src = np.concatenate([src, np.array([0, 2], np.int32)])
+    dst = np.concatenate([dst, np.array([1, 1], np.int32)])
+    t = np.concatenate([t, np.array([0, 3], np.int64)])
+    g = tw.Graph(V)
+    og = oracle.OracleGraph(V)
+    g.ingest_batch(*to_dev(torch, src, dst, t))
+    og.ingest_batch(src, dst, t)
+    W, L = 3000, 24
+    starts = np.full(W, 1, np.int32)
+    span = float(t_groups[-1] - t_groups[0])
+    for tau in (1e-3 * span, 0.1 * span, 10.0 * span):
+        for dispatch in ("full_walk", "queue"):
+            kw = dict(hop_bias="weight", hop_tau=tau, start_bias="uniform", start_mode="node",
+                      seed=21)
+            nodes, tts, lens = g.sample_walks(W, L, start_nodes=to_dev(torch, starts)[0],
+                                              dispatch=dispatch, **kw)
+            g.sync()
+            r = og.sample_walks(W, L, start_nodes=starts, with_margin=True, **kw)
+            compare_walks((nodes.cpu().numpy(), tts.cpu().numpy(), lens.cpu().numpy()), r,
+                          exact=False, label=f"weight_uneven/{groups}/{tau:g}/{dispatch}",
+                          kind="weight")
+    g.close()
+
+
 @pytest.mark.parametrize("at_ingest", [False, True])
 def test_weight_walks_follow_the_window(at_ingest):
     # the weight-based picker's cumulative weights are rebuilt after every
