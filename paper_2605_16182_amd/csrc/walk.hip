@@ -402,8 +402,8 @@ __device__ __forceinline__ bool back_pick(const WalkArgs& a, const HopBias& hb, 
                                           uint32_t* cap_count = nullptr) {
     const uint32_t end = hi < r.ge ? a.ng[hi].first : r.ee;  // the candidates' edges end
     const bool rate = reads_first_ts(hb.kind);
-    const int64_t t_lo = rate ? a.ng[r.gb].ts : 0;
-    const int64_t t_hi = rate ? a.ng[hi - 1].ts : 0;
+    const int64_t t_lo = rate ? group_ts(a.ng, a.fence, r, r.gb) : 0;
+    const int64_t t_hi = rate ? group_ts(a.ng, a.fence, r, hi - 1) : 0;
     if (hb.kind != TW_NODE2VEC) {
         const Draw d = philox(id, hop, 0, seed);
         p = pick_node(a.ng, a.n_dst, a.n_ts, r.gb, hi, end, hb.kind, hb.tau, t_lo, t_hi, d,
