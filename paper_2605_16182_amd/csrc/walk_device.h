@@ -301,11 +301,11 @@ __device__ __forceinline__ Pick pick_weight(const GroupRec* __restrict__ ng,
     const uint32_t n = ge - gc;
     if (n > 8) {
         const uint32_t p = gc + pick_exponential(n, exp_lambda(t_first, t_last, n, sc), d.x0);
-        uint32_t step = 1;
+        uint64_t step = 1;  // 64-bit: it may pass 2^31 before a gallop ends
         if (reaches(p)) {
             hi = p;
             while (hi > gc) {
-                const uint32_t q = hi - gc > step ? hi - step : gc;
+                const uint32_t q = hi - gc > step ? hi - (uint32_t)step : gc;
                 if (!reaches(q)) {
                     lo = q + 1;
                     break;
@@ -316,7 +316,7 @@ __device__ __forceinline__ Pick pick_weight(const GroupRec* __restrict__ ng,
         } else {
             lo = p + 1;
             while (true) {
-                const uint32_t q = last - lo > step ? lo + step : last;
+                const uint32_t q = last - lo > step ? lo + (uint32_t)step : last;
                 if (reaches(q)) {
                     hi = q;
                     break;
