@@ -283,10 +283,12 @@ __device__ __forceinline__ Pick pick_node(const GroupRec* __restrict__ ng,
 // group weights grow by a constant factor, and the closed-form exponential
 // picker with the rate that spacing gives returns the group sought. From
 // there a galloping search (steps 1, 2, 4, ... toward the answer, then
-// bisection of the last step) finds the first group reaching the target;
-// cumulative weights never decrease, so the result is the one a bisection
-// of all candidates gives, in a few reads near the prediction instead of
-// log2(candidates) dependent reads.
+// bisection of the last step) finds the first group reaching the target, in
+// a few reads near the prediction instead of log2(candidates) dependent
+// reads. Cumulative weights do not decrease except by rounding where the
+// build's parallel scan joins two partial sums, so the result is the one a
+// bisection of all candidates gives unless the target lies within that
+// rounding of a boundary (inside the picks' boundary tolerance).
 __device__ __forceinline__ Pick pick_weight(const GroupRec* __restrict__ ng,
                                             const int32_t* __restrict__ n_dst,
                                             const double* __restrict__ cw, uint32_t gb,
