@@ -29,6 +29,11 @@ namespace {
 constexpr int T = 256;
 constexpr int W_ITEMS = 16;            // consecutive items per thread
 constexpr int W_TILE = T * W_ITEMS;    // items per tile
+// LDS position of tile item k: one pad word after every W_ITEMS items, so
+// that a thread's W_ITEMS consecutive items (the scan's reads) and lanes'
+// consecutive items (the loads' writes) fall in distinct banks
+constexpr int W_LDS = W_TILE + W_TILE / W_ITEMS;
+__device__ __forceinline__ int lds_at(int k) { return k + k / W_ITEMS; }
 
 // (head, sum): a segment head inside the range, and the sum since the last
 // head (the whole sum when there is none)
@@ -56,33 +61,85 @@ __device__ __forceinline__ uint32_t node_of(const uint32_t* __restrict__ off, ui
     return lo;
 }
 
-// Weights and heads of a tile's items into LDS (lane-strided, so the group
-// records are read in order); slot (nullable) receives the group slots.
+// exclusive prefix maximum of one value per thread over the workgroup
+__device__ uint32_t block_max_excl(uint32_t x) {
+    __shared__ uint32_t wmax[T / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc = y > inc ? y : inc;
+    }
+    if (lane == 63) wmax[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+#pragma unroll
+    for (int k = 0; k < T / 64; ++k)
+        if (k < wave) before = wmax[k] > before ? wmax[k] : before;
+    uint32_t ex = __shfl_up(inc, 1, 64);
+    if (lane == 0) ex = 0;
+    __syncthreads();
+    return ex > before ? ex : before;
+}
+
+// Weights of a tile's items into LDS (lane-strided, so the group records
+// are read in order), a segment head (a node's first item) as a negative
+// weight (-0.0 for a zero weight), and the items' group slots into slot. The
+// owning node of every item comes from LDS: each non-empty node of the
+// tile's node range marks its first item with its id, and a prefix maximum
+// over the tile (node ids grow with the items) carries it to the node's
+// other items, with the node of the tile's first item as the start.
 __device__ void tile_weights(const uint32_t* __restrict__ off, int64_t V, uint32_t G,
                              const NodeRec* __restrict__ rec, const GroupRec* __restrict__ ng,
-                             double inv_sc, uint32_t base, double* w, uint8_t* head,
-                             uint32_t* slot, uint32_t* vr) {
+                             double inv_sc, uint32_t base, double* w, uint32_t* slot,
+                             uint32_t* vr) {
+    const uint32_t last = std::min<uint32_t>(base + W_TILE, G) - 1;
     if (threadIdx.x == 0) {
-        const uint32_t last = std::min<uint32_t>(base + W_TILE, G) - 1;
         vr[0] = node_of(off, 0, (uint32_t)V - 1, base);
         vr[1] = node_of(off, vr[0], (uint32_t)V - 1, last);
+    }
+    for (int k = threadIdx.x; k < W_TILE; k += T) slot[lds_at(k)] = 0;
+    __syncthreads();
+    // nodes after vr[0] start inside the tile (vr[0] is the last node whose
+    // first item is at or before base); only a non-empty node marks its start
+    for (uint32_t v = vr[0] + 1 + threadIdx.x; v <= vr[1]; v += T) {
+        const uint32_t next = (int64_t)v + 1 < V ? off[v + 1] : G;
+        if (off[v] < next) slot[lds_at((int)(off[v] - base))] = v;
+    }
+    __syncthreads();
+    {
+        const int k0 = threadIdx.x * W_ITEMS;
+        uint32_t m = threadIdx.x == 0 ? vr[0] : 0u;
+#pragma unroll
+        for (int k = 0; k < W_ITEMS; ++k) {
+            const uint32_t x = slot[lds_at(k0 + k)];
+            m = x > m ? x : m;
+        }
+        uint32_t run = block_max_excl(m);
+        if (threadIdx.x == 0) run = vr[0];
+#pragma unroll
+        for (int k = 0; k < W_ITEMS; ++k) {
+            const uint32_t x = slot[lds_at(k0 + k)];
+            run = x > run ? x : run;
+            slot[lds_at(k0 + k)] = run;
+        }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < W_TILE; k += T) {
         const uint32_t f = base + (uint32_t)k;
         if (f >= G) {
-            w[k] = 0.0;
-            head[k] = 0;
+            w[lds_at(k)] = 0.0;
             continue;
         }
-        const uint32_t v = node_of(off, vr[0], vr[1], f);
+        const uint32_t v = slot[lds_at(k)];
         const NodeRec r = rec[v];
         const uint32_t g = r.gb + (f - off[v]);
         const GroupRec a = ng[g];
         const uint32_t next = g + 1 < r.ge ? ng[g + 1].first : r.ee;
-        w[k] = (double)(next - a.first) * exp((double)(a.ts - r.t_last) * inv_sc);
-        head[k] = f == off[v];
-        if (slot) slot[k] = g;
+        const double wt = (double)(next - a.first) * exp((double)(a.ts - r.t_last) * inv_sc);
+        w[lds_at(k)] = f == off[v] ? -wt : wt;
+        slot[lds_at(k)] = g;
     }
     __syncthreads();
 }
@@ -167,25 +224,28 @@ k_w_scan(const uint32_t* __restrict__ off, int64_t V, const uint32_t* __restrict
          const NodeRec* __restrict__ rec, const GroupRec* __restrict__ ng, double inv_sc,
          const uint32_t* __restrict__ c_head, const double* __restrict__ c_sum,
          double* __restrict__ cw) {
-    __shared__ double w[W_TILE];
-    __shared__ uint8_t head[W_TILE];
-    __shared__ uint32_t slot[W_TILE];
+    __shared__ double w[W_LDS];
+    __shared__ uint32_t slot[W_LDS];
     __shared__ uint32_t vr[2];
     const uint32_t G = *Gp;
     const uint32_t tile = blockIdx.x;
     const uint32_t base = tile * (uint32_t)W_TILE;
     if (base >= G) return;  // the grid is sized for an upper bound of G
-    tile_weights(off, V, G, rec, ng, inv_sc, base, w, head, slot, vr);
+    tile_weights(off, V, G, rec, ng, inv_sc, base, w, slot, vr);
     // this thread's items [i0, i0 + W_ITEMS) in order
     const int i0 = threadIdx.x * W_ITEMS;
+    auto item = [&](int i) {
+        const double x = w[lds_at(i)];
+        return Seg{signbit(x) ? 1u : 0u, fabs(x)};
+    };
     Seg mine{0, 0.0};
-    for (int k = 0; k < W_ITEMS; ++k) mine = seg_add(mine, Seg{head[i0 + k], w[i0 + k]});
+    for (int k = 0; k < W_ITEMS; ++k) mine = seg_add(mine, item(i0 + k));
     Seg all;
     Seg pre = seg_add(Seg{c_head[tile], c_sum[tile]}, block_seg_excl(mine, &all));
     for (int k = 0; k < W_ITEMS; ++k) {
         const int i = i0 + k;
-        pre = seg_add(pre, Seg{head[i], w[i]});
-        if (base + (uint32_t)i < G) cw[slot[i]] = pre.sum;
+        pre = seg_add(pre, item(i));
+        if (base + (uint32_t)i < G) cw[slot[lds_at(i)]] = pre.sum;
     }
 }
 
